@@ -1,0 +1,1169 @@
+/*
+ * bdf_oracle.c -- plain FP64 CPU reference for per-cell variable-order BDF
+ * integration of mass-action kinetics.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The product path (the
+ * HIP library) shares no code with it and never calls it.
+ *
+ * What it computes (arXiv 2405.01713, Balos et al.):
+ *   For every cell independently, y' = R(y) + F with y(t0) = y0 over one outer
+ *   step [t0, t_out] (the spatially decoupled ODE of Sec. 3.1, Eq. (7)), where
+ *   R is mass-action kinetics and F a constant forcing.  Integration is
+ *   CVODE-style variable-order (1..5), variable-step BDF (Sec. 2, Eq. (1)):
+ *   local error tested in the WRMS norm of Sec. 2, Eq. (3); modified Newton
+ *   with the stopping test of Sec. 2, Eq. (4) (c_eps = 0.1, c_r = 0.3);
+ *   Newton matrix I - gamma*J with an analytic Jacobian (Table 1, approaches
+ *   2A/2B) factored by dense LU with partial pivoting (Sec. 4.1.4).
+ *   Step and order are controlled per cell (the paper's batches run in lock
+ *   step; per-cell control removes the "stiffest cell dictates the step"
+ *   limitation of Sec. 2).
+ *
+ * The paper gives no BDF coefficients, heuristics or constants beyond
+ * Eqs. (3)-(4).  Where it is silent the following readings are used, each
+ * stated where it is implemented: Nordsieck variable-coefficient BDF with
+ * Lambda(x) = prod_i (1 + x/xi_i); error constant 1/(l_1 xi_{q+1});
+ * interpolation-preserving order changes; the initial-step estimate; the
+ * failure-recovery and setup heuristics.
+ *
+ * Everything is scalar, straightforward and unblocked so that it can be
+ * checked against the mathematics by eye.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAXS 64
+#define ORC_QMAX 5
+#define ORC_SLOTS 3
+#define ORC_UROUND 2.220446049250313e-16
+
+/* Per-cell status codes. */
+#define ORC_SUCCESS 0
+#define ORC_TOO_MUCH_WORK (-1)
+#define ORC_ERR_FAILURE (-3)
+#define ORC_CONV_FAILURE (-4)
+#define ORC_SETUP_FAILURE (-6)
+#define ORC_NONFINITE (-9)
+#define ORC_RECORD_FULL (-10)
+
+typedef struct {
+  int32_t n_species, n_reactions;
+  const int32_t *reac; /* [R][3] reactant species, -1 = empty */
+  const int32_t *prod; /* [R][3] product species, -1 = empty */
+  const double *lnA;   /* [R] ln of the forward pre-exponential factor */
+  const double *EaR;   /* [R] activation temperature Ea/R (K); NULL = 0 */
+  const double *lnK;   /* [R] ln equilibrium constant; NULL = irreversible */
+} orc_mech;
+
+typedef struct {
+  double rtol;
+  const double *atol; /* [atol_len] */
+  int32_t atol_len;   /* 1 or >= S */
+  int32_t max_order;  /* 1..5 */
+  int32_t max_steps;  /* per integrate call */
+} orc_opts;
+
+typedef struct {
+  int32_t status, nst, nfe, nni, nsetups, netf, ncfn, q_last;
+  double h_last, t_reached;
+} orc_stats;
+
+/* Per-cell record of accepted steps, for the frozen replay / adjoint. */
+typedef struct {
+  int32_t cap, n;    /* capacity (steps) and number recorded */
+  double h_pad;      /* value the step-size history was padded with */
+  double *y;         /* [cap][S] accepted solutions y_n */
+  double *h;         /* [cap] accepted step sizes h_n */
+  int32_t *q;        /* [cap] order used for step n */
+  int32_t *rebuild;  /* [cap] 1 if z was rebuilt at order 1 before step n */
+} orc_record;
+
+/* ------------------------------------------------------------------------ */
+/* Kinetics: rates, right-hand side, analytic Jacobian                       */
+/* ------------------------------------------------------------------------ */
+
+/* Arrhenius rate constants k_f = exp(lnA - Ea/(R T)) * scale and, for
+ * reversible reactions, k_r = k_f / K = k_f * exp(-lnK). */
+void orc_rates(const orc_mech *m, double T, const double *kscale, double *kf, double *kr) {
+  for (int r = 0; r < m->n_reactions; ++r) {
+    double lk = m->lnA[r];
+    if (m->EaR) lk -= m->EaR[r] / T;
+    kf[r] = exp(lk);
+    if (kscale) kf[r] *= kscale[r];
+    kr[r] = m->lnK ? kf[r] * exp(-m->lnK[r]) : 0.0;
+  }
+}
+
+/* Net rate of every reaction: q_r = k_f prod(y_reac) - k_r prod(y_prod). */
+static void orc_reaction_rates(const orc_mech *m, const double *kf, const double *kr,
+                               const double *y, double *qr) {
+  for (int r = 0; r < m->n_reactions; ++r) {
+    double fwd = kf[r], rev = kr[r];
+    for (int s = 0; s < ORC_SLOTS; ++s) {
+      int a = m->reac[r * ORC_SLOTS + s];
+      int b = m->prod[r * ORC_SLOTS + s];
+      if (a >= 0) fwd *= y[a];
+      if (b >= 0) rev *= y[b];
+    }
+    qr[r] = fwd - rev;
+  }
+}
+
+/* f = F + sum_r nu_r q_r (mass-action chemistry source term R plus forcing). */
+void orc_rhs(const orc_mech *m, const double *kf, const double *kr, const double *F,
+             const double *y, double *f) {
+  double qr[4096];
+  double *q = m->n_reactions <= 4096 ? qr : (double *)malloc(sizeof(double) * m->n_reactions);
+  int S = m->n_species;
+  for (int i = 0; i < S; ++i) f[i] = F ? F[i] : 0.0;
+  orc_reaction_rates(m, kf, kr, y, q);
+  for (int r = 0; r < m->n_reactions; ++r) {
+    for (int s = 0; s < ORC_SLOTS; ++s) {
+      int a = m->reac[r * ORC_SLOTS + s];
+      int b = m->prod[r * ORC_SLOTS + s];
+      if (a >= 0) f[a] -= q[r];
+      if (b >= 0) f[b] += q[r];
+    }
+  }
+  if (q != qr) free(q);
+}
+
+/* Analytic Jacobian J[i][j] = d f_i / d y_j (row-major S x S).
+ * d(prod_l y_{a_l}) / d y_j = sum over slots l with a_l = j of the product of
+ * the other slots. */
+void orc_jac(const orc_mech *m, const double *kf, const double *kr, const double *y, double *J) {
+  int S = m->n_species;
+  memset(J, 0, sizeof(double) * S * S);
+  for (int r = 0; r < m->n_reactions; ++r) {
+    const int32_t *side[2] = {m->reac + r * ORC_SLOTS, m->prod + r * ORC_SLOTS};
+    double kside[2] = {kf[r], -kr[r]}; /* q_r = kf*P_reac - kr*P_prod */
+    for (int sd = 0; sd < 2; ++sd) {
+      if (kside[sd] == 0.0) continue;
+      for (int l = 0; l < ORC_SLOTS; ++l) {
+        int j = side[sd][l];
+        if (j < 0) continue;
+        double d = kside[sd];
+        for (int o = 0; o < ORC_SLOTS; ++o)
+          if (o != l && side[sd][o] >= 0) d *= y[side[sd][o]];
+        /* d = d q_r / d y_j contribution of slot l; distribute with nu */
+        for (int s = 0; s < ORC_SLOTS; ++s) {
+          int a = m->reac[r * ORC_SLOTS + s];
+          int b = m->prod[r * ORC_SLOTS + s];
+          if (a >= 0) J[a * S + j] -= d;
+          if (b >= 0) J[b * S + j] += d;
+        }
+      }
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense LU with partial pivoting (Sec. 4.1.4: "LU factorization with       */
+/* pivoting").  Ties in |pivot| go to the lowest original row index.         */
+/* ------------------------------------------------------------------------ */
+
+/* Factor A (n x n, row-major) in place: P A = L U, unit lower L stored below
+ * the diagonal.  perm[i] = original index of the row now at position i.
+ * Returns 0, or k+1 if the pivot of column k is exactly zero. */
+int32_t orc_lu_factor(int n, double *A, int32_t *perm) {
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = fabs(A[k * n + k]);
+    for (int i = k + 1; i < n; ++i) {
+      double v = fabs(A[i * n + k]);
+      if (v > best || (v == best && perm[i] < perm[p])) {
+        best = v;
+        p = i;
+      }
+    }
+    if (best == 0.0) return k + 1;
+    if (p != k) {
+      for (int j = 0; j < n; ++j) {
+        double t = A[k * n + j];
+        A[k * n + j] = A[p * n + j];
+        A[p * n + j] = t;
+      }
+      int32_t t = perm[k];
+      perm[k] = perm[p];
+      perm[p] = t;
+    }
+    for (int i = k + 1; i < n; ++i) {
+      double l = A[i * n + k] / A[k * n + k];
+      A[i * n + k] = l;
+      for (int j = k + 1; j < n; ++j) A[i * n + j] -= l * A[k * n + j];
+    }
+  }
+  return 0;
+}
+
+/* Solve A x = b with the factors of orc_lu_factor; b is overwritten by x. */
+void orc_lu_solve(int n, const double *LU, const int32_t *perm, double *b) {
+  double y[ORC_MAXS];
+  for (int i = 0; i < n; ++i) {
+    double s = b[perm[i]];
+    for (int j = 0; j < i; ++j) s -= LU[i * n + j] * y[j];
+    y[i] = s;
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = y[i];
+    for (int j = i + 1; j < n; ++j) s -= LU[i * n + j] * b[j];
+    b[i] = s / LU[i * n + i];
+  }
+}
+
+/* Solve A^T x = b with the factors of A (P A = L U  =>  A^T = U^T L^T P). */
+static void orc_lu_solve_transposed(int n, const double *LU, const int32_t *perm, double *b) {
+  double w[ORC_MAXS];
+  for (int i = 0; i < n; ++i) { /* U^T w = b */
+    double s = b[i];
+    for (int j = 0; j < i; ++j) s -= LU[j * n + i] * w[j];
+    w[i] = s / LU[i * n + i];
+  }
+  for (int i = n - 1; i >= 0; --i) { /* L^T v = w */
+    double s = w[i];
+    for (int j = i + 1; j < n; ++j) s -= LU[j * n + i] * w[j];
+    w[i] = s;
+  }
+  for (int i = 0; i < n; ++i) b[perm[i]] = w[i]; /* x = P^T v */
+}
+
+/* ------------------------------------------------------------------------ */
+/* Norms and BDF coefficients                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Weighted root-mean-square norm, Sec. 2, Eq. (3): sqrt(1/N sum (w_i v_i)^2). */
+double orc_wrms(int n, const double *v, const double *w) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += (v[i] * w[i]) * (v[i] * w[i]);
+  return sqrt(s / n);
+}
+
+/* Error weights of Sec. 2, Eq. (3): w_i = 1/(rtol |y_i| + atol_i). */
+static void orc_ewt(int n, const double *y, const orc_opts *o, double *w) {
+  for (int i = 0; i < n; ++i) {
+    double a = o->atol_len == 1 ? o->atol[0] : o->atol[i];
+    w[i] = 1.0 / (o->rtol * fabs(y[i]) + a);
+  }
+}
+
+/* Coefficients of the variable-coefficient BDF of order q in Nordsieck form.
+ * xi[i] = (t_n - t_{n-i}) / h_n for i = 1..q+1 (xi[0] unused).
+ * l[j] = coefficient of x^j in Lambda(x) = prod_{i=1}^{q} (1 + x/xi_i), so the
+ * corrected polynomial z + l e keeps interpolating the q past values.
+ * The local error estimate is Cerr * e with Cerr = 1/(l_1 xi_{q+1}); for
+ * constant steps this is 1/((q+1) H_q) (H_q the harmonic number). */
+void orc_bdf_coeffs(int q, const double *xi, double *l, double *Cerr) {
+  for (int j = 0; j <= ORC_QMAX + 1; ++j) l[j] = 0.0;
+  l[0] = 1.0;
+  for (int i = 1; i <= q; ++i)
+    for (int j = i; j >= 1; --j) l[j] += l[j - 1] / xi[i];
+  *Cerr = 1.0 / (l[1] * xi[q + 1]);
+}
+
+/* xi_i for a step of size h given accepted-step history hist[0] = h_{n-1},
+ * hist[1] = h_{n-2}, ...: xi_1 = 1, xi_i = (h + hist[0] + ... + hist[i-2])/h. */
+static void orc_xi(double h, const double *hist, int q, double *xi) {
+  double sum = h;
+  xi[1] = 1.0;
+  for (int i = 2; i <= q + 1; ++i) {
+    sum += hist[i - 2];
+    xi[i] = sum / h;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Nordsieck array operations.  z[j] = h^j y^(j) / j!, j = 0..q.              */
+/* ------------------------------------------------------------------------ */
+
+/* Predictor: z <- z * Pascal (Taylor shift by one step). */
+static void orc_predict(int S, int q, double z[][ORC_MAXS]) {
+  for (int k = 1; k <= q; ++k)
+    for (int j = q; j >= k; --j)
+      for (int i = 0; i < S; ++i) z[j - 1][i] += z[j][i];
+}
+
+/* Exact inverse of orc_predict (restore after a rejected attempt). */
+static void orc_unpredict(int S, int q, double z[][ORC_MAXS]) {
+  for (int k = 1; k <= q; ++k)
+    for (int j = q; j >= k; --j)
+      for (int i = 0; i < S; ++i) z[j - 1][i] -= z[j][i];
+}
+
+/* Change of step size h -> eta h: z_j <- eta^j z_j. */
+static void orc_rescale(int S, int q, double eta, double z[][ORC_MAXS]) {
+  double f = 1.0;
+  for (int j = 1; j <= q; ++j) {
+    f *= eta;
+    for (int i = 0; i < S; ++i) z[j][i] *= f;
+  }
+}
+
+/* Order q -> q+1 after an accepted step (reading of Sec. 2, "the method order
+ * may be changed"): add (e/xi_{q+1}) x Lambda(x), the degree-(q+1) term that
+ * makes z also interpolate the value the predictor interpolated at
+ * t_{n-q-1}; l and xi are those of the step just accepted. */
+static void orc_order_up(int S, int q, const double *l, const double *xi, const double *e,
+                         double z[][ORC_MAXS]) {
+  double c = 1.0 / xi[q + 1];
+  for (int i = 0; i < S; ++i) z[q + 1][i] = 0.0;
+  for (int j = 1; j <= q + 1; ++j)
+    for (int i = 0; i < S; ++i) z[j][i] += c * l[j - 1] * e[i];
+}
+
+/* Order q -> q-1: subtract z_q x prod_{i=1}^{q-1} (x + xi_i), which removes
+ * the x^q term and keeps interpolation at t_n, ..., t_{n-q+1}. */
+static void orc_order_down(int S, int q, const double *xi, double z[][ORC_MAXS]) {
+  double c[ORC_QMAX + 2];
+  for (int j = 0; j <= q; ++j) c[j] = 0.0;
+  c[1] = 1.0; /* polynomial x */
+  for (int i = 1; i <= q - 1; ++i) /* multiply by (x + xi_i) */
+    for (int j = i + 1; j >= 1; --j) c[j] = c[j - 1] + xi[i] * c[j];
+  for (int j = 1; j < q; ++j)
+    for (int i = 0; i < S; ++i) z[j][i] -= c[j] * z[q][i];
+  for (int i = 0; i < S; ++i) z[q][i] = 0.0;
+}
+
+static double orc_harmonic(int k) {
+  double s = 0.0;
+  for (int i = 1; i <= k; ++i) s += 1.0 / i;
+  return s;
+}
+
+static double orc_factorial(int k) {
+  double s = 1.0;
+  for (int i = 2; i <= k; ++i) s *= i;
+  return s;
+}
+
+static int orc_all_finite(int n, const double *v) {
+  for (int i = 0; i < n; ++i)
+    if (!isfinite(v[i])) return 0;
+  return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-cell adaptive integration                                            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  const orc_mech *m;
+  const double *kf, *kr, *F;
+  int S;
+} orc_sys;
+
+static void sys_f(const orc_sys *s, const double *y, double *f) { orc_rhs(s->m, s->kf, s->kr, s->F, y, f); }
+
+/* Initial step size (reading; the paper is silent).  Bounds
+ * h_lb = 100 u max(|t0|, |t_out|), h_ub = min(0.1 |t_out - t0|,
+ * 1 / max_i(|f0_i| / (0.1 |y0_i| + atol_i))); then up to four refinements
+ * of h = sqrt(2 / ||y''||) with y'' ~ (f(y0 + h f0) - f0)/h, stopping when the
+ * new value is within a factor 2 of the previous; h0 = 0.5 h clamped to
+ * [h_lb, h_ub] (h_ub if y'' vanishes). */
+static double orc_initial_step(const orc_sys *s, const orc_opts *o, double t0, double tout,
+                               const double *y0, const double *f0, const double *ewt, int *nfe) {
+  int S = s->S;
+  double tdist = fabs(tout - t0);
+  double hlb = 100.0 * ORC_UROUND * fmax(fabs(t0), fabs(tout));
+  double hub = 0.1 * tdist;
+  double hub_inv = 0.0;
+  for (int i = 0; i < S; ++i) {
+    double a = o->atol_len == 1 ? o->atol[0] : o->atol[i];
+    double v = fabs(f0[i]) / (0.1 * fabs(y0[i]) + a);
+    if (v > hub_inv) hub_inv = v;
+  }
+  if (hub * hub_inv > 1.0) hub = 1.0 / hub_inv;
+  if (hub < hlb) return hub;
+  double hg = sqrt(hlb * hub), hnew = hg;
+  double ytmp[ORC_MAXS], ftmp[ORC_MAXS], ydd[ORC_MAXS];
+  for (int it = 0; it < 4; ++it) {
+    for (int i = 0; i < S; ++i) ytmp[i] = y0[i] + hg * f0[i];
+    sys_f(s, ytmp, ftmp);
+    (*nfe)++;
+    for (int i = 0; i < S; ++i) ydd[i] = (ftmp[i] - f0[i]) / hg;
+    double yddnrm = orc_wrms(S, ydd, ewt);
+    if (!(yddnrm > 0.0)) return hub;
+    hnew = sqrt(2.0 / yddnrm);
+    double ratio = hnew / hg;
+    hg = hnew;
+    if (ratio >= 0.5 && ratio <= 2.0) break;
+  }
+  double h0 = 0.5 * hnew;
+  if (h0 < hlb) h0 = hlb;
+  if (h0 > hub) h0 = hub;
+  return h0;
+}
+
+/* eta = 1 / ((bias * err)^(1/p) + 1e-6): step ratio that would bring an
+ * error estimate err of an order-(p-1) method to 1/bias. */
+static double orc_eta(double bias, double err, int p) {
+  return 1.0 / (pow(bias * err, 1.0 / p) + 1.0e-6);
+}
+
+/* Integrate one cell from t0 to tout.  y (length S) is the initial state on
+ * entry and the final state (or the last accepted state on failure) on exit.
+ *
+ * Step loop (Sec. 2): weights from y^{n-1} (Eq. (3)); predict; Newton on
+ * G(e) = e - gamma f(z_0 + e) + z_1/l_1 with M = I - gamma J (modified
+ * Newton, Sec. 3.1), stopped by Eq. (4) with c_eps = 0.1, c_r = 0.3 and
+ * eps = 1/Cerr; accept when Cerr ||e|| <= 1, otherwise cut h (and possibly
+ * the order) and retry; after acceptance choose the next h and q.
+ *
+ * Readings where the paper is silent: at most 3 Newton iterations,
+ * divergence when ||delta_m|| > 2 ||delta_{m-1}||; the convergence rate R
+ * persists across steps and is reset to 1 at every setup; the Newton matrix
+ * is rebuilt (fresh J) on the first step, 20 steps after the last setup,
+ * when |gamma/gamma_setup - 1| > 0.3 and after a convergence failure with a
+ * stale matrix; when gamma differs from the factored one, delta is scaled by
+ * 2/(1 + gamma/gamma_setup).  Convergence failure with a fresh matrix cuts
+ * h by 4; 10 in one step fail the cell (-4).  Error-test failure: 7 in one
+ * step fail the cell (-3); from the third, restart at order 1 from y with
+ * eta = 0.1; otherwise eta = max(0.1, eta_q) and eta <= 0.2 from the second.
+ * After every accepted step the next step size is chosen (Sec. 2) from
+ * eta_q (bias 6); the order is reconsidered only when qwait reaches 0
+ * (qwait = q+1 after an order change, 2 at the start, after a restart and
+ * after each order decision), adding candidates eta_{q-1} (bias 6) and
+ * eta_{q+1} (bias 10, from the difference of successive corrections); the
+ * largest wins, ties going to q then q-1.  Ratios below 1.5 change
+ * nothing; growth is capped by eta_max (1e4 on the first step, 10
+ * afterwards); right after a failure h and q are held for that step.
+ * The last step is clipped to land on tout exactly.
+ */
+static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0, double tout,
+                                  double *y, orc_stats *st, orc_record *rec, double *zout) {
+  const int S = s->S;
+  const int qmax = o->max_order < 1 ? 1 : (o->max_order > ORC_QMAX ? ORC_QMAX : o->max_order);
+  double z[ORC_QMAX + 2][ORC_MAXS];
+  double ewt[ORC_MAXS], e[ORC_MAXS], eprev[ORC_MAXS], ycur[ORC_MAXS], f[ORC_MAXS], G[ORC_MAXS];
+  double delta[ORC_MAXS];
+  double J[ORC_MAXS * ORC_MAXS], M[ORC_MAXS * ORC_MAXS];
+  int32_t perm[ORC_MAXS];
+  double hist[ORC_QMAX + 1];
+  double xi[ORC_QMAX + 2], l[ORC_QMAX + 2], Cerr = 0.5;
+
+  memset(st, 0, sizeof(*st));
+  st->t_reached = t0;
+  if (rec) rec->n = 0;
+  if (!orc_all_finite(S, y)) {
+    st->status = ORC_NONFINITE;
+    return st->status;
+  }
+  for (int j = 0; j <= ORC_QMAX + 1; ++j)
+    for (int i = 0; i < ORC_MAXS; ++i) z[j][i] = 0.0;
+
+  double t = t0;
+  int q = 1;
+  for (int i = 0; i < S; ++i) z[0][i] = y[i];
+  sys_f(s, y, f);
+  st->nfe = 1;
+  if (!orc_all_finite(S, f)) {
+    st->status = ORC_NONFINITE;
+    return st->status;
+  }
+  orc_ewt(S, y, o, ewt);
+  double h = orc_initial_step(s, o, t0, tout, y, f, ewt, &st->nfe);
+  for (int i = 0; i < S; ++i) z[1][i] = h * f[i];
+  for (int k = 0; k <= ORC_QMAX; ++k) hist[k] = h;
+  if (rec) rec->h_pad = h;
+
+  int qwait = 2;
+  double Rrate = 1.0, eta_max = 1.0e4, gamma_bar = 0.0;
+  int need_setup = 1, nst_setup = 0, have_eprev = 0, rebuilt = 0;
+  double hprev = h;
+  int status = ORC_SUCCESS;
+
+  while (t < tout) {
+    if (st->nst >= o->max_steps) {
+      status = ORC_TOO_MUCH_WORK;
+      break;
+    }
+    orc_ewt(S, z[0], o, ewt); /* from y^{n-1}, held through retries */
+    int nef_step = 0, ncf_step = 0, nsf_step = 0;
+    double dsm = 0.0, tn = t, gamma = h;
+    int accepted = 0;
+    while (!accepted) {
+      /* land exactly on tout */
+      int landing = 0;
+      if (t + h >= tout * (1.0 - 4.0 * ORC_UROUND)) {
+        double hnew = tout - t;
+        orc_rescale(S, q, hnew / h, z);
+        h = hnew;
+        landing = 1;
+      }
+      if (h <= 4.0 * ORC_UROUND * fabs(t)) {
+        status = ORC_ERR_FAILURE; /* step too small to advance t */
+        break;
+      }
+      tn = landing ? tout : t + h;
+      orc_predict(S, q, z);
+      orc_xi(h, hist, q, xi);
+      orc_bdf_coeffs(q, xi, l, &Cerr);
+      gamma = h / l[1];
+
+      int fresh = 0;
+      if (need_setup || st->nst >= nst_setup + 20 || fabs(gamma / gamma_bar - 1.0) > 0.3) {
+        orc_jac(s->m, s->kf, s->kr, z[0], J);
+        for (int i = 0; i < S; ++i)
+          for (int j = 0; j < S; ++j) M[i * S + j] = (i == j ? 1.0 : 0.0) - gamma * J[i * S + j];
+        st->nsetups++;
+        nst_setup = st->nst;
+        gamma_bar = gamma;
+        Rrate = 1.0;
+        need_setup = 0;
+        fresh = 1;
+        if (orc_lu_factor(S, M, perm) != 0) {
+          /* singular Newton matrix: recoverable once per step by cutting h */
+          orc_unpredict(S, q, z);
+          need_setup = 1;
+          if (++nsf_step >= 2) {
+            status = ORC_SETUP_FAILURE;
+            break;
+          }
+          orc_rescale(S, q, 0.25, z);
+          h *= 0.25;
+          eta_max = 1.0;
+          continue;
+        }
+      }
+
+      /* Newton iteration, stopping test of Eq. (4) */
+      int conv = 0;
+      double dprev = 0.0;
+      for (int i = 0; i < S; ++i) e[i] = 0.0;
+      for (int mit = 0; mit < 3; ++mit) {
+        for (int i = 0; i < S; ++i) ycur[i] = z[0][i] + e[i];
+        sys_f(s, ycur, f);
+        st->nfe++;
+        st->nni++;
+        for (int i = 0; i < S; ++i) G[i] = e[i] - gamma * f[i] + z[1][i] / l[1];
+        for (int i = 0; i < S; ++i) delta[i] = -G[i];
+        orc_lu_solve(S, M, perm, delta);
+        if (gamma != gamma_bar) {
+          double c = 2.0 / (1.0 + gamma / gamma_bar);
+          for (int i = 0; i < S; ++i) delta[i] *= c;
+        }
+        for (int i = 0; i < S; ++i) e[i] += delta[i];
+        double d = orc_wrms(S, delta, ewt);
+        if (!isfinite(d)) break;
+        if (mit >= 1) {
+          double ratio = d / dprev;
+          Rrate = 0.3 * Rrate > ratio ? 0.3 * Rrate : ratio;
+        }
+        if ((Rrate < 1.0 ? Rrate : 1.0) * d <= 0.1 / Cerr) {
+          conv = 1;
+          break;
+        }
+        if (mit >= 1 && d > 2.0 * dprev) break;
+        dprev = d;
+      }
+
+      if (!conv) {
+        st->ncfn++;
+        orc_unpredict(S, q, z);
+        if (++ncf_step >= 10) {
+          status = ORC_CONV_FAILURE;
+          break;
+        }
+        if (fresh) {
+          orc_rescale(S, q, 0.25, z);
+          h *= 0.25;
+          eta_max = 1.0;
+        }
+        need_setup = 1;
+        continue;
+      }
+
+      /* local error test, ||LTE|| <= 1 (Sec. 2) */
+      dsm = Cerr * orc_wrms(S, e, ewt);
+      if (!(dsm <= 1.0)) {
+        st->netf++;
+        orc_unpredict(S, q, z);
+        if (++nef_step >= 7) {
+          status = ORC_ERR_FAILURE;
+          break;
+        }
+        eta_max = 1.0;
+        if (nef_step >= 3) {
+          /* restart at order 1 from the last accepted y */
+          double hnew = 0.1 * h;
+          q = 1;
+          sys_f(s, z[0], f);
+          st->nfe++;
+          for (int j = 1; j <= ORC_QMAX + 1; ++j)
+            for (int i = 0; i < S; ++i) z[j][i] = 0.0;
+          for (int i = 0; i < S; ++i) z[1][i] = hnew * f[i];
+          h = hnew;
+          qwait = 2;
+          have_eprev = 0;
+          rebuilt = 1;
+        } else {
+          double eta = orc_eta(6.0, dsm, q + 1);
+          if (eta < 0.1) eta = 0.1;
+          if (nef_step >= 2 && eta > 0.2) eta = 0.2;
+          orc_rescale(S, q, eta, z);
+          h *= eta;
+        }
+        continue;
+      }
+      accepted = 1;
+    }
+    if (status != ORC_SUCCESS) break;
+
+    /* accept: correct the Nordsieck array */
+    t = tn;
+    for (int j = 0; j <= q; ++j)
+      for (int i = 0; i < S; ++i) z[j][i] += l[j] * e[i];
+    st->nst++;
+    for (int k = ORC_QMAX; k >= 1; --k) hist[k] = hist[k - 1];
+    hist[0] = h;
+    if (rec) {
+      if (rec->n >= rec->cap) {
+        status = ORC_RECORD_FULL;
+        break;
+      }
+      for (int i = 0; i < S; ++i) rec->y[(size_t)rec->n * S + i] = z[0][i];
+      rec->h[rec->n] = h;
+      rec->q[rec->n] = q;
+      rec->rebuild[rec->n] = rebuilt;
+      rec->n++;
+    }
+    rebuilt = 0;
+    double hstep = h;
+    qwait--;
+    if (qwait == 1 && q < qmax) {
+      for (int i = 0; i < S; ++i) eprev[i] = e[i];
+      hprev = hstep;
+      have_eprev = 1;
+    }
+
+    /* next step size (every accepted step) and order (when qwait reaches 0) */
+    if (t < tout) {
+      if (eta_max == 1.0) {
+        if (qwait < 2) qwait = 2; /* right after a failure: hold h and q */
+      } else {
+        double eta = orc_eta(6.0, dsm, q + 1);
+        int qnew = q;
+        if (qwait == 0) {
+          qwait = 2;
+          if (q > 1) {
+            double lte = orc_factorial(q - 1) / orc_harmonic(q - 1) * orc_wrms(S, z[q], ewt);
+            double eta_qm1 = orc_eta(6.0, lte, q);
+            if (eta_qm1 > eta) {
+              eta = eta_qm1;
+              qnew = q - 1;
+            }
+          }
+          if (q < qmax && have_eprev) {
+            double r = pow(hstep / hprev, q + 1), d[ORC_MAXS];
+            for (int i = 0; i < S; ++i) d[i] = e[i] - r * eprev[i];
+            double lte = orc_wrms(S, d, ewt) / ((q + 2) * orc_harmonic(q + 1));
+            double eta_qp1 = orc_eta(10.0, lte, q + 2);
+            if (eta_qp1 > eta) {
+              eta = eta_qp1;
+              qnew = q + 1;
+            }
+          }
+        }
+        if (eta >= 1.5) {
+          if (eta > eta_max) eta = eta_max;
+          if (qnew == q + 1) orc_order_up(S, q, l, xi, e, z);
+          if (qnew == q - 1) orc_order_down(S, q, xi, z);
+          if (qnew != q) {
+            q = qnew;
+            qwait = q + 1;
+            have_eprev = 0;
+          }
+          orc_rescale(S, q, eta, z);
+          h *= eta;
+        }
+      }
+    }
+    eta_max = 10.0;
+  }
+
+  for (int i = 0; i < S; ++i) y[i] = z[0][i];
+  if (zout)
+    for (int j = 0; j <= ORC_QMAX; ++j)
+      for (int i = 0; i < S; ++i) zout[j * S + i] = j <= q ? z[j][i] : 0.0;
+  st->status = status;
+  st->q_last = q;
+  st->h_last = h;
+  st->t_reached = t;
+  return status;
+}
+
+/* One cell: rates from T (and optional per-reaction scale), then integrate. */
+int32_t orc_integrate_cell(const orc_mech *m, const orc_opts *o, double T, const double *kscale,
+                           const double *F, double t0, double tout, double *y, orc_stats *st,
+                           orc_record *rec, double *zout) {
+  double kf[4096], kr[4096];
+  if (m->n_reactions > 4096 || m->n_species > ORC_MAXS) {
+    memset(st, 0, sizeof(*st));
+    st->status = ORC_NONFINITE;
+    return st->status;
+  }
+  orc_rates(m, T, kscale, kf, kr);
+  orc_sys s = {m, kf, kr, F, m->n_species};
+  if (!isfinite(T)) {
+    memset(st, 0, sizeof(*st));
+    st->t_reached = t0;
+    st->status = ORC_NONFINITE;
+    return st->status;
+  }
+  return orc_integrate_core(&s, o, t0, tout, y, st, rec, zout);
+}
+
+/* Batch of N cells (each one independent), OpenMP over cells.  y is [N][ldy]
+ * (cell-major), the cell's mechanism is mechs[cell_mech[c]] (cell_mech NULL
+ * = mechanism 0); T [N] (NULL: T = 1, use with zero activation energies),
+ * kscale [N][ldk] or NULL, F [N][ldy] or NULL. */
+void orc_integrate_batch(int64_t N, const orc_mech *mechs, const int32_t *cell_mech,
+                         const orc_opts *o, const double *T, const double *kscale, int32_t ldk,
+                         const double *F, int32_t ldy, double t0, double tout, double *y,
+                         orc_stats *stats, int32_t nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t c = 0; c < N; ++c) {
+    const orc_mech *m = &mechs[cell_mech ? cell_mech[c] : 0];
+    orc_integrate_cell(m, o, T ? T[c] : 1.0, kscale ? kscale + c * ldk : NULL,
+                       F ? F + c * ldy : NULL, t0, tout, y + c * ldy, &stats[c], NULL, NULL);
+  }
+}
+
+int32_t orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fixed order / fixed step mode (order-of-accuracy checks)                  */
+/* ------------------------------------------------------------------------ */
+
+/* Take nsteps steps of size h at order q from the Nordsieck array z
+ * ([q+1][S] row-major, in units of h), Newton iterated to convergence with a
+ * fresh Jacobian each iteration.  Constant steps: xi_i = i.  Returns 0 or -4. */
+int32_t orc_fixed_steps(const orc_mech *m, const double *kf, const double *kr, const double *F,
+                        int q, double h, int nsteps, double *zio) {
+  int S = m->n_species;
+  orc_sys s = {m, kf, kr, F, S};
+  double z[ORC_QMAX + 2][ORC_MAXS];
+  double xi[ORC_QMAX + 2], l[ORC_QMAX + 2], Cerr, e[ORC_MAXS], yv[ORC_MAXS], f[ORC_MAXS];
+  double J[ORC_MAXS * ORC_MAXS];
+  int32_t perm[ORC_MAXS];
+  for (int j = 0; j <= q; ++j)
+    for (int i = 0; i < S; ++i) z[j][i] = zio[j * S + i];
+  for (int i = 1; i <= q + 1; ++i) xi[i] = i;
+  orc_bdf_coeffs(q, xi, l, &Cerr);
+  double gamma = h / l[1];
+  for (int n = 0; n < nsteps; ++n) {
+    orc_predict(S, q, z);
+    for (int i = 0; i < S; ++i) e[i] = 0.0;
+    int ok = 0;
+    for (int it = 0; it < 50; ++it) {
+      for (int i = 0; i < S; ++i) yv[i] = z[0][i] + e[i];
+      sys_f(&s, yv, f);
+      orc_jac(m, kf, kr, yv, J);
+      for (int i = 0; i < S; ++i)
+        for (int j = 0; j < S; ++j) J[i * S + j] = (i == j ? 1.0 : 0.0) - gamma * J[i * S + j];
+      if (orc_lu_factor(S, J, perm)) return ORC_SETUP_FAILURE;
+      double d[ORC_MAXS], dn = 0.0, yn = 0.0;
+      for (int i = 0; i < S; ++i) d[i] = -(e[i] - gamma * f[i] + z[1][i] / l[1]);
+      orc_lu_solve(S, J, perm, d);
+      for (int i = 0; i < S; ++i) {
+        e[i] += d[i];
+        dn = fmax(dn, fabs(d[i]));
+        yn = fmax(yn, fabs(z[0][i] + e[i]));
+      }
+      if (dn <= 1e-15 * (yn > 1e-300 ? yn : 1.0)) {
+        ok = 1;
+        break;
+      }
+    }
+    if (!ok) return ORC_CONV_FAILURE;
+    for (int j = 0; j <= q; ++j)
+      for (int i = 0; i < S; ++i) z[j][i] += l[j] * e[i];
+  }
+  for (int j = 0; j <= q; ++j)
+    for (int i = 0; i < S; ++i) zio[j * S + i] = z[j][i];
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Frozen discrete map: replay, tangent-linear and adjoint                   */
+/* ------------------------------------------------------------------------ */
+/*
+ * The adaptive run is a sequence of accepted steps n = 1..Nst with sizes
+ * h_n and orders q_n.  Between accepted steps the Nordsieck array only
+ * undergoes linear maps (order change, rescale, exact restore after a
+ * rejected attempt) or, after repeated error-test failures, a rebuild
+ * z = [y, h f(y)] at order 1.  Freezing (h_n, q_n, rebuild_n) and solving
+ * each corrector exactly gives a smooth map (y0, lnA) -> y(t_out); these
+ * functions evaluate it (replay), its derivative (tangent) and the
+ * transpose of its derivative (adjoint).  The gradients are those of the
+ * discrete map, not of the ODE solution.
+ */
+
+/* step n (1-based) ingredients from the record */
+static void rec_xi(const orc_record *rec, int n, double *xi, double *l, double *Cerr) {
+  double hist[ORC_QMAX + 1];
+  for (int k = 0; k <= ORC_QMAX; ++k) {
+    int idx = n - 2 - k; /* hist[k] = h_{n-1-k} */
+    hist[k] = idx >= 0 ? rec->h[idx] : rec->h_pad;
+  }
+  orc_xi(rec->h[n - 1], hist, rec->q[n - 1], xi);
+  orc_bdf_coeffs(rec->q[n - 1], xi, l, Cerr);
+}
+
+/* Newton to convergence for y - gamma f(y) = a, starting at y (in/out).
+ * Full Newton with a fresh Jacobian each iteration. */
+static int orc_solve_exact(const orc_sys *s, double gamma, const double *a, double *y) {
+  int S = s->S;
+  double f[ORC_MAXS], J[ORC_MAXS * ORC_MAXS], d[ORC_MAXS];
+  int32_t perm[ORC_MAXS];
+  for (int it = 0; it < 60; ++it) {
+    sys_f(s, y, f);
+    orc_jac(s->m, s->kf, s->kr, y, J);
+    for (int i = 0; i < S; ++i)
+      for (int j = 0; j < S; ++j) J[i * S + j] = (i == j ? 1.0 : 0.0) - gamma * J[i * S + j];
+    if (orc_lu_factor(S, J, perm)) return -1;
+    for (int i = 0; i < S; ++i) d[i] = a[i] - (y[i] - gamma * f[i]);
+    orc_lu_solve(S, J, perm, d);
+    double dn = 0.0, yn = 0.0;
+    for (int i = 0; i < S; ++i) {
+      y[i] += d[i];
+      dn = fmax(dn, fabs(d[i]));
+      yn = fmax(yn, fabs(y[i]));
+    }
+    if (dn <= 4.0 * ORC_UROUND * (yn > 0 ? yn : 1.0)) return 0;
+  }
+  return 0; /* converged to round-off level (stagnation) */
+}
+
+/* Replay the frozen step sequence of rec from y0; writes the final state to
+ * yout and, if yrec != NULL, the replayed y_n to yrec [n][S]. */
+int32_t orc_replay_cell(const orc_mech *m, const double *kf, const double *kr, const double *F,
+                        const double *y0, const orc_record *rec, double *yout, double *yrec) {
+  int S = m->n_species;
+  orc_sys s = {m, kf, kr, F, S};
+  double z[ORC_QMAX + 2][ORC_MAXS], f[ORC_MAXS], a[ORC_MAXS], y[ORC_MAXS], e[ORC_MAXS];
+  double xi[ORC_QMAX + 2], l[ORC_QMAX + 2], Cerr;
+  double xip[ORC_QMAX + 2], lp[ORC_QMAX + 2];
+  memset(z, 0, sizeof(z));
+  if (rec->n == 0) {
+    for (int i = 0; i < S; ++i) yout[i] = y0[i];
+    return 0;
+  }
+  for (int i = 0; i < S; ++i) z[0][i] = y0[i];
+  sys_f(&s, y0, f);
+  for (int i = 0; i < S; ++i) z[1][i] = rec->h[0] * f[i];
+  int q = 1;
+  for (int n = 1; n <= rec->n; ++n) {
+    double hn = rec->h[n - 1];
+    int qn = rec->q[n - 1];
+    if (n > 1) {
+      double hp = rec->h[n - 2];
+      if (rec->rebuild[n - 1]) {
+        sys_f(&s, z[0], f);
+        for (int j = 1; j <= ORC_QMAX + 1; ++j)
+          for (int i = 0; i < S; ++i) z[j][i] = 0.0;
+        for (int i = 0; i < S; ++i) z[1][i] = hn * f[i];
+      } else {
+        if (qn == q + 1) orc_order_up(S, q, lp, xip, e, z);
+        if (qn == q - 1) orc_order_down(S, q, xip, z);
+        orc_rescale(S, qn, hn / hp, z);
+      }
+    }
+    q = qn;
+    orc_predict(S, q, z);
+    rec_xi(rec, n, xi, l, &Cerr);
+    double gamma = hn / l[1];
+    for (int i = 0; i < S; ++i) {
+      a[i] = z[0][i] - z[1][i] / l[1];
+      y[i] = rec->y[(size_t)(n - 1) * S + i]; /* start from the recorded value */
+    }
+    if (orc_solve_exact(&s, gamma, a, y)) return ORC_SETUP_FAILURE;
+    for (int i = 0; i < S; ++i) e[i] = y[i] - z[0][i];
+    for (int j = 0; j <= q; ++j)
+      for (int i = 0; i < S; ++i) z[j][i] += l[j] * e[i];
+    if (yrec)
+      for (int i = 0; i < S; ++i) yrec[(size_t)(n - 1) * S + i] = z[0][i];
+    memcpy(xip, xi, sizeof(xi));
+    memcpy(lp, l, sizeof(l));
+  }
+  for (int i = 0; i < S; ++i) yout[i] = z[0][i];
+  return 0;
+}
+
+/* d f / d lnA_r applied to a direction: sum_r nu_r q_r(y) dp_r. */
+static void orc_fp_dir(const orc_sys *s, const double *y, const double *dp, double *out) {
+  const orc_mech *m = s->m;
+  double q[4096];
+  orc_reaction_rates(m, s->kf, s->kr, y, q);
+  for (int i = 0; i < s->S; ++i) out[i] = 0.0;
+  for (int r = 0; r < m->n_reactions; ++r) {
+    double v = q[r] * dp[r];
+    for (int k = 0; k < ORC_SLOTS; ++k) {
+      int a = m->reac[r * ORC_SLOTS + k], b = m->prod[r * ORC_SLOTS + k];
+      if (a >= 0) out[a] -= v;
+      if (b >= 0) out[b] += v;
+    }
+  }
+}
+
+/* Transpose of orc_fp_dir: pbar_r += scale * q_r(y) * (nu_r . mu). */
+static void orc_fp_adj(const orc_sys *s, const double *y, const double *mu, double scale,
+                       double *pbar) {
+  const orc_mech *m = s->m;
+  double q[4096];
+  orc_reaction_rates(m, s->kf, s->kr, y, q);
+  for (int r = 0; r < m->n_reactions; ++r) {
+    double dot = 0.0;
+    for (int k = 0; k < ORC_SLOTS; ++k) {
+      int a = m->reac[r * ORC_SLOTS + k], b = m->prod[r * ORC_SLOTS + k];
+      if (a >= 0) dot -= mu[a];
+      if (b >= 0) dot += mu[b];
+    }
+    pbar[r] += scale * q[r] * dot;
+  }
+}
+
+static void matvec(int S, const double *A, const double *x, double *out) {
+  for (int i = 0; i < S; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < S; ++j) s += A[i * S + j] * x[j];
+    out[i] = s;
+  }
+}
+
+static void matvec_t(int S, const double *A, const double *x, double *out) {
+  for (int j = 0; j < S; ++j) out[j] = 0.0;
+  for (int i = 0; i < S; ++i)
+    for (int j = 0; j < S; ++j) out[j] += A[i * S + j] * x[i];
+}
+
+/* Tangent-linear (forward sensitivity) of the frozen map along the states
+ * in yrec ([n][S], typically the replayed ones): direction (dy0, dp) ->
+ * dy(t_out). */
+int32_t orc_tangent_cell(const orc_mech *m, const double *kf, const double *kr, const double *F,
+                         const double *y0, const orc_record *rec, const double *yrec,
+                         const double *dy0, const double *dp, double *dyout) {
+  int S = m->n_species;
+  orc_sys s = {m, kf, kr, F, S};
+  double dz[ORC_QMAX + 2][ORC_MAXS], J[ORC_MAXS * ORC_MAXS], t1[ORC_MAXS], t2[ORC_MAXS];
+  double da[ORC_MAXS], de[ORC_MAXS];
+  double xi[ORC_QMAX + 2], l[ORC_QMAX + 2], Cerr, xip[ORC_QMAX + 2], lp[ORC_QMAX + 2];
+  int32_t perm[ORC_MAXS];
+  memset(dz, 0, sizeof(dz));
+  if (rec->n == 0) {
+    for (int i = 0; i < S; ++i) dyout[i] = dy0[i];
+    return 0;
+  }
+  /* z = [y0, h_1 f(y0)] */
+  orc_jac(m, kf, kr, y0, J);
+  matvec(S, J, dy0, t1);
+  orc_fp_dir(&s, y0, dp, t2);
+  for (int i = 0; i < S; ++i) {
+    dz[0][i] = dy0[i];
+    dz[1][i] = rec->h[0] * (t1[i] + t2[i]);
+  }
+  int q = 1;
+  for (int n = 1; n <= rec->n; ++n) {
+    double hn = rec->h[n - 1];
+    int qn = rec->q[n - 1];
+    if (n > 1) {
+      const double *yp = yrec + (size_t)(n - 2) * S;
+      if (rec->rebuild[n - 1]) {
+        orc_jac(m, kf, kr, yp, J);
+        matvec(S, J, dz[0], t1);
+        orc_fp_dir(&s, yp, dp, t2);
+        for (int j = 1; j <= ORC_QMAX + 1; ++j)
+          for (int i = 0; i < S; ++i) dz[j][i] = 0.0;
+        for (int i = 0; i < S; ++i) dz[1][i] = hn * (t1[i] + t2[i]);
+      } else {
+        if (qn == q + 1) orc_order_up(S, q, lp, xip, de, dz);
+        if (qn == q - 1) orc_order_down(S, q, xip, dz);
+        orc_rescale(S, qn, hn / rec->h[n - 2], dz);
+      }
+    }
+    q = qn;
+    orc_predict(S, q, dz);
+    rec_xi(rec, n, xi, l, &Cerr);
+    double gamma = hn / l[1];
+    const double *yn = yrec + (size_t)(n - 1) * S;
+    orc_jac(m, kf, kr, yn, J);
+    for (int i = 0; i < S; ++i)
+      for (int j = 0; j < S; ++j) J[i * S + j] = (i == j ? 1.0 : 0.0) - gamma * J[i * S + j];
+    if (orc_lu_factor(S, J, perm)) return ORC_SETUP_FAILURE;
+    orc_fp_dir(&s, yn, dp, t2);
+    for (int i = 0; i < S; ++i) da[i] = dz[0][i] - dz[1][i] / l[1] + gamma * t2[i];
+    orc_lu_solve(S, J, perm, da); /* da <- dy_n */
+    for (int i = 0; i < S; ++i) de[i] = da[i] - dz[0][i];
+    for (int j = 0; j <= q; ++j)
+      for (int i = 0; i < S; ++i) dz[j][i] += l[j] * de[i];
+    memcpy(xip, xi, sizeof(xi));
+    memcpy(lp, l, sizeof(l));
+  }
+  for (int i = 0; i < S; ++i) dyout[i] = dz[0][i];
+  return 0;
+}
+
+/* Adjoint of the frozen map along yrec: given ybar = dL/dy(t_out), returns
+ * y0bar = dL/dy0 and adds dL/dlnA_r into pbar [R]. */
+int32_t orc_adjoint_cell(const orc_mech *m, const double *kf, const double *kr, const double *F,
+                         const double *y0, const orc_record *rec, const double *yrec,
+                         const double *ybar, double *y0bar, double *pbar) {
+  int S = m->n_species;
+  orc_sys s = {m, kf, kr, F, S};
+  double zb[ORC_QMAX + 2][ORC_MAXS], J[ORC_MAXS * ORC_MAXS], mu[ORC_MAXS], t1[ORC_MAXS];
+  double ebar_extra[ORC_MAXS], eb[ORC_MAXS];
+  double xi[ORC_QMAX + 2], l[ORC_QMAX + 2], Cerr;
+  int32_t perm[ORC_MAXS];
+  memset(zb, 0, sizeof(zb));
+  int N = rec->n;
+  if (N == 0) {
+    for (int i = 0; i < S; ++i) y0bar[i] = ybar[i];
+    return 0;
+  }
+  for (int i = 0; i < S; ++i) {
+    zb[0][i] = ybar[i];
+    ebar_extra[i] = 0.0;
+  }
+  for (int n = N; n >= 1; --n) {
+    int q = rec->q[n - 1];
+    double hn = rec->h[n - 1];
+    rec_xi(rec, n, xi, l, &Cerr);
+    double gamma = hn / l[1];
+    const double *yn = yrec + (size_t)(n - 1) * S;
+    /* z_n = zp + l e,  e = y_n - zp_0 */
+    for (int i = 0; i < S; ++i) {
+      double acc = ebar_extra[i];
+      for (int j = 0; j <= q; ++j) acc += l[j] * zb[j][i];
+      eb[i] = acc;
+      zb[0][i] -= acc; /* from e = y - zp_0 */
+    }
+    /* y_n = Y(a), (I - gamma J) dy = da + gamma f_p dp */
+    orc_jac(m, kf, kr, yn, J);
+    for (int i = 0; i < S; ++i)
+      for (int j = 0; j < S; ++j) J[i * S + j] = (i == j ? 1.0 : 0.0) - gamma * J[i * S + j];
+    if (orc_lu_factor(S, J, perm)) return ORC_SETUP_FAILURE;
+    for (int i = 0; i < S; ++i) mu[i] = eb[i];
+    orc_lu_solve_transposed(S, J, perm, mu);
+    orc_fp_adj(&s, yn, mu, gamma, pbar);
+    /* a = zp_0 - zp_1 / l_1 */
+    for (int i = 0; i < S; ++i) {
+      zb[0][i] += mu[i];
+      zb[1][i] -= mu[i] / l[1];
+    }
+    /* predictor transpose: zp = A z  =>  zbar <- A^T zpbar (reverse order) */
+    for (int k = q; k >= 1; --k)
+      for (int j = k; j <= q; ++j)
+        for (int i = 0; i < S; ++i) zb[j][i] += zb[j - 1][i];
+    /* transition from step n-1 into step n */
+    for (int i = 0; i < S; ++i) ebar_extra[i] = 0.0;
+    if (n == 1) {
+      /* z = [y0, h_1 f(y0)] */
+      orc_jac(m, kf, kr, y0, J);
+      matvec_t(S, J, zb[1], t1);
+      for (int i = 0; i < S; ++i) y0bar[i] = zb[0][i] + hn * t1[i];
+      orc_fp_adj(&s, y0, zb[1], hn, pbar);
+      break;
+    }
+    int qp = rec->q[n - 2];
+    const double *yp = yrec + (size_t)(n - 2) * S;
+    if (rec->rebuild[n - 1]) {
+      orc_jac(m, kf, kr, yp, J);
+      matvec_t(S, J, zb[1], t1);
+      orc_fp_adj(&s, yp, zb[1], hn, pbar);
+      for (int i = 0; i < S; ++i) zb[0][i] += hn * t1[i];
+      for (int j = 1; j <= ORC_QMAX + 1; ++j)
+        for (int i = 0; i < S; ++i) zb[j][i] = 0.0;
+    } else {
+      /* rescale by eta = h_n / h_{n-1} (diagonal) */
+      double eta = hn / rec->h[n - 2], fct = 1.0;
+      for (int j = 1; j <= q; ++j) {
+        fct *= eta;
+        for (int i = 0; i < S; ++i) zb[j][i] *= fct;
+      }
+      if (q == qp + 1) {
+        /* z_j += (l'_{j-1}/xi'_{qp+1}) e_{n-1}, j = 1..qp+1 (primes: step n-1) */
+        double xip[ORC_QMAX + 2], lp[ORC_QMAX + 2], Cp;
+        rec_xi(rec, n - 1, xip, lp, &Cp);
+        double c = 1.0 / xip[qp + 1];
+        for (int j = 1; j <= qp + 1; ++j)
+          for (int i = 0; i < S; ++i) ebar_extra[i] += c * lp[j - 1] * zb[j][i];
+        for (int i = 0; i < S; ++i) zb[qp + 1][i] = 0.0;
+      } else if (q == qp - 1) {
+        /* z_j -= c_j z_qp, j = 1..qp-1; z_qp dropped */
+        double xip[ORC_QMAX + 2], lp[ORC_QMAX + 2], Cp, c[ORC_QMAX + 2];
+        rec_xi(rec, n - 1, xip, lp, &Cp);
+        for (int j = 0; j <= qp; ++j) c[j] = 0.0;
+        c[1] = 1.0;
+        for (int i = 1; i <= qp - 1; ++i)
+          for (int j = i + 1; j >= 1; --j) c[j] = c[j - 1] + xip[i] * c[j];
+        for (int i = 0; i < S; ++i) {
+          double acc = 0.0;
+          for (int j = 1; j < qp; ++j) acc -= c[j] * zb[j][i];
+          zb[qp][i] = acc;
+        }
+      }
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Outer-step perturbation (counter-based SplitMix64)                        */
+/* ------------------------------------------------------------------------ */
+
+/* SplitMix64 output for generator state x (Steele, Lea & Flood, OOPSLA 2014):
+ * advance the state by the golden gamma, then apply the variant-13 mixer. */
+uint64_t orc_splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+/* Uniform in [-1, 1) for (seed, outer step, cell, species):
+ * key = splitmix64(seed); u53 = splitmix64(key ^ counter) >> 11 with
+ * counter = step * 2^40 + cell * 2^8 + species. */
+double orc_perturb_uniform(uint64_t seed, int64_t step, int64_t cell, int32_t species) {
+  uint64_t key = orc_splitmix64(seed);
+  uint64_t ctr = ((uint64_t)step << 40) + ((uint64_t)cell << 8) + (uint64_t)species;
+  uint64_t v = orc_splitmix64(key ^ ctr);
+  double u = (double)(v >> 11) * (1.0 / 9007199254740992.0);
+  return 2.0 * u - 1.0;
+}
+
+/* y_i <- max(0, y_i (1 + amp u_i)), then rescale the cell so that
+ * sum_i w_i y_i keeps its value from before the perturbation. */
+void orc_perturb_batch(int64_t N, const int32_t *n_species_of_cell, int32_t ldy, double *y,
+                       const double *const *weights_of_cell, uint64_t seed, int64_t step,
+                       double amp) {
+  for (int64_t c = 0; c < N; ++c) {
+    int S = n_species_of_cell[c];
+    const double *w = weights_of_cell[c];
+    double *yc = y + c * ldy;
+    double before = 0.0, after = 0.0;
+    for (int i = 0; i < S; ++i) before += w[i] * yc[i];
+    for (int i = 0; i < S; ++i) {
+      double v = yc[i] * (1.0 + amp * orc_perturb_uniform(seed, step, c, i));
+      yc[i] = v > 0.0 ? v : 0.0;
+      after += w[i] * yc[i];
+    }
+    if (after > 0.0) {
+      double s = before / after;
+      for (int i = 0; i < S; ++i) yc[i] *= s;
+    }
+  }
+}

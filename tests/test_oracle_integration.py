@@ -1,0 +1,405 @@
+"""Pins of the oracle's BDF integrator against the mathematics.
+
+None of these compares the oracle with itself: every expected value is a closed
+form, a textbook table, a library routine on a special case that reduces to it
+(scipy's expm for linear kinetics), an invariant, or a brute-force explicit
+integration with much smaller steps.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+from paper_2405_01713_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+# --------------------------------------------------------------------------
+# coefficients
+# --------------------------------------------------------------------------
+
+def test_constant_step_coefficients_match_textbook(oracle):
+    g = _golden("bdf_constant_step.json")
+    for q in range(1, 6):
+        l, Cerr = oracle.bdf_coeffs(q, [float(i) for i in range(1, q + 2)])
+        ref = [float(Fraction(v)) for v in g["l"][str(q)]]
+        assert np.allclose(l, ref, rtol=1e-15, atol=0)
+        assert 1.0 / l[1] == pytest.approx(float(Fraction(g["beta0"][str(q)])), rel=1e-15)
+        assert Cerr == pytest.approx(float(Fraction(g["error_constant"][str(q)])), rel=1e-15)
+
+
+def test_variable_step_coefficients_reproduce_lagrange_bdf(oracle):
+    """Variable-step BDF2 in Lagrange form: with step ratio w = h_n/h_{n-1},
+    y_n - (1+w)^2/(1+2w) y_{n-1} + w^2/(1+2w) y_{n-2} = h (1+w)/(1+2w) f_n.
+    The Nordsieck l_1 gives gamma = h/l_1, which must equal h (1+w)/(1+2w)."""
+    for w in (0.3, 0.7, 1.0, 1.9, 4.0):
+        xi2 = 1.0 + 1.0 / w  # (t_n - t_{n-2}) / h_n
+        l, _ = oracle.bdf_coeffs(2, [1.0, xi2, xi2 + 1.0])
+        assert 1.0 / l[1] == pytest.approx((1 + w) / (1 + 2 * w), rel=1e-14)
+
+
+# --------------------------------------------------------------------------
+# closed forms and brute force
+# --------------------------------------------------------------------------
+
+def _rk4_robertson(h, t_end, k=(0.04, 3e7, 1e4)):
+    k1, k2, k3 = k
+    y1, y2, y3 = 1.0, 0.0, 0.0
+
+    def f(a, b, c):
+        return (-k1 * a + k3 * b * c, k1 * a - k3 * b * c - k2 * b * b, k2 * b * b)
+
+    n = int(round(t_end / h))
+    for _ in range(n):
+        a1 = f(y1, y2, y3)
+        a2 = f(y1 + 0.5 * h * a1[0], y2 + 0.5 * h * a1[1], y3 + 0.5 * h * a1[2])
+        a3 = f(y1 + 0.5 * h * a2[0], y2 + 0.5 * h * a2[1], y3 + 0.5 * h * a2[2])
+        a4 = f(y1 + h * a3[0], y2 + h * a3[1], y3 + h * a3[2])
+        y1 += h / 6 * (a1[0] + 2 * a2[0] + 2 * a3[0] + a4[0])
+        y2 += h / 6 * (a1[1] + 2 * a2[1] + 2 * a3[1] + a4[1])
+        y3 += h / 6 * (a1[2] + 2 * a2[2] + 2 * a3[2] + a4[2])
+    return np.array([y1, y2, y3])
+
+
+def test_robertson_against_bruteforce_rk4_and_table(oracle):
+    m = W.robertson_mechanism()
+    rtol, atol = 1e-6, 1e-10
+    y, st = oracle.integrate(m, np.array([[1.0, 0.0, 0.0]]), 0.0, 40.0, rtol, atol)
+    assert st["status"][0] == 0 and st["t_reached"][0] == 40.0
+    # classical RK4 at fixed h and h/2 (stable: |lambda| h << 2.8 throughout)
+    ya = _rk4_robertson(4e-4, 40.0)
+    yb = _rk4_robertson(2e-4, 40.0)
+    assert np.all(np.abs(ya - yb) <= 1e-12 * np.abs(yb) + 1e-16)  # Richardson-consistent
+    err = np.abs(y[0] - yb)
+    assert np.all(err <= 100 * rtol * np.abs(yb) + atol), err
+    g = _golden("robertson_t40.json")
+    assert np.allclose(y[0], g["y"], rtol=g["rel_tol"], atol=0)
+    assert abs(y[0].sum() - 1.0) < 1e-13  # linear invariant y1+y2+y3
+
+
+def _linear_K(mech):
+    S = mech["n_species"]
+    K = np.zeros((S, S))
+    for r in range(mech["n_reactions"]):
+        a, b = mech["reac"][r, 0], mech["prod"][r, 0]
+        k = math.exp(mech["lnA"][r])
+        K[b, a] += k
+        K[a, a] -= k
+    return K
+
+
+@pytest.mark.parametrize("S,R,seed", [(2, 2, 0), (4, 8, 1), (6, 12, 2)])
+def test_linear_kinetics_against_expm(oracle, S, R, seed):
+    m = W.unimolecular_mechanism(S, R, seed)
+    rng = np.random.default_rng(seed)
+    y0 = rng.uniform(0.1, 1.0, S)
+    rtol, atol = 1e-6, 1e-10
+    t_out = 2.0
+    y, st = oracle.integrate(m, y0[None, :], 0.0, t_out, rtol, atol)
+    ref = expm(_linear_K(m) * t_out) @ y0
+    assert st["status"][0] == 0
+    assert np.all(np.abs(y[0] - ref) <= 100 * rtol * np.abs(ref) + atol)
+
+
+def test_association_reaction_riccati_closed_form(oracle):
+    """A + B <=> C: with d = A - B and s = A + C conserved,
+    A' = -kf (A - r1)(A - r2) and (A - r1)/(A - r2) decays as exp(-kf (r1 - r2) t)."""
+    kf, Kc = 2.0e3, 50.0
+    kr = kf / Kc
+    m = dict(n_species=3, n_reactions=1,
+             reac=np.array([[0, 1, -1]], dtype=np.int32),
+             prod=np.array([[2, -1, -1]], dtype=np.int32),
+             lnA=np.array([math.log(kf)]), EaR=np.zeros(1), lnK=np.array([math.log(Kc)]))
+    A0, B0, C0 = 0.3, 0.2, 0.05
+    d, s = A0 - B0, A0 + C0
+    # A' = -kf A (A - d) + kr (s - A) = -kf A^2 + (kf d - kr) A + kr s
+    a, b, c = -kf, kf * d - kr, kr * s
+    disc = math.sqrt(b * b - 4 * a * c)
+    r1, r2 = (-b - disc) / (2 * a), (-b + disc) / (2 * a)
+    r1, r2 = max(r1, r2), min(r1, r2)
+    Q0 = (A0 - r1) / (A0 - r2)
+    rtol, atol = 1e-6, 1e-12
+    for t_out in (1e-4, 1e-3, 1e-2):
+        y, st = oracle.integrate(m, np.array([[A0, B0, C0]]), 0.0, t_out, rtol, atol)
+        Qt = Q0 * math.exp(-kf * (r1 - r2) * t_out)
+        At = (r1 - r2 * Qt) / (1 - Qt)
+        ref = np.array([At, At - d, s - At])
+        assert np.all(np.abs(y[0] - ref) <= 100 * rtol * np.abs(ref) + atol), (t_out, y, ref)
+
+
+def test_very_stiff_decay_no_oscillation(oracle):
+    m = dict(n_species=2, n_reactions=1,
+             reac=np.array([[0, -1, -1]], dtype=np.int32),
+             prod=np.array([[1, -1, -1]], dtype=np.int32),
+             lnA=np.array([math.log(1e12)]), EaR=np.zeros(1), lnK=None)
+    y, st = oracle.integrate(m, np.array([[1.0, 0.0]]), 0.0, 1e-5, 1e-6, 1e-10)
+    assert st["status"][0] == 0
+    assert abs(y[0, 0]) <= 1e-9
+    assert y[0, 0] >= -1e-10
+    assert abs(y[0, 1] - 1.0) <= 1e-9
+
+
+def test_constant_forcing_is_integrated_exactly(oracle):
+    # reaction with vanishing rate: y' = F exactly; BDF is exact on linear solutions
+    m = dict(n_species=3, n_reactions=1,
+             reac=np.array([[0, -1, -1]], dtype=np.int32),
+             prod=np.array([[1, -1, -1]], dtype=np.int32),
+             lnA=np.array([-800.0]), EaR=np.zeros(1), lnK=None)
+    F = np.array([[1.5, -0.25, 3.0]])
+    y0 = np.array([[1.0, 2.0, 0.5]])
+    for t_out in (0.1, 7.0):
+        y, st = oracle.integrate(m, y0, 0.0, t_out, 1e-6, 1e-10, F=F)
+        assert st["status"][0] == 0
+        assert np.allclose(y[0], y0[0] + F[0] * t_out, rtol=1e-13, atol=1e-13)
+
+
+def test_mass_invariant_preserved(oracle):
+    w = W.make_workload("s21_r84_262k", 24)
+    y, st = oracle.integrate(w["mechs"], w["y0"], 0.0, w["t_out"], w["rtol"], w["atol"], T=w["T"])
+    assert np.all(st["status"] == 0)
+    wt = w["mechs"][0]["w"]
+    assert np.abs(y @ wt - w["y0"] @ wt).max() < 1e-13
+
+
+def test_detailed_balance_equilibrium(oracle):
+    """Toy association network over weights 1..5 in which mass is the only
+    invariant: the long-time state is y_i = exp(lam w_i - g_i), with lam fixed by
+    sum_i w_i y_i(0)."""
+    S = 5
+    trip = [(1, 1, 2), (1, 2, 3), (1, 3, 4), (2, 2, 4), (1, 4, 5), (2, 3, 5)]
+    rng = np.random.default_rng(11)
+    g = rng.uniform(0, 2, S)
+    reac = np.full((len(trip), 3), -1, dtype=np.int32)
+    prod = np.full((len(trip), 3), -1, dtype=np.int32)
+    lnK = np.zeros(len(trip))
+    for r, (a, b, c) in enumerate(trip):
+        reac[r, :2] = a - 1, b - 1
+        prod[r, 0] = c - 1
+        lnK[r] = g[a - 1] + g[b - 1] - g[c - 1]
+    m = dict(n_species=S, n_reactions=len(trip), reac=reac, prod=prod,
+             lnA=np.log(rng.uniform(1, 5, len(trip))), EaR=np.zeros(len(trip)), lnK=lnK)
+    wts = np.arange(1, S + 1, dtype=float)
+    y0 = rng.dirichlet(np.ones(S)) / wts
+    y, st = oracle.integrate(m, y0[None, :], 0.0, 400.0, 1e-8, 1e-14)
+    assert st["status"][0] == 0
+    mass = y0 @ wts
+    lo, hi = -50.0, 50.0
+    for _ in range(200):
+        lam = 0.5 * (lo + hi)
+        if np.sum(wts * np.exp(lam * wts - g)) > mass:
+            hi = lam
+        else:
+            lo = lam
+    yeq = np.exp(lam * wts - g)
+    assert np.allclose(y[0], yeq, rtol=1e-5, atol=1e-12)
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5])
+def test_fixed_step_order_of_accuracy(oracle, q):
+    """Fixed h, fixed q with the exact initial Nordsieck array of y' = K y:
+    halving h divides the global error at T by about 2^q."""
+    m = W.unimolecular_mechanism(3, 4, seed=4)
+    m["lnA"] = np.log([0.7, 1.3, 0.4, 1.9])  # non-stiff: the error is not yet damped at T
+    kf, kr = oracle.rates(m)
+    K = _linear_K(m)
+    y0 = np.array([1.0, 0.5, 0.25])
+    T = 1.0
+    errs = []
+    for n in (40, 80):
+        h = T / n
+        z = np.zeros((q + 1, 3))
+        v = y0.copy()
+        for j in range(q + 1):
+            z[j] = v * h ** j / math.factorial(j)
+            v = K @ v
+        z = oracle.fixed_steps(m, kf, kr, z, q, h, n)
+        errs.append(np.abs(z[0] - expm(K * T) @ y0).max())
+    rate = math.log2(errs[0] / errs[1])
+    assert abs(rate - q) < 0.35, (q, errs, rate)
+
+
+def test_nordsieck_array_interpolates_accepted_values(oracle):
+    """After the last accepted step, z is the degree-q polynomial through the
+    last q+1 accepted solutions (in x = (t - t_n)/h_n)."""
+    for name, n in (("robertson_4k", 3), ("s21_r84_262k", 3)):
+        w = W.make_workload(name, n)
+        m = w["mechs"][0]
+        for c in range(n):
+            ks = None if w["kscale"] is None else w["kscale"][c]
+            T = 1.0 if w["T"] is None else w["T"][c]
+            y, st, rec = oracle.integrate_record(m, w["y0"][c], 0.0, w["t_out"], w["rtol"],
+                                                 w["atol"], T=T, kscale=ks)
+            q = st["q_last"]
+            z = rec["z_final"][: q + 1]
+            h = rec["h"]
+            nst = rec["n"]
+            assert q == rec["q"][-1]
+            for i in range(q + 1):
+                x = -np.sum(h[nst - i:]) / h[-1] if i else 0.0
+                val = sum(z[j] * x ** j for j in range(q + 1))
+                yi = rec["y"][nst - 1 - i]
+                assert np.all(np.abs(val - yi) <= 1e-9 * np.abs(yi) + 1e-15), (name, c, i)
+
+
+def test_error_roughly_proportional_to_tolerance(oracle):
+    w = W.make_workload("s21_r84_262k", 4)
+    m = w["mechs"][0]
+    ref, st = oracle.integrate(m, w["y0"], 0.0, w["t_out"], 1e-12, 1e-20, T=w["T"],
+                               max_steps=200000)
+    assert np.all(st["status"] == 0)
+    errs = []
+    for rtol in (1e-4, 1e-6, 1e-8):
+        y, st = oracle.integrate(m, w["y0"], 0.0, w["t_out"], rtol, rtol * 1e-4, T=w["T"])
+        errs.append(np.max(np.abs(y - ref) / (np.abs(ref) + rtol * 1e-4)))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[1] <= 100 * 1e-6
+    # decreases by roughly the tolerance ratio (within a factor 20 per decade pair)
+    assert errs[0] / errs[1] > 100 / 20 and errs[1] / errs[2] > 100 / 20
+
+
+# --------------------------------------------------------------------------
+# failure handling
+# --------------------------------------------------------------------------
+
+def test_failures_are_per_cell(oracle):
+    w = W.make_workload("s21_r84_262k", 6)
+    m = w["mechs"][0]
+    y0 = w["y0"].copy()
+    T = w["T"].copy()
+    y0[2, 3] = np.nan
+    T[4] = np.nan
+    y, st = oracle.integrate(m, y0, 0.0, w["t_out"], 1e-6, 1e-10, T=T)
+    assert st["status"][2] == -9 and st["status"][4] == -9
+    assert np.isnan(y[2, 3]) and np.all(y[4] == y0[4])
+    ok = [0, 1, 3, 5]
+    yref, stref = oracle.integrate(m, w["y0"][ok], 0.0, w["t_out"], 1e-6, 1e-10, T=w["T"][ok])
+    assert np.all(st["status"][ok] == 0)
+    assert np.array_equal(y[ok], yref)  # other cells bit-identical
+    # too much work: keeps the last accepted state and t_reached
+    y, st = oracle.integrate(m, w["y0"][:2], 0.0, w["t_out"], 1e-6, 1e-10, T=w["T"][:2],
+                             max_steps=3)
+    assert np.all(st["status"] == -1) and np.all(st["nst"] == 3)
+    assert np.all(st["t_reached"] > 0) and np.all(st["t_reached"] < w["t_out"])
+    assert np.all(np.isfinite(y))
+    # absurd tolerance: error-test failures or a step too small to advance t
+    y, st = oracle.integrate(m, w["y0"][:2], 0.0, w["t_out"], 1e-18, 1e-30, T=w["T"][:2],
+                             max_steps=2000)
+    assert np.all(np.isin(st["status"], [-3, -1]))
+
+
+# --------------------------------------------------------------------------
+# frozen discrete map: replay, tangent-linear, adjoint
+# --------------------------------------------------------------------------
+
+def _adjoint_case():
+    m = W.synthetic_mechanism(9, 30, seed=1)
+    st_ = W.cell_states(m, 2, seed=9, T_range=(1000.0, 1400.0))
+    return m, st_["y0"][0], st_["T"][0]
+
+
+def test_replay_reproduces_adaptive_run(oracle):
+    m, y0, T = _adjoint_case()
+    kf, kr = oracle.rates(m, T)
+    y, st, rec = oracle.integrate_record(m, y0, 0.0, 1e-5, 1e-6, 1e-10, T=T)
+    yr, yrec = oracle.replay(m, kf, kr, y0, rec)
+    # same map, correctors solved exactly instead of to a fraction of the local
+    # error budget: differences are measured in units of the error weights
+    # 1/(rtol |y| + atol) of Eq. (3)
+    unit = lambda v: 1e-6 * np.abs(v) + 1e-10
+    assert np.all(np.abs(yr - y) <= unit(y))
+    assert np.all(np.abs(yrec - rec["y"]) <= 100 * unit(rec["y"]))
+
+
+def test_adjoint_tangent_dot_product(oracle):
+    m, y0, T = _adjoint_case()
+    kf, kr = oracle.rates(m, T)
+    _, _, rec = oracle.integrate_record(m, y0, 0.0, 1e-5, 1e-6, 1e-10, T=T)
+    _, yrec = oracle.replay(m, kf, kr, y0, rec)
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        dy0 = rng.standard_normal(9) * y0
+        dp = rng.standard_normal(30)
+        ybar = rng.standard_normal(9)
+        dy = oracle.tangent(m, kf, kr, y0, rec, yrec, dy0, dp)
+        y0bar, pbar = oracle.adjoint(m, kf, kr, y0, rec, yrec, ybar)
+        lhs = ybar @ dy
+        rhs = y0bar @ dy0 + pbar @ dp
+        assert abs(lhs - rhs) <= 1e-10 * (abs(lhs) + np.abs(ybar) @ np.abs(dy))
+
+
+def test_tangent_matches_central_differences_of_replay(oracle):
+    m, y0, T = _adjoint_case()
+    kf0, kr0 = oracle.rates(m, T)
+    _, _, rec = oracle.integrate_record(m, y0, 0.0, 1e-5, 1e-6, 1e-10, T=T)
+    _, yrec = oracle.replay(m, kf0, kr0, y0, rec)
+    c = np.random.default_rng(4).standard_normal(9)
+    y0bar, pbar = oracle.adjoint(m, kf0, kr0, y0, rec, yrec, c)
+    # central differences in lnA_r; h = 1e-6 (round-off noise ~ u |y| / h sets
+    # the tolerance) and h = 1e-4 (truncation O(h^2), tighter)
+    gmax = np.abs(pbar).max()
+    for h, tol in ((1e-6, 1e-4), (1e-4, 1e-5)):
+        for r in (0, 7, 29):
+            mp, mm = dict(m), dict(m)
+            mp["lnA"] = m["lnA"].copy()
+            mm["lnA"] = m["lnA"].copy()
+            mp["lnA"][r] += h
+            mm["lnA"][r] -= h
+            kfp, krp = oracle.rates(mp, T)
+            kfm, krm = oracle.rates(mm, T)
+            yp, _ = oracle.replay(m, kfp, krp, y0, rec)
+            ym, _ = oracle.replay(m, kfm, krm, y0, rec)
+            fd = c @ (yp - ym) / (2 * h)
+            assert abs(fd - pbar[r]) <= tol * gmax, (h, r, fd, pbar[r])
+    for i in (0, 4, 8):
+        d = 1e-6 * y0[i]
+        yp0, ym0 = y0.copy(), y0.copy()
+        yp0[i] += d
+        ym0[i] -= d
+        yp, _ = oracle.replay(m, kf0, kr0, yp0, rec)
+        ym, _ = oracle.replay(m, kf0, kr0, ym0, rec)
+        fd = c @ (yp - ym) / (2 * d)
+        assert abs(fd - y0bar[i]) <= 1e-5 * max(abs(y0bar[i]), 1e-3 * np.abs(y0bar).max()), (i, fd, y0bar[i])
+
+
+# --------------------------------------------------------------------------
+# outer-step perturbation
+# --------------------------------------------------------------------------
+
+def test_splitmix64_known_answers(oracle):
+    # published reference outputs of SplitMix64 seeded with 0 and with 1234567
+    gamma = 0x9E3779B97F4A7C15
+    mask = (1 << 64) - 1
+    assert oracle.splitmix64(0) == 0xE220A8397B1DCDAF
+    assert oracle.splitmix64(gamma) == 0x6E789E6AA1B965F4
+    assert oracle.splitmix64((2 * gamma) & mask) == 0x06C45D188009454F
+    assert oracle.splitmix64(1234567) == 6457827717110365317
+
+
+def test_perturbation_properties(oracle):
+    w = W.make_workload("mixed_s9_s53_1m", 64)
+    ms = w["mechs"]
+    ns = [ms[k]["n_species"] for k in w["cell_mech"]]
+    ws = [ms[k]["w"] for k in w["cell_mech"]]
+    yp = oracle.perturb(w["y0"], ns, ws, 3, 1, 0.01)
+    for c in range(64):
+        S = ns[c]
+        ratio = yp[c, :S] / w["y0"][c, :S]
+        # each species moves by at most 1 %, then one common factor restores the mass
+        u = np.array([oracle.perturb_uniform(3, 1, c, i) for i in range(S)])
+        s_common = ratio / (1 + 0.01 * u)
+        assert np.allclose(s_common, s_common[0], rtol=1e-14)
+        assert abs(s_common[0] - 1) <= 0.0101
+        assert abs(yp[c, :S] @ ws[c] - w["y0"][c, :S] @ ws[c]) < 1e-15
+        assert np.all(yp[c, S:] == 0)
+    u = np.array([oracle.perturb_uniform(3, 1, c, i) for c in range(200) for i in range(10)])
+    assert u.min() >= -1 and u.max() < 1 and abs(u.mean()) < 0.05
