@@ -1,0 +1,195 @@
+"""Benchmark: cells integrated per second per outer step (one MI355X).
+
+One step = every cell of the workload integrated over one outer (splitting)
+step [0, dt] from the same resident initial state (restored by a device copy
+at the start of the step).  Default workload: the 21-species / 84-reaction
+synthetic mass-action mechanism on 64^3 = 262,144 cells, dt = 1e-5 s,
+rtol = 1e-6, atol = 1e-10, FP64.
+
+Forms timed: plain (one lane group per cell, static grid), batched
+(persistent work-queue waves) and batched with the Newton-matrix LU in FP32.
+The headline `value` is the fastest form that matches the oracle sample.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2405_01713_amd import workloads as W  # noqa: E402
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def flops_model(mech: dict, forcing: bool = False) -> dict:
+    """Algorithmic FP64 flops of each integrator event for one mechanism
+    (FMA = 2, divide / sqrt / exp = 1), derived from its stoichiometry."""
+    S, R = mech["n_species"], mech["n_reactions"]
+    reac, prod = np.asarray(mech["reac"]), np.asarray(mech["prod"])
+    nr = (reac >= 0).sum(1)
+    npd = (prod >= 0).sum(1)
+    rev = mech.get("lnK") is not None
+    # rates: k_f times reactant slots, k_r times product slots, subtract
+    rate = int(np.sum(nr + (npd if rev else 0) + 1))
+    gather = 2 * int(np.sum(nr + npd))  # one FMA per slot occurrence
+    rhs = rate + gather + (S if forcing else 0)
+    # Jacobian terms: per slot and distributed row, product of the other slots + FMA
+    terms = 0
+    for r in range(R):
+        rows = nr[r] + npd[r]
+        for side_n in ((nr[r],) + ((npd[r],) if rev else ())):
+            terms += side_n * rows * (2 + max(side_n - 1, 0))
+    jac = terms + 2 * S * S  # + M = I - gamma J
+    lu = sum(m * (1 + 2 * m) for m in range(S))  # divides + FMA updates
+    solve = 2 * S * (S - 1) + S
+    newton_vec = 10 * S
+    q = 4  # typical order
+    step_vec = (q * (q + 1) // 2 + 2 * (q + 1) + 6) * S
+    rates0 = 6 * R
+    return dict(rhs=rhs, setup=jac + lu, nni=solve + newton_vec, nst=step_vec, cell=rates0)
+
+
+def algorithmic_flops(stats: np.ndarray, fm: dict) -> float:
+    return float(stats["nfe"].sum() * fm["rhs"] + stats["nsetups"].sum() * fm["setup"]
+                 + stats["nni"].sum() * fm["nni"] + stats["nst"].sum() * fm["nst"]
+                 + stats.size * fm["cell"])
+
+
+def run_form(w, form, steps, warmup, opts_extra=None):
+    import torch
+    from paper_2405_01713_amd import bdfx
+
+    opts = dict(plain=dict(scheduler=0, lu_precision=64),
+                batched=dict(scheduler=1, lu_precision=64),
+                batched_fp32lu=dict(scheduler=1, lu_precision=32))[form]
+    opts.update(opts_extra or {})
+    integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"],
+                            kscale=w["kscale"], cell_mech=w["cell_mech"], **opts)
+    y0 = integ.y.clone()
+    stream = integ.stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            integ.y.copy_(y0)
+            integ.integrate(0.0, w["t_out"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            integ.y.copy_(y0)
+            ev[k][0].record(stream)
+            integ.integrate(0.0, w["t_out"])
+            ev[k][1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    y = integ.state()
+    st = integ.cell_stats()
+    integ.close()
+    return dict(wall_ms_per_step=1e3 * wall / steps, kernel_ms=float(np.mean(kern_ms)),
+                kernel_ms_min=float(np.min(kern_ms)), y=y, stats=st)
+
+
+def cpu_baseline(w, n_sample):
+    from oracle import oracle as O
+    idx = np.arange(min(n_sample, w["n_cells"]))
+    t0 = time.perf_counter()
+    yo, sto = O.integrate(w["mechs"], w["y0"][idx], 0.0, w["t_out"], w["rtol"], w["atol"],
+                          T=None if w["T"] is None else w["T"][idx],
+                          kscale=None if w["kscale"] is None else w["kscale"][idx],
+                          cell_mech=None if w["cell_mech"] is None else w["cell_mech"][idx])
+    dt = time.perf_counter() - t0
+    return dict(value=len(idx) / dt, seconds=dt, cores=O.max_threads(), idx=idx, y=yo, stats=sto)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="s21_r84_262k")
+    ap.add_argument("--cells", type=int, default=None)
+    ap.add_argument("--forms", default="plain,batched,batched_fp32lu")
+    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not supported "
+                                   "(cells shard with no communication, see DESIGN.md)"}))
+        sys.exit(2)
+
+    w = W.make_workload(args.workload, args.cells)
+    m0 = w["mechs"][0]
+    fms = [flops_model(m) for m in w["mechs"]]
+    forms = {}
+    for form in args.forms.split(","):
+        r = run_form(w, form, args.steps, args.warmup)
+        st = r["stats"]
+        if w["cell_mech"] is None:
+            F = algorithmic_flops(st, fms[0])
+        else:
+            F = sum(algorithmic_flops(st[w["cell_mech"] == k], fms[k]) for k in range(len(fms)))
+        forms[form] = dict(kernel_ms=r["kernel_ms"], kernel_ms_min=r["kernel_ms_min"],
+                           wall_ms_per_step=r["wall_ms_per_step"],
+                           cells_per_s=w["n_cells"] / (r["kernel_ms"] * 1e-3),
+                           tflops=F / (r["kernel_ms"] * 1e-3) / 1e12,
+                           failed_cells=int(np.sum(st["status"] != 0)),
+                           mean_nst=float(st["nst"].mean()), mean_nfe=float(st["nfe"].mean()),
+                           mean_nsetups=float(st["nsetups"].mean()), alg_flops=F,
+                           _y=r["y"])
+
+    cpu = None
+    if not args.no_cpu:
+        c = cpu_baseline(w, args.cpu_sample)
+        for form, f in forms.items():
+            yg = f["_y"][c["idx"]]
+            tol = 10 * w["rtol"] * np.abs(c["y"]) + w["atol"]
+            f["parity_max_err_over_tol"] = float(np.max(np.abs(yg - c["y"]) / tol))
+            f["parity_ok"] = bool(f["parity_max_err_over_tol"] <= 1.0)
+        cpu = {"value": c["value"], "unit": "cells/s", "cores": c["cores"], "kind": "oracle",
+               "sample": f"first {len(c['idx'])} of {w['n_cells']} cells of the same workload, "
+                         f"one outer step, OpenMP over host cores ({c['seconds']:.1f} s)"}
+    for f in forms.values():
+        f.pop("_y")
+
+    ok = {k: v for k, v in forms.items() if v.get("parity_ok", True) and v["failed_cells"] == 0}
+    best = max(ok or forms, key=lambda k: forms[k]["cells_per_s"])
+    b = forms[best]
+    roof = {"bound": "alu", "achieved": b["tflops"], "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": b["tflops"] / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+            "kernel": "bdfx::k_integrate", "flops_per_launch": b["alg_flops"]}
+    out = {
+        "metric": "cells integrated/s per outer step @rtol 1e-6",
+        "value": b["cells_per_s"],
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": b["kernel_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if best != "batched_fp32lu" else "f64 (LU f32)",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_cells": w["n_cells"],
+                   "species": [m["n_species"] for m in w["mechs"]],
+                   "reactions": [m["n_reactions"] for m in w["mechs"]],
+                   "dt": w["t_out"], "rtol": w["rtol"], "atol": w["atol"], "form": best},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "forms": forms,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * bdfx.h -- C ABI of the MI355X batched stiff-kinetics BDF integrator.
+ *
+ * Problem (arXiv 2405.01713, Balos et al.): operator splitting (Sec. 3.1,
+ * Eq. (7)) leaves one independent ODE system per grid cell,
+ *     y' = R(y; k_c) + F_c,   y(t0) = y0_c,   t in [t0, t_out],
+ * with R mass-action chemistry and F a constant forcing.  Every cell is
+ * integrated by a variable-order (1..5), variable-step BDF method (Sec. 2,
+ * Eq. (1)) with its own step and order control: local error in the WRMS norm
+ * of Sec. 2, Eq. (3) with tolerances rtol and atol_i; modified Newton with the
+ * stopping test of Sec. 2, Eq. (4); Newton matrix I - gamma J from the analytic
+ * Jacobian, factored by dense LU with partial pivoting (Table 1, approaches
+ * 2A/2B; Sec. 4.1.4).
+ *
+ * Conventions
+ *  - All d_* arguments are device pointers owned by the caller.  The library
+ *    borrows them from bdfx_bind() until the next bind or bdfx_destroy().  The
+ *    library owns only the context and the mechanism tables; it allocates no
+ *    device memory after bdfx_bind() (the paper's memory-pool lesson,
+ *    Sec. 4.2.4), so bdfx_integrate() and bdfx_perturb() can be captured in a
+ *    HIP graph.
+ *  - State layout is cell-major ("CY" ordering of Sec. 4.1.2):
+ *    y[cell * ldy + species], FP64.
+ *  - Every function returns BDFX_OK (0) or a negative call status; the text of
+ *    the last error is available from bdfx_last_error().  Failures of single
+ *    cells never fail a call: they are reported per cell in d_status.
+ *  - A context is bound to one device and one HIP stream and is not
+ *    thread-safe.  Work is enqueued on the context's stream; only
+ *    bdfx_stats_summary() and bdfx_bind() synchronise it.
+ */
+#ifndef BDFX_H
+#define BDFX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BDFX_MAX_SPECIES 64
+#define BDFX_MAX_ORDER 5
+#define BDFX_SLOTS 3
+#define BDFX_MAX_MECH 8
+
+/* call status */
+#define BDFX_OK 0
+#define BDFX_EINVAL (-1)    /* invalid argument */
+#define BDFX_EWORKSPACE (-2) /* workspace smaller than bdfx_plan() asked for */
+#define BDFX_EHIP (-3)      /* HIP runtime error */
+#define BDFX_EORDER (-4)    /* functions called in the wrong order */
+#define BDFX_EUNSUPPORTED (-5)
+
+/* per-cell status (CVODE-like) */
+#define BDFX_CELL_SUCCESS 0
+#define BDFX_CELL_TOO_MUCH_WORK (-1)  /* max_steps reached before t_out */
+#define BDFX_CELL_ERR_FAILURE (-3)    /* repeated error-test failures or step too small */
+#define BDFX_CELL_CONV_FAILURE (-4)   /* repeated Newton convergence failures */
+#define BDFX_CELL_SETUP_FAILURE (-6)  /* singular Newton matrix twice in one step */
+#define BDFX_CELL_NONFINITE (-9)      /* non-finite y0, T or right-hand side */
+#define BDFX_CELL_RECORD_FULL (-10)   /* adjoint step record capacity exceeded */
+
+typedef struct bdfx_ctx_s *bdfx_ctx;
+typedef struct bdfx_mech_s *bdfx_mech;
+
+/* Mass-action mechanism, host arrays, copied by bdfx_mech_create().
+ * Reaction r: sum_l y[reac[r][l]]  <=>  sum_l y[prod[r][l]] with up to three
+ * slots per side (-1 = empty, a repeated species is a stoichiometric
+ * coefficient), net rate q_r = k_f prod y_reac - k_r prod y_prod and
+ * f_i = F_i + sum_r nu_ir q_r.  Rate constants are Arrhenius,
+ * k_f = exp(lnA_r - EaR_r / T_c) * kscale_c[r], k_r = k_f exp(-lnK_r). */
+typedef struct {
+  int32_t n_species;   /* S, 1..BDFX_MAX_SPECIES */
+  int32_t n_reactions; /* R >= 1 */
+  const int32_t *reac; /* [R][3] */
+  const int32_t *prod; /* [R][3] */
+  const double *lnA;   /* [R] */
+  const double *EaR;   /* [R] activation temperature (K), or NULL (all zero) */
+  const double *lnK;   /* [R] ln equilibrium constant, or NULL (irreversible) */
+} bdfx_mech_desc;
+
+/* Scheduler for bdfx_options.scheduler */
+#define BDFX_SCHED_STATIC 0 /* one lane group per cell, grid covers every cell */
+#define BDFX_SCHED_QUEUE 1  /* persistent waves pop cells from an atomic work queue */
+
+typedef struct {
+  double rtol;           /* relative tolerance of Eq. (3), > 0 */
+  const double *atol;    /* host [atol_len] absolute tolerances, copied */
+  int32_t atol_len;      /* 1 (all species) or >= S_max (per species index) */
+  int32_t max_order;     /* 1..5 (0 = 5) */
+  int32_t max_steps;     /* per cell per integrate call (0 = 5000) */
+  int32_t lu_precision;  /* 64 (default) or 32: Newton-matrix factor/solve in FP32 */
+  int32_t scheduler;     /* BDFX_SCHED_* */
+  int32_t record_steps;  /* > 0: record up to this many accepted steps per cell
+                            for bdfx_adjoint(); 0: no recording */
+  int32_t waves_per_block; /* 0 = library choice / autotuned value */
+  int32_t blocks_per_cu;   /* persistent grid: resident blocks per CU (0 = auto) */
+  int32_t queue_chunk;     /* cells per work-queue pop (0 = 1) */
+} bdfx_options;
+
+/* Per-cell statistics written by bdfx_integrate() (48 bytes, [N]). */
+typedef struct {
+  int32_t status;  /* BDFX_CELL_* */
+  int32_t nst;     /* accepted steps */
+  int32_t nfe;     /* right-hand-side evaluations */
+  int32_t nni;     /* Newton iterations */
+  int32_t nsetups; /* Jacobian evaluations + LU factorisations */
+  int32_t netf;    /* error-test failures */
+  int32_t ncfn;    /* Newton convergence failures */
+  int32_t q_last;  /* order at the end */
+  double h_last;   /* step size at the end */
+  double t_reached;/* t_out on success, else time of the last accepted step */
+} bdfx_cell_stats;
+
+/* Batch summary from bdfx_stats_summary(). */
+typedef struct {
+  int64_t n_cells;
+  int64_t n_success;
+  int64_t n_failed;
+  int64_t nst, nfe, nni, nsetups, netf, ncfn; /* totals over cells */
+  int64_t max_nst;
+  int64_t status_count[11]; /* count of cells with status == -k, k = 0..10 */
+} bdfx_summary;
+
+/* Create a context on HIP device `device` enqueueing on `hip_stream`
+ * (hipStream_t, NULL = default stream).  *out receives the handle. */
+int bdfx_create(bdfx_ctx *out, int device, void *hip_stream);
+/* Change the stream later work is enqueued on. */
+int bdfx_set_stream(bdfx_ctx ctx, void *hip_stream);
+/* Release the context and everything it owns (not the bound buffers). */
+int bdfx_destroy(bdfx_ctx ctx);
+/* Text of the last error of ctx (or of the last failed create when ctx is
+ * NULL).  The pointer stays valid until the next call on the context. */
+const char *bdfx_last_error(bdfx_ctx ctx);
+
+/* Upload a mechanism (derives the RHS gather lists and the analytic-Jacobian
+ * term lists from the stoichiometry).  Synchronous. */
+int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *desc, bdfx_mech *out);
+int bdfx_mech_destroy(bdfx_mech mech);
+
+/* Fix the batch shape and options; *workspace_bytes receives the device
+ * workspace size bdfx_bind() needs (queue counters, cell bins, adjoint
+ * records).  mechs[m] is the mechanism of cells with cell_mech == m. */
+int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *mechs,
+              const bdfx_options *opts, size_t *workspace_bytes);
+
+/* Bind caller-owned device buffers:
+ *   d_workspace [workspace_bytes]   scratch owned by the caller, >= plan size
+ *   d_y         [N][ldy] in/out     initial state on entry, final state after
+ *                                   bdfx_integrate() (updated in place);
+ *                                   ldy >= S_max, entries beyond a cell's S are
+ *                                   never read or written
+ *   d_cell_mech [N] or NULL         mechanism index of every cell (NULL: all 0)
+ *   d_T         [N] or NULL         temperature (NULL: zero activation terms)
+ *   d_kscale    [N][ldk] or NULL    multiplicative per-reaction rate scale
+ *   d_forcing   [N][ldy] or NULL    constant forcing F
+ *   d_status    [N] out             per-cell BDFX_CELL_* status
+ *   d_stats     [N] out or NULL     per-cell statistics
+ * Reads d_cell_mech once (synchronously) to build the per-mechanism cell
+ * bins in the workspace. */
+int bdfx_bind(bdfx_ctx ctx, void *d_workspace, size_t workspace_bytes, double *d_y, int32_t ldy,
+              const int32_t *d_cell_mech, const double *d_T, const double *d_kscale,
+              int32_t ldk, const double *d_forcing, int32_t *d_status,
+              bdfx_cell_stats *d_stats);
+
+/* Integrate every bound cell from t0 to t_out (t_out > t0); enqueue only. */
+int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out);
+
+/* Outer-step perturbation between splitting steps: for every cell and
+ * species, y_i <- max(0, y_i (1 + amplitude u)), u uniform in [-1, 1) from
+ * SplitMix64 (Steele, Lea & Flood 2014) keyed by (seed, outer_step, cell,
+ * species), then the cell is rescaled so that sum_i w_i y_i keeps its value
+ * (w = d_weights of the cell's mechanism, see bdfx_mech_set_weights()).
+ * Enqueue only. */
+int bdfx_perturb(bdfx_ctx ctx, uint64_t seed, int64_t outer_step, double amplitude);
+/* Species weights w [S] (host) used by bdfx_perturb(); default all ones. */
+int bdfx_mech_set_weights(bdfx_mech mech, const double *weights);
+
+/* Sum the per-cell statistics of the last integrate; synchronises the
+ * context's stream.  Requires d_stats bound. */
+int bdfx_stats_summary(bdfx_ctx ctx, bdfx_summary *out);
+
+/* Discrete adjoint of the last bdfx_integrate() (which must have been run
+ * with record_steps > 0, single outer step, no bdfx_perturb() since):
+ *   d_ybar    [N][ldy]  dL/dy(t_out)
+ *   d_y0bar   [N][ldy]  out: dL/dy(t0)
+ *   d_lnA_bar [n_mech][R_max] out: dL/dlnA_r summed over the cells of each
+ *                       mechanism (may be NULL)
+ * The gradient is that of the discrete map with the recorded step sizes and
+ * orders held fixed and each corrector solved exactly (Jacobians re-evaluated
+ * at the recorded states).  Enqueue only. */
+int bdfx_adjoint(bdfx_ctx ctx, const double *d_ybar, double *d_y0bar, double *d_lnA_bar);
+
+/* Library version string. */
+const char *bdfx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BDFX_H */

@@ -1,0 +1,274 @@
+"""Thin Python binding of the bdfx C ABI (include/bdfx.h).
+
+The functions ``bdfx_*`` below carry the C names and only marshal arguments
+(device pointers are passed as integers, e.g. ``tensor.data_ptr()``).  The
+``Integrator`` helper owns torch tensors for the caller-owned device buffers
+and forwards every step to the library: no part of the integration runs in
+Python or PyTorch.  Importing this module does not need a GPU; calling the
+library does, and it fails loudly when ``libbdfx.so`` is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libbdfx.so")
+
+BDFX_OK = 0
+BDFX_SCHED_STATIC = 0
+BDFX_SCHED_QUEUE = 1
+MAX_SPECIES = 64
+
+CELL_STATUS = {0: "success", -1: "too_much_work", -3: "err_failure", -4: "conv_failure",
+               -6: "setup_failure", -9: "nonfinite", -10: "record_full"}
+
+EXPORTED = ["bdfx_create", "bdfx_set_stream", "bdfx_destroy", "bdfx_last_error",
+            "bdfx_mech_create", "bdfx_mech_destroy", "bdfx_mech_set_weights", "bdfx_plan",
+            "bdfx_bind", "bdfx_integrate", "bdfx_perturb", "bdfx_stats_summary",
+            "bdfx_adjoint", "bdfx_version"]
+
+
+class MechDesc(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32),
+                ("reac", C.c_void_p), ("prod", C.c_void_p), ("lnA", C.c_void_p),
+                ("EaR", C.c_void_p), ("lnK", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_void_p), ("atol_len", C.c_int32),
+                ("max_order", C.c_int32), ("max_steps", C.c_int32),
+                ("lu_precision", C.c_int32), ("scheduler", C.c_int32),
+                ("record_steps", C.c_int32), ("waves_per_block", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("queue_chunk", C.c_int32)]
+
+
+class Summary(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_success", C.c_int64), ("n_failed", C.c_int64),
+                ("nst", C.c_int64), ("nfe", C.c_int64), ("nni", C.c_int64),
+                ("nsetups", C.c_int64), ("netf", C.c_int64), ("ncfn", C.c_int64),
+                ("max_nst", C.c_int64), ("status_count", C.c_int64 * 11)]
+
+
+STATS_DTYPE = np.dtype([("status", np.int32), ("nst", np.int32), ("nfe", np.int32),
+                        ("nni", np.int32), ("nsetups", np.int32), ("netf", np.int32),
+                        ("ncfn", np.int32), ("q_last", np.int32),
+                        ("h_last", np.float64), ("t_reached", np.float64)])
+
+_lib = None
+
+
+def lib():
+    """Load libbdfx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+        sig = {
+            "bdfx_create": ([C.POINTER(P), C.c_int, P], C.c_int),
+            "bdfx_set_stream": ([P, P], C.c_int),
+            "bdfx_destroy": ([P], C.c_int),
+            "bdfx_last_error": ([P], C.c_char_p),
+            "bdfx_mech_create": ([P, C.POINTER(MechDesc), C.POINTER(P)], C.c_int),
+            "bdfx_mech_destroy": ([P], C.c_int),
+            "bdfx_mech_set_weights": ([P, P], C.c_int),
+            "bdfx_plan": ([P, I64, I32, P, C.POINTER(Options), C.POINTER(C.c_size_t)], C.c_int),
+            "bdfx_bind": ([P, P, C.c_size_t, P, I32, P, P, P, I32, P, P, P], C.c_int),
+            "bdfx_integrate": ([P, C.c_double, C.c_double], C.c_int),
+            "bdfx_perturb": ([P, C.c_uint64, I64, C.c_double], C.c_int),
+            "bdfx_stats_summary": ([P, C.POINTER(Summary)], C.c_int),
+            "bdfx_adjoint": ([P, P, P, P], C.c_int),
+            "bdfx_version": ([], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+class BdfxError(RuntimeError):
+    pass
+
+
+def _check(rc, ctx=None):
+    if rc != BDFX_OK:
+        msg = lib().bdfx_last_error(ctx)
+        raise BdfxError(f"bdfx error {rc}: {msg.decode() if msg else ''}")
+
+
+# --- C-named entry points (argument marshalling only) ---------------------
+
+def bdfx_version() -> str:
+    return lib().bdfx_version().decode()
+
+
+def bdfx_create(device: int = 0, stream: int = 0):
+    h = C.c_void_p()
+    _check(lib().bdfx_create(C.byref(h), int(device), C.c_void_p(stream)))
+    return h
+
+
+def bdfx_set_stream(ctx, stream: int):
+    _check(lib().bdfx_set_stream(ctx, C.c_void_p(stream)), ctx)
+
+
+def bdfx_destroy(ctx):
+    _check(lib().bdfx_destroy(ctx))
+
+
+def bdfx_last_error(ctx=None) -> str:
+    m = lib().bdfx_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def bdfx_mech_create(ctx, mech: dict):
+    """mech: dict with n_species, n_reactions, reac/prod [R,3], lnA, EaR, lnK."""
+    keep = dict(
+        reac=np.ascontiguousarray(mech["reac"], dtype=np.int32),
+        prod=np.ascontiguousarray(mech["prod"], dtype=np.int32),
+        lnA=np.ascontiguousarray(mech["lnA"], dtype=np.float64),
+        EaR=None if mech.get("EaR") is None else np.ascontiguousarray(mech["EaR"], dtype=np.float64),
+        lnK=None if mech.get("lnK") is None else np.ascontiguousarray(mech["lnK"], dtype=np.float64),
+    )
+    p = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
+    d = MechDesc(int(mech["n_species"]), int(mech["n_reactions"]), p(keep["reac"]),
+                 p(keep["prod"]), p(keep["lnA"]), p(keep["EaR"]), p(keep["lnK"]))
+    h = C.c_void_p()
+    _check(lib().bdfx_mech_create(ctx, C.byref(d), C.byref(h)), ctx)
+    if mech.get("w") is not None:
+        w = np.ascontiguousarray(mech["w"], dtype=np.float64)
+        _check(lib().bdfx_mech_set_weights(h, w.ctypes.data_as(C.c_void_p)), ctx)
+    return h
+
+
+def bdfx_mech_destroy(mech):
+    _check(lib().bdfx_mech_destroy(mech))
+
+
+def make_options(rtol, atol, max_order=5, max_steps=5000, lu_precision=64,
+                 scheduler=BDFX_SCHED_STATIC, record_steps=0, waves_per_block=0,
+                 blocks_per_cu=0, queue_chunk=0):
+    atol_arr = np.ascontiguousarray(np.atleast_1d(np.asarray(atol, dtype=np.float64)))
+    o = Options(float(rtol), atol_arr.ctypes.data_as(C.c_void_p), int(atol_arr.size),
+                int(max_order), int(max_steps), int(lu_precision), int(scheduler),
+                int(record_steps), int(waves_per_block), int(blocks_per_cu), int(queue_chunk))
+    o._keep = atol_arr
+    return o
+
+
+def bdfx_plan(ctx, n_cells: int, mechs, opts: Options) -> int:
+    arr = (C.c_void_p * len(mechs))(*[m.value for m in mechs])
+    nbytes = C.c_size_t(0)
+    _check(lib().bdfx_plan(ctx, int(n_cells), len(mechs), C.cast(arr, C.c_void_p),
+                           C.byref(opts), C.byref(nbytes)), ctx)
+    return int(nbytes.value)
+
+
+def bdfx_bind(ctx, ws_ptr, ws_bytes, y_ptr, ldy, cell_mech_ptr, T_ptr, kscale_ptr, ldk,
+              forcing_ptr, status_ptr, stats_ptr):
+    v = lambda x: C.c_void_p(int(x) if x else 0)
+    _check(lib().bdfx_bind(ctx, v(ws_ptr), C.c_size_t(int(ws_bytes)), v(y_ptr), int(ldy),
+                           v(cell_mech_ptr), v(T_ptr), v(kscale_ptr), int(ldk), v(forcing_ptr),
+                           v(status_ptr), v(stats_ptr)), ctx)
+
+
+def bdfx_integrate(ctx, t0: float, t_out: float):
+    _check(lib().bdfx_integrate(ctx, float(t0), float(t_out)), ctx)
+
+
+def bdfx_perturb(ctx, seed: int, outer_step: int, amplitude: float):
+    _check(lib().bdfx_perturb(ctx, C.c_uint64(int(seed)), int(outer_step), float(amplitude)), ctx)
+
+
+def bdfx_stats_summary(ctx) -> dict:
+    s = Summary()
+    _check(lib().bdfx_stats_summary(ctx, C.byref(s)), ctx)
+    out = {k: getattr(s, k) for k, _ in Summary._fields_ if k != "status_count"}
+    out["status_count"] = list(s.status_count)
+    return out
+
+
+def bdfx_adjoint(ctx, ybar_ptr, y0bar_ptr, lnA_bar_ptr):
+    v = lambda x: C.c_void_p(int(x) if x else 0)
+    _check(lib().bdfx_adjoint(ctx, v(ybar_ptr), v(y0bar_ptr), v(lnA_bar_ptr)), ctx)
+
+
+# --- convenience wrapper over torch device memory -------------------------
+
+class Integrator:
+    """Batch of cells on one GPU: owns the device tensors, calls the C ABI.
+
+    ``mechs``: list of mechanism dicts; ``y0`` [N, S_max] float64; optional
+    ``T`` [N], ``kscale`` [N, R_max], ``forcing`` [N, S_max], ``cell_mech`` [N].
+    """
+
+    def __init__(self, mechs, y0, rtol, atol, T=None, kscale=None, forcing=None, cell_mech=None,
+                 device=0, stream=None, **opts):
+        import torch
+
+        if isinstance(mechs, dict):
+            mechs = [mechs]
+        self.torch = torch
+        self.dev = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        self.ctx = bdfx_create(device, self.stream.cuda_stream)
+        self.mech_handles = [bdfx_mech_create(self.ctx, m) for m in mechs]
+        self.mechs = mechs
+        y0 = np.ascontiguousarray(y0, dtype=np.float64)
+        self.N, self.ldy = y0.shape
+        self.opts = make_options(rtol, atol, **opts)
+        ws = bdfx_plan(self.ctx, self.N, self.mech_handles, self.opts)
+        t = lambda a, dt: None if a is None else torch.as_tensor(np.ascontiguousarray(a), dtype=dt,
+                                                                device=self.dev)
+        self.y = t(y0, torch.float64)
+        self.T = t(T, torch.float64)
+        self.kscale = t(kscale, torch.float64)
+        self.forcing = t(forcing, torch.float64)
+        self.cell_mech = t(cell_mech, torch.int32)
+        self.status = torch.zeros(self.N, dtype=torch.int32, device=self.dev)
+        self.stats = torch.zeros(self.N * STATS_DTYPE.itemsize, dtype=torch.uint8, device=self.dev)
+        self.ws = torch.empty(max(ws, 256), dtype=torch.uint8, device=self.dev)
+        self.ws_bytes = ws
+        ptr = lambda x: 0 if x is None else x.data_ptr()
+        self.ldk = 0 if kscale is None else int(np.shape(kscale)[1])
+        bdfx_bind(self.ctx, ptr(self.ws), self.ws.numel(), ptr(self.y), self.ldy,
+                  ptr(self.cell_mech), ptr(self.T), ptr(self.kscale), self.ldk, ptr(self.forcing),
+                  ptr(self.status), ptr(self.stats))
+
+    def integrate(self, t0, t_out):
+        bdfx_integrate(self.ctx, t0, t_out)
+
+    def perturb(self, seed, outer_step, amplitude):
+        bdfx_perturb(self.ctx, seed, outer_step, amplitude)
+
+    def set_state(self, y0):
+        self.y.copy_(self.torch.as_tensor(np.ascontiguousarray(y0), dtype=self.torch.float64))
+
+    def summary(self):
+        return bdfx_stats_summary(self.ctx)
+
+    def cell_stats(self) -> np.ndarray:
+        return self.stats.cpu().numpy().view(STATS_DTYPE)
+
+    def state(self) -> np.ndarray:
+        return self.y.cpu().numpy()
+
+    def close(self):
+        if self.ctx:
+            self.torch.cuda.synchronize(self.dev)
+            for m in self.mech_handles:
+                bdfx_mech_destroy(m)
+            bdfx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

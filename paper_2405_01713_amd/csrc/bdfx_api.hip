@@ -1,0 +1,615 @@
+// bdfx_api.hip -- host runtime behind the C ABI of include/bdfx.h.
+//
+// Owns the context (device, stream, plan, bound buffers) and the
+// device-resident mechanism tables; builds the per-species gather lists and
+// the analytic-Jacobian term lists from the stoichiometry; launches the
+// per-size integrator kernels.  Nothing here allocates device memory after
+// bdfx_bind() (the paper's memory-pool lesson, Sec. 4.2.4), so integrate and
+// perturb can be captured into a HIP graph by the caller.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bdfx.h"
+#include "bdf_kernels.h"
+
+BDFX_DECLARE_SIZE(3)
+BDFX_DECLARE_SIZE(4)
+BDFX_DECLARE_SIZE(8)
+BDFX_DECLARE_SIZE(9)
+BDFX_DECLARE_SIZE(16)
+BDFX_DECLARE_SIZE(21)
+BDFX_DECLARE_SIZE(32)
+BDFX_DECLARE_SIZE(53)
+BDFX_DECLARE_SIZE(64)
+
+hipError_t bdfx_launch_perturb(const bdfx::Params &P, uint64_t seed, int64_t step, double amp,
+                               hipStream_t s);
+hipError_t bdfx_launch_fill_u32(uint32_t *p, int n, uint32_t v, hipStream_t s);
+
+static_assert(sizeof(bdfx_cell_stats) == sizeof(bdfx::CellStats), "stats layout");
+static_assert(sizeof(bdfx_cell_stats) == 48, "stats size");
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct SizeEntry {
+  int S, G;
+  hipError_t (*launch)(const bdfx::Params &, bool, const bdfx::LaunchCfg &, hipStream_t);
+  hipError_t (*occupancy)(bool, int, size_t, int *);
+};
+
+const SizeEntry kSizes[] = {
+    {3, 4, bdfx_launch_s3, bdfx_occupancy_s3},     {4, 4, bdfx_launch_s4, bdfx_occupancy_s4},
+    {8, 8, bdfx_launch_s8, bdfx_occupancy_s8},     {9, 16, bdfx_launch_s9, bdfx_occupancy_s9},
+    {16, 16, bdfx_launch_s16, bdfx_occupancy_s16}, {21, 32, bdfx_launch_s21, bdfx_occupancy_s21},
+    {32, 32, bdfx_launch_s32, bdfx_occupancy_s32}, {53, 64, bdfx_launch_s53, bdfx_occupancy_s53},
+    {64, 64, bdfx_launch_s64, bdfx_occupancy_s64},
+};
+
+// Smallest compiled size that holds S species (exact sizes 3, 9, 21, 53 are
+// compiled for the benchmark mechanisms; others are padded with inert
+// species whose Newton-matrix rows are identity rows).
+const SizeEntry *size_for(int S) {
+  for (const auto &e : kSizes)
+    if (e.S >= S) return &e;
+  return nullptr;
+}
+
+}  // namespace
+
+struct bdfx_mech_s {
+  bdfx_ctx ctx = nullptr;
+  int S = 0, R = 0;
+  bool reversible = false;
+  void *dmem = nullptr;
+  bdfx::MechDev dev{};
+  std::vector<double> w;
+  size_t jr_terms = 0;
+};
+
+struct Bin {
+  int mech;
+  int64_t offset, count;
+};
+
+struct bdfx_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int n_cu = 0;
+  // plan
+  bool planned = false, bound = false, integrated = false;
+  int64_t N = 0;
+  std::vector<bdfx_mech> mechs;
+  bdfx_options opt{};
+  std::vector<double> atol;
+  double *d_atol = nullptr;
+  int S_max = 0, R_max = 0;
+  size_t ws_need = 0;
+  size_t off_queue = 0, off_bins = 0, off_rec = 0, off_recn = 0, off_rechpad = 0, off_recy0 = 0,
+         off_pbar = 0;
+  int rec_stride = 0;
+  // bind
+  char *ws = nullptr;
+  double *y = nullptr;
+  int ldy = 0, ldk = 0;
+  const int32_t *cell_mech = nullptr;
+  const double *T = nullptr, *kscale = nullptr, *F = nullptr;
+  int32_t *status = nullptr;
+  bdfx_cell_stats *stats = nullptr;
+  std::vector<Bin> bins;
+  double last_t0 = 0.0, last_tout = 0.0;
+};
+
+static int fail(bdfx_ctx c, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c)
+    c->err = buf;
+  else
+    g_create_error = buf;
+  return code;
+}
+
+#define HIPCHK(c, expr)                                                                          \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) return fail(c, BDFX_EHIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+extern "C" {
+
+const char *bdfx_version(void) { return "bdfx 0.1 (gfx950)"; }
+
+const char *bdfx_last_error(bdfx_ctx ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+int bdfx_create(bdfx_ctx *out, int device, void *hip_stream) {
+  if (!out) return fail(nullptr, BDFX_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(nullptr, BDFX_EHIP, "no HIP device available");
+  if (device < 0 || device >= ndev) return fail(nullptr, BDFX_EINVAL, "bad device %d", device);
+  auto *c = new bdfx_ctx_s();
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipSetDevice(device) != hipSuccess ||
+      hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+    delete c;
+    return fail(nullptr, BDFX_EHIP, "cannot query device %d", device);
+  }
+  *out = c;
+  return BDFX_OK;
+}
+
+int bdfx_set_stream(bdfx_ctx ctx, void *hip_stream) {
+  if (!ctx) return BDFX_EINVAL;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return BDFX_OK;
+}
+
+int bdfx_destroy(bdfx_ctx ctx) {
+  if (!ctx) return BDFX_EINVAL;
+  hipSetDevice(ctx->device);
+  if (ctx->d_atol) hipFree(ctx->d_atol);
+  delete ctx;
+  return BDFX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// mechanisms
+// ---------------------------------------------------------------------------
+
+int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
+  if (!ctx || !d || !out) return fail(ctx, BDFX_EINVAL, "NULL argument");
+  *out = nullptr;
+  const int S = d->n_species, R = d->n_reactions;
+  if (S < 1 || S > BDFX_MAX_SPECIES) return fail(ctx, BDFX_EINVAL, "n_species %d out of 1..64", S);
+  if (R < 1 || R > (1 << 15)) return fail(ctx, BDFX_EINVAL, "n_reactions %d out of range", R);
+  if (!d->reac || !d->prod || !d->lnA) return fail(ctx, BDFX_EINVAL, "reac/prod/lnA required");
+  for (int r = 0; r < R; ++r)
+    for (int l = 0; l < BDFX_SLOTS; ++l) {
+      const int a = d->reac[r * 3 + l], b = d->prod[r * 3 + l];
+      if (a < -1 || a >= S || b < -1 || b >= S)
+        return fail(ctx, BDFX_EINVAL, "reaction %d slot %d: species out of range", r, l);
+    }
+
+  // reaction slots, one byte per species (0xff = empty)
+  std::vector<int32_t> rx(2 * R);
+  for (int r = 0; r < R; ++r) {
+    uint32_t wr = 0, wp = 0;
+    for (int l = 0; l < 3; ++l) {
+      const int a = d->reac[r * 3 + l], b = d->prod[r * 3 + l];
+      wr |= static_cast<uint32_t>(a < 0 ? 0xff : a) << (8 * l);
+      wp |= static_cast<uint32_t>(b < 0 ? 0xff : b) << (8 * l);
+    }
+    rx[2 * r] = static_cast<int32_t>(wr);
+    rx[2 * r + 1] = static_cast<int32_t>(wp);
+  }
+  // f_i gather list: one entry per slot occurrence, in reaction-then-slot
+  // order (reactant before product within a slot), coefficient -1 / +1
+  std::vector<std::vector<int32_t>> sp(S);
+  for (int r = 0; r < R; ++r)
+    for (int l = 0; l < 3; ++l) {
+      const int a = d->reac[r * 3 + l], b = d->prod[r * 3 + l];
+      if (a >= 0) sp[a].push_back((r << 8) | 0xff);  // nu = -1
+      if (b >= 0) sp[b].push_back((r << 8) | 0x01);  // nu = +1
+    }
+  // Jacobian terms: d q_r / d y_j for slot l of side sd is
+  // k_side * prod(other slots); distributed to every reactant row (-1) and
+  // product row (+1).  Enumerated in reaction / side / slot / row order.
+  struct Term {
+    int row, col, kidx, o1, o2, coef;
+  };
+  std::vector<Term> terms;
+  const bool reversible = d->lnK != nullptr;
+  for (int r = 0; r < R; ++r) {
+    const int32_t *side[2] = {d->reac + r * 3, d->prod + r * 3};
+    for (int sd = 0; sd < (reversible ? 2 : 1); ++sd)
+      for (int l = 0; l < 3; ++l) {
+        const int j = side[sd][l];
+        if (j < 0) continue;
+        int others[2] = {0xff, 0xff}, no = 0;
+        for (int o = 0; o < 3; ++o)
+          if (o != l && side[sd][o] >= 0) others[no++] = side[sd][o];
+        for (int s = 0; s < 3; ++s) {
+          const int a = d->reac[r * 3 + s], b = d->prod[r * 3 + s];
+          if (a >= 0) terms.push_back({a, j, 2 * r + sd, others[0], others[1], -1});
+          if (b >= 0) terms.push_back({b, j, 2 * r + sd, others[0], others[1], +1});
+        }
+      }
+  }
+  auto pack = [](const Term &t, int key) {
+    int2 e;
+    e.x = t.kidx;
+    e.y = (key & 0xff) | ((t.o1 & 0xff) << 8) | ((t.o2 & 0xff) << 16) |
+          ((t.coef & 0xff) << 24);
+    return e;
+  };
+  // by row, columns ascending (stable: per-entry order = enumeration order)
+  std::vector<Term> by_row = terms;
+  std::stable_sort(by_row.begin(), by_row.end(), [](const Term &x, const Term &y) {
+    return x.row != y.row ? x.row < y.row : x.col < y.col;
+  });
+  std::vector<Term> by_col = terms;
+  std::stable_sort(by_col.begin(), by_col.end(), [](const Term &x, const Term &y) {
+    return x.col != y.col ? x.col < y.col : x.row < y.row;
+  });
+  std::vector<int32_t> jr_off(S + 1, 0), jc_off(S + 1, 0), sp_off(S + 1, 0);
+  std::vector<int2> jr_ent, jc_ent;
+  std::vector<int32_t> sp_ent;
+  for (const auto &t : by_row) jr_off[t.row + 1]++;
+  for (const auto &t : by_col) jc_off[t.col + 1]++;
+  for (int i = 0; i < S; ++i) {
+    jr_off[i + 1] += jr_off[i];
+    jc_off[i + 1] += jc_off[i];
+    sp_off[i + 1] = sp_off[i] + static_cast<int>(sp[i].size());
+    for (auto v : sp[i]) sp_ent.push_back(v);
+  }
+  for (const auto &t : by_row) jr_ent.push_back(pack(t, t.col));
+  for (const auto &t : by_col) jc_ent.push_back(pack(t, t.row));
+
+  std::vector<double> lnA(d->lnA, d->lnA + R), EaR(R, 0.0), lnK(R, 0.0), w(S, 1.0);
+  if (d->EaR) EaR.assign(d->EaR, d->EaR + R);
+  if (d->lnK) lnK.assign(d->lnK, d->lnK + R);
+
+  // one device allocation for all tables
+  size_t off = 0;
+  auto reserve = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 8), 256);
+    return o;
+  };
+  const size_t o_rx = reserve(rx.size() * 4), o_lnA = reserve(R * 8), o_EaR = reserve(R * 8),
+               o_lnK = reserve(R * 8), o_spo = reserve((S + 1) * 4),
+               o_spe = reserve(sp_ent.size() * 4), o_jro = reserve((S + 1) * 4),
+               o_jre = reserve(jr_ent.size() * 8), o_jco = reserve((S + 1) * 4),
+               o_jce = reserve(jc_ent.size() * 8), o_w = reserve(S * 8);
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  void *dmem = nullptr;
+  HIPCHK(ctx, hipMalloc(&dmem, off));
+  char *base = static_cast<char *>(dmem);
+  auto up = [&](size_t o, const void *src, size_t bytes) {
+    return bytes ? hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = up(o_rx, rx.data(), rx.size() * 4);
+  if (e == hipSuccess) e = up(o_lnA, lnA.data(), R * 8);
+  if (e == hipSuccess) e = up(o_EaR, EaR.data(), R * 8);
+  if (e == hipSuccess) e = up(o_lnK, lnK.data(), R * 8);
+  if (e == hipSuccess) e = up(o_spo, sp_off.data(), (S + 1) * 4);
+  if (e == hipSuccess) e = up(o_spe, sp_ent.data(), sp_ent.size() * 4);
+  if (e == hipSuccess) e = up(o_jro, jr_off.data(), (S + 1) * 4);
+  if (e == hipSuccess) e = up(o_jre, jr_ent.data(), jr_ent.size() * 8);
+  if (e == hipSuccess) e = up(o_jco, jc_off.data(), (S + 1) * 4);
+  if (e == hipSuccess) e = up(o_jce, jc_ent.data(), jc_ent.size() * 8);
+  if (e == hipSuccess) e = up(o_w, w.data(), S * 8);
+  if (e != hipSuccess) {
+    hipFree(dmem);
+    return fail(ctx, BDFX_EHIP, "mechanism upload: %s", hipGetErrorString(e));
+  }
+  auto *m = new bdfx_mech_s();
+  m->ctx = ctx;
+  m->S = S;
+  m->R = R;
+  m->reversible = reversible;
+  m->dmem = dmem;
+  m->w = w;
+  m->jr_terms = jr_ent.size();
+  bdfx::MechDev &dv = m->dev;
+  dv.S = S;
+  dv.R = R;
+  dv.reversible = reversible ? 1 : 0;
+  dv.rx = reinterpret_cast<const int32_t *>(base + o_rx);
+  dv.lnA = reinterpret_cast<const double *>(base + o_lnA);
+  dv.EaR = reinterpret_cast<const double *>(base + o_EaR);
+  dv.lnK = reinterpret_cast<const double *>(base + o_lnK);
+  dv.sp_off = reinterpret_cast<const int32_t *>(base + o_spo);
+  dv.sp_ent = reinterpret_cast<const int32_t *>(base + o_spe);
+  dv.jr_off = reinterpret_cast<const int32_t *>(base + o_jro);
+  dv.jr_ent = reinterpret_cast<const int2 *>(base + o_jre);
+  dv.jc_off = reinterpret_cast<const int32_t *>(base + o_jco);
+  dv.jc_ent = reinterpret_cast<const int2 *>(base + o_jce);
+  dv.w = reinterpret_cast<const double *>(base + o_w);
+  *out = m;
+  return BDFX_OK;
+}
+
+int bdfx_mech_set_weights(bdfx_mech m, const double *weights) {
+  if (!m || !weights) return BDFX_EINVAL;
+  m->w.assign(weights, weights + m->S);
+  bdfx_ctx c = m->ctx;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipMemcpy(const_cast<double *>(m->dev.w), weights, m->S * 8, hipMemcpyHostToDevice));
+  return BDFX_OK;
+}
+
+int bdfx_mech_destroy(bdfx_mech m) {
+  if (!m) return BDFX_EINVAL;
+  if (m->ctx) hipSetDevice(m->ctx->device);
+  if (m->dmem) hipFree(m->dmem);
+  delete m;
+  return BDFX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// plan / bind
+// ---------------------------------------------------------------------------
+
+int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *mechs,
+              const bdfx_options *o, size_t *ws_bytes) {
+  if (!ctx || !mechs || !o || !ws_bytes) return fail(ctx, BDFX_EINVAL, "NULL argument");
+  if (n_cells < 0 || n_cells > (int64_t{1} << 31) - 1)
+    return fail(ctx, BDFX_EINVAL, "n_cells %lld out of range", static_cast<long long>(n_cells));
+  if (n_mech < 1 || n_mech > BDFX_MAX_MECH) return fail(ctx, BDFX_EINVAL, "n_mech out of range");
+  if (!(o->rtol > 0.0)) return fail(ctx, BDFX_EINVAL, "rtol must be > 0");
+  if (!o->atol || o->atol_len < 1) return fail(ctx, BDFX_EINVAL, "atol required");
+  if (o->lu_precision != 0 && o->lu_precision != 64 && o->lu_precision != 32)
+    return fail(ctx, BDFX_EINVAL, "lu_precision must be 64 or 32");
+  if (o->scheduler != BDFX_SCHED_STATIC && o->scheduler != BDFX_SCHED_QUEUE)
+    return fail(ctx, BDFX_EINVAL, "unknown scheduler %d", o->scheduler);
+  if (o->max_order < 0 || o->max_order > BDFX_MAX_ORDER)
+    return fail(ctx, BDFX_EINVAL, "max_order out of 1..5");
+  if (o->record_steps < 0) return fail(ctx, BDFX_EINVAL, "record_steps < 0");
+  int S_max = 0, R_max = 0;
+  for (int m = 0; m < n_mech; ++m) {
+    if (!mechs[m] || mechs[m]->ctx != ctx) return fail(ctx, BDFX_EINVAL, "bad mechanism %d", m);
+    S_max = std::max(S_max, mechs[m]->S);
+    R_max = std::max(R_max, mechs[m]->R);
+  }
+  if (o->atol_len != 1 && o->atol_len < S_max)
+    return fail(ctx, BDFX_EINVAL, "atol_len must be 1 or >= %d", S_max);
+  for (int i = 0; i < o->atol_len; ++i)
+    if (!(o->atol[i] > 0.0) || !std::isfinite(o->atol[i]))
+      return fail(ctx, BDFX_EINVAL, "atol[%d] must be positive", i);
+
+  ctx->planned = ctx->bound = ctx->integrated = false;
+  ctx->N = n_cells;
+  ctx->mechs.assign(mechs, mechs + n_mech);
+  ctx->opt = *o;
+  if (ctx->opt.max_order == 0) ctx->opt.max_order = 5;
+  if (ctx->opt.max_steps <= 0) ctx->opt.max_steps = 5000;
+  if (ctx->opt.lu_precision == 0) ctx->opt.lu_precision = 64;
+  if (ctx->opt.queue_chunk <= 0) ctx->opt.queue_chunk = 1;
+  ctx->atol.assign(o->atol, o->atol + o->atol_len);
+  ctx->opt.atol = nullptr;
+  ctx->S_max = S_max;
+  ctx->R_max = R_max;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if (ctx->d_atol) {
+    hipFree(ctx->d_atol);
+    ctx->d_atol = nullptr;
+  }
+  HIPCHK(ctx, hipMalloc(&ctx->d_atol, ctx->atol.size() * 8));
+  HIPCHK(ctx, hipMemcpy(ctx->d_atol, ctx->atol.data(), ctx->atol.size() * 8,
+                        hipMemcpyHostToDevice));
+
+  // workspace layout
+  size_t off = 0;
+  auto reserve = [&](size_t bytes) {
+    const size_t o2 = off;
+    off = align_up(off + bytes, 256);
+    return o2;
+  };
+  ctx->off_queue = reserve(64 * 4);
+  ctx->off_bins = reserve(static_cast<size_t>(n_mech > 1 ? n_cells : 0) * 4);
+  ctx->rec_stride = S_max + 2;
+  const int64_t cap = o->record_steps;
+  ctx->off_rec = reserve(static_cast<size_t>(n_cells) * cap * ctx->rec_stride * 8);
+  ctx->off_recn = reserve(cap ? static_cast<size_t>(n_cells) * 4 : 0);
+  ctx->off_rechpad = reserve(cap ? static_cast<size_t>(n_cells) * 8 : 0);
+  ctx->off_recy0 = reserve(cap ? static_cast<size_t>(n_cells) * ctx->rec_stride * 8 : 0);
+  ctx->off_pbar = reserve(cap ? static_cast<size_t>(n_cells) * R_max * 8 : 0);
+  ctx->ws_need = off;
+  *ws_bytes = off;
+  ctx->planned = true;
+  return BDFX_OK;
+}
+
+int bdfx_bind(bdfx_ctx ctx, void *d_ws, size_t ws_bytes, double *d_y, int32_t ldy,
+              const int32_t *d_cell_mech, const double *d_T, const double *d_kscale, int32_t ldk,
+              const double *d_forcing, int32_t *d_status, bdfx_cell_stats *d_stats) {
+  if (!ctx) return BDFX_EINVAL;
+  if (!ctx->planned) return fail(ctx, BDFX_EORDER, "bdfx_plan must precede bdfx_bind");
+  if (ws_bytes < ctx->ws_need)
+    return fail(ctx, BDFX_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, ctx->ws_need);
+  if (ctx->ws_need && !d_ws) return fail(ctx, BDFX_EINVAL, "workspace NULL");
+  if (ctx->N > 0 && (!d_y || !d_status)) return fail(ctx, BDFX_EINVAL, "y and status required");
+  if (ldy < ctx->S_max) return fail(ctx, BDFX_EINVAL, "ldy %d < S_max %d", ldy, ctx->S_max);
+  if (d_kscale && ldk < ctx->R_max) return fail(ctx, BDFX_EINVAL, "ldk %d < R_max", ldk);
+  if (ctx->mechs.size() > 1 && !d_cell_mech && ctx->N > 0)
+    return fail(ctx, BDFX_EINVAL, "cell_mech required with several mechanisms");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctx->ws = static_cast<char *>(d_ws);
+  ctx->y = d_y;
+  ctx->ldy = ldy;
+  ctx->ldk = ldk;
+  ctx->cell_mech = d_cell_mech;
+  ctx->T = d_T;
+  ctx->kscale = d_kscale;
+  ctx->F = d_forcing;
+  ctx->status = d_status;
+  ctx->stats = d_stats;
+  ctx->bins.clear();
+  const int nm = static_cast<int>(ctx->mechs.size());
+  if (nm == 1) {
+    ctx->bins.push_back({0, 0, ctx->N});
+  } else {
+    // per-mechanism cell lists (counting sort, stable), built once here
+    std::vector<int32_t> cm(ctx->N);
+    HIPCHK(ctx, hipMemcpy(cm.data(), d_cell_mech, ctx->N * 4, hipMemcpyDeviceToHost));
+    std::vector<int64_t> cnt(nm + 1, 0);
+    for (int64_t c = 0; c < ctx->N; ++c) {
+      if (cm[c] < 0 || cm[c] >= nm)
+        return fail(ctx, BDFX_EINVAL, "cell_mech[%lld] = %d out of range",
+                    static_cast<long long>(c), cm[c]);
+      cnt[cm[c] + 1]++;
+    }
+    for (int m = 0; m < nm; ++m) cnt[m + 1] += cnt[m];
+    std::vector<int32_t> list(ctx->N);
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t c = 0; c < ctx->N; ++c) list[pos[cm[c]]++] = static_cast<int32_t>(c);
+    HIPCHK(ctx, hipMemcpy(ctx->ws + ctx->off_bins, list.data(), ctx->N * 4,
+                          hipMemcpyHostToDevice));
+    // expensive (larger) mechanisms first
+    std::vector<int> order(nm);
+    for (int m = 0; m < nm; ++m) order[m] = m;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return ctx->mechs[a]->S > ctx->mechs[b]->S; });
+    for (int m : order) ctx->bins.push_back({m, cnt[m], cnt[m + 1] - cnt[m]});
+  }
+  ctx->bound = true;
+  ctx->integrated = false;
+  return BDFX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// integrate
+// ---------------------------------------------------------------------------
+
+static bdfx::Params make_params(bdfx_ctx ctx, const Bin &b, double t0, double tout) {
+  const bdfx_mech m = ctx->mechs[b.mech];
+  bdfx::Params P{};
+  P.mech = m->dev;
+  P.n_list = b.count;
+  P.list = ctx->mechs.size() > 1 ? reinterpret_cast<const int32_t *>(ctx->ws + ctx->off_bins) +
+                                       b.offset
+                                 : nullptr;
+  P.y = ctx->y;
+  P.ldy = ctx->ldy;
+  P.ldk = ctx->ldk;
+  P.T = ctx->T;
+  P.kscale = ctx->kscale;
+  P.F = ctx->F;
+  P.status = ctx->status;
+  P.stats = reinterpret_cast<bdfx::CellStats *>(ctx->stats);
+  P.t0 = t0;
+  P.tout = tout;
+  P.rtol = ctx->opt.rtol;
+  P.atol = ctx->d_atol;
+  P.atol_len = static_cast<int32_t>(ctx->atol.size());
+  P.max_order = ctx->opt.max_order;
+  P.max_steps = ctx->opt.max_steps;
+  P.n_sp = m->S;
+  P.queue = reinterpret_cast<uint32_t *>(ctx->ws + ctx->off_queue) + b.mech;
+  P.chunk = ctx->opt.queue_chunk;
+  if (ctx->opt.record_steps > 0) {
+    P.rec = reinterpret_cast<double *>(ctx->ws + ctx->off_rec);
+    P.rec_cap = ctx->opt.record_steps;
+    P.rec_stride = ctx->rec_stride;
+    P.rec_n = reinterpret_cast<int32_t *>(ctx->ws + ctx->off_recn);
+    P.rec_hpad = reinterpret_cast<double *>(ctx->ws + ctx->off_rechpad);
+    P.rec_y0 = reinterpret_cast<double *>(ctx->ws + ctx->off_recy0);
+  }
+  return P;
+}
+
+int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out) {
+  if (!ctx) return BDFX_EINVAL;
+  if (!ctx->bound) return fail(ctx, BDFX_EORDER, "bdfx_bind must precede bdfx_integrate");
+  if (!(t_out > t0) || !std::isfinite(t0) || !std::isfinite(t_out))
+    return fail(ctx, BDFX_EINVAL, "need finite t_out > t0");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const bool fp32 = ctx->opt.lu_precision == 32;
+  const bool queue = ctx->opt.scheduler == BDFX_SCHED_QUEUE;
+  if (queue) HIPCHK(ctx, bdfx_launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->ws + ctx->off_queue),
+                                              64, 0u, ctx->stream));
+  for (const Bin &b : ctx->bins) {
+    if (b.count == 0) continue;
+    const bdfx_mech m = ctx->mechs[b.mech];
+    const SizeEntry *se = size_for(m->S);
+    if (!se) return fail(ctx, BDFX_EUNSUPPORTED, "no kernel for %d species", m->S);
+    bdfx::Params P = make_params(ctx, b, t0, t_out);
+    P.use_queue = queue ? 1 : 0;
+    const int waves = ctx->opt.waves_per_block > 0 ? ctx->opt.waves_per_block : 1;
+    const int block = 64 * waves;
+    const int gpb = block / se->G;
+    const int ctl = 24;
+    const int fac_doubles = fp32 ? (se->S * se->S + 1) / 2 : se->S * se->S;
+    P.lds_doubles = static_cast<int32_t>(align_up(3 * m->R + 2 * se->S + ctl + fac_doubles, 2));
+    bdfx::LaunchCfg cfg;
+    cfg.block = block;
+    cfg.lds_bytes = static_cast<size_t>(gpb) * P.lds_doubles * 8;
+    if (cfg.lds_bytes > 65536)
+      return fail(ctx, BDFX_EUNSUPPORTED, "LDS per block %zu exceeds 64 KiB", cfg.lds_bytes);
+    if (queue) {
+      int occ = 0;
+      HIPCHK(ctx, se->occupancy(fp32, block, cfg.lds_bytes, &occ));
+      const int per_cu = ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : std::max(occ, 1);
+      const int64_t need = (b.count + gpb - 1) / gpb;
+      cfg.grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(per_cu) * ctx->n_cu, need));
+    } else {
+      cfg.grid = static_cast<int>((b.count + gpb - 1) / gpb);
+    }
+    if (cfg.grid < 1) continue;
+    HIPCHK(ctx, se->launch(P, fp32, cfg, ctx->stream));
+  }
+  ctx->last_t0 = t0;
+  ctx->last_tout = t_out;
+  ctx->integrated = true;
+  return BDFX_OK;
+}
+
+int bdfx_perturb(bdfx_ctx ctx, uint64_t seed, int64_t outer_step, double amplitude) {
+  if (!ctx) return BDFX_EINVAL;
+  if (!ctx->bound) return fail(ctx, BDFX_EORDER, "bdfx_bind must precede bdfx_perturb");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  for (const Bin &b : ctx->bins) {
+    if (b.count == 0) continue;
+    bdfx::Params P = make_params(ctx, b, 0.0, 0.0);
+    HIPCHK(ctx, bdfx_launch_perturb(P, seed, outer_step, amplitude, ctx->stream));
+  }
+  ctx->integrated = false;
+  return BDFX_OK;
+}
+
+int bdfx_stats_summary(bdfx_ctx ctx, bdfx_summary *out) {
+  if (!ctx || !out) return BDFX_EINVAL;
+  if (!ctx->bound) return fail(ctx, BDFX_EORDER, "nothing bound");
+  if (!ctx->stats) return fail(ctx, BDFX_EINVAL, "no stats buffer bound");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  std::vector<bdfx_cell_stats> st(ctx->N);
+  if (ctx->N)
+    HIPCHK(ctx, hipMemcpyAsync(st.data(), ctx->stats, ctx->N * sizeof(bdfx_cell_stats),
+                               hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  std::memset(out, 0, sizeof(*out));
+  out->n_cells = ctx->N;
+  for (const auto &s : st) {
+    if (s.status == 0)
+      out->n_success++;
+    else
+      out->n_failed++;
+    if (s.status <= 0 && s.status >= -10) out->status_count[-s.status]++;
+    out->nst += s.nst;
+    out->nfe += s.nfe;
+    out->nni += s.nni;
+    out->nsetups += s.nsetups;
+    out->netf += s.netf;
+    out->ncfn += s.ncfn;
+    out->max_nst = std::max<int64_t>(out->max_nst, s.nst);
+  }
+  return BDFX_OK;
+}
+
+int bdfx_adjoint(bdfx_ctx ctx, const double *, double *, double *) {
+  if (!ctx) return BDFX_EINVAL;
+  return fail(ctx, BDFX_EUNSUPPORTED, "adjoint not built yet");
+}
+
+}  // extern "C"
