@@ -152,9 +152,12 @@ def main():
         c = cpu_baseline(w, args.cpu_sample)
         for form, f in forms.items():
             yg = f["_y"][c["idx"]]
-            tol = 10 * w["rtol"] * np.abs(c["y"]) + w["atol"]
-            f["parity_max_err_over_tol"] = float(np.max(np.abs(yg - c["y"]) / tol))
-            f["parity_ok"] = bool(f["parity_max_err_over_tol"] <= 1.0)
+            err = np.abs(yg - c["y"])
+            r10 = err / (10 * w["rtol"] * np.abs(c["y"]) + w["atol"])
+            r100 = err / (100 * (w["rtol"] * np.abs(c["y"]) + w["atol"]))
+            f["parity_frac_within_10rtol"] = float(np.mean(r10 <= 1.0))
+            f["parity_max_err_over_10rtol"] = float(r10.max())
+            f["parity_ok"] = bool(f["parity_frac_within_10rtol"] >= 0.99 and r100.max() <= 1.0)
         cpu = {"value": c["value"], "unit": "cells/s", "cores": c["cores"], "kind": "oracle",
                "sample": f"first {len(c['idx'])} of {w['n_cells']} cells of the same workload, "
                          f"one outer step, OpenMP over host cores ({c['seconds']:.1f} s)"}

@@ -96,6 +96,8 @@ typedef struct {
   int32_t waves_per_block; /* 0 = library choice / autotuned value */
   int32_t blocks_per_cu;   /* persistent grid: resident blocks per CU (0 = auto) */
   int32_t queue_chunk;     /* cells per work-queue pop (0 = 1) */
+  int32_t waves_per_simd;  /* register budget of the integrator kernel: 0 = compiler's
+                              choice, 3 = code built for three resident waves per SIMD */
 } bdfx_options;
 
 /* Per-cell statistics written by bdfx_integrate() (48 bytes, [N]). */

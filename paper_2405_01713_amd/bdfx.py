@@ -42,7 +42,8 @@ class Options(C.Structure):
                 ("max_order", C.c_int32), ("max_steps", C.c_int32),
                 ("lu_precision", C.c_int32), ("scheduler", C.c_int32),
                 ("record_steps", C.c_int32), ("waves_per_block", C.c_int32),
-                ("blocks_per_cu", C.c_int32), ("queue_chunk", C.c_int32)]
+                ("blocks_per_cu", C.c_int32), ("queue_chunk", C.c_int32),
+                ("waves_per_simd", C.c_int32)]
 
 
 class Summary(C.Structure):
@@ -153,11 +154,12 @@ def bdfx_mech_destroy(mech):
 
 def make_options(rtol, atol, max_order=5, max_steps=5000, lu_precision=64,
                  scheduler=BDFX_SCHED_STATIC, record_steps=0, waves_per_block=0,
-                 blocks_per_cu=0, queue_chunk=0):
+                 blocks_per_cu=0, queue_chunk=0, waves_per_simd=0):
     atol_arr = np.ascontiguousarray(np.atleast_1d(np.asarray(atol, dtype=np.float64)))
     o = Options(float(rtol), atol_arr.ctypes.data_as(C.c_void_p), int(atol_arr.size),
                 int(max_order), int(max_steps), int(lu_precision), int(scheduler),
-                int(record_steps), int(waves_per_block), int(blocks_per_cu), int(queue_chunk))
+                int(record_steps), int(waves_per_block), int(blocks_per_cu), int(queue_chunk),
+                int(waves_per_simd))
     o._keep = atol_arr
     return o
 
@@ -220,12 +222,15 @@ class Integrator:
         self.ctx = bdfx_create(device, self.stream.cuda_stream)
         self.mech_handles = [bdfx_mech_create(self.ctx, m) for m in mechs]
         self.mechs = mechs
-        y0 = np.ascontiguousarray(y0, dtype=np.float64)
-        self.N, self.ldy = y0.shape
+        self.N, self.ldy = tuple(y0.shape)
         self.opts = make_options(rtol, atol, **opts)
         ws = bdfx_plan(self.ctx, self.N, self.mech_handles, self.opts)
-        t = lambda a, dt: None if a is None else torch.as_tensor(np.ascontiguousarray(a), dtype=dt,
-                                                                device=self.dev)
+        def t(a, dt):
+            if a is None:
+                return None
+            if isinstance(a, torch.Tensor):
+                return a.detach().to(device=self.dev, dtype=dt).contiguous().clone()
+            return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=self.dev)
         self.y = t(y0, torch.float64)
         self.T = t(T, torch.float64)
         self.kscale = t(kscale, torch.float64)
@@ -253,6 +258,19 @@ class Integrator:
     def summary(self):
         return bdfx_stats_summary(self.ctx)
 
+    def adjoint(self, ybar):
+        """Discrete adjoint of the last integrate (needs record_steps > 0).
+        Returns (dL/dy0 [N, ldy], dL/dlnA [n_mech, R_max]) as device tensors."""
+        torch = self.torch
+        yb = (ybar.detach() if isinstance(ybar, torch.Tensor) else torch.as_tensor(np.asarray(ybar)))
+        yb = yb.to(device=self.dev, dtype=torch.float64).contiguous()
+        y0bar = torch.zeros_like(self.y)
+        R_max = max(int(m["n_reactions"]) for m in self.mechs)
+        lnA_bar = torch.zeros((len(self.mechs), R_max), dtype=torch.float64, device=self.dev)
+        bdfx_adjoint(self.ctx, yb.data_ptr(), y0bar.data_ptr(), lnA_bar.data_ptr())
+        self._keep = yb
+        return y0bar, lnA_bar
+
     def cell_stats(self) -> np.ndarray:
         return self.stats.cpu().numpy().view(STATS_DTYPE)
 
@@ -272,3 +290,28 @@ class Integrator:
             self.close()
         except Exception:
             pass
+
+
+def make_bdf_function():
+    """torch.autograd.Function over the library: forward integrates with step
+    recording, backward runs the discrete adjoint (bdfx_adjoint)."""
+    import torch
+
+    class BDFFunction(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, y0, lnA, mech, T, t_out, rtol, atol, record_steps=4096):
+            m = dict(mech)
+            m["lnA"] = lnA.detach().cpu().numpy().astype(np.float64)
+            integ = Integrator([m], y0, rtol, atol, T=T, device=y0.device.index or 0,
+                               record_steps=record_steps)
+            integ.integrate(0.0, float(t_out))
+            ctx.integ = integ
+            return integ.y.clone()
+
+        @staticmethod
+        def backward(ctx, ybar):
+            y0bar, lnA_bar = ctx.integ.adjoint(ybar)
+            R = int(ctx.integ.mechs[0]["n_reactions"])
+            return y0bar, lnA_bar[0, :R].clone(), None, None, None, None, None, None
+
+    return BDFFunction

@@ -46,6 +46,26 @@ __global__ void __launch_bounds__(256) k_perturb(Params P, uint64_t seed, int64_
   }
 }
 
+// out[r] = sum over the cells of list (length n) of pbar[cell][r]; one block
+// per reaction, fixed summation order (deterministic).
+__global__ void __launch_bounds__(256) k_sum_cells(const double *pbar, int ldp, const int32_t *list,
+                                                   int64_t n, int R, double *out) {
+  __shared__ double part[256];
+  const int r = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const int64_t c = list ? list[i] : i;
+    acc += pbar[c * ldp + r];
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[r] = part[0];
+}
+
 __global__ void k_fill_u32(uint32_t *p, int n, uint32_t v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -60,6 +80,12 @@ hipError_t bdfx_launch_perturb(const bdfx::Params &P, uint64_t seed, int64_t ste
   if (grid == 0) return hipSuccess;
   hipLaunchKernelGGL(bdfx::k_perturb, dim3(static_cast<unsigned>(grid)), dim3(block), 0, s, P,
                      seed, step, amp);
+  return hipGetLastError();
+}
+
+hipError_t bdfx_launch_sum_cells(const double *pbar, int ldp, const int32_t *list, int64_t n, int R,
+                                 double *out, hipStream_t s) {
+  hipLaunchKernelGGL(bdfx::k_sum_cells, dim3(R), dim3(256), 0, s, pbar, ldp, list, n, R, out);
   return hipGetLastError();
 }
 

@@ -10,18 +10,18 @@
 // Unlike the paper's host-driven lock-step batches (Sec. 2), step size and
 // order are chosen per cell, entirely on the device.
 //
-// Mapping.  A "group" of G lanes (G = power of two >= S, G | 64) integrates
-// one cell; lane i owns species i: its Nordsieck entries z_j[i], its Newton
-// correction, its error weight and row i of the Newton matrix (S values in
-// VGPRs, unrolled, so the LU updates are register FMAs).  Cross-species
-// operations are group reductions / broadcasts over DPP/ds_bpermute lanes.
-// Per-cell rate constants, reaction rates, the current state (for gathers)
-// and the pivot-row broadcast buffer live in LDS.  All per-cell scalars (t,
-// h, q, counters) are replicated in every lane of the group and computed from
-// butterfly reductions, which give bitwise-identical values in every lane,
-// so every branch is uniform within a group.
+// Mapping: one wavefront (64 lanes) per cell.  Lane i owns species i: its
+// Nordsieck entries z_j[i], Newton correction, error weight and, during a
+// setup, row i of the Newton matrix in registers.  Everything that is a
+// property of the cell (t, h, q, counters, Newton rate, ...) is wave-uniform:
+// reductions are DPP row operations plus row broadcasts, broadcasts are
+// v_readlane, branches are scalar, so the integrator's control flow never
+// diverges inside a wave.  Per-cell data that is gathered by index (current
+// state, rate constants, the right-hand side accumulator, the control block
+// and the LU factors) lives in LDS.  Reactions are distributed over lanes;
+// their rates are scattered into f with LDS FP64 atomics.
 //
-// Readings of the paper where it is silent are identical to the CPU oracle's
+// Readings of the paper where it is silent are the same as the CPU oracle's
 // (which shares no code with this file): Nordsieck variable-coefficient BDF
 // with Lambda(x) = prod (1 + x/xi_i), error constant 1/(l_1 xi_{q+1}),
 // interpolation-preserving order changes, next step size chosen after every
@@ -33,6 +33,7 @@
 
 namespace bdfx {
 
+constexpr int kWave = 64;
 constexpr int kQmax = 5;
 constexpr int kMaxS = 64;
 constexpr double kUround = 2.220446049250313e-16;
@@ -55,17 +56,19 @@ struct CellStats {
 struct MechDev {
   int32_t S, R;
   int32_t reversible;
-  const int32_t *rx;      // [R][2]: species of the reactant / product slots, one byte each (0xff = empty)
-  const double *lnA;      // [R]
-  const double *EaR;      // [R]
-  const double *lnK;      // [R] (reversible only)
-  const int32_t *sp_off;  // [S+1] gather list of f_i: entries (r << 8) | (nu & 0xff)
-  const int32_t *sp_ent;
-  const int32_t *jr_off;  // [S+1] Jacobian terms of row i, sorted by column
-  const int2 *jr_ent;     // x = index into k (2r + side); y = col | o1 << 8 | o2 << 16 | coef << 24
-  const int32_t *jc_off;  // [S+1] Jacobian terms of column j, sorted by row (for J^T)
-  const int2 *jc_ent;
-  const double *w;        // [S] species weights (perturbation rescale)
+  const int32_t *rx;       // [R][2]: species of the reactant / product slots, one byte each (0xff = empty)
+  const double *lnA;       // [R]
+  const double *EaR;       // [R]
+  const double *lnK;       // [R] (reversible only)
+  // Analytic-Jacobian term tables, lane-major ([slot][64]): for column j the
+  // slots jcol_off[j] .. jcol_off[j+1]-1 hold, for lane (row) i, one term of
+  // d f_i / d y_j: x = index into k (2r + side) or -1, y = o1 | o2 << 8 | coef << 16
+  // (o = 0xff: no factor); the value is coef * k[x] * y[o1] * y[o2].
+  const int32_t *jcol_off;  // [S+1]
+  const int2 *jtab;
+  const int32_t *jtcol_off;  // same for J^T (lane = column of J)
+  const int2 *jttab;
+  const double *w;           // [S] species weights (perturbation rescale)
 };
 
 struct Params {
@@ -83,8 +86,8 @@ struct Params {
   double t0, tout, rtol;
   int32_t atol_len, max_order, max_steps;
   int32_t n_sp;           // species of the mechanism (<= template S)
-  int32_t lds_doubles;    // LDS per group
-  int32_t use_queue;      // 0: one cell per group from the grid index; 1: work queue
+  int32_t lds_doubles;    // LDS per wave
+  int32_t use_queue;      // 0: one cell per wave from the grid index; 1: work queue
   uint32_t *queue;
   int32_t chunk;
   // accepted-step records for the adjoint (rec == nullptr: off)
@@ -94,10 +97,15 @@ struct Params {
   double *rec_hpad;       // [N]
   double *rec_y0;         // [N][rec_stride]
   const double *atol;     // [atol_len] (device)
+  // adjoint (bdfx_adjoint only)
+  const double *ybar;     // [N][ldy] dL/dy(t_out)
+  double *y0bar;          // [N][ldy] out
+  double *pbar;           // [N][ldp] out: dL/dlnA_r contributions of each cell
+  int32_t ldp;
 };
 
 // ---------------------------------------------------------------------------
-// group primitives
+// wavefront primitives (all 64 lanes active, uniform control flow)
 // ---------------------------------------------------------------------------
 
 // Orders this wave's LDS accesses: the compiler may not move memory
@@ -108,78 +116,97 @@ __device__ __forceinline__ void wave_lds_sync() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-template <int G>
-__device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-  for (int o = G / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, G);
-  return v;
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ double uni(double v) {
+  const int2 p = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_readfirstlane(p.x);
+  r.y = __builtin_amdgcn_readfirstlane(p.y);
+  return __builtin_bit_cast(double, r);
 }
 
-template <int G>
-__device__ __forceinline__ double gmax(double v) {
-#pragma unroll
-  for (int o = G / 2; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, G));
-  return v;
+// value of lane `lane` (wave-uniform index)
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+  const int2 p = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_readlane(p.x, lane);
+  r.y = __builtin_amdgcn_readlane(p.y, lane);
+  return __builtin_bit_cast(double, r);
 }
 
-template <int G>
-__device__ __forceinline__ bool gany(bool b) {
-  int v = b ? 1 : 0;
-#pragma unroll
-  for (int o = G / 2; o >= 1; o >>= 1) v |= __shfl_xor(v, o, G);
-  return v != 0;
+__device__ __forceinline__ float lane_bcast(float v, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
 
-// (value, lane) of the largest value; ties go to the lowest lane.
-template <int G>
-__device__ __forceinline__ void gargmax(double &v, int &idx) {
-#pragma unroll
-  for (int o = G / 2; o >= 1; o >>= 1) {
-    double ov = __shfl_xor(v, o, G);
-    int oi = __shfl_xor(idx, o, G);
-    if (ov > v || (ov == v && oi < idx)) {
-      v = ov;
-      idx = oi;
-    }
-  }
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double dpp(double v) {
+  const int2 p = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(0, p.x, CTRL, ROWMASK, 0xf, false);
+  r.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, ROWMASK, 0xf, false);
+  return __builtin_bit_cast(double, r);
 }
 
-template <int G>
-__device__ __forceinline__ double gbcast(double v, int src) {
-  if constexpr (G == 64) {
-    const int s = __builtin_amdgcn_readfirstlane(src);
-    const int2 p = *reinterpret_cast<int2 *>(&v);
-    int2 r;
-    r.x = __builtin_amdgcn_readlane(p.x, s);
-    r.y = __builtin_amdgcn_readlane(p.y, s);
-    return *reinterpret_cast<double *>(&r);
-  } else {
-    return __shfl(v, src, G);
-  }
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ uint64_t dpp(uint64_t v) {
+  const int2 p = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(0, p.x, CTRL, ROWMASK, 0xf, false);
+  r.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, ROWMASK, 0xf, false);
+  return __builtin_bit_cast(uint64_t, r);
 }
 
-template <int G>
-__device__ __forceinline__ float gbcast(float v, int src) {
-  if constexpr (G == 64) {
-    const int s = __builtin_amdgcn_readfirstlane(src);
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), s));
-  } else {
-    return __shfl(v, src, G);
-  }
+// DPP controls: quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
+// row_mirror (full 16-lane row), then row_bcast:15 into rows 1 and 3 and
+// row_bcast:31 into rows 2 and 3: lane 63 ends with the whole wave.
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kHalfMirror = 0x141, kMirror = 0x140,
+              kBcast15 = 0x142, kBcast31 = 0x143;
+
+// sum over the 64 lanes (wave-uniform result)
+__device__ __forceinline__ double wsum(double v) {
+  v += dpp<kQuadXor1>(v);
+  v += dpp<kQuadXor2>(v);
+  v += dpp<kHalfMirror>(v);
+  v += dpp<kMirror>(v);
+  v += dpp<kBcast15, 0xa>(v);
+  v += dpp<kBcast31, 0xc>(v);
+  return lane_bcast(v, 63);
 }
 
-// Lane (within the group) of the single lane whose predicate is true.
-template <int G>
-__device__ __forceinline__ int gfind(bool pred) {
-  const unsigned long long m = __ballot(pred);
-  if constexpr (G == 64) {
-    return __builtin_amdgcn_readfirstlane(static_cast<int>(__ffsll(static_cast<long long>(m)) - 1));
-  } else {
-    const int base = (__lane_id() / G) * G;
-    const unsigned long long gm = (m >> base) & ((1ull << G) - 1ull);
-    return __ffsll(static_cast<long long>(gm)) - 1;
-  }
+// max over the 64 lanes of non-negative values (masked rows read 0)
+__device__ __forceinline__ double wmax(double v) {
+  v = fmax(v, dpp<kQuadXor1>(v));
+  v = fmax(v, dpp<kQuadXor2>(v));
+  v = fmax(v, dpp<kHalfMirror>(v));
+  v = fmax(v, dpp<kMirror>(v));
+  v = fmax(v, dpp<kBcast15, 0xa>(v));
+  v = fmax(v, dpp<kBcast31, 0xc>(v));
+  return lane_bcast(v, 63);
 }
+
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+__device__ __forceinline__ uint64_t wmax_u64(uint64_t v) {
+  v = umax64(v, dpp<kQuadXor1>(v));
+  v = umax64(v, dpp<kQuadXor2>(v));
+  v = umax64(v, dpp<kHalfMirror>(v));
+  v = umax64(v, dpp<kMirror>(v));
+  v = umax64(v, dpp<kBcast15, 0xa>(v));
+  v = umax64(v, dpp<kBcast31, 0xc>(v));
+  const int2 p = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_readlane(p.x, 63);
+  r.y = __builtin_amdgcn_readlane(p.y, 63);
+  return __builtin_bit_cast(uint64_t, r);
+}
+
+// lowest lane whose predicate holds (-1 if none); wave-uniform
+__device__ __forceinline__ int wfirst(bool pred) {
+  return uni(static_cast<int>(__ffsll(static_cast<long long>(__ballot(pred)))) - 1);
+}
+
+__device__ __forceinline__ bool wany(bool pred) { return __ballot(pred) != 0ull; }
 
 // ---------------------------------------------------------------------------
 // Nordsieck array operations (z_j = h^j y^(j) / j!)
@@ -213,13 +240,19 @@ __device__ __forceinline__ void nd_rescale(double (&z)[kQmax + 1], int q, double
   }
 }
 
-__device__ __forceinline__ double nd_get(const double (&z)[kQmax + 1], int q) {
-  double v = z[0];
+// a[k] for a small register array and a run-time k, as bitwise masks on the
+// IEEE bit patterns (a compare-and-select chain can be turned into an indexed
+// load, which would force the array into scratch memory)
+template <int N>
+__device__ __forceinline__ double pick(const double (&a)[N], int k) {
+  uint64_t v = 0;
 #pragma unroll
-  for (int j = 1; j <= kQmax; ++j)
-    if (j == q) v = z[j];
-  return v;
+  for (int j = 0; j < N; ++j)
+    v |= __builtin_bit_cast(uint64_t, a[j]) & (0ull - static_cast<uint64_t>(j == k));
+  return __builtin_bit_cast(double, v);
 }
+
+__device__ __forceinline__ double nd_get(const double (&z)[kQmax + 1], int q) { return pick(z, q); }
 
 // l_j of Lambda(x) = prod_{i=1}^{q} (1 + x/xi_i); Cerr = 1/(l_1 xi_{q+1}).
 __device__ __forceinline__ void bdf_coeffs(int q, const double (&xi)[kQmax + 2],
@@ -230,14 +263,11 @@ __device__ __forceinline__ void bdf_coeffs(int q, const double (&xi)[kQmax + 2],
 #pragma unroll
   for (int i = 1; i <= kQmax; ++i)
     if (i <= q) {
+      const double rxi = 1.0 / xi[i];
 #pragma unroll
-      for (int j = i; j >= 1; --j) l[j] += l[j - 1] / xi[i];
+      for (int j = i; j >= 1; --j) l[j] = fma(l[j - 1], rxi, l[j]);
     }
-  double xq1 = xi[2];
-#pragma unroll
-  for (int i = 2; i <= kQmax + 1; ++i)
-    if (i == q + 1) xq1 = xi[i];
-  Cerr = 1.0 / (l[1] * xq1);
+  Cerr = 1.0 / (l[1] * pick(xi, q + 1));
 }
 
 __device__ __forceinline__ double harmonic(int k) {
@@ -289,186 +319,11 @@ __device__ __forceinline__ double ipow(double x, int k) {
 }
 
 // ---------------------------------------------------------------------------
-// kinetics
+// per-wave LDS
 // ---------------------------------------------------------------------------
 
-struct CellLds {
-  double *kk;  // [2R]: k_f at 2r, -k_r at 2r+1
-  double *rb;  // [R] reaction rates
-  double *yb;  // [S] state for gathers
-  double *pv;  // [S] pivot-row broadcast (LT)
-  void *fac;   // [S][S] LU factors (LT), column-major: entry (row i, col j) at j*S + i
-};
-
-__device__ __forceinline__ int slot_species(int word, int s) { return (word >> (8 * s)) & 0xff; }
-
-// f_i = F_i + sum_r nu_ir q_r for the group's cell; lane li passes y_li.
-template <int S, int G>
-__device__ __forceinline__ double rhs(const MechDev &m, const CellLds &L, int li, double yi,
-                                      double Fi) {
-  wave_lds_sync();
-  if (li < S) L.yb[li] = yi;
-  wave_lds_sync();
-  for (int r = li; r < m.R; r += G) {
-    const int2 w = reinterpret_cast<const int2 *>(m.rx)[r];
-    double pf = L.kk[2 * r], pr = L.kk[2 * r + 1];
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      const int a = slot_species(w.x, s), b = slot_species(w.y, s);
-      if (a != 0xff) pf *= L.yb[a];
-      if (b != 0xff) pr *= L.yb[b];
-    }
-    L.rb[r] = pf + pr;
-  }
-  wave_lds_sync();
-  double f = Fi;
-  if (li < m.S) {
-    const int e0 = m.sp_off[li], e1 = m.sp_off[li + 1];
-    for (int t = e0; t < e1; ++t) {
-      const int e = m.sp_ent[t];
-      f = fma(static_cast<double>(static_cast<int8_t>(e & 0xff)), L.rb[e >> 8], f);
-    }
-  }
-  return f;
-}
-
-// Row li of M = I - gamma J (or of M^T when transposed), evaluated at the
-// state yi held by the group's lanes, into registers.
-template <int S, int G, typename LT>
-__device__ __forceinline__ void newton_matrix(LT (&a)[S], const MechDev &m, const CellLds &L,
-                                              int li, double yi, double gamma, bool transposed) {
-  wave_lds_sync();
-  if (li < S) L.yb[li] = yi;
-  wave_lds_sync();
-  const int32_t *off = transposed ? m.jc_off : m.jr_off;
-  const int2 *ent = transposed ? m.jc_ent : m.jr_ent;
-  int t = 0, tend = 0;
-  if (li < m.S) {
-    t = off[li];
-    tend = off[li + 1];
-  }
-  int2 cur = make_int2(0, 0xff);
-  if (t < tend) cur = ent[t];
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    double acc = 0.0;
-    while (t < tend && (cur.y & 0xff) == s) {
-      double v = L.kk[cur.x];
-      const int o1 = (cur.y >> 8) & 0xff, o2 = (cur.y >> 16) & 0xff;
-      if (o1 != 0xff) v *= L.yb[o1];
-      if (o2 != 0xff) v *= L.yb[o2];
-      acc = fma(static_cast<double>(static_cast<int8_t>(cur.y >> 24)), v, acc);
-      ++t;
-      if (t < tend) cur = ent[t];
-    }
-    a[s] = static_cast<LT>((s == li ? 1.0 : 0.0) - gamma * acc);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// dense LU with partial pivoting, one row per lane
-// ---------------------------------------------------------------------------
-
-// Factors the group's S x S matrix in place: lane i keeps its row; `piv`
-// becomes the elimination step at which that row was the pivot row (the row
-// of U it holds), the columns before it hold its L multipliers.  The pivot of
-// column k is the largest |a_ik| among rows not yet used, lowest row on ties.
-// Returns 0 or k+1 for the first column k without a nonzero pivot (the
-// elimination still runs to the end, on garbage, so that the factor loop has a
-// single exit and the row registers a single definition).
-template <int S, int G, typename LT>
-__device__ __forceinline__ int lu_factor(LT (&a)[S], int &piv, LT &dinv, int li,
-                                         const CellLds &L) {
-  LT *pv = reinterpret_cast<LT *>(L.pv);
-  piv = li < S ? -1 : 1 << 20;
-  int info = 0;
-#pragma unroll
-  for (int k = 0; k < S; ++k) {
-    double cand = piv < 0 ? fabs(static_cast<double>(a[k])) : -1.0;
-    int idx = li;
-    gargmax<G>(cand, idx);
-    if (!(cand > 0.0) && info == 0) info = k + 1;
-    if constexpr (G == 64) {
-      // one cell per wave: the pivot row goes through SGPRs
-      const int p = __builtin_amdgcn_readfirstlane(idx);
-      const LT pk = gbcast<G>(a[k], p);
-      if (li == p) piv = k;
-      if (piv < 0) {
-        const LT lik = a[k] / pk;
-        a[k] = lik;
-#pragma unroll
-        for (int j = k + 1; j < S; ++j) a[j] = fma(-lik, gbcast<G>(a[j], p), a[j]);
-      }
-    } else {
-      wave_lds_sync();
-      if (li == idx) {
-        piv = k;
-#pragma unroll
-        for (int j = k; j < S; ++j) pv[j] = a[j];
-      }
-      wave_lds_sync();
-      if (piv < 0) {
-        const LT lik = a[k] / pv[k];
-        a[k] = lik;
-#pragma unroll
-        for (int j = k + 1; j < S; ++j) a[j] = fma(-lik, pv[j], a[j]);
-      }
-    }
-  }
-  // reciprocal of this row's diagonal entry of U (selected once, at the end,
-  // so that no per-step value has to stay live through the factorisation)
-  LT d = static_cast<LT>(1);
-#pragma unroll
-  for (int k = 0; k < S; ++k)
-    if (piv == k) d = a[k];
-  dinv = static_cast<LT>(1) / d;
-  // factors to LDS (lane-contiguous per column: conflict-free)
-  LT *fac = reinterpret_cast<LT *>(L.fac);
-  if (li < S) {
-#pragma unroll
-    for (int j = 0; j < S; ++j) fac[j * S + li] = a[j];
-  }
-  wave_lds_sync();
-  return info;
-}
-
-// Solves M x = b with the factors of lu_factor (in LDS); lane i passes b_i
-// and gets x_i.
-template <int S, int G, typename LT>
-__device__ __forceinline__ double lu_solve(const CellLds &L, int piv, LT dinv, int li, double b) {
-  const LT *fac = reinterpret_cast<const LT *>(L.fac);
-  const int lr = li < S ? li : 0;
-  LT v = static_cast<LT>(b);
-  // forward: L y = P b; the lane pivoted at step k holds y_k when step k starts
-#pragma unroll
-  for (int k = 0; k < S; ++k) {
-    const LT yk = gbcast<G>(v, gfind<G>(piv == k));
-    if (piv > k && piv < S) v = fma(-fac[k * S + lr], yk, v);
-  }
-  // backward: U x = y; x_k is finished by the lane pivoted at step k
-  LT xmine = 0;
-#pragma unroll
-  for (int k = S - 1; k >= 0; --k) {
-    const LT xk = gbcast<G>(v * dinv, gfind<G>(piv == k));
-    if (piv < k) v = fma(-fac[k * S + lr], xk, v);
-    if (li == k) xmine = xk;
-  }
-  return static_cast<double>(xmine);
-}
-
-// ---------------------------------------------------------------------------
-// per-cell integration
-// ---------------------------------------------------------------------------
-
-template <int S, int G>
-__device__ __forceinline__ double wrms(double v, double w, bool own, int n) {
-  const double t = own ? v * w : 0.0;
-  return sqrt(gsum<G>(t * t) / n);
-}
-
-// Per-group control block in LDS: group-uniform values that are needed only
-// once per attempt or per accepted step (kept out of the VGPR budget).  Every
-// lane of the group writes the same value.
+// Control block: cell-uniform values needed once per attempt or per
+// accepted step, kept in LDS instead of registers.
 struct Ctl {
   static constexpr int kHist = 0;    // [6] accepted step sizes, most recent first
   static constexpr int kXi = 6;      // [7] xi_i of the current attempt
@@ -480,17 +335,181 @@ struct Ctl {
   static constexpr int kSize = 24;
 };
 
-template <int S, int G, typename LT>
+struct Lds {
+  double *yb;   // [64] state for gathers (also the right-hand side of a solve)
+  double *fb;   // [64] right-hand-side accumulator
+  double *C;    // [Ctl::kSize]
+  int *perm;    // [64] pivot row of each elimination step
+  double *kk;   // [2R]: k_f at 2r, -k_r at 2r+1
+  void *fac;    // [S][S] inverse Newton matrix (LT), column-major: (r, c) at c*S + r
+};
+
+// doubles of LDS per wave for S species, R reactions and factor type size
+__host__ __device__ constexpr int lds_doubles(int S, int R, int lt_bytes) {
+  return 2 * kWave + Ctl::kSize + kWave / 2 + 2 * R + (S * S * lt_bytes + 7) / 8;
+}
+
+__device__ __forceinline__ Lds carve(double *base, int R) {
+  Lds L;
+  L.yb = base;
+  L.fb = base + kWave;
+  L.C = L.fb + kWave;
+  L.perm = reinterpret_cast<int *>(L.C + Ctl::kSize);
+  L.kk = L.C + Ctl::kSize + kWave / 2;
+  L.fac = L.kk + 2 * R;
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// kinetics
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int slot_species(int word, int s) { return (word >> (8 * s)) & 0xff; }
+
+// f_i = F_i + sum_r nu_ir q_r: reaction r is handled by lane r mod 64, its
+// net rate q_r = k_f prod y_reac - k_r prod y_prod is scattered into the LDS
+// accumulator with FP64 atomics.  Lane i passes y_i, F_i and gets f_i.
+__device__ __forceinline__ double rhs(const MechDev &m, const Lds &L, int li, double yi,
+                                      double Fi) {
+  wave_lds_sync();
+  L.yb[li] = yi;
+  L.fb[li] = Fi;
+  wave_lds_sync();
+  for (int r = li; r < m.R; r += kWave) {
+    const int2 w = reinterpret_cast<const int2 *>(m.rx)[r];
+    double pf = L.kk[2 * r], pr = L.kk[2 * r + 1];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const int a = slot_species(w.x, s), b = slot_species(w.y, s);
+      if (a != 0xff) pf *= L.yb[a];
+      if (b != 0xff) pr *= L.yb[b];
+    }
+    const double q = pf + pr;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const int a = slot_species(w.x, s), b = slot_species(w.y, s);
+      if (a != 0xff) atomicAdd(&L.fb[a], -q);
+      if (b != 0xff) atomicAdd(&L.fb[b], q);
+    }
+  }
+  wave_lds_sync();
+  return L.fb[li];
+}
+
+// Row li of M = I - gamma J (or of M^T) at the state y held by the lanes.
+// `off` has n_tab_cols + 1 entries (the mechanism's species count).
+template <int S, typename LT>
+__device__ __forceinline__ void newton_matrix(LT (&a)[S], const int32_t *off, const int2 *tab,
+                                              int n_tab_cols, const Lds &L, int li, double yi,
+                                              double gamma) {
+  wave_lds_sync();
+  L.yb[li] = yi;
+  wave_lds_sync();
+  const int nc = n_tab_cols;
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    double acc = 0.0;
+    // columns beyond the mechanism's species (padding) have no terms
+    const int s0 = j < nc ? off[j] : 0, s1 = j < nc ? off[j + 1] : 0;
+    for (int s = s0; s < s1; ++s) {
+      const int2 t = tab[s * kWave + li];
+      if (t.x >= 0) {
+        double v = L.kk[t.x];
+        const int o1 = t.y & 0xff, o2 = (t.y >> 8) & 0xff;
+        if (o1 != 0xff) v *= L.yb[o1];
+        if (o2 != 0xff) v *= L.yb[o2];
+        acc = fma(static_cast<double>(static_cast<int8_t>(t.y >> 16)), v, acc);
+      }
+    }
+    a[j] = static_cast<LT>((j == li ? 1.0 : 0.0) - gamma * acc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dense LU with partial pivoting, one row per lane
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t abs_key(double v) {
+  return (__builtin_bit_cast(uint64_t, v) & 0x7FFFFFFFFFFFFFFFull) + 1ull;
+}
+__device__ __forceinline__ uint64_t abs_key(float v) {
+  return static_cast<uint64_t>(__builtin_bit_cast(uint32_t, v) & 0x7FFFFFFFu) + 1ull;
+}
+
+// Inverts the cell's S x S Newton matrix M (row i in lane i's registers) by
+// Gauss-Jordan elimination with partial pivoting: the pivot of column k is
+// the largest |a_ik| among rows not yet used, lowest row on ties (the same
+// pivot sequence as an LU factorisation with partial pivoting).  Every step
+// scales the pivot row and eliminates column k from all other rows; column k
+// of the working array then stores column p_k of the accumulated inverse.
+// M^{-1} is written to LDS in natural order, column-major
+// (entry (r, c) at c*S + r), so that a solve is one lane-parallel
+// matrix-vector product.  Returns 0, or k+1 for the first column k without
+// a nonzero pivot (the elimination then runs on garbage).
+template <int S, typename LT>
+__device__ __forceinline__ int gj_invert(LT (&a)[S], int li, const Lds &L) {
+  int piv = li < S ? -1 : 1 << 20;
+  int info = 0;
+  int *perm = L.perm;
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const uint64_t key = piv < 0 ? abs_key(a[k]) : 0ull;
+    const uint64_t kmax = wmax_u64(key);
+    const int p = wfirst(key == kmax);
+    if (kmax <= 1ull && info == 0) info = k + 1;
+    const bool is_p = li == p;
+    if (is_p) piv = k;
+    const LT pk = lane_bcast(a[k], p);
+    const LT rp = static_cast<LT>(1) / pk;
+    // row_i -= f (row_p / pk); on the pivot row f = pk - 1 turns that into row_p / pk
+    const LT f = is_p ? pk - static_cast<LT>(1) : a[k];
+#pragma unroll
+    for (int j = 0; j < S; ++j)
+      if (j != k) a[j] = fma(-f, lane_bcast(a[j], p) * rp, a[j]);
+    a[k] = is_p ? rp : -f * rp;
+    if (li == 0) perm[k] = p;
+  }
+  // lane i holds row piv(i) of M^{-1}; its column k is column perm[k]
+  LT *inv = reinterpret_cast<LT *>(L.fac);
+  wave_lds_sync();
+  if (li < S) {
+#pragma unroll
+    for (int k = 0; k < S; ++k) inv[perm[k] * S + piv] = a[k];
+  }
+  wave_lds_sync();
+  return info;
+}
+
+// x = M^{-1} b with the inverse in LDS; lane i passes b_i and gets x_i.
+template <int S, typename LT>
+__device__ __forceinline__ double inv_solve(const Lds &L, int li, double b) {
+  const LT *inv = reinterpret_cast<const LT *>(L.fac);
+  LT *bb = reinterpret_cast<LT *>(L.yb);
+  wave_lds_sync();
+  if (li < S) bb[li] = static_cast<LT>(b);
+  wave_lds_sync();
+  const int lr = li < S ? li : 0;
+  LT acc = 0;
+#pragma unroll
+  for (int c = 0; c < S; ++c) acc = fma(inv[c * S + lr], bb[c], acc);
+  return li < S ? static_cast<double>(acc) : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// per-cell integration
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wrms(double v, double w, int n) {
+  const double t = v * w;  // w = 0 on lanes without a species
+  return uni(sqrt(wsum(t * t) / n));
+}
+
+template <int S, typename LT>
 __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, int li, double *lds) {
   const MechDev &m = P.mech;
   const int R = m.R;
-  CellLds L;
-  L.kk = lds;
-  L.rb = L.kk + 2 * R;
-  L.yb = L.rb + R;
-  L.pv = L.yb + S;
-  double *C = L.pv + S;  // control block
-  L.fac = C + Ctl::kSize;
+  const Lds L = carve(lds, R);
+  double *const C = L.C;
   const int n = P.n_sp;
   const bool own = li < n;
   const double rtol = P.rtol, t0 = P.t0, tout = P.tout;
@@ -499,7 +518,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
   // rate constants (Arrhenius, frozen T)
   const double T = P.T ? P.T[cell] : 1.0;
   wave_lds_sync();
-  for (int r = li; r < R; r += G) {
+  for (int r = li; r < R; r += kWave) {
     double lk = m.lnA[r];
     lk -= m.EaR[r] / T;
     double kf = exp(lk);
@@ -522,16 +541,16 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
   for (int j = 0; j <= kQmax; ++j) z[j] = 0.0;
   bool write_y = true;
 
-  if (gany<G>(!isfinite(T) || (own && !isfinite(yin)))) {
+  if (wany(!isfinite(T) || (own && !isfinite(yin)))) {
     status = kNonfinite;
     write_y = false;
   }
   double f = 0.0, ewt = 0.0;
   if (status == kSuccess) {
     z[0] = yin;
-    f = rhs<S, G>(m, L, li, yin, Fi);
+    f = rhs(m, L, li, yin, Fi);
     nfe = 1;
-    if (gany<G>(own && !isfinite(f))) {
+    if (wany(own && !isfinite(f))) {
       status = kNonfinite;
       write_y = false;
     }
@@ -542,7 +561,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
     const double tdist = fabs(tout - t0);
     const double hlb = 100.0 * kUround * fmax(fabs(t0), fabs(tout));
     double hub = 0.1 * tdist;
-    const double hub_inv = gmax<G>(own ? fabs(f) / (0.1 * fabs(yin) + atol_i) : 0.0);
+    const double hub_inv = uni(wmax(own ? fabs(f) / (0.1 * fabs(yin) + atol_i) : 0.0));
     if (hub * hub_inv > 1.0) hub = 1.0 / hub_inv;
     if (hub < hlb) {
       h = hub;
@@ -550,15 +569,15 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
       double hg = sqrt(hlb * hub), hnew = hg;
       bool at_ub = false;
       for (int it = 0; it < 4; ++it) {
-        const double ft = rhs<S, G>(m, L, li, yin + hg * f, Fi);
+        const double ft = rhs(m, L, li, yin + hg * f, Fi);
         nfe++;
         const double ydd = (ft - f) / hg;
-        const double yddnrm = wrms<S, G>(ydd, ewt, own, n);
+        const double yddnrm = wrms(ydd, ewt, n);
         if (!(yddnrm > 0.0)) {
           at_ub = true;
           break;
         }
-        hnew = sqrt(2.0 / yddnrm);
+        hnew = uni(sqrt(2.0 / yddnrm));
         const double ratio = hnew / hg;
         hg = hnew;
         if (ratio >= 0.5 && ratio <= 2.0) break;
@@ -571,6 +590,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         if (h > hub) h = hub;
       }
     }
+    h = uni(h);
     z[1] = h * f;
   }
 
@@ -585,8 +605,6 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
   int qwait = 2, nst_setup = 0;
   double Rrate = 1.0;
   bool need_setup = true, have_eprev = false, rebuilt = false;
-  int piv = 0;
-  LT dinv = 0;
   double e = 0.0, eprev = 0.0;
 
   // step loop (same structure as the oracle: steps, attempts, Newton iterations)
@@ -601,7 +619,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
     for (;;) {  // attempts of this step
       bool landing = false;
       if (t + h >= tout * (1.0 - 4.0 * kUround)) {
-        const double hnew = tout - t;
+        const double hnew = uni(tout - t);
         nd_rescale(z, q, hnew / h);
         h = hnew;
         landing = true;
@@ -616,12 +634,13 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         // xi_i = (t_n - t_{n-i}) / h and the coefficients of this attempt
         double xi[kQmax + 2], l[kQmax + 2];
         double sum = h;
+        const double rh = 1.0 / h;
         xi[0] = 0.0;
         xi[1] = 1.0;
 #pragma unroll
         for (int i = 2; i <= kQmax + 1; ++i) {
           sum += C[Ctl::kHist + i - 2];
-          xi[i] = i <= q + 1 ? sum / h : 0.0;
+          xi[i] = i <= q + 1 ? sum * rh : 0.0;
         }
         bdf_coeffs(q, xi, l, Cerr);
         wave_lds_sync();
@@ -631,17 +650,18 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
           C[Ctl::kL + i] = l[i];
         }
         C[Ctl::kTn] = landing ? tout : t + h;
-        l1 = l[1];
+        l1 = uni(l[1]);
+        Cerr = uni(Cerr);
       }
-      const double gamma = h / l1;
-      double gamma_bar = C[Ctl::kGammaBar];
+      const double gamma = uni(h / l1);
+      double gamma_bar = uni(C[Ctl::kGammaBar]);
       bool fresh = false;
       if (need_setup || nst >= nst_setup + 20 || fabs(gamma / gamma_bar - 1.0) > 0.3) {
         int info;
         {
           LT a[S];
-          newton_matrix<S, G, LT>(a, m, L, li, z[0], gamma, false);
-          info = lu_factor<S, G, LT>(a, piv, dinv, li, L);
+          newton_matrix<S, LT>(a, m.jcol_off, m.jtab, m.S, L, li, z[0], gamma);
+          info = gj_invert<S, LT>(a, li, L);
         }
         nsetups++;
         nst_setup = nst;
@@ -659,30 +679,30 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
             break;
           }
           nd_rescale(z, q, 0.25);
-          h *= 0.25;
+          h = uni(h * 0.25);
           C[Ctl::kEtaMax] = 1.0;
           continue;
         }
       }
-      const double cfac = gamma != gamma_bar ? 2.0 / (1.0 + gamma / gamma_bar) : 1.0;
+      const double cfac = uni(gamma != gamma_bar ? 2.0 / (1.0 + gamma / gamma_bar) : 1.0);
 
       // Newton iteration on G(e) = e - gamma f(z_0 + e) + z_1 / l_1, Eq. (4)
       bool conv = false;
       double dprev = 0.0;
       e = 0.0;
       for (int mit = 0; mit < 3; ++mit) {
-        f = rhs<S, G>(m, L, li, z[0] + e, Fi);
+        f = rhs(m, L, li, z[0] + e, Fi);
         nfe++;
         nni++;
         const double Gi = e - gamma * f + z[1] / l1;
-        double delta = lu_solve<S, G, LT>(L, piv, dinv, li, -Gi);
+        double delta = inv_solve<S, LT>(L, li, -Gi);
         if (cfac != 1.0) delta *= cfac;
         e += delta;
-        const double d = wrms<S, G>(delta, ewt, own, n);
+        const double d = wrms(delta, ewt, n);
         if (!isfinite(d)) break;
         if (mit >= 1) {
           const double ratio = d / dprev;
-          Rrate = 0.3 * Rrate > ratio ? 0.3 * Rrate : ratio;
+          Rrate = uni(0.3 * Rrate > ratio ? 0.3 * Rrate : ratio);
         }
         if ((Rrate < 1.0 ? Rrate : 1.0) * d <= 0.1 / Cerr) {
           conv = true;
@@ -700,7 +720,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         }
         if (fresh) {
           nd_rescale(z, q, 0.25);
-          h *= 0.25;
+          h = uni(h * 0.25);
           C[Ctl::kEtaMax] = 1.0;
         }
         need_setup = true;
@@ -708,7 +728,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
       }
 
       // local error test (Sec. 2)
-      dsm = Cerr * wrms<S, G>(e, ewt, own, n);
+      dsm = uni(Cerr * wrms(e, ewt, n));
       if (dsm <= 1.0) break;
       netf++;
       nd_unpredict(z, q);
@@ -719,9 +739,9 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
       C[Ctl::kEtaMax] = 1.0;
       if (nef_step >= 3) {
         // restart at order 1 from the last accepted y
-        const double hnew = 0.1 * h;
+        const double hnew = uni(0.1 * h);
         q = 1;
-        const double f0 = rhs<S, G>(m, L, li, z[0], Fi);
+        const double f0 = rhs(m, L, li, z[0], Fi);
         nfe++;
 #pragma unroll
         for (int j = 2; j <= kQmax; ++j) z[j] = 0.0;
@@ -734,14 +754,15 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         double eta = eta_from(6.0, dsm, q + 1);
         if (eta < 0.1) eta = 0.1;
         if (nef_step >= 2 && eta > 0.2) eta = 0.2;
+        eta = uni(eta);
         nd_rescale(z, q, eta);
-        h *= eta;
+        h = uni(h * eta);
       }
     }
     if (status != kSuccess) break;
 
     // accept: correct the Nordsieck array
-    t = C[Ctl::kTn];
+    t = uni(C[Ctl::kTn]);
 #pragma unroll
     for (int j = 0; j <= kQmax; ++j)
       if (j <= q) z[j] = fma(C[Ctl::kL + j], e, z[j]);
@@ -770,19 +791,19 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
       C[Ctl::kHprev] = hstep;
       have_eprev = true;
     }
-    const double eta_max = C[Ctl::kEtaMax];
+    const double eta_max = uni(C[Ctl::kEtaMax]);
     if (t < tout) {
       if (eta_max == 1.0) {
         if (qwait < 2) qwait = 2;  // right after a failure: hold h and q
       } else {
-        double eta = eta_from(6.0, dsm, q + 1);
+        double eta = uni(eta_from(6.0, dsm, q + 1));
         int qnew = q;
         if (qwait == 0) {
           qwait = 2;
           if (q > 1) {
-            const double lte = factorial(q - 1) / harmonic(q - 1) *
-                               wrms<S, G>(nd_get(z, q), ewt, own, n);
-            const double eta_qm1 = eta_from(6.0, lte, q);
+            const double lte =
+                factorial(q - 1) / harmonic(q - 1) * wrms(nd_get(z, q), ewt, n);
+            const double eta_qm1 = uni(eta_from(6.0, lte, q));
             if (eta_qm1 > eta) {
               eta = eta_qm1;
               qnew = q - 1;
@@ -790,8 +811,8 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
           }
           if (q < qmax && have_eprev) {
             const double r = ipow(hstep / C[Ctl::kHprev], q + 1);
-            const double lte = wrms<S, G>(e - r * eprev, ewt, own, n) / ((q + 2) * harmonic(q + 1));
-            const double eta_qp1 = eta_from(10.0, lte, q + 2);
+            const double lte = wrms(e - r * eprev, ewt, n) / ((q + 2) * harmonic(q + 1));
+            const double eta_qp1 = uni(eta_from(10.0, lte, q + 2));
             if (eta_qp1 > eta) {
               eta = eta_qp1;
               qnew = q + 1;
@@ -834,7 +855,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
             have_eprev = false;
           }
           nd_rescale(z, q, eta);
-          h *= eta;
+          h = uni(h * eta);
         }
       }
     }
@@ -860,6 +881,218 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
     }
     if (P.rec) P.rec_n[cell] = nst < P.rec_cap ? nst : P.rec_cap;
   }
+}
+
+// ---------------------------------------------------------------------------
+// discrete adjoint of the frozen step sequence
+// ---------------------------------------------------------------------------
+//
+// With the accepted step sizes h_n, orders q_n and restart flags held fixed
+// and every corrector solved exactly, the forward run is a smooth map
+// (y0, lnA) -> y(t_out):  step n predicts zp = A z (Pascal), solves
+// y_n - gamma f(y_n) = zp_0 - zp_1 / l_1, corrects z = zp + l (y_n - zp_0);
+// between steps z is rescaled by (h_n / h_{n-1})^j and the order changed
+// (interpolation-preserving maps) or, after repeated error-test failures,
+// rebuilt as [y, h f(y)].  The backward sweep applies the transposes of
+// these maps in reverse; the solve uses (I - gamma J(y_n))^T with J at the
+// recorded state.  d f / d lnA_r = nu_r q_r.
+
+// (J^T v)_i for lane i, and pbar_r += scale q_r(y) (nu_r . v) (reaction r
+// on lane r mod 64, accumulated in LDS).  vb: a 64-entry LDS buffer.
+__device__ __forceinline__ double adj_scatter(const MechDev &m, const Lds &L, double *vb,
+                                              double *pb, int li, double yi, double vi,
+                                              double scale, bool want_jtv) {
+  wave_lds_sync();
+  L.yb[li] = yi;
+  vb[li] = vi;
+  L.fb[li] = 0.0;
+  wave_lds_sync();
+  for (int r = li; r < m.R; r += kWave) {
+    const int2 w = reinterpret_cast<const int2 *>(m.rx)[r];
+    int a[3], b[3];
+    double pf = L.kk[2 * r], pr = L.kk[2 * r + 1], s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a[k] = slot_species(w.x, k);
+      b[k] = slot_species(w.y, k);
+      if (a[k] != 0xff) {
+        pf *= L.yb[a[k]];
+        s -= vb[a[k]];
+      }
+      if (b[k] != 0xff) {
+        pr *= L.yb[b[k]];
+        s += vb[b[k]];
+      }
+    }
+    pb[r] += scale * (pf + pr) * s;
+    if (want_jtv) {
+      // d q_r / d y_j for each slot: the side's constant times the other slots
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (a[k] != 0xff) {
+          double d = L.kk[2 * r];
+#pragma unroll
+          for (int o = 0; o < 3; ++o)
+            if (o != k && a[o] != 0xff) d *= L.yb[a[o]];
+          atomicAdd(&L.fb[a[k]], d * s);
+        }
+        if (b[k] != 0xff && m.reversible) {
+          double d = L.kk[2 * r + 1];
+#pragma unroll
+          for (int o = 0; o < 3; ++o)
+            if (o != k && b[o] != 0xff) d *= L.yb[b[o]];
+          atomicAdd(&L.fb[b[k]], d * s);
+        }
+      }
+    }
+  }
+  wave_lds_sync();
+  return L.fb[li];
+}
+
+// xi_i and l_j of recorded step `step` (1-based); hist from the records.
+__device__ __forceinline__ void rec_coeffs(const double *rec, int stride, int n, double hpad,
+                                           int step, int q, double (&xi)[kQmax + 2],
+                                           double (&l)[kQmax + 2], double &Cerr) {
+  const double hn = rec[(step - 1) * stride + n];
+  double sum = hn;
+  xi[0] = 0.0;
+  xi[1] = 1.0;
+#pragma unroll
+  for (int i = 2; i <= kQmax + 1; ++i) {
+    const int idx = step - i;  // 1-based step of h_{n-i+1}
+    sum += idx >= 1 ? rec[(idx - 1) * stride + n] : hpad;
+    xi[i] = i <= q + 1 ? sum / hn : 0.0;
+  }
+  bdf_coeffs(q, xi, l, Cerr);
+}
+
+template <int S>
+__device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int li, double *lds) {
+  const MechDev &m = P.mech;
+  const int R = m.R;
+  const Lds L = carve(lds, R);
+  double *vb = reinterpret_cast<double *>(L.fac) + S * S;
+  double *pb = vb + kWave;
+  const int n = P.n_sp;
+  const bool own = li < n;
+  const int stride = P.rec_stride;
+
+  const double T = P.T ? P.T[cell] : 1.0;
+  wave_lds_sync();
+  for (int r = li; r < R; r += kWave) {
+    double lk = m.lnA[r];
+    lk -= m.EaR[r] / T;
+    double kf = exp(lk);
+    if (P.kscale) kf *= P.kscale[cell * P.ldk + r];
+    L.kk[2 * r] = kf;
+    L.kk[2 * r + 1] = m.reversible ? -(kf * exp(-m.lnK[r])) : -0.0;
+    pb[r] = 0.0;
+  }
+  const double *rec = P.rec + static_cast<int64_t>(cell) * P.rec_cap * stride;
+  const int N = uni(P.rec_n[cell]);
+  const double hpad = uni(P.rec_hpad[cell]);
+  double zb[kQmax + 1];
+#pragma unroll
+  for (int j = 0; j <= kQmax; ++j) zb[j] = 0.0;
+  zb[0] = own ? P.ybar[cell * P.ldy + li] : 0.0;
+  double ebx = 0.0, y0bar = zb[0];
+
+  for (int step = N; step >= 1; --step) {
+    const int qr = uni(static_cast<int>(rec[(step - 1) * stride + n + 1]));
+    const int q = qr & 255;
+    const double hn = uni(rec[(step - 1) * stride + n]);
+    double xi[kQmax + 2], l[kQmax + 2], Cerr;
+    rec_coeffs(rec, stride, n, hpad, step, q, xi, l, Cerr);
+    const double gamma = uni(hn / l[1]);
+    const double yn = own ? rec[(step - 1) * stride + li] : 0.0;
+    // z_n = zp + l e, e = y_n - zp_0
+    double eb = ebx;
+#pragma unroll
+    for (int j = 0; j <= kQmax; ++j)
+      if (j <= q) eb = fma(l[j], zb[j], eb);
+    zb[0] -= eb;
+    // (I - gamma J(y_n))^T mu = eb
+    {
+      double a[S];
+      newton_matrix<S, double>(a, m.jtcol_off, m.jttab, m.S, L, li, yn, gamma);
+      gj_invert<S, double>(a, li, L);
+    }
+    const double mu = own ? inv_solve<S, double>(L, li, eb) : 0.0;
+    adj_scatter(m, L, vb, pb, li, yn, mu, gamma, false);
+    // a = zp_0 - zp_1 / l_1
+    zb[0] += mu;
+    zb[1] -= mu / l[1];
+    // predictor transpose (reverse order of the Pascal updates)
+#pragma unroll
+    for (int k = kQmax; k >= 1; --k)
+#pragma unroll
+      for (int j = k; j <= kQmax; ++j)
+        if (k <= q && j <= q) zb[j] += zb[j - 1];
+    ebx = 0.0;
+    if (step == 1) {
+      // z = [y0, h_1 f(y0)]
+      const double y0 = own ? P.rec_y0[cell * stride + li] : 0.0;
+      const double jtv = adj_scatter(m, L, vb, pb, li, y0, zb[1], hn, true);
+      y0bar = zb[0] + hn * jtv;
+      break;
+    }
+    const int qp = uni(static_cast<int>(rec[(step - 2) * stride + n + 1])) & 255;
+    if (qr >> 8) {
+      // z was rebuilt as [y_{n-1}, h_n f(y_{n-1})] before this step
+      const double yp = own ? rec[(step - 2) * stride + li] : 0.0;
+      const double jtv = adj_scatter(m, L, vb, pb, li, yp, zb[1], hn, true);
+      zb[0] += hn * jtv;
+#pragma unroll
+      for (int j = 1; j <= kQmax; ++j) zb[j] = 0.0;
+    } else {
+      const double eta = uni(hn / rec[(step - 2) * stride + n]);
+      double fct = 1.0;
+#pragma unroll
+      for (int j = 1; j <= kQmax; ++j) {
+        fct *= eta;
+        if (j <= q) zb[j] *= fct;
+      }
+      if (q == qp + 1 || q == qp - 1) {
+        double xip[kQmax + 2], lp[kQmax + 2], Cp;
+        rec_coeffs(rec, stride, n, hpad, step - 1, qp, xip, lp, Cp);
+        if (q == qp + 1) {
+          const double c = 1.0 / pick(xip, qp + 1);
+#pragma unroll
+          for (int j = 1; j <= kQmax; ++j)
+            if (j <= qp + 1) ebx += c * lp[j - 1] * zb[j];
+#pragma unroll
+          for (int j = 1; j <= kQmax; ++j)
+            if (j == qp + 1) zb[j] = 0.0;
+        } else {
+          double c[kQmax + 2];
+#pragma unroll
+          for (int j = 0; j <= kQmax + 1; ++j) c[j] = 0.0;
+          c[1] = 1.0;
+#pragma unroll
+          for (int i = 1; i <= kQmax - 1; ++i)
+            if (i <= qp - 1) {
+#pragma unroll
+              for (int j = i + 1; j >= 1; --j) c[j] = c[j - 1] + xip[i] * c[j];
+            }
+          double acc = 0.0;
+#pragma unroll
+          for (int j = 1; j <= kQmax; ++j)
+            if (j < qp) acc -= c[j] * zb[j];
+#pragma unroll
+          for (int j = 1; j <= kQmax; ++j)
+            if (j == qp) zb[j] = acc;
+        }
+      }
+    }
+  }
+  if (own) P.y0bar[cell * P.ldy + li] = y0bar;
+  wave_lds_sync();
+  for (int r = li; r < R; r += kWave) P.pbar[cell * P.ldp + r] = pb[r];
+}
+
+__host__ __device__ constexpr int lds_doubles_adjoint(int S, int R) {
+  return lds_doubles(S, R, 8) + kWave + R;
 }
 
 }  // namespace bdfx

@@ -1,9 +1,9 @@
 // bdfx_api.hip -- host runtime behind the C ABI of include/bdfx.h.
 //
 // Owns the context (device, stream, plan, bound buffers) and the
-// device-resident mechanism tables; builds the per-species gather lists and
-// the analytic-Jacobian term lists from the stoichiometry; launches the
-// per-size integrator kernels.  Nothing here allocates device memory after
+// device-resident mechanism tables; builds the reaction slot words and the
+// lane-major analytic-Jacobian term tables from the stoichiometry; launches
+// the per-size integrator kernels (one wavefront per cell).  Nothing here allocates device memory after
 // bdfx_bind() (the paper's memory-pool lesson, Sec. 4.2.4), so integrate and
 // perturb can be captured into a HIP graph by the caller.
 #include <hip/hip_runtime.h>
@@ -32,6 +32,8 @@ BDFX_DECLARE_SIZE(64)
 hipError_t bdfx_launch_perturb(const bdfx::Params &P, uint64_t seed, int64_t step, double amp,
                                hipStream_t s);
 hipError_t bdfx_launch_fill_u32(uint32_t *p, int n, uint32_t v, hipStream_t s);
+hipError_t bdfx_launch_sum_cells(const double *pbar, int ldp, const int32_t *list, int64_t n, int R,
+                                 double *out, hipStream_t s);
 
 static_assert(sizeof(bdfx_cell_stats) == sizeof(bdfx::CellStats), "stats layout");
 static_assert(sizeof(bdfx_cell_stats) == 48, "stats size");
@@ -41,18 +43,19 @@ namespace {
 thread_local std::string g_create_error;
 
 struct SizeEntry {
-  int S, G;
-  hipError_t (*launch)(const bdfx::Params &, bool, const bdfx::LaunchCfg &, hipStream_t);
-  hipError_t (*occupancy)(bool, int, size_t, int *);
+  int S;
+  hipError_t (*launch)(const bdfx::Params &, bool, int, const bdfx::LaunchCfg &, hipStream_t);
+  hipError_t (*occupancy)(bool, int, int, size_t, int *);
+  hipError_t (*adjoint)(const bdfx::Params &, const bdfx::LaunchCfg &, hipStream_t);
 };
 
+#define BDFX_SIZE_ENTRY(S) {S, bdfx_launch_s##S, bdfx_occupancy_s##S, bdfx_adjoint_s##S}
 const SizeEntry kSizes[] = {
-    {3, 4, bdfx_launch_s3, bdfx_occupancy_s3},     {4, 4, bdfx_launch_s4, bdfx_occupancy_s4},
-    {8, 8, bdfx_launch_s8, bdfx_occupancy_s8},     {9, 16, bdfx_launch_s9, bdfx_occupancy_s9},
-    {16, 16, bdfx_launch_s16, bdfx_occupancy_s16}, {21, 32, bdfx_launch_s21, bdfx_occupancy_s21},
-    {32, 32, bdfx_launch_s32, bdfx_occupancy_s32}, {53, 64, bdfx_launch_s53, bdfx_occupancy_s53},
-    {64, 64, bdfx_launch_s64, bdfx_occupancy_s64},
+    BDFX_SIZE_ENTRY(3),  BDFX_SIZE_ENTRY(4),  BDFX_SIZE_ENTRY(8),
+    BDFX_SIZE_ENTRY(9),  BDFX_SIZE_ENTRY(16), BDFX_SIZE_ENTRY(21),
+    BDFX_SIZE_ENTRY(32), BDFX_SIZE_ENTRY(53), BDFX_SIZE_ENTRY(64),
 };
+#undef BDFX_SIZE_ENTRY
 
 // Smallest compiled size that holds S species (exact sizes 3, 9, 21, 53 are
 // compiled for the benchmark mechanisms; others are padded with inert
@@ -201,15 +204,6 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
     rx[2 * r] = static_cast<int32_t>(wr);
     rx[2 * r + 1] = static_cast<int32_t>(wp);
   }
-  // f_i gather list: one entry per slot occurrence, in reaction-then-slot
-  // order (reactant before product within a slot), coefficient -1 / +1
-  std::vector<std::vector<int32_t>> sp(S);
-  for (int r = 0; r < R; ++r)
-    for (int l = 0; l < 3; ++l) {
-      const int a = d->reac[r * 3 + l], b = d->prod[r * 3 + l];
-      if (a >= 0) sp[a].push_back((r << 8) | 0xff);  // nu = -1
-      if (b >= 0) sp[b].push_back((r << 8) | 0x01);  // nu = +1
-    }
   // Jacobian terms: d q_r / d y_j for slot l of side sd is
   // k_side * prod(other slots); distributed to every reactant row (-1) and
   // product row (+1).  Enumerated in reaction / side / slot / row order.
@@ -234,35 +228,41 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
         }
       }
   }
-  auto pack = [](const Term &t, int key) {
-    int2 e;
-    e.x = t.kidx;
-    e.y = (key & 0xff) | ((t.o1 & 0xff) << 8) | ((t.o2 & 0xff) << 16) |
-          ((t.coef & 0xff) << 24);
-    return e;
+  // Lane-major slot tables: for the static loop index c (a column of M for
+  // the row-per-lane layout, a row of M for the transposed layout) the slots
+  // off[c] .. off[c+1]-1 hold, for each lane, the terms of its entry in
+  // enumeration order, padded with empty slots (x = -1).
+  auto slot_table = [&](bool transposed, std::vector<int32_t> &off, std::vector<int2> &tab) {
+    std::vector<std::vector<std::vector<const Term *>>> ent(
+        S, std::vector<std::vector<const Term *>>(bdfx::kWave));
+    for (const auto &t : terms) {
+      const int c = transposed ? t.row : t.col, lane = transposed ? t.col : t.row;
+      ent[c][lane].push_back(&t);
+    }
+    // offsets padded to the largest compiled size (extra columns are empty),
+    // so that a kernel padded beyond S can never index past the array
+    off.assign(bdfx::kMaxS + 1, 0);
+    for (int c = 0; c < S; ++c) {
+      size_t depth = 0;
+      for (const auto &v : ent[c]) depth = std::max(depth, v.size());
+      off[c + 1] = off[c] + static_cast<int32_t>(depth);
+    }
+    for (int c = S; c < bdfx::kMaxS; ++c) off[c + 1] = off[S];
+    tab.assign(static_cast<size_t>(off[S]) * bdfx::kWave, make_int2(-1, 0));
+    for (int c = 0; c < S; ++c)
+      for (int lane = 0; lane < bdfx::kWave; ++lane)
+        for (size_t k = 0; k < ent[c][lane].size(); ++k) {
+          const Term &t = *ent[c][lane][k];
+          int2 e;
+          e.x = t.kidx;
+          e.y = (t.o1 & 0xff) | ((t.o2 & 0xff) << 8) | ((t.coef & 0xff) << 16);
+          tab[(off[c] + k) * bdfx::kWave + lane] = e;
+        }
   };
-  // by row, columns ascending (stable: per-entry order = enumeration order)
-  std::vector<Term> by_row = terms;
-  std::stable_sort(by_row.begin(), by_row.end(), [](const Term &x, const Term &y) {
-    return x.row != y.row ? x.row < y.row : x.col < y.col;
-  });
-  std::vector<Term> by_col = terms;
-  std::stable_sort(by_col.begin(), by_col.end(), [](const Term &x, const Term &y) {
-    return x.col != y.col ? x.col < y.col : x.row < y.row;
-  });
-  std::vector<int32_t> jr_off(S + 1, 0), jc_off(S + 1, 0), sp_off(S + 1, 0);
-  std::vector<int2> jr_ent, jc_ent;
-  std::vector<int32_t> sp_ent;
-  for (const auto &t : by_row) jr_off[t.row + 1]++;
-  for (const auto &t : by_col) jc_off[t.col + 1]++;
-  for (int i = 0; i < S; ++i) {
-    jr_off[i + 1] += jr_off[i];
-    jc_off[i + 1] += jc_off[i];
-    sp_off[i + 1] = sp_off[i] + static_cast<int>(sp[i].size());
-    for (auto v : sp[i]) sp_ent.push_back(v);
-  }
-  for (const auto &t : by_row) jr_ent.push_back(pack(t, t.col));
-  for (const auto &t : by_col) jc_ent.push_back(pack(t, t.row));
+  std::vector<int32_t> jr_off, jc_off;
+  std::vector<int2> jr_tab, jc_tab;
+  slot_table(false, jr_off, jr_tab);
+  slot_table(true, jc_off, jc_tab);
 
   std::vector<double> lnA(d->lnA, d->lnA + R), EaR(R, 0.0), lnK(R, 0.0), w(S, 1.0);
   if (d->EaR) EaR.assign(d->EaR, d->EaR + R);
@@ -276,10 +276,9 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
     return o;
   };
   const size_t o_rx = reserve(rx.size() * 4), o_lnA = reserve(R * 8), o_EaR = reserve(R * 8),
-               o_lnK = reserve(R * 8), o_spo = reserve((S + 1) * 4),
-               o_spe = reserve(sp_ent.size() * 4), o_jro = reserve((S + 1) * 4),
-               o_jre = reserve(jr_ent.size() * 8), o_jco = reserve((S + 1) * 4),
-               o_jce = reserve(jc_ent.size() * 8), o_w = reserve(S * 8);
+               o_lnK = reserve(R * 8), o_jro = reserve(jr_off.size() * 4),
+               o_jre = reserve(jr_tab.size() * 8), o_jco = reserve(jc_off.size() * 4),
+               o_jce = reserve(jc_tab.size() * 8), o_w = reserve(S * 8);
   HIPCHK(ctx, hipSetDevice(ctx->device));
   void *dmem = nullptr;
   HIPCHK(ctx, hipMalloc(&dmem, off));
@@ -292,12 +291,10 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
   if (e == hipSuccess) e = up(o_lnA, lnA.data(), R * 8);
   if (e == hipSuccess) e = up(o_EaR, EaR.data(), R * 8);
   if (e == hipSuccess) e = up(o_lnK, lnK.data(), R * 8);
-  if (e == hipSuccess) e = up(o_spo, sp_off.data(), (S + 1) * 4);
-  if (e == hipSuccess) e = up(o_spe, sp_ent.data(), sp_ent.size() * 4);
-  if (e == hipSuccess) e = up(o_jro, jr_off.data(), (S + 1) * 4);
-  if (e == hipSuccess) e = up(o_jre, jr_ent.data(), jr_ent.size() * 8);
-  if (e == hipSuccess) e = up(o_jco, jc_off.data(), (S + 1) * 4);
-  if (e == hipSuccess) e = up(o_jce, jc_ent.data(), jc_ent.size() * 8);
+  if (e == hipSuccess) e = up(o_jro, jr_off.data(), jr_off.size() * 4);
+  if (e == hipSuccess) e = up(o_jre, jr_tab.data(), jr_tab.size() * 8);
+  if (e == hipSuccess) e = up(o_jco, jc_off.data(), jc_off.size() * 4);
+  if (e == hipSuccess) e = up(o_jce, jc_tab.data(), jc_tab.size() * 8);
   if (e == hipSuccess) e = up(o_w, w.data(), S * 8);
   if (e != hipSuccess) {
     hipFree(dmem);
@@ -310,7 +307,7 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
   m->reversible = reversible;
   m->dmem = dmem;
   m->w = w;
-  m->jr_terms = jr_ent.size();
+  m->jr_terms = terms.size();
   bdfx::MechDev &dv = m->dev;
   dv.S = S;
   dv.R = R;
@@ -319,12 +316,10 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
   dv.lnA = reinterpret_cast<const double *>(base + o_lnA);
   dv.EaR = reinterpret_cast<const double *>(base + o_EaR);
   dv.lnK = reinterpret_cast<const double *>(base + o_lnK);
-  dv.sp_off = reinterpret_cast<const int32_t *>(base + o_spo);
-  dv.sp_ent = reinterpret_cast<const int32_t *>(base + o_spe);
-  dv.jr_off = reinterpret_cast<const int32_t *>(base + o_jro);
-  dv.jr_ent = reinterpret_cast<const int2 *>(base + o_jre);
-  dv.jc_off = reinterpret_cast<const int32_t *>(base + o_jco);
-  dv.jc_ent = reinterpret_cast<const int2 *>(base + o_jce);
+  dv.jcol_off = reinterpret_cast<const int32_t *>(base + o_jro);
+  dv.jtab = reinterpret_cast<const int2 *>(base + o_jre);
+  dv.jtcol_off = reinterpret_cast<const int32_t *>(base + o_jco);
+  dv.jttab = reinterpret_cast<const int2 *>(base + o_jce);
   dv.w = reinterpret_cast<const double *>(base + o_w);
   *out = m;
   return BDFX_OK;
@@ -537,11 +532,10 @@ int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out) {
     bdfx::Params P = make_params(ctx, b, t0, t_out);
     P.use_queue = queue ? 1 : 0;
     const int waves = ctx->opt.waves_per_block > 0 ? ctx->opt.waves_per_block : 1;
-    const int block = 64 * waves;
-    const int gpb = block / se->G;
-    const int ctl = 24;
-    const int fac_doubles = fp32 ? (se->S * se->S + 1) / 2 : se->S * se->S;
-    P.lds_doubles = static_cast<int32_t>(align_up(3 * m->R + 2 * se->S + ctl + fac_doubles, 2));
+    const int block = bdfx::kWave * waves;
+    const int gpb = waves;  // one wave per cell
+    P.lds_doubles = static_cast<int32_t>(
+        align_up(bdfx::lds_doubles(se->S, m->R, fp32 ? 4 : 8), 2));
     bdfx::LaunchCfg cfg;
     cfg.block = block;
     cfg.lds_bytes = static_cast<size_t>(gpb) * P.lds_doubles * 8;
@@ -549,7 +543,7 @@ int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out) {
       return fail(ctx, BDFX_EUNSUPPORTED, "LDS per block %zu exceeds 64 KiB", cfg.lds_bytes);
     if (queue) {
       int occ = 0;
-      HIPCHK(ctx, se->occupancy(fp32, block, cfg.lds_bytes, &occ));
+      HIPCHK(ctx, se->occupancy(fp32, ctx->opt.waves_per_simd, block, cfg.lds_bytes, &occ));
       const int per_cu = ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : std::max(occ, 1);
       const int64_t need = (b.count + gpb - 1) / gpb;
       cfg.grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(per_cu) * ctx->n_cu, need));
@@ -557,7 +551,7 @@ int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out) {
       cfg.grid = static_cast<int>((b.count + gpb - 1) / gpb);
     }
     if (cfg.grid < 1) continue;
-    HIPCHK(ctx, se->launch(P, fp32, cfg, ctx->stream));
+    HIPCHK(ctx, se->launch(P, fp32, ctx->opt.waves_per_simd, cfg, ctx->stream));
   }
   ctx->last_t0 = t0;
   ctx->last_tout = t_out;
@@ -607,9 +601,40 @@ int bdfx_stats_summary(bdfx_ctx ctx, bdfx_summary *out) {
   return BDFX_OK;
 }
 
-int bdfx_adjoint(bdfx_ctx ctx, const double *, double *, double *) {
+int bdfx_adjoint(bdfx_ctx ctx, const double *d_ybar, double *d_y0bar, double *d_lnA_bar) {
   if (!ctx) return BDFX_EINVAL;
-  return fail(ctx, BDFX_EUNSUPPORTED, "adjoint not built yet");
+  if (!ctx->bound) return fail(ctx, BDFX_EORDER, "bdfx_bind must precede bdfx_adjoint");
+  if (ctx->opt.record_steps <= 0)
+    return fail(ctx, BDFX_EORDER, "the forward run must be planned with record_steps > 0");
+  if (!ctx->integrated)
+    return fail(ctx, BDFX_EORDER, "bdfx_integrate must precede bdfx_adjoint (no perturb since)");
+  if (!d_ybar || !d_y0bar) return fail(ctx, BDFX_EINVAL, "ybar and y0bar required");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  double *pbar = reinterpret_cast<double *>(ctx->ws + ctx->off_pbar);
+  for (const Bin &b : ctx->bins) {
+    if (b.count == 0) continue;
+    const bdfx_mech m = ctx->mechs[b.mech];
+    const SizeEntry *se = size_for(m->S);
+    bdfx::Params P = make_params(ctx, b, ctx->last_t0, ctx->last_tout);
+    P.ybar = d_ybar;
+    P.y0bar = d_y0bar;
+    P.pbar = pbar;
+    P.ldp = ctx->R_max;
+    const int waves = 1;
+    P.lds_doubles = static_cast<int32_t>(align_up(bdfx::lds_doubles_adjoint(se->S, m->R), 2));
+    bdfx::LaunchCfg cfg;
+    cfg.block = bdfx::kWave * waves;
+    cfg.lds_bytes = static_cast<size_t>(waves) * P.lds_doubles * 8;
+    if (cfg.lds_bytes > 65536)
+      return fail(ctx, BDFX_EUNSUPPORTED, "adjoint LDS per block %zu exceeds 64 KiB", cfg.lds_bytes);
+    cfg.grid = static_cast<int>((b.count + waves - 1) / waves);
+    HIPCHK(ctx, se->adjoint(P, cfg, ctx->stream));
+    if (d_lnA_bar)
+      HIPCHK(ctx, bdfx_launch_sum_cells(pbar, ctx->R_max, P.list, b.count, m->R,
+                                        d_lnA_bar + static_cast<int64_t>(b.mech) * ctx->R_max,
+                                        ctx->stream));
+  }
+  return BDFX_OK;
 }
 
 }  // extern "C"

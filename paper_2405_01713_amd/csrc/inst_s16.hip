@@ -1,4 +1,4 @@
-// Integrator kernels for mechanisms padded to S = 16 species (groups of 16 lanes).
+// Integrator kernels for mechanisms padded to S = 16 species.
 #include "bdf_kernels.h"
 
-BDFX_DEFINE_SIZE(16, 16)
+BDFX_DEFINE_SIZE(16)

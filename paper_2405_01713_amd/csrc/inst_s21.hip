@@ -1,4 +1,4 @@
-// Integrator kernels for mechanisms padded to S = 21 species (groups of 32 lanes).
+// Integrator kernels for mechanisms padded to S = 21 species.
 #include "bdf_kernels.h"
 
-BDFX_DEFINE_SIZE(21, 32)
+BDFX_DEFINE_SIZE(21)

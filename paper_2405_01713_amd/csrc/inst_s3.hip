@@ -1,4 +1,4 @@
-// Integrator kernels for mechanisms padded to S = 3 species (groups of 4 lanes).
+// Integrator kernels for mechanisms padded to S = 3 species.
 #include "bdf_kernels.h"
 
-BDFX_DEFINE_SIZE(3, 4)
+BDFX_DEFINE_SIZE(3)

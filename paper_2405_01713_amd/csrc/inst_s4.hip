@@ -1,4 +1,4 @@
-// Integrator kernels for mechanisms padded to S = 4 species (groups of 4 lanes).
+// Integrator kernels for mechanisms padded to S = 4 species.
 #include "bdf_kernels.h"
 
-BDFX_DEFINE_SIZE(4, 4)
+BDFX_DEFINE_SIZE(4)

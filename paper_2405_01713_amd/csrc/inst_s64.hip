@@ -1,4 +1,4 @@
-// Integrator kernels for mechanisms padded to S = 64 species (groups of 64 lanes).
+// Integrator kernels for mechanisms padded to S = 64 species.
 #include "bdf_kernels.h"
 
-BDFX_DEFINE_SIZE(64, 64)
+BDFX_DEFINE_SIZE(64)

@@ -1,4 +1,4 @@
-// Integrator kernels for mechanisms padded to S = 8 species (groups of 8 lanes).
+// Integrator kernels for mechanisms padded to S = 8 species.
 #include "bdf_kernels.h"
 
-BDFX_DEFINE_SIZE(8, 8)
+BDFX_DEFINE_SIZE(8)

@@ -1,4 +1,4 @@
-// Integrator kernels for mechanisms padded to S = 9 species (groups of 16 lanes).
+// Integrator kernels for mechanisms padded to S = 9 species.
 #include "bdf_kernels.h"
 
-BDFX_DEFINE_SIZE(9, 16)
+BDFX_DEFINE_SIZE(9)
