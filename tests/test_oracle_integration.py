@@ -419,3 +419,30 @@ def test_parity_criterion_is_met_by_the_oracle_itself(oracle):
     y2, _ = oracle.integrate(m, y0p, 0.0, 1e-5, 1e-6, 1e-10, T=c["T"])
     stats = assert_parity(y2, y1, w, oracle, "oracle self")
     assert stats["cells_beyond_10rtol"] > 0  # the bar alone is not met entry-wise
+
+
+def test_adjoint_parity_criterion_is_met_by_the_oracle_itself(oracle):
+    """The GPU adjoint criterion (conftest.assert_adjoint_parity) holds between
+    the oracle's adjoint and itself on inputs perturbed by 1e-15 relative, each
+    differentiated along its own adaptive record; equal step counts do not
+    imply equal step sequences."""
+    from tests.conftest import assert_adjoint_parity
+    w = W.make_workload("s21_r84_65k_adjoint", 48)
+    m = w["mechs"][0]
+    c = W.loss_weights(21)
+    rng = np.random.default_rng(3)
+    g1, g2, same_n_other_seq = [], [], 0
+    for k in range(48):
+        kf, kr = oracle.rates(m, w["T"][k])
+        y0 = w["y0"][k]
+        y0p = y0 * (1 + 1e-15 * rng.uniform(-1, 1, y0.shape))
+        _, s1, r1 = oracle.integrate_record(m, y0, 0.0, w["t_out"], w["rtol"], w["atol"], T=w["T"][k])
+        _, s2, r2 = oracle.integrate_record(m, y0p, 0.0, w["t_out"], w["rtol"], w["atol"],
+                                            T=w["T"][k])
+        g1.append(oracle.adjoint(m, kf, kr, y0, r1, r1["y"], c)[0])
+        g2.append(oracle.adjoint(m, kf, kr, y0p, r2, r2["y"], c)[0])
+        if s1["nst"] == s2["nst"] and not np.allclose(r1["h"], r2["h"], rtol=1e-9):
+            same_n_other_seq += 1
+    rel = assert_adjoint_parity(np.array(g2), np.array(g1), "oracle self")
+    assert rel.max() > 1e-6       # a tighter per-cell bar would fail the oracle itself
+    assert same_n_other_seq >= 1  # equal nst, different sequence
