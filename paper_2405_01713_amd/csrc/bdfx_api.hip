@@ -16,7 +16,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/bdfx.h"
+#include "bdfx.h"
 #include "bdf_kernels.h"
 
 BDFX_DECLARE_SIZE(3)
