@@ -271,6 +271,36 @@ class Integrator:
         self._keep = yb
         return y0bar, lnA_bar
 
+    def outer_loop(self, n_outer, dt, seed, amplitude, t0=0.0):
+        """Operator-splitting outer loop on the current stream: for k = 0 ..
+        n_outer-1, perturb the states (outer step k of the counter-based
+        perturbation, skipped when amplitude == 0), then integrate over
+        [t0 + k dt, t0 + (k + 1) dt]."""
+        for k in range(n_outer):
+            if amplitude != 0.0:
+                self.perturb(seed, k, amplitude)
+            self.integrate(t0 + k * dt, t0 + (k + 1) * dt)
+
+    def capture_outer_loop(self, n_outer, dt, seed, amplitude, t0=0.0):
+        """Capture outer_loop() in a HIP graph (torch.cuda.CUDAGraph).
+
+        The graph holds only the library's kernels (perturbation, queue reset
+        by a fill kernel, integrator launches) with the bound buffers; replay
+        it with ``g.replay()`` on any stream.  The context's stream is switched
+        to a side stream for the capture and restored afterwards."""
+        torch = self.torch
+        side = torch.cuda.Stream(device=self.dev)
+        side.wait_stream(self.stream)
+        g = torch.cuda.CUDAGraph()
+        bdfx_set_stream(self.ctx, side.cuda_stream)
+        try:
+            with torch.cuda.graph(g, stream=side):
+                self.outer_loop(n_outer, dt, seed, amplitude, t0)
+        finally:
+            bdfx_set_stream(self.ctx, self.stream.cuda_stream)
+        self.stream.wait_stream(side)
+        return g
+
     def cell_stats(self) -> np.ndarray:
         return self.stats.cpu().numpy().view(STATS_DTYPE)
 

@@ -81,6 +81,11 @@ struct bdfx_mech_s {
 struct Bin {
   int mech;
   int64_t offset, count;
+  // launch of the integrator for this bin, fixed at bind time so that
+  // bdfx_integrate() only enqueues kernels (it may be captured in a graph)
+  const SizeEntry *se = nullptr;
+  int32_t lds_doubles = 0;
+  bdfx::LaunchCfg cfg{};
 };
 
 struct bdfx_ctx_s {
@@ -416,6 +421,8 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
   return BDFX_OK;
 }
 
+static int configure_bins(bdfx_ctx ctx);
+
 int bdfx_bind(bdfx_ctx ctx, void *d_ws, size_t ws_bytes, double *d_y, int32_t ldy,
               const int32_t *d_cell_mech, const double *d_T, const double *d_kscale, int32_t ldk,
               const double *d_forcing, int32_t *d_status, bdfx_cell_stats *d_stats) {
@@ -468,6 +475,7 @@ int bdfx_bind(bdfx_ctx ctx, void *d_ws, size_t ws_bytes, double *d_y, int32_t ld
                      [&](int a, int b) { return ctx->mechs[a]->S > ctx->mechs[b]->S; });
     for (int m : order) ctx->bins.push_back({m, cnt[m], cnt[m + 1] - cnt[m]});
   }
+  if (const int rc = configure_bins(ctx)) return rc;
   ctx->bound = true;
   ctx->integrated = false;
   return BDFX_OK;
@@ -476,6 +484,34 @@ int bdfx_bind(bdfx_ctx ctx, void *d_ws, size_t ws_bytes, double *d_y, int32_t ld
 // ---------------------------------------------------------------------------
 // integrate
 // ---------------------------------------------------------------------------
+
+// Kernel, LDS size and grid of every bin (called by bdfx_bind).
+static int configure_bins(bdfx_ctx ctx) {
+  const bool fp32 = ctx->opt.lu_precision == 32;
+  const bool queue = ctx->opt.scheduler == BDFX_SCHED_QUEUE;
+  for (Bin &b : ctx->bins) {
+    const bdfx_mech m = ctx->mechs[b.mech];
+    b.se = size_for(m->S);
+    if (!b.se) return fail(ctx, BDFX_EUNSUPPORTED, "no kernel for %d species", m->S);
+    const int waves = ctx->opt.waves_per_block > 0 ? ctx->opt.waves_per_block : 1;
+    b.lds_doubles = static_cast<int32_t>(align_up(bdfx::lds_doubles(b.se->S, m->R, fp32 ? 4 : 8), 2));
+    b.cfg.block = bdfx::kWave * waves;
+    b.cfg.lds_bytes = static_cast<size_t>(waves) * b.lds_doubles * 8;  // one wave per cell
+    if (b.cfg.lds_bytes > 65536)
+      return fail(ctx, BDFX_EUNSUPPORTED, "LDS per block %zu exceeds 64 KiB", b.cfg.lds_bytes);
+    const int64_t need = (b.count + waves - 1) / waves;
+    if (queue) {
+      int occ = 0;
+      HIPCHK(ctx, b.se->occupancy(fp32, ctx->opt.waves_per_simd, b.cfg.block, b.cfg.lds_bytes, &occ));
+      const int per_cu = ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : std::max(occ, 1);
+      b.cfg.grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(per_cu) * ctx->n_cu, need));
+    } else {
+      if (need > INT32_MAX) return fail(ctx, BDFX_EUNSUPPORTED, "too many cells for one grid");
+      b.cfg.grid = static_cast<int>(need);
+    }
+  }
+  return BDFX_OK;
+}
 
 static bdfx::Params make_params(bdfx_ctx ctx, const Bin &b, double t0, double tout) {
   const bdfx_mech m = ctx->mechs[b.mech];
@@ -525,33 +561,11 @@ int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out) {
   if (queue) HIPCHK(ctx, bdfx_launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->ws + ctx->off_queue),
                                               64, 0u, ctx->stream));
   for (const Bin &b : ctx->bins) {
-    if (b.count == 0) continue;
-    const bdfx_mech m = ctx->mechs[b.mech];
-    const SizeEntry *se = size_for(m->S);
-    if (!se) return fail(ctx, BDFX_EUNSUPPORTED, "no kernel for %d species", m->S);
+    if (b.count == 0 || b.cfg.grid < 1) continue;
     bdfx::Params P = make_params(ctx, b, t0, t_out);
     P.use_queue = queue ? 1 : 0;
-    const int waves = ctx->opt.waves_per_block > 0 ? ctx->opt.waves_per_block : 1;
-    const int block = bdfx::kWave * waves;
-    const int gpb = waves;  // one wave per cell
-    P.lds_doubles = static_cast<int32_t>(
-        align_up(bdfx::lds_doubles(se->S, m->R, fp32 ? 4 : 8), 2));
-    bdfx::LaunchCfg cfg;
-    cfg.block = block;
-    cfg.lds_bytes = static_cast<size_t>(gpb) * P.lds_doubles * 8;
-    if (cfg.lds_bytes > 65536)
-      return fail(ctx, BDFX_EUNSUPPORTED, "LDS per block %zu exceeds 64 KiB", cfg.lds_bytes);
-    if (queue) {
-      int occ = 0;
-      HIPCHK(ctx, se->occupancy(fp32, ctx->opt.waves_per_simd, block, cfg.lds_bytes, &occ));
-      const int per_cu = ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : std::max(occ, 1);
-      const int64_t need = (b.count + gpb - 1) / gpb;
-      cfg.grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(per_cu) * ctx->n_cu, need));
-    } else {
-      cfg.grid = static_cast<int>((b.count + gpb - 1) / gpb);
-    }
-    if (cfg.grid < 1) continue;
-    HIPCHK(ctx, se->launch(P, fp32, ctx->opt.waves_per_simd, cfg, ctx->stream));
+    P.lds_doubles = b.lds_doubles;
+    HIPCHK(ctx, b.se->launch(P, fp32, ctx->opt.waves_per_simd, b.cfg, ctx->stream));
   }
   ctx->last_t0 = t0;
   ctx->last_tout = t_out;

@@ -153,6 +153,57 @@ def test_perturbation_bitwise(oracle):
     assert np.array_equal(yg, yo)
 
 
+def _oracle_outer_loop(oracle, w, n_outer, seed, rtol, atol, max_steps=5000):
+    """The splitting loop composed from the oracle's perturbation and
+    integrator: perturb (outer step k), then integrate over [k dt, (k+1) dt]."""
+    ms, cm = w["mechs"], w["cell_mech"]
+    y, dt = w["y0"].copy(), w["t_out"]
+    for k in range(n_outer):
+        y = oracle.perturb(y, [ms[m]["n_species"] for m in cm], [ms[m]["w"] for m in cm], seed, k,
+                           w["perturb"])
+        y, st = oracle.integrate(ms, y, k * dt, (k + 1) * dt, rtol, atol, T=w["T"], cell_mech=cm,
+                                 max_steps=max_steps)
+        assert np.all(st["status"] == 0)
+    return y
+
+
+def test_outer_loop_graph(oracle, parity):
+    """Outer splitting loop (perturb 1 %, integrate) of the mixed batch:
+    eager launches vs the oracle, and HIP-graph replays vs the eager run bit
+    for bit, with eager work and synchronisation between the replays."""
+    import torch
+    from paper_2405_01713_amd import bdfx
+    w = W.make_workload("mixed_s9_s53_1m", 200)
+    n_outer, seed = 3, 3
+    integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"],
+                            cell_mech=w["cell_mech"], scheduler=1, waves_per_simd=3)
+    y0 = integ.y.clone()
+    integ.outer_loop(n_outer, w["t_out"], seed, w["perturb"])
+    torch.cuda.synchronize()
+    y_eager, st_eager = integ.state(), integ.cell_stats()
+    g = integ.capture_outer_loop(n_outer, w["t_out"], seed, w["perturb"])
+    for rep in range(3):
+        integ.y.copy_(y0)
+        integ.status.fill_(7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(integ.state(), y_eager), f"replay {rep}"
+        assert np.array_equal(integ.cell_stats(), st_eager), f"replay {rep}"
+    integ.close()
+    assert np.all(st_eager["status"] == 0)
+    yo = _oracle_outer_loop(oracle, w, n_outer, seed, w["rtol"], w["atol"])
+    tight = {}
+
+    def reference(cells):
+        if "y" not in tight:
+            tight["y"] = _oracle_outer_loop(oracle, w, n_outer, seed, 1e-12, 1e-20, 200000)
+        return tight["y"][cells]
+
+    from tests.conftest import assert_parity
+    assert_parity(y_eager, yo, w, oracle, "outer loop", reference=reference)
+
+
 def test_adjoint_matches_oracle(oracle):
     """GPU discrete adjoint vs the oracle's adjoint along its own adaptive
     record (both use the recorded states), loss = sum_cells sum_i c_i y_i."""
