@@ -102,6 +102,81 @@ def run_form(w, form, steps, warmup, opts_extra=None):
                 kernel_ms_min=float(np.min(kern_ms)), y=y, stats=st)
 
 
+def run_adjoint(steps, warmup, n_cells=None, record_steps=2048, n_check=32):
+    """Adjoint/forward cost on the 65,536-cell 21-species workload: plain
+    forward (no recording), forward with step recording, discrete-adjoint
+    backward of the loss sum_cells sum_i c_i y_i; a sample of cells is checked
+    against the oracle's adjoint along its own step record."""
+    import torch
+    from paper_2405_01713_amd import bdfx
+
+    w = W.make_workload("s21_r84_65k_adjoint", n_cells)
+    m, N = w["mechs"][0], w["n_cells"]
+    c = W.loss_weights(m["n_species"])
+    ybar = torch.as_tensor(np.tile(c, (N, 1)), device="cuda")
+
+    def timed(fn, stream):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        for k in range(steps):
+            ev[k][0].record(stream)
+            fn()
+            ev[k][1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+    common = dict(scheduler=1, waves_per_simd=3)
+    plain = bdfx.Integrator([m], w["y0"], w["rtol"], w["atol"], T=w["T"], **common)
+    y0 = plain.y.clone()
+
+    def fwd_plain():
+        plain.y.copy_(y0)
+        plain.integrate(0.0, w["t_out"])
+
+    t_fwd = timed(fwd_plain, plain.stream)
+    plain.close()
+    rec = bdfx.Integrator([m], w["y0"], w["rtol"], w["atol"], T=w["T"],
+                          record_steps=record_steps, **common)
+
+    def fwd_rec():
+        rec.y.copy_(y0)
+        rec.integrate(0.0, w["t_out"])
+
+    t_rec = timed(fwd_rec, rec.stream)
+    out = {}
+
+    def bwd():
+        out["g"] = rec.adjoint(ybar)
+
+    t_bwd = timed(bwd, rec.stream)
+    st = rec.cell_stats()
+    y0bar = out["g"][0][:n_check].cpu().numpy()
+    rec.close()
+    res = dict(workload="s21_r84_65k_adjoint", n_cells=N, fwd_ms=t_fwd, fwd_record_ms=t_rec,
+               bwd_ms=t_bwd, ratio_bwd_over_fwd=t_bwd / t_fwd,
+               ratio_fwd_record_plus_bwd_over_fwd=(t_rec + t_bwd) / t_fwd,
+               failed_cells=int(np.sum(st["status"] != 0)), max_nst=int(st["nst"].max()))
+    try:
+        from oracle import oracle as O
+        go = np.zeros((n_check, m["n_species"]))
+        for k in range(n_check):
+            kf, kr = O.rates(m, w["T"][k])
+            _, _, r = O.integrate_record(m, w["y0"][k], 0.0, w["t_out"], w["rtol"], w["atol"],
+                                         T=w["T"][k])
+            go[k] = O.adjoint(m, kf, kr, w["y0"][k], r, r["y"], c)[0]
+        rel = np.abs(y0bar[:, :m["n_species"]] - go).max(axis=1) / np.abs(go).max()
+        res["check_cells"] = n_check
+        res["check_worst_rel"] = float(rel.max())
+        res["check_median_rel"] = float(np.median(rel))
+        res["check_ok"] = bool(rel.max() <= 1e-4 and np.median(rel) <= 1e-6)
+    except Exception as e:  # the oracle is optional on the timing path
+        res["check_error"] = repr(e)
+    return res
+
+
 def cpu_baseline(w, n_sample):
     from oracle import oracle as O
     idx = np.arange(min(n_sample, w["n_cells"]))
@@ -124,6 +199,7 @@ def main():
     ap.add_argument("--forms", default="plain,batched,batched_fp32lu")
     ap.add_argument("--cpu-sample", type=int, default=262144)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not supported "
@@ -167,6 +243,7 @@ def main():
     for f in forms.values():
         f.pop("_y")
 
+    adj = None if args.no_adjoint else run_adjoint(args.steps, args.warmup)
     ok = {k: v for k, v in forms.items() if v.get("parity_ok", True) and v["failed_cells"] == 0}
     best = max(ok or forms, key=lambda k: forms[k]["cells_per_s"])
     b = forms[best]
@@ -193,6 +270,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "forms": forms,
+        "adjoint": adj,
     }
     print(json.dumps(out))
 

@@ -440,17 +440,21 @@ __device__ __forceinline__ uint64_t abs_key(float v) {
 // Gauss-Jordan elimination with partial pivoting: the pivot of column k is
 // the largest |a_ik| among rows not yet used, lowest row on ties (the same
 // pivot sequence as an LU factorisation with partial pivoting).  Every step
-// scales the pivot row and eliminates column k from all other rows; column k
-// of the working array then stores column p_k of the accumulated inverse.
-// M^{-1} is written to LDS in natural order, column-major
-// (entry (r, c) at c*S + r), so that a solve is one lane-parallel
-// matrix-vector product.  Returns 0, or k+1 for the first column k without
-// a nonzero pivot (the elimination then runs on garbage).
+// eliminates column k from all other rows, row_i -= (a_ik / p_k) row_p, and
+// column k of the working array then stores column p_k of the accumulated
+// inverse.  Pivot rows are left unscaled during the elimination (all later
+// updates are linear in them) and each lane divides its row by its own pivot
+// at the end: one FMA per entry and step, and no cancellation on large pivots.
+// M^{-1} is written to LDS in natural order, column-major (entry (r, c) at
+// c*S + r), so that a solve is one lane-parallel matrix-vector product.
+// Returns 0, or k+1 for the first column k without a nonzero pivot (the
+// elimination then runs on garbage).
 template <int S, typename LT>
 __device__ __forceinline__ int gj_invert(LT (&a)[S], int li, const Lds &L) {
   int piv = li < S ? -1 : 1 << 20;
   int info = 0;
   int *perm = L.perm;
+  LT dinv = static_cast<LT>(1);  // 1 / own pivot
 #pragma unroll
   for (int k = 0; k < S; ++k) {
     const uint64_t key = piv < 0 ? abs_key(a[k]) : 0ull;
@@ -458,23 +462,25 @@ __device__ __forceinline__ int gj_invert(LT (&a)[S], int li, const Lds &L) {
     const int p = wfirst(key == kmax);
     if (kmax <= 1ull && info == 0) info = k + 1;
     const bool is_p = li == p;
-    if (is_p) piv = k;
     const LT pk = lane_bcast(a[k], p);
     const LT rp = static_cast<LT>(1) / pk;
-    // row_i -= f (row_p / pk); on the pivot row f = pk - 1 turns that into row_p / pk
-    const LT f = is_p ? pk - static_cast<LT>(1) : a[k];
+    const LT g = is_p ? static_cast<LT>(0) : a[k] * rp;
+    if (is_p) {
+      piv = k;
+      dinv = rp;
+    }
 #pragma unroll
     for (int j = 0; j < S; ++j)
-      if (j != k) a[j] = fma(-f, lane_bcast(a[j], p) * rp, a[j]);
-    a[k] = is_p ? rp : -f * rp;
+      if (j != k) a[j] = fma(-g, lane_bcast(a[j], p), a[j]);
+    a[k] = is_p ? static_cast<LT>(1) : -g;
     if (li == 0) perm[k] = p;
   }
-  // lane i holds row piv(i) of M^{-1}; its column k is column perm[k]
+  // lane i holds row piv(i) of M^{-1} (times its pivot); column k is column perm[k]
   LT *inv = reinterpret_cast<LT *>(L.fac);
   wave_lds_sync();
   if (li < S) {
 #pragma unroll
-    for (int k = 0; k < S; ++k) inv[perm[k] * S + piv] = a[k];
+    for (int k = 0; k < S; ++k) inv[perm[k] * S + piv] = a[k] * dinv;
   }
   wave_lds_sync();
   return info;
