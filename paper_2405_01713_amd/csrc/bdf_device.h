@@ -60,14 +60,6 @@ struct MechDev {
   const double *lnA;       // [R]
   const double *EaR;       // [R]
   const double *lnK;       // [R] (reversible only)
-  // Analytic-Jacobian term tables, lane-major ([slot][64]): for column j the
-  // slots jcol_off[j] .. jcol_off[j+1]-1 hold, for lane (row) i, one term of
-  // d f_i / d y_j: x = index into k (2r + side) or -1, y = o1 | o2 << 8 | coef << 16
-  // (o = 0xff: no factor); the value is coef * k[x] * y[o1] * y[o2].
-  const int32_t *jcol_off;  // [S+1]
-  const int2 *jtab;
-  const int32_t *jtcol_off;  // same for J^T (lane = column of J)
-  const int2 *jttab;
   const double *w;           // [S] species weights (perturbation rescale)
 };
 
@@ -396,33 +388,63 @@ __device__ __forceinline__ double rhs(const MechDev &m, const Lds &L, int li, do
   return L.fb[li];
 }
 
-// Row li of M = I - gamma J (or of M^T) at the state y held by the lanes.
-// `off` has n_tab_cols + 1 entries (the mechanism's species count).
+// Row li of M = I - gamma J (or of M^T when `transposed`) at the state y held
+// by the lanes (lane i passes y_i).  M is assembled in LDS, in the area that
+// afterwards holds the inverse, column-major ((i, c) at c*S + i): starting
+// from the identity, lane r mod 64 takes reaction r, forms d q_r / d y_c for
+// every occupied slot c (the side's rate constant times the other slots of
+// that side; the reverse constant is stored negated) and adds
+// -gamma nu_ir d q_r / d y_c to M(i, c) for every occupied slot i of the
+// reaction (reactant slots count -1, product slots +1) with LDS atomics.
+// Each lane then reads its row (its column for M^T).  Terms are rounded to LT
+// before they are summed.
 template <int S, typename LT>
-__device__ __forceinline__ void newton_matrix(LT (&a)[S], const int32_t *off, const int2 *tab,
-                                              int n_tab_cols, const Lds &L, int li, double yi,
-                                              double gamma) {
+__device__ __forceinline__ void newton_matrix(LT (&a)[S], const MechDev &m, const Lds &L, int li,
+                                              double yi, double gamma, bool transposed) {
+  LT *M = reinterpret_cast<LT *>(L.fac);
   wave_lds_sync();
   L.yb[li] = yi;
+  for (int e = li; e < S * S; e += kWave)
+    M[e] = e % (S + 1) == 0 ? static_cast<LT>(1) : static_cast<LT>(0);
   wave_lds_sync();
-  const int nc = n_tab_cols;
+  for (int r = li; r < m.R; r += kWave) {
+    const int2 w = reinterpret_cast<const int2 *>(m.rx)[r];
+    int sp[2][3];
 #pragma unroll
-  for (int j = 0; j < S; ++j) {
-    double acc = 0.0;
-    // columns beyond the mechanism's species (padding) have no terms
-    const int s0 = j < nc ? off[j] : 0, s1 = j < nc ? off[j + 1] : 0;
-    for (int s = s0; s < s1; ++s) {
-      const int2 t = tab[s * kWave + li];
-      if (t.x >= 0) {
-        double v = L.kk[t.x];
-        const int o1 = t.y & 0xff, o2 = (t.y >> 8) & 0xff;
-        if (o1 != 0xff) v *= L.yb[o1];
-        if (o2 != 0xff) v *= L.yb[o2];
-        acc = fma(static_cast<double>(static_cast<int8_t>(t.y >> 16)), v, acc);
+    for (int k = 0; k < 3; ++k) {
+      sp[0][k] = slot_species(w.x, k);
+      sp[1][k] = slot_species(w.y, k);
+    }
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      if (side == 1 && !m.reversible) break;
+      const double kside = L.kk[2 * r + side];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int col = sp[side][c];
+        if (col == 0xff) continue;
+        double d = kside;
+#pragma unroll
+        for (int o = 0; o < 3; ++o)
+          if (o != c && sp[side][o] != 0xff) d *= L.yb[sp[side][o]];
+        const LT g = static_cast<LT>(gamma * d);
+        LT *Mc = M + col * S;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          if (sp[0][i] != 0xff) atomicAdd(Mc + sp[0][i], g);
+          if (sp[1][i] != 0xff) atomicAdd(Mc + sp[1][i], -g);
+        }
       }
     }
-    a[j] = static_cast<LT>((j == li ? 1.0 : 0.0) - gamma * acc);
   }
+  wave_lds_sync();
+  const int lr = li < S ? li : 0;
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    const LT v = transposed ? M[lr * S + j] : M[j * S + lr];
+    a[j] = li < S ? v : static_cast<LT>(0);
+  }
+  wave_lds_sync();
 }
 
 // ---------------------------------------------------------------------------
@@ -666,7 +688,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         int info;
         {
           LT a[S];
-          newton_matrix<S, LT>(a, m.jcol_off, m.jtab, m.S, L, li, z[0], gamma);
+          newton_matrix<S, LT>(a, m, L, li, z[0], gamma, false);
           info = gj_invert<S, LT>(a, li, L);
         }
         nsetups++;
@@ -1021,7 +1043,7 @@ __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int 
     // (I - gamma J(y_n))^T mu = eb
     {
       double a[S];
-      newton_matrix<S, double>(a, m.jtcol_off, m.jttab, m.S, L, li, yn, gamma);
+      newton_matrix<S, double>(a, m, L, li, yn, gamma, true);
       gj_invert<S, double>(a, li, L);
     }
     const double mu = own ? inv_solve<S, double>(L, li, eb) : 0.0;

@@ -75,7 +75,6 @@ struct bdfx_mech_s {
   void *dmem = nullptr;
   bdfx::MechDev dev{};
   std::vector<double> w;
-  size_t jr_terms = 0;
 };
 
 struct Bin {
@@ -209,65 +208,7 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
     rx[2 * r] = static_cast<int32_t>(wr);
     rx[2 * r + 1] = static_cast<int32_t>(wp);
   }
-  // Jacobian terms: d q_r / d y_j for slot l of side sd is
-  // k_side * prod(other slots); distributed to every reactant row (-1) and
-  // product row (+1).  Enumerated in reaction / side / slot / row order.
-  struct Term {
-    int row, col, kidx, o1, o2, coef;
-  };
-  std::vector<Term> terms;
   const bool reversible = d->lnK != nullptr;
-  for (int r = 0; r < R; ++r) {
-    const int32_t *side[2] = {d->reac + r * 3, d->prod + r * 3};
-    for (int sd = 0; sd < (reversible ? 2 : 1); ++sd)
-      for (int l = 0; l < 3; ++l) {
-        const int j = side[sd][l];
-        if (j < 0) continue;
-        int others[2] = {0xff, 0xff}, no = 0;
-        for (int o = 0; o < 3; ++o)
-          if (o != l && side[sd][o] >= 0) others[no++] = side[sd][o];
-        for (int s = 0; s < 3; ++s) {
-          const int a = d->reac[r * 3 + s], b = d->prod[r * 3 + s];
-          if (a >= 0) terms.push_back({a, j, 2 * r + sd, others[0], others[1], -1});
-          if (b >= 0) terms.push_back({b, j, 2 * r + sd, others[0], others[1], +1});
-        }
-      }
-  }
-  // Lane-major slot tables: for the static loop index c (a column of M for
-  // the row-per-lane layout, a row of M for the transposed layout) the slots
-  // off[c] .. off[c+1]-1 hold, for each lane, the terms of its entry in
-  // enumeration order, padded with empty slots (x = -1).
-  auto slot_table = [&](bool transposed, std::vector<int32_t> &off, std::vector<int2> &tab) {
-    std::vector<std::vector<std::vector<const Term *>>> ent(
-        S, std::vector<std::vector<const Term *>>(bdfx::kWave));
-    for (const auto &t : terms) {
-      const int c = transposed ? t.row : t.col, lane = transposed ? t.col : t.row;
-      ent[c][lane].push_back(&t);
-    }
-    // offsets padded to the largest compiled size (extra columns are empty),
-    // so that a kernel padded beyond S can never index past the array
-    off.assign(bdfx::kMaxS + 1, 0);
-    for (int c = 0; c < S; ++c) {
-      size_t depth = 0;
-      for (const auto &v : ent[c]) depth = std::max(depth, v.size());
-      off[c + 1] = off[c] + static_cast<int32_t>(depth);
-    }
-    for (int c = S; c < bdfx::kMaxS; ++c) off[c + 1] = off[S];
-    tab.assign(static_cast<size_t>(off[S]) * bdfx::kWave, make_int2(-1, 0));
-    for (int c = 0; c < S; ++c)
-      for (int lane = 0; lane < bdfx::kWave; ++lane)
-        for (size_t k = 0; k < ent[c][lane].size(); ++k) {
-          const Term &t = *ent[c][lane][k];
-          int2 e;
-          e.x = t.kidx;
-          e.y = (t.o1 & 0xff) | ((t.o2 & 0xff) << 8) | ((t.coef & 0xff) << 16);
-          tab[(off[c] + k) * bdfx::kWave + lane] = e;
-        }
-  };
-  std::vector<int32_t> jr_off, jc_off;
-  std::vector<int2> jr_tab, jc_tab;
-  slot_table(false, jr_off, jr_tab);
-  slot_table(true, jc_off, jc_tab);
 
   std::vector<double> lnA(d->lnA, d->lnA + R), EaR(R, 0.0), lnK(R, 0.0), w(S, 1.0);
   if (d->EaR) EaR.assign(d->EaR, d->EaR + R);
@@ -281,9 +222,7 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
     return o;
   };
   const size_t o_rx = reserve(rx.size() * 4), o_lnA = reserve(R * 8), o_EaR = reserve(R * 8),
-               o_lnK = reserve(R * 8), o_jro = reserve(jr_off.size() * 4),
-               o_jre = reserve(jr_tab.size() * 8), o_jco = reserve(jc_off.size() * 4),
-               o_jce = reserve(jc_tab.size() * 8), o_w = reserve(S * 8);
+               o_lnK = reserve(R * 8), o_w = reserve(S * 8);
   HIPCHK(ctx, hipSetDevice(ctx->device));
   void *dmem = nullptr;
   HIPCHK(ctx, hipMalloc(&dmem, off));
@@ -296,10 +235,6 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
   if (e == hipSuccess) e = up(o_lnA, lnA.data(), R * 8);
   if (e == hipSuccess) e = up(o_EaR, EaR.data(), R * 8);
   if (e == hipSuccess) e = up(o_lnK, lnK.data(), R * 8);
-  if (e == hipSuccess) e = up(o_jro, jr_off.data(), jr_off.size() * 4);
-  if (e == hipSuccess) e = up(o_jre, jr_tab.data(), jr_tab.size() * 8);
-  if (e == hipSuccess) e = up(o_jco, jc_off.data(), jc_off.size() * 4);
-  if (e == hipSuccess) e = up(o_jce, jc_tab.data(), jc_tab.size() * 8);
   if (e == hipSuccess) e = up(o_w, w.data(), S * 8);
   if (e != hipSuccess) {
     hipFree(dmem);
@@ -312,7 +247,6 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
   m->reversible = reversible;
   m->dmem = dmem;
   m->w = w;
-  m->jr_terms = terms.size();
   bdfx::MechDev &dv = m->dev;
   dv.S = S;
   dv.R = R;
@@ -321,10 +255,6 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
   dv.lnA = reinterpret_cast<const double *>(base + o_lnA);
   dv.EaR = reinterpret_cast<const double *>(base + o_EaR);
   dv.lnK = reinterpret_cast<const double *>(base + o_lnK);
-  dv.jcol_off = reinterpret_cast<const int32_t *>(base + o_jro);
-  dv.jtab = reinterpret_cast<const int2 *>(base + o_jre);
-  dv.jtcol_off = reinterpret_cast<const int32_t *>(base + o_jco);
-  dv.jttab = reinterpret_cast<const int2 *>(base + o_jce);
   dv.w = reinterpret_cast<const double *>(base + o_w);
   *out = m;
   return BDFX_OK;
