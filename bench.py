@@ -28,6 +28,68 @@ from paper_2405_01713_amd import workloads as W  # noqa: E402
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources and build flags; a stored traffic figure is
+    reported only while this matches."""
+    import hashlib
+    from paper_2405_01713_amd import build as B
+    h = hashlib.sha256(" ".join(B.CFLAGS).encode())
+    csrc = os.path.join(ROOT, "paper_2405_01713_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def _pmc_rows(d):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def traffic_from(fetch_dir, write_dir, copy_mib, workload, form, out=TRAFFIC_FILE):
+    """HBM traffic of the integrator launch from two rocprofv3 --pmc runs of
+    ``bench.py --copy-probe copy_mib --forms form --steps 1 --warmup 0``
+    (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  Each counter is scaled
+    by its reading for the probe copy, which reads and writes copy_mib MiB."""
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _pmc_rows(d) if r["Counter_Name"] == counter]
+        by = {}
+        for r in rows:
+            k = int(r["Dispatch_Id"])
+            by.setdefault(k, [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
+        integ = [v for k, v in sorted(by.items()) if "k_integrate" in v[0]]
+        copies = [v for k, v in sorted(by.items()) if "bdfx" not in v[0]]
+        copy_kib = max(v[1] for v in copies)
+        factor = copy_mib * 1024.0 / copy_kib
+        res[counter] = dict(integrate_kib=integ[-1][1], copy_kib=copy_kib, scale=factor,
+                            bytes=integ[-1][1] * factor * 1024.0)
+    doc = dict(workload=workload, form=form, source_hash=kernel_source_hash(), copy_mib=copy_mib,
+               fetch=res["FETCH_SIZE"], write=res["WRITE_SIZE"],
+               traffic_bytes=res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"])
+    with open(out, "w") as fh:
+        json.dump(doc, fh, indent=1)
+    return doc
+
+
+def stored_traffic(workload, form):
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("workload") != workload or d.get("form") != form:
+        return None
+    return d["traffic_bytes"] if d.get("source_hash") == kernel_source_hash() else None
 
 
 def flops_model(mech: dict, forcing: bool = False) -> dict:
@@ -64,19 +126,20 @@ def algorithmic_flops(stats: np.ndarray, fm: dict) -> float:
                  + stats.size * fm["cell"])
 
 
-def run_form(w, form, steps, warmup, opts_extra=None):
+def run_form(w, form, steps, warmup, opts_extra=None, tuning_cache=None):
     import torch
     from paper_2405_01713_amd import bdfx
 
-    # waves_per_simd=3: register allocation for three resident waves per SIMD
-    # (measured faster than the compiler's unconstrained allocation at S = 21
-    # and S = 53 despite spills)
-    opts = dict(plain=dict(scheduler=0, lu_precision=64, waves_per_simd=3),
-                batched=dict(scheduler=1, lu_precision=64, waves_per_simd=3),
-                batched_fp32lu=dict(scheduler=1, lu_precision=32, waves_per_simd=3))[form]
+    # plain: static grid, default launch shape; batched: persistent work
+    # queue with the launch shape picked by the autotuner (untimed)
+    opts = dict(plain=dict(scheduler=0, lu_precision=64),
+                batched=dict(scheduler=1, lu_precision=64),
+                batched_fp32lu=dict(scheduler=1, lu_precision=32))[form]
     opts.update(opts_extra or {})
     integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"],
                             kscale=w["kscale"], cell_mech=w["cell_mech"], **opts)
+    tuning = (integ.autotune(0.0, w["t_out"], cache=tuning_cache) if opts["scheduler"] == 1
+              else None)
     y0 = integ.y.clone()
     stream = integ.stream
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -99,7 +162,7 @@ def run_form(w, form, steps, warmup, opts_extra=None):
     st = integ.cell_stats()
     integ.close()
     return dict(wall_ms_per_step=1e3 * wall / steps, kernel_ms=float(np.mean(kern_ms)),
-                kernel_ms_min=float(np.min(kern_ms)), y=y, stats=st)
+                kernel_ms_min=float(np.min(kern_ms)), y=y, stats=st, tuning=tuning)
 
 
 def run_adjoint(steps, warmup, n_cells=None, record_steps=2048, n_check=32):
@@ -128,8 +191,11 @@ def run_adjoint(steps, warmup, n_cells=None, record_steps=2048, n_check=32):
         torch.cuda.synchronize()
         return float(np.median([a.elapsed_time(b) for a, b in ev]))
 
-    common = dict(scheduler=1, waves_per_simd=3)
+    common = dict(scheduler=1)
     plain = bdfx.Integrator([m], w["y0"], w["rtol"], w["atol"], T=w["T"], **common)
+    tune = plain.autotune(0.0, w["t_out"])
+    common.update(waves_per_simd=tune[0]["waves_per_simd"],
+                  waves_per_block=tune[0]["waves_per_block"], queue_chunk=tune[0]["queue_chunk"])
     y0 = plain.y.clone()
 
     def fwd_plain():
@@ -200,18 +266,36 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=262144)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--tuning-cache", default=None,
+                    help="JSON file of autotuned launch shapes (reused when present)")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="first run a device copy of this many MiB (traffic scale reference)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc outputs and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not supported "
                                    "(cells shard with no communication, see DESIGN.md)"}))
         sys.exit(2)
 
+    if args.traffic_from:
+        form = args.forms.split(",")[0]
+        print(json.dumps(traffic_from(*args.traffic_from, args.copy_probe, args.workload, form)))
+        return
+    if args.copy_probe > 0:
+        import torch
+        n = int(args.copy_probe * 2**20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = W.make_workload(args.workload, args.cells)
     m0 = w["mechs"][0]
     fms = [flops_model(m) for m in w["mechs"]]
     forms = {}
     for form in args.forms.split(","):
-        r = run_form(w, form, args.steps, args.warmup)
+        r = run_form(w, form, args.steps, args.warmup, tuning_cache=args.tuning_cache)
         st = r["stats"]
         if w["cell_mech"] is None:
             F = algorithmic_flops(st, fms[0])
@@ -224,6 +308,7 @@ def main():
                            failed_cells=int(np.sum(st["status"] != 0)),
                            mean_nst=float(st["nst"].mean()), mean_nfe=float(st["nfe"].mean()),
                            mean_nsetups=float(st["nsetups"].mean()), alg_flops=F,
+                           tuning=r["tuning"],
                            _y=r["y"])
 
     cpu = None
@@ -248,8 +333,10 @@ def main():
     best = max(ok or forms, key=lambda k: forms[k]["cells_per_s"])
     b = forms[best]
     roof = {"bound": "alu", "achieved": b["tflops"], "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": b["tflops"] / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-            "kernel": "bdfx::k_integrate", "flops_per_launch": b["alg_flops"]}
+            "unit": "TFLOP/s", "frac": b["tflops"] / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": stored_traffic(args.workload, best),
+            "kernel": "bdfx::k_integrate", "flops_per_launch": b["alg_flops"],
+            "alg_bytes_per_launch": w["n_cells"] * (16 * max(m["n_species"] for m in w["mechs"]) + 56)}
     out = {
         "metric": "cells integrated/s per outer step @rtol 1e-6",
         "value": b["cells_per_s"],

@@ -193,6 +193,31 @@ int bdfx_stats_summary(bdfx_ctx ctx, bdfx_summary *out);
  * at the recorded states).  Enqueue only. */
 int bdfx_adjoint(bdfx_ctx ctx, const double *d_ybar, double *d_y0bar, double *d_lnA_bar);
 
+/* Launch shape of the integrator for the cells of one mechanism. */
+typedef struct {
+  int32_t mech;            /* mechanism index (as in d_cell_mech) */
+  int32_t waves_per_simd;  /* 0 or 3, as bdfx_options.waves_per_simd */
+  int32_t waves_per_block; /* 1..16 */
+  int32_t queue_chunk;     /* cells per work-queue pop, >= 1 */
+  int64_t sample_cells;    /* bdfx_autotune(): cells timed */
+  float ms;                /* bdfx_autotune(): time of the fastest shape on the sample */
+  float reserved;
+} bdfx_tuning;
+
+/* Autotuner: for every mechanism, times each candidate launch shape
+ * (waves_per_simd in {0, 3} x waves_per_block in {1, 2, 4} x queue_chunk in
+ * {1, 4} for the queue scheduler) integrating the first min(sample_cells,
+ * 16384) cells of that mechanism over [t0, t_out] with HIP events, and keeps
+ * the fastest; sample_cells <= 0 means 16384.  The sampled states are saved
+ * in the workspace and restored after every trial; their d_status / d_stats
+ * entries are overwritten.  out: [n_mech] results in launch order (larger
+ * mechanisms first), or NULL.  Synchronises the stream.  The choice holds
+ * until the next bdfx_bind(). */
+int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, bdfx_tuning *out);
+/* Apply launch shapes chosen earlier (for example cached results of
+ * bdfx_autotune()); entries name their mechanism; the rest are ignored. */
+int bdfx_set_tuning(bdfx_ctx ctx, const bdfx_tuning *tunings, int32_t n);
+
 /* Library version string. */
 const char *bdfx_version(void);
 

@@ -28,7 +28,7 @@ CELL_STATUS = {0: "success", -1: "too_much_work", -3: "err_failure", -4: "conv_f
 EXPORTED = ["bdfx_create", "bdfx_set_stream", "bdfx_destroy", "bdfx_last_error",
             "bdfx_mech_create", "bdfx_mech_destroy", "bdfx_mech_set_weights", "bdfx_plan",
             "bdfx_bind", "bdfx_integrate", "bdfx_perturb", "bdfx_stats_summary",
-            "bdfx_adjoint", "bdfx_version"]
+            "bdfx_adjoint", "bdfx_autotune", "bdfx_set_tuning", "bdfx_version"]
 
 
 class MechDesc(C.Structure):
@@ -51,6 +51,12 @@ class Summary(C.Structure):
                 ("nst", C.c_int64), ("nfe", C.c_int64), ("nni", C.c_int64),
                 ("nsetups", C.c_int64), ("netf", C.c_int64), ("ncfn", C.c_int64),
                 ("max_nst", C.c_int64), ("status_count", C.c_int64 * 11)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("mech", C.c_int32), ("waves_per_simd", C.c_int32),
+                ("waves_per_block", C.c_int32), ("queue_chunk", C.c_int32),
+                ("sample_cells", C.c_int64), ("ms", C.c_float), ("reserved", C.c_float)]
 
 
 STATS_DTYPE = np.dtype([("status", np.int32), ("nst", np.int32), ("nfe", np.int32),
@@ -83,6 +89,8 @@ def lib():
             "bdfx_perturb": ([P, C.c_uint64, I64, C.c_double], C.c_int),
             "bdfx_stats_summary": ([P, C.POINTER(Summary)], C.c_int),
             "bdfx_adjoint": ([P, P, P, P], C.c_int),
+            "bdfx_autotune": ([P, C.c_double, C.c_double, I64, C.POINTER(Tuning)], C.c_int),
+            "bdfx_set_tuning": ([P, C.POINTER(Tuning), I32], C.c_int),
             "bdfx_version": ([], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -201,6 +209,23 @@ def bdfx_adjoint(ctx, ybar_ptr, y0bar_ptr, lnA_bar_ptr):
     _check(lib().bdfx_adjoint(ctx, v(ybar_ptr), v(y0bar_ptr), v(lnA_bar_ptr)), ctx)
 
 
+_TUNING_KEYS = ("mech", "waves_per_simd", "waves_per_block", "queue_chunk", "sample_cells", "ms")
+
+
+def bdfx_autotune(ctx, n_mech: int, t0: float, t_out: float, sample_cells: int = 0) -> list:
+    out = (Tuning * max(n_mech, 1))()
+    _check(lib().bdfx_autotune(ctx, float(t0), float(t_out), int(sample_cells), out), ctx)
+    return [{k: getattr(t, k) for k in _TUNING_KEYS} for t in out[:n_mech]]
+
+
+def bdfx_set_tuning(ctx, tunings: list):
+    arr = (Tuning * max(len(tunings), 1))()
+    for i, t in enumerate(tunings):
+        for k in ("mech", "waves_per_simd", "waves_per_block", "queue_chunk"):
+            setattr(arr[i], k, int(t[k]))
+    _check(lib().bdfx_set_tuning(ctx, arr, len(tunings)), ctx)
+
+
 # --- convenience wrapper over torch device memory -------------------------
 
 class Integrator:
@@ -270,6 +295,33 @@ class Integrator:
         bdfx_adjoint(self.ctx, yb.data_ptr(), y0bar.data_ptr(), lnA_bar.data_ptr())
         self._keep = yb
         return y0bar, lnA_bar
+
+    def autotune(self, t0, t_out, sample_cells=0, cache=None):
+        """Pick the launch shape per mechanism with bdfx_autotune().  With
+        ``cache`` (a JSON file path) results are looked up by device name,
+        mechanism size, LU precision and scheduler, and stored after tuning."""
+        import json
+
+        name = self.torch.cuda.get_device_properties(self.dev).name
+        key = lambda m: (f"{name}|S{self.mechs[m]['n_species']}|R{self.mechs[m]['n_reactions']}"
+                         f"|lu{self.opts.lu_precision}|sched{self.opts.scheduler}")
+        db = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                db = json.load(fh)
+        hits = [dict(db[key(m)], mech=m) for m in range(len(self.mechs)) if key(m) in db]
+        if cache and len(hits) == len(self.mechs):
+            bdfx_set_tuning(self.ctx, hits)
+            return hits
+        res = bdfx_autotune(self.ctx, len(self.mechs), t0, t_out, sample_cells)
+        if cache:
+            for r in res:
+                db[key(r["mech"])] = {k: r[k] for k in _TUNING_KEYS if k != "mech"}
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(db, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return res
 
     def outer_loop(self, n_outer, dt, seed, amplitude, t0=0.0):
         """Operator-splitting outer loop on the current stream: for k = 0 ..

@@ -89,6 +89,30 @@ hipError_t bdfx_launch_sum_cells(const double *pbar, int ldp, const int32_t *lis
   return hipGetLastError();
 }
 
+// dst[i][0..S) <- y[list[i]][0..S) (save) or the reverse (restore), i < n.
+__global__ void __launch_bounds__(256) k_copy_rows(double *y, int ldy, const int32_t *list, int64_t n,
+                                                   int S, double *dst, bool restore) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n * S) return;
+  const int64_t i = idx / S;
+  const int k = static_cast<int>(idx - i * S);
+  const int64_t cell = list ? list[i] : i;
+  if (restore)
+    y[cell * ldy + k] = dst[i * S + k];
+  else
+    dst[i * S + k] = y[cell * ldy + k];
+}
+
+hipError_t bdfx_launch_copy_rows(double *y, int ldy, const int32_t *list, int64_t n, int S,
+                                 double *dst, bool restore, hipStream_t s) {
+  const int64_t total = n * S;
+  if (total <= 0) return hipSuccess;
+  const int64_t blocks = (total + 255) / 256;
+  hipLaunchKernelGGL(k_copy_rows, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, y, ldy, list,
+                     n, S, dst, restore);
+  return hipGetLastError();
+}
+
 hipError_t bdfx_launch_fill_u32(uint32_t *p, int n, uint32_t v, hipStream_t s) {
   hipLaunchKernelGGL(bdfx::k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
   return hipGetLastError();

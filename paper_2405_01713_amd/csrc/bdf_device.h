@@ -193,6 +193,27 @@ __device__ __forceinline__ uint64_t wmax_u64(uint64_t v) {
   return __builtin_bit_cast(uint64_t, r);
 }
 
+__device__ __forceinline__ uint32_t wmax_u32(uint32_t v) {
+  auto step = [](uint32_t a, uint32_t b) { return a > b ? a : b; };
+  v = step(v, __builtin_amdgcn_update_dpp(0u, v, kQuadXor1, 0xf, 0xf, false));
+  v = step(v, __builtin_amdgcn_update_dpp(0u, v, kQuadXor2, 0xf, 0xf, false));
+  v = step(v, __builtin_amdgcn_update_dpp(0u, v, kHalfMirror, 0xf, 0xf, false));
+  v = step(v, __builtin_amdgcn_update_dpp(0u, v, kMirror, 0xf, 0xf, false));
+  v = step(v, __builtin_amdgcn_update_dpp(0u, v, kBcast15, 0xa, 0xf, false));
+  v = step(v, __builtin_amdgcn_update_dpp(0u, v, kBcast31, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+// 1/x for finite, normal, nonzero x: the hardware estimate refined by two
+// Newton-Raphson steps r <- r + r (1 - x r) (within about one ulp).
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // lowest lane whose predicate holds (-1 if none); wave-uniform
 __device__ __forceinline__ int wfirst(bool pred) {
   return uni(static_cast<int>(__ffsll(static_cast<long long>(__ballot(pred)))) - 1);
@@ -204,31 +225,34 @@ __device__ __forceinline__ bool wany(bool pred) { return __ballot(pred) != 0ull;
 // Nordsieck array operations (z_j = h^j y^(j) / j!)
 // ---------------------------------------------------------------------------
 
+// The integrator keeps z_j = 0 for every j > q (columns start at zero, an
+// order decrease zeroes z_q, an order increase writes z_{q+1}, a restart
+// zeroes z_2..), so the operations below run over all kQmax columns with no
+// per-order selects: the extra terms add or scale exact zeros.
+
 // z <- z * Pascal: Taylor shift by one step (predictor).
-__device__ __forceinline__ void nd_predict(double (&z)[kQmax + 1], int q) {
+__device__ __forceinline__ void nd_predict(double (&z)[kQmax + 1]) {
 #pragma unroll
   for (int k = 1; k <= kQmax; ++k)
 #pragma unroll
-    for (int j = kQmax; j >= k; --j)
-      if (k <= q && j <= q) z[j - 1] += z[j];
+    for (int j = kQmax; j >= k; --j) z[j - 1] += z[j];
 }
 
 // exact inverse of nd_predict (restore after a rejected attempt)
-__device__ __forceinline__ void nd_unpredict(double (&z)[kQmax + 1], int q) {
+__device__ __forceinline__ void nd_unpredict(double (&z)[kQmax + 1]) {
 #pragma unroll
   for (int k = 1; k <= kQmax; ++k)
 #pragma unroll
-    for (int j = kQmax; j >= k; --j)
-      if (k <= q && j <= q) z[j - 1] -= z[j];
+    for (int j = kQmax; j >= k; --j) z[j - 1] -= z[j];
 }
 
 // h -> eta h: z_j <- eta^j z_j
-__device__ __forceinline__ void nd_rescale(double (&z)[kQmax + 1], int q, double eta) {
+__device__ __forceinline__ void nd_rescale(double (&z)[kQmax + 1], double eta) {
   double f = 1.0;
 #pragma unroll
   for (int j = 1; j <= kQmax; ++j) {
     f *= eta;
-    if (j <= q) z[j] *= f;
+    z[j] *= f;
   }
 }
 
@@ -255,53 +279,47 @@ __device__ __forceinline__ void bdf_coeffs(int q, const double (&xi)[kQmax + 2],
 #pragma unroll
   for (int i = 1; i <= kQmax; ++i)
     if (i <= q) {
-      const double rxi = 1.0 / xi[i];
+      const double rxi = rcp(xi[i]);
 #pragma unroll
       for (int j = i; j >= 1; --j) l[j] = fma(l[j - 1], rxi, l[j]);
     }
-  Cerr = 1.0 / (l[1] * pick(xi, q + 1));
+  Cerr = rcp(l[1] * pick(xi, q + 1));
 }
 
+// H_k = 1 + 1/2 + ... + 1/k and k! for k = 0..6
 __device__ __forceinline__ double harmonic(int k) {
-  double s = 0.0;
-  for (int i = 1; i <= k; ++i) s += 1.0 / i;
-  return s;
+  constexpr double kH[7] = {0.0, 1.0, 1.5, 11.0 / 6.0, 25.0 / 12.0, 137.0 / 60.0, 49.0 / 20.0};
+  return kH[k];
 }
 
 __device__ __forceinline__ double factorial(int k) {
-  double s = 1.0;
-  for (int i = 2; i <= k; ++i) s *= i;
-  return s;
+  constexpr double kF[7] = {1.0, 1.0, 2.0, 6.0, 24.0, 120.0, 720.0};
+  return kF[k];
 }
 
-// x^(1/p) for x >= 0 and p in 1..7: with x = u 2^(p k) (u in [0.5, 2^p), exact
-// power-of-two scaling) the root is 2^k u^(1/p); u^(1/p) starts from the
-// hardware FP32 log2/exp2 estimate and takes two Newton steps on y^p = u in
-// FP64 (quadratic convergence from ~1e-7 gives full double precision).
+// x^(1/p) for x >= 0 and p in 1..7.  With x = u 2^(p k) (k from the binary
+// exponent, u in about [2^-1, 2^(p+1)), exact power-of-two scaling) the root
+// is 2^k u^(1/p); u^(1/p) starts from the FP32 hardware log2/exp2 estimate
+// (relative error below 1e-6) and takes one Newton step on y^p = u in FP64
+// (relative error below 1e-12).
 __device__ __forceinline__ double root_p(double x, int p) {
   if (p == 1 || !(x > 0.0) || !(x < __builtin_huge_val())) return x;
   const int e = __builtin_amdgcn_frexp_exp(x);
   const double m = __builtin_amdgcn_frexp_mant(x);  // x = m 2^e, m in [0.5, 1)
-  int k = e / p, r = e - k * p;
-  if (r < 0) {
-    r += p;
-    k -= 1;
-  }
-  const double u = __builtin_ldexp(m, r);
-  const float uf = static_cast<float>(u);
-  double y = static_cast<double>(__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(uf) / p));
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    double yp1 = 1.0;  // y^(p-1)
-    for (int i = 1; i < p; ++i) yp1 *= y;
-    y += (u - yp1 * y) / (p * yp1);
-  }
+  const float rp = __builtin_amdgcn_rcpf(static_cast<float>(p));
+  const int k = static_cast<int>(__builtin_floorf(static_cast<float>(e) * rp));
+  const double u = __builtin_ldexp(m, e - k * p);  // any integer k keeps x = u 2^(p k) exact
+  double y = static_cast<double>(
+      __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(static_cast<float>(u)) * rp));
+  double yp1 = 1.0;  // y^(p-1)
+  for (int i = 1; i < p; ++i) yp1 *= y;
+  y = fma(fma(-y, yp1, u), __builtin_amdgcn_rcp(p * yp1), y);
   return __builtin_ldexp(y, k);
 }
 
 // eta = 1 / ((bias err)^(1/p) + 1e-6)
 __device__ __forceinline__ double eta_from(double bias, double err, int p) {
-  return 1.0 / (root_p(bias * err, p) + 1.0e-6);
+  return rcp(root_p(bias * err, p) + 1.0e-6);
 }
 
 __device__ __forceinline__ double ipow(double x, int k) {
@@ -333,12 +351,13 @@ struct Lds {
   double *C;    // [Ctl::kSize]
   int *perm;    // [64] pivot row of each elimination step
   double *kk;   // [2R]: k_f at 2r, -k_r at 2r+1
+  int2 *rx;     // [R]: reactant / product slot words of the mechanism
   void *fac;    // [S][S] inverse Newton matrix (LT), column-major: (r, c) at c*S + r
 };
 
 // doubles of LDS per wave for S species, R reactions and factor type size
 __host__ __device__ constexpr int lds_doubles(int S, int R, int lt_bytes) {
-  return 2 * kWave + Ctl::kSize + kWave / 2 + 2 * R + (S * S * lt_bytes + 7) / 8;
+  return 2 * kWave + Ctl::kSize + kWave / 2 + 3 * R + (S * S * lt_bytes + 7) / 8;
 }
 
 __device__ __forceinline__ Lds carve(double *base, int R) {
@@ -348,7 +367,8 @@ __device__ __forceinline__ Lds carve(double *base, int R) {
   L.C = L.fb + kWave;
   L.perm = reinterpret_cast<int *>(L.C + Ctl::kSize);
   L.kk = L.C + Ctl::kSize + kWave / 2;
-  L.fac = L.kk + 2 * R;
+  L.rx = reinterpret_cast<int2 *>(L.kk + 2 * R);
+  L.fac = L.kk + 3 * R;
   return L;
 }
 
@@ -368,7 +388,7 @@ __device__ __forceinline__ double rhs(const MechDev &m, const Lds &L, int li, do
   L.fb[li] = Fi;
   wave_lds_sync();
   for (int r = li; r < m.R; r += kWave) {
-    const int2 w = reinterpret_cast<const int2 *>(m.rx)[r];
+    const int2 w = L.rx[r];
     double pf = L.kk[2 * r], pr = L.kk[2 * r + 1];
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
@@ -408,7 +428,7 @@ __device__ __forceinline__ void newton_matrix(LT (&a)[S], const MechDev &m, cons
     M[e] = e % (S + 1) == 0 ? static_cast<LT>(1) : static_cast<LT>(0);
   wave_lds_sync();
   for (int r = li; r < m.R; r += kWave) {
-    const int2 w = reinterpret_cast<const int2 *>(m.rx)[r];
+    const int2 w = L.rx[r];
     int sp[2][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -479,13 +499,23 @@ __device__ __forceinline__ int gj_invert(LT (&a)[S], int li, const Lds &L) {
   LT dinv = static_cast<LT>(1);  // 1 / own pivot
 #pragma unroll
   for (int k = 0; k < S; ++k) {
-    const uint64_t key = piv < 0 ? abs_key(a[k]) : 0ull;
-    const uint64_t kmax = wmax_u64(key);
-    const int p = wfirst(key == kmax);
-    if (kmax <= 1ull && info == 0) info = k + 1;
+    int p;
+    bool zero_pivot;
+    if constexpr (sizeof(LT) == 4) {
+      const uint32_t key = piv < 0 ? static_cast<uint32_t>(abs_key(a[k])) : 0u;
+      const uint32_t kmax = wmax_u32(key);
+      p = wfirst(key == kmax);
+      zero_pivot = kmax <= 1u;
+    } else {
+      const uint64_t key = piv < 0 ? abs_key(a[k]) : 0ull;
+      const uint64_t kmax = wmax_u64(key);
+      p = wfirst(key == kmax);
+      zero_pivot = kmax <= 1ull;
+    }
+    if (zero_pivot && info == 0) info = k + 1;
     const bool is_p = li == p;
     const LT pk = lane_bcast(a[k], p);
-    const LT rp = static_cast<LT>(1) / pk;
+    const LT rp = rcp(pk);
     const LT g = is_p ? static_cast<LT>(0) : a[k] * rp;
     if (is_p) {
       piv = k;
@@ -553,6 +583,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
     if (P.kscale) kf *= P.kscale[cell * P.ldk + r];
     L.kk[2 * r] = kf;
     L.kk[2 * r + 1] = m.reversible ? -(kf * exp(-m.lnK[r])) : -0.0;
+    L.rx[r] = reinterpret_cast<const int2 *>(m.rx)[r];
   }
 
   const double yin = own ? P.y[cell * P.ldy + li] : 0.0;
@@ -641,14 +672,14 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
       status = kTooMuchWork;
       break;
     }
-    ewt = own ? 1.0 / (rtol * fabs(z[0]) + atol_i) : 0.0;  // from y^{n-1}, Eq. (3)
+    ewt = own ? rcp(rtol * fabs(z[0]) + atol_i) : 0.0;  // from y^{n-1}, Eq. (3)
     int nef_step = 0, ncf_step = 0, nsf_step = 0;
     double dsm = 0.0, Cerr = 0.5;
     for (;;) {  // attempts of this step
       bool landing = false;
       if (t + h >= tout * (1.0 - 4.0 * kUround)) {
         const double hnew = uni(tout - t);
-        nd_rescale(z, q, hnew / h);
+        nd_rescale(z, hnew / h);
         h = hnew;
         landing = true;
       }
@@ -656,13 +687,13 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         status = kErrFailure;
         break;
       }
-      nd_predict(z, q);
+      nd_predict(z);
       double l1;
       {
         // xi_i = (t_n - t_{n-i}) / h and the coefficients of this attempt
         double xi[kQmax + 2], l[kQmax + 2];
         double sum = h;
-        const double rh = 1.0 / h;
+        const double rh = rcp(h);
         xi[0] = 0.0;
         xi[1] = 1.0;
 #pragma unroll
@@ -681,10 +712,12 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         l1 = uni(l[1]);
         Cerr = uni(Cerr);
       }
-      const double gamma = uni(h / l1);
+      const double rl1 = uni(rcp(l1));
+      const double gamma = uni(h * rl1);
       double gamma_bar = uni(C[Ctl::kGammaBar]);
       bool fresh = false;
-      if (need_setup || nst >= nst_setup + 20 || fabs(gamma / gamma_bar - 1.0) > 0.3) {
+      // (gamma_bar = 0 before the first setup, which need_setup forces)
+      if (need_setup || nst >= nst_setup + 20 || fabs(gamma * rcp(gamma_bar) - 1.0) > 0.3) {
         int info;
         {
           LT a[S];
@@ -700,19 +733,20 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         fresh = true;
         if (info != 0) {
           // singular Newton matrix: recoverable once per step by cutting h
-          nd_unpredict(z, q);
+          nd_unpredict(z);
           need_setup = true;
           if (++nsf_step >= 2) {
             status = kSetupFailure;
             break;
           }
-          nd_rescale(z, q, 0.25);
+          nd_rescale(z, 0.25);
           h = uni(h * 0.25);
           C[Ctl::kEtaMax] = 1.0;
           continue;
         }
       }
-      const double cfac = uni(gamma != gamma_bar ? 2.0 / (1.0 + gamma / gamma_bar) : 1.0);
+      const double cfac =
+          uni(gamma != gamma_bar ? 2.0 * rcp(1.0 + gamma * rcp(gamma_bar)) : 1.0);
 
       // Newton iteration on G(e) = e - gamma f(z_0 + e) + z_1 / l_1, Eq. (4)
       bool conv = false;
@@ -722,14 +756,14 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         f = rhs(m, L, li, z[0] + e, Fi);
         nfe++;
         nni++;
-        const double Gi = e - gamma * f + z[1] / l1;
+        const double Gi = e - gamma * f + z[1] * rl1;
         double delta = inv_solve<S, LT>(L, li, -Gi);
         if (cfac != 1.0) delta *= cfac;
         e += delta;
         const double d = wrms(delta, ewt, n);
         if (!isfinite(d)) break;
         if (mit >= 1) {
-          const double ratio = d / dprev;
+          const double ratio = d * rcp(dprev);
           Rrate = uni(0.3 * Rrate > ratio ? 0.3 * Rrate : ratio);
         }
         if ((Rrate < 1.0 ? Rrate : 1.0) * d <= 0.1 / Cerr) {
@@ -741,13 +775,13 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
       }
       if (!conv) {
         ncfn++;
-        nd_unpredict(z, q);
+        nd_unpredict(z);
         if (++ncf_step >= 10) {
           status = kConvFailure;
           break;
         }
         if (fresh) {
-          nd_rescale(z, q, 0.25);
+          nd_rescale(z, 0.25);
           h = uni(h * 0.25);
           C[Ctl::kEtaMax] = 1.0;
         }
@@ -759,7 +793,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
       dsm = uni(Cerr * wrms(e, ewt, n));
       if (dsm <= 1.0) break;
       netf++;
-      nd_unpredict(z, q);
+      nd_unpredict(z);
       if (++nef_step >= 7) {
         status = kErrFailure;
         break;
@@ -783,7 +817,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         if (eta < 0.1) eta = 0.1;
         if (nef_step >= 2 && eta > 0.2) eta = 0.2;
         eta = uni(eta);
-        nd_rescale(z, q, eta);
+        nd_rescale(z, eta);
         h = uni(h * eta);
       }
     }
@@ -791,9 +825,9 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
 
     // accept: correct the Nordsieck array
     t = uni(C[Ctl::kTn]);
+    // l_j = 0 for j > q
 #pragma unroll
-    for (int j = 0; j <= kQmax; ++j)
-      if (j <= q) z[j] = fma(C[Ctl::kL + j], e, z[j]);
+    for (int j = 0; j <= kQmax; ++j) z[j] = fma(C[Ctl::kL + j], e, z[j]);
     nst++;
     wave_lds_sync();
 #pragma unroll
@@ -882,7 +916,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
             qwait = q + 1;
             have_eprev = false;
           }
-          nd_rescale(z, q, eta);
+          nd_rescale(z, eta);
           h = uni(h * eta);
         }
       }
@@ -936,7 +970,7 @@ __device__ __forceinline__ double adj_scatter(const MechDev &m, const Lds &L, do
   L.fb[li] = 0.0;
   wave_lds_sync();
   for (int r = li; r < m.R; r += kWave) {
-    const int2 w = reinterpret_cast<const int2 *>(m.rx)[r];
+    const int2 w = L.rx[r];
     int a[3], b[3];
     double pf = L.kk[2 * r], pr = L.kk[2 * r + 1], s = 0.0;
 #pragma unroll
@@ -1015,6 +1049,7 @@ __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int 
     if (P.kscale) kf *= P.kscale[cell * P.ldk + r];
     L.kk[2 * r] = kf;
     L.kk[2 * r + 1] = m.reversible ? -(kf * exp(-m.lnK[r])) : -0.0;
+    L.rx[r] = reinterpret_cast<const int2 *>(m.rx)[r];
     pb[r] = 0.0;
   }
   const double *rec = P.rec + static_cast<int64_t>(cell) * P.rec_cap * stride;

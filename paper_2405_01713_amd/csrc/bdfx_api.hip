@@ -32,6 +32,8 @@ BDFX_DECLARE_SIZE(64)
 hipError_t bdfx_launch_perturb(const bdfx::Params &P, uint64_t seed, int64_t step, double amp,
                                hipStream_t s);
 hipError_t bdfx_launch_fill_u32(uint32_t *p, int n, uint32_t v, hipStream_t s);
+hipError_t bdfx_launch_copy_rows(double *y, int ldy, const int32_t *list, int64_t n, int S,
+                                 double *dst, bool restore, hipStream_t s);
 hipError_t bdfx_launch_sum_cells(const double *pbar, int ldp, const int32_t *list, int64_t n, int R,
                                  double *out, hipStream_t s);
 
@@ -68,6 +70,9 @@ const SizeEntry *size_for(int S) {
 
 }  // namespace
 
+// largest per-bin sample the autotuner times (rows saved in the workspace)
+constexpr int64_t kTuneCells = 16384;
+
 struct bdfx_mech_s {
   bdfx_ctx ctx = nullptr;
   int S = 0, R = 0;
@@ -85,6 +90,9 @@ struct Bin {
   const SizeEntry *se = nullptr;
   int32_t lds_doubles = 0;
   bdfx::LaunchCfg cfg{};
+  // launch shape: from the options, or chosen by bdfx_autotune()
+  int32_t waves_per_simd = 0, waves_per_block = 1, queue_chunk = 1;
+  bool tuned = false;
 };
 
 struct bdfx_ctx_s {
@@ -102,7 +110,8 @@ struct bdfx_ctx_s {
   int S_max = 0, R_max = 0;
   size_t ws_need = 0;
   size_t off_queue = 0, off_bins = 0, off_rec = 0, off_recn = 0, off_rechpad = 0, off_recy0 = 0,
-         off_pbar = 0;
+         off_pbar = 0, off_tune = 0;
+  int64_t tune_cells = 0;  // rows the autotuner can save in the workspace
   int rec_stride = 0;
   // bind
   char *ws = nullptr;
@@ -345,6 +354,8 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
   ctx->off_rechpad = reserve(cap ? static_cast<size_t>(n_cells) * 8 : 0);
   ctx->off_recy0 = reserve(cap ? static_cast<size_t>(n_cells) * ctx->rec_stride * 8 : 0);
   ctx->off_pbar = reserve(cap ? static_cast<size_t>(n_cells) * R_max * 8 : 0);
+  ctx->tune_cells = std::min<int64_t>(n_cells, kTuneCells);
+  ctx->off_tune = reserve(static_cast<size_t>(ctx->tune_cells) * S_max * 8);
   ctx->ws_need = off;
   *ws_bytes = off;
   ctx->planned = true;
@@ -416,29 +427,40 @@ int bdfx_bind(bdfx_ctx ctx, void *d_ws, size_t ws_bytes, double *d_y, int32_t ld
 // ---------------------------------------------------------------------------
 
 // Kernel, LDS size and grid of every bin (called by bdfx_bind).
-static int configure_bins(bdfx_ctx ctx) {
+static int configure_bin(bdfx_ctx ctx, Bin &b) {
   const bool fp32 = ctx->opt.lu_precision == 32;
   const bool queue = ctx->opt.scheduler == BDFX_SCHED_QUEUE;
+  const bdfx_mech m = ctx->mechs[b.mech];
+  b.se = size_for(m->S);
+  if (!b.se) return fail(ctx, BDFX_EUNSUPPORTED, "no kernel for %d species", m->S);
+  const int waves = std::max(b.waves_per_block, 1);
+  b.lds_doubles = static_cast<int32_t>(align_up(bdfx::lds_doubles(b.se->S, m->R, fp32 ? 4 : 8), 2));
+  b.cfg.block = bdfx::kWave * waves;
+  b.cfg.lds_bytes = static_cast<size_t>(waves) * b.lds_doubles * 8;  // one wave per cell
+  if (b.cfg.lds_bytes > 65536)
+    return fail(ctx, BDFX_EUNSUPPORTED, "LDS per block %zu exceeds 64 KiB", b.cfg.lds_bytes);
+  const int64_t need = (b.count + waves - 1) / waves;
+  if (queue) {
+    int occ = 0;
+    HIPCHK(ctx, b.se->occupancy(fp32, b.waves_per_simd, b.cfg.block, b.cfg.lds_bytes, &occ));
+    const int per_cu = ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : std::max(occ, 1);
+    b.cfg.grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(per_cu) * ctx->n_cu, need));
+  } else {
+    if (need > INT32_MAX) return fail(ctx, BDFX_EUNSUPPORTED, "too many cells for one grid");
+    b.cfg.grid = static_cast<int>(need);
+  }
+  return BDFX_OK;
+}
+
+// Kernel, LDS size and grid of every bin (called by bdfx_bind).
+static int configure_bins(bdfx_ctx ctx) {
   for (Bin &b : ctx->bins) {
-    const bdfx_mech m = ctx->mechs[b.mech];
-    b.se = size_for(m->S);
-    if (!b.se) return fail(ctx, BDFX_EUNSUPPORTED, "no kernel for %d species", m->S);
-    const int waves = ctx->opt.waves_per_block > 0 ? ctx->opt.waves_per_block : 1;
-    b.lds_doubles = static_cast<int32_t>(align_up(bdfx::lds_doubles(b.se->S, m->R, fp32 ? 4 : 8), 2));
-    b.cfg.block = bdfx::kWave * waves;
-    b.cfg.lds_bytes = static_cast<size_t>(waves) * b.lds_doubles * 8;  // one wave per cell
-    if (b.cfg.lds_bytes > 65536)
-      return fail(ctx, BDFX_EUNSUPPORTED, "LDS per block %zu exceeds 64 KiB", b.cfg.lds_bytes);
-    const int64_t need = (b.count + waves - 1) / waves;
-    if (queue) {
-      int occ = 0;
-      HIPCHK(ctx, b.se->occupancy(fp32, ctx->opt.waves_per_simd, b.cfg.block, b.cfg.lds_bytes, &occ));
-      const int per_cu = ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : std::max(occ, 1);
-      b.cfg.grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(per_cu) * ctx->n_cu, need));
-    } else {
-      if (need > INT32_MAX) return fail(ctx, BDFX_EUNSUPPORTED, "too many cells for one grid");
-      b.cfg.grid = static_cast<int>(need);
+    if (!b.tuned) {
+      b.waves_per_simd = ctx->opt.waves_per_simd;
+      b.waves_per_block = ctx->opt.waves_per_block > 0 ? ctx->opt.waves_per_block : 1;
+      b.queue_chunk = ctx->opt.queue_chunk > 0 ? ctx->opt.queue_chunk : 1;
     }
+    if (const int rc = configure_bin(ctx, b)) return rc;
   }
   return BDFX_OK;
 }
@@ -468,7 +490,7 @@ static bdfx::Params make_params(bdfx_ctx ctx, const Bin &b, double t0, double to
   P.max_steps = ctx->opt.max_steps;
   P.n_sp = m->S;
   P.queue = reinterpret_cast<uint32_t *>(ctx->ws + ctx->off_queue) + b.mech;
-  P.chunk = ctx->opt.queue_chunk;
+  P.chunk = b.queue_chunk;
   if (ctx->opt.record_steps > 0) {
     P.rec = reinterpret_cast<double *>(ctx->ws + ctx->off_rec);
     P.rec_cap = ctx->opt.record_steps;
@@ -495,7 +517,7 @@ int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out) {
     bdfx::Params P = make_params(ctx, b, t0, t_out);
     P.use_queue = queue ? 1 : 0;
     P.lds_doubles = b.lds_doubles;
-    HIPCHK(ctx, b.se->launch(P, fp32, ctx->opt.waves_per_simd, b.cfg, ctx->stream));
+    HIPCHK(ctx, b.se->launch(P, fp32, b.waves_per_simd, b.cfg, ctx->stream));
   }
   ctx->last_t0 = t0;
   ctx->last_tout = t_out;
@@ -513,6 +535,121 @@ int bdfx_perturb(bdfx_ctx ctx, uint64_t seed, int64_t outer_step, double amplitu
     HIPCHK(ctx, bdfx_launch_perturb(P, seed, outer_step, amplitude, ctx->stream));
   }
   ctx->integrated = false;
+  return BDFX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuning of the launch shape
+// ---------------------------------------------------------------------------
+
+int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, bdfx_tuning *out) {
+  if (!ctx) return BDFX_EINVAL;
+  if (!ctx->bound) return fail(ctx, BDFX_EORDER, "bdfx_bind must precede bdfx_autotune");
+  if (!(t_out > t0) || !std::isfinite(t0) || !std::isfinite(t_out))
+    return fail(ctx, BDFX_EINVAL, "need finite t_out > t0");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const bool fp32 = ctx->opt.lu_precision == 32;
+  const bool queue = ctx->opt.scheduler == BDFX_SCHED_QUEUE;
+  const int64_t ns = sample_cells > 0 ? std::min(sample_cells, ctx->tune_cells) : ctx->tune_cells;
+  double *save = reinterpret_cast<double *>(ctx->ws + ctx->off_tune);
+  uint32_t *qctr = reinterpret_cast<uint32_t *>(ctx->ws + ctx->off_queue);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(ctx, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(ctx, BDFX_EHIP, "hipEventCreate failed");
+  }
+  int rc = BDFX_OK;
+  const int wps_c[] = {0, 3}, wpb_c[] = {1, 2, 4}, chunk_c[] = {1, 4};
+  for (size_t bi = 0; bi < ctx->bins.size() && rc == BDFX_OK; ++bi) {
+    Bin &b = ctx->bins[bi];
+    if (b.count == 0) continue;
+    const bdfx_mech m = ctx->mechs[b.mech];
+    Bin trial = b;
+    trial.count = std::min(ns, b.count);  // the first cells of the bin
+    bdfx::Params P = make_params(ctx, trial, t0, t_out);
+    P.use_queue = queue ? 1 : 0;
+    float best = 0.0f;
+    bool have = false;
+    Bin pick = b;
+    for (int wps : wps_c)
+      for (int wpb : wpb_c)
+        for (int chunk : chunk_c) {
+          if (!queue && chunk != 1) continue;
+          trial.waves_per_simd = wps;
+          trial.waves_per_block = wpb;
+          trial.queue_chunk = chunk;
+          if (configure_bin(ctx, trial) != BDFX_OK) continue;  // e.g. LDS too large
+          P.lds_doubles = trial.lds_doubles;
+          P.chunk = chunk;
+          float total = 0.0f;
+          hipError_t e = hipSuccess;
+          for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // rep 0 warms up
+            e = bdfx_launch_copy_rows(ctx->y, ctx->ldy, P.list, trial.count, m->S, save, false,
+                                      ctx->stream);
+            if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+            if (e == hipSuccess && queue) e = bdfx_launch_fill_u32(qctr, 64, 0u, ctx->stream);
+            if (e == hipSuccess) e = trial.se->launch(P, fp32, wps, trial.cfg, ctx->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+            if (e == hipSuccess)
+              e = bdfx_launch_copy_rows(ctx->y, ctx->ldy, P.list, trial.count, m->S, save, true,
+                                        ctx->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) total += ms;
+          }
+          if (e != hipSuccess) {
+            rc = fail(ctx, BDFX_EHIP, "autotune trial: %s", hipGetErrorString(e));
+            break;
+          }
+          if (!have || total < best) {
+            best = total;
+            have = true;
+            pick = trial;
+          }
+        }
+    if (rc != BDFX_OK || !have) break;
+    b.waves_per_simd = pick.waves_per_simd;
+    b.waves_per_block = pick.waves_per_block;
+    b.queue_chunk = pick.queue_chunk;
+    b.tuned = true;
+    rc = configure_bin(ctx, b);
+    if (out) {
+      out[bi].mech = b.mech;
+      out[bi].waves_per_simd = b.waves_per_simd;
+      out[bi].waves_per_block = b.waves_per_block;
+      out[bi].queue_chunk = b.queue_chunk;
+      out[bi].sample_cells = trial.count;
+      out[bi].ms = best / 2.0f;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc == BDFX_OK) {
+    const hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(ctx, BDFX_EHIP, "%s", hipGetErrorString(e));
+  }
+  return rc;
+}
+
+int bdfx_set_tuning(bdfx_ctx ctx, const bdfx_tuning *t, int32_t n) {
+  if (!ctx || (n > 0 && !t)) return BDFX_EINVAL;
+  if (!ctx->bound) return fail(ctx, BDFX_EORDER, "bdfx_bind must precede bdfx_set_tuning");
+  for (int32_t k = 0; k < n; ++k) {
+    if (t[k].waves_per_simd != 0 && t[k].waves_per_simd != 3)
+      return fail(ctx, BDFX_EINVAL, "waves_per_simd must be 0 or 3");
+    if (t[k].waves_per_block < 1 || t[k].waves_per_block > 16 || t[k].queue_chunk < 1)
+      return fail(ctx, BDFX_EINVAL, "invalid launch shape");
+    for (Bin &b : ctx->bins)
+      if (b.mech == t[k].mech) {
+        b.waves_per_simd = t[k].waves_per_simd;
+        b.waves_per_block = t[k].waves_per_block;
+        b.queue_chunk = t[k].queue_chunk;
+        b.tuned = true;
+        if (const int rc = configure_bin(ctx, b)) return rc;
+      }
+  }
   return BDFX_OK;
 }
 

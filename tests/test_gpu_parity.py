@@ -204,6 +204,40 @@ def test_outer_loop_graph(oracle, parity):
     assert_parity(y_eager, yo, w, oracle, "outer loop", reference=reference)
 
 
+def test_autotune(tmp_path):
+    """The autotuner leaves the states as they were, the tuned launch gives
+    the same bits as the untuned one (cells are independent), and cached
+    shapes are reapplied without timing."""
+    import torch
+    from paper_2405_01713_amd import bdfx
+    w = W.make_workload("mixed_s9_s53_1m", 3000)
+    kw = dict(T=w["T"], cell_mech=w["cell_mech"], scheduler=1)
+    ref = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], **kw)
+    ref.integrate(0.0, w["t_out"])
+    torch.cuda.synchronize()
+    y_ref, st_ref = ref.state(), ref.cell_stats()
+    ref.close()
+    cache = str(tmp_path / "tuning.json")
+    integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], **kw)
+    res = integ.autotune(0.0, w["t_out"], sample_cells=1024, cache=cache)
+    assert sorted(r["mech"] for r in res) == [0, 1]
+    for r in res:
+        assert r["waves_per_simd"] in (0, 3) and r["waves_per_block"] in (1, 2, 4)
+        assert r["queue_chunk"] in (1, 4) and r["ms"] > 0 and r["sample_cells"] > 0
+    assert np.array_equal(integ.state(), w["y0"])
+    integ.integrate(0.0, w["t_out"])
+    torch.cuda.synchronize()
+    assert np.array_equal(integ.state(), y_ref)
+    assert np.array_equal(integ.cell_stats(), st_ref)
+    integ.close()
+    again = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], **kw)
+    hit = again.autotune(0.0, w["t_out"], cache=cache)
+    again.close()
+    shape = lambda rs: sorted((r["mech"], r["waves_per_simd"], r["waves_per_block"],
+                               r["queue_chunk"]) for r in rs)
+    assert shape(hit) == shape(res)
+
+
 def test_adjoint_matches_oracle(oracle):
     """GPU discrete adjoint vs the oracle's adjoint along its own adaptive
     record (both use the recorded states), loss = sum_cells sum_i c_i y_i."""
