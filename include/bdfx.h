@@ -97,7 +97,8 @@ typedef struct {
   int32_t blocks_per_cu;   /* persistent grid: resident blocks per CU (0 = auto) */
   int32_t queue_chunk;     /* cells per work-queue pop (0 = 1) */
   int32_t waves_per_simd;  /* register budget of the integrator kernel: 0 = compiler's
-                              choice, 3 = code built for three resident waves per SIMD */
+                              choice, 3 or 4 = code built for that many resident waves
+                              per SIMD (at most 168 / 128 VGPRs, spilling if needed) */
 } bdfx_options;
 
 /* Per-cell statistics written by bdfx_integrate() (48 bytes, [N]). */
@@ -196,7 +197,7 @@ int bdfx_adjoint(bdfx_ctx ctx, const double *d_ybar, double *d_y0bar, double *d_
 /* Launch shape of the integrator for the cells of one mechanism. */
 typedef struct {
   int32_t mech;            /* mechanism index (as in d_cell_mech) */
-  int32_t waves_per_simd;  /* 0 or 3, as bdfx_options.waves_per_simd */
+  int32_t waves_per_simd;  /* 0, 3 or 4, as bdfx_options.waves_per_simd */
   int32_t waves_per_block; /* 1..16 */
   int32_t queue_chunk;     /* cells per work-queue pop, >= 1 */
   int64_t sample_cells;    /* bdfx_autotune(): cells timed */
@@ -205,7 +206,7 @@ typedef struct {
 } bdfx_tuning;
 
 /* Autotuner: for every mechanism, times each candidate launch shape
- * (waves_per_simd in {0, 3} x waves_per_block in {1, 2, 4} x queue_chunk in
+ * (waves_per_simd in {0, 3, 4} x waves_per_block in {1, 2, 4} x queue_chunk in
  * {1, 4} for the queue scheduler) integrating the first min(sample_cells,
  * 16384) cells of that mechanism over [t0, t_out] with HIP events, and keeps
  * the fastest; sample_cells <= 0 means 16384.  The sampled states are saved

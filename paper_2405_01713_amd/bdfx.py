@@ -298,12 +298,15 @@ class Integrator:
 
     def autotune(self, t0, t_out, sample_cells=0, cache=None):
         """Pick the launch shape per mechanism with bdfx_autotune().  With
-        ``cache`` (a JSON file path) results are looked up by device name,
-        mechanism size, LU precision and scheduler, and stored after tuning."""
+        ``cache`` (a JSON file path, one per machine) results are looked up by
+        compute-unit count, mechanism size, LU precision and scheduler, and
+        stored after tuning."""
         import json
 
-        name = self.torch.cuda.get_device_properties(self.dev).name
-        key = lambda m: (f"{name}|S{self.mechs[m]['n_species']}|R{self.mechs[m]['n_reactions']}"
+        # the cache file belongs to one machine; the key tells apart batch
+        # shapes and GPUs of different size
+        n_cu = self.torch.cuda.get_device_properties(self.dev).multi_processor_count
+        key = lambda m: (f"CU{n_cu}|S{self.mechs[m]['n_species']}|R{self.mechs[m]['n_reactions']}"
                          f"|lu{self.opts.lu_precision}|sched{self.opts.scheduler}")
         db = {}
         if cache and os.path.exists(cache):

@@ -297,7 +297,7 @@ __device__ __forceinline__ double factorial(int k) {
   return kF[k];
 }
 
-// x^(1/p) for x >= 0 and p in 1..7.  With x = u 2^(p k) (k from the binary
+// x^(1/p) for x >= 0 and p in 1..14.  With x = u 2^(p k) (k from the binary
 // exponent, u in about [2^-1, 2^(p+1)), exact power-of-two scaling) the root
 // is 2^k u^(1/p); u^(1/p) starts from the FP32 hardware log2/exp2 estimate
 // (relative error below 1e-6) and takes one Newton step on y^p = u in FP64
@@ -317,9 +317,10 @@ __device__ __forceinline__ double root_p(double x, int p) {
   return __builtin_ldexp(y, k);
 }
 
-// eta = 1 / ((bias err)^(1/p) + 1e-6)
-__device__ __forceinline__ double eta_from(double bias, double err, int p) {
-  return rcp(root_p(bias * err, p) + 1.0e-6);
+// eta = 1 / ((bias err)^(1/p) + 1e-6), from the squared error err2 = err^2:
+// 1 / ((bias^2 err2)^(1/(2p)) + 1e-6)
+__device__ __forceinline__ double eta_from2(double bias, double err2, int p) {
+  return rcp(root_p(bias * bias * err2, 2 * p) + 1.0e-6);
 }
 
 __device__ __forceinline__ double ipow(double x, int k) {
@@ -380,29 +381,40 @@ __device__ __forceinline__ int slot_species(int word, int s) { return (word >> (
 
 // f_i = F_i + sum_r nu_ir q_r: reaction r is handled by lane r mod 64, its
 // net rate q_r = k_f prod y_reac - k_r prod y_prod is scattered into the LDS
-// accumulator with FP64 atomics.  Lane i passes y_i, F_i and gets f_i.
+// accumulator with FP64 atomics.  Two passes of 64 reactions are processed
+// per loop iteration so that their LDS round trips overlap; lanes past R take
+// an all-empty slot word.  Lane i passes y_i, F_i and gets f_i.
+__device__ __forceinline__ void rhs_reaction(const Lds &L, int r, int2 w) {
+  double pf = L.kk[2 * r], pr = L.kk[2 * r + 1];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int a = slot_species(w.x, s), b = slot_species(w.y, s);
+    if (a != 0xff) pf *= L.yb[a];
+    if (b != 0xff) pr *= L.yb[b];
+  }
+  const double q = pf + pr;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int a = slot_species(w.x, s), b = slot_species(w.y, s);
+    if (a != 0xff) atomicAdd(&L.fb[a], -q);
+    if (b != 0xff) atomicAdd(&L.fb[b], q);
+  }
+}
+
 __device__ __forceinline__ double rhs(const MechDev &m, const Lds &L, int li, double yi,
                                       double Fi) {
   wave_lds_sync();
   L.yb[li] = yi;
   L.fb[li] = Fi;
   wave_lds_sync();
-  for (int r = li; r < m.R; r += kWave) {
-    const int2 w = L.rx[r];
-    double pf = L.kk[2 * r], pr = L.kk[2 * r + 1];
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      const int a = slot_species(w.x, s), b = slot_species(w.y, s);
-      if (a != 0xff) pf *= L.yb[a];
-      if (b != 0xff) pr *= L.yb[b];
-    }
-    const double q = pf + pr;
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      const int a = slot_species(w.x, s), b = slot_species(w.y, s);
-      if (a != 0xff) atomicAdd(&L.fb[a], -q);
-      if (b != 0xff) atomicAdd(&L.fb[b], q);
-    }
+  const int R = m.R;
+  const int2 none = make_int2(-1, -1);  // every slot empty
+  for (int r0 = 0; r0 < R; r0 += 2 * kWave) {
+    const int ra = r0 + li, rb = ra + kWave;
+    const int2 wa = ra < R ? L.rx[ra] : none;
+    const int2 wb = rb < R ? L.rx[rb] : none;
+    if (ra < R) rhs_reaction(L, ra, wa);
+    if (rb < R) rhs_reaction(L, rb, wb);
   }
   wave_lds_sync();
   return L.fb[li];
@@ -557,9 +569,11 @@ __device__ __forceinline__ double inv_solve(const Lds &L, int li, double b) {
 // per-cell integration
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double wrms(double v, double w, int n) {
+// squared WRMS norm of Eq. (3); inv_n = 1 / (species of the cell).  The
+// integrator compares and raises squared norms, so no square root is taken.
+__device__ __forceinline__ double wrms2(double v, double w, double inv_n) {
   const double t = v * w;  // w = 0 on lanes without a species
-  return uni(sqrt(wsum(t * t) / n));
+  return uni(wsum(t * t) * inv_n);
 }
 
 template <int S, typename LT>
@@ -569,6 +583,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
   const Lds L = carve(lds, R);
   double *const C = L.C;
   const int n = P.n_sp;
+  const double inv_n = 1.0 / n;
   const bool own = li < n;
   const double rtol = P.rtol, t0 = P.t0, tout = P.tout;
   const int qmax = P.max_order < 1 ? 1 : (P.max_order > kQmax ? kQmax : P.max_order);
@@ -631,7 +646,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         const double ft = rhs(m, L, li, yin + hg * f, Fi);
         nfe++;
         const double ydd = (ft - f) / hg;
-        const double yddnrm = wrms(ydd, ewt, n);
+        const double yddnrm = sqrt(wrms2(ydd, ewt, inv_n));
         if (!(yddnrm > 0.0)) {
           at_ub = true;
           break;
@@ -662,7 +677,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
   if (P.rec && li == 0) P.rec_hpad[cell] = h;
 
   int qwait = 2, nst_setup = 0;
-  double Rrate = 1.0;
+  double R2 = 1.0;  // squared Newton convergence rate
   bool need_setup = true, have_eprev = false, rebuilt = false;
   double e = 0.0, eprev = 0.0;
 
@@ -674,7 +689,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
     }
     ewt = own ? rcp(rtol * fabs(z[0]) + atol_i) : 0.0;  // from y^{n-1}, Eq. (3)
     int nef_step = 0, ncf_step = 0, nsf_step = 0;
-    double dsm = 0.0, Cerr = 0.5;
+    double dsm2 = 0.0, Cerr = 0.5;
     for (;;) {  // attempts of this step
       bool landing = false;
       if (t + h >= tout * (1.0 - 4.0 * kUround)) {
@@ -728,7 +743,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         nst_setup = nst;
         gamma_bar = gamma;
         C[Ctl::kGammaBar] = gamma;
-        Rrate = 1.0;
+        R2 = 1.0;
         need_setup = false;
         fresh = true;
         if (info != 0) {
@@ -750,7 +765,9 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
 
       // Newton iteration on G(e) = e - gamma f(z_0 + e) + z_1 / l_1, Eq. (4)
       bool conv = false;
-      double dprev = 0.0;
+      double dprev2 = 0.0;
+      // stopping test of Eq. (4) with eps = 1/Cerr, on squared norms
+      const double tol2 = 0.01 * uni(rcp(Cerr * Cerr));
       e = 0.0;
       for (int mit = 0; mit < 3; ++mit) {
         f = rhs(m, L, li, z[0] + e, Fi);
@@ -760,18 +777,18 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         double delta = inv_solve<S, LT>(L, li, -Gi);
         if (cfac != 1.0) delta *= cfac;
         e += delta;
-        const double d = wrms(delta, ewt, n);
-        if (!isfinite(d)) break;
+        const double d2 = wrms2(delta, ewt, inv_n);
+        if (!isfinite(d2)) break;
         if (mit >= 1) {
-          const double ratio = d * rcp(dprev);
-          Rrate = uni(0.3 * Rrate > ratio ? 0.3 * Rrate : ratio);
+          const double ratio2 = d2 * rcp(dprev2);
+          R2 = uni(0.09 * R2 > ratio2 ? 0.09 * R2 : ratio2);
         }
-        if ((Rrate < 1.0 ? Rrate : 1.0) * d <= 0.1 / Cerr) {
+        if ((R2 < 1.0 ? R2 : 1.0) * d2 <= tol2) {
           conv = true;
           break;
         }
-        if (mit >= 1 && d > 2.0 * dprev) break;
-        dprev = d;
+        if (mit >= 1 && d2 > 4.0 * dprev2) break;
+        dprev2 = d2;
       }
       if (!conv) {
         ncfn++;
@@ -790,8 +807,8 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
       }
 
       // local error test (Sec. 2)
-      dsm = uni(Cerr * wrms(e, ewt, n));
-      if (dsm <= 1.0) break;
+      dsm2 = uni(Cerr * Cerr * wrms2(e, ewt, inv_n));
+      if (dsm2 <= 1.0) break;
       netf++;
       nd_unpredict(z);
       if (++nef_step >= 7) {
@@ -813,7 +830,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         have_eprev = false;
         rebuilt = true;
       } else {
-        double eta = eta_from(6.0, dsm, q + 1);
+        double eta = eta_from2(6.0, dsm2, q + 1);
         if (eta < 0.1) eta = 0.1;
         if (nef_step >= 2 && eta > 0.2) eta = 0.2;
         eta = uni(eta);
@@ -858,14 +875,15 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
       if (eta_max == 1.0) {
         if (qwait < 2) qwait = 2;  // right after a failure: hold h and q
       } else {
-        double eta = uni(eta_from(6.0, dsm, q + 1));
+        double eta = uni(eta_from2(6.0, dsm2, q + 1));
         int qnew = q;
         if (qwait == 0) {
           qwait = 2;
           if (q > 1) {
             const double lte =
-                factorial(q - 1) / harmonic(q - 1) * wrms(nd_get(z, q), ewt, n);
-            const double eta_qm1 = uni(eta_from(6.0, lte, q));
+                factorial(q - 1) / harmonic(q - 1);
+            const double lte2 = lte * lte * wrms2(nd_get(z, q), ewt, inv_n);
+            const double eta_qm1 = uni(eta_from2(6.0, lte2, q));
             if (eta_qm1 > eta) {
               eta = eta_qm1;
               qnew = q - 1;
@@ -873,8 +891,9 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
           }
           if (q < qmax && have_eprev) {
             const double r = ipow(hstep / C[Ctl::kHprev], q + 1);
-            const double lte = wrms(e - r * eprev, ewt, n) / ((q + 2) * harmonic(q + 1));
-            const double eta_qp1 = uni(eta_from(10.0, lte, q + 2));
+            const double c = rcp((q + 2) * harmonic(q + 1));
+            const double lte2 = c * c * wrms2(e - r * eprev, ewt, inv_n);
+            const double eta_qp1 = uni(eta_from2(10.0, lte2, q + 2));
             if (eta_qp1 > eta) {
               eta = eta_qp1;
               qnew = q + 1;

@@ -12,7 +12,8 @@
 namespace bdfx {
 
 // MINW: minimum resident waves per SIMD the register allocation must allow
-// (1 = compiler's choice; 3 = at most 168 VGPRs, spilling if needed).
+// (1 = compiler's choice; 3 = at most 168 VGPRs, 4 = at most 128, spilling
+// if needed).
 template <int S, typename LT, int MINW>
 __global__ void __launch_bounds__(256, MINW) k_integrate(Params P) {
   extern __shared__ double smem[];
@@ -58,14 +59,16 @@ struct LaunchCfg {
 template <int S>
 hipError_t launch_integrate(const Params &P, bool fp32, int minw, const LaunchCfg &c,
                             hipStream_t s) {
-  if (fp32 && minw >= 3)
-    hipLaunchKernelGGL((k_integrate<S, float, 3>), dim3(c.grid), dim3(c.block), c.lds_bytes, s, P);
-  else if (fp32)
-    hipLaunchKernelGGL((k_integrate<S, float, 1>), dim3(c.grid), dim3(c.block), c.lds_bytes, s, P);
-  else if (minw >= 3)
-    hipLaunchKernelGGL((k_integrate<S, double, 3>), dim3(c.grid), dim3(c.block), c.lds_bytes, s, P);
-  else
-    hipLaunchKernelGGL((k_integrate<S, double, 1>), dim3(c.grid), dim3(c.block), c.lds_bytes, s, P);
+  const dim3 g(c.grid), b(c.block);
+  if (fp32) {
+    if (minw >= 4) hipLaunchKernelGGL((k_integrate<S, float, 4>), g, b, c.lds_bytes, s, P);
+    else if (minw >= 3) hipLaunchKernelGGL((k_integrate<S, float, 3>), g, b, c.lds_bytes, s, P);
+    else hipLaunchKernelGGL((k_integrate<S, float, 1>), g, b, c.lds_bytes, s, P);
+  } else {
+    if (minw >= 4) hipLaunchKernelGGL((k_integrate<S, double, 4>), g, b, c.lds_bytes, s, P);
+    else if (minw >= 3) hipLaunchKernelGGL((k_integrate<S, double, 3>), g, b, c.lds_bytes, s, P);
+    else hipLaunchKernelGGL((k_integrate<S, double, 1>), g, b, c.lds_bytes, s, P);
+  }
   return hipGetLastError();
 }
 
@@ -78,10 +81,15 @@ hipError_t launch_adjoint(const Params &P, const LaunchCfg &c, hipStream_t s) {
 template <int S>
 hipError_t occupancy_integrate(bool fp32, int minw, int block, size_t lds_bytes,
                                int *blocks_per_cu) {
-  const void *f = fp32 ? (minw >= 3 ? reinterpret_cast<const void *>(&k_integrate<S, float, 3>)
-                                    : reinterpret_cast<const void *>(&k_integrate<S, float, 1>))
-                       : (minw >= 3 ? reinterpret_cast<const void *>(&k_integrate<S, double, 3>)
-                                    : reinterpret_cast<const void *>(&k_integrate<S, double, 1>));
+  const void *f;
+  if (fp32)
+    f = minw >= 4   ? reinterpret_cast<const void *>(&k_integrate<S, float, 4>)
+        : minw >= 3 ? reinterpret_cast<const void *>(&k_integrate<S, float, 3>)
+                    : reinterpret_cast<const void *>(&k_integrate<S, float, 1>);
+  else
+    f = minw >= 4   ? reinterpret_cast<const void *>(&k_integrate<S, double, 4>)
+        : minw >= 3 ? reinterpret_cast<const void *>(&k_integrate<S, double, 3>)
+                    : reinterpret_cast<const void *>(&k_integrate<S, double, 1>);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds_bytes);
 }
 

@@ -302,6 +302,11 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
     return fail(ctx, BDFX_EINVAL, "lu_precision must be 64 or 32");
   if (o->scheduler != BDFX_SCHED_STATIC && o->scheduler != BDFX_SCHED_QUEUE)
     return fail(ctx, BDFX_EINVAL, "unknown scheduler %d", o->scheduler);
+  if (o->waves_per_simd != 0 && o->waves_per_simd != 3 && o->waves_per_simd != 4)
+    return fail(ctx, BDFX_EINVAL, "waves_per_simd must be 0, 3 or 4");
+  if (o->waves_per_block < 0 || o->waves_per_block > 16 || o->blocks_per_cu < 0 ||
+      o->queue_chunk < 0)
+    return fail(ctx, BDFX_EINVAL, "invalid launch shape");
   if (o->max_order < 0 || o->max_order > BDFX_MAX_ORDER)
     return fail(ctx, BDFX_EINVAL, "max_order out of 1..5");
   if (o->record_steps < 0) return fail(ctx, BDFX_EINVAL, "record_steps < 0");
@@ -560,7 +565,7 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
     return fail(ctx, BDFX_EHIP, "hipEventCreate failed");
   }
   int rc = BDFX_OK;
-  const int wps_c[] = {0, 3}, wpb_c[] = {1, 2, 4}, chunk_c[] = {1, 4};
+  const int wps_c[] = {0, 3, 4}, wpb_c[] = {1, 2, 4}, chunk_c[] = {1, 4};
   for (size_t bi = 0; bi < ctx->bins.size() && rc == BDFX_OK; ++bi) {
     Bin &b = ctx->bins[bi];
     if (b.count == 0) continue;
@@ -637,8 +642,8 @@ int bdfx_set_tuning(bdfx_ctx ctx, const bdfx_tuning *t, int32_t n) {
   if (!ctx || (n > 0 && !t)) return BDFX_EINVAL;
   if (!ctx->bound) return fail(ctx, BDFX_EORDER, "bdfx_bind must precede bdfx_set_tuning");
   for (int32_t k = 0; k < n; ++k) {
-    if (t[k].waves_per_simd != 0 && t[k].waves_per_simd != 3)
-      return fail(ctx, BDFX_EINVAL, "waves_per_simd must be 0 or 3");
+    if (t[k].waves_per_simd != 0 && t[k].waves_per_simd != 3 && t[k].waves_per_simd != 4)
+      return fail(ctx, BDFX_EINVAL, "waves_per_simd must be 0, 3 or 4");
     if (t[k].waves_per_block < 1 || t[k].waves_per_block > 16 || t[k].queue_chunk < 1)
       return fail(ctx, BDFX_EINVAL, "invalid launch shape");
     for (Bin &b : ctx->bins)
