@@ -493,53 +493,55 @@ __device__ __forceinline__ uint64_t abs_key(float v) {
 // Inverts the cell's S x S Newton matrix M (row i in lane i's registers) by
 // Gauss-Jordan elimination with partial pivoting: the pivot of column k is
 // the largest |a_ik| among rows not yet used, lowest row on ties (the same
-// pivot sequence as an LU factorisation with partial pivoting).  Every step
+// pivot sequence as an LU factorisation with partial pivoting).  Step k
 // eliminates column k from all other rows, row_i -= (a_ik / p_k) row_p, and
-// column k of the working array then stores column p_k of the accumulated
-// inverse.  Pivot rows are left unscaled during the elimination (all later
-// updates are linear in them) and each lane divides its row by its own pivot
-// at the end: one FMA per entry and step, and no cancellation on large pivots.
-// M^{-1} is written to LDS in natural order, column-major (entry (r, c) at
-// c*S + r), so that a solve is one lane-parallel matrix-vector product.
-// Returns 0, or k+1 for the first column k without a nonzero pivot (the
-// elimination then runs on garbage).
+// turns it into column p_k of the accumulated inverse.  The working row is
+// rotated by one slot per step (the column being eliminated is always slot 0,
+// the updated slot j is written to slot j-1 and the new inverse column to the
+// last slot), so every register index is static and the step loop need not
+// be unrolled; after S steps slot k holds the inverse column of step k.
+// Pivot rows are left unscaled during the elimination (all later updates are
+// linear in them) and each lane divides its row by its own pivot at the end:
+// one FMA per entry and step, and no cancellation on large pivots.  M^{-1} is
+// written to LDS in natural order, column-major (entry (r, c) at c*S + r), so
+// that a solve is one lane-parallel matrix-vector product.  Returns 0, or k+1
+// for the first column k without a nonzero pivot (the elimination then runs
+// on garbage).
 template <int S, typename LT>
 __device__ __forceinline__ int gj_invert(LT (&a)[S], int li, const Lds &L) {
   int piv = li < S ? -1 : 1 << 20;
   int info = 0;
   int *perm = L.perm;
   LT dinv = static_cast<LT>(1);  // 1 / own pivot
-#pragma unroll
   for (int k = 0; k < S; ++k) {
     int p;
     bool zero_pivot;
     if constexpr (sizeof(LT) == 4) {
-      const uint32_t key = piv < 0 ? static_cast<uint32_t>(abs_key(a[k])) : 0u;
+      const uint32_t key = piv < 0 ? static_cast<uint32_t>(abs_key(a[0])) : 0u;
       const uint32_t kmax = wmax_u32(key);
       p = wfirst(key == kmax);
       zero_pivot = kmax <= 1u;
     } else {
-      const uint64_t key = piv < 0 ? abs_key(a[k]) : 0ull;
+      const uint64_t key = piv < 0 ? abs_key(a[0]) : 0ull;
       const uint64_t kmax = wmax_u64(key);
       p = wfirst(key == kmax);
       zero_pivot = kmax <= 1ull;
     }
     if (zero_pivot && info == 0) info = k + 1;
     const bool is_p = li == p;
-    const LT pk = lane_bcast(a[k], p);
+    const LT pk = lane_bcast(a[0], p);
     const LT rp = rcp(pk);
-    const LT g = is_p ? static_cast<LT>(0) : a[k] * rp;
+    const LT g = is_p ? static_cast<LT>(0) : a[0] * rp;
     if (is_p) {
       piv = k;
       dinv = rp;
     }
 #pragma unroll
-    for (int j = 0; j < S; ++j)
-      if (j != k) a[j] = fma(-g, lane_bcast(a[j], p), a[j]);
-    a[k] = is_p ? static_cast<LT>(1) : -g;
+    for (int j = 1; j < S; ++j) a[j - 1] = fma(-g, lane_bcast(a[j], p), a[j]);
+    a[S - 1] = is_p ? static_cast<LT>(1) : -g;
     if (li == 0) perm[k] = p;
   }
-  // lane i holds row piv(i) of M^{-1} (times its pivot); column k is column perm[k]
+  // lane i holds row piv(i) of M^{-1} (times its pivot); slot k is column perm[k]
   LT *inv = reinterpret_cast<LT *>(L.fac);
   wave_lds_sync();
   if (li < S) {
