@@ -177,22 +177,6 @@ __device__ __forceinline__ double wmax(double v) {
   return lane_bcast(v, 63);
 }
 
-__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
-
-__device__ __forceinline__ uint64_t wmax_u64(uint64_t v) {
-  v = umax64(v, dpp<kQuadXor1>(v));
-  v = umax64(v, dpp<kQuadXor2>(v));
-  v = umax64(v, dpp<kHalfMirror>(v));
-  v = umax64(v, dpp<kMirror>(v));
-  v = umax64(v, dpp<kBcast15, 0xa>(v));
-  v = umax64(v, dpp<kBcast31, 0xc>(v));
-  const int2 p = __builtin_bit_cast(int2, v);
-  int2 r;
-  r.x = __builtin_amdgcn_readlane(p.x, 63);
-  r.y = __builtin_amdgcn_readlane(p.y, 63);
-  return __builtin_bit_cast(uint64_t, r);
-}
-
 __device__ __forceinline__ uint32_t wmax_u32(uint32_t v) {
   auto step = [](uint32_t a, uint32_t b) { return a > b ? a : b; };
   v = step(v, __builtin_amdgcn_update_dpp(0u, v, kQuadXor1, 0xf, 0xf, false));
@@ -522,10 +506,14 @@ __device__ __forceinline__ int gj_invert(LT (&a)[S], int li, const Lds &L) {
       p = wfirst(key == kmax);
       zero_pivot = kmax <= 1u;
     } else {
+      // exact 64-bit maximum in two 32-bit passes: high words, then the low
+      // words of the lanes that tie on the high word
       const uint64_t key = piv < 0 ? abs_key(a[0]) : 0ull;
-      const uint64_t kmax = wmax_u64(key);
-      p = wfirst(key == kmax);
-      zero_pivot = kmax <= 1ull;
+      const uint32_t hi = static_cast<uint32_t>(key >> 32), lo = static_cast<uint32_t>(key);
+      const uint32_t hmax = wmax_u32(hi);
+      const uint32_t lmax = wmax_u32(hi == hmax ? lo : 0u);
+      p = wfirst(hi == hmax && lo == lmax);
+      zero_pivot = hmax == 0u && lmax <= 1u;
     }
     if (zero_pivot && info == 0) info = k + 1;
     const bool is_p = li == p;
