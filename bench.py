@@ -218,6 +218,7 @@ def run_adjoint(steps, warmup, n_cells=None, record_steps=2048, n_check=32):
         out["g"] = rec.adjoint(ybar)
 
     t_bwd = timed(bwd, rec.stream)
+    log(f"adjoint: forward {t_fwd:.1f} ms, backward {t_bwd:.1f} ms")
     st = rec.cell_stats()
     y0bar = out["g"][0][:n_check].cpu().numpy()
     rec.close()
@@ -243,6 +244,139 @@ def run_adjoint(steps, warmup, n_cells=None, record_steps=2048, n_check=32):
     return res
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _timed_events(fn, stream, steps, warmup):
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        fn()
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def _errors(y, yo, rtol, atol):
+    """max |dy| / (|y_o| + atol) and max |dy| / (rtol |y_o| + atol) (error-weight units)."""
+    dy = np.abs(y - yo)
+    return dict(max_rel_err=float(np.max(dy / (np.abs(yo) + atol))),
+                max_err_units=float(np.max(dy / (rtol * np.abs(yo) + atol))),
+                frac_within_10rtol=float(np.mean(dy <= 10 * rtol * np.abs(yo) + atol)))
+
+
+def run_precision(steps, warmup, tuning_cache=None, n_cells=None, n_check=256):
+    """53 species / 325 reactions on 262,144 cells: FP64 vs FP32 Newton-matrix
+    inverse, both through the autotuned work queue; errors of both against the
+    FP64 oracle on the first n_check cells."""
+    from paper_2405_01713_amd import bdfx
+
+    w = W.make_workload("s53_r325_262k_fp32lu", n_cells)
+    out = dict(workload="s53_r325_262k_fp32lu", n_cells=w["n_cells"])
+    ys = {}
+    for lu in (64, 32):
+        integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"], scheduler=1,
+                                lu_precision=lu)
+        tune = integ.autotune(0.0, w["t_out"], cache=tuning_cache)
+        y0 = integ.y.clone()
+
+        def step():
+            integ.y.copy_(y0)
+            integ.integrate(0.0, w["t_out"])
+
+        ms = _timed_events(step, integ.stream, steps, warmup)
+        st = integ.cell_stats()
+        ys[lu] = integ.state()[:n_check]
+        integ.close()
+        log(f"precision lu{lu}: {ms:.1f} ms")
+        out[f"lu{lu}"] = dict(kernel_ms=ms, cells_per_s=w["n_cells"] / (ms * 1e-3), tuning=tune,
+                              failed_cells=int(np.sum(st["status"] != 0)),
+                              mean_nst=float(st["nst"].mean()))
+    out["speedup_fp32lu_over_fp64"] = out["lu64"]["kernel_ms"] / out["lu32"]["kernel_ms"]
+    try:
+        from oracle import oracle as O
+        yo, _ = O.integrate(w["mechs"], w["y0"][:n_check], 0.0, w["t_out"], w["rtol"], w["atol"],
+                            T=w["T"][:n_check])
+        for lu in (64, 32):
+            out[f"lu{lu}"]["vs_oracle"] = _errors(ys[lu], yo, w["rtol"], w["atol"])
+        out["check_cells"] = n_check
+    except Exception as e:  # the oracle is optional on the timing path
+        out["check_error"] = repr(e)
+    return out
+
+
+def _oracle_outer_loop(O, w, idx, n_outer, seed):
+    ms, cm = w["mechs"], w["cell_mech"][idx]
+    y = w["y0"][idx].copy()
+    for k in range(n_outer):
+        # the perturbation is keyed by the cell index: perturb the whole rows
+        # of the sampled cells at their own indices
+        full = np.zeros_like(w["y0"][: idx.max() + 1])
+        full[idx] = y
+        S_of = [ms[m]["n_species"] for m in w["cell_mech"][: idx.max() + 1]]
+        W_of = [ms[m]["w"] for m in w["cell_mech"][: idx.max() + 1]]
+        full = O.perturb(full, S_of, W_of, seed, k, w["perturb"])
+        y, _ = O.integrate(ms, full[idx], k * w["t_out"], (k + 1) * w["t_out"], w["rtol"], w["atol"],
+                           T=w["T"][idx], cell_mech=cm)
+    return y
+
+
+def run_batching(steps, warmup, tuning_cache=None, n_cells=None, n_check=64, seed=3):
+    """1,048,576 cells, half 9 / 30 and half 53 / 325, 10 outer splitting steps
+    (1 % perturbation, then integration over 1e-5 s) captured in one HIP graph;
+    cells/s = 10 N / t_graph for the plain (static grid) and batched (work
+    queue, autotuned) forms; the first n_check cells are checked against the
+    oracle's composed loop."""
+    from paper_2405_01713_amd import bdfx
+
+    w = W.make_workload("mixed_s9_s53_1m", n_cells)
+    n_outer = w["outer_steps"]
+    out = dict(workload="mixed_s9_s53_1m", n_cells=w["n_cells"], outer_steps=n_outer)
+    y_check = {}
+    for form, sched in (("plain", 0), ("batched", 1)):
+        integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"],
+                                cell_mech=w["cell_mech"], scheduler=sched)
+        tune = integ.autotune(0.0, w["t_out"], cache=tuning_cache) if sched else None
+        y0 = integ.y.clone()
+        g = integ.capture_outer_loop(n_outer, w["t_out"], seed, w["perturb"])
+
+        def run():
+            integ.y.copy_(y0)
+            g.replay()
+
+        import torch
+        ms = _timed_events(run, torch.cuda.current_stream(), steps, warmup)
+        st = integ.cell_stats()
+        y_check[form] = integ.state()[:n_check]
+        per_mech = {}
+        for m in range(len(w["mechs"])):
+            nst = st["nst"][w["cell_mech"] == m]
+            per_mech[f"S{w['mechs'][m]['n_species']}"] = dict(
+                mean_nst=float(nst.mean()), p01_nst=float(np.percentile(nst, 1)),
+                p99_nst=float(np.percentile(nst, 99)))
+        integ.close()
+        log(f"batching {form}: {ms:.1f} ms per graph of {n_outer} outer steps")
+        out[form] = dict(graph_ms=ms, cells_per_s=n_outer * w["n_cells"] / (ms * 1e-3),
+                         tuning=tune, failed_cells=int(np.sum(st["status"] != 0)),
+                         last_outer_step_nst=per_mech)
+    out["speedup_batched_over_plain"] = out["plain"]["graph_ms"] / out["batched"]["graph_ms"]
+    try:
+        from oracle import oracle as O
+        yo = _oracle_outer_loop(O, w, np.arange(n_check), n_outer, seed)
+        for form in ("plain", "batched"):
+            out[form]["vs_oracle"] = _errors(y_check[form], yo, w["rtol"], w["atol"])
+        out["check_cells"] = n_check
+    except Exception as e:
+        out["check_error"] = repr(e)
+    return out
+
+
 def cpu_baseline(w, n_sample):
     from oracle import oracle as O
     idx = np.arange(min(n_sample, w["n_cells"]))
@@ -266,6 +400,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=262144)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the 53-species FP64 vs FP32-LU measurement")
+    ap.add_argument("--extra", default="",
+                    help="comma list of longer measurements: 'batching' (1 M mixed cells, "
+                         "10 outer steps in a HIP graph)")
     ap.add_argument("--tuning-cache", default=None,
                     help="JSON file of autotuned launch shapes (reused when present)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
@@ -296,6 +435,7 @@ def main():
     forms = {}
     for form in args.forms.split(","):
         r = run_form(w, form, args.steps, args.warmup, tuning_cache=args.tuning_cache)
+        log(f"{form}: {r['kernel_ms']:.1f} ms per step")
         st = r["stats"]
         if w["cell_mech"] is None:
             F = algorithmic_flops(st, fms[0])
@@ -314,6 +454,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         c = cpu_baseline(w, args.cpu_sample)
+        log(f"cpu baseline: {c['value']:.0f} cells/s on {c['cores']} threads")
         for form, f in forms.items():
             yg = f["_y"][c["idx"]]
             err = np.abs(yg - c["y"])
@@ -329,6 +470,11 @@ def main():
         f.pop("_y")
 
     adj = None if args.no_adjoint else run_adjoint(args.steps, args.warmup)
+    prec = (None if args.no_precision else
+            run_precision(args.steps, args.warmup, tuning_cache=args.tuning_cache))
+    extra = {}
+    if "batching" in args.extra.split(","):
+        extra["batching"] = run_batching(1, 1, tuning_cache=args.tuning_cache)
     ok = {k: v for k, v in forms.items() if v.get("parity_ok", True) and v["failed_cells"] == 0}
     best = max(ok or forms, key=lambda k: forms[k]["cells_per_s"])
     b = forms[best]
@@ -358,6 +504,8 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
         "adjoint": adj,
+        "precision": prec,
+        **extra,
     }
     print(json.dumps(out))
 
