@@ -36,6 +36,9 @@ namespace bdfx {
 constexpr int kWave = 64;
 constexpr int kQmax = 5;
 constexpr int kMaxS = 64;
+// slot byte of an empty reaction slot: indexes a 1.0 kept after the 64 state
+// entries, so that a rate is a product over all three slots without branches
+constexpr int kEmptySlot = 64;
 constexpr double kUround = 2.220446049250313e-16;
 
 constexpr int kSuccess = 0;
@@ -56,7 +59,7 @@ struct CellStats {
 struct MechDev {
   int32_t S, R;
   int32_t reversible;
-  const int32_t *rx;       // [R][2]: species of the reactant / product slots, one byte each (0xff = empty)
+  const int32_t *rx;       // [R][2]: species of the reactant / product slots, one byte each (kEmptySlot = empty)
   const double *lnA;       // [R]
   const double *EaR;       // [R]
   const double *lnK;       // [R] (reversible only)
@@ -331,7 +334,7 @@ struct Ctl {
 };
 
 struct Lds {
-  double *yb;   // [64] state for gathers (also the right-hand side of a solve)
+  double *yb;   // [64 + 8] state for gathers (also the right-hand side of a solve); yb[kEmptySlot] = 1
   double *fb;   // [64] right-hand-side accumulator
   double *C;    // [Ctl::kSize]
   int *perm;    // [64] pivot row of each elimination step
@@ -342,13 +345,13 @@ struct Lds {
 
 // doubles of LDS per wave for S species, R reactions and factor type size
 __host__ __device__ constexpr int lds_doubles(int S, int R, int lt_bytes) {
-  return 2 * kWave + Ctl::kSize + kWave / 2 + 3 * R + (S * S * lt_bytes + 7) / 8;
+  return 2 * kWave + 8 + Ctl::kSize + kWave / 2 + 3 * R + (S * S * lt_bytes + 7) / 8;
 }
 
 __device__ __forceinline__ Lds carve(double *base, int R) {
   Lds L;
   L.yb = base;
-  L.fb = base + kWave;
+  L.fb = base + kWave + 8;
   L.C = L.fb + kWave;
   L.perm = reinterpret_cast<int *>(L.C + Ctl::kSize);
   L.kk = L.C + Ctl::kSize + kWave / 2;
@@ -370,18 +373,18 @@ __device__ __forceinline__ int slot_species(int word, int s) { return (word >> (
 // an all-empty slot word.  Lane i passes y_i, F_i and gets f_i.
 __device__ __forceinline__ void rhs_reaction(const Lds &L, int r, int2 w) {
   double pf = L.kk[2 * r], pr = L.kk[2 * r + 1];
+  // empty slots read the 1.0 at yb[kEmptySlot]: the six gathers issue together
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
-    const int a = slot_species(w.x, s), b = slot_species(w.y, s);
-    if (a != 0xff) pf *= L.yb[a];
-    if (b != 0xff) pr *= L.yb[b];
+    pf *= L.yb[slot_species(w.x, s)];
+    pr *= L.yb[slot_species(w.y, s)];
   }
   const double q = pf + pr;
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     const int a = slot_species(w.x, s), b = slot_species(w.y, s);
-    if (a != 0xff) atomicAdd(&L.fb[a], -q);
-    if (b != 0xff) atomicAdd(&L.fb[b], q);
+    if (a != kEmptySlot) atomicAdd(&L.fb[a], -q);
+    if (b != kEmptySlot) atomicAdd(&L.fb[b], q);
   }
 }
 
@@ -392,7 +395,7 @@ __device__ __forceinline__ double rhs(const MechDev &m, const Lds &L, int li, do
   L.fb[li] = Fi;
   wave_lds_sync();
   const int R = m.R;
-  const int2 none = make_int2(-1, -1);  // every slot empty
+  const int2 none = make_int2(0x40404040, 0x40404040);  // every slot empty
   for (int r0 = 0; r0 < R; r0 += 2 * kWave) {
     const int ra = r0 + li, rb = ra + kWave;
     const int2 wa = ra < R ? L.rx[ra] : none;
@@ -438,17 +441,17 @@ __device__ __forceinline__ void newton_matrix(LT (&a)[S], const MechDev &m, cons
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const int col = sp[side][c];
-        if (col == 0xff) continue;
+        if (col == kEmptySlot) continue;
         double d = kside;
 #pragma unroll
         for (int o = 0; o < 3; ++o)
-          if (o != c && sp[side][o] != 0xff) d *= L.yb[sp[side][o]];
+          if (o != c) d *= L.yb[sp[side][o]];  // empty slots multiply by 1
         const LT g = static_cast<LT>(gamma * d);
         LT *Mc = M + col * S;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          if (sp[0][i] != 0xff) atomicAdd(Mc + sp[0][i], g);
-          if (sp[1][i] != 0xff) atomicAdd(Mc + sp[1][i], -g);
+          if (sp[0][i] != kEmptySlot) atomicAdd(Mc + sp[0][i], g);
+          if (sp[1][i] != kEmptySlot) atomicAdd(Mc + sp[1][i], -g);
         }
       }
     }
@@ -571,6 +574,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
   const MechDev &m = P.mech;
   const int R = m.R;
   const Lds L = carve(lds, R);
+  if (li == 0) L.yb[kEmptySlot] = 1.0;  // empty reaction slots multiply by 1
   double *const C = L.C;
   const int n = P.n_sp;
   const double inv_n = 1.0 / n;
@@ -986,32 +990,29 @@ __device__ __forceinline__ double adj_scatter(const MechDev &m, const Lds &L, do
     for (int k = 0; k < 3; ++k) {
       a[k] = slot_species(w.x, k);
       b[k] = slot_species(w.y, k);
-      if (a[k] != 0xff) {
-        pf *= L.yb[a[k]];
-        s -= vb[a[k]];
-      }
-      if (b[k] != 0xff) {
-        pr *= L.yb[b[k]];
-        s += vb[b[k]];
-      }
+      // empty slots read yb = 1 and vb = 0 at kEmptySlot
+      pf *= L.yb[a[k]];
+      s -= vb[a[k]];
+      pr *= L.yb[b[k]];
+      s += vb[b[k]];
     }
     pb[r] += scale * (pf + pr) * s;
     if (want_jtv) {
       // d q_r / d y_j for each slot: the side's constant times the other slots
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        if (a[k] != 0xff) {
+        if (a[k] != kEmptySlot) {
           double d = L.kk[2 * r];
 #pragma unroll
           for (int o = 0; o < 3; ++o)
-            if (o != k && a[o] != 0xff) d *= L.yb[a[o]];
+            if (o != k) d *= L.yb[a[o]];
           atomicAdd(&L.fb[a[k]], d * s);
         }
-        if (b[k] != 0xff && m.reversible) {
+        if (b[k] != kEmptySlot && m.reversible) {
           double d = L.kk[2 * r + 1];
 #pragma unroll
           for (int o = 0; o < 3; ++o)
-            if (o != k && b[o] != 0xff) d *= L.yb[b[o]];
+            if (o != k) d *= L.yb[b[o]];
           atomicAdd(&L.fb[b[k]], d * s);
         }
       }
@@ -1043,8 +1044,12 @@ __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int 
   const MechDev &m = P.mech;
   const int R = m.R;
   const Lds L = carve(lds, R);
-  double *vb = reinterpret_cast<double *>(L.fac) + S * S;
-  double *pb = vb + kWave;
+  double *vb = reinterpret_cast<double *>(L.fac) + S * S;  // [64 + 8], vb[kEmptySlot] = 0
+  double *pb = vb + kWave + 8;
+  if (li == 0) {
+    L.yb[kEmptySlot] = 1.0;
+    vb[kEmptySlot] = 0.0;
+  }
   const int n = P.n_sp;
   const bool own = li < n;
   const int stride = P.rec_stride;
@@ -1164,7 +1169,7 @@ __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int 
 }
 
 __host__ __device__ constexpr int lds_doubles_adjoint(int S, int R) {
-  return lds_doubles(S, R, 8) + kWave + R;
+  return lds_doubles(S, R, 8) + kWave + 8 + R;
 }
 
 }  // namespace bdfx

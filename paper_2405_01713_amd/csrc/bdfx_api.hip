@@ -205,14 +205,14 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
         return fail(ctx, BDFX_EINVAL, "reaction %d slot %d: species out of range", r, l);
     }
 
-  // reaction slots, one byte per species (0xff = empty)
+  // reaction slots, one byte per species (bdfx::kEmptySlot = empty)
   std::vector<int32_t> rx(2 * R);
   for (int r = 0; r < R; ++r) {
     uint32_t wr = 0, wp = 0;
     for (int l = 0; l < 3; ++l) {
       const int a = d->reac[r * 3 + l], b = d->prod[r * 3 + l];
-      wr |= static_cast<uint32_t>(a < 0 ? 0xff : a) << (8 * l);
-      wp |= static_cast<uint32_t>(b < 0 ? 0xff : b) << (8 * l);
+      wr |= static_cast<uint32_t>(a < 0 ? bdfx::kEmptySlot : a) << (8 * l);
+      wp |= static_cast<uint32_t>(b < 0 ? bdfx::kEmptySlot : b) << (8 * l);
     }
     rx[2 * r] = static_cast<int32_t>(wr);
     rx[2 * r + 1] = static_cast<int32_t>(wp);

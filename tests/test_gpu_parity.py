@@ -270,3 +270,32 @@ def test_adjoint_matches_oracle(oracle):
     assert np.all(np.abs(lnA_bar - g_lnA) <= 1e-3 * np.abs(g_lnA).max())
     # dL/dy0 per cell: each side follows its own valid step sequence
     assert_adjoint_parity(y0bar, y0bar_o, "adjoint dL/dy0")
+
+
+def test_bdf_function_autograd(oracle):
+    """torch.autograd.Function over the library: loss = sum_cells c . y(t_out);
+    loss.backward() fills dL/dy0 and dL/dlnA from the discrete adjoint, which
+    match the oracle's adjoint (per-cell criterion; lnA summed over cells)."""
+    import torch
+    from paper_2405_01713_amd import bdfx
+    w = W.make_workload("s21_r84_65k_adjoint", 32)
+    m = w["mechs"][0]
+    c = W.loss_weights(21)
+    BDF = bdfx.make_bdf_function()
+    y0 = torch.as_tensor(w["y0"], device="cuda").requires_grad_()
+    lnA = torch.as_tensor(m["lnA"], device="cuda").requires_grad_()
+    y = BDF.apply(y0, lnA, m, w["T"], w["t_out"], w["rtol"], w["atol"], 3000)
+    loss = (y * torch.as_tensor(c, device="cuda")).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    g_y0, g_lnA = y0.grad.cpu().numpy(), lnA.grad.cpu().numpy()
+    go_lnA = np.zeros(84)
+    go_y0 = np.zeros((32, 21))
+    for k in range(32):
+        kf, kr = oracle.rates(m, w["T"][k])
+        _, _, rec = oracle.integrate_record(m, w["y0"][k], 0.0, w["t_out"], w["rtol"], w["atol"],
+                                            T=w["T"][k])
+        go_y0[k], pb = oracle.adjoint(m, kf, kr, w["y0"][k], rec, rec["y"], c)
+        go_lnA += pb
+    assert_adjoint_parity(g_y0, go_y0, "autograd dL/dy0")
+    assert np.all(np.abs(g_lnA - go_lnA) <= 1e-3 * np.abs(go_lnA).max())
