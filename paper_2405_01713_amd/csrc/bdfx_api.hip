@@ -661,7 +661,7 @@ int bdfx_set_tuning(bdfx_ctx ctx, const bdfx_tuning *t, int32_t n) {
 int bdfx_stats_summary(bdfx_ctx ctx, bdfx_summary *out) {
   if (!ctx || !out) return BDFX_EINVAL;
   if (!ctx->bound) return fail(ctx, BDFX_EORDER, "nothing bound");
-  if (!ctx->stats) return fail(ctx, BDFX_EINVAL, "no stats buffer bound");
+  if (!ctx->stats && ctx->N > 0) return fail(ctx, BDFX_EINVAL, "no stats buffer bound");
   HIPCHK(ctx, hipSetDevice(ctx->device));
   std::vector<bdfx_cell_stats> st(ctx->N);
   if (ctx->N)

@@ -299,3 +299,58 @@ def test_bdf_function_autograd(oracle):
         go_lnA += pb
     assert_adjoint_parity(g_y0, go_y0, "autograd dL/dy0")
     assert np.all(np.abs(g_lnA - go_lnA) <= 1e-3 * np.abs(go_lnA).max())
+
+
+def _three_body_mechanism():
+    """Six species with weights (1, 1, 2, 3, 4, 2) and mass-conserving
+    reactions that use three reactant slots and repeated species:
+    2A + B <=> D, 2A <=> C, A + B + C <=> E, C <=> F, D + A <=> E, 2F <=> E."""
+    reac = [[0, 0, 1], [0, 0, -1], [0, 1, 2], [2, -1, -1], [3, 0, -1], [5, 5, -1]]
+    prod = [[3, -1, -1], [2, -1, -1], [4, -1, -1], [5, -1, -1], [4, -1, -1], [4, -1, -1]]
+    return dict(n_species=6, n_reactions=6, reac=np.array(reac, dtype=np.int32),
+                prod=np.array(prod, dtype=np.int32),
+                lnA=np.log([3e3, 5e4, 2e5, 7e2, 1e4, 3e5]), EaR=np.zeros(6),
+                lnK=np.log([20.0, 0.5, 3.0, 0.2, 8.0, 1.5]),
+                w=np.array([1.0, 1.0, 2.0, 3.0, 4.0, 2.0]))
+
+
+def test_three_body_and_repeated_species(oracle, parity):
+    m = _three_body_mechanism()
+    c = W.cell_states(m, 200, seed=21)
+    w = dict(mechs=[m], y0=c["y0"], T=c["T"], rtol=1e-6, atol=1e-10, t_out=1e-3)
+    y, st = _gpu(w)
+    yo, sto = _oracle(oracle, w)
+    assert np.all(st["status"] == 0) and np.all(sto["status"] == 0)
+    parity(y, yo, w, "three-body")
+    # sum_i w_i y_i is conserved by every reaction
+    inv0, inv1 = c["y0"] @ m["w"], y[:, :6] @ m["w"]
+    assert np.abs(inv1 - inv0).max() <= 1e-12 * np.abs(inv0).max()
+
+
+def test_largest_size_all_lanes(oracle, parity):
+    """64 species: every lane of the wave holds a species."""
+    m = W.synthetic_mechanism(64, 150, 5)
+    c = W.cell_states(m, 96, seed=8)
+    w = dict(mechs=[m], y0=c["y0"], T=c["T"], rtol=1e-6, atol=1e-10, t_out=1e-5)
+    y, st = _gpu(w, scheduler=1)
+    yo, sto = _oracle(oracle, w)
+    assert np.all(st["status"] == 0)
+    parity(y, yo, w, "S=64")
+
+
+def test_empty_and_single_cell_batches(oracle, parity):
+    import torch
+    from paper_2405_01713_amd import bdfx
+    w = W.make_workload("s21_r84_262k", 1)
+    m = w["mechs"][0]
+    for sched in (0, 1):
+        empty = bdfx.Integrator([m], np.zeros((0, 21)), w["rtol"], w["atol"], scheduler=sched)
+        empty.integrate(0.0, w["t_out"])
+        torch.cuda.synchronize()
+        assert empty.state().shape == (0, 21)
+        assert empty.summary()["n_cells"] == 0
+        empty.close()
+        y, st = _gpu(w, scheduler=sched)
+        yo, sto = _oracle(oracle, w)
+        assert st["status"][0] == 0
+        parity(y, yo, w, f"single cell, scheduler {sched}")
