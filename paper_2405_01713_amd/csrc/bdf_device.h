@@ -339,24 +339,34 @@ struct Lds {
   double *C;    // [Ctl::kSize]
   int *perm;    // [64] pivot row of each elimination step
   double *kk;   // [2R]: k_f at 2r, -k_r at 2r+1
-  int2 *rx;     // [R]: reactant / product slot words of the mechanism
+  const int2 *rx;  // [R]: reactant / product slot words (an LDS copy, or the mechanism's table)
   void *fac;    // [S][S] inverse Newton matrix (LT), column-major: (r, c) at c*S + r
 };
 
-// doubles of LDS per wave for S species, R reactions and factor type size
-__host__ __device__ constexpr int lds_doubles(int S, int R, int lt_bytes) {
-  return 2 * kWave + 8 + Ctl::kSize + kWave / 2 + 3 * R + (S * S * lt_bytes + 7) / 8;
+// doubles of LDS per wave for S species, R reactions, factor type size and
+// whether the slot words are copied to LDS
+__host__ __device__ constexpr int lds_doubles(int S, int R, int lt_bytes, bool rx_lds = true) {
+  return 2 * kWave + 8 + Ctl::kSize + kWave / 2 + (rx_lds ? 3 : 2) * R + (S * S * lt_bytes + 7) / 8;
 }
 
-__device__ __forceinline__ Lds carve(double *base, int R) {
+// RXL: the reaction slot words live in LDS (copied per cell) or are read from
+// the mechanism's table in global memory (saves R words of LDS per wave where
+// LDS limits the resident waves).
+template <bool RXL>
+__device__ __forceinline__ Lds carve(double *base, int R, const int32_t *mech_rx) {
   Lds L;
   L.yb = base;
   L.fb = base + kWave + 8;
   L.C = L.fb + kWave;
   L.perm = reinterpret_cast<int *>(L.C + Ctl::kSize);
   L.kk = L.C + Ctl::kSize + kWave / 2;
-  L.rx = reinterpret_cast<int2 *>(L.kk + 2 * R);
-  L.fac = L.kk + 3 * R;
+  if constexpr (RXL) {
+    L.rx = reinterpret_cast<const int2 *>(L.kk + 2 * R);
+    L.fac = L.kk + 3 * R;
+  } else {
+    L.rx = reinterpret_cast<const int2 *>(mech_rx);
+    L.fac = L.kk + 2 * R;
+  }
   return L;
 }
 
@@ -569,11 +579,11 @@ __device__ __forceinline__ double wrms2(double v, double w, double inv_n) {
   return uni(wsum(t * t) * inv_n);
 }
 
-template <int S, typename LT>
+template <int S, typename LT, bool RXL>
 __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, int li, double *lds) {
   const MechDev &m = P.mech;
   const int R = m.R;
-  const Lds L = carve(lds, R);
+  const Lds L = carve<RXL>(lds, R, m.rx);
   if (li == 0) L.yb[kEmptySlot] = 1.0;  // empty reaction slots multiply by 1
   double *const C = L.C;
   const int n = P.n_sp;
@@ -592,7 +602,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
     if (P.kscale) kf *= P.kscale[cell * P.ldk + r];
     L.kk[2 * r] = kf;
     L.kk[2 * r + 1] = m.reversible ? -(kf * exp(-m.lnK[r])) : -0.0;
-    L.rx[r] = reinterpret_cast<const int2 *>(m.rx)[r];
+    if constexpr (RXL) const_cast<int2 *>(L.rx)[r] = reinterpret_cast<const int2 *>(m.rx)[r];
   }
 
   const double yin = own ? P.y[cell * P.ldy + li] : 0.0;
@@ -1043,7 +1053,7 @@ template <int S>
 __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int li, double *lds) {
   const MechDev &m = P.mech;
   const int R = m.R;
-  const Lds L = carve(lds, R);
+  const Lds L = carve<true>(lds, R, m.rx);
   double *vb = reinterpret_cast<double *>(L.fac) + S * S;  // [64 + 8], vb[kEmptySlot] = 0
   double *pb = vb + kWave + 8;
   if (li == 0) {
@@ -1063,7 +1073,7 @@ __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int 
     if (P.kscale) kf *= P.kscale[cell * P.ldk + r];
     L.kk[2 * r] = kf;
     L.kk[2 * r + 1] = m.reversible ? -(kf * exp(-m.lnK[r])) : -0.0;
-    L.rx[r] = reinterpret_cast<const int2 *>(m.rx)[r];
+    const_cast<int2 *>(L.rx)[r] = reinterpret_cast<const int2 *>(m.rx)[r];
     pb[r] = 0.0;
   }
   const double *rec = P.rec + static_cast<int64_t>(cell) * P.rec_cap * stride;

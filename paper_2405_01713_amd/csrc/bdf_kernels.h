@@ -13,8 +13,8 @@ namespace bdfx {
 
 // MINW: minimum resident waves per SIMD the register allocation must allow
 // (1 = compiler's choice; 3 = at most 168 VGPRs, 4 = at most 128, spilling
-// if needed).
-template <int S, typename LT, int MINW>
+// if needed).  RXL: reaction slot words copied to LDS (see carve).
+template <int S, typename LT, int MINW, bool RXL>
 __global__ void __launch_bounds__(256, MINW) k_integrate(Params P) {
   extern __shared__ double smem[];
   const int wib = threadIdx.x / kWave;
@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(256, MINW) k_integrate(Params P) {
     if (next >= P.n_list) break;
     const int64_t cell = P.list ? P.list[next] : next;
     ++next;
-    integrate_cell<S, LT>(P, cell, li, lds);
+    integrate_cell<S, LT, RXL>(P, cell, li, lds);
   }
 }
 
@@ -56,20 +56,28 @@ struct LaunchCfg {
   size_t lds_bytes;
 };
 
+// the integrator kernel for (LU precision, register budget, slot words in LDS)
 template <int S>
-hipError_t launch_integrate(const Params &P, bool fp32, int minw, const LaunchCfg &c,
+const void *integrate_kernel(bool fp32, int minw, bool rx_lds) {
+  using F = const void *;
+  const int w = minw >= 4 ? 2 : minw >= 3 ? 1 : 0;
+  static const F tab[2][3][2] = {
+      {{F(&k_integrate<S, double, 1, false>), F(&k_integrate<S, double, 1, true>)},
+       {F(&k_integrate<S, double, 3, false>), F(&k_integrate<S, double, 3, true>)},
+       {F(&k_integrate<S, double, 4, false>), F(&k_integrate<S, double, 4, true>)}},
+      {{F(&k_integrate<S, float, 1, false>), F(&k_integrate<S, float, 1, true>)},
+       {F(&k_integrate<S, float, 3, false>), F(&k_integrate<S, float, 3, true>)},
+       {F(&k_integrate<S, float, 4, false>), F(&k_integrate<S, float, 4, true>)}}};
+  return tab[fp32 ? 1 : 0][w][rx_lds ? 1 : 0];
+}
+
+template <int S>
+hipError_t launch_integrate(const Params &P, bool fp32, int minw, bool rx_lds, const LaunchCfg &c,
                             hipStream_t s) {
-  const dim3 g(c.grid), b(c.block);
-  if (fp32) {
-    if (minw >= 4) hipLaunchKernelGGL((k_integrate<S, float, 4>), g, b, c.lds_bytes, s, P);
-    else if (minw >= 3) hipLaunchKernelGGL((k_integrate<S, float, 3>), g, b, c.lds_bytes, s, P);
-    else hipLaunchKernelGGL((k_integrate<S, float, 1>), g, b, c.lds_bytes, s, P);
-  } else {
-    if (minw >= 4) hipLaunchKernelGGL((k_integrate<S, double, 4>), g, b, c.lds_bytes, s, P);
-    else if (minw >= 3) hipLaunchKernelGGL((k_integrate<S, double, 3>), g, b, c.lds_bytes, s, P);
-    else hipLaunchKernelGGL((k_integrate<S, double, 1>), g, b, c.lds_bytes, s, P);
-  }
-  return hipGetLastError();
+  Params arg = P;
+  void *args[] = {&arg};
+  return hipLaunchKernel(integrate_kernel<S>(fp32, minw, rx_lds), dim3(c.grid), dim3(c.block), args,
+                         c.lds_bytes, s);
 }
 
 template <int S>
@@ -79,37 +87,31 @@ hipError_t launch_adjoint(const Params &P, const LaunchCfg &c, hipStream_t s) {
 }
 
 template <int S>
-hipError_t occupancy_integrate(bool fp32, int minw, int block, size_t lds_bytes,
+hipError_t occupancy_integrate(bool fp32, int minw, bool rx_lds, int block, size_t lds_bytes,
                                int *blocks_per_cu) {
-  const void *f;
-  if (fp32)
-    f = minw >= 4   ? reinterpret_cast<const void *>(&k_integrate<S, float, 4>)
-        : minw >= 3 ? reinterpret_cast<const void *>(&k_integrate<S, float, 3>)
-                    : reinterpret_cast<const void *>(&k_integrate<S, float, 1>);
-  else
-    f = minw >= 4   ? reinterpret_cast<const void *>(&k_integrate<S, double, 4>)
-        : minw >= 3 ? reinterpret_cast<const void *>(&k_integrate<S, double, 3>)
-                    : reinterpret_cast<const void *>(&k_integrate<S, double, 1>);
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds_bytes);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      blocks_per_cu, integrate_kernel<S>(fp32, minw, rx_lds), block, lds_bytes);
 }
 
 }  // namespace bdfx
 
 // One translation unit per species size (compiled in parallel).
 #define BDFX_DEFINE_SIZE(S)                                                                      \
-  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw,                        \
+  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, bool rx_lds,           \
                               const bdfx::LaunchCfg &c, hipStream_t s) {                         \
-    return bdfx::launch_integrate<S>(P, fp32, minw, c, s);                                       \
+    return bdfx::launch_integrate<S>(P, fp32, minw, rx_lds, c, s);                               \
   }                                                                                              \
-  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int block, size_t lds, int *out) {         \
-    return bdfx::occupancy_integrate<S>(fp32, minw, block, lds, out);                            \
+  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, bool rx_lds, int block, size_t lds,        \
+                                 int *out) {                                                     \
+    return bdfx::occupancy_integrate<S>(fp32, minw, rx_lds, block, lds, out);                    \
   }                                                                                              \
   hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s) { \
     return bdfx::launch_adjoint<S>(P, c, s);                                                     \
   }
 
 #define BDFX_DECLARE_SIZE(S)                                                                     \
-  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw,                        \
+  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, bool rx_lds,           \
                               const bdfx::LaunchCfg &c, hipStream_t s);                          \
-  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int block, size_t lds, int *out);          \
+  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, bool rx_lds, int block, size_t lds,        \
+                                 int *out);                                                      \
   hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s);

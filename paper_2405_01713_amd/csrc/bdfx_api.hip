@@ -46,8 +46,8 @@ thread_local std::string g_create_error;
 
 struct SizeEntry {
   int S;
-  hipError_t (*launch)(const bdfx::Params &, bool, int, const bdfx::LaunchCfg &, hipStream_t);
-  hipError_t (*occupancy)(bool, int, int, size_t, int *);
+  hipError_t (*launch)(const bdfx::Params &, bool, int, bool, const bdfx::LaunchCfg &, hipStream_t);
+  hipError_t (*occupancy)(bool, int, bool, int, size_t, int *);
   hipError_t (*adjoint)(const bdfx::Params &, const bdfx::LaunchCfg &, hipStream_t);
 };
 
@@ -93,6 +93,7 @@ struct Bin {
   // launch shape: from the options, or chosen by bdfx_autotune()
   int32_t waves_per_simd = 0, waves_per_block = 1, queue_chunk = 1;
   bool tuned = false;
+  bool rx_lds = true;  // reaction slot words copied to LDS (else read from global memory)
 };
 
 struct bdfx_ctx_s {
@@ -431,7 +432,7 @@ int bdfx_bind(bdfx_ctx ctx, void *d_ws, size_t ws_bytes, double *d_y, int32_t ld
 // integrate
 // ---------------------------------------------------------------------------
 
-// Kernel, LDS size and grid of every bin (called by bdfx_bind).
+// Kernel, LDS size and grid of one bin from its launch shape.
 static int configure_bin(bdfx_ctx ctx, Bin &b) {
   const bool fp32 = ctx->opt.lu_precision == 32;
   const bool queue = ctx->opt.scheduler == BDFX_SCHED_QUEUE;
@@ -439,16 +440,27 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
   b.se = size_for(m->S);
   if (!b.se) return fail(ctx, BDFX_EUNSUPPORTED, "no kernel for %d species", m->S);
   const int waves = std::max(b.waves_per_block, 1);
-  b.lds_doubles = static_cast<int32_t>(align_up(bdfx::lds_doubles(b.se->S, m->R, fp32 ? 4 : 8), 2));
   b.cfg.block = bdfx::kWave * waves;
-  b.cfg.lds_bytes = static_cast<size_t>(waves) * b.lds_doubles * 8;  // one wave per cell
+  // slot words in LDS unless leaving them in global memory lets more waves
+  // reside (LDS-limited sizes)
+  int occ[2] = {0, 0};
+  size_t lds[2];
+  for (int k = 0; k < 2; ++k) {
+    const int32_t d = static_cast<int32_t>(
+        align_up(bdfx::lds_doubles(b.se->S, m->R, fp32 ? 4 : 8, k == 1), 2));
+    lds[k] = static_cast<size_t>(waves) * d * 8;  // one wave per cell
+    if (lds[k] <= 65536)
+      HIPCHK(ctx, b.se->occupancy(fp32, b.waves_per_simd, k == 1, b.cfg.block, lds[k], &occ[k]));
+  }
+  b.rx_lds = !(occ[0] > occ[1]);
+  const int k = b.rx_lds ? 1 : 0;
+  b.cfg.lds_bytes = lds[k];
+  b.lds_doubles = static_cast<int32_t>(lds[k] / 8 / waves);
   if (b.cfg.lds_bytes > 65536)
     return fail(ctx, BDFX_EUNSUPPORTED, "LDS per block %zu exceeds 64 KiB", b.cfg.lds_bytes);
   const int64_t need = (b.count + waves - 1) / waves;
   if (queue) {
-    int occ = 0;
-    HIPCHK(ctx, b.se->occupancy(fp32, b.waves_per_simd, b.cfg.block, b.cfg.lds_bytes, &occ));
-    const int per_cu = ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : std::max(occ, 1);
+    const int per_cu = ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : std::max(occ[k], 1);
     b.cfg.grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(per_cu) * ctx->n_cu, need));
   } else {
     if (need > INT32_MAX) return fail(ctx, BDFX_EUNSUPPORTED, "too many cells for one grid");
@@ -522,7 +534,7 @@ int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out) {
     bdfx::Params P = make_params(ctx, b, t0, t_out);
     P.use_queue = queue ? 1 : 0;
     P.lds_doubles = b.lds_doubles;
-    HIPCHK(ctx, b.se->launch(P, fp32, b.waves_per_simd, b.cfg, ctx->stream));
+    HIPCHK(ctx, b.se->launch(P, fp32, b.waves_per_simd, b.rx_lds, b.cfg, ctx->stream));
   }
   ctx->last_t0 = t0;
   ctx->last_tout = t_out;
@@ -594,7 +606,8 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
                                       ctx->stream);
             if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
             if (e == hipSuccess && queue) e = bdfx_launch_fill_u32(qctr, 64, 0u, ctx->stream);
-            if (e == hipSuccess) e = trial.se->launch(P, fp32, wps, trial.cfg, ctx->stream);
+            if (e == hipSuccess)
+              e = trial.se->launch(P, fp32, wps, trial.rx_lds, trial.cfg, ctx->stream);
             if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
             if (e == hipSuccess)
               e = bdfx_launch_copy_rows(ctx->y, ctx->ldy, P.list, trial.count, m->S, save, true,
