@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 from paper_2405_01713_amd import workloads as W  # noqa: E402
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -117,13 +118,18 @@ def flops_model(mech: dict, forcing: bool = False) -> dict:
     q = 4  # typical order
     step_vec = (q * (q + 1) // 2 + 2 * (q + 1) + 6) * S
     rates0 = 6 * R
-    return dict(rhs=rhs, setup=jac + lu, nni=solve + newton_vec, nst=step_vec, cell=rates0)
+    return dict(rhs=rhs, setup=jac + lu, nni=solve + newton_vec, nst=step_vec, cell=rates0,
+                lu=lu, solve=solve)
 
 
-def algorithmic_flops(stats: np.ndarray, fm: dict) -> float:
-    return float(stats["nfe"].sum() * fm["rhs"] + stats["nsetups"].sum() * fm["setup"]
-                 + stats["nni"].sum() * fm["nni"] + stats["nst"].sum() * fm["nst"]
-                 + stats.size * fm["cell"])
+def algorithmic_flops(stats: np.ndarray, fm: dict, fp32_lu: bool = False) -> tuple:
+    """(FP64 flops, FP32 flops) of a launch; with the FP32 Newton-matrix
+    inverse the factorisation and the solves are FP32."""
+    total = float(stats["nfe"].sum() * fm["rhs"] + stats["nsetups"].sum() * fm["setup"]
+                  + stats["nni"].sum() * fm["nni"] + stats["nst"].sum() * fm["nst"]
+                  + stats.size * fm["cell"])
+    f32 = float(stats["nsetups"].sum() * fm["lu"] + stats["nni"].sum() * fm["solve"]) if fp32_lu else 0.0
+    return total - f32, f32
 
 
 def run_form(w, form, steps, warmup, opts_extra=None, tuning_cache=None):
@@ -437,14 +443,22 @@ def main():
         r = run_form(w, form, args.steps, args.warmup, tuning_cache=args.tuning_cache)
         log(f"{form}: {r['kernel_ms']:.1f} ms per step")
         st = r["stats"]
+        f32lu = form == "batched_fp32lu"
         if w["cell_mech"] is None:
-            F = algorithmic_flops(st, fms[0])
+            F64, F32 = algorithmic_flops(st, fms[0], f32lu)
         else:
-            F = sum(algorithmic_flops(st[w["cell_mech"] == k], fms[k]) for k in range(len(fms)))
+            parts = [algorithmic_flops(st[w["cell_mech"] == k], fms[k], f32lu) for k in range(len(fms))]
+            F64, F32 = sum(p[0] for p in parts), sum(p[1] for p in parts)
+        F = F64 + F32
+        t_s = r["kernel_ms"] * 1e-3
         forms[form] = dict(kernel_ms=r["kernel_ms"], kernel_ms_min=r["kernel_ms_min"],
                            wall_ms_per_step=r["wall_ms_per_step"],
                            cells_per_s=w["n_cells"] / (r["kernel_ms"] * 1e-3),
-                           tflops=F / (r["kernel_ms"] * 1e-3) / 1e12,
+                           tflops=F / t_s / 1e12,
+                           # FP32 flops weighted by the FP64 : FP32 vector peak ratio
+                           fp64_equiv_tflops=(F64 + F32 * FP64_VECTOR_PEAK_TFLOPS
+                                              / FP32_VECTOR_PEAK_TFLOPS) / t_s / 1e12,
+                           fp64_flops=F64, fp32_flops=F32,
                            failed_cells=int(np.sum(st["status"] != 0)),
                            mean_nst=float(st["nst"].mean()), mean_nfe=float(st["nfe"].mean()),
                            mean_nsetups=float(st["nsetups"].mean()), alg_flops=F,
@@ -478,8 +492,10 @@ def main():
     ok = {k: v for k, v in forms.items() if v.get("parity_ok", True) and v["failed_cells"] == 0}
     best = max(ok or forms, key=lambda k: forms[k]["cells_per_s"])
     b = forms[best]
-    roof = {"bound": "alu", "achieved": b["tflops"], "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": b["tflops"] / FP64_VECTOR_PEAK_TFLOPS,
+    # achieved: algorithmic flops per second, FP32 flops (FP32 inverse form)
+    # counted at the FP64 : FP32 peak ratio, so that frac = F64 / t / P64 + F32 / t / P32
+    roof = {"bound": "alu", "achieved": b["fp64_equiv_tflops"], "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": b["fp64_equiv_tflops"] / FP64_VECTOR_PEAK_TFLOPS,
             "traffic": stored_traffic(args.workload, best),
             "kernel": "bdfx::k_integrate", "flops_per_launch": b["alg_flops"],
             "alg_bytes_per_launch": w["n_cells"] * (16 * max(m["n_species"] for m in w["mechs"]) + 56)}
