@@ -99,6 +99,8 @@ typedef struct {
   int32_t waves_per_simd;  /* register budget of the integrator kernel: 0 = compiler's
                               choice, 3 or 4 = code built for that many resident waves
                               per SIMD (at most 168 / 128 VGPRs, spilling if needed) */
+  int32_t cells_per_wave;  /* 0 or 1; 2 = each half-wave integrates its own cell
+                              (mechanisms of at most 32 species) */
 } bdfx_options;
 
 /* Per-cell statistics written by bdfx_integrate() (48 bytes, [N]). */
@@ -202,12 +204,13 @@ typedef struct {
   int32_t queue_chunk;     /* cells per work-queue pop, >= 1 */
   int64_t sample_cells;    /* bdfx_autotune(): cells timed */
   float ms;                /* bdfx_autotune(): time of the fastest shape on the sample */
-  float reserved;
+  int32_t cells_per_wave;  /* 1, or 2 for mechanisms of at most 32 species */
 } bdfx_tuning;
 
 /* Autotuner: for every mechanism, times each candidate launch shape
- * (waves_per_simd in {0, 3, 4} x waves_per_block in {1, 2, 4} x queue_chunk in
- * {1, 4} for the queue scheduler) integrating the first min(sample_cells,
+ * (cells_per_wave in {1, 2} (2 only up to 32 species) x waves_per_simd in
+ * {0, 3, 4} x waves_per_block in {1, 2, 4} x queue_chunk in {1, 4} for the
+ * queue scheduler) integrating the first min(sample_cells,
  * 16384) cells of that mechanism over [t0, t_out] with HIP events, and keeps
  * the fastest; sample_cells <= 0 means 16384.  The sampled states are saved
  * in the workspace and restored after every trial; their d_status / d_stats

@@ -43,7 +43,7 @@ class Options(C.Structure):
                 ("lu_precision", C.c_int32), ("scheduler", C.c_int32),
                 ("record_steps", C.c_int32), ("waves_per_block", C.c_int32),
                 ("blocks_per_cu", C.c_int32), ("queue_chunk", C.c_int32),
-                ("waves_per_simd", C.c_int32)]
+                ("waves_per_simd", C.c_int32), ("cells_per_wave", C.c_int32)]
 
 
 class Summary(C.Structure):
@@ -56,7 +56,7 @@ class Summary(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("mech", C.c_int32), ("waves_per_simd", C.c_int32),
                 ("waves_per_block", C.c_int32), ("queue_chunk", C.c_int32),
-                ("sample_cells", C.c_int64), ("ms", C.c_float), ("reserved", C.c_float)]
+                ("sample_cells", C.c_int64), ("ms", C.c_float), ("cells_per_wave", C.c_int32)]
 
 
 STATS_DTYPE = np.dtype([("status", np.int32), ("nst", np.int32), ("nfe", np.int32),
@@ -162,12 +162,12 @@ def bdfx_mech_destroy(mech):
 
 def make_options(rtol, atol, max_order=5, max_steps=5000, lu_precision=64,
                  scheduler=BDFX_SCHED_STATIC, record_steps=0, waves_per_block=0,
-                 blocks_per_cu=0, queue_chunk=0, waves_per_simd=0):
+                 blocks_per_cu=0, queue_chunk=0, waves_per_simd=0, cells_per_wave=0):
     atol_arr = np.ascontiguousarray(np.atleast_1d(np.asarray(atol, dtype=np.float64)))
     o = Options(float(rtol), atol_arr.ctypes.data_as(C.c_void_p), int(atol_arr.size),
                 int(max_order), int(max_steps), int(lu_precision), int(scheduler),
                 int(record_steps), int(waves_per_block), int(blocks_per_cu), int(queue_chunk),
-                int(waves_per_simd))
+                int(waves_per_simd), int(cells_per_wave))
     o._keep = atol_arr
     return o
 
@@ -209,7 +209,8 @@ def bdfx_adjoint(ctx, ybar_ptr, y0bar_ptr, lnA_bar_ptr):
     _check(lib().bdfx_adjoint(ctx, v(ybar_ptr), v(y0bar_ptr), v(lnA_bar_ptr)), ctx)
 
 
-_TUNING_KEYS = ("mech", "waves_per_simd", "waves_per_block", "queue_chunk", "sample_cells", "ms")
+_TUNING_KEYS = ("mech", "waves_per_simd", "waves_per_block", "queue_chunk", "cells_per_wave",
+                "sample_cells", "ms")
 
 
 def bdfx_autotune(ctx, n_mech: int, t0: float, t_out: float, sample_cells: int = 0) -> list:
@@ -221,8 +222,8 @@ def bdfx_autotune(ctx, n_mech: int, t0: float, t_out: float, sample_cells: int =
 def bdfx_set_tuning(ctx, tunings: list):
     arr = (Tuning * max(len(tunings), 1))()
     for i, t in enumerate(tunings):
-        for k in ("mech", "waves_per_simd", "waves_per_block", "queue_chunk"):
-            setattr(arr[i], k, int(t[k]))
+        for k in ("mech", "waves_per_simd", "waves_per_block", "queue_chunk", "cells_per_wave"):
+            setattr(arr[i], k, int(t.get(k, 1) if k == "cells_per_wave" else t[k]))
     _check(lib().bdfx_set_tuning(ctx, arr, len(tunings)), ctx)
 
 

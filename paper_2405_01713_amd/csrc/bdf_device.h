@@ -208,6 +208,107 @@ __device__ __forceinline__ int wfirst(bool pred) {
 
 __device__ __forceinline__ bool wany(bool pred) { return __ballot(pred) != 0ull; }
 
+// The lanes that integrate one cell: the whole wave (G = 1) or one half-wave
+// (G = 2, two cells per wave for S <= 32).  Reductions, broadcasts and
+// "uniform" values are per group: for G = 1 they are wave-uniform (scalar
+// registers, scalar branches); for G = 2 they are uniform within each half
+// and the two halves follow their own control flow under the exec mask.  The
+// reductions run over 16-lane rows and then combine rows 0+1 (and 2+3), so a
+// half-wave sum of S <= 32 species uses the same operations as the full-wave
+// one, whose rows 2 and 3 only add zeros.
+template <int G>
+struct Grp {
+  static_assert(G == 1 || G == 2, "one or two cells per wave");
+  static constexpr int kLanes = kWave / G;
+  int lane;  // lane within the group (species index)
+  int grp;   // group index within the wave
+  __device__ explicit Grp(int li) : lane(li % kLanes), grp(li / kLanes) {}
+
+  __device__ double uni(double v) const {
+    if constexpr (G == 1) return bdfx::uni(v);
+    else return v;
+  }
+  __device__ int uni(int v) const {
+    if constexpr (G == 1) return bdfx::uni(v);
+    else return v;
+  }
+  // the value of lane 0 of the group
+  __device__ int from_lane0(int v) const {
+    if constexpr (G == 1) return bdfx::uni(v);
+    else return grp ? __builtin_amdgcn_readlane(v, 32) : __builtin_amdgcn_readlane(v, 0);
+  }
+  // the value of the group's lane p (p uniform within the group)
+  template <typename T>
+  __device__ T bcast(T v, int p) const {
+    if constexpr (G == 1) {
+      return lane_bcast(v, p);
+    } else {
+      const int p0 = __builtin_amdgcn_readlane(p, 0), p1 = __builtin_amdgcn_readlane(p, 32);
+      const T a = lane_bcast(v, p0), b = lane_bcast(v, 32 + p1);
+      return grp ? b : a;
+    }
+  }
+  // group-uniform result from the group's last lane
+  template <typename T>
+  __device__ T last(T v) const {
+    if constexpr (G == 1) {
+      return lane_bcast(v, 63);
+    } else {
+      const T a = lane_bcast(v, 31), b = lane_bcast(v, 63);
+      return grp ? b : a;
+    }
+  }
+  __device__ double sum(double v) const {
+    v += dpp<kQuadXor1>(v);
+    v += dpp<kQuadXor2>(v);
+    v += dpp<kHalfMirror>(v);
+    v += dpp<kMirror>(v);
+    v += dpp<kBcast15, 0xa>(v);
+    if constexpr (G == 1) v += dpp<kBcast31, 0xc>(v);
+    return last(v);
+  }
+  // max of non-negative values (masked rows read 0)
+  __device__ double max(double v) const {
+    v = fmax(v, dpp<kQuadXor1>(v));
+    v = fmax(v, dpp<kQuadXor2>(v));
+    v = fmax(v, dpp<kHalfMirror>(v));
+    v = fmax(v, dpp<kMirror>(v));
+    v = fmax(v, dpp<kBcast15, 0xa>(v));
+    if constexpr (G == 1) v = fmax(v, dpp<kBcast31, 0xc>(v));
+    return last(v);
+  }
+  __device__ uint32_t max_u32(uint32_t v) const {
+    auto step = [](uint32_t a, uint32_t b) { return a > b ? a : b; };
+    v = step(v, __builtin_amdgcn_update_dpp(0u, v, kQuadXor1, 0xf, 0xf, false));
+    v = step(v, __builtin_amdgcn_update_dpp(0u, v, kQuadXor2, 0xf, 0xf, false));
+    v = step(v, __builtin_amdgcn_update_dpp(0u, v, kHalfMirror, 0xf, 0xf, false));
+    v = step(v, __builtin_amdgcn_update_dpp(0u, v, kMirror, 0xf, 0xf, false));
+    v = step(v, __builtin_amdgcn_update_dpp(0u, v, kBcast15, 0xa, 0xf, false));
+    if constexpr (G == 1) v = step(v, __builtin_amdgcn_update_dpp(0u, v, kBcast31, 0xc, 0xf, false));
+    if constexpr (G == 1) {
+      return __builtin_amdgcn_readlane(v, 63);
+    } else {
+      const uint32_t a = __builtin_amdgcn_readlane(v, 31), b = __builtin_amdgcn_readlane(v, 63);
+      return grp ? b : a;
+    }
+  }
+  // lowest lane of the group whose predicate holds (-1 if none)
+  __device__ int first(bool pred) const {
+    const uint64_t b = __ballot(pred);
+    if constexpr (G == 1) {
+      return bdfx::uni(static_cast<int>(__ffsll(static_cast<long long>(b))) - 1);
+    } else {
+      const uint32_t h = grp ? static_cast<uint32_t>(b >> 32) : static_cast<uint32_t>(b);
+      return h ? __ffs(static_cast<int>(h)) - 1 : -1;
+    }
+  }
+  __device__ bool any(bool pred) const {
+    const uint64_t b = __ballot(pred);
+    if constexpr (G == 1) return b != 0ull;
+    else return (grp ? (b >> 32) : (b & 0xffffffffull)) != 0ull;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Nordsieck array operations (z_j = h^j y^(j) / j!)
 // ---------------------------------------------------------------------------
@@ -398,23 +499,24 @@ __device__ __forceinline__ void rhs_reaction(const Lds &L, int r, int2 w) {
   }
 }
 
-__device__ __forceinline__ double rhs(const MechDev &m, const Lds &L, int li, double yi,
+template <int G>
+__device__ __forceinline__ double rhs(const MechDev &m, const Lds &L, const Grp<G> &W, double yi,
                                       double Fi) {
   wave_lds_sync();
-  L.yb[li] = yi;
-  L.fb[li] = Fi;
+  L.yb[W.lane] = yi;
+  L.fb[W.lane] = Fi;
   wave_lds_sync();
   const int R = m.R;
   const int2 none = make_int2(0x40404040, 0x40404040);  // every slot empty
-  for (int r0 = 0; r0 < R; r0 += 2 * kWave) {
-    const int ra = r0 + li, rb = ra + kWave;
+  for (int r0 = 0; r0 < R; r0 += 2 * W.kLanes) {
+    const int ra = r0 + W.lane, rb = ra + W.kLanes;
     const int2 wa = ra < R ? L.rx[ra] : none;
     const int2 wb = rb < R ? L.rx[rb] : none;
     if (ra < R) rhs_reaction(L, ra, wa);
     if (rb < R) rhs_reaction(L, rb, wb);
   }
   wave_lds_sync();
-  return L.fb[li];
+  return L.fb[W.lane];
 }
 
 // Row li of M = I - gamma J (or of M^T when `transposed`) at the state y held
@@ -427,16 +529,16 @@ __device__ __forceinline__ double rhs(const MechDev &m, const Lds &L, int li, do
 // reaction (reactant slots count -1, product slots +1) with LDS atomics.
 // Each lane then reads its row (its column for M^T).  Terms are rounded to LT
 // before they are summed.
-template <int S, typename LT>
-__device__ __forceinline__ void newton_matrix(LT (&a)[S], const MechDev &m, const Lds &L, int li,
+template <int S, typename LT, int G>
+__device__ __forceinline__ void newton_matrix(LT (&a)[S], const MechDev &m, const Lds &L, const Grp<G> &W,
                                               double yi, double gamma, bool transposed) {
   LT *M = reinterpret_cast<LT *>(L.fac);
   wave_lds_sync();
-  L.yb[li] = yi;
-  for (int e = li; e < S * S; e += kWave)
+  L.yb[W.lane] = yi;
+  for (int e = W.lane; e < S * S; e += W.kLanes)
     M[e] = e % (S + 1) == 0 ? static_cast<LT>(1) : static_cast<LT>(0);
   wave_lds_sync();
-  for (int r = li; r < m.R; r += kWave) {
+  for (int r = W.lane; r < m.R; r += W.kLanes) {
     const int2 w = L.rx[r];
     int sp[2][3];
 #pragma unroll
@@ -467,11 +569,11 @@ __device__ __forceinline__ void newton_matrix(LT (&a)[S], const MechDev &m, cons
     }
   }
   wave_lds_sync();
-  const int lr = li < S ? li : 0;
+  const int lr = W.lane < S ? W.lane : 0;
 #pragma unroll
   for (int j = 0; j < S; ++j) {
     const LT v = transposed ? M[lr * S + j] : M[j * S + lr];
-    a[j] = li < S ? v : static_cast<LT>(0);
+    a[j] = W.lane < S ? v : static_cast<LT>(0);
   }
   wave_lds_sync();
 }
@@ -504,9 +606,9 @@ __device__ __forceinline__ uint64_t abs_key(float v) {
 // that a solve is one lane-parallel matrix-vector product.  Returns 0, or k+1
 // for the first column k without a nonzero pivot (the elimination then runs
 // on garbage).
-template <int S, typename LT>
-__device__ __forceinline__ int gj_invert(LT (&a)[S], int li, const Lds &L) {
-  int piv = li < S ? -1 : 1 << 20;
+template <int S, typename LT, int G>
+__device__ __forceinline__ int gj_invert(LT (&a)[S], const Grp<G> &W, const Lds &L) {
+  int piv = W.lane < S ? -1 : 1 << 20;
   int info = 0;
   int *perm = L.perm;
   LT dinv = static_cast<LT>(1);  // 1 / own pivot
@@ -515,22 +617,22 @@ __device__ __forceinline__ int gj_invert(LT (&a)[S], int li, const Lds &L) {
     bool zero_pivot;
     if constexpr (sizeof(LT) == 4) {
       const uint32_t key = piv < 0 ? static_cast<uint32_t>(abs_key(a[0])) : 0u;
-      const uint32_t kmax = wmax_u32(key);
-      p = wfirst(key == kmax);
+      const uint32_t kmax = W.max_u32(key);
+      p = W.first(key == kmax);
       zero_pivot = kmax <= 1u;
     } else {
       // exact 64-bit maximum in two 32-bit passes: high words, then the low
       // words of the lanes that tie on the high word
       const uint64_t key = piv < 0 ? abs_key(a[0]) : 0ull;
       const uint32_t hi = static_cast<uint32_t>(key >> 32), lo = static_cast<uint32_t>(key);
-      const uint32_t hmax = wmax_u32(hi);
-      const uint32_t lmax = wmax_u32(hi == hmax ? lo : 0u);
-      p = wfirst(hi == hmax && lo == lmax);
+      const uint32_t hmax = W.max_u32(hi);
+      const uint32_t lmax = W.max_u32(hi == hmax ? lo : 0u);
+      p = W.first(hi == hmax && lo == lmax);
       zero_pivot = hmax == 0u && lmax <= 1u;
     }
     if (zero_pivot && info == 0) info = k + 1;
-    const bool is_p = li == p;
-    const LT pk = lane_bcast(a[0], p);
+    const bool is_p = W.lane == p;
+    const LT pk = W.bcast(a[0], p);
     const LT rp = rcp(pk);
     const LT g = is_p ? static_cast<LT>(0) : a[0] * rp;
     if (is_p) {
@@ -538,14 +640,14 @@ __device__ __forceinline__ int gj_invert(LT (&a)[S], int li, const Lds &L) {
       dinv = rp;
     }
 #pragma unroll
-    for (int j = 1; j < S; ++j) a[j - 1] = fma(-g, lane_bcast(a[j], p), a[j]);
+    for (int j = 1; j < S; ++j) a[j - 1] = fma(-g, W.bcast(a[j], p), a[j]);
     a[S - 1] = is_p ? static_cast<LT>(1) : -g;
-    if (li == 0) perm[k] = p;
+    if (W.lane == 0) perm[k] = p;
   }
   // lane i holds row piv(i) of M^{-1} (times its pivot); slot k is column perm[k]
   LT *inv = reinterpret_cast<LT *>(L.fac);
   wave_lds_sync();
-  if (li < S) {
+  if (W.lane < S) {
 #pragma unroll
     for (int k = 0; k < S; ++k) inv[perm[k] * S + piv] = a[k] * dinv;
   }
@@ -554,18 +656,18 @@ __device__ __forceinline__ int gj_invert(LT (&a)[S], int li, const Lds &L) {
 }
 
 // x = M^{-1} b with the inverse in LDS; lane i passes b_i and gets x_i.
-template <int S, typename LT>
-__device__ __forceinline__ double inv_solve(const Lds &L, int li, double b) {
+template <int S, typename LT, int G>
+__device__ __forceinline__ double inv_solve(const Lds &L, const Grp<G> &W, double b) {
   const LT *inv = reinterpret_cast<const LT *>(L.fac);
   LT *bb = reinterpret_cast<LT *>(L.yb);
   wave_lds_sync();
-  if (li < S) bb[li] = static_cast<LT>(b);
+  if (W.lane < S) bb[W.lane] = static_cast<LT>(b);
   wave_lds_sync();
-  const int lr = li < S ? li : 0;
+  const int lr = W.lane < S ? W.lane : 0;
   LT acc = 0;
 #pragma unroll
   for (int c = 0; c < S; ++c) acc = fma(inv[c * S + lr], bb[c], acc);
-  return li < S ? static_cast<double>(acc) : 0.0;
+  return W.lane < S ? static_cast<double>(acc) : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -574,28 +676,30 @@ __device__ __forceinline__ double inv_solve(const Lds &L, int li, double b) {
 
 // squared WRMS norm of Eq. (3); inv_n = 1 / (species of the cell).  The
 // integrator compares and raises squared norms, so no square root is taken.
-__device__ __forceinline__ double wrms2(double v, double w, double inv_n) {
+template <int G>
+__device__ __forceinline__ double wrms2(const Grp<G> &W, double v, double w, double inv_n) {
   const double t = v * w;  // w = 0 on lanes without a species
-  return uni(wsum(t * t) * inv_n);
+  return W.uni(W.sum(t * t) * inv_n);
 }
 
-template <int S, typename LT, bool RXL>
-__device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, int li, double *lds) {
+template <int S, typename LT, bool RXL, int G>
+__device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, const Grp<G> &W,
+                                               double *lds) {
   const MechDev &m = P.mech;
   const int R = m.R;
   const Lds L = carve<RXL>(lds, R, m.rx);
-  if (li == 0) L.yb[kEmptySlot] = 1.0;  // empty reaction slots multiply by 1
+  if (W.lane == 0) L.yb[kEmptySlot] = 1.0;  // empty reaction slots multiply by 1
   double *const C = L.C;
   const int n = P.n_sp;
   const double inv_n = 1.0 / n;
-  const bool own = li < n;
+  const bool own = W.lane < n;
   const double rtol = P.rtol, t0 = P.t0, tout = P.tout;
   const int qmax = P.max_order < 1 ? 1 : (P.max_order > kQmax ? kQmax : P.max_order);
 
   // rate constants (Arrhenius, frozen T)
   const double T = P.T ? P.T[cell] : 1.0;
   wave_lds_sync();
-  for (int r = li; r < R; r += kWave) {
+  for (int r = W.lane; r < R; r += W.kLanes) {
     double lk = m.lnA[r];
     lk -= m.EaR[r] / T;
     double kf = exp(lk);
@@ -605,10 +709,10 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
     if constexpr (RXL) const_cast<int2 *>(L.rx)[r] = reinterpret_cast<const int2 *>(m.rx)[r];
   }
 
-  const double yin = own ? P.y[cell * P.ldy + li] : 0.0;
-  const double Fi = (own && P.F) ? P.F[cell * P.ldy + li] : 0.0;
-  const double atol_i = own ? (P.atol_len == 1 ? P.atol[0] : P.atol[li]) : 1.0;
-  if (P.rec && own) P.rec_y0[cell * P.rec_stride + li] = yin;
+  const double yin = own ? P.y[cell * P.ldy + W.lane] : 0.0;
+  const double Fi = (own && P.F) ? P.F[cell * P.ldy + W.lane] : 0.0;
+  const double atol_i = own ? (P.atol_len == 1 ? P.atol[0] : P.atol[W.lane]) : 1.0;
+  if (P.rec && own) P.rec_y0[cell * P.rec_stride + W.lane] = yin;
 
   int status = kSuccess;
   int nst = 0, nfe = 0, nni = 0, nsetups = 0, netf = 0, ncfn = 0;
@@ -619,16 +723,16 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
   for (int j = 0; j <= kQmax; ++j) z[j] = 0.0;
   bool write_y = true;
 
-  if (wany(!isfinite(T) || (own && !isfinite(yin)))) {
+  if (W.any(!isfinite(T) || (own && !isfinite(yin)))) {
     status = kNonfinite;
     write_y = false;
   }
   double f = 0.0, ewt = 0.0;
   if (status == kSuccess) {
     z[0] = yin;
-    f = rhs(m, L, li, yin, Fi);
+    f = rhs(m, L, W, yin, Fi);
     nfe = 1;
-    if (wany(own && !isfinite(f))) {
+    if (W.any(own && !isfinite(f))) {
       status = kNonfinite;
       write_y = false;
     }
@@ -639,7 +743,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
     const double tdist = fabs(tout - t0);
     const double hlb = 100.0 * kUround * fmax(fabs(t0), fabs(tout));
     double hub = 0.1 * tdist;
-    const double hub_inv = uni(wmax(own ? fabs(f) / (0.1 * fabs(yin) + atol_i) : 0.0));
+    const double hub_inv = W.uni(W.max(own ? fabs(f) / (0.1 * fabs(yin) + atol_i) : 0.0));
     if (hub * hub_inv > 1.0) hub = 1.0 / hub_inv;
     if (hub < hlb) {
       h = hub;
@@ -647,15 +751,15 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
       double hg = sqrt(hlb * hub), hnew = hg;
       bool at_ub = false;
       for (int it = 0; it < 4; ++it) {
-        const double ft = rhs(m, L, li, yin + hg * f, Fi);
+        const double ft = rhs(m, L, W, yin + hg * f, Fi);
         nfe++;
         const double ydd = (ft - f) / hg;
-        const double yddnrm = sqrt(wrms2(ydd, ewt, inv_n));
+        const double yddnrm = sqrt(wrms2(W, ydd, ewt, inv_n));
         if (!(yddnrm > 0.0)) {
           at_ub = true;
           break;
         }
-        hnew = uni(sqrt(2.0 / yddnrm));
+        hnew = W.uni(sqrt(2.0 / yddnrm));
         const double ratio = hnew / hg;
         hg = hnew;
         if (ratio >= 0.5 && ratio <= 2.0) break;
@@ -668,7 +772,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         if (h > hub) h = hub;
       }
     }
-    h = uni(h);
+    h = W.uni(h);
     z[1] = h * f;
   }
 
@@ -678,7 +782,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
   C[Ctl::kEtaMax] = 1.0e4;
   C[Ctl::kHprev] = h;
   C[Ctl::kGammaBar] = 0.0;
-  if (P.rec && li == 0) P.rec_hpad[cell] = h;
+  if (P.rec && W.lane == 0) P.rec_hpad[cell] = h;
 
   int qwait = 2, nst_setup = 0;
   double R2 = 1.0;  // squared Newton convergence rate
@@ -697,7 +801,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
     for (;;) {  // attempts of this step
       bool landing = false;
       if (t + h >= tout * (1.0 - 4.0 * kUround)) {
-        const double hnew = uni(tout - t);
+        const double hnew = W.uni(tout - t);
         nd_rescale(z, hnew / h);
         h = hnew;
         landing = true;
@@ -728,20 +832,20 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
           C[Ctl::kL + i] = l[i];
         }
         C[Ctl::kTn] = landing ? tout : t + h;
-        l1 = uni(l[1]);
-        Cerr = uni(Cerr);
+        l1 = W.uni(l[1]);
+        Cerr = W.uni(Cerr);
       }
-      const double rl1 = uni(rcp(l1));
-      const double gamma = uni(h * rl1);
-      double gamma_bar = uni(C[Ctl::kGammaBar]);
+      const double rl1 = W.uni(rcp(l1));
+      const double gamma = W.uni(h * rl1);
+      double gamma_bar = W.uni(C[Ctl::kGammaBar]);
       bool fresh = false;
       // (gamma_bar = 0 before the first setup, which need_setup forces)
       if (need_setup || nst >= nst_setup + 20 || fabs(gamma * rcp(gamma_bar) - 1.0) > 0.3) {
         int info;
         {
           LT a[S];
-          newton_matrix<S, LT>(a, m, L, li, z[0], gamma, false);
-          info = gj_invert<S, LT>(a, li, L);
+          newton_matrix<S, LT>(a, m, L, W, z[0], gamma, false);
+          info = gj_invert<S, LT>(a, W, L);
         }
         nsetups++;
         nst_setup = nst;
@@ -759,33 +863,33 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
             break;
           }
           nd_rescale(z, 0.25);
-          h = uni(h * 0.25);
+          h = W.uni(h * 0.25);
           C[Ctl::kEtaMax] = 1.0;
           continue;
         }
       }
       const double cfac =
-          uni(gamma != gamma_bar ? 2.0 * rcp(1.0 + gamma * rcp(gamma_bar)) : 1.0);
+          W.uni(gamma != gamma_bar ? 2.0 * rcp(1.0 + gamma * rcp(gamma_bar)) : 1.0);
 
       // Newton iteration on G(e) = e - gamma f(z_0 + e) + z_1 / l_1, Eq. (4)
       bool conv = false;
       double dprev2 = 0.0;
       // stopping test of Eq. (4) with eps = 1/Cerr, on squared norms
-      const double tol2 = 0.01 * uni(rcp(Cerr * Cerr));
+      const double tol2 = 0.01 * W.uni(rcp(Cerr * Cerr));
       e = 0.0;
       for (int mit = 0; mit < 3; ++mit) {
-        f = rhs(m, L, li, z[0] + e, Fi);
+        f = rhs(m, L, W, z[0] + e, Fi);
         nfe++;
         nni++;
         const double Gi = e - gamma * f + z[1] * rl1;
-        double delta = inv_solve<S, LT>(L, li, -Gi);
+        double delta = inv_solve<S, LT>(L, W, -Gi);
         if (cfac != 1.0) delta *= cfac;
         e += delta;
-        const double d2 = wrms2(delta, ewt, inv_n);
+        const double d2 = wrms2(W, delta, ewt, inv_n);
         if (!isfinite(d2)) break;
         if (mit >= 1) {
           const double ratio2 = d2 * rcp(dprev2);
-          R2 = uni(0.09 * R2 > ratio2 ? 0.09 * R2 : ratio2);
+          R2 = W.uni(0.09 * R2 > ratio2 ? 0.09 * R2 : ratio2);
         }
         if ((R2 < 1.0 ? R2 : 1.0) * d2 <= tol2) {
           conv = true;
@@ -803,7 +907,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         }
         if (fresh) {
           nd_rescale(z, 0.25);
-          h = uni(h * 0.25);
+          h = W.uni(h * 0.25);
           C[Ctl::kEtaMax] = 1.0;
         }
         need_setup = true;
@@ -811,7 +915,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
       }
 
       // local error test (Sec. 2)
-      dsm2 = uni(Cerr * Cerr * wrms2(e, ewt, inv_n));
+      dsm2 = W.uni(Cerr * Cerr * wrms2(W, e, ewt, inv_n));
       if (dsm2 <= 1.0) break;
       netf++;
       nd_unpredict(z);
@@ -822,9 +926,9 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
       C[Ctl::kEtaMax] = 1.0;
       if (nef_step >= 3) {
         // restart at order 1 from the last accepted y
-        const double hnew = uni(0.1 * h);
+        const double hnew = W.uni(0.1 * h);
         q = 1;
-        const double f0 = rhs(m, L, li, z[0], Fi);
+        const double f0 = rhs(m, L, W, z[0], Fi);
         nfe++;
 #pragma unroll
         for (int j = 2; j <= kQmax; ++j) z[j] = 0.0;
@@ -837,15 +941,15 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         double eta = eta_from2(6.0, dsm2, q + 1);
         if (eta < 0.1) eta = 0.1;
         if (nef_step >= 2 && eta > 0.2) eta = 0.2;
-        eta = uni(eta);
+        eta = W.uni(eta);
         nd_rescale(z, eta);
-        h = uni(h * eta);
+        h = W.uni(h * eta);
       }
     }
     if (status != kSuccess) break;
 
     // accept: correct the Nordsieck array
-    t = uni(C[Ctl::kTn]);
+    t = W.uni(C[Ctl::kTn]);
     // l_j = 0 for j > q
 #pragma unroll
     for (int j = 0; j <= kQmax; ++j) z[j] = fma(C[Ctl::kL + j], e, z[j]);
@@ -860,8 +964,8 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
         break;
       }
       double *rp = P.rec + (static_cast<int64_t>(cell) * P.rec_cap + (nst - 1)) * P.rec_stride;
-      if (own) rp[li] = z[0];
-      if (li == 0) {
+      if (own) rp[W.lane] = z[0];
+      if (W.lane == 0) {
         rp[n] = h;
         rp[n + 1] = static_cast<double>(q + (rebuilt ? 256 : 0));
       }
@@ -874,20 +978,20 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
       C[Ctl::kHprev] = hstep;
       have_eprev = true;
     }
-    const double eta_max = uni(C[Ctl::kEtaMax]);
+    const double eta_max = W.uni(C[Ctl::kEtaMax]);
     if (t < tout) {
       if (eta_max == 1.0) {
         if (qwait < 2) qwait = 2;  // right after a failure: hold h and q
       } else {
-        double eta = uni(eta_from2(6.0, dsm2, q + 1));
+        double eta = W.uni(eta_from2(6.0, dsm2, q + 1));
         int qnew = q;
         if (qwait == 0) {
           qwait = 2;
           if (q > 1) {
             const double lte =
                 factorial(q - 1) / harmonic(q - 1);
-            const double lte2 = lte * lte * wrms2(nd_get(z, q), ewt, inv_n);
-            const double eta_qm1 = uni(eta_from2(6.0, lte2, q));
+            const double lte2 = lte * lte * wrms2(W, nd_get(z, q), ewt, inv_n);
+            const double eta_qm1 = W.uni(eta_from2(6.0, lte2, q));
             if (eta_qm1 > eta) {
               eta = eta_qm1;
               qnew = q - 1;
@@ -896,8 +1000,8 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
           if (q < qmax && have_eprev) {
             const double r = ipow(hstep / C[Ctl::kHprev], q + 1);
             const double c = rcp((q + 2) * harmonic(q + 1));
-            const double lte2 = c * c * wrms2(e - r * eprev, ewt, inv_n);
-            const double eta_qp1 = uni(eta_from2(10.0, lte2, q + 2));
+            const double lte2 = c * c * wrms2(W, e - r * eprev, ewt, inv_n);
+            const double eta_qp1 = W.uni(eta_from2(10.0, lte2, q + 2));
             if (eta_qp1 > eta) {
               eta = eta_qp1;
               qnew = q + 1;
@@ -940,15 +1044,15 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, in
             have_eprev = false;
           }
           nd_rescale(z, eta);
-          h = uni(h * eta);
+          h = W.uni(h * eta);
         }
       }
     }
     C[Ctl::kEtaMax] = 10.0;
   }
 
-  if (write_y && own) P.y[cell * P.ldy + li] = z[0];
-  if (li == 0) {
+  if (write_y && own) P.y[cell * P.ldy + W.lane] = z[0];
+  if (W.lane == 0) {
     P.status[cell] = status;
     if (P.stats) {
       CellStats st;
@@ -1054,6 +1158,7 @@ __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int 
   const MechDev &m = P.mech;
   const int R = m.R;
   const Lds L = carve<true>(lds, R, m.rx);
+  const Grp<1> W1(li);
   double *vb = reinterpret_cast<double *>(L.fac) + S * S;  // [64 + 8], vb[kEmptySlot] = 0
   double *pb = vb + kWave + 8;
   if (li == 0) {
@@ -1102,10 +1207,10 @@ __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int 
     // (I - gamma J(y_n))^T mu = eb
     {
       double a[S];
-      newton_matrix<S, double>(a, m, L, li, yn, gamma, true);
-      gj_invert<S, double>(a, li, L);
+      newton_matrix<S, double>(a, m, L, W1, yn, gamma, true);
+      gj_invert<S, double>(a, W1, L);
     }
-    const double mu = own ? inv_solve<S, double>(L, li, eb) : 0.0;
+    const double mu = own ? inv_solve<S, double>(L, W1, eb) : 0.0;
     adj_scatter(m, L, vb, pb, li, yn, mu, gamma, false);
     // a = zp_0 - zp_1 / l_1
     zb[0] += mu;

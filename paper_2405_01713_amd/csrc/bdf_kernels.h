@@ -13,31 +13,33 @@ namespace bdfx {
 
 // MINW: minimum resident waves per SIMD the register allocation must allow
 // (1 = compiler's choice; 3 = at most 168 VGPRs, 4 = at most 128, spilling
-// if needed).  RXL: reaction slot words copied to LDS (see carve).
-template <int S, typename LT, int MINW, bool RXL>
+// if needed).  RXL: reaction slot words copied to LDS (see carve).  G: cells
+// per wave (2: each half-wave integrates its own cell, S <= 32); each group
+// has its own LDS area of P.lds_doubles and pops its own cells.
+template <int S, typename LT, int MINW, bool RXL, int G>
 __global__ void __launch_bounds__(256, MINW) k_integrate(Params P) {
   extern __shared__ double smem[];
   const int wib = threadIdx.x / kWave;
-  const int li = threadIdx.x & (kWave - 1);
+  const Grp<G> W(threadIdx.x & (kWave - 1));
   const int wpb = blockDim.x / kWave;
-  double *lds = smem + static_cast<int64_t>(wib) * P.lds_doubles;
+  double *lds = smem + static_cast<int64_t>(wib * G + W.grp) * P.lds_doubles;
   int64_t next = 0, stop = 0;
   if (!P.use_queue) {
-    next = static_cast<int64_t>(blockIdx.x) * wpb + wib;
+    next = (static_cast<int64_t>(blockIdx.x) * wpb + wib) * G + W.grp;
     stop = next + 1;
   }
   for (;;) {
     if (next >= stop) {
       if (!P.use_queue) break;
       unsigned int base = 0;
-      if (li == 0) base = atomicAdd(P.queue, static_cast<unsigned int>(P.chunk));
-      next = uni(static_cast<int>(base));
+      if (W.lane == 0) base = atomicAdd(P.queue, static_cast<unsigned int>(P.chunk));
+      next = W.from_lane0(static_cast<int>(base));
       stop = next + P.chunk;
     }
     if (next >= P.n_list) break;
     const int64_t cell = P.list ? P.list[next] : next;
     ++next;
-    integrate_cell<S, LT, RXL>(P, cell, li, lds);
+    integrate_cell<S, LT, RXL, G>(P, cell, W, lds);
   }
 }
 
@@ -56,28 +58,41 @@ struct LaunchCfg {
   size_t lds_bytes;
 };
 
-// the integrator kernel for (LU precision, register budget, slot words in LDS)
+// the integrator kernel for (LU precision, register budget, slot words in
+// LDS, cells per wave); nullptr where no such variant is built
 template <int S>
-const void *integrate_kernel(bool fp32, int minw, bool rx_lds) {
+const void *integrate_kernel(bool fp32, int minw, bool rx_lds, int cells_per_wave) {
   using F = const void *;
   const int w = minw >= 4 ? 2 : minw >= 3 ? 1 : 0;
+  if (cells_per_wave == 2) {
+    if constexpr (S <= 32) {
+      static const F tab2[2][3] = {
+          {F(&k_integrate<S, double, 1, true, 2>), F(&k_integrate<S, double, 3, true, 2>),
+           F(&k_integrate<S, double, 4, true, 2>)},
+          {F(&k_integrate<S, float, 1, true, 2>), F(&k_integrate<S, float, 3, true, 2>),
+           F(&k_integrate<S, float, 4, true, 2>)}};
+      return rx_lds ? tab2[fp32 ? 1 : 0][w] : nullptr;
+    }
+    return nullptr;
+  }
   static const F tab[2][3][2] = {
-      {{F(&k_integrate<S, double, 1, false>), F(&k_integrate<S, double, 1, true>)},
-       {F(&k_integrate<S, double, 3, false>), F(&k_integrate<S, double, 3, true>)},
-       {F(&k_integrate<S, double, 4, false>), F(&k_integrate<S, double, 4, true>)}},
-      {{F(&k_integrate<S, float, 1, false>), F(&k_integrate<S, float, 1, true>)},
-       {F(&k_integrate<S, float, 3, false>), F(&k_integrate<S, float, 3, true>)},
-       {F(&k_integrate<S, float, 4, false>), F(&k_integrate<S, float, 4, true>)}}};
+      {{F(&k_integrate<S, double, 1, false, 1>), F(&k_integrate<S, double, 1, true, 1>)},
+       {F(&k_integrate<S, double, 3, false, 1>), F(&k_integrate<S, double, 3, true, 1>)},
+       {F(&k_integrate<S, double, 4, false, 1>), F(&k_integrate<S, double, 4, true, 1>)}},
+      {{F(&k_integrate<S, float, 1, false, 1>), F(&k_integrate<S, float, 1, true, 1>)},
+       {F(&k_integrate<S, float, 3, false, 1>), F(&k_integrate<S, float, 3, true, 1>)},
+       {F(&k_integrate<S, float, 4, false, 1>), F(&k_integrate<S, float, 4, true, 1>)}}};
   return tab[fp32 ? 1 : 0][w][rx_lds ? 1 : 0];
 }
 
 template <int S>
-hipError_t launch_integrate(const Params &P, bool fp32, int minw, bool rx_lds, const LaunchCfg &c,
-                            hipStream_t s) {
+hipError_t launch_integrate(const Params &P, bool fp32, int minw, bool rx_lds, int cells_per_wave,
+                            const LaunchCfg &c, hipStream_t s) {
+  const void *f = integrate_kernel<S>(fp32, minw, rx_lds, cells_per_wave);
+  if (!f) return hipErrorInvalidDeviceFunction;
   Params arg = P;
   void *args[] = {&arg};
-  return hipLaunchKernel(integrate_kernel<S>(fp32, minw, rx_lds), dim3(c.grid), dim3(c.block), args,
-                         c.lds_bytes, s);
+  return hipLaunchKernel(f, dim3(c.grid), dim3(c.block), args, c.lds_bytes, s);
 }
 
 template <int S>
@@ -87,31 +102,35 @@ hipError_t launch_adjoint(const Params &P, const LaunchCfg &c, hipStream_t s) {
 }
 
 template <int S>
-hipError_t occupancy_integrate(bool fp32, int minw, bool rx_lds, int block, size_t lds_bytes,
-                               int *blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks_per_cu, integrate_kernel<S>(fp32, minw, rx_lds), block, lds_bytes);
+hipError_t occupancy_integrate(bool fp32, int minw, bool rx_lds, int cells_per_wave, int block,
+                               size_t lds_bytes, int *blocks_per_cu) {
+  const void *f = integrate_kernel<S>(fp32, minw, rx_lds, cells_per_wave);
+  if (!f) {
+    *blocks_per_cu = 0;
+    return hipSuccess;
+  }
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds_bytes);
 }
 
 }  // namespace bdfx
 
 // One translation unit per species size (compiled in parallel).
 #define BDFX_DEFINE_SIZE(S)                                                                      \
-  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, bool rx_lds,           \
+  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, bool rx_lds, int cpw,  \
                               const bdfx::LaunchCfg &c, hipStream_t s) {                         \
-    return bdfx::launch_integrate<S>(P, fp32, minw, rx_lds, c, s);                               \
+    return bdfx::launch_integrate<S>(P, fp32, minw, rx_lds, cpw, c, s);                          \
   }                                                                                              \
-  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, bool rx_lds, int block, size_t lds,        \
-                                 int *out) {                                                     \
-    return bdfx::occupancy_integrate<S>(fp32, minw, rx_lds, block, lds, out);                    \
+  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, bool rx_lds, int cpw, int block,           \
+                                 size_t lds, int *out) {                                         \
+    return bdfx::occupancy_integrate<S>(fp32, minw, rx_lds, cpw, block, lds, out);               \
   }                                                                                              \
   hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s) { \
     return bdfx::launch_adjoint<S>(P, c, s);                                                     \
   }
 
 #define BDFX_DECLARE_SIZE(S)                                                                     \
-  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, bool rx_lds,           \
+  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, bool rx_lds, int cpw,  \
                               const bdfx::LaunchCfg &c, hipStream_t s);                          \
-  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, bool rx_lds, int block, size_t lds,        \
-                                 int *out);                                                      \
+  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, bool rx_lds, int cpw, int block,           \
+                                 size_t lds, int *out);                                          \
   hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s);

@@ -46,8 +46,9 @@ thread_local std::string g_create_error;
 
 struct SizeEntry {
   int S;
-  hipError_t (*launch)(const bdfx::Params &, bool, int, bool, const bdfx::LaunchCfg &, hipStream_t);
-  hipError_t (*occupancy)(bool, int, bool, int, size_t, int *);
+  hipError_t (*launch)(const bdfx::Params &, bool, int, bool, int, const bdfx::LaunchCfg &,
+                       hipStream_t);
+  hipError_t (*occupancy)(bool, int, bool, int, int, size_t, int *);
   hipError_t (*adjoint)(const bdfx::Params &, const bdfx::LaunchCfg &, hipStream_t);
 };
 
@@ -91,7 +92,7 @@ struct Bin {
   int32_t lds_doubles = 0;
   bdfx::LaunchCfg cfg{};
   // launch shape: from the options, or chosen by bdfx_autotune()
-  int32_t waves_per_simd = 0, waves_per_block = 1, queue_chunk = 1;
+  int32_t waves_per_simd = 0, waves_per_block = 1, queue_chunk = 1, cells_per_wave = 1;
   bool tuned = false;
   bool rx_lds = true;  // reaction slot words copied to LDS (else read from global memory)
 };
@@ -306,7 +307,7 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
   if (o->waves_per_simd != 0 && o->waves_per_simd != 3 && o->waves_per_simd != 4)
     return fail(ctx, BDFX_EINVAL, "waves_per_simd must be 0, 3 or 4");
   if (o->waves_per_block < 0 || o->waves_per_block > 16 || o->blocks_per_cu < 0 ||
-      o->queue_chunk < 0)
+      o->queue_chunk < 0 || o->cells_per_wave < 0 || o->cells_per_wave > 2)
     return fail(ctx, BDFX_EINVAL, "invalid launch shape");
   if (o->max_order < 0 || o->max_order > BDFX_MAX_ORDER)
     return fail(ctx, BDFX_EINVAL, "max_order out of 1..5");
@@ -439,26 +440,31 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
   const bdfx_mech m = ctx->mechs[b.mech];
   b.se = size_for(m->S);
   if (!b.se) return fail(ctx, BDFX_EUNSUPPORTED, "no kernel for %d species", m->S);
+  const int cpw = b.cells_per_wave;
+  if (cpw != 1 && !(cpw == 2 && b.se->S <= 32))
+    return fail(ctx, BDFX_EUNSUPPORTED, "%d cells per wave with %d species", cpw, b.se->S);
   const int waves = std::max(b.waves_per_block, 1);
   b.cfg.block = bdfx::kWave * waves;
   // slot words in LDS unless leaving them in global memory lets more waves
-  // reside (LDS-limited sizes)
+  // reside (LDS-limited sizes; one cell per wave only)
   int occ[2] = {0, 0};
   size_t lds[2];
   for (int k = 0; k < 2; ++k) {
     const int32_t d = static_cast<int32_t>(
         align_up(bdfx::lds_doubles(b.se->S, m->R, fp32 ? 4 : 8, k == 1), 2));
-    lds[k] = static_cast<size_t>(waves) * d * 8;  // one wave per cell
-    if (lds[k] <= 65536)
-      HIPCHK(ctx, b.se->occupancy(fp32, b.waves_per_simd, k == 1, b.cfg.block, lds[k], &occ[k]));
+    lds[k] = static_cast<size_t>(waves) * cpw * d * 8;
+    if (lds[k] <= 65536 && (k == 1 || cpw == 1))
+      HIPCHK(ctx, b.se->occupancy(fp32, b.waves_per_simd, k == 1, cpw, b.cfg.block, lds[k],
+                                  &occ[k]));
   }
   b.rx_lds = !(occ[0] > occ[1]);
   const int k = b.rx_lds ? 1 : 0;
   b.cfg.lds_bytes = lds[k];
-  b.lds_doubles = static_cast<int32_t>(lds[k] / 8 / waves);
+  b.lds_doubles = static_cast<int32_t>(lds[k] / 8 / (waves * cpw));
   if (b.cfg.lds_bytes > 65536)
     return fail(ctx, BDFX_EUNSUPPORTED, "LDS per block %zu exceeds 64 KiB", b.cfg.lds_bytes);
-  const int64_t need = (b.count + waves - 1) / waves;
+  const int64_t per_block = static_cast<int64_t>(waves) * cpw;
+  const int64_t need = (b.count + per_block - 1) / per_block;
   if (queue) {
     const int per_cu = ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : std::max(occ[k], 1);
     b.cfg.grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(per_cu) * ctx->n_cu, need));
@@ -476,6 +482,9 @@ static int configure_bins(bdfx_ctx ctx) {
       b.waves_per_simd = ctx->opt.waves_per_simd;
       b.waves_per_block = ctx->opt.waves_per_block > 0 ? ctx->opt.waves_per_block : 1;
       b.queue_chunk = ctx->opt.queue_chunk > 0 ? ctx->opt.queue_chunk : 1;
+      // two cells per wave where the mechanism fits a half-wave
+      const SizeEntry *se = size_for(ctx->mechs[b.mech]->S);
+      b.cells_per_wave = ctx->opt.cells_per_wave == 2 && se && se->S <= 32 ? 2 : 1;
     }
     if (const int rc = configure_bin(ctx, b)) return rc;
   }
@@ -534,7 +543,8 @@ int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out) {
     bdfx::Params P = make_params(ctx, b, t0, t_out);
     P.use_queue = queue ? 1 : 0;
     P.lds_doubles = b.lds_doubles;
-    HIPCHK(ctx, b.se->launch(P, fp32, b.waves_per_simd, b.rx_lds, b.cfg, ctx->stream));
+    HIPCHK(ctx, b.se->launch(P, fp32, b.waves_per_simd, b.rx_lds, b.cells_per_wave, b.cfg,
+                             ctx->stream));
   }
   ctx->last_t0 = t0;
   ctx->last_tout = t_out;
@@ -577,7 +587,7 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
     return fail(ctx, BDFX_EHIP, "hipEventCreate failed");
   }
   int rc = BDFX_OK;
-  const int wps_c[] = {0, 3, 4}, wpb_c[] = {1, 2, 4}, chunk_c[] = {1, 4};
+  const int wps_c[] = {0, 3, 4}, wpb_c[] = {1, 2, 4}, chunk_c[] = {1, 4}, cpw_c[] = {1, 2};
   for (size_t bi = 0; bi < ctx->bins.size() && rc == BDFX_OK; ++bi) {
     Bin &b = ctx->bins[bi];
     if (b.count == 0) continue;
@@ -589,10 +599,13 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
     float best = 0.0f;
     bool have = false;
     Bin pick = b;
+    for (int cpw : cpw_c)
     for (int wps : wps_c)
       for (int wpb : wpb_c)
         for (int chunk : chunk_c) {
           if (!queue && chunk != 1) continue;
+          if (cpw == 2 && b.se->S > 32) continue;
+          trial.cells_per_wave = cpw;
           trial.waves_per_simd = wps;
           trial.waves_per_block = wpb;
           trial.queue_chunk = chunk;
@@ -607,7 +620,7 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
             if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
             if (e == hipSuccess && queue) e = bdfx_launch_fill_u32(qctr, 64, 0u, ctx->stream);
             if (e == hipSuccess)
-              e = trial.se->launch(P, fp32, wps, trial.rx_lds, trial.cfg, ctx->stream);
+              e = trial.se->launch(P, fp32, wps, trial.rx_lds, cpw, trial.cfg, ctx->stream);
             if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
             if (e == hipSuccess)
               e = bdfx_launch_copy_rows(ctx->y, ctx->ldy, P.list, trial.count, m->S, save, true,
@@ -631,6 +644,7 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
     b.waves_per_simd = pick.waves_per_simd;
     b.waves_per_block = pick.waves_per_block;
     b.queue_chunk = pick.queue_chunk;
+    b.cells_per_wave = pick.cells_per_wave;
     b.tuned = true;
     rc = configure_bin(ctx, b);
     if (out) {
@@ -638,6 +652,7 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
       out[bi].waves_per_simd = b.waves_per_simd;
       out[bi].waves_per_block = b.waves_per_block;
       out[bi].queue_chunk = b.queue_chunk;
+      out[bi].cells_per_wave = b.cells_per_wave;
       out[bi].sample_cells = trial.count;
       out[bi].ms = best / 2.0f;
     }
@@ -657,13 +672,15 @@ int bdfx_set_tuning(bdfx_ctx ctx, const bdfx_tuning *t, int32_t n) {
   for (int32_t k = 0; k < n; ++k) {
     if (t[k].waves_per_simd != 0 && t[k].waves_per_simd != 3 && t[k].waves_per_simd != 4)
       return fail(ctx, BDFX_EINVAL, "waves_per_simd must be 0, 3 or 4");
-    if (t[k].waves_per_block < 1 || t[k].waves_per_block > 16 || t[k].queue_chunk < 1)
+    if (t[k].waves_per_block < 1 || t[k].waves_per_block > 16 || t[k].queue_chunk < 1 ||
+        (t[k].cells_per_wave != 1 && t[k].cells_per_wave != 2))
       return fail(ctx, BDFX_EINVAL, "invalid launch shape");
     for (Bin &b : ctx->bins)
       if (b.mech == t[k].mech) {
         b.waves_per_simd = t[k].waves_per_simd;
         b.waves_per_block = t[k].waves_per_block;
         b.queue_chunk = t[k].queue_chunk;
+        b.cells_per_wave = t[k].cells_per_wave;
         b.tuned = true;
         if (const int rc = configure_bin(ctx, b)) return rc;
       }

@@ -354,3 +354,37 @@ def test_empty_and_single_cell_batches(oracle, parity):
         yo, sto = _oracle(oracle, w)
         assert st["status"][0] == 0
         parity(y, yo, w, f"single cell, scheduler {sched}")
+
+
+@pytest.mark.parametrize("lu", [64, 32])
+def test_two_cells_per_wave(oracle, parity, lu):
+    """Two cells per wave (one per half-wave): parity with the oracle for an
+    odd number of cells (the last wave has an idle half) and for padded
+    mechanism sizes.  The RHS and Newton-matrix sums are accumulated by lanes
+    in another order than with one cell per wave (last-bit differences), but
+    the static and the work-queue schedules give the same bits."""
+    w = W.make_workload("s21_r84_262k", 255)
+    ys, sts = _gpu(w, scheduler=0, lu_precision=lu, cells_per_wave=2)
+    yq, stq = _gpu(w, scheduler=1, lu_precision=lu, cells_per_wave=2)
+    assert np.all(sts["status"] == 0)
+    assert np.array_equal(ys, yq) and np.array_equal(sts, stq)
+    yo, _ = _oracle(oracle, w)
+    parity(ys, yo, w, f"two cells per wave, LU{lu}")
+    for S, R, seed in ((5, 9, 1), (12, 20, 2)):
+        m = W.synthetic_mechanism(S, R, seed)
+        c = W.cell_states(m, 37, seed=seed + 7)
+        wp = dict(mechs=[m], y0=c["y0"], T=c["T"], rtol=1e-6, atol=1e-10, t_out=1e-5)
+        y2, st2 = _gpu(wp, scheduler=1, lu_precision=lu, cells_per_wave=2)
+        yo, sto = _oracle(oracle, wp)
+        assert np.all(st2["status"] == sto["status"])
+        parity(y2, yo, wp, f"two cells per wave, S={S}")
+
+
+def test_two_cells_per_wave_mixed(oracle, parity):
+    """Mixed 9 / 53 species batch: the 9-species bin runs two cells per wave,
+    the 53-species bin one."""
+    w = W.make_workload("mixed_s9_s53_1m", 301)
+    y2, st2 = _gpu(w, scheduler=1, cells_per_wave=2)
+    assert np.all(st2["status"] == 0)
+    yo, _ = _oracle(oracle, w)
+    parity(y2, yo, w, "mixed, two cells per wave")
