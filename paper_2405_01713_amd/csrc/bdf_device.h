@@ -589,6 +589,21 @@ __device__ __forceinline__ uint64_t abs_key(float v) {
   return static_cast<uint64_t>(__builtin_bit_cast(uint32_t, v) & 0x7FFFFFFFu) + 1ull;
 }
 
+// x * y + z as the three-address VOP3 FMA with y in a scalar register, so
+// that the rotated working row needs no register copies (the two-address form
+// ties its result to z).  y is usually written by v_readlane just before:
+// two wait states keep the VALU write of the SGPR ahead of the read.
+__device__ __forceinline__ float fma3s(float x, float y, float z) {
+  float r;
+  asm("s_nop 1\n\tv_fma_f32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "s"(y), "v"(z));
+  return r;
+}
+__device__ __forceinline__ double fma3s(double x, double y, double z) {
+  double r;
+  asm("s_nop 1\n\tv_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(x), "s"(y), "v"(z));
+  return r;
+}
+
 // Inverts the cell's S x S Newton matrix M (row i in lane i's registers) by
 // Gauss-Jordan elimination with partial pivoting: the pivot of column k is
 // the largest |a_ik| among rows not yet used, lowest row on ties (the same
@@ -640,7 +655,10 @@ __device__ __forceinline__ int gj_invert(LT (&a)[S], const Grp<G> &W, const Lds 
       dinv = rp;
     }
 #pragma unroll
-    for (int j = 1; j < S; ++j) a[j - 1] = fma(-g, W.bcast(a[j], p), a[j]);
+    for (int j = 1; j < S; ++j) {
+      if constexpr (G == 1) a[j - 1] = fma3s(-g, W.bcast(a[j], p), a[j]);
+      else a[j - 1] = fma(-g, W.bcast(a[j], p), a[j]);
+    }
     a[S - 1] = is_p ? static_cast<LT>(1) : -g;
     if (W.lane == 0) perm[k] = p;
   }
