@@ -134,12 +134,21 @@ __device__ __forceinline__ float lane_bcast(float v, int lane) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
 
+// One 32-bit DPP move.  With every row enabled the permutations used here
+// read a valid source lane everywhere, so no old value is needed (and none
+// is materialised); rows a row mask disables read 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp32(int x) {
+  if constexpr (ROWMASK == 0xf) return __builtin_amdgcn_mov_dpp(x, CTRL, 0xf, 0xf, false);
+  else return __builtin_amdgcn_update_dpp(0, x, CTRL, ROWMASK, 0xf, false);
+}
+
 template <int CTRL, int ROWMASK = 0xf>
 __device__ __forceinline__ double dpp(double v) {
   const int2 p = __builtin_bit_cast(int2, v);
   int2 r;
-  r.x = __builtin_amdgcn_update_dpp(0, p.x, CTRL, ROWMASK, 0xf, false);
-  r.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, ROWMASK, 0xf, false);
+  r.x = dpp32<CTRL, ROWMASK>(p.x);
+  r.y = dpp32<CTRL, ROWMASK>(p.y);
   return __builtin_bit_cast(double, r);
 }
 
@@ -147,8 +156,8 @@ template <int CTRL, int ROWMASK = 0xf>
 __device__ __forceinline__ uint64_t dpp(uint64_t v) {
   const int2 p = __builtin_bit_cast(int2, v);
   int2 r;
-  r.x = __builtin_amdgcn_update_dpp(0, p.x, CTRL, ROWMASK, 0xf, false);
-  r.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, ROWMASK, 0xf, false);
+  r.x = dpp32<CTRL, ROWMASK>(p.x);
+  r.y = dpp32<CTRL, ROWMASK>(p.y);
   return __builtin_bit_cast(uint64_t, r);
 }
 
@@ -248,47 +257,58 @@ struct Grp {
       return grp ? b : a;
     }
   }
-  // group-uniform result from the group's last lane
-  template <typename T>
+  // Reductions over the group.  NROW: 16-lane rows that can hold nonzero
+  // data (the first ceil(S/16) of each group); the rounds that would only
+  // combine zero rows are left out, which changes no result bit.
+  static constexpr int rows(int nrow) { return nrow < kLanes / 16 ? nrow : kLanes / 16; }
+  // the group-uniform result from the lane that holds it
+  template <int NROW, typename T>
   __device__ T last(T v) const {
+    constexpr int l = 16 * rows(NROW) - 1;  // 15, 31 or 63 within the group
     if constexpr (G == 1) {
-      return lane_bcast(v, 63);
+      return lane_bcast(v, l);
     } else {
-      const T a = lane_bcast(v, 31), b = lane_bcast(v, 63);
+      const T a = lane_bcast(v, l), b = lane_bcast(v, 32 + l);
       return grp ? b : a;
     }
   }
+  template <int NROW = 4>
   __device__ double sum(double v) const {
     v += dpp<kQuadXor1>(v);
     v += dpp<kQuadXor2>(v);
     v += dpp<kHalfMirror>(v);
     v += dpp<kMirror>(v);
-    v += dpp<kBcast15, 0xa>(v);
-    if constexpr (G == 1) v += dpp<kBcast31, 0xc>(v);
-    return last(v);
+    if constexpr (rows(NROW) >= 2) v += dpp<kBcast15, 0xa>(v);
+    if constexpr (rows(NROW) >= 3) v += dpp<kBcast31, 0xc>(v);
+    return last<NROW>(v);
   }
   // max of non-negative values (masked rows read 0)
+  template <int NROW = 4>
   __device__ double max(double v) const {
     v = fmax(v, dpp<kQuadXor1>(v));
     v = fmax(v, dpp<kQuadXor2>(v));
     v = fmax(v, dpp<kHalfMirror>(v));
     v = fmax(v, dpp<kMirror>(v));
-    v = fmax(v, dpp<kBcast15, 0xa>(v));
-    if constexpr (G == 1) v = fmax(v, dpp<kBcast31, 0xc>(v));
-    return last(v);
+    if constexpr (rows(NROW) >= 2) v = fmax(v, dpp<kBcast15, 0xa>(v));
+    if constexpr (rows(NROW) >= 3) v = fmax(v, dpp<kBcast31, 0xc>(v));
+    return last<NROW>(v);
   }
+  template <int NROW = 4>
   __device__ uint32_t max_u32(uint32_t v) const {
     auto step = [](uint32_t a, uint32_t b) { return a > b ? a : b; };
     v = step(v, __builtin_amdgcn_update_dpp(0u, v, kQuadXor1, 0xf, 0xf, false));
     v = step(v, __builtin_amdgcn_update_dpp(0u, v, kQuadXor2, 0xf, 0xf, false));
     v = step(v, __builtin_amdgcn_update_dpp(0u, v, kHalfMirror, 0xf, 0xf, false));
     v = step(v, __builtin_amdgcn_update_dpp(0u, v, kMirror, 0xf, 0xf, false));
-    v = step(v, __builtin_amdgcn_update_dpp(0u, v, kBcast15, 0xa, 0xf, false));
-    if constexpr (G == 1) v = step(v, __builtin_amdgcn_update_dpp(0u, v, kBcast31, 0xc, 0xf, false));
+    if constexpr (rows(NROW) >= 2)
+      v = step(v, __builtin_amdgcn_update_dpp(0u, v, kBcast15, 0xa, 0xf, false));
+    if constexpr (rows(NROW) >= 3)
+      v = step(v, __builtin_amdgcn_update_dpp(0u, v, kBcast31, 0xc, 0xf, false));
+    constexpr int l = 16 * rows(NROW) - 1;
     if constexpr (G == 1) {
-      return __builtin_amdgcn_readlane(v, 63);
+      return __builtin_amdgcn_readlane(v, l);
     } else {
-      const uint32_t a = __builtin_amdgcn_readlane(v, 31), b = __builtin_amdgcn_readlane(v, 63);
+      const uint32_t a = __builtin_amdgcn_readlane(v, l), b = __builtin_amdgcn_readlane(v, 32 + l);
       return grp ? b : a;
     }
   }
@@ -375,14 +395,28 @@ __device__ __forceinline__ void bdf_coeffs(int q, const double (&xi)[kQmax + 2],
 }
 
 // H_k = 1 + 1/2 + ... + 1/k and k! for k = 0..6
+// (a switch on the wave-uniform order: scalar branches, no table in registers)
 __device__ __forceinline__ double harmonic(int k) {
-  constexpr double kH[7] = {0.0, 1.0, 1.5, 11.0 / 6.0, 25.0 / 12.0, 137.0 / 60.0, 49.0 / 20.0};
-  return kH[k];
+  switch (k) {
+    case 1: return 1.0;
+    case 2: return 1.5;
+    case 3: return 11.0 / 6.0;
+    case 4: return 25.0 / 12.0;
+    case 5: return 137.0 / 60.0;
+    case 6: return 49.0 / 20.0;
+    default: return 0.0;
+  }
 }
 
 __device__ __forceinline__ double factorial(int k) {
-  constexpr double kF[7] = {1.0, 1.0, 2.0, 6.0, 24.0, 120.0, 720.0};
-  return kF[k];
+  switch (k) {
+    case 2: return 2.0;
+    case 3: return 6.0;
+    case 4: return 24.0;
+    case 5: return 120.0;
+    case 6: return 720.0;
+    default: return 1.0;
+  }
 }
 
 // x^(1/p) for x >= 0 and p in 1..14.  With x = u 2^(p k) (k from the binary
@@ -632,7 +666,7 @@ __device__ __forceinline__ int gj_invert(LT (&a)[S], const Grp<G> &W, const Lds 
     bool zero_pivot;
     if constexpr (sizeof(LT) == 4) {
       const uint32_t key = piv < 0 ? static_cast<uint32_t>(abs_key(a[0])) : 0u;
-      const uint32_t kmax = W.max_u32(key);
+      const uint32_t kmax = W.template max_u32<(S + 15) / 16>(key);
       p = W.first(key == kmax);
       zero_pivot = kmax <= 1u;
     } else {
@@ -640,8 +674,8 @@ __device__ __forceinline__ int gj_invert(LT (&a)[S], const Grp<G> &W, const Lds 
       // words of the lanes that tie on the high word
       const uint64_t key = piv < 0 ? abs_key(a[0]) : 0ull;
       const uint32_t hi = static_cast<uint32_t>(key >> 32), lo = static_cast<uint32_t>(key);
-      const uint32_t hmax = W.max_u32(hi);
-      const uint32_t lmax = W.max_u32(hi == hmax ? lo : 0u);
+      const uint32_t hmax = W.template max_u32<(S + 15) / 16>(hi);
+      const uint32_t lmax = W.template max_u32<(S + 15) / 16>(hi == hmax ? lo : 0u);
       p = W.first(hi == hmax && lo == lmax);
       zero_pivot = hmax == 0u && lmax <= 1u;
     }
@@ -694,10 +728,10 @@ __device__ __forceinline__ double inv_solve(const Lds &L, const Grp<G> &W, doubl
 
 // squared WRMS norm of Eq. (3); inv_n = 1 / (species of the cell).  The
 // integrator compares and raises squared norms, so no square root is taken.
-template <int G>
+template <int S, int G>
 __device__ __forceinline__ double wrms2(const Grp<G> &W, double v, double w, double inv_n) {
   const double t = v * w;  // w = 0 on lanes without a species
-  return W.uni(W.sum(t * t) * inv_n);
+  return W.uni(W.template sum<(S + 15) / 16>(t * t) * inv_n);
 }
 
 template <int S, typename LT, bool RXL, int G>
@@ -761,7 +795,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
     const double tdist = fabs(tout - t0);
     const double hlb = 100.0 * kUround * fmax(fabs(t0), fabs(tout));
     double hub = 0.1 * tdist;
-    const double hub_inv = W.uni(W.max(own ? fabs(f) / (0.1 * fabs(yin) + atol_i) : 0.0));
+    const double hub_inv = W.uni(W.template max<(S + 15) / 16>(own ? fabs(f) / (0.1 * fabs(yin) + atol_i) : 0.0));
     if (hub * hub_inv > 1.0) hub = 1.0 / hub_inv;
     if (hub < hlb) {
       h = hub;
@@ -772,7 +806,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
         const double ft = rhs(m, L, W, yin + hg * f, Fi);
         nfe++;
         const double ydd = (ft - f) / hg;
-        const double yddnrm = sqrt(wrms2(W, ydd, ewt, inv_n));
+        const double yddnrm = sqrt(wrms2<S>(W, ydd, ewt, inv_n));
         if (!(yddnrm > 0.0)) {
           at_ub = true;
           break;
@@ -903,7 +937,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
         double delta = inv_solve<S, LT>(L, W, -Gi);
         if (cfac != 1.0) delta *= cfac;
         e += delta;
-        const double d2 = wrms2(W, delta, ewt, inv_n);
+        const double d2 = wrms2<S>(W, delta, ewt, inv_n);
         if (!isfinite(d2)) break;
         if (mit >= 1) {
           const double ratio2 = d2 * rcp(dprev2);
@@ -933,7 +967,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       }
 
       // local error test (Sec. 2)
-      dsm2 = W.uni(Cerr * Cerr * wrms2(W, e, ewt, inv_n));
+      dsm2 = W.uni(Cerr * Cerr * wrms2<S>(W, e, ewt, inv_n));
       if (dsm2 <= 1.0) break;
       netf++;
       nd_unpredict(z);
@@ -1008,7 +1042,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
           if (q > 1) {
             const double lte =
                 factorial(q - 1) / harmonic(q - 1);
-            const double lte2 = lte * lte * wrms2(W, nd_get(z, q), ewt, inv_n);
+            const double lte2 = lte * lte * wrms2<S>(W, nd_get(z, q), ewt, inv_n);
             const double eta_qm1 = W.uni(eta_from2(6.0, lte2, q));
             if (eta_qm1 > eta) {
               eta = eta_qm1;
@@ -1018,7 +1052,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
           if (q < qmax && have_eprev) {
             const double r = ipow(hstep / C[Ctl::kHprev], q + 1);
             const double c = rcp((q + 2) * harmonic(q + 1));
-            const double lte2 = c * c * wrms2(W, e - r * eprev, ewt, inv_n);
+            const double lte2 = c * c * wrms2<S>(W, e - r * eprev, ewt, inv_n);
             const double eta_qp1 = W.uni(eta_from2(10.0, lte2, q + 2));
             if (eta_qp1 > eta) {
               eta = eta_qp1;
