@@ -205,6 +205,11 @@ typedef struct {
   int64_t sample_cells;    /* bdfx_autotune(): cells timed */
   float ms;                /* bdfx_autotune(): time of the fastest shape on the sample */
   int32_t cells_per_wave;  /* 1, or 2 for mechanisms of at most 32 species */
+  int32_t tables;          /* out: where the reaction tables of this launch live, chosen by
+                              occupancy: 1 all in LDS; 0 slot words read from global memory;
+                              2 slot words and the cell's rate constants in global memory
+                              (a per-wave workspace slot; work-queue scheduler, one cell per
+                              wave, 32 species or more).  Ignored by bdfx_set_tuning(). */
 } bdfx_tuning;
 
 /* Autotuner: for every mechanism, times each candidate launch shape
@@ -221,6 +226,11 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
 /* Apply launch shapes chosen earlier (for example cached results of
  * bdfx_autotune()); entries name their mechanism; the rest are ignored. */
 int bdfx_set_tuning(bdfx_ctx ctx, const bdfx_tuning *tunings, int32_t n);
+/* The launch shape in effect for every mechanism (after bdfx_bind(),
+ * bdfx_autotune() or bdfx_set_tuning()), in launch order: out[k] for
+ * k < min(n, n_mech); sample_cells and ms are 0 unless the shape came from
+ * bdfx_autotune() in this binding.  Host-only. */
+int bdfx_get_tuning(bdfx_ctx ctx, bdfx_tuning *out, int32_t n);
 
 /* Library version string. */
 const char *bdfx_version(void);

@@ -28,7 +28,7 @@ CELL_STATUS = {0: "success", -1: "too_much_work", -3: "err_failure", -4: "conv_f
 EXPORTED = ["bdfx_create", "bdfx_set_stream", "bdfx_destroy", "bdfx_last_error",
             "bdfx_mech_create", "bdfx_mech_destroy", "bdfx_mech_set_weights", "bdfx_plan",
             "bdfx_bind", "bdfx_integrate", "bdfx_perturb", "bdfx_stats_summary",
-            "bdfx_adjoint", "bdfx_autotune", "bdfx_set_tuning", "bdfx_version"]
+            "bdfx_adjoint", "bdfx_autotune", "bdfx_set_tuning", "bdfx_get_tuning", "bdfx_version"]
 
 
 class MechDesc(C.Structure):
@@ -56,7 +56,8 @@ class Summary(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("mech", C.c_int32), ("waves_per_simd", C.c_int32),
                 ("waves_per_block", C.c_int32), ("queue_chunk", C.c_int32),
-                ("sample_cells", C.c_int64), ("ms", C.c_float), ("cells_per_wave", C.c_int32)]
+                ("sample_cells", C.c_int64), ("ms", C.c_float), ("cells_per_wave", C.c_int32),
+                ("tables", C.c_int32)]
 
 
 STATS_DTYPE = np.dtype([("status", np.int32), ("nst", np.int32), ("nfe", np.int32),
@@ -91,6 +92,7 @@ def lib():
             "bdfx_adjoint": ([P, P, P, P], C.c_int),
             "bdfx_autotune": ([P, C.c_double, C.c_double, I64, C.POINTER(Tuning)], C.c_int),
             "bdfx_set_tuning": ([P, C.POINTER(Tuning), I32], C.c_int),
+            "bdfx_get_tuning": ([P, C.POINTER(Tuning), I32], C.c_int),
             "bdfx_version": ([], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -210,12 +212,18 @@ def bdfx_adjoint(ctx, ybar_ptr, y0bar_ptr, lnA_bar_ptr):
 
 
 _TUNING_KEYS = ("mech", "waves_per_simd", "waves_per_block", "queue_chunk", "cells_per_wave",
-                "sample_cells", "ms")
+                "sample_cells", "ms", "tables")
 
 
 def bdfx_autotune(ctx, n_mech: int, t0: float, t_out: float, sample_cells: int = 0) -> list:
     out = (Tuning * max(n_mech, 1))()
     _check(lib().bdfx_autotune(ctx, float(t0), float(t_out), int(sample_cells), out), ctx)
+    return [{k: getattr(t, k) for k in _TUNING_KEYS} for t in out[:n_mech]]
+
+
+def bdfx_get_tuning(ctx, n_mech: int) -> list:
+    out = (Tuning * max(n_mech, 1))()
+    _check(lib().bdfx_get_tuning(ctx, out, n_mech), ctx)
     return [{k: getattr(t, k) for k in _TUNING_KEYS} for t in out[:n_mech]]
 
 
@@ -326,6 +334,10 @@ class Integrator:
                 json.dump(db, fh, indent=1, sort_keys=True)
             os.replace(tmp, cache)
         return res
+
+    def tuning(self):
+        """Launch shape in effect per mechanism (bdfx_get_tuning())."""
+        return bdfx_get_tuning(self.ctx, len(self.mechs))
 
     def outer_loop(self, n_outer, dt, seed, amplitude, t0=0.0):
         """Operator-splitting outer loop on the current stream: for k = 0 ..

@@ -85,6 +85,8 @@ struct Params {
   int32_t use_queue;      // 0: one cell per wave from the grid index; 1: work queue
   uint32_t *queue;
   int32_t chunk;
+  double *kk_slots;       // [waves][2R] rate constants of each wave's cell (tables in global memory)
+  int64_t kk_nslots;      // waves the slot array can hold
   // accepted-step records for the adjoint (rec == nullptr: off)
   double *rec;            // [N][cap][stride]: y (n_sp), h, q | rebuild << 8
   int32_t rec_cap, rec_stride;
@@ -473,35 +475,50 @@ struct Lds {
   double *fb;   // [64] right-hand-side accumulator
   double *C;    // [Ctl::kSize]
   int *perm;    // [64] pivot row of each elimination step
-  double *kk;   // [2R]: k_f at 2r, -k_r at 2r+1
+  double *kk;   // [2R]: k_f at 2r, -k_r at 2r+1 (LDS, or the wave's slot in global memory)
   const int2 *rx;  // [R]: reactant / product slot words (an LDS copy, or the mechanism's table)
   void *fac;    // [S][S] inverse Newton matrix (LT), column-major: (r, c) at c*S + r
 };
 
+// Where a wave keeps the tables its inner loops read: the reaction slot words
+// (copied per cell, or read from the mechanism's table) and the cell's rate
+// constants (LDS, or the wave's own slot of a global array, which each lane
+// writes and reads back for its own reactions only).  Placements that leave
+// tables in global memory free LDS where LDS limits the resident waves.
+enum : int {
+  kTabRxGlobal = 0,  // slot words in global memory, rate constants in LDS
+  kTabLds = 1,       // both in LDS
+  kTabGlobal = 2,    // both in global memory (persistent waves only)
+};
+
 // doubles of LDS per wave for S species, R reactions, factor type size and
-// whether the slot words are copied to LDS
-__host__ __device__ constexpr int lds_doubles(int S, int R, int lt_bytes, bool rx_lds = true) {
-  return 2 * kWave + 8 + Ctl::kSize + kWave / 2 + (rx_lds ? 3 : 2) * R + (S * S * lt_bytes + 7) / 8;
+// table placement
+__host__ __device__ constexpr int lds_doubles(int S, int R, int lt_bytes, int tab = kTabLds) {
+  return 2 * kWave + 8 + Ctl::kSize + kWave / 2 + (tab == kTabLds ? R : 0) +
+         (tab == kTabGlobal ? 0 : 2 * R) + (S * S * lt_bytes + 7) / 8;
 }
 
-// RXL: the reaction slot words live in LDS (copied per cell) or are read from
-// the mechanism's table in global memory (saves R words of LDS per wave where
-// LDS limits the resident waves).
-template <bool RXL>
-__device__ __forceinline__ Lds carve(double *base, int R, const int32_t *mech_rx) {
+template <int TAB>
+__device__ __forceinline__ Lds carve(double *base, int R, const int32_t *mech_rx, double *kk_slot) {
   Lds L;
   L.yb = base;
   L.fb = base + kWave + 8;
   L.C = L.fb + kWave;
   L.perm = reinterpret_cast<int *>(L.C + Ctl::kSize);
-  L.kk = L.C + Ctl::kSize + kWave / 2;
-  if constexpr (RXL) {
-    L.rx = reinterpret_cast<const int2 *>(L.kk + 2 * R);
-    L.fac = L.kk + 3 * R;
+  double *next = L.C + Ctl::kSize + kWave / 2;
+  if constexpr (TAB == kTabGlobal) {
+    L.kk = kk_slot;
+  } else {
+    L.kk = next;
+    next += 2 * R;
+  }
+  if constexpr (TAB == kTabLds) {
+    L.rx = reinterpret_cast<const int2 *>(next);
+    next += R;
   } else {
     L.rx = reinterpret_cast<const int2 *>(mech_rx);
-    L.fac = L.kk + 2 * R;
   }
+  L.fac = next;
   return L;
 }
 
@@ -734,12 +751,12 @@ __device__ __forceinline__ double wrms2(const Grp<G> &W, double v, double w, dou
   return W.uni(W.template sum<(S + 15) / 16>(t * t) * inv_n);
 }
 
-template <int S, typename LT, bool RXL, int G>
+template <int S, typename LT, int TAB, int G>
 __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, const Grp<G> &W,
-                                               double *lds) {
+                                               double *lds, double *kk_slot) {
   const MechDev &m = P.mech;
   const int R = m.R;
-  const Lds L = carve<RXL>(lds, R, m.rx);
+  const Lds L = carve<TAB>(lds, R, m.rx, kk_slot);
   if (W.lane == 0) L.yb[kEmptySlot] = 1.0;  // empty reaction slots multiply by 1
   double *const C = L.C;
   const int n = P.n_sp;
@@ -758,7 +775,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
     if (P.kscale) kf *= P.kscale[cell * P.ldk + r];
     L.kk[2 * r] = kf;
     L.kk[2 * r + 1] = m.reversible ? -(kf * exp(-m.lnK[r])) : -0.0;
-    if constexpr (RXL) const_cast<int2 *>(L.rx)[r] = reinterpret_cast<const int2 *>(m.rx)[r];
+    if constexpr (TAB == kTabLds) const_cast<int2 *>(L.rx)[r] = reinterpret_cast<const int2 *>(m.rx)[r];
   }
 
   const double yin = own ? P.y[cell * P.ldy + W.lane] : 0.0;
@@ -1209,7 +1226,7 @@ template <int S>
 __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int li, double *lds) {
   const MechDev &m = P.mech;
   const int R = m.R;
-  const Lds L = carve<true>(lds, R, m.rx);
+  const Lds L = carve<kTabLds>(lds, R, m.rx, nullptr);
   const Grp<1> W1(li);
   double *vb = reinterpret_cast<double *>(L.fac) + S * S;  // [64 + 8], vb[kEmptySlot] = 0
   double *pb = vb + kWave + 8;

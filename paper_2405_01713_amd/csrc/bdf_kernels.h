@@ -13,16 +13,21 @@ namespace bdfx {
 
 // MINW: minimum resident waves per SIMD the register allocation must allow
 // (1 = compiler's choice; 3 = at most 168 VGPRs, 4 = at most 128, spilling
-// if needed).  RXL: reaction slot words copied to LDS (see carve).  G: cells
-// per wave (2: each half-wave integrates its own cell, S <= 32); each group
-// has its own LDS area of P.lds_doubles and pops its own cells.
-template <int S, typename LT, int MINW, bool RXL, int G>
+// if needed).  TAB: placement of the reaction tables (kTab*).  G: cells per
+// wave (2: each half-wave integrates its own cell, S <= 32); each group has
+// its own LDS area of P.lds_doubles and pops its own cells.  With the tables
+// in global memory, wave w of the grid owns rate-constant slot w (the host
+// guarantees that the grid's waves fit the slot array).
+template <int S, typename LT, int MINW, int TAB, int G>
 __global__ void __launch_bounds__(256, MINW) k_integrate(Params P) {
   extern __shared__ double smem[];
   const int wib = threadIdx.x / kWave;
   const Grp<G> W(threadIdx.x & (kWave - 1));
   const int wpb = blockDim.x / kWave;
   double *lds = smem + static_cast<int64_t>(wib * G + W.grp) * P.lds_doubles;
+  double *kk_slot = nullptr;
+  if constexpr (TAB == kTabGlobal)
+    kk_slot = P.kk_slots + ((static_cast<int64_t>(blockIdx.x) * wpb + wib) * G + W.grp) * (2 * P.mech.R);
   int64_t next = 0, stop = 0;
   if (!P.use_queue) {
     next = (static_cast<int64_t>(blockIdx.x) * wpb + wib) * G + W.grp;
@@ -39,7 +44,7 @@ __global__ void __launch_bounds__(256, MINW) k_integrate(Params P) {
     if (next >= P.n_list) break;
     const int64_t cell = P.list ? P.list[next] : next;
     ++next;
-    integrate_cell<S, LT, RXL, G>(P, cell, W, lds);
+    integrate_cell<S, LT, TAB, G>(P, cell, W, lds, kk_slot);
   }
 }
 
@@ -58,37 +63,51 @@ struct LaunchCfg {
   size_t lds_bytes;
 };
 
-// the integrator kernel for (LU precision, register budget, slot words in
-// LDS, cells per wave); nullptr where no such variant is built
+// the integrator kernel for (LU precision, register budget, table placement,
+// cells per wave); nullptr where no such variant is built (two cells per wave
+// only with the tables in LDS; tables in global memory only for sizes whose
+// LDS can limit the resident waves)
 template <int S>
-const void *integrate_kernel(bool fp32, int minw, bool rx_lds, int cells_per_wave) {
+const void *integrate_kernel(bool fp32, int minw, int tab, int cells_per_wave) {
   using F = const void *;
   const int w = minw >= 4 ? 2 : minw >= 3 ? 1 : 0;
+  if (tab < kTabRxGlobal || tab > kTabGlobal) return nullptr;
   if (cells_per_wave == 2) {
     if constexpr (S <= 32) {
       static const F tab2[2][3] = {
-          {F(&k_integrate<S, double, 1, true, 2>), F(&k_integrate<S, double, 3, true, 2>),
-           F(&k_integrate<S, double, 4, true, 2>)},
-          {F(&k_integrate<S, float, 1, true, 2>), F(&k_integrate<S, float, 3, true, 2>),
-           F(&k_integrate<S, float, 4, true, 2>)}};
-      return rx_lds ? tab2[fp32 ? 1 : 0][w] : nullptr;
+          {F(&k_integrate<S, double, 1, kTabLds, 2>), F(&k_integrate<S, double, 3, kTabLds, 2>),
+           F(&k_integrate<S, double, 4, kTabLds, 2>)},
+          {F(&k_integrate<S, float, 1, kTabLds, 2>), F(&k_integrate<S, float, 3, kTabLds, 2>),
+           F(&k_integrate<S, float, 4, kTabLds, 2>)}};
+      return tab == kTabLds ? tab2[fp32 ? 1 : 0][w] : nullptr;
     }
     return nullptr;
   }
-  static const F tab[2][3][2] = {
-      {{F(&k_integrate<S, double, 1, false, 1>), F(&k_integrate<S, double, 1, true, 1>)},
-       {F(&k_integrate<S, double, 3, false, 1>), F(&k_integrate<S, double, 3, true, 1>)},
-       {F(&k_integrate<S, double, 4, false, 1>), F(&k_integrate<S, double, 4, true, 1>)}},
-      {{F(&k_integrate<S, float, 1, false, 1>), F(&k_integrate<S, float, 1, true, 1>)},
-       {F(&k_integrate<S, float, 3, false, 1>), F(&k_integrate<S, float, 3, true, 1>)},
-       {F(&k_integrate<S, float, 4, false, 1>), F(&k_integrate<S, float, 4, true, 1>)}}};
-  return tab[fp32 ? 1 : 0][w][rx_lds ? 1 : 0];
+  if (tab == kTabGlobal) {
+    if constexpr (S >= 32) {
+      static const F tabg[2][3] = {
+          {F(&k_integrate<S, double, 1, kTabGlobal, 1>), F(&k_integrate<S, double, 3, kTabGlobal, 1>),
+           F(&k_integrate<S, double, 4, kTabGlobal, 1>)},
+          {F(&k_integrate<S, float, 1, kTabGlobal, 1>), F(&k_integrate<S, float, 3, kTabGlobal, 1>),
+           F(&k_integrate<S, float, 4, kTabGlobal, 1>)}};
+      return tabg[fp32 ? 1 : 0][w];
+    }
+    return nullptr;
+  }
+  static const F tab1[2][3][2] = {
+      {{F(&k_integrate<S, double, 1, kTabRxGlobal, 1>), F(&k_integrate<S, double, 1, kTabLds, 1>)},
+       {F(&k_integrate<S, double, 3, kTabRxGlobal, 1>), F(&k_integrate<S, double, 3, kTabLds, 1>)},
+       {F(&k_integrate<S, double, 4, kTabRxGlobal, 1>), F(&k_integrate<S, double, 4, kTabLds, 1>)}},
+      {{F(&k_integrate<S, float, 1, kTabRxGlobal, 1>), F(&k_integrate<S, float, 1, kTabLds, 1>)},
+       {F(&k_integrate<S, float, 3, kTabRxGlobal, 1>), F(&k_integrate<S, float, 3, kTabLds, 1>)},
+       {F(&k_integrate<S, float, 4, kTabRxGlobal, 1>), F(&k_integrate<S, float, 4, kTabLds, 1>)}}};
+  return tab1[fp32 ? 1 : 0][w][tab];
 }
 
 template <int S>
-hipError_t launch_integrate(const Params &P, bool fp32, int minw, bool rx_lds, int cells_per_wave,
+hipError_t launch_integrate(const Params &P, bool fp32, int minw, int tab, int cells_per_wave,
                             const LaunchCfg &c, hipStream_t s) {
-  const void *f = integrate_kernel<S>(fp32, minw, rx_lds, cells_per_wave);
+  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave);
   if (!f) return hipErrorInvalidDeviceFunction;
   Params arg = P;
   void *args[] = {&arg};
@@ -102,9 +121,9 @@ hipError_t launch_adjoint(const Params &P, const LaunchCfg &c, hipStream_t s) {
 }
 
 template <int S>
-hipError_t occupancy_integrate(bool fp32, int minw, bool rx_lds, int cells_per_wave, int block,
+hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave, int block,
                                size_t lds_bytes, int *blocks_per_cu) {
-  const void *f = integrate_kernel<S>(fp32, minw, rx_lds, cells_per_wave);
+  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave);
   if (!f) {
     *blocks_per_cu = 0;
     return hipSuccess;
@@ -116,21 +135,21 @@ hipError_t occupancy_integrate(bool fp32, int minw, bool rx_lds, int cells_per_w
 
 // One translation unit per species size (compiled in parallel).
 #define BDFX_DEFINE_SIZE(S)                                                                      \
-  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, bool rx_lds, int cpw,  \
+  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, int tab, int cpw,  \
                               const bdfx::LaunchCfg &c, hipStream_t s) {                         \
-    return bdfx::launch_integrate<S>(P, fp32, minw, rx_lds, cpw, c, s);                          \
+    return bdfx::launch_integrate<S>(P, fp32, minw, tab, cpw, c, s);                          \
   }                                                                                              \
-  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, bool rx_lds, int cpw, int block,           \
+  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, int block,           \
                                  size_t lds, int *out) {                                         \
-    return bdfx::occupancy_integrate<S>(fp32, minw, rx_lds, cpw, block, lds, out);               \
+    return bdfx::occupancy_integrate<S>(fp32, minw, tab, cpw, block, lds, out);               \
   }                                                                                              \
   hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s) { \
     return bdfx::launch_adjoint<S>(P, c, s);                                                     \
   }
 
 #define BDFX_DECLARE_SIZE(S)                                                                     \
-  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, bool rx_lds, int cpw,  \
+  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, int tab, int cpw,  \
                               const bdfx::LaunchCfg &c, hipStream_t s);                          \
-  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, bool rx_lds, int cpw, int block,           \
+  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, int block,           \
                                  size_t lds, int *out);                                          \
   hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s);

@@ -46,9 +46,9 @@ thread_local std::string g_create_error;
 
 struct SizeEntry {
   int S;
-  hipError_t (*launch)(const bdfx::Params &, bool, int, bool, int, const bdfx::LaunchCfg &,
+  hipError_t (*launch)(const bdfx::Params &, bool, int, int, int, const bdfx::LaunchCfg &,
                        hipStream_t);
-  hipError_t (*occupancy)(bool, int, bool, int, int, size_t, int *);
+  hipError_t (*occupancy)(bool, int, int, int, int, size_t, int *);
   hipError_t (*adjoint)(const bdfx::Params &, const bdfx::LaunchCfg &, hipStream_t);
 };
 
@@ -73,6 +73,9 @@ const SizeEntry *size_for(int S) {
 
 // largest per-bin sample the autotuner times (rows saved in the workspace)
 constexpr int64_t kTuneCells = 16384;
+// most waves one CU can hold (8 per SIMD): bounds the rate-constant slots of
+// persistent grids
+constexpr int64_t kMaxWavesPerCu = 32;
 
 struct bdfx_mech_s {
   bdfx_ctx ctx = nullptr;
@@ -94,7 +97,9 @@ struct Bin {
   // launch shape: from the options, or chosen by bdfx_autotune()
   int32_t waves_per_simd = 0, waves_per_block = 1, queue_chunk = 1, cells_per_wave = 1;
   bool tuned = false;
-  bool rx_lds = true;  // reaction slot words copied to LDS (else read from global memory)
+  int tab = bdfx::kTabLds;  // placement of the reaction tables (bdfx::kTab*)
+  int64_t tune_sample = 0;  // bdfx_autotune(): cells timed and time of the pick
+  float tune_ms = 0.0f;
 };
 
 struct bdfx_ctx_s {
@@ -112,8 +117,9 @@ struct bdfx_ctx_s {
   int S_max = 0, R_max = 0;
   size_t ws_need = 0;
   size_t off_queue = 0, off_bins = 0, off_rec = 0, off_recn = 0, off_rechpad = 0, off_recy0 = 0,
-         off_pbar = 0, off_tune = 0;
+         off_pbar = 0, off_tune = 0, off_kk = 0;
   int64_t tune_cells = 0;  // rows the autotuner can save in the workspace
+  int64_t kk_slots = 0;    // rate-constant slots (waves) for tables in global memory
   int rec_stride = 0;
   // bind
   char *ws = nullptr;
@@ -363,6 +369,11 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
   ctx->off_pbar = reserve(cap ? static_cast<size_t>(n_cells) * R_max * 8 : 0);
   ctx->tune_cells = std::min<int64_t>(n_cells, kTuneCells);
   ctx->off_tune = reserve(static_cast<size_t>(ctx->tune_cells) * S_max * 8);
+  // persistent grids may keep each wave's rate constants in global memory
+  ctx->kk_slots = o->scheduler == BDFX_SCHED_QUEUE
+                      ? std::min<int64_t>(static_cast<int64_t>(ctx->n_cu) * kMaxWavesPerCu, n_cells + 16)
+                      : 0;
+  ctx->off_kk = reserve(static_cast<size_t>(ctx->kk_slots) * 2 * R_max * 8);
   ctx->ws_need = off;
   *ws_bytes = off;
   ctx->planned = true;
@@ -445,29 +456,38 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
     return fail(ctx, BDFX_EUNSUPPORTED, "%d cells per wave with %d species", cpw, b.se->S);
   const int waves = std::max(b.waves_per_block, 1);
   b.cfg.block = bdfx::kWave * waves;
-  // slot words in LDS unless leaving them in global memory lets more waves
-  // reside (LDS-limited sizes; one cell per wave only)
-  int occ[2] = {0, 0};
-  size_t lds[2];
-  for (int k = 0; k < 2; ++k) {
+  const int64_t per_block = static_cast<int64_t>(waves) * cpw;
+  const int64_t need = (b.count + per_block - 1) / per_block;
+  // Tables in LDS unless leaving some in global memory lets more waves reside
+  // (LDS-limited sizes): first the slot words, then also the rate constants
+  // (persistent grids only, whose waves each own a slot).  Ties keep the
+  // tables in LDS.
+  int occ[3] = {0, 0, 0};
+  size_t lds[3];
+  int64_t grid[3] = {0, 0, 0};
+  for (int k : {bdfx::kTabLds, bdfx::kTabRxGlobal, bdfx::kTabGlobal}) {
     const int32_t d = static_cast<int32_t>(
-        align_up(bdfx::lds_doubles(b.se->S, m->R, fp32 ? 4 : 8, k == 1), 2));
+        align_up(bdfx::lds_doubles(b.se->S, m->R, fp32 ? 4 : 8, k), 2));
     lds[k] = static_cast<size_t>(waves) * cpw * d * 8;
-    if (lds[k] <= 65536 && (k == 1 || cpw == 1))
-      HIPCHK(ctx, b.se->occupancy(fp32, b.waves_per_simd, k == 1, cpw, b.cfg.block, lds[k],
-                                  &occ[k]));
+    if (lds[k] > 65536 || (k != bdfx::kTabLds && cpw != 1) || (k == bdfx::kTabGlobal && !queue))
+      continue;
+    HIPCHK(ctx, b.se->occupancy(fp32, b.waves_per_simd, k, cpw, b.cfg.block, lds[k], &occ[k]));
+    if (queue) {
+      const int per_cu = ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : std::max(occ[k], 1);
+      grid[k] = std::min<int64_t>(static_cast<int64_t>(per_cu) * ctx->n_cu, need);
+    }
+    if (k == bdfx::kTabGlobal && grid[k] * waves > ctx->kk_slots) occ[k] = 0;
   }
-  b.rx_lds = !(occ[0] > occ[1]);
-  const int k = b.rx_lds ? 1 : 0;
+  int k = bdfx::kTabLds;
+  if (occ[bdfx::kTabRxGlobal] > occ[k]) k = bdfx::kTabRxGlobal;
+  if (occ[bdfx::kTabGlobal] > occ[k]) k = bdfx::kTabGlobal;
+  b.tab = k;
   b.cfg.lds_bytes = lds[k];
   b.lds_doubles = static_cast<int32_t>(lds[k] / 8 / (waves * cpw));
   if (b.cfg.lds_bytes > 65536)
     return fail(ctx, BDFX_EUNSUPPORTED, "LDS per block %zu exceeds 64 KiB", b.cfg.lds_bytes);
-  const int64_t per_block = static_cast<int64_t>(waves) * cpw;
-  const int64_t need = (b.count + per_block - 1) / per_block;
   if (queue) {
-    const int per_cu = ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : std::max(occ[k], 1);
-    b.cfg.grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(per_cu) * ctx->n_cu, need));
+    b.cfg.grid = static_cast<int>(grid[k]);
   } else {
     if (need > INT32_MAX) return fail(ctx, BDFX_EUNSUPPORTED, "too many cells for one grid");
     b.cfg.grid = static_cast<int>(need);
@@ -517,6 +537,8 @@ static bdfx::Params make_params(bdfx_ctx ctx, const Bin &b, double t0, double to
   P.n_sp = m->S;
   P.queue = reinterpret_cast<uint32_t *>(ctx->ws + ctx->off_queue) + b.mech;
   P.chunk = b.queue_chunk;
+  P.kk_slots = ctx->kk_slots ? reinterpret_cast<double *>(ctx->ws + ctx->off_kk) : nullptr;
+  P.kk_nslots = ctx->kk_slots;
   if (ctx->opt.record_steps > 0) {
     P.rec = reinterpret_cast<double *>(ctx->ws + ctx->off_rec);
     P.rec_cap = ctx->opt.record_steps;
@@ -543,7 +565,7 @@ int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out) {
     bdfx::Params P = make_params(ctx, b, t0, t_out);
     P.use_queue = queue ? 1 : 0;
     P.lds_doubles = b.lds_doubles;
-    HIPCHK(ctx, b.se->launch(P, fp32, b.waves_per_simd, b.rx_lds, b.cells_per_wave, b.cfg,
+    HIPCHK(ctx, b.se->launch(P, fp32, b.waves_per_simd, b.tab, b.cells_per_wave, b.cfg,
                              ctx->stream));
   }
   ctx->last_t0 = t0;
@@ -568,6 +590,19 @@ int bdfx_perturb(bdfx_ctx ctx, uint64_t seed, int64_t outer_step, double amplitu
 // ---------------------------------------------------------------------------
 // autotuning of the launch shape
 // ---------------------------------------------------------------------------
+
+static bdfx_tuning tuning_of(const Bin &b) {
+  bdfx_tuning t{};
+  t.mech = b.mech;
+  t.waves_per_simd = b.waves_per_simd;
+  t.waves_per_block = b.waves_per_block;
+  t.queue_chunk = b.queue_chunk;
+  t.cells_per_wave = b.cells_per_wave;
+  t.sample_cells = b.tune_sample;
+  t.ms = b.tune_ms;
+  t.tables = b.tab;
+  return t;
+}
 
 int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, bdfx_tuning *out) {
   if (!ctx) return BDFX_EINVAL;
@@ -620,7 +655,7 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
             if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
             if (e == hipSuccess && queue) e = bdfx_launch_fill_u32(qctr, 64, 0u, ctx->stream);
             if (e == hipSuccess)
-              e = trial.se->launch(P, fp32, wps, trial.rx_lds, cpw, trial.cfg, ctx->stream);
+              e = trial.se->launch(P, fp32, wps, trial.tab, cpw, trial.cfg, ctx->stream);
             if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
             if (e == hipSuccess)
               e = bdfx_launch_copy_rows(ctx->y, ctx->ldy, P.list, trial.count, m->S, save, true,
@@ -646,16 +681,10 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
     b.queue_chunk = pick.queue_chunk;
     b.cells_per_wave = pick.cells_per_wave;
     b.tuned = true;
+    b.tune_sample = trial.count;
+    b.tune_ms = best / 2.0f;
     rc = configure_bin(ctx, b);
-    if (out) {
-      out[bi].mech = b.mech;
-      out[bi].waves_per_simd = b.waves_per_simd;
-      out[bi].waves_per_block = b.waves_per_block;
-      out[bi].queue_chunk = b.queue_chunk;
-      out[bi].cells_per_wave = b.cells_per_wave;
-      out[bi].sample_cells = trial.count;
-      out[bi].ms = best / 2.0f;
-    }
+    if (out) out[bi] = tuning_of(b);
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -682,9 +711,19 @@ int bdfx_set_tuning(bdfx_ctx ctx, const bdfx_tuning *t, int32_t n) {
         b.queue_chunk = t[k].queue_chunk;
         b.cells_per_wave = t[k].cells_per_wave;
         b.tuned = true;
+        b.tune_sample = 0;
+        b.tune_ms = 0.0f;
         if (const int rc = configure_bin(ctx, b)) return rc;
       }
   }
+  return BDFX_OK;
+}
+
+int bdfx_get_tuning(bdfx_ctx ctx, bdfx_tuning *out, int32_t n) {
+  if (!ctx || (n > 0 && !out) || n < 0) return BDFX_EINVAL;
+  if (!ctx->bound) return fail(ctx, BDFX_EORDER, "bdfx_bind must precede bdfx_get_tuning");
+  for (int32_t k = 0; k < n && k < static_cast<int32_t>(ctx->bins.size()); ++k)
+    out[k] = tuning_of(ctx->bins[k]);
   return BDFX_OK;
 }
 

@@ -77,6 +77,31 @@ def test_s53_fp32_lu_parity(oracle, parity):
     parity(y, yo, w)
 
 
+@pytest.mark.parametrize("lu,wps", [(64, 0), (32, 3)])
+def test_tables_in_global_memory(oracle, parity, lu, wps):
+    """53 species under the work queue: LDS limits the resident waves, so the
+    slot words and rate constants move to global memory (each persistent wave
+    owning a slot).  Results match the oracle and are bit-identical to the
+    static grid, which keeps the rate constants in LDS."""
+    import torch
+    from paper_2405_01713_amd import bdfx
+    w = W.make_workload("s53_r325_262k_fp32lu", 600)
+    integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"],
+                            scheduler=1, lu_precision=lu, waves_per_simd=wps)
+    assert integ.tuning()[0]["tables"] == 2
+    integ.integrate(0.0, w["t_out"])
+    torch.cuda.synchronize()
+    yq, stq = integ.state(), integ.cell_stats()
+    integ.close()
+    ys, sts = _gpu(w, lu_precision=lu, waves_per_simd=wps)
+    assert np.all(stq["status"] == 0)
+    assert np.array_equal(yq, ys) and np.array_equal(stq, sts)
+    idx = np.arange(0, 600, 6)
+    wo = dict(w, y0=w["y0"][idx], T=w["T"][idx], n_cells=len(idx))
+    yo, sto = _oracle(oracle, wo)
+    parity(yq[idx], yo, wo, f"global tables lu{lu}")
+
+
 def test_mixed_mechanisms_and_queue(oracle, parity):
     w = W.make_workload("mixed_s9_s53_1m", 300)
     ys, sts = _gpu(w)
