@@ -278,9 +278,9 @@ def _errors(y, yo, rtol, atol):
 
 
 def run_precision(steps, warmup, tuning_cache=None, n_cells=None, n_check=256):
-    """53 species / 325 reactions on 262,144 cells: FP64 vs FP32 Newton-matrix
-    inverse, both through the autotuned work queue; errors of both against the
-    FP64 oracle on the first n_check cells."""
+    """53 species / 325 reactions on 262,144 cells (or n_cells): FP64 vs FP32
+    Newton-matrix inverse, both through the autotuned work queue; errors of
+    both against the FP64 oracle on the first n_check cells."""
     from paper_2405_01713_amd import bdfx
 
     w = W.make_workload("s53_r325_262k_fp32lu", n_cells)
@@ -336,18 +336,18 @@ def _oracle_outer_loop(O, w, idx, n_outer, seed):
 def run_batching(steps, warmup, tuning_cache=None, n_cells=None, n_check=64, seed=3):
     """1,048,576 cells, half 9 / 30 and half 53 / 325, 10 outer splitting steps
     (1 % perturbation, then integration over 1e-5 s) captured in one HIP graph;
-    cells/s = 10 N / t_graph for the plain (static grid) and batched (work
-    queue, autotuned) forms; the first n_check cells are checked against the
-    oracle's composed loop."""
+    cells/s = 10 N / t_graph for the plain (static grid, FP64) and batched
+    (work queue, autotuned; FP64 and FP32 Newton matrix) forms; the first
+    n_check cells are checked against the oracle's composed loop."""
     from paper_2405_01713_amd import bdfx
 
     w = W.make_workload("mixed_s9_s53_1m", n_cells)
     n_outer = w["outer_steps"]
     out = dict(workload="mixed_s9_s53_1m", n_cells=w["n_cells"], outer_steps=n_outer)
     y_check = {}
-    for form, sched in (("plain", 0), ("batched", 1)):
+    for form, sched, lu in (("plain", 0, 64), ("batched", 1, 64), ("batched_fp32lu", 1, 32)):
         integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"],
-                                cell_mech=w["cell_mech"], scheduler=sched)
+                                cell_mech=w["cell_mech"], scheduler=sched, lu_precision=lu)
         tune = integ.autotune(0.0, w["t_out"], cache=tuning_cache) if sched else None
         y0 = integ.y.clone()
         g = integ.capture_outer_loop(n_outer, w["t_out"], seed, w["perturb"])
@@ -372,10 +372,12 @@ def run_batching(steps, warmup, tuning_cache=None, n_cells=None, n_check=64, see
                          tuning=tune, failed_cells=int(np.sum(st["status"] != 0)),
                          last_outer_step_nst=per_mech)
     out["speedup_batched_over_plain"] = out["plain"]["graph_ms"] / out["batched"]["graph_ms"]
+    out["speedup_batched_fp32lu_over_plain"] = (out["plain"]["graph_ms"] /
+                                                out["batched_fp32lu"]["graph_ms"])
     try:
         from oracle import oracle as O
         yo = _oracle_outer_loop(O, w, np.arange(n_check), n_outer, seed)
-        for form in ("plain", "batched"):
+        for form in ("plain", "batched", "batched_fp32lu"):
             out[form]["vs_oracle"] = _errors(y_check[form], yo, w["rtol"], w["atol"])
         out["check_cells"] = n_check
     except Exception as e:
@@ -410,7 +412,8 @@ def main():
                     help="skip the 53-species FP64 vs FP32-LU measurement")
     ap.add_argument("--extra", default="",
                     help="comma list of longer measurements: 'batching' (1 M mixed cells, "
-                         "10 outer steps in a HIP graph)")
+                         "10 outer steps in a HIP graph), 's53_1m' (1 M cells of the "
+                         "53-species mechanism, FP64 and FP32 Newton matrix)")
     ap.add_argument("--tuning-cache", default=None,
                     help="JSON file of autotuned launch shapes (reused when present)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
@@ -489,6 +492,8 @@ def main():
     extra = {}
     if "batching" in args.extra.split(","):
         extra["batching"] = run_batching(1, 1, tuning_cache=args.tuning_cache)
+    if "s53_1m" in args.extra.split(","):
+        extra["s53_1m"] = run_precision(1, 1, tuning_cache=args.tuning_cache, n_cells=1 << 20)
     ok = {k: v for k, v in forms.items() if v.get("parity_ok", True) and v["failed_cells"] == 0}
     best = max(ok or forms, key=lambda k: forms[k]["cells_per_s"])
     b = forms[best]

@@ -533,7 +533,25 @@ __device__ __forceinline__ int slot_species(int word, int s) { return (word >> (
 // accumulator with FP64 atomics.  Two passes of 64 reactions are processed
 // per loop iteration so that their LDS round trips overlap; lanes past R take
 // an all-empty slot word.  Lane i passes y_i, F_i and gets f_i.
+//
+// ABC: every reaction of the mechanism has the form A + B <=> C (reactant
+// slots 0 and 1 and product slot 0 occupied, the others empty), so the empty
+// slots are neither gathered nor tested.  The products and sums are formed in
+// the generic path's order (the empty slots there multiply by exactly 1) and
+// the atomics land in its order, so both paths give the same bits.
+template <bool ABC>
 __device__ __forceinline__ void rhs_reaction(const Lds &L, int r, int2 w) {
+  if constexpr (ABC) {
+#pragma clang fp contract(off)
+    const int a0 = slot_species(w.x, 0), a1 = slot_species(w.x, 1), b0 = slot_species(w.y, 0);
+    const double pf = L.kk[2 * r] * L.yb[a0] * L.yb[a1];
+    const double pr = L.kk[2 * r + 1] * L.yb[b0];
+    const double q = pf + pr;
+    atomicAdd(&L.fb[a0], -q);
+    atomicAdd(&L.fb[b0], q);
+    atomicAdd(&L.fb[a1], -q);
+    return;
+  }
   double pf = L.kk[2 * r], pr = L.kk[2 * r + 1];
   // empty slots read the 1.0 at yb[kEmptySlot]: the six gathers issue together
 #pragma unroll
@@ -550,7 +568,7 @@ __device__ __forceinline__ void rhs_reaction(const Lds &L, int r, int2 w) {
   }
 }
 
-template <int G>
+template <bool ABC, int G>
 __device__ __forceinline__ double rhs(const MechDev &m, const Lds &L, const Grp<G> &W, double yi,
                                       double Fi) {
   wave_lds_sync();
@@ -563,8 +581,8 @@ __device__ __forceinline__ double rhs(const MechDev &m, const Lds &L, const Grp<
     const int ra = r0 + W.lane, rb = ra + W.kLanes;
     const int2 wa = ra < R ? L.rx[ra] : none;
     const int2 wb = rb < R ? L.rx[rb] : none;
-    if (ra < R) rhs_reaction(L, ra, wa);
-    if (rb < R) rhs_reaction(L, rb, wb);
+    if (ra < R) rhs_reaction<ABC>(L, ra, wa);
+    if (rb < R) rhs_reaction<ABC>(L, rb, wb);
   }
   wave_lds_sync();
   return L.fb[W.lane];
@@ -580,7 +598,7 @@ __device__ __forceinline__ double rhs(const MechDev &m, const Lds &L, const Grp<
 // reaction (reactant slots count -1, product slots +1) with LDS atomics.
 // Each lane then reads its row (its column for M^T).  Terms are rounded to LT
 // before they are summed.
-template <int S, typename LT, int G>
+template <int S, typename LT, bool ABC = false, int G>
 __device__ __forceinline__ void newton_matrix(LT (&a)[S], const MechDev &m, const Lds &L, const Grp<G> &W,
                                               double yi, double gamma, bool transposed) {
   LT *M = reinterpret_cast<LT *>(L.fac);
@@ -591,6 +609,24 @@ __device__ __forceinline__ void newton_matrix(LT (&a)[S], const MechDev &m, cons
   wave_lds_sync();
   for (int r = W.lane; r < m.R; r += W.kLanes) {
     const int2 w = L.rx[r];
+    if constexpr (ABC) {
+      // columns A, B (forward side) and C (reverse side), each scattered
+      // into rows A, C, B: the generic path's terms in its order
+      const int a0 = slot_species(w.x, 0), a1 = slot_species(w.x, 1), b0 = slot_species(w.y, 0);
+      const double kf = L.kk[2 * r];
+      const int col[3] = {a0, a1, b0};
+      const double d[3] = {kf * L.yb[a1], kf * L.yb[a0], L.kk[2 * r + 1]};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (c == 2 && !m.reversible) break;
+        const LT g = static_cast<LT>(gamma * d[c]);
+        LT *Mc = M + col[c] * S;
+        atomicAdd(Mc + a0, g);
+        atomicAdd(Mc + b0, -g);
+        atomicAdd(Mc + a1, g);
+      }
+      continue;
+    }
     int sp[2][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -751,7 +787,7 @@ __device__ __forceinline__ double wrms2(const Grp<G> &W, double v, double w, dou
   return W.uni(W.template sum<(S + 15) / 16>(t * t) * inv_n);
 }
 
-template <int S, typename LT, int TAB, int G>
+template <int S, typename LT, int TAB, int G, bool ABC>
 __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, const Grp<G> &W,
                                                double *lds, double *kk_slot) {
   const MechDev &m = P.mech;
@@ -799,7 +835,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
   double f = 0.0, ewt = 0.0;
   if (status == kSuccess) {
     z[0] = yin;
-    f = rhs(m, L, W, yin, Fi);
+    f = rhs<ABC>(m, L, W, yin, Fi);
     nfe = 1;
     if (W.any(own && !isfinite(f))) {
       status = kNonfinite;
@@ -820,7 +856,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       double hg = sqrt(hlb * hub), hnew = hg;
       bool at_ub = false;
       for (int it = 0; it < 4; ++it) {
-        const double ft = rhs(m, L, W, yin + hg * f, Fi);
+        const double ft = rhs<ABC>(m, L, W, yin + hg * f, Fi);
         nfe++;
         const double ydd = (ft - f) / hg;
         const double yddnrm = sqrt(wrms2<S>(W, ydd, ewt, inv_n));
@@ -913,7 +949,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
         int info;
         {
           LT a[S];
-          newton_matrix<S, LT>(a, m, L, W, z[0], gamma, false);
+          newton_matrix<S, LT, ABC>(a, m, L, W, z[0], gamma, false);
           info = gj_invert<S, LT>(a, W, L);
         }
         nsetups++;
@@ -947,7 +983,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       const double tol2 = 0.01 * W.uni(rcp(Cerr * Cerr));
       e = 0.0;
       for (int mit = 0; mit < 3; ++mit) {
-        f = rhs(m, L, W, z[0] + e, Fi);
+        f = rhs<ABC>(m, L, W, z[0] + e, Fi);
         nfe++;
         nni++;
         const double Gi = e - gamma * f + z[1] * rl1;
@@ -997,7 +1033,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
         // restart at order 1 from the last accepted y
         const double hnew = W.uni(0.1 * h);
         q = 1;
-        const double f0 = rhs(m, L, W, z[0], Fi);
+        const double f0 = rhs<ABC>(m, L, W, z[0], Fi);
         nfe++;
 #pragma unroll
         for (int j = 2; j <= kQmax; ++j) z[j] = 0.0;

@@ -17,8 +17,9 @@ namespace bdfx {
 // wave (2: each half-wave integrates its own cell, S <= 32); each group has
 // its own LDS area of P.lds_doubles and pops its own cells.  With the tables
 // in global memory, wave w of the grid owns rate-constant slot w (the host
-// guarantees that the grid's waves fit the slot array).
-template <int S, typename LT, int MINW, int TAB, int G>
+// guarantees that the grid's waves fit the slot array).  ABC: every reaction
+// is A + B <=> C (see rhs_reaction).
+template <int S, typename LT, int MINW, int TAB, int G, bool ABC>
 __global__ void __launch_bounds__(256, MINW) k_integrate(Params P) {
   extern __shared__ double smem[];
   const int wib = threadIdx.x / kWave;
@@ -44,7 +45,7 @@ __global__ void __launch_bounds__(256, MINW) k_integrate(Params P) {
     if (next >= P.n_list) break;
     const int64_t cell = P.list ? P.list[next] : next;
     ++next;
-    integrate_cell<S, LT, TAB, G>(P, cell, W, lds, kk_slot);
+    integrate_cell<S, LT, TAB, G, ABC>(P, cell, W, lds, kk_slot);
   }
 }
 
@@ -63,51 +64,56 @@ struct LaunchCfg {
   size_t lds_bytes;
 };
 
-// the integrator kernel for (LU precision, register budget, table placement,
-// cells per wave); nullptr where no such variant is built (two cells per wave
-// only with the tables in LDS; tables in global memory only for sizes whose
-// LDS can limit the resident waves)
-template <int S>
-const void *integrate_kernel(bool fp32, int minw, int tab, int cells_per_wave) {
+// the three register budgets of one kernel configuration
+template <int S, typename LT, int TAB, int G, bool ABC>
+const void *by_budget(int w) {
   using F = const void *;
-  const int w = minw >= 4 ? 2 : minw >= 3 ? 1 : 0;
-  if (tab < kTabRxGlobal || tab > kTabGlobal) return nullptr;
+  static const F t[3] = {F(&k_integrate<S, LT, 1, TAB, G, ABC>), F(&k_integrate<S, LT, 3, TAB, G, ABC>),
+                         F(&k_integrate<S, LT, 4, TAB, G, ABC>)};
+  return t[w];
+}
+
+template <int S, bool ABC>
+const void *integrate_kernel_abc(bool fp32, int w, int tab, int cells_per_wave) {
   if (cells_per_wave == 2) {
     if constexpr (S <= 32) {
-      static const F tab2[2][3] = {
-          {F(&k_integrate<S, double, 1, kTabLds, 2>), F(&k_integrate<S, double, 3, kTabLds, 2>),
-           F(&k_integrate<S, double, 4, kTabLds, 2>)},
-          {F(&k_integrate<S, float, 1, kTabLds, 2>), F(&k_integrate<S, float, 3, kTabLds, 2>),
-           F(&k_integrate<S, float, 4, kTabLds, 2>)}};
-      return tab == kTabLds ? tab2[fp32 ? 1 : 0][w] : nullptr;
+      if (tab != kTabLds) return nullptr;
+      return fp32 ? by_budget<S, float, kTabLds, 2, ABC>(w) : by_budget<S, double, kTabLds, 2, ABC>(w);
     }
     return nullptr;
   }
-  if (tab == kTabGlobal) {
-    if constexpr (S >= 32) {
-      static const F tabg[2][3] = {
-          {F(&k_integrate<S, double, 1, kTabGlobal, 1>), F(&k_integrate<S, double, 3, kTabGlobal, 1>),
-           F(&k_integrate<S, double, 4, kTabGlobal, 1>)},
-          {F(&k_integrate<S, float, 1, kTabGlobal, 1>), F(&k_integrate<S, float, 3, kTabGlobal, 1>),
-           F(&k_integrate<S, float, 4, kTabGlobal, 1>)}};
-      return tabg[fp32 ? 1 : 0][w];
-    }
-    return nullptr;
+  if (cells_per_wave != 1) return nullptr;
+  switch (tab) {
+    case kTabRxGlobal:
+      return fp32 ? by_budget<S, float, kTabRxGlobal, 1, ABC>(w)
+                  : by_budget<S, double, kTabRxGlobal, 1, ABC>(w);
+    case kTabLds:
+      return fp32 ? by_budget<S, float, kTabLds, 1, ABC>(w) : by_budget<S, double, kTabLds, 1, ABC>(w);
+    case kTabGlobal:
+      if constexpr (S >= 32)
+        return fp32 ? by_budget<S, float, kTabGlobal, 1, ABC>(w)
+                    : by_budget<S, double, kTabGlobal, 1, ABC>(w);
+      return nullptr;
+    default:
+      return nullptr;
   }
-  static const F tab1[2][3][2] = {
-      {{F(&k_integrate<S, double, 1, kTabRxGlobal, 1>), F(&k_integrate<S, double, 1, kTabLds, 1>)},
-       {F(&k_integrate<S, double, 3, kTabRxGlobal, 1>), F(&k_integrate<S, double, 3, kTabLds, 1>)},
-       {F(&k_integrate<S, double, 4, kTabRxGlobal, 1>), F(&k_integrate<S, double, 4, kTabLds, 1>)}},
-      {{F(&k_integrate<S, float, 1, kTabRxGlobal, 1>), F(&k_integrate<S, float, 1, kTabLds, 1>)},
-       {F(&k_integrate<S, float, 3, kTabRxGlobal, 1>), F(&k_integrate<S, float, 3, kTabLds, 1>)},
-       {F(&k_integrate<S, float, 4, kTabRxGlobal, 1>), F(&k_integrate<S, float, 4, kTabLds, 1>)}}};
-  return tab1[fp32 ? 1 : 0][w][tab];
+}
+
+// the integrator kernel for (LU precision, register budget, table placement,
+// cells per wave, A + B <=> C mechanism); nullptr where no such variant is
+// built (two cells per wave only with the tables in LDS; tables in global
+// memory only for sizes whose LDS can limit the resident waves)
+template <int S>
+const void *integrate_kernel(bool fp32, int minw, int tab, int cells_per_wave, bool abc) {
+  const int w = minw >= 4 ? 2 : minw >= 3 ? 1 : 0;
+  return abc ? integrate_kernel_abc<S, true>(fp32, w, tab, cells_per_wave)
+             : integrate_kernel_abc<S, false>(fp32, w, tab, cells_per_wave);
 }
 
 template <int S>
 hipError_t launch_integrate(const Params &P, bool fp32, int minw, int tab, int cells_per_wave,
-                            const LaunchCfg &c, hipStream_t s) {
-  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave);
+                            bool abc, const LaunchCfg &c, hipStream_t s) {
+  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc);
   if (!f) return hipErrorInvalidDeviceFunction;
   Params arg = P;
   void *args[] = {&arg};
@@ -121,9 +127,9 @@ hipError_t launch_adjoint(const Params &P, const LaunchCfg &c, hipStream_t s) {
 }
 
 template <int S>
-hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave, int block,
-                               size_t lds_bytes, int *blocks_per_cu) {
-  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave);
+hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave, bool abc,
+                               int block, size_t lds_bytes, int *blocks_per_cu) {
+  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc);
   if (!f) {
     *blocks_per_cu = 0;
     return hipSuccess;
@@ -135,21 +141,21 @@ hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave,
 
 // One translation unit per species size (compiled in parallel).
 #define BDFX_DEFINE_SIZE(S)                                                                      \
-  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, int tab, int cpw,  \
-                              const bdfx::LaunchCfg &c, hipStream_t s) {                         \
-    return bdfx::launch_integrate<S>(P, fp32, minw, tab, cpw, c, s);                          \
+  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, int tab, int cpw,      \
+                              bool abc, const bdfx::LaunchCfg &c, hipStream_t s) {               \
+    return bdfx::launch_integrate<S>(P, fp32, minw, tab, cpw, abc, c, s);                        \
   }                                                                                              \
-  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, int block,           \
+  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, bool abc, int block,     \
                                  size_t lds, int *out) {                                         \
-    return bdfx::occupancy_integrate<S>(fp32, minw, tab, cpw, block, lds, out);               \
+    return bdfx::occupancy_integrate<S>(fp32, minw, tab, cpw, abc, block, lds, out);             \
   }                                                                                              \
   hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s) { \
     return bdfx::launch_adjoint<S>(P, c, s);                                                     \
   }
 
 #define BDFX_DECLARE_SIZE(S)                                                                     \
-  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, int tab, int cpw,  \
-                              const bdfx::LaunchCfg &c, hipStream_t s);                          \
-  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, int block,           \
+  hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, int tab, int cpw,      \
+                              bool abc, const bdfx::LaunchCfg &c, hipStream_t s);                \
+  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, bool abc, int block,     \
                                  size_t lds, int *out);                                          \
   hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s);

@@ -46,9 +46,9 @@ thread_local std::string g_create_error;
 
 struct SizeEntry {
   int S;
-  hipError_t (*launch)(const bdfx::Params &, bool, int, int, int, const bdfx::LaunchCfg &,
+  hipError_t (*launch)(const bdfx::Params &, bool, int, int, int, bool, const bdfx::LaunchCfg &,
                        hipStream_t);
-  hipError_t (*occupancy)(bool, int, int, int, int, size_t, int *);
+  hipError_t (*occupancy)(bool, int, int, int, bool, int, size_t, int *);
   hipError_t (*adjoint)(const bdfx::Params &, const bdfx::LaunchCfg &, hipStream_t);
 };
 
@@ -81,6 +81,7 @@ struct bdfx_mech_s {
   bdfx_ctx ctx = nullptr;
   int S = 0, R = 0;
   bool reversible = false;
+  bool abc = false;  // every reaction A + B <=> C (specialised kernels)
   void *dmem = nullptr;
   bdfx::MechDev dev{};
   std::vector<double> w;
@@ -226,6 +227,10 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
     rx[2 * r + 1] = static_cast<int32_t>(wp);
   }
   const bool reversible = d->lnK != nullptr;
+  bool abc = true;
+  for (int r = 0; r < R && abc; ++r)
+    abc = d->reac[r * 3] >= 0 && d->reac[r * 3 + 1] >= 0 && d->reac[r * 3 + 2] < 0 &&
+          d->prod[r * 3] >= 0 && d->prod[r * 3 + 1] < 0 && d->prod[r * 3 + 2] < 0;
 
   std::vector<double> lnA(d->lnA, d->lnA + R), EaR(R, 0.0), lnK(R, 0.0), w(S, 1.0);
   if (d->EaR) EaR.assign(d->EaR, d->EaR + R);
@@ -262,6 +267,7 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
   m->S = S;
   m->R = R;
   m->reversible = reversible;
+  m->abc = abc;
   m->dmem = dmem;
   m->w = w;
   bdfx::MechDev &dv = m->dev;
@@ -471,7 +477,8 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
     lds[k] = static_cast<size_t>(waves) * cpw * d * 8;
     if (lds[k] > 65536 || (k != bdfx::kTabLds && cpw != 1) || (k == bdfx::kTabGlobal && !queue))
       continue;
-    HIPCHK(ctx, b.se->occupancy(fp32, b.waves_per_simd, k, cpw, b.cfg.block, lds[k], &occ[k]));
+    HIPCHK(ctx, b.se->occupancy(fp32, b.waves_per_simd, k, cpw, m->abc, b.cfg.block, lds[k],
+                                &occ[k]));
     if (queue) {
       const int per_cu = ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : std::max(occ[k], 1);
       grid[k] = std::min<int64_t>(static_cast<int64_t>(per_cu) * ctx->n_cu, need);
@@ -565,8 +572,8 @@ int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out) {
     bdfx::Params P = make_params(ctx, b, t0, t_out);
     P.use_queue = queue ? 1 : 0;
     P.lds_doubles = b.lds_doubles;
-    HIPCHK(ctx, b.se->launch(P, fp32, b.waves_per_simd, b.tab, b.cells_per_wave, b.cfg,
-                             ctx->stream));
+    HIPCHK(ctx, b.se->launch(P, fp32, b.waves_per_simd, b.tab, b.cells_per_wave,
+                             ctx->mechs[b.mech]->abc, b.cfg, ctx->stream));
   }
   ctx->last_t0 = t0;
   ctx->last_tout = t_out;
@@ -655,7 +662,7 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
             if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
             if (e == hipSuccess && queue) e = bdfx_launch_fill_u32(qctr, 64, 0u, ctx->stream);
             if (e == hipSuccess)
-              e = trial.se->launch(P, fp32, wps, trial.tab, cpw, trial.cfg, ctx->stream);
+              e = trial.se->launch(P, fp32, wps, trial.tab, cpw, m->abc, trial.cfg, ctx->stream);
             if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
             if (e == hipSuccess)
               e = bdfx_launch_copy_rows(ctx->y, ctx->ldy, P.list, trial.count, m->S, save, true,

@@ -352,6 +352,28 @@ def test_three_body_and_repeated_species(oracle, parity):
     assert np.abs(inv1 - inv0).max() <= 1e-12 * np.abs(inv0).max()
 
 
+@pytest.mark.parametrize("lu", [64, 32])
+def test_abc_specialisation_matches_generic(oracle, parity, lu):
+    """A + B <=> C mechanisms run specialised kernels (two reactant slots and
+    one product slot, no empty-slot work).  The same mechanism with its
+    product moved to slot 1 is not recognised as such and runs the generic
+    slot loops; both match the oracle, and the same terms only land in another
+    order (so results agree to rounding)."""
+    m = W.synthetic_mechanism(21, 84)
+    g = dict(m, prod=np.roll(m["prod"], 1, axis=1))
+    assert np.all(g["prod"][:, 1] == m["prod"][:, 0]) and np.all(g["prod"][:, 0] == -1)
+    c = W.cell_states(m, 256, seed=13, T_range=(1000.0, 2500.0))
+    w = dict(mechs=[m], y0=c["y0"], T=c["T"], rtol=1e-6, atol=1e-10, t_out=1e-5)
+    ya, sta = _gpu(w, scheduler=1, lu_precision=lu)
+    yg, stg = _gpu(dict(w, mechs=[g]), scheduler=1, lu_precision=lu)
+    assert np.all(sta["status"] == 0) and np.all(stg["status"] == 0)
+    yo, sto = _oracle(oracle, w)
+    parity(ya, yo, w, f"A+B<=>C kernels lu{lu}")
+    parity(yg, yo, w, f"generic kernels lu{lu}")
+    tol = 10 * 1e-6 * np.abs(yo) + 1e-10
+    assert np.mean(np.abs(ya - yg) <= tol) >= 0.99
+
+
 def test_largest_size_all_lanes(oracle, parity):
     """64 species: every lane of the wave holds a species."""
     m = W.synthetic_mechanism(64, 150, 5)
