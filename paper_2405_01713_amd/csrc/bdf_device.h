@@ -447,6 +447,19 @@ __device__ __forceinline__ double eta_from2(double bias, double err2, int p) {
   return rcp(root_p(bias * bias * err2, 2 * p) + 1.0e-6);
 }
 
+// eta_from2(6, err2, p) >= 1.5 needs (36 err2)^(1/(2p)) <= 2/3 - 1e-6, i.e.
+// 36 err2 <= (2/3 - 1e-6)^(2p).  hold_bound(p) is that bound raised by 1e-9
+// relative (far above the rounding of either side): above it, eta < 1.5 for
+// certain and the root need not be taken.
+__device__ __forceinline__ double hold_bound(int p) {
+  constexpr double c = 2.0 / 3.0 - 1.0e-6;
+  constexpr double c2 = c * c, c4 = c2 * c2, c8 = c4 * c4;
+  double b = (p & 1) ? c2 : 1.0;
+  if (p & 2) b *= c4;
+  if (p & 4) b *= c8;
+  return b * (1.0 + 1.0e-9);
+}
+
 __device__ __forceinline__ double ipow(double x, int k) {
   double r = 1.0;
   for (int i = 0; i < k; ++i) r *= x;
@@ -1088,7 +1101,9 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       if (eta_max == 1.0) {
         if (qwait < 2) qwait = 2;  // right after a failure: hold h and q
       } else {
-        double eta = W.uni(eta_from2(6.0, dsm2, q + 1));
+        // without an order decision this step, h changes only if eta >= 1.5
+        double eta = 0.0;
+        if (qwait == 0 || 36.0 * dsm2 <= hold_bound(q + 1)) eta = W.uni(eta_from2(6.0, dsm2, q + 1));
         int qnew = q;
         if (qwait == 0) {
           qwait = 2;
