@@ -344,3 +344,34 @@ def perturb(y, n_species_of_cell, weights_of_cell, seed, step, amp):
                             int(step), float(amp))
     del uniq
     return y
+
+
+def typical_atol(y, eta, n_species, cell_mech=None):
+    """Typical-value absolute tolerances (Sec. 4.1.3, Eq. (eta)).
+
+    For each mechanism m and species i < n_species[m], the typical value is
+    half the sum of the smallest and largest y[c][i] over the cells c of
+    mechanism m, and atol[m][i] = eta * typical.  Where the typical value is
+    not positive (a species absent, or driven below zero, everywhere) the
+    paper's default for unmanaged values, a typical value of 1, is used.
+    Entries of a mechanism without cells, and beyond n_species[m], are left
+    at eta and at 0 (typical).  Returns (typical [n_mech][ldy],
+    atol [n_mech][ldy]); the arithmetic is 0.5 * (min + max), then * eta.
+    """
+    y = np.asarray(y, dtype=np.float64)
+    N, ldy = y.shape
+    n_species = [int(s) for s in np.atleast_1d(n_species)]
+    n_mech = len(n_species)
+    cm = np.zeros(N, dtype=np.int64) if cell_mech is None else np.asarray(cell_mech)
+    typ = np.zeros((n_mech, ldy))
+    atol = np.full((n_mech, ldy), float(eta))
+    for m in range(n_mech):
+        rows = y[cm == m]
+        if rows.shape[0] == 0:
+            continue
+        for i in range(n_species[m]):
+            lo, hi = np.min(rows[:, i]), np.max(rows[:, i])
+            t = 0.5 * (lo + hi)
+            typ[m, i] = t
+            atol[m, i] = (t if t > 0.0 else 1.0) * float(eta)
+    return typ, atol
