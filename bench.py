@@ -317,6 +317,59 @@ def run_precision(steps, warmup, tuning_cache=None, n_cells=None, n_check=256):
     return out
 
 
+def run_typical(tuning_cache=None, reps=50, eta=1e-10):
+    """Typical-value absolute tolerances (Sec. 4.1.3): the device min/max pass
+    over the states (HBM-bound; bytes = cells x species x 8 read) timed with
+    HIP events on the 21-species workload and on 1,048,576 cells of the
+    53-species mechanism, checked bit for bit against the oracle; then one
+    outer step of the 21-species workload integrated with those tolerances
+    (batched, FP32 Newton matrix) against the same run with atol = 1e-10."""
+    import torch
+    from paper_2405_01713_amd import bdfx
+
+    out = {}
+    for name, n in (("s21_r84_262k", None), ("s53_r325_262k_fp32lu", 1 << 20)):
+        w = W.make_workload(name, n)
+        S = w["mechs"][0]["n_species"]
+        integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"], scheduler=1)
+        typ = torch.empty((1, integ.S_max), dtype=torch.float64, device=integ.dev)
+        ms = _timed_events(lambda: integ.typical_atol(eta, typ), integ.stream, reps, 5)
+        nbytes = w["n_cells"] * S * 8
+        t_host = typ.cpu().numpy()
+        d = dict(n_cells=w["n_cells"], species=S, ms=ms, bytes=nbytes,
+                 gb_per_s=nbytes / (ms * 1e-3) / 1e9, frac_hbm=nbytes / (ms * 1e-3) / 8.0e12)
+        try:
+            from oracle import oracle as O
+            to, _ = O.typical_atol(w["y0"], eta, [S])
+            d["bit_exact_vs_oracle"] = bool(np.array_equal(t_host, to[:, :integ.S_max]))
+        except Exception as e:  # the oracle is optional on the timing path
+            d["check_error"] = repr(e)
+        integ.close()
+        out[name if n is None else f"{name}@{n}"] = d
+        log(f"typical {name}: {ms * 1e3:.1f} us, {d['gb_per_s']:.0f} GB/s")
+    w = W.make_workload("s21_r84_262k")
+    for mode in ("fixed", "typical"):
+        integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"], scheduler=1,
+                                lu_precision=32)
+        integ.autotune(0.0, w["t_out"], cache=tuning_cache)
+        y0 = integ.y.clone()
+
+        def step():
+            integ.y.copy_(y0)
+            if mode == "typical":
+                integ.typical_atol(eta)
+            integ.integrate(0.0, w["t_out"])
+
+        ms = _timed_events(step, integ.stream, 1, 1)
+        st = integ.cell_stats()
+        integ.close()
+        out[f"integrate_{mode}"] = dict(ms=ms, cells_per_s=w["n_cells"] / (ms * 1e-3),
+                                        mean_nst=float(st["nst"].mean()),
+                                        failed_cells=int(np.sum(st["status"] != 0)))
+        log(f"typical: integrate with {mode} atol {ms:.1f} ms")
+    return out
+
+
 def _oracle_outer_loop(O, w, idx, n_outer, seed):
     ms, cm = w["mechs"], w["cell_mech"][idx]
     y = w["y0"][idx].copy()
@@ -413,7 +466,8 @@ def main():
     ap.add_argument("--extra", default="",
                     help="comma list of longer measurements: 'batching' (1 M mixed cells, "
                          "10 outer steps in a HIP graph), 's53_1m' (1 M cells of the "
-                         "53-species mechanism, FP64 and FP32 Newton matrix)")
+                         "53-species mechanism, FP64 and FP32 Newton matrix), 'typical' "
+                         "(typical-value tolerances: reduction bandwidth and integration)")
     ap.add_argument("--tuning-cache", default=None,
                     help="JSON file of autotuned launch shapes (reused when present)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
@@ -494,6 +548,8 @@ def main():
         extra["batching"] = run_batching(1, 1, tuning_cache=args.tuning_cache)
     if "s53_1m" in args.extra.split(","):
         extra["s53_1m"] = run_precision(1, 1, tuning_cache=args.tuning_cache, n_cells=1 << 20)
+    if "typical" in args.extra.split(","):
+        extra["typical"] = run_typical(tuning_cache=args.tuning_cache)
     ok = {k: v for k, v in forms.items() if v.get("parity_ok", True) and v["failed_cells"] == 0}
     best = max(ok or forms, key=lambda k: forms[k]["cells_per_s"])
     b = forms[best]

@@ -178,6 +178,22 @@ int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out);
  * (w = d_weights of the cell's mechanism, see bdfx_mech_set_weights()).
  * Enqueue only. */
 int bdfx_perturb(bdfx_ctx ctx, uint64_t seed, int64_t outer_step, double amplitude);
+
+/* Typical-value absolute tolerances (Sec. 4.1.3, Eq. (eta)).  For every
+ * mechanism m and species i < S_m, the typical value ytyp[m][i] is
+ * 0.5 * (min + max) of y[c][i] over the bound cells c of mechanism m (their
+ * current states), and atol[m][i] = eta * ytyp[m][i], or eta where ytyp is
+ * not positive (a species absent everywhere; the paper's default typical
+ * value 1).  A NaN state entry makes ytyp NaN and atol eta.  Every later
+ * bdfx_integrate() uses these per-mechanism tolerances in place of the
+ * options' atol; calling again (e.g. every K outer steps) recomputes them
+ * from the current states; eta = 0 returns to the options' atol.  The choice
+ * of tolerance array is fixed into graphs captured meanwhile.
+ * d_typical: NULL, or device memory [n_mech][S_max] (S_max = largest species
+ * count of the plan) that receives ytyp (0 beyond S_m and for a mechanism
+ * without cells).  Enqueue only (two kernels, no allocation, capturable).
+ * Errors: BDFX_EINVAL for eta < 0 or not finite; BDFX_EORDER before bind. */
+int bdfx_typical_atol(bdfx_ctx ctx, double eta, double *d_typical);
 /* Species weights w [S] (host) used by bdfx_perturb(); default all ones. */
 int bdfx_mech_set_weights(bdfx_mech mech, const double *weights);
 

@@ -28,7 +28,8 @@ CELL_STATUS = {0: "success", -1: "too_much_work", -3: "err_failure", -4: "conv_f
 EXPORTED = ["bdfx_create", "bdfx_set_stream", "bdfx_destroy", "bdfx_last_error",
             "bdfx_mech_create", "bdfx_mech_destroy", "bdfx_mech_set_weights", "bdfx_plan",
             "bdfx_bind", "bdfx_integrate", "bdfx_perturb", "bdfx_stats_summary",
-            "bdfx_adjoint", "bdfx_autotune", "bdfx_set_tuning", "bdfx_get_tuning", "bdfx_version"]
+            "bdfx_adjoint", "bdfx_autotune", "bdfx_set_tuning", "bdfx_get_tuning", "bdfx_typical_atol",
+            "bdfx_version"]
 
 
 class MechDesc(C.Structure):
@@ -93,6 +94,7 @@ def lib():
             "bdfx_autotune": ([P, C.c_double, C.c_double, I64, C.POINTER(Tuning)], C.c_int),
             "bdfx_set_tuning": ([P, C.POINTER(Tuning), I32], C.c_int),
             "bdfx_get_tuning": ([P, C.POINTER(Tuning), I32], C.c_int),
+            "bdfx_typical_atol": ([P, C.c_double, P], C.c_int),
             "bdfx_version": ([], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -198,6 +200,10 @@ def bdfx_perturb(ctx, seed: int, outer_step: int, amplitude: float):
     _check(lib().bdfx_perturb(ctx, C.c_uint64(int(seed)), int(outer_step), float(amplitude)), ctx)
 
 
+def bdfx_typical_atol(ctx, eta: float, d_typical=None):
+    _check(lib().bdfx_typical_atol(ctx, float(eta), d_typical), ctx)
+
+
 def bdfx_stats_summary(ctx) -> dict:
     s = Summary()
     _check(lib().bdfx_stats_summary(ctx, C.byref(s)), ctx)
@@ -256,6 +262,7 @@ class Integrator:
         self.ctx = bdfx_create(device, self.stream.cuda_stream)
         self.mech_handles = [bdfx_mech_create(self.ctx, m) for m in mechs]
         self.mechs = mechs
+        self.S_max = max(int(m["n_species"]) for m in mechs)
         self.N, self.ldy = tuple(y0.shape)
         self.opts = make_options(rtol, atol, **opts)
         ws = bdfx_plan(self.ctx, self.N, self.mech_handles, self.opts)
@@ -285,6 +292,15 @@ class Integrator:
 
     def perturb(self, seed, outer_step, amplitude):
         bdfx_perturb(self.ctx, seed, outer_step, amplitude)
+
+    def typical_atol(self, eta, typical=None):
+        """Typical-value tolerances from the current states (bdfx_typical_atol);
+        ``typical``: optional float64 device tensor [n_mech, S_max] that
+        receives the typical values.  eta = 0 returns to the options' atol."""
+        if typical is not None:
+            assert typical.is_cuda and typical.dtype == self.torch.float64
+            assert typical.is_contiguous() and typical.numel() >= len(self.mechs) * self.S_max
+        bdfx_typical_atol(self.ctx, eta, None if typical is None else typical.data_ptr())
 
     def set_state(self, y0):
         self.y.copy_(self.torch.as_tensor(np.ascontiguousarray(y0), dtype=self.torch.float64))
@@ -339,17 +355,21 @@ class Integrator:
         """Launch shape in effect per mechanism (bdfx_get_tuning())."""
         return bdfx_get_tuning(self.ctx, len(self.mechs))
 
-    def outer_loop(self, n_outer, dt, seed, amplitude, t0=0.0):
+    def outer_loop(self, n_outer, dt, seed, amplitude, t0=0.0, typical_every=0, eta=1e-10):
         """Operator-splitting outer loop on the current stream: for k = 0 ..
         n_outer-1, perturb the states (outer step k of the counter-based
-        perturbation, skipped when amplitude == 0), then integrate over
-        [t0 + k dt, t0 + (k + 1) dt]."""
+        perturbation, skipped when amplitude == 0), recompute the
+        typical-value tolerances every ``typical_every`` outer steps (k = 0,
+        K, 2K, ...; 0 = never), then integrate over [t0 + k dt, t0 + (k+1) dt]."""
         for k in range(n_outer):
             if amplitude != 0.0:
                 self.perturb(seed, k, amplitude)
+            if typical_every > 0 and k % typical_every == 0:
+                self.typical_atol(eta)
             self.integrate(t0 + k * dt, t0 + (k + 1) * dt)
 
-    def capture_outer_loop(self, n_outer, dt, seed, amplitude, t0=0.0):
+    def capture_outer_loop(self, n_outer, dt, seed, amplitude, t0=0.0, typical_every=0,
+                           eta=1e-10):
         """Capture outer_loop() in a HIP graph (torch.cuda.CUDAGraph).
 
         The graph holds only the library's kernels (perturbation, queue reset
@@ -363,7 +383,7 @@ class Integrator:
         bdfx_set_stream(self.ctx, side.cuda_stream)
         try:
             with torch.cuda.graph(g, stream=side):
-                self.outer_loop(n_outer, dt, seed, amplitude, t0)
+                self.outer_loop(n_outer, dt, seed, amplitude, t0, typical_every, eta)
         finally:
             bdfx_set_stream(self.ctx, self.stream.cuda_stream)
         self.stream.wait_stream(side)

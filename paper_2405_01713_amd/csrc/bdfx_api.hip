@@ -36,6 +36,12 @@ hipError_t bdfx_launch_copy_rows(double *y, int ldy, const int32_t *list, int64_
                                  double *dst, bool restore, hipStream_t s);
 hipError_t bdfx_launch_sum_cells(const double *pbar, int ldp, const int32_t *list, int64_t n, int R,
                                  double *out, hipStream_t s);
+int bdfx_extremes_blocks(int64_t n, int S, int max_blocks);
+hipError_t bdfx_launch_extremes(const double *y, int ldy, const int32_t *list, int64_t n, int S,
+                                int blocks, double *part, hipStream_t s);
+hipError_t bdfx_launch_typical(int n_mech, int ldt, const int32_t *S, const int32_t *nblk,
+                               const int64_t *part_off, const double *part, double eta, double *atol,
+                               double *typ, hipStream_t s);
 
 static_assert(sizeof(bdfx_cell_stats) == sizeof(bdfx::CellStats), "stats layout");
 static_assert(sizeof(bdfx_cell_stats) == 48, "stats size");
@@ -76,6 +82,8 @@ constexpr int64_t kTuneCells = 16384;
 // most waves one CU can hold (8 per SIMD): bounds the rate-constant slots of
 // persistent grids
 constexpr int64_t kMaxWavesPerCu = 32;
+// blocks of the typical-value extremes pass per mechanism (partials in the workspace)
+constexpr int kExtMaxBlocks = 1024;
 
 struct bdfx_mech_s {
   bdfx_ctx ctx = nullptr;
@@ -118,7 +126,8 @@ struct bdfx_ctx_s {
   int S_max = 0, R_max = 0;
   size_t ws_need = 0;
   size_t off_queue = 0, off_bins = 0, off_rec = 0, off_recn = 0, off_rechpad = 0, off_recy0 = 0,
-         off_pbar = 0, off_tune = 0, off_kk = 0;
+         off_pbar = 0, off_tune = 0, off_kk = 0, off_ext = 0, off_tatol = 0;
+  bool typical = false;  // per-mechanism typical-value atol in effect (bdfx_typical_atol)
   int64_t tune_cells = 0;  // rows the autotuner can save in the workspace
   int64_t kk_slots = 0;    // rate-constant slots (waves) for tables in global memory
   int rec_stride = 0;
@@ -380,6 +389,9 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
                       ? std::min<int64_t>(static_cast<int64_t>(ctx->n_cu) * kMaxWavesPerCu, n_cells + 16)
                       : 0;
   ctx->off_kk = reserve(static_cast<size_t>(ctx->kk_slots) * 2 * R_max * 8);
+  ctx->off_ext = reserve(static_cast<size_t>(n_mech) * kExtMaxBlocks * 2 * bdfx::kWave * 8);
+  ctx->off_tatol = reserve(static_cast<size_t>(n_mech) * S_max * 8);
+  ctx->typical = false;
   ctx->ws_need = off;
   *ws_bytes = off;
   ctx->planned = true;
@@ -537,8 +549,14 @@ static bdfx::Params make_params(bdfx_ctx ctx, const Bin &b, double t0, double to
   P.t0 = t0;
   P.tout = tout;
   P.rtol = ctx->opt.rtol;
-  P.atol = ctx->d_atol;
-  P.atol_len = static_cast<int32_t>(ctx->atol.size());
+  if (ctx->typical) {
+    P.atol = reinterpret_cast<const double *>(ctx->ws + ctx->off_tatol) +
+             static_cast<int64_t>(b.mech) * ctx->S_max;
+    P.atol_len = ctx->S_max;
+  } else {
+    P.atol = ctx->d_atol;
+    P.atol_len = static_cast<int32_t>(ctx->atol.size());
+  }
   P.max_order = ctx->opt.max_order;
   P.max_steps = ctx->opt.max_steps;
   P.n_sp = m->S;
@@ -723,6 +741,40 @@ int bdfx_set_tuning(bdfx_ctx ctx, const bdfx_tuning *t, int32_t n) {
         if (const int rc = configure_bin(ctx, b)) return rc;
       }
   }
+  return BDFX_OK;
+}
+
+int bdfx_typical_atol(bdfx_ctx ctx, double eta, double *d_typical) {
+  if (!ctx) return BDFX_EINVAL;
+  if (!ctx->bound) return fail(ctx, BDFX_EORDER, "bdfx_bind must precede bdfx_typical_atol");
+  if (!std::isfinite(eta) || eta < 0.0) return fail(ctx, BDFX_EINVAL, "eta must be finite, >= 0");
+  if (eta == 0.0) {
+    ctx->typical = false;
+    return BDFX_OK;
+  }
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const int n_mech = static_cast<int>(ctx->mechs.size());
+  double *part = reinterpret_cast<double *>(ctx->ws + ctx->off_ext);
+  int32_t S[BDFX_MAX_MECH] = {0}, nblk[BDFX_MAX_MECH] = {0};
+  int64_t off[BDFX_MAX_MECH] = {0};
+  for (int m = 0; m < n_mech; ++m) {
+    S[m] = ctx->mechs[m]->S;
+    off[m] = static_cast<int64_t>(m) * kExtMaxBlocks * 2 * bdfx::kWave;
+  }
+  for (const Bin &b : ctx->bins) {
+    if (b.count == 0) continue;
+    const int32_t *list = n_mech > 1 ? reinterpret_cast<const int32_t *>(ctx->ws + ctx->off_bins) +
+                                           b.offset
+                                     : nullptr;
+    const int nb = bdfx_extremes_blocks(b.count, S[b.mech], kExtMaxBlocks);
+    HIPCHK(ctx, bdfx_launch_extremes(ctx->y, ctx->ldy, list, b.count, S[b.mech], nb,
+                                     part + off[b.mech], ctx->stream));
+    nblk[b.mech] = nb;
+  }
+  HIPCHK(ctx, bdfx_launch_typical(n_mech, ctx->S_max, S, nblk, off, part, eta,
+                                  reinterpret_cast<double *>(ctx->ws + ctx->off_tatol), d_typical,
+                                  ctx->stream));
+  ctx->typical = true;
   return BDFX_OK;
 }
 

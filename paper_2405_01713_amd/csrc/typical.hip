@@ -1,0 +1,160 @@
+// typical.hip -- typical-value absolute tolerances (Sec. 4.1.3, Eq. (eta)):
+// atol_i = eta * (min_c y_ci + max_c y_ci) / 2 over the cells of a mechanism.
+//
+// Two kernels per call.  k_extremes streams the state rows of one mechanism
+// once (the HBM-bound part): a wave covers floor(64 / S) cells per pass, lane
+// l holding species l mod S of cell l / S, so the rows of consecutive cells
+// are read as one contiguous run; each block leaves its per-species extremes
+// in a partial array.  k_typical combines the partials of every mechanism
+// and writes the tolerances.  Minimum and maximum are exact, so the result
+// does not depend on the order in which cells are visited.  A NaN entry
+// makes both extremes NaN (as a plain minimum over the values would).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bdf_device.h"
+#include "bdfx.h"
+
+namespace bdfx {
+
+constexpr int kExtBlock = 256;  // threads per k_extremes block
+constexpr int kExtUnroll = 4;   // passes per loop iteration (loads in flight)
+
+__device__ __forceinline__ double lo_of(double a, double v) { return (v < a || v != v) ? v : a; }
+__device__ __forceinline__ double hi_of(double a, double v) { return (v > a || v != v) ? v : a; }
+
+// part[block][0][i] = min, part[block][1][i] = max over this block's cells.
+__global__ void __launch_bounds__(kExtBlock) k_extremes(const double *y, int ldy, const int32_t *list,
+                                                        int64_t n, int S, double *part) {
+  __shared__ double lo_s[kExtBlock], hi_s[kExtBlock];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wib = threadIdx.x / kWave;
+  const int per = kWave / S;  // cells per wave pass
+  const int sub = lane / S, sp = lane - sub * S;
+  const bool act = sub < per;
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (kExtBlock / kWave);
+  const int64_t w0 = static_cast<int64_t>(blockIdx.x) * (kExtBlock / kWave) + wib;
+  const int64_t passes = (n + per - 1) / per;
+  double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
+  for (int64_t p0 = w0; p0 < passes; p0 += waves * kExtUnroll) {
+    double v[kExtUnroll];
+#pragma unroll
+    for (int u = 0; u < kExtUnroll; ++u) {
+      const int64_t idx = (p0 + u * waves) * per + sub;
+      v[u] = __builtin_nan("");
+      if (act && p0 + u * waves < passes && idx < n) {
+        const int64_t c = list ? list[idx] : idx;
+        v[u] = y[c * ldy + sp];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kExtUnroll; ++u) {
+      const int64_t idx = (p0 + u * waves) * per + sub;
+      if (act && p0 + u * waves < passes && idx < n) {
+        lo = lo_of(lo, v[u]);
+        hi = hi_of(hi, v[u]);
+      }
+    }
+  }
+  lo_s[threadIdx.x] = lo;
+  hi_s[threadIdx.x] = hi;
+  __syncthreads();
+  if (threadIdx.x < S) {
+    // lanes sp, sp + S, ... of every wave hold species sp
+    double l = __builtin_huge_val(), h = -__builtin_huge_val();
+    for (int w = 0; w < kExtBlock / kWave; ++w)
+      for (int k = 0; k < per; ++k) {
+        l = lo_of(l, lo_s[w * kWave + k * S + threadIdx.x]);
+        h = hi_of(h, hi_s[w * kWave + k * S + threadIdx.x]);
+      }
+    part[(static_cast<int64_t>(blockIdx.x) * 2) * kWave + threadIdx.x] = l;
+    part[(static_cast<int64_t>(blockIdx.x) * 2 + 1) * kWave + threadIdx.x] = h;
+  }
+}
+
+struct TypicalArgs {
+  int32_t n_mech, ldt;               // mechanisms; row length of the outputs
+  int32_t S[BDFX_MAX_MECH];          // species of each mechanism
+  int32_t nblk[BDFX_MAX_MECH];       // k_extremes blocks that ran (0: no cells)
+  int64_t part_off[BDFX_MAX_MECH];   // offset (doubles) of its partials
+};
+
+// One block per mechanism: kTypGroups groups of 64 threads split the partial
+// blocks (thread (g, i) takes blocks g, g + kTypGroups, ... for species i),
+// the groups' extremes are combined in LDS, then
+// typ = 0.5 (min + max), atol = (typ > 0 ? typ : 1) eta.  Entries beyond the
+// mechanism's species (and all of a mechanism without cells) get typ = 0,
+// atol = eta.
+constexpr int kTypGroups = 16;
+
+__global__ void __launch_bounds__(kTypGroups * kWave) k_typical(TypicalArgs a, const double *part,
+                                                               double eta, double *atol, double *typ) {
+#pragma clang fp contract(off)
+  __shared__ double lo_s[kTypGroups][kWave], hi_s[kTypGroups][kWave];
+  const int m = blockIdx.x;
+  const int g = threadIdx.x / kWave, i = threadIdx.x % kWave;
+  const double *pm = part + a.part_off[m];
+  double l = __builtin_huge_val(), h = -__builtin_huge_val();
+  if (i < a.S[m]) {
+#pragma unroll 4
+    for (int b = g; b < a.nblk[m]; b += kTypGroups) {
+      l = lo_of(l, pm[(static_cast<int64_t>(b) * 2) * kWave + i]);
+      h = hi_of(h, pm[(static_cast<int64_t>(b) * 2 + 1) * kWave + i]);
+    }
+  }
+  lo_s[g][i] = l;
+  hi_s[g][i] = h;
+  __syncthreads();
+  if (g == 0) {
+    for (int k = 1; k < kTypGroups; ++k) {
+      l = lo_of(l, lo_s[k][i]);
+      h = hi_of(h, hi_s[k][i]);
+    }
+    for (int j = i; j < a.ldt; j += kWave) {
+      double t = 0.0, at = eta;
+      if (j < a.S[m] && a.nblk[m] > 0) {  // j == i: ldt <= 64
+        t = 0.5 * (l + h);
+        at = (t > 0.0 ? t : 1.0) * eta;
+      }
+      atol[static_cast<int64_t>(m) * a.ldt + j] = at;
+      if (typ) typ[static_cast<int64_t>(m) * a.ldt + j] = t;
+    }
+  }
+}
+
+}  // namespace bdfx
+
+// blocks of k_extremes for n cells of S species (at most max_blocks)
+int bdfx_extremes_blocks(int64_t n, int S, int max_blocks) {
+  if (n <= 0 || S < 1 || S > bdfx::kWave) return 0;
+  const int per = bdfx::kWave / S;
+  const int64_t passes = (n + per - 1) / per;
+  const int64_t waves_needed = (passes + bdfx::kExtUnroll - 1) / bdfx::kExtUnroll;
+  const int64_t blocks = (waves_needed + bdfx::kExtBlock / bdfx::kWave - 1) / (bdfx::kExtBlock / bdfx::kWave);
+  return static_cast<int>(blocks < max_blocks ? blocks : max_blocks);
+}
+
+hipError_t bdfx_launch_extremes(const double *y, int ldy, const int32_t *list, int64_t n, int S,
+                                int blocks, double *part, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bdfx::k_extremes, dim3(blocks), dim3(bdfx::kExtBlock), 0, s, y, ldy, list, n,
+                     S, part);
+  return hipGetLastError();
+}
+
+hipError_t bdfx_launch_typical(int n_mech, int ldt, const int32_t *S, const int32_t *nblk,
+                               const int64_t *part_off, const double *part, double eta, double *atol,
+                               double *typ, hipStream_t s) {
+  bdfx::TypicalArgs a{};
+  a.n_mech = n_mech;
+  a.ldt = ldt;
+  for (int m = 0; m < n_mech && m < BDFX_MAX_MECH; ++m) {
+    a.S[m] = S[m];
+    a.nblk[m] = nblk[m];
+    a.part_off[m] = part_off[m];
+  }
+  hipLaunchKernelGGL(bdfx::k_typical, dim3(n_mech), dim3(bdfx::kTypGroups * bdfx::kWave), 0, s, a,
+                     part, eta, atol, typ);
+  return hipGetLastError();
+}
