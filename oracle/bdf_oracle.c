@@ -26,6 +26,14 @@
  * interpolation-preserving order changes; the initial-step estimate; the
  * failure-recovery and setup heuristics.
  *
+ * Non-isothermal cells (a mechanism with heat capacities): temperature is
+ * the state's last component and the rate constants are re-evaluated from it
+ * at every right-hand side (the Arrhenius terms of Sec. 3.1 with T varying,
+ * Sec. 4.2.1).  The reactor is adiabatic at constant volume with synthetic
+ * species energies u_i(T) = u0_i + cv_i T, so the total energy
+ * sum_i y_i u_i(T) is constant: dT/dt = F_T - sum_i u_i(T) dy_i/dt / sum_i
+ * cv_i y_i.
+ *
  * Everything is scalar, straightforward and unblocked so that it can be
  * checked against the mathematics by eye.
  */
@@ -58,6 +66,8 @@ typedef struct {
   const double *lnA;   /* [R] ln of the forward pre-exponential factor */
   const double *EaR;   /* [R] activation temperature Ea/R (K); NULL = 0 */
   const double *lnK;   /* [R] ln equilibrium constant; NULL = irreversible */
+  const double *cv;    /* [S] heat capacity per unit amount; NULL = isothermal */
+  const double *u0;    /* [S] energy at T = 0 per unit amount (with cv) */
 } orc_mech;
 
 typedef struct {
@@ -159,6 +169,69 @@ void orc_jac(const orc_mech *m, const double *kf, const double *kr, const double
         }
       }
     }
+  }
+}
+
+/* Non-isothermal right-hand side: x = (y_0 .. y_{S-1}, T), f the same
+ * length.  Rates at T = x[S]; species rates as in orc_rhs (forcing F[0..S-1]);
+ * dT/dt = F[S] - N / D with N = sum_i u_i(T) f_i, D = sum_i cv_i y_i and
+ * u_i(T) = u0_i + cv_i T (constant-volume adiabatic energy balance). */
+void orc_rhs_thermal(const orc_mech *m, const double *kscale, const double *F, const double *x,
+                     double *f) {
+  int S = m->n_species;
+  double kf[4096], kr[4096];
+  double T = x[S];
+  orc_rates(m, T, kscale, kf, kr);
+  orc_rhs(m, kf, kr, F, x, f);
+  double N = 0.0, D = 0.0;
+  for (int i = 0; i < S; ++i) {
+    N += (m->u0[i] + m->cv[i] * T) * f[i];
+    D += m->cv[i] * x[i];
+  }
+  f[S] = (F ? F[S] : 0.0) - N / D;
+}
+
+/* Analytic Jacobian of orc_rhs_thermal, (S+1) x (S+1) row-major.
+ *   species block: orc_jac at the rates of T;
+ *   T column: d f_i / dT = sum_r nu_ir q_r EaR_r / T^2 (both rate constants
+ *     carry the factor exp(-EaR_r / T));
+ *   T row: d f_T / dy_j = -(sum_i u_i J_ij) / D + N cv_j / D^2,
+ *          d f_T / dT = -(sum_i cv_i f_i + sum_i u_i J_iT) / D. */
+void orc_jac_thermal(const orc_mech *m, const double *kscale, const double *F, const double *x,
+                     double *J) {
+  int S = m->n_species, n = S + 1;
+  double kf[4096], kr[4096], Js[ORC_MAXS * ORC_MAXS], f[ORC_MAXS];
+  double qr[4096];
+  double T = x[S];
+  orc_rates(m, T, kscale, kf, kr);
+  orc_jac(m, kf, kr, x, Js);
+  orc_rhs(m, kf, kr, F, x, f);
+  memset(J, 0, sizeof(double) * n * n);
+  for (int i = 0; i < S; ++i)
+    for (int j = 0; j < S; ++j) J[i * n + j] = Js[i * S + j];
+  orc_reaction_rates(m, kf, kr, x, qr);
+  for (int r = 0; r < m->n_reactions; ++r) {
+    double dq = qr[r] * (m->EaR ? m->EaR[r] : 0.0) / (T * T);
+    for (int s = 0; s < ORC_SLOTS; ++s) {
+      int a = m->reac[r * ORC_SLOTS + s];
+      int b = m->prod[r * ORC_SLOTS + s];
+      if (a >= 0) J[a * n + S] -= dq;
+      if (b >= 0) J[b * n + S] += dq;
+    }
+  }
+  double N = 0.0, D = 0.0, cf = 0.0;
+  for (int i = 0; i < S; ++i) {
+    N += (m->u0[i] + m->cv[i] * T) * f[i];
+    D += m->cv[i] * x[i];
+    cf += m->cv[i] * f[i];
+  }
+  for (int j = 0; j <= S; ++j) {
+    double uj = 0.0;
+    for (int i = 0; i < S; ++i) uj += (m->u0[i] + m->cv[i] * T) * J[i * n + j];
+    if (j < S)
+      J[S * n + j] = -uj / D + N * m->cv[j] / (D * D);
+    else
+      J[S * n + S] = -(cf + uj) / D;
   }
 }
 
@@ -354,10 +427,25 @@ static int orc_all_finite(int n, const double *v) {
 typedef struct {
   const orc_mech *m;
   const double *kf, *kr, *F;
-  int S;
+  int S;                 /* state length: species, plus 1 for a non-isothermal cell */
+  const double *kscale;  /* non-isothermal: per-reaction scale for the rates at T */
 } orc_sys;
 
-static void sys_f(const orc_sys *s, const double *y, double *f) { orc_rhs(s->m, s->kf, s->kr, s->F, y, f); }
+static int sys_thermal(const orc_sys *s) { return s->m->cv != NULL; }
+
+static void sys_f(const orc_sys *s, const double *y, double *f) {
+  if (sys_thermal(s))
+    orc_rhs_thermal(s->m, s->kscale, s->F, y, f);
+  else
+    orc_rhs(s->m, s->kf, s->kr, s->F, y, f);
+}
+
+static void sys_jac(const orc_sys *s, const double *y, double *J) {
+  if (sys_thermal(s))
+    orc_jac_thermal(s->m, s->kscale, s->F, y, J);
+  else
+    orc_jac(s->m, s->kf, s->kr, y, J);
+}
 
 /* Initial step size (reading; the paper is silent).  Bounds
  * h_lb = 100 u max(|t0|, |t_out|), h_ub = min(0.1 |t_out - t0|,
@@ -507,7 +595,7 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
 
       int fresh = 0;
       if (need_setup || st->nst >= nst_setup + 20 || fabs(gamma / gamma_bar - 1.0) > 0.3) {
-        orc_jac(s->m, s->kf, s->kr, z[0], J);
+        sys_jac(s, z[0], J);
         for (int i = 0; i < S; ++i)
           for (int j = 0; j < S; ++j) M[i * S + j] = (i == j ? 1.0 : 0.0) - gamma * J[i * S + j];
         st->nsetups++;
@@ -707,8 +795,18 @@ int32_t orc_integrate_cell(const orc_mech *m, const orc_opts *o, double T, const
     st->status = ORC_NONFINITE;
     return st->status;
   }
-  orc_rates(m, T, kscale, kf, kr);
-  orc_sys s = {m, kf, kr, F, m->n_species};
+  const int thermal = m->cv != NULL;
+  if (thermal) {
+    if (m->n_species + 1 > ORC_MAXS) {
+      memset(st, 0, sizeof(*st));
+      st->status = ORC_NONFINITE;
+      return st->status;
+    }
+    T = y[m->n_species];  /* temperature is the last state component */
+  } else {
+    orc_rates(m, T, kscale, kf, kr);
+  }
+  orc_sys s = {m, kf, kr, F, m->n_species + thermal, kscale};
   if (!isfinite(T)) {
     memset(st, 0, sizeof(*st));
     st->t_reached = t0;

@@ -37,7 +37,8 @@ def build(force: bool = True) -> str:
 class Mech(C.Structure):
     _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32),
                 ("reac", C.c_void_p), ("prod", C.c_void_p),
-                ("lnA", C.c_void_p), ("EaR", C.c_void_p), ("lnK", C.c_void_p)]
+                ("lnA", C.c_void_p), ("EaR", C.c_void_p), ("lnK", C.c_void_p),
+                ("cv", C.c_void_p), ("u0", C.c_void_p)]
 
 
 class Opts(C.Structure):
@@ -78,6 +79,8 @@ def lib():
         L.orc_rates.argtypes = [P, C.c_double, P, P, P]
         L.orc_rhs.argtypes = [P, P, P, P, P, P]
         L.orc_jac.argtypes = [P, P, P, P, P]
+        L.orc_rhs_thermal.argtypes = [P, P, P, P, P]
+        L.orc_jac_thermal.argtypes = [P, P, P, P, P]
         L.orc_lu_factor.argtypes = [C.c_int, P, P]
         L.orc_lu_factor.restype = C.c_int32
         L.orc_lu_solve.argtypes = [C.c_int, P, P, P]
@@ -127,8 +130,11 @@ class OracleMech:
         self.lnA = _f64(mech["lnA"])
         self.EaR = _f64(mech.get("EaR"))
         self.lnK = _f64(mech.get("lnK"))
+        self.cv = _f64(mech.get("cv"))
+        self.u0 = _f64(mech.get("u0"))
+        self.thermal = self.cv is not None
         self.c = Mech(self.S, self.R, _p(self.reac), _p(self.prod), _p(self.lnA),
-                      _p(self.EaR), _p(self.lnK))
+                      _p(self.EaR), _p(self.lnK), _p(self.cv), _p(self.u0))
 
     @property
     def ptr(self):
@@ -156,6 +162,24 @@ def rhs(mech, kf, kr, y, F=None):
     f = np.zeros(m.S)
     lib().orc_rhs(m.ptr, _p(kf), _p(kr), _p(F), _p(y), _p(f))
     return f
+
+
+def rhs_thermal(mech, x, kscale=None, F=None):
+    """Non-isothermal right-hand side: x = (y_0 .. y_{S-1}, T)."""
+    m = OracleMech(mech)
+    x = _f64(x)
+    f = np.zeros(m.S + 1)
+    lib().orc_rhs_thermal(m.ptr, _p(_f64(kscale)), _p(_f64(F)), _p(x), _p(f))
+    return f
+
+
+def jac_thermal(mech, x, kscale=None, F=None):
+    """Analytic (S+1) x (S+1) Jacobian of rhs_thermal."""
+    m = OracleMech(mech)
+    x = _f64(x)
+    J = np.zeros((m.S + 1, m.S + 1))
+    lib().orc_jac_thermal(m.ptr, _p(_f64(kscale)), _p(_f64(F)), _p(x), _p(J))
+    return J
 
 
 def jac(mech, kf, kr, y):

@@ -114,6 +114,19 @@ def synthetic_mechanism(n_species: int, n_reactions: int, seed: int = SEED_MECH)
     )
 
 
+def thermal_mechanism(mech: dict, seed: int = 17) -> dict:
+    """The mechanism with synthetic thermochemistry for a non-isothermal
+    cell: heat capacity ``cv_i = 1.5 + 0.5 w_i`` and energy at zero
+    temperature ``u0_i = 1000 w_i + d_i`` with ``d_i ~ U[-300, 300]`` (the
+    weight-proportional part cancels in every A + B <=> C reaction, so
+    reaction energies come from ``d`` and from the heat-capacity change)."""
+    rng = _rng(seed)
+    w = np.asarray(mech["w"], dtype=np.float64)
+    d = rng.uniform(-300.0, 300.0, size=w.size)
+    return dict(mech, name=mech.get("name", "mech") + "_thermal", cv=1.5 + 0.5 * w,
+                u0=1000.0 * w + d)
+
+
 def unimolecular_mechanism(n_species: int, n_reactions: int, seed: int) -> dict:
     """Random first-order network (A -> B), i.e. a linear system y' = K y."""
     S, R = int(n_species), int(n_reactions)
@@ -197,6 +210,9 @@ WORKLOADS = {
                                  rtol=1e-6, atol=1e-10, T_range=(1000.0, 2500.0)),
     "s21_r84_65k_adjoint": dict(kind="synthetic", S=21, R=84, n_cells=65536, t_out=1e-5,
                                 rtol=1e-6, atol=1e-10, T_range=(1000.0, 2500.0), state_seed=5),
+    # non-isothermal: temperature is the state's last component (atol 1e-6 K)
+    "s21_r84_thermal_262k": dict(kind="thermal", S=21, R=84, n_cells=262144, t_out=1e-5,
+                                 rtol=1e-6, atol=1e-10, atol_T=1e-6, T_range=(1000.0, 2500.0)),
 }
 
 # Mechanism seeds: the mixed workload draws its two mechanisms from seeds 1 and
@@ -225,6 +241,13 @@ def make_workload(name: str, n_cells: int | None = None) -> dict:
         m = synthetic_mechanism(spec["S"], spec["R"], MECH_SEED_S53)
         c = cell_states(m, N, SEED_STATE, spec["T_range"])
         out.update(mechs=[m], y0=c["y0"], T=c["T"], kscale=None, cell_mech=None)
+    elif kind == "thermal":
+        m0 = synthetic_mechanism(spec["S"], spec["R"], SEED_MECH)
+        m = thermal_mechanism(m0)
+        c = cell_states(m0, N, spec.get("state_seed", SEED_STATE), spec["T_range"])
+        y0 = np.concatenate([c["y0"], c["T"][:, None]], axis=1)
+        out.update(mechs=[m], y0=y0, T=None, kscale=None, cell_mech=None,
+                   atol=np.array([spec["atol"]] * spec["S"] + [spec["atol_T"]]))
     elif kind == "mixed":
         (s1, r1), (s2, r2) = spec["mechs"]
         ms = [synthetic_mechanism(s1, r1, MECH_SEED_S9), synthetic_mechanism(s2, r2, MECH_SEED_S53)]

@@ -1,0 +1,135 @@
+"""Pins of the oracle's non-isothermal cells (temperature as a state, rates
+re-evaluated from it; adiabatic constant-volume energy balance with species
+energies u_i(T) = u0_i + cv_i T).
+
+* The species part of the right-hand side is the isothermal one at the
+  current temperature; dT/dt follows from d/dt sum_i y_i u_i(T) = 0.
+* The analytic Jacobian (temperature row and column included) matches
+  central differences.
+* The total energy and the mass sum_i w_i y_i are conserved along the
+  integrated solution.
+* With huge heat capacities proportional to the weights the temperature
+  stays put and the solution equals the isothermal integration.
+* A tiny system matches brute-force classical RK4 at small steps.
+"""
+import numpy as np
+import pytest
+
+from paper_2405_01713_amd import workloads as W
+
+
+def _mech(S=6, R=9, seed=3):
+    return W.thermal_mechanism(W.synthetic_mechanism(S, R, seed), seed=seed + 1)
+
+
+def _state(m, seed=4, T=1600.0):
+    c = W.cell_states(m, 1, seed=seed)
+    return np.concatenate([c["y0"][0], [T]])
+
+
+def _energy(m, x):
+    S = m["n_species"]
+    return float(np.sum(x[..., :S] * (m["u0"] + m["cv"] * x[..., S:S + 1]), axis=-1))
+
+
+def test_rhs_species_part_and_energy_balance(oracle):
+    m = _mech()
+    x = _state(m)
+    S = m["n_species"]
+    f = oracle.rhs_thermal(m, x)
+    kf, kr = oracle.rates(m, T=x[S])
+    fs = oracle.rhs(m, kf, kr, x[:S])
+    assert np.array_equal(f[:S], fs)
+    u = m["u0"] + m["cv"] * x[S]
+    # d/dt sum_i y_i u_i(T) = sum_i u_i f_i + (sum_i cv_i y_i) f_T = 0
+    dU = np.dot(u, f[:S]) + np.dot(m["cv"], x[:S]) * f[S]
+    assert abs(dU) <= 1e-12 * np.dot(np.abs(u), np.abs(f[:S]))
+    # forcing adds F_T to dT/dt and F_i to the species
+    F = np.linspace(-1, 1, S + 1)
+    fF = oracle.rhs_thermal(m, x, F=F)
+    assert np.allclose(fF[:S], f[:S] + F[:S], rtol=1e-14, atol=1e-14 * np.abs(f[:S]).max())
+    uF = np.dot(u, fF[:S]) / np.dot(m["cv"], x[:S])
+    assert np.isclose(fF[S], F[S] - uF, rtol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_jacobian_central_differences(oracle, seed):
+    m = _mech(seed=seed)
+    x = _state(m, seed=seed + 10, T=900.0 + 500.0 * seed)
+    S = m["n_species"]
+    J = oracle.jac_thermal(m, x)
+    Jfd = np.zeros_like(J)
+    for j in range(S + 1):
+        h = 1e-6 * max(abs(x[j]), 1e-6)
+        xp, xm = x.copy(), x.copy()
+        xp[j] += h
+        xm[j] -= h
+        Jfd[:, j] = (oracle.rhs_thermal(m, xp) - oracle.rhs_thermal(m, xm)) / (2 * h)
+    scale = np.abs(J).max(axis=1, keepdims=True)
+    assert np.all(np.abs(J - Jfd) <= 1e-6 * scale + 1e-300)
+
+
+def test_energy_and_mass_conserved(oracle):
+    m = _mech(S=8, R=14, seed=5)
+    S = m["n_species"]
+    c = W.cell_states(m, 16, seed=6)
+    x0 = np.concatenate([c["y0"], c["T"][:, None]], axis=1)
+    atol = np.array([1e-14] * S + [1e-8])
+    drift = {}
+    for rtol in (1e-7, 1e-10):
+        x, st = oracle.integrate([m], x0, 0.0, 1e-5, rtol, atol, max_steps=200000)
+        assert np.all(st["status"] == 0)
+        assert np.any(np.abs(x[:, S] - x0[:, S]) > 1.0)  # the temperature does move
+        e0 = np.array([_energy(m, v) for v in x0])
+        e1 = np.array([_energy(m, v) for v in x])
+        drift[rtol] = np.max(np.abs(e1 - e0) / np.abs(e0))
+        # the linear invariant is kept to round-off by any linear multistep method
+        assert np.all(np.abs(x[:, :S] @ m["w"] - x0[:, :S] @ m["w"]) <= 1e-13)
+    # energy is nonlinear in (y, T): conserved to the integration accuracy,
+    # and the drift falls with the tolerance
+    assert drift[1e-10] <= 1e-6 and drift[1e-10] <= 1e-2 * drift[1e-7]
+
+
+def test_huge_heat_capacity_is_isothermal(oracle):
+    m0 = W.synthetic_mechanism(8, 14, 5)
+    # cv proportional to the weights: sum_i cv_i f_i = 0 by mass conservation,
+    # so dT/dt = -sum_i u0_i f_i / sum_i cv_i y_i, which vanishes as cv grows
+    m = dict(W.thermal_mechanism(m0), cv=1e16 * m0["w"])
+    c = W.cell_states(m0, 8, seed=2)
+    x0 = np.concatenate([c["y0"], c["T"][:, None]], axis=1)
+    atol = np.array([1e-12] * 8 + [1e-6])
+    x, st = oracle.integrate([m], x0, 0.0, 1e-5, 1e-9, atol)
+    y, sti = oracle.integrate([m0], c["y0"], 0.0, 1e-5, 1e-9, 1e-12, T=c["T"])
+    assert np.all(st["status"] == 0) and np.all(sti["status"] == 0)
+    assert np.all(np.abs(x[:, 8] - x0[:, 8]) <= 1e-9 * x0[:, 8])
+    assert np.all(np.abs(x[:, :8] - y) <= 1e-5 * np.abs(y) + 1e-11)
+
+
+def _rk4(f, x, t1, n):
+    h = t1 / n
+    for _ in range(n):
+        k1 = f(x)
+        k2 = f(x + 0.5 * h * k1)
+        k3 = f(x + 0.5 * h * k2)
+        k4 = f(x + h * k3)
+        x = x + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return x
+
+
+def test_tiny_system_against_rk4(oracle):
+    # 3 species, A + A <=> B, A + B <=> C with moderate rates (non-stiff for RK4)
+    m = dict(n_species=3, n_reactions=2,
+             reac=np.array([[0, 0, -1], [0, 1, -1]], dtype=np.int32),
+             prod=np.array([[1, -1, -1], [2, -1, -1]], dtype=np.int32),
+             lnA=np.log([3e3, 5e3]), EaR=np.array([2000.0, 4000.0]), lnK=np.log([4.0, 2.0]),
+             w=np.array([1.0, 2.0, 3.0]), cv=np.array([1.5, 2.5, 3.0]),
+             u0=np.array([0.0, -800.0, -1500.0]))
+    x0 = np.array([0.6, 0.1, 0.05, 1200.0])
+    t1 = 2e-3
+    ref1 = _rk4(lambda x: oracle.rhs_thermal(m, x), x0, t1, 4000)
+    ref2 = _rk4(lambda x: oracle.rhs_thermal(m, x), x0, t1, 8000)
+    assert np.all(np.abs(ref1 - ref2) <= 1e-12 * np.abs(ref2) + 1e-14)
+    assert abs(ref2[3] - x0[3]) > 1.0
+    x, st = oracle.integrate([m], x0[None, :], 0.0, t1, 1e-10, np.array([1e-14] * 3 + [1e-10]))
+    assert st["status"][0] == 0
+    assert np.all(np.abs(x[0] - ref2) <= 1e-7 * np.abs(ref2) + 1e-12)
