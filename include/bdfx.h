@@ -68,7 +68,17 @@ typedef struct bdfx_mech_s *bdfx_mech;
  * slots per side (-1 = empty, a repeated species is a stoichiometric
  * coefficient), net rate q_r = k_f prod y_reac - k_r prod y_prod and
  * f_i = F_i + sum_r nu_ir q_r.  Rate constants are Arrhenius,
- * k_f = exp(lnA_r - EaR_r / T_c) * kscale_c[r], k_r = k_f exp(-lnK_r). */
+ * k_f = exp(lnA_r - EaR_r / T_c) * kscale_c[r], k_r = k_f exp(-lnK_r).
+ *
+ * Non-isothermal cells (cv and u0 given; Sec. 3.1 with the temperature
+ * evolving, the transcendental-heavy cost shape of Sec. 4.2.1): the
+ * temperature is state entry n_species of every cell of this mechanism
+ * (y[cell][n_species], so the state has n_species + 1 entries and ldy, atol
+ * and the workspace count it), T_c is not used, the rate constants are
+ * re-evaluated from the state's temperature at every right-hand side, and
+ * dT/dt = F_T - sum_i u_i(T) f_i / sum_i cv_i y_i with u_i(T) = u0_i + cv_i T
+ * (adiabatic, constant volume).  Step recording (bdfx_adjoint) is not
+ * available for such mechanisms. */
 typedef struct {
   int32_t n_species;   /* S, 1..BDFX_MAX_SPECIES */
   int32_t n_reactions; /* R >= 1 */
@@ -77,6 +87,8 @@ typedef struct {
   const double *lnA;   /* [R] */
   const double *EaR;   /* [R] activation temperature (K), or NULL (all zero) */
   const double *lnK;   /* [R] ln equilibrium constant, or NULL (irreversible) */
+  const double *cv;    /* [S] heat capacities (> 0), or NULL (isothermal) */
+  const double *u0;    /* [S] species energies at T = 0, with cv (NULL iff cv is) */
 } bdfx_mech_desc;
 
 /* Scheduler for bdfx_options.scheduler */

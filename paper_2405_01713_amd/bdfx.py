@@ -35,7 +35,8 @@ EXPORTED = ["bdfx_create", "bdfx_set_stream", "bdfx_destroy", "bdfx_last_error",
 class MechDesc(C.Structure):
     _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32),
                 ("reac", C.c_void_p), ("prod", C.c_void_p), ("lnA", C.c_void_p),
-                ("EaR", C.c_void_p), ("lnK", C.c_void_p)]
+                ("EaR", C.c_void_p), ("lnK", C.c_void_p), ("cv", C.c_void_p),
+                ("u0", C.c_void_p)]
 
 
 class Options(C.Structure):
@@ -141,17 +142,23 @@ def bdfx_last_error(ctx=None) -> str:
 
 
 def bdfx_mech_create(ctx, mech: dict):
-    """mech: dict with n_species, n_reactions, reac/prod [R,3], lnA, EaR, lnK."""
+    """mech: dict with n_species, n_reactions, reac/prod [R,3], lnA, EaR, lnK,
+    and for a non-isothermal mechanism cv, u0 [S]."""
+    f64 = lambda k: (None if mech.get(k) is None
+                     else np.ascontiguousarray(mech[k], dtype=np.float64))
     keep = dict(
         reac=np.ascontiguousarray(mech["reac"], dtype=np.int32),
         prod=np.ascontiguousarray(mech["prod"], dtype=np.int32),
         lnA=np.ascontiguousarray(mech["lnA"], dtype=np.float64),
         EaR=None if mech.get("EaR") is None else np.ascontiguousarray(mech["EaR"], dtype=np.float64),
         lnK=None if mech.get("lnK") is None else np.ascontiguousarray(mech["lnK"], dtype=np.float64),
+        cv=f64("cv"),
+        u0=f64("u0"),
     )
     p = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
     d = MechDesc(int(mech["n_species"]), int(mech["n_reactions"]), p(keep["reac"]),
-                 p(keep["prod"]), p(keep["lnA"]), p(keep["EaR"]), p(keep["lnK"]))
+                 p(keep["prod"]), p(keep["lnA"]), p(keep["EaR"]), p(keep["lnK"]), p(keep["cv"]),
+                 p(keep["u0"]))
     h = C.c_void_p()
     _check(lib().bdfx_mech_create(ctx, C.byref(d), C.byref(h)), ctx)
     if mech.get("w") is not None:
@@ -262,7 +269,8 @@ class Integrator:
         self.ctx = bdfx_create(device, self.stream.cuda_stream)
         self.mech_handles = [bdfx_mech_create(self.ctx, m) for m in mechs]
         self.mechs = mechs
-        self.S_max = max(int(m["n_species"]) for m in mechs)
+        # state entries per cell (a non-isothermal mechanism adds the temperature)
+        self.S_max = max(int(m["n_species"]) + (m.get("cv") is not None) for m in mechs)
         self.N, self.ldy = tuple(y0.shape)
         self.opts = make_options(rtol, atol, **opts)
         ws = bdfx_plan(self.ctx, self.N, self.mech_handles, self.opts)

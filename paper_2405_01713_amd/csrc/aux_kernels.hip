@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(256) k_perturb(Params P, uint64_t seed, int64_
   const int64_t cell = P.list ? P.list[idx] : idx;
   double *yc = P.y + cell * P.ldy;
   const double *w = P.mech.w;
-  const int S = P.n_sp;
+  const int S = P.mech.S;  // species only (a temperature entry is not perturbed)
   const uint64_t key = splitmix64(seed);
   double before = 0.0, after = 0.0;
   for (int i = 0; i < S; ++i) before = before + w[i] * yc[i];

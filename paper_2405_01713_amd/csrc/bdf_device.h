@@ -64,6 +64,10 @@ struct MechDev {
   const double *EaR;       // [R]
   const double *lnK;       // [R] (reversible only)
   const double *w;           // [S] species weights (perturbation rescale)
+  // non-isothermal cells (nullptr: isothermal): temperature is state entry S,
+  // species energies u_i(T) = u0_i + cv_i T, adiabatic at constant volume
+  const double *cv;        // [S]
+  const double *u0;        // [S]
 };
 
 struct Params {
@@ -491,6 +495,8 @@ struct Lds {
   double *kk;   // [2R]: k_f at 2r, -k_r at 2r+1 (LDS, or the wave's slot in global memory)
   const int2 *rx;  // [R]: reactant / product slot words (an LDS copy, or the mechanism's table)
   void *fac;    // [S][S] inverse Newton matrix (LT), column-major: (r, c) at c*S + r
+  double *uT;   // non-isothermal: [64 + 8] u_i(T) at the setup state (uT[kEmptySlot] = 0)
+  double *uj;   // non-isothermal: [64 + 8] sum_r dU_r dq_r/dx_c per column c (Jacobian T row)
 };
 
 // Where a wave keeps the tables its inner loops read: the reaction slot words
@@ -504,15 +510,18 @@ enum : int {
   kTabGlobal = 2,    // both in global memory (persistent waves only)
 };
 
-// doubles of LDS per wave for S species, R reactions, factor type size and
-// table placement
-__host__ __device__ constexpr int lds_doubles(int S, int R, int lt_bytes, int tab = kTabLds) {
+// doubles of LDS per wave for S state entries, R reactions, factor type
+// size, table placement and non-isothermal cells
+__host__ __device__ constexpr int lds_doubles(int S, int R, int lt_bytes, int tab = kTabLds,
+                                              bool thermal = false) {
   return 2 * kWave + 8 + Ctl::kSize + kWave / 2 + (tab == kTabLds ? R : 0) +
-         (tab == kTabGlobal ? 0 : 2 * R) + (S * S * lt_bytes + 7) / 8;
+         (tab == kTabGlobal ? 0 : 2 * R) + (S * S * lt_bytes + 7) / 8 +
+         (thermal ? 2 * (kWave + 8) : 0);
 }
 
-template <int TAB>
-__device__ __forceinline__ Lds carve(double *base, int R, const int32_t *mech_rx, double *kk_slot) {
+template <int TAB, bool TH = false>
+__device__ __forceinline__ Lds carve(double *base, int R, const int32_t *mech_rx, double *kk_slot,
+                                     int S = 0, int lt_bytes = 8) {
   Lds L;
   L.yb = base;
   L.fb = base + kWave + 8;
@@ -532,6 +541,12 @@ __device__ __forceinline__ Lds carve(double *base, int R, const int32_t *mech_rx
     L.rx = reinterpret_cast<const int2 *>(mech_rx);
   }
   L.fac = next;
+  if constexpr (TH) {
+    L.uT = next + (S * S * lt_bytes + 7) / 8;
+    L.uj = L.uT + kWave + 8;
+  } else {
+    L.uT = L.uj = nullptr;
+  }
   return L;
 }
 
@@ -552,20 +567,23 @@ __device__ __forceinline__ int slot_species(int word, int s) { return (word >> (
 // slots are neither gathered nor tested.  The products and sums are formed in
 // the generic path's order (the empty slots there multiply by exactly 1) and
 // the atomics land in its order, so both paths give the same bits.
+//
+// Non-isothermal cells (TH) pass the rate constants at the current
+// temperature (kf and -kr); otherwise they come from the table of the cell.
 template <bool ABC>
-__device__ __forceinline__ void rhs_reaction(const Lds &L, int r, int2 w) {
+__device__ __forceinline__ void rhs_reaction(const Lds &L, int r, int2 w, double kf, double krn) {
   if constexpr (ABC) {
 #pragma clang fp contract(off)
     const int a0 = slot_species(w.x, 0), a1 = slot_species(w.x, 1), b0 = slot_species(w.y, 0);
-    const double pf = L.kk[2 * r] * L.yb[a0] * L.yb[a1];
-    const double pr = L.kk[2 * r + 1] * L.yb[b0];
+    const double pf = kf * L.yb[a0] * L.yb[a1];
+    const double pr = krn * L.yb[b0];
     const double q = pf + pr;
     atomicAdd(&L.fb[a0], -q);
     atomicAdd(&L.fb[b0], q);
     atomicAdd(&L.fb[a1], -q);
     return;
   }
-  double pf = L.kk[2 * r], pr = L.kk[2 * r + 1];
+  double pf = kf, pr = krn;
   // empty slots read the 1.0 at yb[kEmptySlot]: the six gathers issue together
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
@@ -581,23 +599,58 @@ __device__ __forceinline__ void rhs_reaction(const Lds &L, int r, int2 w) {
   }
 }
 
-template <bool ABC, int G>
+// Rate constants of reaction r at temperature 1 / rT for a non-isothermal
+// cell: the table holds ln k_f0 (ln A plus the log of the cell's scale) and
+// -exp(-ln K); k_f = exp(ln k_f0 - EaR rT).
+__device__ __forceinline__ void thermal_rates(const MechDev &m, const Lds &L, int r, double rT,
+                                              double &kf, double &krn) {
+  kf = exp(L.kk[2 * r] - m.EaR[r] * rT);
+  krn = kf * L.kk[2 * r + 1];
+}
+
+// Non-isothermal cells (TH): lane ns (= the species count) holds the
+// temperature; the rate constants are evaluated at it, and that lane gets
+// dT/dt = F_T - sum_i u_i(T) f_i / sum_i cv_i y_i.
+template <bool ABC, bool TH = false, int G>
 __device__ __forceinline__ double rhs(const MechDev &m, const Lds &L, const Grp<G> &W, double yi,
-                                      double Fi) {
+                                      double Fi, int ns = 0) {
   wave_lds_sync();
   L.yb[W.lane] = yi;
   L.fb[W.lane] = Fi;
   wave_lds_sync();
   const int R = m.R;
+  double rT = 0.0;
+  if constexpr (TH) rT = W.uni(rcp(W.bcast(yi, ns)));
   const int2 none = make_int2(0x40404040, 0x40404040);  // every slot empty
   for (int r0 = 0; r0 < R; r0 += 2 * W.kLanes) {
     const int ra = r0 + W.lane, rb = ra + W.kLanes;
     const int2 wa = ra < R ? L.rx[ra] : none;
     const int2 wb = rb < R ? L.rx[rb] : none;
-    if (ra < R) rhs_reaction<ABC>(L, ra, wa);
-    if (rb < R) rhs_reaction<ABC>(L, rb, wb);
+    if constexpr (TH) {
+      if (ra < R) {
+        double kf, krn;
+        thermal_rates(m, L, ra, rT, kf, krn);
+        rhs_reaction<ABC>(L, ra, wa, kf, krn);
+      }
+      if (rb < R) {
+        double kf, krn;
+        thermal_rates(m, L, rb, rT, kf, krn);
+        rhs_reaction<ABC>(L, rb, wb, kf, krn);
+      }
+    } else {
+      if (ra < R) rhs_reaction<ABC>(L, ra, wa, L.kk[2 * ra], L.kk[2 * ra + 1]);
+      if (rb < R) rhs_reaction<ABC>(L, rb, wb, L.kk[2 * rb], L.kk[2 * rb + 1]);
+    }
   }
   wave_lds_sync();
+  if constexpr (TH) {
+    const double f = L.fb[W.lane];
+    const bool sp = W.lane < ns;
+    const double T = W.uni(W.bcast(yi, ns));
+    const double cv = sp ? m.cv[W.lane] : 0.0, u = sp ? fma(cv, T, m.u0[W.lane]) : 0.0;
+    const double N = W.uni(W.sum(u * f)), D = W.uni(W.sum(cv * yi));
+    return W.lane == ns ? f - N / D : f;
+  }
   return L.fb[W.lane];
 }
 
@@ -673,6 +726,111 @@ __device__ __forceinline__ void newton_matrix(LT (&a)[S], const MechDev &m, cons
 #pragma unroll
   for (int j = 0; j < S; ++j) {
     const LT v = transposed ? M[lr * S + j] : M[j * S + lr];
+    a[j] = W.lane < S ? v : static_cast<LT>(0);
+  }
+  wave_lds_sync();
+}
+
+// Row li of M = I - gamma J for a non-isothermal cell (state: ns species,
+// then the temperature T at entry ns).  As newton_matrix for the species
+// columns, with the rate constants at T; in the same pass over the reactions
+// each lane also scatters
+//   the T column: d q_r / dT = q_r EaR_r / T^2 (both rate constants carry
+//     exp(-EaR_r / T)) into the rows of the reaction's species,
+//   the species rates f_i (for the energy balance), and
+//   sum_r dU_r d q_r / dx_c for every column c, with dU_r = sum_i nu_ir u_i(T)
+//     the reaction's energy change, into L.uj,
+// and the T row follows from the energy balance dT/dt = F_T - N / D,
+// N = sum_i u_i f_i, D = sum_i cv_i y_i:
+//   M(T, j) = gamma (sum_r dU_r dq_r/dy_j - N cv_j / D) / D,
+//   M(T, T) = 1 + gamma (sum_i cv_i f_i + sum_r dU_r dq_r/dT) / D.
+template <int S, typename LT, int G>
+__device__ __forceinline__ void newton_matrix_thermal(LT (&a)[S], const MechDev &m, const Lds &L,
+                                                   const Grp<G> &W, double yi, double Fi,
+                                                   double gamma, int ns) {
+  LT *M = reinterpret_cast<LT *>(L.fac);
+  const double T = W.uni(W.bcast(yi, ns));
+  const double rT = W.uni(rcp(T));
+  const bool sp = W.lane < ns;
+  const double cv = sp ? m.cv[W.lane] : 0.0;
+  const double u = sp ? fma(cv, T, m.u0[W.lane]) : 0.0;
+  wave_lds_sync();
+  L.yb[W.lane] = yi;
+  L.fb[W.lane] = sp ? Fi : 0.0;
+  L.uT[W.lane] = u;  // 0 past the species
+  if (W.lane == 0) L.uT[kEmptySlot] = 0.0;
+  L.uj[W.lane] = 0.0;
+  for (int e = W.lane; e < S * S; e += W.kLanes)
+    M[e] = e % (S + 1) == 0 ? static_cast<LT>(1) : static_cast<LT>(0);
+  wave_lds_sync();
+  for (int r = W.lane; r < m.R; r += W.kLanes) {
+    const int2 w = L.rx[r];
+    double kf, krn;
+    thermal_rates(m, L, r, rT, kf, krn);
+    int sp2[2][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      sp2[0][k] = slot_species(w.x, k);
+      sp2[1][k] = slot_species(w.y, k);
+    }
+    double dU = 0.0, pf = kf, pr = krn;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {  // empty slots read u = 0 and y = 1
+      dU += L.uT[sp2[1][k]] - L.uT[sp2[0][k]];
+      pf *= L.yb[sp2[0][k]];
+      pr *= L.yb[sp2[1][k]];
+    }
+    const double q = pf + pr;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (sp2[0][k] != kEmptySlot) atomicAdd(&L.fb[sp2[0][k]], -q);
+      if (sp2[1][k] != kEmptySlot) atomicAdd(&L.fb[sp2[1][k]], q);
+    }
+#pragma unroll
+    for (int side = 0; side < 3; ++side) {  // 0, 1: species columns of each side; 2: T
+      if (side == 1 && !m.reversible) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (side == 2 && c > 0) break;
+        int col;
+        double d;
+        if (side == 2) {
+          col = ns;
+          d = q * m.EaR[r] * rT * rT;
+        } else {
+          col = sp2[side][c];
+          if (col == kEmptySlot) continue;
+          d = side == 0 ? kf : krn;
+#pragma unroll
+          for (int o = 0; o < 3; ++o)
+            if (o != c) d *= L.yb[sp2[side][o]];
+        }
+        const LT g = static_cast<LT>(gamma * d);
+        LT *Mc = M + col * S;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          if (sp2[0][i] != kEmptySlot) atomicAdd(Mc + sp2[0][i], g);
+          if (sp2[1][i] != kEmptySlot) atomicAdd(Mc + sp2[1][i], -g);
+        }
+        atomicAdd(&L.uj[col], d * dU);
+      }
+    }
+  }
+  wave_lds_sync();
+  const double f = L.fb[W.lane];
+  const double N = W.uni(W.sum(u * f)), cf = W.uni(W.sum(cv * f));
+  const double D = W.uni(W.sum(cv * yi));
+  const double rD = 1.0 / D;
+  if (W.lane <= ns) {
+    const double v = W.lane < ns ? gamma * (L.uj[W.lane] - N * cv * rD) * rD
+                                 : 1.0 + gamma * (cf + L.uj[ns]) * rD;
+    M[W.lane * S + ns] = static_cast<LT>(v);
+  }
+  wave_lds_sync();
+  const int lr = W.lane < S ? W.lane : 0;
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    const LT v = M[j * S + lr];
     a[j] = W.lane < S ? v : static_cast<LT>(0);
   }
   wave_lds_sync();
@@ -800,12 +958,13 @@ __device__ __forceinline__ double wrms2(const Grp<G> &W, double v, double w, dou
   return W.uni(W.template sum<(S + 15) / 16>(t * t) * inv_n);
 }
 
-template <int S, typename LT, int TAB, int G, bool ABC>
+template <int S, typename LT, int TAB, int G, bool ABC, bool TH>
 __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, const Grp<G> &W,
                                                double *lds, double *kk_slot) {
   const MechDev &m = P.mech;
   const int R = m.R;
-  const Lds L = carve<TAB>(lds, R, m.rx, kk_slot);
+  const int ns = m.S;  // species; a non-isothermal state also holds T at entry ns
+  const Lds L = carve<TAB, TH>(lds, R, m.rx, kk_slot, S, static_cast<int>(sizeof(LT)));
   if (W.lane == 0) L.yb[kEmptySlot] = 1.0;  // empty reaction slots multiply by 1
   double *const C = L.C;
   const int n = P.n_sp;
@@ -814,10 +973,19 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
   const double rtol = P.rtol, t0 = P.t0, tout = P.tout;
   const int qmax = P.max_order < 1 ? 1 : (P.max_order > kQmax ? kQmax : P.max_order);
 
-  // rate constants (Arrhenius, frozen T)
-  const double T = P.T ? P.T[cell] : 1.0;
+  // rate constants (Arrhenius, frozen T); a non-isothermal cell keeps
+  // ln k_f0 and -exp(-ln K) and evaluates them at its temperature later
+  const double T = (P.T && !TH) ? P.T[cell] : 1.0;
   wave_lds_sync();
   for (int r = W.lane; r < R; r += W.kLanes) {
+    if constexpr (TH) {
+      double lk = m.lnA[r];
+      if (P.kscale) lk += log(P.kscale[cell * P.ldk + r]);
+      L.kk[2 * r] = lk;
+      L.kk[2 * r + 1] = m.reversible ? -exp(-m.lnK[r]) : -0.0;
+      if constexpr (TAB == kTabLds) const_cast<int2 *>(L.rx)[r] = reinterpret_cast<const int2 *>(m.rx)[r];
+      continue;
+    }
     double lk = m.lnA[r];
     lk -= m.EaR[r] / T;
     double kf = exp(lk);
@@ -848,7 +1016,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
   double f = 0.0, ewt = 0.0;
   if (status == kSuccess) {
     z[0] = yin;
-    f = rhs<ABC>(m, L, W, yin, Fi);
+    f = rhs<ABC, TH>(m, L, W, yin, Fi, ns);
     nfe = 1;
     if (W.any(own && !isfinite(f))) {
       status = kNonfinite;
@@ -869,7 +1037,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       double hg = sqrt(hlb * hub), hnew = hg;
       bool at_ub = false;
       for (int it = 0; it < 4; ++it) {
-        const double ft = rhs<ABC>(m, L, W, yin + hg * f, Fi);
+        const double ft = rhs<ABC, TH>(m, L, W, yin + hg * f, Fi, ns);
         nfe++;
         const double ydd = (ft - f) / hg;
         const double yddnrm = sqrt(wrms2<S>(W, ydd, ewt, inv_n));
@@ -962,7 +1130,10 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
         int info;
         {
           LT a[S];
-          newton_matrix<S, LT, ABC>(a, m, L, W, z[0], gamma, false);
+          if constexpr (TH)
+            newton_matrix_thermal<S, LT>(a, m, L, W, z[0], Fi, gamma, ns);
+          else
+            newton_matrix<S, LT, ABC>(a, m, L, W, z[0], gamma, false);
           info = gj_invert<S, LT>(a, W, L);
         }
         nsetups++;
@@ -996,7 +1167,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       const double tol2 = 0.01 * W.uni(rcp(Cerr * Cerr));
       e = 0.0;
       for (int mit = 0; mit < 3; ++mit) {
-        f = rhs<ABC>(m, L, W, z[0] + e, Fi);
+        f = rhs<ABC, TH>(m, L, W, z[0] + e, Fi, ns);
         nfe++;
         nni++;
         const double Gi = e - gamma * f + z[1] * rl1;
@@ -1046,7 +1217,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
         // restart at order 1 from the last accepted y
         const double hnew = W.uni(0.1 * h);
         q = 1;
-        const double f0 = rhs<ABC>(m, L, W, z[0], Fi);
+        const double f0 = rhs<ABC, TH>(m, L, W, z[0], Fi, ns);
         nfe++;
 #pragma unroll
         for (int j = 2; j <= kQmax; ++j) z[j] = 0.0;

@@ -18,8 +18,9 @@ namespace bdfx {
 // its own LDS area of P.lds_doubles and pops its own cells.  With the tables
 // in global memory, wave w of the grid owns rate-constant slot w (the host
 // guarantees that the grid's waves fit the slot array).  ABC: every reaction
-// is A + B <=> C (see rhs_reaction).
-template <int S, typename LT, int MINW, int TAB, int G, bool ABC>
+// is A + B <=> C (see rhs_reaction).  TH: non-isothermal cells (temperature
+// as the last state entry, rates re-evaluated from it).
+template <int S, typename LT, int MINW, int TAB, int G, bool ABC, bool TH>
 __global__ void __launch_bounds__(256, MINW) k_integrate(Params P) {
   extern __shared__ double smem[];
   const int wib = threadIdx.x / kWave;
@@ -45,7 +46,7 @@ __global__ void __launch_bounds__(256, MINW) k_integrate(Params P) {
     if (next >= P.n_list) break;
     const int64_t cell = P.list ? P.list[next] : next;
     ++next;
-    integrate_cell<S, LT, TAB, G, ABC>(P, cell, W, lds, kk_slot);
+    integrate_cell<S, LT, TAB, G, ABC, TH>(P, cell, W, lds, kk_slot);
   }
 }
 
@@ -65,11 +66,12 @@ struct LaunchCfg {
 };
 
 // the three register budgets of one kernel configuration
-template <int S, typename LT, int TAB, int G, bool ABC>
+template <int S, typename LT, int TAB, int G, bool ABC, bool TH = false>
 const void *by_budget(int w) {
   using F = const void *;
-  static const F t[3] = {F(&k_integrate<S, LT, 1, TAB, G, ABC>), F(&k_integrate<S, LT, 3, TAB, G, ABC>),
-                         F(&k_integrate<S, LT, 4, TAB, G, ABC>)};
+  static const F t[3] = {F(&k_integrate<S, LT, 1, TAB, G, ABC, TH>),
+                         F(&k_integrate<S, LT, 3, TAB, G, ABC, TH>),
+                         F(&k_integrate<S, LT, 4, TAB, G, ABC, TH>)};
   return t[w];
 }
 
@@ -100,20 +102,30 @@ const void *integrate_kernel_abc(bool fp32, int w, int tab, int cells_per_wave) 
 }
 
 // the integrator kernel for (LU precision, register budget, table placement,
-// cells per wave, A + B <=> C mechanism); nullptr where no such variant is
-// built (two cells per wave only with the tables in LDS; tables in global
-// memory only for sizes whose LDS can limit the resident waves)
+// cells per wave, A + B <=> C mechanism, non-isothermal); nullptr where no
+// such variant is built (two cells per wave only with the tables in LDS;
+// tables in global memory only for sizes whose LDS can limit the resident
+// waves; non-isothermal cells one per wave with the tables in LDS)
 template <int S>
-const void *integrate_kernel(bool fp32, int minw, int tab, int cells_per_wave, bool abc) {
+const void *integrate_kernel(bool fp32, int minw, int tab, int cells_per_wave, bool abc,
+                             bool thermal) {
   const int w = minw >= 4 ? 2 : minw >= 3 ? 1 : 0;
+  if (thermal) {
+    if (tab != kTabLds || cells_per_wave != 1) return nullptr;
+    if (abc)
+      return fp32 ? by_budget<S, float, kTabLds, 1, true, true>(w)
+                  : by_budget<S, double, kTabLds, 1, true, true>(w);
+    return fp32 ? by_budget<S, float, kTabLds, 1, false, true>(w)
+                : by_budget<S, double, kTabLds, 1, false, true>(w);
+  }
   return abc ? integrate_kernel_abc<S, true>(fp32, w, tab, cells_per_wave)
              : integrate_kernel_abc<S, false>(fp32, w, tab, cells_per_wave);
 }
 
 template <int S>
 hipError_t launch_integrate(const Params &P, bool fp32, int minw, int tab, int cells_per_wave,
-                            bool abc, const LaunchCfg &c, hipStream_t s) {
-  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc);
+                            bool abc, bool thermal, const LaunchCfg &c, hipStream_t s) {
+  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc, thermal);
   if (!f) return hipErrorInvalidDeviceFunction;
   Params arg = P;
   void *args[] = {&arg};
@@ -128,8 +140,8 @@ hipError_t launch_adjoint(const Params &P, const LaunchCfg &c, hipStream_t s) {
 
 template <int S>
 hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave, bool abc,
-                               int block, size_t lds_bytes, int *blocks_per_cu) {
-  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc);
+                               bool thermal, int block, size_t lds_bytes, int *blocks_per_cu) {
+  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc, thermal);
   if (!f) {
     *blocks_per_cu = 0;
     return hipSuccess;
@@ -142,12 +154,12 @@ hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave,
 // One translation unit per species size (compiled in parallel).
 #define BDFX_DEFINE_SIZE(S)                                                                      \
   hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, int tab, int cpw,      \
-                              bool abc, const bdfx::LaunchCfg &c, hipStream_t s) {               \
-    return bdfx::launch_integrate<S>(P, fp32, minw, tab, cpw, abc, c, s);                        \
+                              bool abc, bool th, const bdfx::LaunchCfg &c, hipStream_t s) {      \
+    return bdfx::launch_integrate<S>(P, fp32, minw, tab, cpw, abc, th, c, s);                    \
   }                                                                                              \
-  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, bool abc, int block,     \
-                                 size_t lds, int *out) {                                         \
-    return bdfx::occupancy_integrate<S>(fp32, minw, tab, cpw, abc, block, lds, out);             \
+  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, bool abc, bool th,       \
+                                 int block, size_t lds, int *out) {                              \
+    return bdfx::occupancy_integrate<S>(fp32, minw, tab, cpw, abc, th, block, lds, out);         \
   }                                                                                              \
   hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s) { \
     return bdfx::launch_adjoint<S>(P, c, s);                                                     \
@@ -155,7 +167,7 @@ hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave,
 
 #define BDFX_DECLARE_SIZE(S)                                                                     \
   hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, int tab, int cpw,      \
-                              bool abc, const bdfx::LaunchCfg &c, hipStream_t s);                \
-  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, bool abc, int block,     \
-                                 size_t lds, int *out);                                          \
+                              bool abc, bool th, const bdfx::LaunchCfg &c, hipStream_t s);       \
+  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, bool abc, bool th,       \
+                                 int block, size_t lds, int *out);                               \
   hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s);

@@ -52,9 +52,9 @@ thread_local std::string g_create_error;
 
 struct SizeEntry {
   int S;
-  hipError_t (*launch)(const bdfx::Params &, bool, int, int, int, bool, const bdfx::LaunchCfg &,
-                       hipStream_t);
-  hipError_t (*occupancy)(bool, int, int, int, bool, int, size_t, int *);
+  hipError_t (*launch)(const bdfx::Params &, bool, int, int, int, bool, bool,
+                       const bdfx::LaunchCfg &, hipStream_t);
+  hipError_t (*occupancy)(bool, int, int, int, bool, bool, int, size_t, int *);
   hipError_t (*adjoint)(const bdfx::Params &, const bdfx::LaunchCfg &, hipStream_t);
 };
 
@@ -88,8 +88,10 @@ constexpr int kExtMaxBlocks = 1024;
 struct bdfx_mech_s {
   bdfx_ctx ctx = nullptr;
   int S = 0, R = 0;
+  int n = 0;             // state entries per cell: S, plus the temperature if non-isothermal
   bool reversible = false;
-  bool abc = false;  // every reaction A + B <=> C (specialised kernels)
+  bool abc = false;      // every reaction A + B <=> C (specialised kernels)
+  bool thermal = false;  // temperature as a state (heat capacities given)
   void *dmem = nullptr;
   bdfx::MechDev dev{};
   std::vector<double> w;
@@ -216,6 +218,14 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
   if (S < 1 || S > BDFX_MAX_SPECIES) return fail(ctx, BDFX_EINVAL, "n_species %d out of 1..64", S);
   if (R < 1 || R > (1 << 15)) return fail(ctx, BDFX_EINVAL, "n_reactions %d out of range", R);
   if (!d->reac || !d->prod || !d->lnA) return fail(ctx, BDFX_EINVAL, "reac/prod/lnA required");
+  const bool thermal = d->cv != nullptr;
+  if (thermal != (d->u0 != nullptr)) return fail(ctx, BDFX_EINVAL, "cv and u0 go together");
+  if (thermal && S + 1 > BDFX_MAX_SPECIES)
+    return fail(ctx, BDFX_EINVAL, "non-isothermal: n_species + 1 must be <= 64");
+  if (thermal)
+    for (int i = 0; i < S; ++i)
+      if (!(d->cv[i] > 0.0) || !std::isfinite(d->cv[i]) || !std::isfinite(d->u0[i]))
+        return fail(ctx, BDFX_EINVAL, "species %d: cv must be positive, u0 finite", i);
   for (int r = 0; r < R; ++r)
     for (int l = 0; l < BDFX_SLOTS; ++l) {
       const int a = d->reac[r * 3 + l], b = d->prod[r * 3 + l];
@@ -253,7 +263,8 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
     return o;
   };
   const size_t o_rx = reserve(rx.size() * 4), o_lnA = reserve(R * 8), o_EaR = reserve(R * 8),
-               o_lnK = reserve(R * 8), o_w = reserve(S * 8);
+               o_lnK = reserve(R * 8), o_w = reserve(S * 8), o_cv = reserve(thermal ? S * 8 : 0),
+               o_u0 = reserve(thermal ? S * 8 : 0);
   HIPCHK(ctx, hipSetDevice(ctx->device));
   void *dmem = nullptr;
   HIPCHK(ctx, hipMalloc(&dmem, off));
@@ -267,6 +278,8 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
   if (e == hipSuccess) e = up(o_EaR, EaR.data(), R * 8);
   if (e == hipSuccess) e = up(o_lnK, lnK.data(), R * 8);
   if (e == hipSuccess) e = up(o_w, w.data(), S * 8);
+  if (e == hipSuccess && thermal) e = up(o_cv, d->cv, S * 8);
+  if (e == hipSuccess && thermal) e = up(o_u0, d->u0, S * 8);
   if (e != hipSuccess) {
     hipFree(dmem);
     return fail(ctx, BDFX_EHIP, "mechanism upload: %s", hipGetErrorString(e));
@@ -275,8 +288,10 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
   m->ctx = ctx;
   m->S = S;
   m->R = R;
+  m->n = S + (thermal ? 1 : 0);
   m->reversible = reversible;
   m->abc = abc;
+  m->thermal = thermal;
   m->dmem = dmem;
   m->w = w;
   bdfx::MechDev &dv = m->dev;
@@ -288,6 +303,8 @@ int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *d, bdfx_mech *out) {
   dv.EaR = reinterpret_cast<const double *>(base + o_EaR);
   dv.lnK = reinterpret_cast<const double *>(base + o_lnK);
   dv.w = reinterpret_cast<const double *>(base + o_w);
+  dv.cv = thermal ? reinterpret_cast<const double *>(base + o_cv) : nullptr;
+  dv.u0 = thermal ? reinterpret_cast<const double *>(base + o_u0) : nullptr;
   *out = m;
   return BDFX_OK;
 }
@@ -336,7 +353,9 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
   int S_max = 0, R_max = 0;
   for (int m = 0; m < n_mech; ++m) {
     if (!mechs[m] || mechs[m]->ctx != ctx) return fail(ctx, BDFX_EINVAL, "bad mechanism %d", m);
-    S_max = std::max(S_max, mechs[m]->S);
+    S_max = std::max(S_max, mechs[m]->n);
+    if (mechs[m]->thermal && o->record_steps > 0)
+      return fail(ctx, BDFX_EUNSUPPORTED, "step recording (adjoint) needs isothermal mechanisms");
     R_max = std::max(R_max, mechs[m]->R);
   }
   if (o->atol_len != 1 && o->atol_len < S_max)
@@ -449,7 +468,7 @@ int bdfx_bind(bdfx_ctx ctx, void *d_ws, size_t ws_bytes, double *d_y, int32_t ld
     std::vector<int> order(nm);
     for (int m = 0; m < nm; ++m) order[m] = m;
     std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return ctx->mechs[a]->S > ctx->mechs[b]->S; });
+                     [&](int a, int b) { return ctx->mechs[a]->n > ctx->mechs[b]->n; });
     for (int m : order) ctx->bins.push_back({m, cnt[m], cnt[m + 1] - cnt[m]});
   }
   if (const int rc = configure_bins(ctx)) return rc;
@@ -467,11 +486,12 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
   const bool fp32 = ctx->opt.lu_precision == 32;
   const bool queue = ctx->opt.scheduler == BDFX_SCHED_QUEUE;
   const bdfx_mech m = ctx->mechs[b.mech];
-  b.se = size_for(m->S);
-  if (!b.se) return fail(ctx, BDFX_EUNSUPPORTED, "no kernel for %d species", m->S);
+  b.se = size_for(m->n);
+  if (!b.se) return fail(ctx, BDFX_EUNSUPPORTED, "no kernel for %d state entries", m->n);
   const int cpw = b.cells_per_wave;
-  if (cpw != 1 && !(cpw == 2 && b.se->S <= 32))
-    return fail(ctx, BDFX_EUNSUPPORTED, "%d cells per wave with %d species", cpw, b.se->S);
+  if (cpw != 1 && !(cpw == 2 && b.se->S <= 32 && !m->thermal))
+    return fail(ctx, BDFX_EUNSUPPORTED, "%d cells per wave with %d state entries%s", cpw, b.se->S,
+                m->thermal ? " (non-isothermal)" : "");
   const int waves = std::max(b.waves_per_block, 1);
   b.cfg.block = bdfx::kWave * waves;
   const int64_t per_block = static_cast<int64_t>(waves) * cpw;
@@ -485,12 +505,12 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
   int64_t grid[3] = {0, 0, 0};
   for (int k : {bdfx::kTabLds, bdfx::kTabRxGlobal, bdfx::kTabGlobal}) {
     const int32_t d = static_cast<int32_t>(
-        align_up(bdfx::lds_doubles(b.se->S, m->R, fp32 ? 4 : 8, k), 2));
+        align_up(bdfx::lds_doubles(b.se->S, m->R, fp32 ? 4 : 8, k, m->thermal), 2));
     lds[k] = static_cast<size_t>(waves) * cpw * d * 8;
     if (lds[k] > 65536 || (k != bdfx::kTabLds && cpw != 1) || (k == bdfx::kTabGlobal && !queue))
       continue;
-    HIPCHK(ctx, b.se->occupancy(fp32, b.waves_per_simd, k, cpw, m->abc, b.cfg.block, lds[k],
-                                &occ[k]));
+    HIPCHK(ctx, b.se->occupancy(fp32, b.waves_per_simd, k, cpw, m->abc, m->thermal, b.cfg.block,
+                                lds[k], &occ[k]));
     if (queue) {
       const int per_cu = ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : std::max(occ[k], 1);
       grid[k] = std::min<int64_t>(static_cast<int64_t>(per_cu) * ctx->n_cu, need);
@@ -522,8 +542,9 @@ static int configure_bins(bdfx_ctx ctx) {
       b.waves_per_block = ctx->opt.waves_per_block > 0 ? ctx->opt.waves_per_block : 1;
       b.queue_chunk = ctx->opt.queue_chunk > 0 ? ctx->opt.queue_chunk : 1;
       // two cells per wave where the mechanism fits a half-wave
-      const SizeEntry *se = size_for(ctx->mechs[b.mech]->S);
-      b.cells_per_wave = ctx->opt.cells_per_wave == 2 && se && se->S <= 32 ? 2 : 1;
+      const SizeEntry *se = size_for(ctx->mechs[b.mech]->n);
+      b.cells_per_wave =
+          ctx->opt.cells_per_wave == 2 && se && se->S <= 32 && !ctx->mechs[b.mech]->thermal ? 2 : 1;
     }
     if (const int rc = configure_bin(ctx, b)) return rc;
   }
@@ -559,7 +580,7 @@ static bdfx::Params make_params(bdfx_ctx ctx, const Bin &b, double t0, double to
   }
   P.max_order = ctx->opt.max_order;
   P.max_steps = ctx->opt.max_steps;
-  P.n_sp = m->S;
+  P.n_sp = m->n;
   P.queue = reinterpret_cast<uint32_t *>(ctx->ws + ctx->off_queue) + b.mech;
   P.chunk = b.queue_chunk;
   P.kk_slots = ctx->kk_slots ? reinterpret_cast<double *>(ctx->ws + ctx->off_kk) : nullptr;
@@ -591,7 +612,8 @@ int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out) {
     P.use_queue = queue ? 1 : 0;
     P.lds_doubles = b.lds_doubles;
     HIPCHK(ctx, b.se->launch(P, fp32, b.waves_per_simd, b.tab, b.cells_per_wave,
-                             ctx->mechs[b.mech]->abc, b.cfg, ctx->stream));
+                             ctx->mechs[b.mech]->abc, ctx->mechs[b.mech]->thermal, b.cfg,
+                             ctx->stream));
   }
   ctx->last_t0 = t0;
   ctx->last_tout = t_out;
@@ -675,15 +697,16 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
           float total = 0.0f;
           hipError_t e = hipSuccess;
           for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // rep 0 warms up
-            e = bdfx_launch_copy_rows(ctx->y, ctx->ldy, P.list, trial.count, m->S, save, false,
+            e = bdfx_launch_copy_rows(ctx->y, ctx->ldy, P.list, trial.count, m->n, save, false,
                                       ctx->stream);
             if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
             if (e == hipSuccess && queue) e = bdfx_launch_fill_u32(qctr, 64, 0u, ctx->stream);
             if (e == hipSuccess)
-              e = trial.se->launch(P, fp32, wps, trial.tab, cpw, m->abc, trial.cfg, ctx->stream);
+              e = trial.se->launch(P, fp32, wps, trial.tab, cpw, m->abc, m->thermal, trial.cfg,
+                                   ctx->stream);
             if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
             if (e == hipSuccess)
-              e = bdfx_launch_copy_rows(ctx->y, ctx->ldy, P.list, trial.count, m->S, save, true,
+              e = bdfx_launch_copy_rows(ctx->y, ctx->ldy, P.list, trial.count, m->n, save, true,
                                         ctx->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.0f;
@@ -758,7 +781,7 @@ int bdfx_typical_atol(bdfx_ctx ctx, double eta, double *d_typical) {
   int32_t S[BDFX_MAX_MECH] = {0}, nblk[BDFX_MAX_MECH] = {0};
   int64_t off[BDFX_MAX_MECH] = {0};
   for (int m = 0; m < n_mech; ++m) {
-    S[m] = ctx->mechs[m]->S;
+    S[m] = ctx->mechs[m]->n;
     off[m] = static_cast<int64_t>(m) * kExtMaxBlocks * 2 * bdfx::kWave;
   }
   for (const Bin &b : ctx->bins) {

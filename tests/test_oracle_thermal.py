@@ -133,3 +133,17 @@ def test_tiny_system_against_rk4(oracle):
     x, st = oracle.integrate([m], x0[None, :], 0.0, t1, 1e-10, np.array([1e-14] * 3 + [1e-10]))
     assert st["status"][0] == 0
     assert np.all(np.abs(x[0] - ref2) <= 1e-7 * np.abs(ref2) + 1e-12)
+
+
+def test_global_parity_criterion_is_met_by_the_oracle_itself(oracle):
+    from tests.conftest import assert_parity_global
+    w = W.make_workload("s21_r84_thermal_262k", 256)
+    yo, st = oracle.integrate(w["mechs"], w["y0"], 0.0, w["t_out"], w["rtol"], w["atol"])
+    assert np.all(st["status"] == 0)
+    rng = np.random.default_rng(0)
+    y1 = w["y0"] * (1 + 1e-15 * rng.standard_normal(w["y0"].shape))
+    yp, stp = oracle.integrate(w["mechs"], y1, 0.0, w["t_out"], w["rtol"], w["atol"])
+    assert np.all(stp["status"] == 0)
+    r = assert_parity_global(yp, yo, w, oracle, "oracle perturbed by 1e-15")
+    # the simple bar (99 % within 10 rtol) is not met by the oracle itself here
+    assert r["frac_within_10rtol"] < 0.99
