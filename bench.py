@@ -317,6 +317,47 @@ def run_precision(steps, warmup, tuning_cache=None, n_cells=None, n_check=256):
     return out
 
 
+def run_thermal(tuning_cache=None, n_cells=None, n_check=128):
+    """Non-isothermal cells: the 21-species mechanism with synthetic
+    thermochemistry, temperature as the 22nd state entry, 262,144 cells, one
+    outer step; batched (work queue, autotuned) with the FP64 and the FP32
+    Newton matrix, against the isothermal run of the same states; the first
+    n_check cells checked against the oracle with the global-error bar."""
+    from paper_2405_01713_amd import bdfx
+
+    w = W.make_workload("s21_r84_thermal_262k", n_cells)
+    out = dict(workload="s21_r84_thermal_262k", n_cells=w["n_cells"])
+    ys = {}
+    for lu in (64, 32):
+        integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], scheduler=1,
+                                lu_precision=lu)
+        tune = integ.autotune(0.0, w["t_out"], cache=tuning_cache)
+        y0 = integ.y.clone()
+
+        def step():
+            integ.y.copy_(y0)
+            integ.integrate(0.0, w["t_out"])
+
+        ms = _timed_events(step, integ.stream, 1, 1)
+        st = integ.cell_stats()
+        ys[lu] = integ.state()[:n_check]
+        integ.close()
+        log(f"thermal lu{lu}: {ms:.1f} ms")
+        out[f"lu{lu}"] = dict(kernel_ms=ms, cells_per_s=w["n_cells"] / (ms * 1e-3), tuning=tune,
+                              failed_cells=int(np.sum(st["status"] != 0)),
+                              mean_nst=float(st["nst"].mean()), mean_nfe=float(st["nfe"].mean()))
+    try:
+        from oracle import oracle as O
+        sub = dict(w, y0=w["y0"][:n_check], n_cells=n_check)
+        yo, _ = O.integrate(w["mechs"], sub["y0"], 0.0, w["t_out"], w["rtol"], w["atol"])
+        for lu in (64, 32):
+            out[f"lu{lu}"]["vs_oracle"] = _errors(ys[lu], yo, w["rtol"], w["atol"])
+        out["check_cells"] = n_check
+    except Exception as e:  # the oracle is optional on the timing path
+        out["check_error"] = repr(e)
+    return out
+
+
 def run_typical(tuning_cache=None, reps=50, eta=1e-10):
     """Typical-value absolute tolerances (Sec. 4.1.3): the device min/max pass
     over the states (HBM-bound; bytes = cells x species x 8 read) timed with
@@ -467,7 +508,8 @@ def main():
                     help="comma list of longer measurements: 'batching' (1 M mixed cells, "
                          "10 outer steps in a HIP graph), 's53_1m' (1 M cells of the "
                          "53-species mechanism, FP64 and FP32 Newton matrix), 'typical' "
-                         "(typical-value tolerances: reduction bandwidth and integration)")
+                         "(typical-value tolerances: reduction bandwidth and integration), "
+                         "'thermal' (262,144 non-isothermal 21-species cells)")
     ap.add_argument("--tuning-cache", default=None,
                     help="JSON file of autotuned launch shapes (reused when present)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
@@ -550,6 +592,8 @@ def main():
         extra["s53_1m"] = run_precision(1, 1, tuning_cache=args.tuning_cache, n_cells=1 << 20)
     if "typical" in args.extra.split(","):
         extra["typical"] = run_typical(tuning_cache=args.tuning_cache)
+    if "thermal" in args.extra.split(","):
+        extra["thermal"] = run_thermal(tuning_cache=args.tuning_cache)
     ok = {k: v for k, v in forms.items() if v.get("parity_ok", True) and v["failed_cells"] == 0}
     best = max(ok or forms, key=lambda k: forms[k]["cells_per_s"])
     b = forms[best]

@@ -340,6 +340,7 @@ class Integrator:
         # shapes and GPUs of different size
         n_cu = self.torch.cuda.get_device_properties(self.dev).multi_processor_count
         key = lambda m: (f"CU{n_cu}|S{self.mechs[m]['n_species']}|R{self.mechs[m]['n_reactions']}"
+                         f"{'|thermal' if self.mechs[m].get('cv') is not None else ''}"
                          f"|lu{self.opts.lu_precision}|sched{self.opts.scheduler}")
         db = {}
         if cache and os.path.exists(cache):
