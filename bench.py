@@ -518,8 +518,9 @@ def main():
                     help="write profiles/traffic.json from two rocprofv3 --pmc outputs and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not supported "
-                                   "(cells shard with no communication, see DESIGN.md)"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1 (cells are independent, so a "
+                                   "larger domain shards as contiguous cell ranges, one context "
+                                   "per GPU, with no communication during integration)"}))
         sys.exit(2)
 
     if args.traffic_from:
