@@ -76,6 +76,7 @@ typedef struct {
   int32_t atol_len;   /* 1 or >= S */
   int32_t max_order;  /* 1..5 */
   int32_t max_steps;  /* per integrate call */
+  int32_t jac_dq;     /* 1: Jacobian by difference quotients (approaches 3A/3B), 0: analytic */
 } orc_opts;
 
 typedef struct {
@@ -487,6 +488,45 @@ static double orc_initial_step(const orc_sys *s, const orc_opts *o, double t0, d
   return h0;
 }
 
+/* Jacobian by forward difference quotients, one right-hand side per column
+ * (Table 1, approaches 3A/3B; the increments follow the dense
+ * difference-quotient scheme documented for CVODE): with f0 = f(y),
+ * ||f0|| its WRMS norm under the weights w and u the unit round-off,
+ *   min_inc = 1000 |h| u n ||f0||  (1 if ||f0|| = 0),
+ *   inc_j   = max(sqrt(u) |y_j|, min_inc / w_j),
+ *   J[i][j] = (f_i(y + inc_j e_j) - f0_i) / inc_j.
+ * Adds n + 1 right-hand sides to *nfe. */
+static void orc_jac_dq(const orc_sys *s, const double *y, const double *ewt, double h, double *J,
+                       int32_t *nfe) {
+  const int n = s->S;
+  double f0[ORC_MAXS], f1[ORC_MAXS], yp[ORC_MAXS];
+  sys_f(s, y, f0);
+  (*nfe)++;
+  double fnorm = orc_wrms(n, f0, ewt);
+  double min_inc = fnorm != 0.0 ? 1000.0 * fabs(h) * ORC_UROUND * n * fnorm : 1.0;
+  double srur = sqrt(ORC_UROUND);
+  for (int j = 0; j < n; ++j) {
+    double inc = fmax(srur * fabs(y[j]), min_inc / ewt[j]);
+    for (int i = 0; i < n; ++i) yp[i] = y[i];
+    yp[j] = y[j] + inc;
+    sys_f(s, yp, f1);
+    (*nfe)++;
+    for (int i = 0; i < n; ++i) J[i * n + j] = (f1[i] - f0[i]) / inc;
+  }
+}
+
+/* Test hook: the difference-quotient Jacobian of one cell at y (rates from T
+ * and kscale for an isothermal mechanism; from y's temperature otherwise). */
+void orc_jacobian_dq(const orc_mech *m, double T, const double *kscale, const double *F,
+                     const double *y, const double *ewt, double h, double *J) {
+  double kf[4096], kr[4096];
+  const int thermal = m->cv != NULL;
+  if (!thermal) orc_rates(m, T, kscale, kf, kr);
+  orc_sys s = {m, kf, kr, F, m->n_species + thermal, kscale};
+  int32_t nfe = 0;
+  orc_jac_dq(&s, y, ewt, h, J, &nfe);
+}
+
 /* eta = 1 / ((bias * err)^(1/p) + 1e-6): step ratio that would bring an
  * error estimate err of an order-(p-1) method to 1/bias. */
 static double orc_eta(double bias, double err, int p) {
@@ -595,7 +635,10 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
 
       int fresh = 0;
       if (need_setup || st->nst >= nst_setup + 20 || fabs(gamma / gamma_bar - 1.0) > 0.3) {
-        sys_jac(s, z[0], J);
+        if (o->jac_dq)
+          orc_jac_dq(s, z[0], ewt, h, J, &st->nfe);
+        else
+          sys_jac(s, z[0], J);
         for (int i = 0; i < S; ++i)
           for (int j = 0; j < S; ++j) M[i * S + j] = (i == j ? 1.0 : 0.0) - gamma * J[i * S + j];
         st->nsetups++;

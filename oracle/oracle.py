@@ -43,7 +43,7 @@ class Mech(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_void_p), ("atol_len", C.c_int32),
-                ("max_order", C.c_int32), ("max_steps", C.c_int32)]
+                ("max_order", C.c_int32), ("max_steps", C.c_int32), ("jac_dq", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -80,6 +80,7 @@ def lib():
         L.orc_rhs.argtypes = [P, P, P, P, P, P]
         L.orc_jac.argtypes = [P, P, P, P, P]
         L.orc_rhs_thermal.argtypes = [P, P, P, P, P]
+        L.orc_jacobian_dq.argtypes = [P, C.c_double, P, P, P, P, C.c_double, P]
         L.orc_jac_thermal.argtypes = [P, P, P, P, P]
         L.orc_lu_factor.argtypes = [C.c_int, P, P]
         L.orc_lu_factor.restype = C.c_int32
@@ -141,9 +142,10 @@ class OracleMech:
         return C.byref(self.c)
 
 
-def _opts(rtol, atol, max_order=5, max_steps=5000):
+def _opts(rtol, atol, max_order=5, max_steps=5000, jac_dq=False):
     atol_arr = np.atleast_1d(np.asarray(atol, dtype=np.float64)).copy()
-    o = Opts(float(rtol), _p(atol_arr), int(atol_arr.size), int(max_order), int(max_steps))
+    o = Opts(float(rtol), _p(atol_arr), int(atol_arr.size), int(max_order), int(max_steps),
+             int(bool(jac_dq)))
     return o, atol_arr
 
 
@@ -179,6 +181,17 @@ def jac_thermal(mech, x, kscale=None, F=None):
     x = _f64(x)
     J = np.zeros((m.S + 1, m.S + 1))
     lib().orc_jac_thermal(m.ptr, _p(_f64(kscale)), _p(_f64(F)), _p(x), _p(J))
+    return J
+
+
+def jacobian_dq(mech, y, ewt, h, T=1.0, kscale=None, F=None):
+    """Difference-quotient Jacobian (n x n, n = state length) at y."""
+    m = OracleMech(mech)
+    y = _f64(y)
+    n = m.S + (1 if m.thermal else 0)
+    J = np.zeros((n, n))
+    lib().orc_jacobian_dq(m.ptr, float(T), _p(_f64(kscale)), _p(_f64(F)), _p(y), _p(_f64(ewt)),
+                          float(h), _p(J))
     return J
 
 
@@ -222,8 +235,9 @@ def bdf_coeffs(q, xi):
 
 
 def integrate(mechs, y0, t0, t_out, rtol, atol, T=None, kscale=None, F=None, cell_mech=None,
-              max_order=5, max_steps=5000, nthreads=0):
-    """Integrate a batch of cells; returns (y, stats structured array)."""
+              max_order=5, max_steps=5000, nthreads=0, jac_dq=False):
+    """Integrate a batch of cells; returns (y, stats structured array).
+    jac_dq: Jacobian by difference quotients instead of the analytic one."""
     if isinstance(mechs, dict):
         mechs = [mechs]
     oms = [OracleMech(m) for m in mechs]
@@ -235,7 +249,7 @@ def integrate(mechs, y0, t0, t_out, rtol, atol, T=None, kscale=None, F=None, cel
     ldk = 0 if ks is None else ks.shape[1]
     F = _f64(F)
     cm = None if cell_mech is None else np.ascontiguousarray(cell_mech, dtype=np.int32)
-    o, atol_arr = _opts(rtol, atol, max_order, max_steps)
+    o, atol_arr = _opts(rtol, atol, max_order, max_steps, jac_dq)
     stats = np.zeros(N, dtype=STATS_DTYPE)
     lib().orc_integrate_batch(N, C.cast(arr, C.c_void_p), _p(cm), C.byref(o), _p(T), _p(ks),
                               ldk, _p(F), ldy, float(t0), float(t_out), _p(y), _p(stats),
