@@ -113,7 +113,13 @@ typedef struct {
                               per SIMD (at most 168 / 128 VGPRs, spilling if needed) */
   int32_t cells_per_wave;  /* 0 or 1; 2 = each half-wave integrates its own cell
                               (mechanisms of at most 32 species) */
+  int32_t jacobian;        /* BDFX_JAC_ANALYTIC (0) or BDFX_JAC_DQ (1): Newton matrix from
+                              forward difference quotients, one right-hand side per state
+                              entry (Table 1, approaches 3A/3B) */
 } bdfx_options;
+
+#define BDFX_JAC_ANALYTIC 0
+#define BDFX_JAC_DQ 1
 
 /* Per-cell statistics written by bdfx_integrate() (48 bytes, [N]). */
 typedef struct {

@@ -836,6 +836,53 @@ __device__ __forceinline__ void newton_matrix_thermal(LT (&a)[S], const MechDev 
   wave_lds_sync();
 }
 
+// Row li of M = I - gamma J with J by forward difference quotients, one
+// right-hand side per state entry (Table 1, approaches 3A/3B; increments of
+// the dense difference-quotient scheme documented for CVODE): f0 = f(y),
+// min_inc = 1000 |h| u n ||f0|| (1 if ||f0|| = 0), inc_j = max(sqrt(u) |y_j|,
+// min_inc / w_j), column j = (f(y + inc_j e_j) - f0) / inc_j.  Columns are
+// written to the LDS matrix area (padding entries keep the identity), then
+// each lane reads its row.  Costs n + 1 right-hand sides.
+template <int S, typename LT, bool ABC, bool TH, int G>
+__device__ __forceinline__ void dq_matrix(LT (&a)[S], const MechDev &m, const Lds &L, const Grp<G> &W,
+                                          double y, double Fi, double gamma, double h, double ewt,
+                                          int ns, int n, double inv_n) {
+  LT *M = reinterpret_cast<LT *>(L.fac);
+  constexpr double kSrur = 1.4901161193847656e-08;  // sqrt(kUround) = 2^-26
+  double f0 = 0.0, min_inc = 1.0;
+  // pass j = -1 evaluates f0; pass j >= 0 column j (one right-hand-side body)
+  for (int j = -1; j < n; ++j) {
+    double inc = 1.0, yp = y;
+    if (j >= 0) {
+      const double yj = W.uni(W.bcast(y, j)), wj = W.uni(W.bcast(ewt, j));
+      const double sy = kSrur * fabs(yj), sm = min_inc / wj;
+      inc = W.uni(sy > sm ? sy : sm);
+      if (W.lane == j) yp = yj + inc;
+    }
+    const double f = rhs<ABC, TH>(m, L, W, yp, Fi, ns);
+    if (j < 0) {
+      f0 = f;
+      const double fnorm = W.uni(sqrt(wrms2<S>(W, f0, ewt, inv_n)));
+      min_inc = fnorm != 0.0 ? 1000.0 * fabs(h) * kUround * n * fnorm : 1.0;
+      wave_lds_sync();
+      for (int e = W.lane; e < S * S; e += W.kLanes)
+        M[e] = e % (S + 1) == 0 ? static_cast<LT>(1) : static_cast<LT>(0);
+    } else {
+      const double col = (f - f0) / inc;
+      wave_lds_sync();
+      if (W.lane < n) M[j * S + W.lane] = static_cast<LT>((W.lane == j ? 1.0 : 0.0) - gamma * col);
+    }
+  }
+  wave_lds_sync();
+  const int lr = W.lane < S ? W.lane : 0;
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    const LT v = M[j * S + lr];
+    a[j] = W.lane < S ? v : static_cast<LT>(0);
+  }
+  wave_lds_sync();
+}
+
 // ---------------------------------------------------------------------------
 // dense LU with partial pivoting, one row per lane
 // ---------------------------------------------------------------------------
@@ -958,7 +1005,7 @@ __device__ __forceinline__ double wrms2(const Grp<G> &W, double v, double w, dou
   return W.uni(W.template sum<(S + 15) / 16>(t * t) * inv_n);
 }
 
-template <int S, typename LT, int TAB, int G, bool ABC, bool TH>
+template <int S, typename LT, int TAB, int G, bool ABC, bool TH, bool DQ>
 __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, const Grp<G> &W,
                                                double *lds, double *kk_slot) {
   const MechDev &m = P.mech;
@@ -1130,10 +1177,14 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
         int info;
         {
           LT a[S];
-          if constexpr (TH)
+          if constexpr (DQ) {
+            dq_matrix<S, LT, ABC, TH>(a, m, L, W, z[0], Fi, gamma, h, ewt, ns, n, inv_n);
+            nfe += n + 1;
+          } else if constexpr (TH) {
             newton_matrix_thermal<S, LT>(a, m, L, W, z[0], Fi, gamma, ns);
-          else
+          } else {
             newton_matrix<S, LT, ABC>(a, m, L, W, z[0], gamma, false);
+          }
           info = gj_invert<S, LT>(a, W, L);
         }
         nsetups++;

@@ -19,8 +19,9 @@ namespace bdfx {
 // in global memory, wave w of the grid owns rate-constant slot w (the host
 // guarantees that the grid's waves fit the slot array).  ABC: every reaction
 // is A + B <=> C (see rhs_reaction).  TH: non-isothermal cells (temperature
-// as the last state entry, rates re-evaluated from it).
-template <int S, typename LT, int MINW, int TAB, int G, bool ABC, bool TH>
+// as the last state entry, rates re-evaluated from it).  DQ: Newton matrix
+// from difference quotients instead of the analytic Jacobian.
+template <int S, typename LT, int MINW, int TAB, int G, bool ABC, bool TH, bool DQ = false>
 __global__ void __launch_bounds__(256, MINW) k_integrate(Params P) {
   extern __shared__ double smem[];
   const int wib = threadIdx.x / kWave;
@@ -46,7 +47,7 @@ __global__ void __launch_bounds__(256, MINW) k_integrate(Params P) {
     if (next >= P.n_list) break;
     const int64_t cell = P.list ? P.list[next] : next;
     ++next;
-    integrate_cell<S, LT, TAB, G, ABC, TH>(P, cell, W, lds, kk_slot);
+    integrate_cell<S, LT, TAB, G, ABC, TH, DQ>(P, cell, W, lds, kk_slot);
   }
 }
 
@@ -66,13 +67,23 @@ struct LaunchCfg {
 };
 
 // the three register budgets of one kernel configuration
-template <int S, typename LT, int TAB, int G, bool ABC, bool TH = false>
+template <int S, typename LT, int TAB, int G, bool ABC, bool TH = false, bool DQ = false>
 const void *by_budget(int w) {
   using F = const void *;
-  static const F t[3] = {F(&k_integrate<S, LT, 1, TAB, G, ABC, TH>),
-                         F(&k_integrate<S, LT, 3, TAB, G, ABC, TH>),
-                         F(&k_integrate<S, LT, 4, TAB, G, ABC, TH>)};
+  static const F t[3] = {F(&k_integrate<S, LT, 1, TAB, G, ABC, TH, DQ>),
+                         F(&k_integrate<S, LT, 3, TAB, G, ABC, TH, DQ>),
+                         F(&k_integrate<S, LT, 4, TAB, G, ABC, TH, DQ>)};
   return t[w];
+}
+
+// difference-quotient kernels: one cell per wave, tables in LDS
+template <int S, bool TH>
+const void *dq_kernel(bool fp32, int w, bool abc) {
+  if (abc)
+    return fp32 ? by_budget<S, float, kTabLds, 1, true, TH, true>(w)
+                : by_budget<S, double, kTabLds, 1, true, TH, true>(w);
+  return fp32 ? by_budget<S, float, kTabLds, 1, false, TH, true>(w)
+              : by_budget<S, double, kTabLds, 1, false, TH, true>(w);
 }
 
 template <int S, bool ABC>
@@ -102,14 +113,19 @@ const void *integrate_kernel_abc(bool fp32, int w, int tab, int cells_per_wave) 
 }
 
 // the integrator kernel for (LU precision, register budget, table placement,
-// cells per wave, A + B <=> C mechanism, non-isothermal); nullptr where no
-// such variant is built (two cells per wave only with the tables in LDS;
-// tables in global memory only for sizes whose LDS can limit the resident
-// waves; non-isothermal cells one per wave with the tables in LDS)
+// cells per wave, A + B <=> C mechanism, non-isothermal, difference-quotient
+// Jacobian); nullptr where no such variant is built (two cells per wave only
+// with the tables in LDS; tables in global memory only for sizes whose LDS
+// can limit the resident waves; non-isothermal cells and difference
+// quotients one cell per wave with the tables in LDS)
 template <int S>
 const void *integrate_kernel(bool fp32, int minw, int tab, int cells_per_wave, bool abc,
-                             bool thermal) {
+                             bool thermal, bool dq) {
   const int w = minw >= 4 ? 2 : minw >= 3 ? 1 : 0;
+  if (dq) {
+    if (tab != kTabLds || cells_per_wave != 1) return nullptr;
+    return thermal ? dq_kernel<S, true>(fp32, w, abc) : dq_kernel<S, false>(fp32, w, abc);
+  }
   if (thermal) {
     if (tab != kTabLds || cells_per_wave != 1) return nullptr;
     if (abc)
@@ -124,8 +140,8 @@ const void *integrate_kernel(bool fp32, int minw, int tab, int cells_per_wave, b
 
 template <int S>
 hipError_t launch_integrate(const Params &P, bool fp32, int minw, int tab, int cells_per_wave,
-                            bool abc, bool thermal, const LaunchCfg &c, hipStream_t s) {
-  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc, thermal);
+                            bool abc, bool thermal, bool dq, const LaunchCfg &c, hipStream_t s) {
+  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc, thermal, dq);
   if (!f) return hipErrorInvalidDeviceFunction;
   Params arg = P;
   void *args[] = {&arg};
@@ -140,8 +156,9 @@ hipError_t launch_adjoint(const Params &P, const LaunchCfg &c, hipStream_t s) {
 
 template <int S>
 hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave, bool abc,
-                               bool thermal, int block, size_t lds_bytes, int *blocks_per_cu) {
-  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc, thermal);
+                               bool thermal, bool dq, int block, size_t lds_bytes,
+                               int *blocks_per_cu) {
+  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc, thermal, dq);
   if (!f) {
     *blocks_per_cu = 0;
     return hipSuccess;
@@ -151,15 +168,19 @@ hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave,
 
 }  // namespace bdfx
 
-// One translation unit per species size (compiled in parallel).
+// One translation unit per species size (compiled in parallel).  The
+// kernel flags are passed packed: bit 0 A + B <=> C, bit 1 non-isothermal,
+// bit 2 difference-quotient Jacobian.
 #define BDFX_DEFINE_SIZE(S)                                                                      \
   hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, int tab, int cpw,      \
-                              bool abc, bool th, const bdfx::LaunchCfg &c, hipStream_t s) {      \
-    return bdfx::launch_integrate<S>(P, fp32, minw, tab, cpw, abc, th, c, s);                    \
+                              int flags, const bdfx::LaunchCfg &c, hipStream_t s) {              \
+    return bdfx::launch_integrate<S>(P, fp32, minw, tab, cpw, flags & 1, flags & 2, flags & 4, c, \
+                                     s);                                                         \
   }                                                                                              \
-  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, bool abc, bool th,       \
-                                 int block, size_t lds, int *out) {                              \
-    return bdfx::occupancy_integrate<S>(fp32, minw, tab, cpw, abc, th, block, lds, out);         \
+  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, int flags, int block,    \
+                                 size_t lds, int *out) {                                         \
+    return bdfx::occupancy_integrate<S>(fp32, minw, tab, cpw, flags & 1, flags & 2, flags & 4,   \
+                                        block, lds, out);                                        \
   }                                                                                              \
   hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s) { \
     return bdfx::launch_adjoint<S>(P, c, s);                                                     \
@@ -167,7 +188,7 @@ hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave,
 
 #define BDFX_DECLARE_SIZE(S)                                                                     \
   hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, int tab, int cpw,      \
-                              bool abc, bool th, const bdfx::LaunchCfg &c, hipStream_t s);       \
-  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, bool abc, bool th,       \
-                                 int block, size_t lds, int *out);                               \
+                              int flags, const bdfx::LaunchCfg &c, hipStream_t s);               \
+  hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, int flags, int block,    \
+                                 size_t lds, int *out);                                          \
   hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s);

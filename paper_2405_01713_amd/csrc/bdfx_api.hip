@@ -52,9 +52,9 @@ thread_local std::string g_create_error;
 
 struct SizeEntry {
   int S;
-  hipError_t (*launch)(const bdfx::Params &, bool, int, int, int, bool, bool,
-                       const bdfx::LaunchCfg &, hipStream_t);
-  hipError_t (*occupancy)(bool, int, int, int, bool, bool, int, size_t, int *);
+  hipError_t (*launch)(const bdfx::Params &, bool, int, int, int, int, const bdfx::LaunchCfg &,
+                       hipStream_t);
+  hipError_t (*occupancy)(bool, int, int, int, int, int, size_t, int *);
   hipError_t (*adjoint)(const bdfx::Params &, const bdfx::LaunchCfg &, hipStream_t);
 };
 
@@ -350,6 +350,8 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
   if (o->max_order < 0 || o->max_order > BDFX_MAX_ORDER)
     return fail(ctx, BDFX_EINVAL, "max_order out of 1..5");
   if (o->record_steps < 0) return fail(ctx, BDFX_EINVAL, "record_steps < 0");
+  if (o->jacobian != BDFX_JAC_ANALYTIC && o->jacobian != BDFX_JAC_DQ)
+    return fail(ctx, BDFX_EINVAL, "jacobian must be BDFX_JAC_ANALYTIC or BDFX_JAC_DQ");
   int S_max = 0, R_max = 0;
   for (int m = 0; m < n_mech; ++m) {
     if (!mechs[m] || mechs[m]->ctx != ctx) return fail(ctx, BDFX_EINVAL, "bad mechanism %d", m);
@@ -418,6 +420,11 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
 }
 
 static int configure_bins(bdfx_ctx ctx);
+
+// kernel selection flags of a mechanism under the context's options
+static int kernel_flags(bdfx_ctx ctx, bdfx_mech m) {
+  return (m->abc ? 1 : 0) | (m->thermal ? 2 : 0) | (ctx->opt.jacobian == BDFX_JAC_DQ ? 4 : 0);
+}
 
 int bdfx_bind(bdfx_ctx ctx, void *d_ws, size_t ws_bytes, double *d_y, int32_t ldy,
               const int32_t *d_cell_mech, const double *d_T, const double *d_kscale, int32_t ldk,
@@ -489,7 +496,8 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
   b.se = size_for(m->n);
   if (!b.se) return fail(ctx, BDFX_EUNSUPPORTED, "no kernel for %d state entries", m->n);
   const int cpw = b.cells_per_wave;
-  if (cpw != 1 && !(cpw == 2 && b.se->S <= 32 && !m->thermal))
+  if (cpw != 1 &&
+      !(cpw == 2 && b.se->S <= 32 && !m->thermal && ctx->opt.jacobian != BDFX_JAC_DQ))
     return fail(ctx, BDFX_EUNSUPPORTED, "%d cells per wave with %d state entries%s", cpw, b.se->S,
                 m->thermal ? " (non-isothermal)" : "");
   const int waves = std::max(b.waves_per_block, 1);
@@ -509,7 +517,7 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
     lds[k] = static_cast<size_t>(waves) * cpw * d * 8;
     if (lds[k] > 65536 || (k != bdfx::kTabLds && cpw != 1) || (k == bdfx::kTabGlobal && !queue))
       continue;
-    HIPCHK(ctx, b.se->occupancy(fp32, b.waves_per_simd, k, cpw, m->abc, m->thermal, b.cfg.block,
+    HIPCHK(ctx, b.se->occupancy(fp32, b.waves_per_simd, k, cpw, kernel_flags(ctx, m), b.cfg.block,
                                 lds[k], &occ[k]));
     if (queue) {
       const int per_cu = ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : std::max(occ[k], 1);
@@ -544,7 +552,10 @@ static int configure_bins(bdfx_ctx ctx) {
       // two cells per wave where the mechanism fits a half-wave
       const SizeEntry *se = size_for(ctx->mechs[b.mech]->n);
       b.cells_per_wave =
-          ctx->opt.cells_per_wave == 2 && se && se->S <= 32 && !ctx->mechs[b.mech]->thermal ? 2 : 1;
+          ctx->opt.cells_per_wave == 2 && se && se->S <= 32 && !ctx->mechs[b.mech]->thermal &&
+                  ctx->opt.jacobian != BDFX_JAC_DQ
+              ? 2
+              : 1;
     }
     if (const int rc = configure_bin(ctx, b)) return rc;
   }
@@ -612,8 +623,7 @@ int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out) {
     P.use_queue = queue ? 1 : 0;
     P.lds_doubles = b.lds_doubles;
     HIPCHK(ctx, b.se->launch(P, fp32, b.waves_per_simd, b.tab, b.cells_per_wave,
-                             ctx->mechs[b.mech]->abc, ctx->mechs[b.mech]->thermal, b.cfg,
-                             ctx->stream));
+                             kernel_flags(ctx, ctx->mechs[b.mech]), b.cfg, ctx->stream));
   }
   ctx->last_t0 = t0;
   ctx->last_tout = t_out;
@@ -702,7 +712,7 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
             if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
             if (e == hipSuccess && queue) e = bdfx_launch_fill_u32(qctr, 64, 0u, ctx->stream);
             if (e == hipSuccess)
-              e = trial.se->launch(P, fp32, wps, trial.tab, cpw, m->abc, m->thermal, trial.cfg,
+              e = trial.se->launch(P, fp32, wps, trial.tab, cpw, kernel_flags(ctx, m), trial.cfg,
                                    ctx->stream);
             if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
             if (e == hipSuccess)

@@ -1,0 +1,55 @@
+"""GPU tests of the difference-quotient Newton matrix (Table 1, approaches
+3A/3B): parity with the oracle run with the same Jacobian option, the
+expected right-hand-side count, non-isothermal cells, and a mixed batch."""
+import numpy as np
+import pytest
+
+from paper_2405_01713_amd import workloads as W
+from tests.conftest import assert_parity_global
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(w, **opts):
+    import torch
+    from paper_2405_01713_amd import bdfx
+    integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w.get("T"),
+                            cell_mech=w.get("cell_mech"), jacobian=bdfx.BDFX_JAC_DQ, **opts)
+    integ.integrate(0.0, w["t_out"])
+    torch.cuda.synchronize()
+    y, st = integ.state(), integ.cell_stats()
+    integ.close()
+    return y, st
+
+
+@pytest.mark.parametrize("lu", [64, 32])
+def test_dq_parity(oracle, parity, lu):
+    w = W.make_workload("s21_r84_262k", 256)
+    y, st = _gpu(w, scheduler=1, lu_precision=lu)
+    yo, sto = oracle.integrate(w["mechs"], w["y0"], 0.0, w["t_out"], w["rtol"], w["atol"],
+                               T=w["T"], jac_dq=True)
+    assert np.all(st["status"] == 0) and np.all(sto["status"] == 0)
+    parity(y, yo, w, f"dq lu{lu}")
+    # n + 1 right-hand sides per setup, as in the oracle
+    extra = st["nfe"] - 22 * st["nsetups"]
+    extra_o = sto["nfe"] - 22 * sto["nsetups"]
+    assert abs(extra.mean() / extra_o.mean() - 1.0) < 0.03
+    assert abs(st["nfe"].mean() / sto["nfe"].mean() - 1.0) < 0.03
+
+
+def test_dq_non_isothermal(oracle):
+    w = W.make_workload("s21_r84_thermal_262k", 512)
+    y, st = _gpu(w, scheduler=1)
+    yo, sto = oracle.integrate(w["mechs"], w["y0"], 0.0, w["t_out"], w["rtol"], w["atol"],
+                               jac_dq=True)
+    assert np.all(st["status"] == 0) and np.all(sto["status"] == 0)
+    assert_parity_global(y, yo, w, oracle, "dq non-isothermal")
+
+
+def test_dq_mixed(oracle, parity):
+    w = W.make_workload("mixed_s9_s53_1m", 200)
+    y, st = _gpu(w, scheduler=1)
+    yo, sto = oracle.integrate(w["mechs"], w["y0"], 0.0, w["t_out"], w["rtol"], w["atol"],
+                               T=w["T"], cell_mech=w["cell_mech"], jac_dq=True)
+    assert np.all(st["status"] == 0) and np.all(sto["status"] == 0)
+    parity(y, yo, w, "dq mixed")
