@@ -358,6 +358,47 @@ def run_thermal(tuning_cache=None, n_cells=None, n_check=128):
     return out
 
 
+def run_dq(tuning_cache=None, n_check=128):
+    """Newton matrix from difference quotients (Table 1, approaches 3A/3B)
+    against the analytic Jacobian on the 21-species workload (262,144 cells,
+    one outer step, work queue, FP32 Newton matrix): time, right-hand sides
+    per cell, and the first n_check cells against the oracle run with
+    difference quotients."""
+    from paper_2405_01713_amd import bdfx
+
+    w = W.make_workload("s21_r84_262k")
+    out = dict(workload="s21_r84_262k", n_cells=w["n_cells"])
+    ys = None
+    for name, jac in (("analytic", bdfx.BDFX_JAC_ANALYTIC), ("dq", bdfx.BDFX_JAC_DQ)):
+        integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"], scheduler=1,
+                                lu_precision=32, jacobian=jac, waves_per_simd=4)
+        y0 = integ.y.clone()
+
+        def step():
+            integ.y.copy_(y0)
+            integ.integrate(0.0, w["t_out"])
+
+        ms = _timed_events(step, integ.stream, 1, 1)
+        st = integ.cell_stats()
+        if jac == bdfx.BDFX_JAC_DQ:
+            ys = integ.state()[:n_check]
+        integ.close()
+        log(f"jacobian {name}: {ms:.1f} ms")
+        out[name] = dict(kernel_ms=ms, cells_per_s=w["n_cells"] / (ms * 1e-3),
+                         mean_nfe=float(st["nfe"].mean()), mean_nsetups=float(st["nsetups"].mean()),
+                         mean_nst=float(st["nst"].mean()), failed_cells=int(np.sum(st["status"] != 0)))
+    out["dq_over_analytic"] = out["dq"]["kernel_ms"] / out["analytic"]["kernel_ms"]
+    try:
+        from oracle import oracle as O
+        yo, _ = O.integrate(w["mechs"], w["y0"][:n_check], 0.0, w["t_out"], w["rtol"], w["atol"],
+                            T=w["T"][:n_check], jac_dq=True)
+        out["dq"]["vs_oracle"] = _errors(ys, yo, w["rtol"], w["atol"])
+        out["check_cells"] = n_check
+    except Exception as e:  # the oracle is optional on the timing path
+        out["check_error"] = repr(e)
+    return out
+
+
 def run_typical(tuning_cache=None, reps=50, eta=1e-10):
     """Typical-value absolute tolerances (Sec. 4.1.3): the device min/max pass
     over the states (HBM-bound; bytes = cells x species x 8 read) timed with
@@ -509,7 +550,8 @@ def main():
                          "10 outer steps in a HIP graph), 's53_1m' (1 M cells of the "
                          "53-species mechanism, FP64 and FP32 Newton matrix), 'typical' "
                          "(typical-value tolerances: reduction bandwidth and integration), "
-                         "'thermal' (262,144 non-isothermal 21-species cells)")
+                         "'thermal' (262,144 non-isothermal 21-species cells), 'dq' "
+                         "(difference-quotient vs analytic Jacobian)")
     ap.add_argument("--tuning-cache", default=None,
                     help="JSON file of autotuned launch shapes (reused when present)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
@@ -595,6 +637,8 @@ def main():
         extra["typical"] = run_typical(tuning_cache=args.tuning_cache)
     if "thermal" in args.extra.split(","):
         extra["thermal"] = run_thermal(tuning_cache=args.tuning_cache)
+    if "dq" in args.extra.split(","):
+        extra["dq"] = run_dq(tuning_cache=args.tuning_cache)
     ok = {k: v for k, v in forms.items() if v.get("parity_ok", True) and v["failed_cells"] == 0}
     best = max(ok or forms, key=lambda k: forms[k]["cells_per_s"])
     b = forms[best]
