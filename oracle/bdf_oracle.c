@@ -17,7 +17,10 @@
  *   2A/2B) factored by dense LU with partial pivoting (Sec. 4.1.4).
  *   Step and order are controlled per cell (the paper's batches run in lock
  *   step; per-cell control removes the "stiffest cell dictates the step"
- *   limitation of Sec. 2).
+ *   limitation of Sec. 2).  Options: a Jacobian by difference quotients
+ *   (approaches 3A/3B), or an inexact Newton iteration whose linear systems
+ *   are solved by matrix-free GMRES on the scaled system of Sec. 2,
+ *   Eqs. (linear) and (stop_linear) (approaches 1A/1B).
  *
  * The paper gives no BDF coefficients, heuristics or constants beyond
  * Eqs. (3)-(4).  Where it is silent the following readings are used, each
@@ -49,6 +52,7 @@
 #define ORC_QMAX 5
 #define ORC_SLOTS 3
 #define ORC_UROUND 2.220446049250313e-16
+#define ORC_GMRES_MAXL 10
 
 /* Per-cell status codes. */
 #define ORC_SUCCESS 0
@@ -77,10 +81,13 @@ typedef struct {
   int32_t max_order;  /* 1..5 */
   int32_t max_steps;  /* per integrate call */
   int32_t jac_dq;     /* 1: Jacobian by difference quotients (approaches 3A/3B), 0: analytic */
+  int32_t gmres_maxl; /* 1..ORC_GMRES_MAXL: inexact Newton with GMRES of this Krylov dimension
+                         (approaches 1A/1B); 0: modified Newton with a direct solve */
 } orc_opts;
 
 typedef struct {
   int32_t status, nst, nfe, nni, nsetups, netf, ncfn, q_last;
+  int32_t nli, ncfl; /* GMRES iterations, linear solves that did not converge */
   double h_last, t_reached;
 } orc_stats;
 
@@ -527,6 +534,118 @@ void orc_jacobian_dq(const orc_mech *m, double T, const double *kscale, const do
   orc_jac_dq(&s, y, ewt, h, J, &nfe);
 }
 
+/* Linear solve of the inexact Newton iteration (Table 1, approaches 1A/1B):
+ * GMRES on the scaled system of Sec. 2, Eq. (linear), with S1 = S2 =
+ * diag(w) and no preconditioner (P1 = P2 = I), for A = I - gamma J(y), b.
+ * A is applied without forming J: the product J v is the difference quotient
+ * (f(y + sigma v) - f(y)) / sigma with sigma = 1 / ||v||_wrms and fy = f(y).
+ * The initial guess is 0; the Arnoldi basis is orthogonalised by modified
+ * Gram-Schmidt; Givens rotations turn the Hessenberg matrix into triangular
+ * form and give the residual norm of the scaled system as the magnitude of
+ * the last rotated right-hand-side entry, without forming the residual
+ * (Sec. 2, after Eq. (stop_linear); Saad, Iterative Methods for Sparse
+ * Linear Systems, Sec. 6.5).  Iteration stops at maxl basis vectors or when
+ * that residual norm is at most delta (Eq. (stop_linear); delta is passed in
+ * the 2-norm of the scaled system).  Returns 0 when converged, 1 when the
+ * residual was reduced but not to delta, 2 otherwise; x receives the
+ * solution of the unscaled system.  *nli counts iterations (one product J v,
+ * hence one right-hand side each), *rho_out the final residual norm. */
+static int orc_gmres(const orc_sys *s, const double *y, const double *fy, const double *ewt,
+                     double gamma, int maxl, double delta, const double *b, double *x,
+                     int32_t *nli, double *rho_out) {
+  const int n = s->S;
+  double V[ORC_GMRES_MAXL + 1][ORC_MAXS];
+  double H[ORC_GMRES_MAXL + 1][ORC_GMRES_MAXL];
+  double cs[ORC_GMRES_MAXL], sn[ORC_GMRES_MAXL], g[ORC_GMRES_MAXL + 1], c[ORC_GMRES_MAXL];
+  double v[ORC_MAXS], yp[ORC_MAXS], fp[ORC_MAXS], w[ORC_MAXS];
+  if (maxl > ORC_GMRES_MAXL) maxl = ORC_GMRES_MAXL;
+
+  for (int i = 0; i < n; ++i) x[i] = 0.0;
+  /* residual of the initial guess 0 in the scaled system: b~ = S1 b */
+  double beta = 0.0;
+  for (int i = 0; i < n; ++i) {
+    V[0][i] = ewt[i] * b[i];
+    beta += V[0][i] * V[0][i];
+  }
+  beta = sqrt(beta);
+  *rho_out = beta;
+  if (beta <= delta) return 0;
+  for (int i = 0; i < n; ++i) V[0][i] /= beta;
+  g[0] = beta;
+
+  int k = 0; /* columns of the triangular system */
+  double rho = beta;
+  for (int l = 0; l < maxl; ++l) {
+    /* w = A~ V_l = S1 (v - gamma J v), v = S2^{-1} V_l */
+    for (int i = 0; i < n; ++i) v[i] = V[l][i] / ewt[i];
+    double sigma = 1.0 / orc_wrms(n, v, ewt);
+    for (int i = 0; i < n; ++i) yp[i] = y[i] + sigma * v[i];
+    sys_f(s, yp, fp);
+    (*nli)++;
+    for (int i = 0; i < n; ++i) w[i] = ewt[i] * (v[i] - gamma * ((fp[i] - fy[i]) / sigma));
+    /* modified Gram-Schmidt against V_0..V_l */
+    for (int j = 0; j <= l; ++j) {
+      double d = 0.0;
+      for (int i = 0; i < n; ++i) d += w[i] * V[j][i];
+      H[j][l] = d;
+      for (int i = 0; i < n; ++i) w[i] -= d * V[j][i];
+    }
+    double hn = 0.0;
+    for (int i = 0; i < n; ++i) hn += w[i] * w[i];
+    hn = sqrt(hn);
+    H[l + 1][l] = hn;
+    /* earlier rotations, then the one that zeroes H[l+1][l] */
+    for (int j = 0; j < l; ++j) {
+      double a0 = H[j][l], a1 = H[j + 1][l];
+      H[j][l] = cs[j] * a0 + sn[j] * a1;
+      H[j + 1][l] = -sn[j] * a0 + cs[j] * a1;
+    }
+    double r = hypot(H[l][l], H[l + 1][l]);
+    if (!(r > 0.0)) break; /* singular Hessenberg column: stop with k columns */
+    cs[l] = H[l][l] / r;
+    sn[l] = H[l + 1][l] / r;
+    H[l][l] = r;
+    H[l + 1][l] = 0.0;
+    g[l + 1] = -sn[l] * g[l];
+    g[l] = cs[l] * g[l];
+    rho = fabs(g[l + 1]);
+    k = l + 1;
+    if (rho <= delta) break;
+    if (l + 1 < maxl) {
+      if (!(hn > 0.0)) break;
+      for (int i = 0; i < n; ++i) V[l + 1][i] = w[i] / hn;
+    }
+  }
+  *rho_out = rho;
+  /* back substitution for the coefficients, x = S2^{-1} sum_j c_j V_j */
+  for (int i = k - 1; i >= 0; --i) {
+    double t = g[i];
+    for (int j = i + 1; j < k; ++j) t -= H[i][j] * c[j];
+    c[i] = t / H[i][i];
+  }
+  for (int i = 0; i < n; ++i) {
+    double t = 0.0;
+    for (int j = 0; j < k; ++j) t += c[j] * V[j][i];
+    x[i] = t / ewt[i];
+  }
+  if (rho <= delta) return 0;
+  return rho < beta ? 1 : 2;
+}
+
+/* Test hook: one GMRES solve of (I - gamma J(y)) x = b for one cell (rates
+ * as in orc_jacobian_dq); returns orc_gmres's code, *nli and *rho. */
+int32_t orc_gmres_solve(const orc_mech *m, double T, const double *kscale, const double *F,
+                        const double *y, const double *ewt, double gamma, int32_t maxl,
+                        double delta, const double *b, double *x, int32_t *nli, double *rho) {
+  double kf[4096], kr[4096], fy[ORC_MAXS];
+  const int thermal = m->cv != NULL;
+  if (!thermal) orc_rates(m, T, kscale, kf, kr);
+  orc_sys s = {m, kf, kr, F, m->n_species + thermal, kscale};
+  sys_f(&s, y, fy);
+  *nli = 0;
+  return orc_gmres(&s, y, fy, ewt, gamma, maxl, delta, b, x, nli, rho);
+}
+
 /* eta = 1 / ((bias * err)^(1/p) + 1e-6): step ratio that would bring an
  * error estimate err of an order-(p-1) method to 1/bias. */
 static double orc_eta(double bias, double err, int p) {
@@ -561,11 +680,20 @@ static double orc_eta(double bias, double err, int p) {
  * nothing; growth is capped by eta_max (1e4 on the first step, 10
  * afterwards); right after a failure h and q are held for that step.
  * The last step is clipped to land on tout exactly.
+ *
+ * With o->gmres_maxl > 0 (Table 1, approaches 1A/1B) each Newton system is
+ * solved by orc_gmres at the current iterate (inexact Newton): no Jacobian
+ * or Newton matrix is formed, so there are no setups and no gamma-ratio
+ * scaling.  A linear solve that does not reach its tolerance ends the Newton
+ * iteration as a convergence failure (a reduced residual is accepted on the
+ * first Newton iteration), which always cuts h by 4.  Right-hand sides of the
+ * products J v count in nfe.
  */
 static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0, double tout,
                                   double *y, orc_stats *st, orc_record *rec, double *zout) {
   const int S = s->S;
   const int qmax = o->max_order < 1 ? 1 : (o->max_order > ORC_QMAX ? ORC_QMAX : o->max_order);
+  const int krylov = o->gmres_maxl > 0;
   double z[ORC_QMAX + 2][ORC_MAXS];
   double ewt[ORC_MAXS], e[ORC_MAXS], eprev[ORC_MAXS], ycur[ORC_MAXS], f[ORC_MAXS], G[ORC_MAXS];
   double delta[ORC_MAXS];
@@ -634,7 +762,8 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
       gamma = h / l[1];
 
       int fresh = 0;
-      if (need_setup || st->nst >= nst_setup + 20 || fabs(gamma / gamma_bar - 1.0) > 0.3) {
+      if (!krylov &&
+          (need_setup || st->nst >= nst_setup + 20 || fabs(gamma / gamma_bar - 1.0) > 0.3)) {
         if (o->jac_dq)
           orc_jac_dq(s, z[0], ewt, h, J, &st->nfe);
         else
@@ -673,8 +802,25 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
         st->nni++;
         for (int i = 0; i < S; ++i) G[i] = e[i] - gamma * f[i] + z[1][i] / l[1];
         for (int i = 0; i < S; ++i) delta[i] = -G[i];
-        orc_lu_solve(S, M, perm, delta);
-        if (gamma != gamma_bar) {
+        if (krylov) {
+          /* inexact Newton: J at the current iterate, Eq. (stop_linear) with
+           * c_l = 0.05 on the Newton tolerance c_eps eps = 0.1 / Cerr, in
+           * WRMS units (the scaled 2-norm is sqrt(S) times the WRMS norm) */
+          double rhs_b[ORC_MAXS], rho;
+          for (int i = 0; i < S; ++i) rhs_b[i] = delta[i];
+          int32_t nli = 0;
+          int lret = orc_gmres(s, ycur, f, ewt, gamma, o->gmres_maxl, 0.05 * (0.1 / Cerr) * sqrt(S),
+                               rhs_b, delta, &nli, &rho);
+          st->nli += nli;
+          st->nfe += nli;
+          /* a reduced but unconverged residual is accepted on the first
+           * iteration only */
+          if (lret != 0) st->ncfl++;
+          if (lret == 2 || (lret == 1 && mit > 0)) break;
+        } else {
+          orc_lu_solve(S, M, perm, delta);
+        }
+        if (!krylov && gamma != gamma_bar) {
           double c = 2.0 / (1.0 + gamma / gamma_bar);
           for (int i = 0; i < S; ++i) delta[i] *= c;
         }
@@ -700,7 +846,7 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
           status = ORC_CONV_FAILURE;
           break;
         }
-        if (fresh) {
+        if (fresh || krylov) {
           orc_rescale(S, q, 0.25, z);
           h *= 0.25;
           eta_max = 1.0;

@@ -43,21 +43,24 @@ class Mech(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_void_p), ("atol_len", C.c_int32),
-                ("max_order", C.c_int32), ("max_steps", C.c_int32), ("jac_dq", C.c_int32)]
+                ("max_order", C.c_int32), ("max_steps", C.c_int32), ("jac_dq", C.c_int32),
+                ("gmres_maxl", C.c_int32)]
 
 
 class Stats(C.Structure):
     _fields_ = [("status", C.c_int32), ("nst", C.c_int32), ("nfe", C.c_int32),
                 ("nni", C.c_int32), ("nsetups", C.c_int32), ("netf", C.c_int32),
                 ("ncfn", C.c_int32), ("q_last", C.c_int32),
+                ("nli", C.c_int32), ("ncfl", C.c_int32),
                 ("h_last", C.c_double), ("t_reached", C.c_double)]
 
 
 STATS_DTYPE = np.dtype([("status", np.int32), ("nst", np.int32), ("nfe", np.int32),
                         ("nni", np.int32), ("nsetups", np.int32), ("netf", np.int32),
                         ("ncfn", np.int32), ("q_last", np.int32),
+                        ("nli", np.int32), ("ncfl", np.int32),
                         ("h_last", np.float64), ("t_reached", np.float64)])
-assert STATS_DTYPE.itemsize == C.sizeof(Stats) == 48
+assert STATS_DTYPE.itemsize == C.sizeof(Stats) == 56
 
 
 class Record(C.Structure):
@@ -82,6 +85,9 @@ def lib():
         L.orc_rhs_thermal.argtypes = [P, P, P, P, P]
         L.orc_jacobian_dq.argtypes = [P, C.c_double, P, P, P, P, C.c_double, P]
         L.orc_jac_thermal.argtypes = [P, P, P, P, P]
+        L.orc_gmres_solve.argtypes = [P, C.c_double, P, P, P, P, C.c_double, C.c_int32,
+                                      C.c_double, P, P, P, P]
+        L.orc_gmres_solve.restype = C.c_int32
         L.orc_lu_factor.argtypes = [C.c_int, P, P]
         L.orc_lu_factor.restype = C.c_int32
         L.orc_lu_solve.argtypes = [C.c_int, P, P, P]
@@ -142,10 +148,10 @@ class OracleMech:
         return C.byref(self.c)
 
 
-def _opts(rtol, atol, max_order=5, max_steps=5000, jac_dq=False):
+def _opts(rtol, atol, max_order=5, max_steps=5000, jac_dq=False, gmres_maxl=0):
     atol_arr = np.atleast_1d(np.asarray(atol, dtype=np.float64)).copy()
     o = Opts(float(rtol), _p(atol_arr), int(atol_arr.size), int(max_order), int(max_steps),
-             int(bool(jac_dq)))
+             int(bool(jac_dq)), int(gmres_maxl))
     return o, atol_arr
 
 
@@ -195,6 +201,21 @@ def jacobian_dq(mech, y, ewt, h, T=1.0, kscale=None, F=None):
     return J
 
 
+def gmres_solve(mech, y, ewt, gamma, b, maxl=5, delta=0.0, T=1.0, kscale=None, F=None):
+    """One matrix-free GMRES solve of (I - gamma J(y)) x = b on the system
+    scaled by ewt.  Returns (x, code, iterations, residual norm of the scaled
+    system); code 0 converged to delta, 1 reduced, 2 not reduced."""
+    m = OracleMech(mech)
+    y, ewt, b = _f64(y), _f64(ewt), _f64(b)
+    x = np.zeros(y.size)
+    nli = C.c_int32(0)
+    rho = C.c_double(0.0)
+    code = lib().orc_gmres_solve(m.ptr, float(T), _p(_f64(kscale)), _p(_f64(F)), _p(y), _p(ewt),
+                                 float(gamma), int(maxl), float(delta), _p(b), _p(x),
+                                 C.byref(nli), C.byref(rho))
+    return x, int(code), int(nli.value), float(rho.value)
+
+
 def jac(mech, kf, kr, y):
     m = OracleMech(mech)
     kf, kr, y = _f64(kf), _f64(kr), _f64(y)
@@ -235,9 +256,11 @@ def bdf_coeffs(q, xi):
 
 
 def integrate(mechs, y0, t0, t_out, rtol, atol, T=None, kscale=None, F=None, cell_mech=None,
-              max_order=5, max_steps=5000, nthreads=0, jac_dq=False):
+              max_order=5, max_steps=5000, nthreads=0, jac_dq=False, gmres_maxl=0):
     """Integrate a batch of cells; returns (y, stats structured array).
-    jac_dq: Jacobian by difference quotients instead of the analytic one."""
+    jac_dq: Jacobian by difference quotients instead of the analytic one.
+    gmres_maxl > 0: inexact Newton with matrix-free GMRES of that Krylov
+    dimension (approaches 1A/1B) instead of the direct solve."""
     if isinstance(mechs, dict):
         mechs = [mechs]
     oms = [OracleMech(m) for m in mechs]
@@ -249,7 +272,7 @@ def integrate(mechs, y0, t0, t_out, rtol, atol, T=None, kscale=None, F=None, cel
     ldk = 0 if ks is None else ks.shape[1]
     F = _f64(F)
     cm = None if cell_mech is None else np.ascontiguousarray(cell_mech, dtype=np.int32)
-    o, atol_arr = _opts(rtol, atol, max_order, max_steps, jac_dq)
+    o, atol_arr = _opts(rtol, atol, max_order, max_steps, jac_dq, gmres_maxl)
     stats = np.zeros(N, dtype=STATS_DTYPE)
     lib().orc_integrate_batch(N, C.cast(arr, C.c_void_p), _p(cm), C.byref(o), _p(T), _p(ks),
                               ldk, _p(F), ldy, float(t0), float(t_out), _p(y), _p(stats),
