@@ -399,6 +399,65 @@ def run_dq(tuning_cache=None, n_check=128):
     return out
 
 
+def run_gmres(tuning_cache=None, n_check=128, t_out=1e-8, steps=3, warmup=1):
+    """Inexact Newton with matrix-free GMRES (Table 1, approaches 1A/1B)
+    against the direct solve (2A, FP64 and FP32 Newton matrix) on 262,144
+    cells of the 21-species mechanism over an outer step of PeleC size
+    (t_out = 1e-8 s), all on the autotuned work queue: time per outer step,
+    work per cell, and the first n_check cells against an rtol = 1e-12 oracle
+    reference (the forms differ in accuracy as well as speed) and against the
+    oracle run with the same linear solver."""
+    from paper_2405_01713_amd import bdfx
+
+    w = dict(W.make_workload("s21_r84_262k"), t_out=t_out)
+    out = dict(workload="s21_r84_262k", n_cells=w["n_cells"], t_out=t_out)
+    forms = (("direct_fp64", dict(lu_precision=64)), ("direct_fp32", dict(lu_precision=32)),
+             ("gmres5", dict(gmres_maxl=5)), ("gmres10", dict(gmres_maxl=10)))
+    ys = {}
+    for name, o in forms:
+        integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"], scheduler=1,
+                                **o)
+        tuning = integ.autotune(0.0, t_out, cache=tuning_cache)
+        y0 = integ.y.clone()
+
+        def step():
+            integ.y.copy_(y0)
+            integ.integrate(0.0, t_out)
+
+        ms = _timed_events(step, integ.stream, steps, warmup)
+        st = integ.cell_stats()
+        ys[name] = integ.state()[:n_check]
+        integ.close()
+        log(f"gmres leg {name}: {ms:.2f} ms")
+        out[name] = dict(kernel_ms=ms, cells_per_s=w["n_cells"] / (ms * 1e-3),
+                         mean_nst=float(st["nst"].mean()), mean_nfe=float(st["nfe"].mean()),
+                         mean_nni=float(st["nni"].mean()), mean_nli=float(st["nli"].mean()),
+                         mean_ncfl=float(st["ncfl"].mean()),
+                         mean_nsetups=float(st["nsetups"].mean()),
+                         failed_cells=int(np.sum(st["status"] != 0)), tuning=tuning)
+    for name in ("gmres5", "gmres10"):
+        out[f"{name}_over_direct_fp64"] = out[name]["kernel_ms"] / out["direct_fp64"]["kernel_ms"]
+    try:
+        from oracle import oracle as O
+        sub = lambda a: a[:n_check]
+        yr, _ = O.integrate(w["mechs"], sub(w["y0"]), 0.0, t_out, 1e-12, 1e-20, T=sub(w["T"]),
+                            max_steps=500000)
+        unit = w["rtol"] * np.abs(yr) + w["atol"]
+        for name, o in forms:
+            e = np.abs(ys[name] - yr) / unit
+            out[name]["vs_tight_reference"] = dict(
+                median_units=float(np.median(e)), p99_units=float(np.percentile(e, 99)),
+                max_units=float(e.max()))
+            if "gmres_maxl" in o:
+                yo, _ = O.integrate(w["mechs"], sub(w["y0"]), 0.0, t_out, w["rtol"], w["atol"],
+                                    T=sub(w["T"]), gmres_maxl=o["gmres_maxl"])
+                out[name]["vs_oracle"] = _errors(ys[name], yo, w["rtol"], w["atol"])
+        out["check_cells"] = n_check
+    except Exception as e:  # the oracle is optional on the timing path
+        out["check_error"] = repr(e)
+    return out
+
+
 def run_typical(tuning_cache=None, reps=50, eta=1e-10):
     """Typical-value absolute tolerances (Sec. 4.1.3): the device min/max pass
     over the states (HBM-bound; bytes = cells x species x 8 read) timed with
@@ -551,7 +610,8 @@ def main():
                          "53-species mechanism, FP64 and FP32 Newton matrix), 'typical' "
                          "(typical-value tolerances: reduction bandwidth and integration), "
                          "'thermal' (262,144 non-isothermal 21-species cells), 'dq' "
-                         "(difference-quotient vs analytic Jacobian)")
+                         "(difference-quotient vs analytic Jacobian), 'gmres' (matrix-free "
+                         "GMRES vs the direct solve over a 1e-8 s outer step)")
     ap.add_argument("--tuning-cache", default=None,
                     help="JSON file of autotuned launch shapes (reused when present)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
@@ -639,6 +699,8 @@ def main():
         extra["thermal"] = run_thermal(tuning_cache=args.tuning_cache)
     if "dq" in args.extra.split(","):
         extra["dq"] = run_dq(tuning_cache=args.tuning_cache)
+    if "gmres" in args.extra.split(","):
+        extra["gmres"] = run_gmres(tuning_cache=args.tuning_cache)
     ok = {k: v for k, v in forms.items() if v.get("parity_ok", True) and v["failed_cells"] == 0}
     best = max(ok or forms, key=lambda k: forms[k]["cells_per_s"])
     b = forms[best]

@@ -10,7 +10,9 @@
  * of Sec. 2, Eq. (3) with tolerances rtol and atol_i; modified Newton with the
  * stopping test of Sec. 2, Eq. (4); Newton matrix I - gamma J from the analytic
  * Jacobian, factored by dense LU with partial pivoting (Table 1, approaches
- * 2A/2B; Sec. 4.1.4).
+ * 2A/2B; Sec. 4.1.4).  Options: the Jacobian by difference quotients
+ * (approaches 3A/3B), or an inexact Newton iteration with matrix-free GMRES
+ * (approaches 1A/1B; Sec. 2, Eqs. (linear) and (stop_linear)).
  *
  * Conventions
  *  - All d_* arguments are device pointers owned by the caller.  The library
@@ -42,6 +44,7 @@ extern "C" {
 #define BDFX_MAX_ORDER 5
 #define BDFX_SLOTS 3
 #define BDFX_MAX_MECH 8
+#define BDFX_GMRES_MAXL 10 /* largest Krylov dimension of bdfx_options.gmres_maxl */
 
 /* call status */
 #define BDFX_OK 0
@@ -116,6 +119,20 @@ typedef struct {
   int32_t jacobian;        /* BDFX_JAC_ANALYTIC (0) or BDFX_JAC_DQ (1): Newton matrix from
                               forward difference quotients, one right-hand side per state
                               entry (Table 1, approaches 3A/3B) */
+  int32_t gmres_maxl;      /* 0: modified Newton with the direct solve (above).
+                              1..BDFX_GMRES_MAXL: inexact Newton (Table 1, approaches 1A/1B):
+                              each Newton system (I - gamma J(y_m)) x = b at the current
+                              iterate is solved by GMRES with at most this many Krylov
+                              vectors, on the system scaled by the error weights (Sec. 2,
+                              Eq. (linear), S1 = S2 = diag(w), no preconditioner), with
+                              J v = (f(y_m + sigma v) - f(y_m)) / sigma, sigma = 1/||v||_wrms,
+                              and the stopping test of Eq. (stop_linear), c_l = 0.05, on the
+                              residual norm from the Givens rotations.  No matrix is formed:
+                              jacobian must be BDFX_JAC_ANALYTIC, lu_precision and
+                              cells_per_wave = 2 do not apply, record_steps must be 0.  A
+                              solve that misses its tolerance after the first Newton
+                              iteration (or does not reduce the residual at all) is a
+                              convergence failure. */
 } bdfx_options;
 
 #define BDFX_JAC_ANALYTIC 0
@@ -131,6 +148,8 @@ typedef struct {
   int32_t netf;    /* error-test failures */
   int32_t ncfn;    /* Newton convergence failures */
   int32_t q_last;  /* order at the end */
+  int32_t nli;     /* GMRES iterations (each one right-hand side, counted in nfe too) */
+  int32_t ncfl;    /* GMRES solves that did not reach their tolerance */
   double h_last;   /* step size at the end */
   double t_reached;/* t_out on success, else time of the last accepted step */
 } bdfx_cell_stats;
@@ -143,6 +162,7 @@ typedef struct {
   int64_t nst, nfe, nni, nsetups, netf, ncfn; /* totals over cells */
   int64_t max_nst;
   int64_t status_count[11]; /* count of cells with status == -k, k = 0..10 */
+  int64_t nli, ncfl;        /* totals over cells */
 } bdfx_summary;
 
 /* Create a context on HIP device `device` enqueueing on `hip_stream`

@@ -21,6 +21,7 @@ BDFX_OK = 0
 BDFX_SCHED_STATIC = 0
 BDFX_SCHED_QUEUE = 1
 BDFX_JAC_ANALYTIC, BDFX_JAC_DQ = 0, 1
+BDFX_GMRES_MAXL = 10
 MAX_SPECIES = 64
 
 CELL_STATUS = {0: "success", -1: "too_much_work", -3: "err_failure", -4: "conv_failure",
@@ -47,14 +48,15 @@ class Options(C.Structure):
                 ("record_steps", C.c_int32), ("waves_per_block", C.c_int32),
                 ("blocks_per_cu", C.c_int32), ("queue_chunk", C.c_int32),
                 ("waves_per_simd", C.c_int32), ("cells_per_wave", C.c_int32),
-                ("jacobian", C.c_int32)]
+                ("jacobian", C.c_int32), ("gmres_maxl", C.c_int32)]
 
 
 class Summary(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_success", C.c_int64), ("n_failed", C.c_int64),
                 ("nst", C.c_int64), ("nfe", C.c_int64), ("nni", C.c_int64),
                 ("nsetups", C.c_int64), ("netf", C.c_int64), ("ncfn", C.c_int64),
-                ("max_nst", C.c_int64), ("status_count", C.c_int64 * 11)]
+                ("max_nst", C.c_int64), ("status_count", C.c_int64 * 11),
+                ("nli", C.c_int64), ("ncfl", C.c_int64)]
 
 
 class Tuning(C.Structure):
@@ -67,7 +69,9 @@ class Tuning(C.Structure):
 STATS_DTYPE = np.dtype([("status", np.int32), ("nst", np.int32), ("nfe", np.int32),
                         ("nni", np.int32), ("nsetups", np.int32), ("netf", np.int32),
                         ("ncfn", np.int32), ("q_last", np.int32),
+                        ("nli", np.int32), ("ncfl", np.int32),
                         ("h_last", np.float64), ("t_reached", np.float64)])
+assert STATS_DTYPE.itemsize == 56
 
 _lib = None
 
@@ -176,12 +180,12 @@ def bdfx_mech_destroy(mech):
 def make_options(rtol, atol, max_order=5, max_steps=5000, lu_precision=64,
                  scheduler=BDFX_SCHED_STATIC, record_steps=0, waves_per_block=0,
                  blocks_per_cu=0, queue_chunk=0, waves_per_simd=0, cells_per_wave=0,
-                 jacobian=0):
+                 jacobian=0, gmres_maxl=0):
     atol_arr = np.ascontiguousarray(np.atleast_1d(np.asarray(atol, dtype=np.float64)))
     o = Options(float(rtol), atol_arr.ctypes.data_as(C.c_void_p), int(atol_arr.size),
                 int(max_order), int(max_steps), int(lu_precision), int(scheduler),
                 int(record_steps), int(waves_per_block), int(blocks_per_cu), int(queue_chunk),
-                int(waves_per_simd), int(cells_per_wave), int(jacobian))
+                int(waves_per_simd), int(cells_per_wave), int(jacobian), int(gmres_maxl))
     o._keep = atol_arr
     return o
 
@@ -335,8 +339,8 @@ class Integrator:
     def autotune(self, t0, t_out, sample_cells=0, cache=None):
         """Pick the launch shape per mechanism with bdfx_autotune().  With
         ``cache`` (a JSON file path, one per machine) results are looked up by
-        compute-unit count, mechanism size, LU precision and scheduler, and
-        stored after tuning."""
+        compute-unit count, mechanism size, LU precision, scheduler and
+        linear solver, and stored after tuning."""
         import json
 
         # the cache file belongs to one machine; the key tells apart batch
@@ -344,7 +348,9 @@ class Integrator:
         n_cu = self.torch.cuda.get_device_properties(self.dev).multi_processor_count
         key = lambda m: (f"CU{n_cu}|S{self.mechs[m]['n_species']}|R{self.mechs[m]['n_reactions']}"
                          f"{'|thermal' if self.mechs[m].get('cv') is not None else ''}"
-                         f"|lu{self.opts.lu_precision}|sched{self.opts.scheduler}")
+                         f"|lu{self.opts.lu_precision}|sched{self.opts.scheduler}"
+                         f"{'|dq' if self.opts.jacobian else ''}"
+                         f"{f'|gmres{self.opts.gmres_maxl}' if self.opts.gmres_maxl else ''}")
         db = {}
         if cache and os.path.exists(cache):
             with open(cache) as fh:

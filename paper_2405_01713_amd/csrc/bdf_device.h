@@ -50,9 +50,16 @@ constexpr int kNonfinite = -9;
 constexpr int kRecordFull = -10;
 
 struct CellStats {
-  int32_t status, nst, nfe, nni, nsetups, netf, ncfn, q_last;
+  int32_t status, nst, nfe, nni, nsetups, netf, ncfn, q_last, nli, ncfl;
   double h_last, t_reached;
 };
+
+// Linear solver of the Newton iteration: modified Newton with a direct solve
+// of the Newton matrix from the analytic Jacobian (Table 1, approaches 2A/2B)
+// or from difference quotients (3A/3B), or inexact Newton with matrix-free
+// GMRES (1A/1B).
+enum : int { kLinAnalytic = 0, kLinDq = 1, kLinGmres = 2 };
+constexpr int kGmresMaxl = 10;
 
 // Device-resident mechanism tables (built on the host from the
 // stoichiometry; see the host runtime for the encodings).
@@ -85,6 +92,7 @@ struct Params {
   double t0, tout, rtol;
   int32_t atol_len, max_order, max_steps;
   int32_t n_sp;           // species of the mechanism (<= template S)
+  int32_t gmres_maxl;     // Krylov vectors per GMRES solve (GMRES kernels only)
   int32_t lds_doubles;    // LDS per wave
   int32_t use_queue;      // 0: one cell per wave from the grid index; 1: work queue
   uint32_t *queue;
@@ -495,6 +503,7 @@ struct Lds {
   double *kk;   // [2R]: k_f at 2r, -k_r at 2r+1 (LDS, or the wave's slot in global memory)
   const int2 *rx;  // [R]: reactant / product slot words (an LDS copy, or the mechanism's table)
   void *fac;    // [S][S] inverse Newton matrix (LT), column-major: (r, c) at c*S + r
+  double *kry;  // GMRES kernels, in place of fac: Krylov basis and Hessenberg data (KryLayout)
   double *uT;   // non-isothermal: [64 + 8] u_i(T) at the setup state (uT[kEmptySlot] = 0)
   double *uj;   // non-isothermal: [64 + 8] sum_r dU_r dq_r/dx_c per column c (Jacobian T row)
 };
@@ -510,16 +519,30 @@ enum : int {
   kTabGlobal = 2,    // both in global memory (persistent waves only)
 };
 
+// GMRES area of a wave's LDS (doubles) for S state entries and at most maxl
+// Krylov vectors: the basis of the scaled space ([maxl + 1][S]), the
+// Hessenberg matrix (column-major, maxl + 1 rows; rotated in place), the
+// rotations, the rotated right-hand side and the solution coefficients.
+struct KryLayout {
+  int V, H, cs, sn, g, c, size;
+  __host__ __device__ constexpr KryLayout(int S, int maxl)
+      : V(0), H((maxl + 1) * S), cs(H + (maxl + 1) * maxl), sn(cs + maxl), g(sn + maxl),
+        c(g + maxl + 1), size(c + maxl) {}
+};
+
 // doubles of LDS per wave for S state entries, R reactions, factor type
-// size, table placement and non-isothermal cells
+// size, table placement and non-isothermal cells; gmres_maxl > 0: GMRES
+// kernels, whose Krylov area replaces the Newton matrix and the
+// non-isothermal Jacobian rows
 __host__ __device__ constexpr int lds_doubles(int S, int R, int lt_bytes, int tab = kTabLds,
-                                              bool thermal = false) {
+                                              bool thermal = false, int gmres_maxl = 0) {
   return 2 * kWave + 8 + Ctl::kSize + kWave / 2 + (tab == kTabLds ? R : 0) +
-         (tab == kTabGlobal ? 0 : 2 * R) + (S * S * lt_bytes + 7) / 8 +
-         (thermal ? 2 * (kWave + 8) : 0);
+         (tab == kTabGlobal ? 0 : 2 * R) +
+         (gmres_maxl > 0 ? KryLayout(S, gmres_maxl).size
+                         : (S * S * lt_bytes + 7) / 8 + (thermal ? 2 * (kWave + 8) : 0));
 }
 
-template <int TAB, bool TH = false>
+template <int TAB, bool TH = false, bool KRY = false>
 __device__ __forceinline__ Lds carve(double *base, int R, const int32_t *mech_rx, double *kk_slot,
                                      int S = 0, int lt_bytes = 8) {
   Lds L;
@@ -541,7 +564,11 @@ __device__ __forceinline__ Lds carve(double *base, int R, const int32_t *mech_rx
     L.rx = reinterpret_cast<const int2 *>(mech_rx);
   }
   L.fac = next;
-  if constexpr (TH) {
+  L.kry = next;
+  if constexpr (KRY) {
+    L.fac = nullptr;
+    L.uT = L.uj = nullptr;
+  } else if constexpr (TH) {
     L.uT = next + (S * S * lt_bytes + 7) / 8;
     L.uj = L.uT + kWave + 8;
   } else {
@@ -1005,13 +1032,113 @@ __device__ __forceinline__ double wrms2(const Grp<G> &W, double v, double w, dou
   return W.uni(W.template sum<(S + 15) / 16>(t * t) * inv_n);
 }
 
-template <int S, typename LT, int TAB, int G, bool ABC, bool TH, bool DQ>
+// Linear solve of the inexact Newton iteration (Table 1, approaches 1A/1B):
+// GMRES on the system scaled by the error weights (Sec. 2, Eq. (linear),
+// S1 = S2 = diag(w), no preconditioner) for (I - gamma J(y)) x = b, with J v
+// the difference quotient (f(y + sigma v) - f(y)) / sigma, sigma =
+// 1 / ||v||_wrms, and fy = f(y).  Initial guess 0; modified Gram-Schmidt
+// Arnoldi; Givens rotations reduce the Hessenberg matrix to triangular form
+// and give the residual norm of the scaled system as the magnitude of the
+// last rotated right-hand-side entry (Sec. 2, after Eq. (stop_linear)).
+// Stops at maxl basis vectors or when that norm is at most delta (the
+// 2-norm of Eq. (stop_linear)).  Lane i holds entry i of y, fy, w and b (w = 0
+// past the state); the basis and the Hessenberg data live in the wave's LDS
+// (KryLayout), so the loop is not unrolled and the right-hand side is
+// inlined once.  Returns 0 when converged, 1 when the residual was reduced
+// but not to delta, 2 otherwise; x receives the lane's solution entry and
+// nli the iterations (one right-hand side each).
+template <int S, bool ABC, bool TH, int G>
+__device__ int gmres(const MechDev &m, const Lds &L, const Grp<G> &W, double y, double fy,
+                     double Fi, double ewt, double gamma, double b, int maxl, double delta,
+                     int ns, int n, double inv_n, double &x, int &nli) {
+  constexpr int NR = (S + 15) / 16;
+  const KryLayout K(S, maxl);
+  double *const kb = L.kry;
+  const int ld = maxl + 1;  // Hessenberg column stride
+  const bool own = W.lane < n;
+  const int li = own ? W.lane : 0;
+  const double r0 = own ? ewt * b : 0.0;  // b~ = S1 b, the residual of x = 0
+  const double beta = W.uni(sqrt(W.template sum<NR>(r0 * r0)));
+  x = 0.0;
+  if (beta <= delta) return 0;
+  wave_lds_sync();
+  if (own) kb[K.V + li] = r0 / beta;
+  double gl = beta;  // last entry of the rotated right-hand side
+  double rho = beta;
+  int k = 0;
+  for (int l = 0; l < maxl; ++l) {
+    wave_lds_sync();
+    // w = A~ V_l = S1 (v - gamma J v) with v = S2^{-1} V_l
+    const double vl = own ? kb[K.V + l * S + li] : 0.0;
+    const double v = own ? vl / ewt : 0.0;
+    const double sigma = W.uni(1.0 / sqrt(wrms2<S>(W, v, ewt, inv_n)));
+    const double fp = rhs<ABC, TH>(m, L, W, y + sigma * v, Fi, ns);
+    nli++;
+    double w = own ? ewt * (v - gamma * ((fp - fy) / sigma)) : 0.0;
+    // modified Gram-Schmidt: column l of the Hessenberg matrix
+    for (int j = 0; j <= l; ++j) {
+      const double vj = own ? kb[K.V + j * S + li] : 0.0;
+      const double d = W.uni(W.template sum<NR>(w * vj));
+      if (W.lane == 0) kb[K.H + l * ld + j] = d;
+      w -= d * vj;
+    }
+    const double hn = W.uni(sqrt(W.template sum<NR>(w * w)));
+    wave_lds_sync();
+    // the earlier rotations, then the one that zeroes the subdiagonal entry
+    double a = kb[K.H + l * ld];
+    for (int j = 0; j < l; ++j) {
+      const double c = kb[K.cs + j], sn = kb[K.sn + j], a1 = kb[K.H + l * ld + j + 1];
+      const double top = c * a + sn * a1;
+      a = -sn * a + c * a1;
+      wave_lds_sync();
+      if (W.lane == 0) kb[K.H + l * ld + j] = top;
+      wave_lds_sync();
+    }
+    const double r = W.uni(hypot(a, hn));
+    if (!(r > 0.0)) break;  // singular Hessenberg column: keep k columns
+    const double c = W.uni(a / r), sn = W.uni(hn / r);
+    wave_lds_sync();
+    if (W.lane == 0) {
+      kb[K.H + l * ld + l] = r;
+      kb[K.cs + l] = c;
+      kb[K.sn + l] = sn;
+      kb[K.g + l] = c * gl;
+    }
+    gl = W.uni(-sn * gl);
+    rho = fabs(gl);
+    k = l + 1;
+    if (rho <= delta) break;
+    if (l + 1 < maxl) {
+      if (!(hn > 0.0)) break;
+      if (own) kb[K.V + (l + 1) * S + li] = w / hn;
+    }
+  }
+  // back substitution for the coefficients, then x = S2^{-1} sum_j c_j V_j
+  wave_lds_sync();
+  for (int i = k - 1; i >= 0; --i) {
+    double t = kb[K.g + i];
+    for (int j = i + 1; j < k; ++j) t -= kb[K.H + j * ld + i] * kb[K.c + j];
+    const double ci = W.uni(t / kb[K.H + i * ld + i]);
+    wave_lds_sync();
+    if (W.lane == 0) kb[K.c + i] = ci;
+    wave_lds_sync();
+  }
+  double t = 0.0;
+  for (int j = 0; j < k; ++j) t += kb[K.c + j] * (own ? kb[K.V + j * S + li] : 0.0);
+  x = own ? t / ewt : 0.0;
+  wave_lds_sync();
+  if (rho <= delta) return 0;
+  return rho < beta ? 1 : 2;
+}
+
+template <int S, typename LT, int TAB, int G, bool ABC, bool TH, int LIN>
 __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, const Grp<G> &W,
                                                double *lds, double *kk_slot) {
+  constexpr bool KRY = LIN == kLinGmres;
   const MechDev &m = P.mech;
   const int R = m.R;
   const int ns = m.S;  // species; a non-isothermal state also holds T at entry ns
-  const Lds L = carve<TAB, TH>(lds, R, m.rx, kk_slot, S, static_cast<int>(sizeof(LT)));
+  const Lds L = carve<TAB, TH, KRY>(lds, R, m.rx, kk_slot, S, static_cast<int>(sizeof(LT)));
   if (W.lane == 0) L.yb[kEmptySlot] = 1.0;  // empty reaction slots multiply by 1
   double *const C = L.C;
   const int n = P.n_sp;
@@ -1048,7 +1175,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
   if (P.rec && own) P.rec_y0[cell * P.rec_stride + W.lane] = yin;
 
   int status = kSuccess;
-  int nst = 0, nfe = 0, nni = 0, nsetups = 0, netf = 0, ncfn = 0;
+  int nst = 0, nfe = 0, nni = 0, nsetups = 0, netf = 0, ncfn = 0, nli = 0, ncfl = 0;
   int q = 1;
   double t = t0, h = 0.0;
   double z[kQmax + 1];
@@ -1173,43 +1300,50 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       double gamma_bar = W.uni(C[Ctl::kGammaBar]);
       bool fresh = false;
       // (gamma_bar = 0 before the first setup, which need_setup forces)
-      if (need_setup || nst >= nst_setup + 20 || fabs(gamma * rcp(gamma_bar) - 1.0) > 0.3) {
-        int info;
-        {
-          LT a[S];
-          if constexpr (DQ) {
-            dq_matrix<S, LT, ABC, TH>(a, m, L, W, z[0], Fi, gamma, h, ewt, ns, n, inv_n);
-            nfe += n + 1;
-          } else if constexpr (TH) {
-            newton_matrix_thermal<S, LT>(a, m, L, W, z[0], Fi, gamma, ns);
-          } else {
-            newton_matrix<S, LT, ABC>(a, m, L, W, z[0], gamma, false);
+      // (GMRES kernels form no matrix and take no setups)
+      if constexpr (!KRY) {
+        if (need_setup || nst >= nst_setup + 20 || fabs(gamma * rcp(gamma_bar) - 1.0) > 0.3) {
+          int info;
+          {
+            LT a[S];
+            if constexpr (LIN == kLinDq) {
+              dq_matrix<S, LT, ABC, TH>(a, m, L, W, z[0], Fi, gamma, h, ewt, ns, n, inv_n);
+              nfe += n + 1;
+            } else if constexpr (TH) {
+              newton_matrix_thermal<S, LT>(a, m, L, W, z[0], Fi, gamma, ns);
+            } else {
+              newton_matrix<S, LT, ABC>(a, m, L, W, z[0], gamma, false);
+            }
+            info = gj_invert<S, LT>(a, W, L);
           }
-          info = gj_invert<S, LT>(a, W, L);
-        }
-        nsetups++;
-        nst_setup = nst;
-        gamma_bar = gamma;
-        C[Ctl::kGammaBar] = gamma;
-        R2 = 1.0;
-        need_setup = false;
-        fresh = true;
-        if (info != 0) {
-          // singular Newton matrix: recoverable once per step by cutting h
-          nd_unpredict(z);
-          need_setup = true;
-          if (++nsf_step >= 2) {
-            status = kSetupFailure;
-            break;
+          nsetups++;
+          nst_setup = nst;
+          gamma_bar = gamma;
+          C[Ctl::kGammaBar] = gamma;
+          R2 = 1.0;
+          need_setup = false;
+          fresh = true;
+          if (info != 0) {
+            // singular Newton matrix: recoverable once per step by cutting h
+            nd_unpredict(z);
+            need_setup = true;
+            if (++nsf_step >= 2) {
+              status = kSetupFailure;
+              break;
+            }
+            nd_rescale(z, 0.25);
+            h = W.uni(h * 0.25);
+            C[Ctl::kEtaMax] = 1.0;
+            continue;
           }
-          nd_rescale(z, 0.25);
-          h = W.uni(h * 0.25);
-          C[Ctl::kEtaMax] = 1.0;
-          continue;
         }
       }
       const double cfac =
-          W.uni(gamma != gamma_bar ? 2.0 * rcp(1.0 + gamma * rcp(gamma_bar)) : 1.0);
+          KRY ? 1.0 : W.uni(gamma != gamma_bar ? 2.0 * rcp(1.0 + gamma * rcp(gamma_bar)) : 1.0);
+      // GMRES tolerance, Eq. (stop_linear): c_l = 0.05 times the Newton
+      // tolerance c_eps eps = 0.1 / Cerr, in the scaled 2-norm (sqrt(n) times
+      // the WRMS norm)
+      const double ltol = KRY ? W.uni(0.005 * rcp(Cerr) * sqrt(static_cast<double>(n))) : 0.0;
 
       // Newton iteration on G(e) = e - gamma f(z_0 + e) + z_1 / l_1, Eq. (4)
       bool conv = false;
@@ -1222,8 +1356,21 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
         nfe++;
         nni++;
         const double Gi = e - gamma * f + z[1] * rl1;
-        double delta = inv_solve<S, LT>(L, W, -Gi);
-        if (cfac != 1.0) delta *= cfac;
+        double delta;
+        if constexpr (KRY) {
+          // inexact Newton: J at the current iterate; a reduced but
+          // unconverged residual is accepted on the first iteration only
+          int nl = 0;
+          const int lret = gmres<S, ABC, TH>(m, L, W, z[0] + e, f, Fi, ewt, gamma, -Gi,
+                                             P.gmres_maxl, ltol, ns, n, inv_n, delta, nl);
+          nli += nl;
+          nfe += nl;
+          if (lret != 0) ncfl++;
+          if (lret == 2 || (lret == 1 && mit > 0)) break;
+        } else {
+          delta = inv_solve<S, LT>(L, W, -Gi);
+          if (cfac != 1.0) delta *= cfac;
+        }
         e += delta;
         const double d2 = wrms2<S>(W, delta, ewt, inv_n);
         if (!isfinite(d2)) break;
@@ -1245,7 +1392,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
           status = kConvFailure;
           break;
         }
-        if (fresh) {
+        if (fresh || KRY) {
           nd_rescale(z, 0.25);
           h = W.uni(h * 0.25);
           C[Ctl::kEtaMax] = 1.0;
@@ -1406,6 +1553,8 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       st.netf = netf;
       st.ncfn = ncfn;
       st.q_last = q;
+      st.nli = nli;
+      st.ncfl = ncfl;
       st.h_last = h;
       st.t_reached = t;
       P.stats[cell] = st;

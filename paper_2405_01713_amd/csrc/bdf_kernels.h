@@ -19,9 +19,10 @@ namespace bdfx {
 // in global memory, wave w of the grid owns rate-constant slot w (the host
 // guarantees that the grid's waves fit the slot array).  ABC: every reaction
 // is A + B <=> C (see rhs_reaction).  TH: non-isothermal cells (temperature
-// as the last state entry, rates re-evaluated from it).  DQ: Newton matrix
-// from difference quotients instead of the analytic Jacobian.
-template <int S, typename LT, int MINW, int TAB, int G, bool ABC, bool TH, bool DQ = false>
+// as the last state entry, rates re-evaluated from it).  LIN: linear solver
+// of the Newton iteration (kLin*: Newton matrix from the analytic Jacobian or
+// from difference quotients, or matrix-free GMRES; LT is unused by GMRES).
+template <int S, typename LT, int MINW, int TAB, int G, bool ABC, bool TH, int LIN = kLinAnalytic>
 __global__ void __launch_bounds__(256, MINW) k_integrate(Params P) {
   extern __shared__ double smem[];
   const int wib = threadIdx.x / kWave;
@@ -47,7 +48,7 @@ __global__ void __launch_bounds__(256, MINW) k_integrate(Params P) {
     if (next >= P.n_list) break;
     const int64_t cell = P.list ? P.list[next] : next;
     ++next;
-    integrate_cell<S, LT, TAB, G, ABC, TH, DQ>(P, cell, W, lds, kk_slot);
+    integrate_cell<S, LT, TAB, G, ABC, TH, LIN>(P, cell, W, lds, kk_slot);
   }
 }
 
@@ -67,23 +68,29 @@ struct LaunchCfg {
 };
 
 // the three register budgets of one kernel configuration
-template <int S, typename LT, int TAB, int G, bool ABC, bool TH = false, bool DQ = false>
+template <int S, typename LT, int TAB, int G, bool ABC, bool TH = false, int LIN = kLinAnalytic>
 const void *by_budget(int w) {
   using F = const void *;
-  static const F t[3] = {F(&k_integrate<S, LT, 1, TAB, G, ABC, TH, DQ>),
-                         F(&k_integrate<S, LT, 3, TAB, G, ABC, TH, DQ>),
-                         F(&k_integrate<S, LT, 4, TAB, G, ABC, TH, DQ>)};
+  static const F t[3] = {F(&k_integrate<S, LT, 1, TAB, G, ABC, TH, LIN>),
+                         F(&k_integrate<S, LT, 3, TAB, G, ABC, TH, LIN>),
+                         F(&k_integrate<S, LT, 4, TAB, G, ABC, TH, LIN>)};
   return t[w];
 }
 
-// difference-quotient kernels: one cell per wave, tables in LDS
-template <int S, bool TH>
-const void *dq_kernel(bool fp32, int w, bool abc) {
-  if (abc)
-    return fp32 ? by_budget<S, float, kTabLds, 1, true, TH, true>(w)
-                : by_budget<S, double, kTabLds, 1, true, TH, true>(w);
-  return fp32 ? by_budget<S, float, kTabLds, 1, false, TH, true>(w)
-              : by_budget<S, double, kTabLds, 1, false, TH, true>(w);
+// difference-quotient and GMRES kernels: one cell per wave, tables in LDS;
+// GMRES forms no matrix, so it has only the FP64 instance
+template <int S, bool TH, int LIN>
+const void *lin_kernel(bool fp32, int w, bool abc) {
+  if constexpr (LIN == kLinGmres) {
+    return abc ? by_budget<S, double, kTabLds, 1, true, TH, LIN>(w)
+               : by_budget<S, double, kTabLds, 1, false, TH, LIN>(w);
+  } else {
+    if (abc)
+      return fp32 ? by_budget<S, float, kTabLds, 1, true, TH, LIN>(w)
+                  : by_budget<S, double, kTabLds, 1, true, TH, LIN>(w);
+    return fp32 ? by_budget<S, float, kTabLds, 1, false, TH, LIN>(w)
+                : by_budget<S, double, kTabLds, 1, false, TH, LIN>(w);
+  }
 }
 
 template <int S, bool ABC>
@@ -113,18 +120,24 @@ const void *integrate_kernel_abc(bool fp32, int w, int tab, int cells_per_wave) 
 }
 
 // the integrator kernel for (LU precision, register budget, table placement,
-// cells per wave, A + B <=> C mechanism, non-isothermal, difference-quotient
-// Jacobian); nullptr where no such variant is built (two cells per wave only
-// with the tables in LDS; tables in global memory only for sizes whose LDS
-// can limit the resident waves; non-isothermal cells and difference
-// quotients one cell per wave with the tables in LDS)
+// cells per wave, A + B <=> C mechanism, non-isothermal, linear solver);
+// nullptr where no such variant is built (two cells per wave only with the
+// tables in LDS; tables in global memory only for sizes whose LDS can limit
+// the resident waves; non-isothermal cells, difference quotients and GMRES
+// one cell per wave with the tables in LDS)
 template <int S>
 const void *integrate_kernel(bool fp32, int minw, int tab, int cells_per_wave, bool abc,
-                             bool thermal, bool dq) {
+                             bool thermal, int lin) {
   const int w = minw >= 4 ? 2 : minw >= 3 ? 1 : 0;
-  if (dq) {
+  if (lin != kLinAnalytic) {
     if (tab != kTabLds || cells_per_wave != 1) return nullptr;
-    return thermal ? dq_kernel<S, true>(fp32, w, abc) : dq_kernel<S, false>(fp32, w, abc);
+    if (lin == kLinDq)
+      return thermal ? lin_kernel<S, true, kLinDq>(fp32, w, abc)
+                     : lin_kernel<S, false, kLinDq>(fp32, w, abc);
+    if (lin == kLinGmres)
+      return thermal ? lin_kernel<S, true, kLinGmres>(fp32, w, abc)
+                     : lin_kernel<S, false, kLinGmres>(fp32, w, abc);
+    return nullptr;
   }
   if (thermal) {
     if (tab != kTabLds || cells_per_wave != 1) return nullptr;
@@ -140,8 +153,8 @@ const void *integrate_kernel(bool fp32, int minw, int tab, int cells_per_wave, b
 
 template <int S>
 hipError_t launch_integrate(const Params &P, bool fp32, int minw, int tab, int cells_per_wave,
-                            bool abc, bool thermal, bool dq, const LaunchCfg &c, hipStream_t s) {
-  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc, thermal, dq);
+                            bool abc, bool thermal, int lin, const LaunchCfg &c, hipStream_t s) {
+  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc, thermal, lin);
   if (!f) return hipErrorInvalidDeviceFunction;
   Params arg = P;
   void *args[] = {&arg};
@@ -156,9 +169,9 @@ hipError_t launch_adjoint(const Params &P, const LaunchCfg &c, hipStream_t s) {
 
 template <int S>
 hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave, bool abc,
-                               bool thermal, bool dq, int block, size_t lds_bytes,
+                               bool thermal, int lin, int block, size_t lds_bytes,
                                int *blocks_per_cu) {
-  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc, thermal, dq);
+  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc, thermal, lin);
   if (!f) {
     *blocks_per_cu = 0;
     return hipSuccess;
@@ -170,17 +183,19 @@ hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave,
 
 // One translation unit per species size (compiled in parallel).  The
 // kernel flags are passed packed: bit 0 A + B <=> C, bit 1 non-isothermal,
-// bit 2 difference-quotient Jacobian.
+// bit 2 difference-quotient Jacobian, bit 3 GMRES.
+#define BDFX_LIN_OF_FLAGS(f) \
+  ((f) & 8 ? bdfx::kLinGmres : (f) & 4 ? bdfx::kLinDq : bdfx::kLinAnalytic)
 #define BDFX_DEFINE_SIZE(S)                                                                      \
   hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, int tab, int cpw,      \
                               int flags, const bdfx::LaunchCfg &c, hipStream_t s) {              \
-    return bdfx::launch_integrate<S>(P, fp32, minw, tab, cpw, flags & 1, flags & 2, flags & 4, c, \
-                                     s);                                                         \
+    return bdfx::launch_integrate<S>(P, fp32, minw, tab, cpw, flags & 1, flags & 2,              \
+                                     BDFX_LIN_OF_FLAGS(flags), c, s);                            \
   }                                                                                              \
   hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, int flags, int block,    \
                                  size_t lds, int *out) {                                         \
-    return bdfx::occupancy_integrate<S>(fp32, minw, tab, cpw, flags & 1, flags & 2, flags & 4,   \
-                                        block, lds, out);                                        \
+    return bdfx::occupancy_integrate<S>(fp32, minw, tab, cpw, flags & 1, flags & 2,              \
+                                        BDFX_LIN_OF_FLAGS(flags), block, lds, out);              \
   }                                                                                              \
   hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s) { \
     return bdfx::launch_adjoint<S>(P, c, s);                                                     \

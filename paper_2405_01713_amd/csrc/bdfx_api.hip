@@ -44,7 +44,7 @@ hipError_t bdfx_launch_typical(int n_mech, int ldt, const int32_t *S, const int3
                                double *typ, hipStream_t s);
 
 static_assert(sizeof(bdfx_cell_stats) == sizeof(bdfx::CellStats), "stats layout");
-static_assert(sizeof(bdfx_cell_stats) == 48, "stats size");
+static_assert(sizeof(bdfx_cell_stats) == 56, "stats size");
 
 namespace {
 
@@ -352,6 +352,13 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
   if (o->record_steps < 0) return fail(ctx, BDFX_EINVAL, "record_steps < 0");
   if (o->jacobian != BDFX_JAC_ANALYTIC && o->jacobian != BDFX_JAC_DQ)
     return fail(ctx, BDFX_EINVAL, "jacobian must be BDFX_JAC_ANALYTIC or BDFX_JAC_DQ");
+  if (o->gmres_maxl < 0 || o->gmres_maxl > BDFX_GMRES_MAXL)
+    return fail(ctx, BDFX_EINVAL, "gmres_maxl must be 0..%d", BDFX_GMRES_MAXL);
+  if (o->gmres_maxl > 0 && o->jacobian != BDFX_JAC_ANALYTIC)
+    return fail(ctx, BDFX_EINVAL, "jacobian selects the Newton matrix of the direct solver; "
+                                  "GMRES forms none (use BDFX_JAC_ANALYTIC)");
+  if (o->gmres_maxl > 0 && o->record_steps > 0)
+    return fail(ctx, BDFX_EUNSUPPORTED, "step recording (adjoint) needs the direct solver");
   int S_max = 0, R_max = 0;
   for (int m = 0; m < n_mech; ++m) {
     if (!mechs[m] || mechs[m]->ctx != ctx) return fail(ctx, BDFX_EINVAL, "bad mechanism %d", m);
@@ -423,7 +430,14 @@ static int configure_bins(bdfx_ctx ctx);
 
 // kernel selection flags of a mechanism under the context's options
 static int kernel_flags(bdfx_ctx ctx, bdfx_mech m) {
-  return (m->abc ? 1 : 0) | (m->thermal ? 2 : 0) | (ctx->opt.jacobian == BDFX_JAC_DQ ? 4 : 0);
+  return (m->abc ? 1 : 0) | (m->thermal ? 2 : 0) | (ctx->opt.jacobian == BDFX_JAC_DQ ? 4 : 0) |
+         (ctx->opt.gmres_maxl > 0 ? 8 : 0);
+}
+
+// whether a mechanism of this size can run two cells per wave under the
+// context's options (isothermal, analytic Jacobian, direct solver)
+static bool two_cells_per_wave_ok(bdfx_ctx ctx, bdfx_mech m, int S) {
+  return S <= 32 && !m->thermal && ctx->opt.jacobian != BDFX_JAC_DQ && ctx->opt.gmres_maxl == 0;
 }
 
 int bdfx_bind(bdfx_ctx ctx, void *d_ws, size_t ws_bytes, double *d_y, int32_t ldy,
@@ -496,8 +510,7 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
   b.se = size_for(m->n);
   if (!b.se) return fail(ctx, BDFX_EUNSUPPORTED, "no kernel for %d state entries", m->n);
   const int cpw = b.cells_per_wave;
-  if (cpw != 1 &&
-      !(cpw == 2 && b.se->S <= 32 && !m->thermal && ctx->opt.jacobian != BDFX_JAC_DQ))
+  if (cpw != 1 && !(cpw == 2 && two_cells_per_wave_ok(ctx, m, b.se->S)))
     return fail(ctx, BDFX_EUNSUPPORTED, "%d cells per wave with %d state entries%s", cpw, b.se->S,
                 m->thermal ? " (non-isothermal)" : "");
   const int waves = std::max(b.waves_per_block, 1);
@@ -513,7 +526,9 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
   int64_t grid[3] = {0, 0, 0};
   for (int k : {bdfx::kTabLds, bdfx::kTabRxGlobal, bdfx::kTabGlobal}) {
     const int32_t d = static_cast<int32_t>(
-        align_up(bdfx::lds_doubles(b.se->S, m->R, fp32 ? 4 : 8, k, m->thermal), 2));
+        align_up(bdfx::lds_doubles(b.se->S, m->R, fp32 ? 4 : 8, k, m->thermal,
+                                   ctx->opt.gmres_maxl),
+                 2));
     lds[k] = static_cast<size_t>(waves) * cpw * d * 8;
     if (lds[k] > 65536 || (k != bdfx::kTabLds && cpw != 1) || (k == bdfx::kTabGlobal && !queue))
       continue;
@@ -552,8 +567,7 @@ static int configure_bins(bdfx_ctx ctx) {
       // two cells per wave where the mechanism fits a half-wave
       const SizeEntry *se = size_for(ctx->mechs[b.mech]->n);
       b.cells_per_wave =
-          ctx->opt.cells_per_wave == 2 && se && se->S <= 32 && !ctx->mechs[b.mech]->thermal &&
-                  ctx->opt.jacobian != BDFX_JAC_DQ
+          ctx->opt.cells_per_wave == 2 && se && two_cells_per_wave_ok(ctx, ctx->mechs[b.mech], se->S)
               ? 2
               : 1;
     }
@@ -592,6 +606,7 @@ static bdfx::Params make_params(bdfx_ctx ctx, const Bin &b, double t0, double to
   P.max_order = ctx->opt.max_order;
   P.max_steps = ctx->opt.max_steps;
   P.n_sp = m->n;
+  P.gmres_maxl = ctx->opt.gmres_maxl;
   P.queue = reinterpret_cast<uint32_t *>(ctx->ws + ctx->off_queue) + b.mech;
   P.chunk = b.queue_chunk;
   P.kk_slots = ctx->kk_slots ? reinterpret_cast<double *>(ctx->ws + ctx->off_kk) : nullptr;
@@ -696,7 +711,7 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
       for (int wpb : wpb_c)
         for (int chunk : chunk_c) {
           if (!queue && chunk != 1) continue;
-          if (cpw == 2 && b.se->S > 32) continue;
+          if (cpw == 2 && !two_cells_per_wave_ok(ctx, m, b.se->S)) continue;
           trial.cells_per_wave = cpw;
           trial.waves_per_simd = wps;
           trial.waves_per_block = wpb;
@@ -843,6 +858,8 @@ int bdfx_stats_summary(bdfx_ctx ctx, bdfx_summary *out) {
     out->nsetups += s.nsetups;
     out->netf += s.netf;
     out->ncfn += s.ncfn;
+    out->nli += s.nli;
+    out->ncfl += s.ncfl;
     out->max_nst = std::max<int64_t>(out->max_nst, s.nst);
   }
   return BDFX_OK;

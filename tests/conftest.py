@@ -84,12 +84,16 @@ def assert_adjoint_parity(g, go, label=""):
     return rel
 
 
-def assert_parity_global(y, yo, w, oracle, label=""):
+def assert_parity_global(y, yo, w, oracle, label="", min_frac=0.88):
     """GPU vs oracle for workloads whose global error is far above the local
     tolerance (non-isothermal cells: the temperature feeds back into every
-    rate, so round-off alone moves solutions by up to ~300 error weights).
+    rate, so round-off alone moves solutions by up to ~300 error weights;
+    inexact Newton with a short Krylov space, whose unconverged linear solves
+    accepted on first Newton iterations amplify round-off the same way).
 
-    (a) >= 88 % of entries within 10 rtol |y_oracle| + atol of the oracle;
+    (a) >= min_frac of entries within 10 rtol |y_oracle| + atol of the oracle
+        (0.88 by default; 0.5 for GMRES with 5 Krylov vectors, where the
+        oracle perturbed by 1e-15 keeps 64-66 %);
     (b) measured against a reference run at rtol 1e-12 (atol 1e-10 of the
         tolerances), in units of the error weights rtol |y| + atol, the GPU's
         global errors are no worse than the oracle's own: median within 1.5
@@ -99,13 +103,14 @@ def assert_parity_global(y, yo, w, oracle, label=""):
     The oracle against itself with inputs perturbed by 1e-15 (512 cells of
     the 21-species non-isothermal workload, with and without forcing, ten
     perturbations each) stays inside: worst 90.5 % of entries; ratios up to
-    1.15, 1.58 and 4.4.  Returns statistics.
+    1.15, 1.58 and 4.4; the 21-species workload over 1e-8 s with 5 Krylov
+    vectors: ratios up to 0.93, 1.05 and 1.03.  Returns statistics.
     """
     import numpy as np
 
     rtol, atol = w["rtol"], np.asarray(w["atol"], dtype=np.float64)
     frac = float(np.mean(np.abs(y - yo) <= 10 * rtol * np.abs(yo) + atol))
-    assert frac >= 0.88, f"{label}: only {frac:.4f} of entries within 10 rtol |y| + atol"
+    assert frac >= min_frac, f"{label}: only {frac:.4f} of entries within 10 rtol |y| + atol"
     yr, st = oracle.integrate(w["mechs"], w["y0"], w.get("t0", 0.0), w["t_out"], 1e-12,
                               np.broadcast_to(atol * 1e-10, (y.shape[1],)).copy(),
                               T=w.get("T"), kscale=w.get("kscale"), F=w.get("F"),

@@ -178,3 +178,19 @@ def test_linear_convergence_failures_cut_the_step(oracle):
     assert np.all(st["status"] == 0)
     assert st["ncfn"].sum() > 0 and np.all(st["ncfl"] >= st["ncfn"])
     assert np.all(st["nsetups"] == 0)
+
+
+def test_global_parity_bar_is_met_by_the_oracle_itself(oracle):
+    """The bar of the GPU parity tests for GMRES with 5 Krylov vectors
+    (conftest.assert_parity_global with min_frac = 0.5): the oracle against
+    itself with inputs perturbed by 1e-15 meets it, and misses the simple bar."""
+    from tests.conftest import assert_parity_global
+    w = dict(W.make_workload("s21_r84_262k", 256), t_out=1e-8)
+    run = lambda y0: oracle.integrate(w["mechs"], y0, 0.0, w["t_out"], w["rtol"], w["atol"],
+                                      T=w["T"], gmres_maxl=5)
+    yo, st = run(w["y0"])
+    rng = np.random.default_rng(0)
+    yp, stp = run(w["y0"] * (1 + 1e-15 * rng.standard_normal(w["y0"].shape)))
+    assert np.all(st["status"] == 0) and np.all(stp["status"] == 0)
+    r = assert_parity_global(yp, yo, w, oracle, "oracle perturbed by 1e-15", min_frac=0.5)
+    assert r["frac_within_10rtol"] < 0.9
