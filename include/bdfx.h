@@ -12,14 +12,14 @@
  * Jacobian, factored by dense LU with partial pivoting (Table 1, approaches
  * 2A/2B; Sec. 4.1.4).  Options: the Jacobian by difference quotients
  * (approaches 3A/3B), or an inexact Newton iteration with matrix-free GMRES
- * (approaches 1A/1B; Sec. 2, Eqs. (linear) and (stop_linear)).
+ * (approaches 1A/1B; Sec. 2, Eqs. (5) and (6)).
  *
  * Conventions
  *  - All d_* arguments are device pointers owned by the caller.  The library
  *    borrows them from bdfx_bind() until the next bind or bdfx_destroy().  The
  *    library owns only the context and the mechanism tables; it allocates no
  *    device memory after bdfx_bind() (the paper's memory-pool lesson,
- *    Sec. 4.2.4), so bdfx_integrate() and bdfx_perturb() can be captured in a
+ *    Sec. 4.3.1), so bdfx_integrate() and bdfx_perturb() can be captured in a
  *    HIP graph.
  *  - State layout is cell-major ("CY" ordering of Sec. 4.1.2):
  *    y[cell * ldy + species], FP64.
@@ -73,8 +73,9 @@ typedef struct bdfx_mech_s *bdfx_mech;
  * f_i = F_i + sum_r nu_ir q_r.  Rate constants are Arrhenius,
  * k_f = exp(lnA_r - EaR_r / T_c) * kscale_c[r], k_r = k_f exp(-lnK_r).
  *
- * Non-isothermal cells (cv and u0 given; Sec. 3.1 with the temperature
- * evolving, the transcendental-heavy cost shape of Sec. 4.2.1): the
+ * Non-isothermal cells (cv and u0 given; the Arrhenius terms of Sec. 3.1
+ * with the temperature evolving, as in the zero-dimensional constant-energy
+ * reactor of Sec. 4.1.3): the
  * temperature is state entry n_species of every cell of this mechanism
  * (y[cell][n_species], so the state has n_species + 1 entries and ldy, atol
  * and the workspace count it), T_c is not used, the rate constants are
@@ -124,9 +125,9 @@ typedef struct {
                               each Newton system (I - gamma J(y_m)) x = b at the current
                               iterate is solved by GMRES with at most this many Krylov
                               vectors, on the system scaled by the error weights (Sec. 2,
-                              Eq. (linear), S1 = S2 = diag(w), no preconditioner), with
+                              Eq. (5), S1 = S2 = diag(w), no preconditioner), with
                               J v = (f(y_m + sigma v) - f(y_m)) / sigma, sigma = 1/||v||_wrms,
-                              and the stopping test of Eq. (stop_linear), c_l = 0.05, on the
+                              and the stopping test of Eq. (6), c_l = 0.05, on the
                               residual norm from the Givens rotations.  No matrix is formed:
                               jacobian must be BDFX_JAC_ANALYTIC, lu_precision and
                               cells_per_wave = 2 do not apply, record_steps must be 0.  A
@@ -217,7 +218,7 @@ int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out);
  * Enqueue only. */
 int bdfx_perturb(bdfx_ctx ctx, uint64_t seed, int64_t outer_step, double amplitude);
 
-/* Typical-value absolute tolerances (Sec. 4.1.3, Eq. (eta)).  For every
+/* Typical-value absolute tolerances (Sec. 4.1.3, Eq. (9)).  For every
  * mechanism m and species i < S_m, the typical value ytyp[m][i] is
  * 0.5 * (min + max) of y[c][i] over the bound cells c of mechanism m (their
  * current states), and atol[m][i] = eta * ytyp[m][i], or eta where ytyp is

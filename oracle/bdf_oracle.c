@@ -20,10 +20,10 @@
  *   limitation of Sec. 2).  Options: a Jacobian by difference quotients
  *   (approaches 3A/3B), or an inexact Newton iteration whose linear systems
  *   are solved by matrix-free GMRES on the scaled system of Sec. 2,
- *   Eqs. (linear) and (stop_linear) (approaches 1A/1B).
+ *   Eqs. (5) and (6) (approaches 1A/1B).
  *
  * The paper gives no BDF coefficients, heuristics or constants beyond
- * Eqs. (3)-(4).  Where it is silent the following readings are used, each
+ * Eqs. (3) and (4).  Where it is silent the following readings are used, each
  * stated where it is implemented: Nordsieck variable-coefficient BDF with
  * Lambda(x) = prod_i (1 + x/xi_i); error constant 1/(l_1 xi_{q+1});
  * interpolation-preserving order changes; the initial-step estimate; the
@@ -32,7 +32,7 @@
  * Non-isothermal cells (a mechanism with heat capacities): temperature is
  * the state's last component and the rate constants are re-evaluated from it
  * at every right-hand side (the Arrhenius terms of Sec. 3.1 with T varying,
- * Sec. 4.2.1).  The reactor is adiabatic at constant volume with synthetic
+ * as in the zero-dimensional constant-internal-energy reactor of Sec. 4.1.3).  The reactor is adiabatic at constant volume with synthetic
  * species energies u_i(T) = u0_i + cv_i T, so the total energy
  * sum_i y_i u_i(T) is constant: dT/dt = F_T - sum_i u_i(T) dy_i/dt / sum_i
  * cv_i y_i.
@@ -244,8 +244,8 @@ void orc_jac_thermal(const orc_mech *m, const double *kscale, const double *F, c
 }
 
 /* ------------------------------------------------------------------------ */
-/* Dense LU with partial pivoting (Sec. 4.1.4: "LU factorization with       */
-/* pivoting").  Ties in |pivot| go to the lowest original row index.         */
+/* Dense LU with partial pivoting (the dense direct solver of Sec. 4.1.4).   */
+/* Ties in |pivot| go to the lowest original row index.                      */
 /* ------------------------------------------------------------------------ */
 
 /* Factor A (n x n, row-major) in place: P A = L U, unit lower L stored below
@@ -535,7 +535,7 @@ void orc_jacobian_dq(const orc_mech *m, double T, const double *kscale, const do
 }
 
 /* Linear solve of the inexact Newton iteration (Table 1, approaches 1A/1B):
- * GMRES on the scaled system of Sec. 2, Eq. (linear), with S1 = S2 =
+ * GMRES on the scaled system of Sec. 2, Eq. (5), with S1 = S2 =
  * diag(w) and no preconditioner (P1 = P2 = I), for A = I - gamma J(y), b.
  * A is applied without forming J: the product J v is the difference quotient
  * (f(y + sigma v) - f(y)) / sigma with sigma = 1 / ||v||_wrms and fy = f(y).
@@ -543,9 +543,9 @@ void orc_jacobian_dq(const orc_mech *m, double T, const double *kscale, const do
  * Gram-Schmidt; Givens rotations turn the Hessenberg matrix into triangular
  * form and give the residual norm of the scaled system as the magnitude of
  * the last rotated right-hand-side entry, without forming the residual
- * (Sec. 2, after Eq. (stop_linear); Saad, Iterative Methods for Sparse
+ * (Sec. 2, after Eq. (6); Saad, Iterative Methods for Sparse
  * Linear Systems, Sec. 6.5).  Iteration stops at maxl basis vectors or when
- * that residual norm is at most delta (Eq. (stop_linear); delta is passed in
+ * that residual norm is at most delta (Eq. (6); delta is passed in
  * the 2-norm of the scaled system).  Returns 0 when converged, 1 when the
  * residual was reduced but not to delta, 2 otherwise; x receives the
  * solution of the unscaled system.  *nli counts iterations (one product J v,
@@ -803,7 +803,7 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
         for (int i = 0; i < S; ++i) G[i] = e[i] - gamma * f[i] + z[1][i] / l[1];
         for (int i = 0; i < S; ++i) delta[i] = -G[i];
         if (krylov) {
-          /* inexact Newton: J at the current iterate, Eq. (stop_linear) with
+          /* inexact Newton: J at the current iterate, Eq. (6) with
            * c_l = 0.05 on the Newton tolerance c_eps eps = 0.1 / Cerr, in
            * WRMS units (the scaled 2-norm is sqrt(S) times the WRMS norm) */
           double rhs_b[ORC_MAXS], rho;

@@ -408,7 +408,7 @@ def perturb(y, n_species_of_cell, weights_of_cell, seed, step, amp):
 
 
 def typical_atol(y, eta, n_species, cell_mech=None):
-    """Typical-value absolute tolerances (Sec. 4.1.3, Eq. (eta)).
+    """Typical-value absolute tolerances (Sec. 4.1.3, Eq. (9)).
 
     For each mechanism m and species i < n_species[m], the typical value is
     half the sum of the smallest and largest y[c][i] over the cells c of

@@ -1033,15 +1033,15 @@ __device__ __forceinline__ double wrms2(const Grp<G> &W, double v, double w, dou
 }
 
 // Linear solve of the inexact Newton iteration (Table 1, approaches 1A/1B):
-// GMRES on the system scaled by the error weights (Sec. 2, Eq. (linear),
+// GMRES on the system scaled by the error weights (Sec. 2, Eq. (5),
 // S1 = S2 = diag(w), no preconditioner) for (I - gamma J(y)) x = b, with J v
 // the difference quotient (f(y + sigma v) - f(y)) / sigma, sigma =
 // 1 / ||v||_wrms, and fy = f(y).  Initial guess 0; modified Gram-Schmidt
 // Arnoldi; Givens rotations reduce the Hessenberg matrix to triangular form
 // and give the residual norm of the scaled system as the magnitude of the
-// last rotated right-hand-side entry (Sec. 2, after Eq. (stop_linear)).
+// last rotated right-hand-side entry (Sec. 2, after Eq. (6)).
 // Stops at maxl basis vectors or when that norm is at most delta (the
-// 2-norm of Eq. (stop_linear)).  Lane i holds entry i of y, fy, w and b (w = 0
+// 2-norm of Eq. (6)).  Lane i holds entry i of y, fy, w and b (w = 0
 // past the state); the basis and the Hessenberg data live in the wave's LDS
 // (KryLayout), so the loop is not unrolled and the right-hand side is
 // inlined once.  Returns 0 when converged, 1 when the residual was reduced
@@ -1340,7 +1340,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       }
       const double cfac =
           KRY ? 1.0 : W.uni(gamma != gamma_bar ? 2.0 * rcp(1.0 + gamma * rcp(gamma_bar)) : 1.0);
-      // GMRES tolerance, Eq. (stop_linear): c_l = 0.05 times the Newton
+      // GMRES tolerance, Eq. (6): c_l = 0.05 times the Newton
       // tolerance c_eps eps = 0.1 / Cerr, in the scaled 2-norm (sqrt(n) times
       // the WRMS norm)
       const double ltol = KRY ? W.uni(0.005 * rcp(Cerr) * sqrt(static_cast<double>(n))) : 0.0;

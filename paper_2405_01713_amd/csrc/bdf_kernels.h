@@ -4,7 +4,7 @@
 // cell of its grid index; in queue mode (persistent waves) a wave pops cell
 // indices from a global atomic counter until the list is exhausted, so waves
 // whose cells finish early take new work instead of leaving their SIMD slot
-// to the tail (the load imbalance of lock-step batches, Sec. 2 and 3.3).
+// to the tail (the load imbalance of lock-step batches, Sec. 2 and 4.1.1).
 #pragma once
 
 #include "bdf_device.h"

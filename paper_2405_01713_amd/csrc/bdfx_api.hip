@@ -4,7 +4,7 @@
 // device-resident mechanism tables; builds the reaction slot words and the
 // lane-major analytic-Jacobian term tables from the stoichiometry; launches
 // the per-size integrator kernels (one wavefront per cell).  Nothing here allocates device memory after
-// bdfx_bind() (the paper's memory-pool lesson, Sec. 4.2.4), so integrate and
+// bdfx_bind() (the paper's memory-pool lesson, Sec. 4.3.1), so integrate and
 // perturb can be captured into a HIP graph by the caller.
 #include <hip/hip_runtime.h>
 

@@ -1,4 +1,4 @@
-// typical.hip -- typical-value absolute tolerances (Sec. 4.1.3, Eq. (eta)):
+// typical.hip -- typical-value absolute tolerances (Sec. 4.1.3, Eq. (9)):
 // atol_i = eta * (min_c y_ci + max_c y_ci) / 2 over the cells of a mechanism.
 //
 // Two kernels per call.  k_extremes streams the state rows of one mechanism

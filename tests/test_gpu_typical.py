@@ -1,4 +1,4 @@
-"""GPU tests of the typical-value absolute tolerances (Sec. 4.1.3, Eq. (eta)).
+"""GPU tests of the typical-value absolute tolerances (Sec. 4.1.3, Eq. (9)).
 
 The typical values are extremes and one rounded mean, so the device values
 must equal the oracle's bit for bit; integrations that use the resulting

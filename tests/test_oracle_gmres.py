@@ -1,5 +1,5 @@
 """Pins of the oracle's inexact Newton with matrix-free GMRES (Table 1,
-approaches 1A/1B; Sec. 2, Eqs. (linear) and (stop_linear)).
+approaches 1A/1B; Sec. 2, Eqs. (5) and (6)).
 
 * The linear solve: exact (to the difference quotients' round-off) for a
   linear system once the Krylov dimension reaches the system size; for fewer

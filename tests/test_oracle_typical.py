@@ -1,4 +1,4 @@
-"""Pins of the oracle's typical-value absolute tolerances (Sec. 4.1.3, Eq. (eta)).
+"""Pins of the oracle's typical-value absolute tolerances (Sec. 4.1.3, Eq. (9)).
 
 The typical value of a species is half the sum of its smallest and largest
 value over the domain; atol_i = eta times it, with the paper's default of 1
