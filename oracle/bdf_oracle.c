@@ -53,6 +53,8 @@
 #define ORC_SLOTS 3
 #define ORC_UROUND 2.220446049250313e-16
 #define ORC_GMRES_MAXL 10
+#define ORC_MAXB 16                    /* cells per lock-step batch */
+#define ORC_MAXN (ORC_MAXS * ORC_MAXB) /* state length of a lock-step batch */
 
 /* Per-cell status codes. */
 #define ORC_SUCCESS 0
@@ -325,10 +327,12 @@ double orc_wrms(int n, const double *v, const double *w) {
   return sqrt(s / n);
 }
 
-/* Error weights of Sec. 2, Eq. (3): w_i = 1/(rtol |y_i| + atol_i). */
-static void orc_ewt(int n, const double *y, const orc_opts *o, double *w) {
+/* Error weights of Sec. 2, Eq. (3): w_i = 1/(rtol |y_i| + atol_i), for n
+ * entries that are consecutive cell states of S entries each (atol per entry
+ * of a cell's state). */
+static void orc_ewt(int n, int S, const double *y, const orc_opts *o, double *w) {
   for (int i = 0; i < n; ++i) {
-    double a = o->atol_len == 1 ? o->atol[0] : o->atol[i];
+    double a = o->atol_len == 1 ? o->atol[0] : o->atol[i % S];
     w[i] = 1.0 / (o->rtol * fabs(y[i]) + a);
   }
 }
@@ -363,21 +367,21 @@ static void orc_xi(double h, const double *hist, int q, double *xi) {
 /* ------------------------------------------------------------------------ */
 
 /* Predictor: z <- z * Pascal (Taylor shift by one step). */
-static void orc_predict(int S, int q, double z[][ORC_MAXS]) {
+static void orc_predict(int S, int q, double z[][ORC_MAXN]) {
   for (int k = 1; k <= q; ++k)
     for (int j = q; j >= k; --j)
       for (int i = 0; i < S; ++i) z[j - 1][i] += z[j][i];
 }
 
 /* Exact inverse of orc_predict (restore after a rejected attempt). */
-static void orc_unpredict(int S, int q, double z[][ORC_MAXS]) {
+static void orc_unpredict(int S, int q, double z[][ORC_MAXN]) {
   for (int k = 1; k <= q; ++k)
     for (int j = q; j >= k; --j)
       for (int i = 0; i < S; ++i) z[j - 1][i] -= z[j][i];
 }
 
 /* Change of step size h -> eta h: z_j <- eta^j z_j. */
-static void orc_rescale(int S, int q, double eta, double z[][ORC_MAXS]) {
+static void orc_rescale(int S, int q, double eta, double z[][ORC_MAXN]) {
   double f = 1.0;
   for (int j = 1; j <= q; ++j) {
     f *= eta;
@@ -390,7 +394,7 @@ static void orc_rescale(int S, int q, double eta, double z[][ORC_MAXS]) {
  * makes z also interpolate the value the predictor interpolated at
  * t_{n-q-1}; l and xi are those of the step just accepted. */
 static void orc_order_up(int S, int q, const double *l, const double *xi, const double *e,
-                         double z[][ORC_MAXS]) {
+                         double z[][ORC_MAXN]) {
   double c = 1.0 / xi[q + 1];
   for (int i = 0; i < S; ++i) z[q + 1][i] = 0.0;
   for (int j = 1; j <= q + 1; ++j)
@@ -399,7 +403,7 @@ static void orc_order_up(int S, int q, const double *l, const double *xi, const 
 
 /* Order q -> q-1: subtract z_q x prod_{i=1}^{q-1} (x + xi_i), which removes
  * the x^q term and keeps interpolation at t_n, ..., t_{n-q+1}. */
-static void orc_order_down(int S, int q, const double *xi, double z[][ORC_MAXS]) {
+static void orc_order_down(int S, int q, const double *xi, double z[][ORC_MAXN]) {
   double c[ORC_QMAX + 2];
   for (int j = 0; j <= q; ++j) c[j] = 0.0;
   c[1] = 1.0; /* polynomial x */
@@ -432,27 +436,42 @@ static int orc_all_finite(int n, const double *v) {
 /* Per-cell adaptive integration                                            */
 /* ------------------------------------------------------------------------ */
 
+/* The system one integration advances: one cell, or nb cells of the same
+ * mechanism in lock step (their states concatenated, cell b at entries
+ * [b S, (b+1) S); rates of cell b at kf + b R, kr + b R; forcing at F + b S;
+ * non-isothermal rate scales at kscale + b R). */
 typedef struct {
   const orc_mech *m;
   const double *kf, *kr, *F;
-  int S;                 /* state length: species, plus 1 for a non-isothermal cell */
+  int S;                 /* state length of a cell: species, plus 1 for a non-isothermal cell */
   const double *kscale;  /* non-isothermal: per-reaction scale for the rates at T */
+  int nb;                /* cells (1 unless integrated in lock step) */
 } orc_sys;
 
 static int sys_thermal(const orc_sys *s) { return s->m->cv != NULL; }
 
 static void sys_f(const orc_sys *s, const double *y, double *f) {
-  if (sys_thermal(s))
-    orc_rhs_thermal(s->m, s->kscale, s->F, y, f);
-  else
-    orc_rhs(s->m, s->kf, s->kr, s->F, y, f);
+  const int S = s->S, R = s->m->n_reactions;
+  for (int b = 0; b < s->nb; ++b) {
+    const double *F = s->F ? s->F + b * S : NULL;
+    if (sys_thermal(s))
+      orc_rhs_thermal(s->m, s->kscale ? s->kscale + b * R : NULL, F, y + b * S, f + b * S);
+    else
+      orc_rhs(s->m, s->kf + b * R, s->kr + b * R, F, y + b * S, f + b * S);
+  }
 }
 
+/* Jacobian blocks: J + b S S is the S x S Jacobian of cell b (the system's
+ * Jacobian is block diagonal). */
 static void sys_jac(const orc_sys *s, const double *y, double *J) {
-  if (sys_thermal(s))
-    orc_jac_thermal(s->m, s->kscale, s->F, y, J);
-  else
-    orc_jac(s->m, s->kf, s->kr, y, J);
+  const int S = s->S, R = s->m->n_reactions;
+  for (int b = 0; b < s->nb; ++b) {
+    const double *F = s->F ? s->F + b * S : NULL;
+    if (sys_thermal(s))
+      orc_jac_thermal(s->m, s->kscale ? s->kscale + b * R : NULL, F, y + b * S, J + b * S * S);
+    else
+      orc_jac(s->m, s->kf + b * R, s->kr + b * R, y + b * S, J + b * S * S);
+  }
 }
 
 /* Initial step size (reading; the paper is silent).  Bounds
@@ -463,26 +482,26 @@ static void sys_jac(const orc_sys *s, const double *y, double *J) {
  * [h_lb, h_ub] (h_ub if y'' vanishes). */
 static double orc_initial_step(const orc_sys *s, const orc_opts *o, double t0, double tout,
                                const double *y0, const double *f0, const double *ewt, int *nfe) {
-  int S = s->S;
+  int S = s->S, n = s->S * s->nb;
   double tdist = fabs(tout - t0);
   double hlb = 100.0 * ORC_UROUND * fmax(fabs(t0), fabs(tout));
   double hub = 0.1 * tdist;
   double hub_inv = 0.0;
-  for (int i = 0; i < S; ++i) {
-    double a = o->atol_len == 1 ? o->atol[0] : o->atol[i];
+  for (int i = 0; i < n; ++i) {
+    double a = o->atol_len == 1 ? o->atol[0] : o->atol[i % S];
     double v = fabs(f0[i]) / (0.1 * fabs(y0[i]) + a);
     if (v > hub_inv) hub_inv = v;
   }
   if (hub * hub_inv > 1.0) hub = 1.0 / hub_inv;
   if (hub < hlb) return hub;
   double hg = sqrt(hlb * hub), hnew = hg;
-  double ytmp[ORC_MAXS], ftmp[ORC_MAXS], ydd[ORC_MAXS];
+  double ytmp[ORC_MAXN], ftmp[ORC_MAXN], ydd[ORC_MAXN];
   for (int it = 0; it < 4; ++it) {
-    for (int i = 0; i < S; ++i) ytmp[i] = y0[i] + hg * f0[i];
+    for (int i = 0; i < n; ++i) ytmp[i] = y0[i] + hg * f0[i];
     sys_f(s, ytmp, ftmp);
     (*nfe)++;
-    for (int i = 0; i < S; ++i) ydd[i] = (ftmp[i] - f0[i]) / hg;
-    double yddnrm = orc_wrms(S, ydd, ewt);
+    for (int i = 0; i < n; ++i) ydd[i] = (ftmp[i] - f0[i]) / hg;
+    double yddnrm = orc_wrms(n, ydd, ewt);
     if (!(yddnrm > 0.0)) return hub;
     hnew = sqrt(2.0 / yddnrm);
     double ratio = hnew / hg;
@@ -529,7 +548,7 @@ void orc_jacobian_dq(const orc_mech *m, double T, const double *kscale, const do
   double kf[4096], kr[4096];
   const int thermal = m->cv != NULL;
   if (!thermal) orc_rates(m, T, kscale, kf, kr);
-  orc_sys s = {m, kf, kr, F, m->n_species + thermal, kscale};
+  orc_sys s = {m, kf, kr, F, m->n_species + thermal, kscale, 1};
   int32_t nfe = 0;
   orc_jac_dq(&s, y, ewt, h, J, &nfe);
 }
@@ -640,7 +659,7 @@ int32_t orc_gmres_solve(const orc_mech *m, double T, const double *kscale, const
   double kf[4096], kr[4096], fy[ORC_MAXS];
   const int thermal = m->cv != NULL;
   if (!thermal) orc_rates(m, T, kscale, kf, kr);
-  orc_sys s = {m, kf, kr, F, m->n_species + thermal, kscale};
+  orc_sys s = {m, kf, kr, F, m->n_species + thermal, kscale, 1};
   sys_f(&s, y, fy);
   *nli = 0;
   return orc_gmres(&s, y, fy, ewt, gamma, maxl, delta, b, x, nli, rho);
@@ -691,42 +710,44 @@ static double orc_eta(double bias, double err, int p) {
  */
 static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0, double tout,
                                   double *y, orc_stats *st, orc_record *rec, double *zout) {
-  const int S = s->S;
+  const int S = s->S, n = s->S * s->nb; /* entries per cell, entries of the system */
   const int qmax = o->max_order < 1 ? 1 : (o->max_order > ORC_QMAX ? ORC_QMAX : o->max_order);
   const int krylov = o->gmres_maxl > 0;
-  double z[ORC_QMAX + 2][ORC_MAXS];
-  double ewt[ORC_MAXS], e[ORC_MAXS], eprev[ORC_MAXS], ycur[ORC_MAXS], f[ORC_MAXS], G[ORC_MAXS];
-  double delta[ORC_MAXS];
-  double J[ORC_MAXS * ORC_MAXS], M[ORC_MAXS * ORC_MAXS];
-  int32_t perm[ORC_MAXS];
+  double z[ORC_QMAX + 2][ORC_MAXN];
+  double ewt[ORC_MAXN], e[ORC_MAXN], eprev[ORC_MAXN], ycur[ORC_MAXN], f[ORC_MAXN], G[ORC_MAXN];
+  double delta[ORC_MAXN];
+  int32_t perm[ORC_MAXN];
   double hist[ORC_QMAX + 1];
   double xi[ORC_QMAX + 2], l[ORC_QMAX + 2], Cerr = 0.5;
 
   memset(st, 0, sizeof(*st));
   st->t_reached = t0;
   if (rec) rec->n = 0;
-  if (!orc_all_finite(S, y)) {
+  if (!orc_all_finite(n, y)) {
     st->status = ORC_NONFINITE;
     return st->status;
   }
   for (int j = 0; j <= ORC_QMAX + 1; ++j)
-    for (int i = 0; i < ORC_MAXS; ++i) z[j][i] = 0.0;
+    for (int i = 0; i < ORC_MAXN; ++i) z[j][i] = 0.0;
 
   double t = t0;
   int q = 1;
-  for (int i = 0; i < S; ++i) z[0][i] = y[i];
+  for (int i = 0; i < n; ++i) z[0][i] = y[i];
   sys_f(s, y, f);
   st->nfe = 1;
-  if (!orc_all_finite(S, f)) {
+  if (!orc_all_finite(n, f)) {
     st->status = ORC_NONFINITE;
     return st->status;
   }
-  orc_ewt(S, y, o, ewt);
+  orc_ewt(n, S, y, o, ewt);
   double h = orc_initial_step(s, o, t0, tout, y, f, ewt, &st->nfe);
-  for (int i = 0; i < S; ++i) z[1][i] = h * f[i];
+  for (int i = 0; i < n; ++i) z[1][i] = h * f[i];
   for (int k = 0; k <= ORC_QMAX; ++k) hist[k] = h;
   if (rec) rec->h_pad = h;
 
+  /* Jacobian and Newton-matrix blocks, one S x S block per cell */
+  double *J = malloc(sizeof(double) * (size_t)s->nb * S * S);
+  double *M = malloc(sizeof(double) * (size_t)s->nb * S * S);
   int qwait = 2;
   double Rrate = 1.0, eta_max = 1.0e4, gamma_bar = 0.0;
   int need_setup = 1, nst_setup = 0, have_eprev = 0, rebuilt = 0;
@@ -738,7 +759,7 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
       status = ORC_TOO_MUCH_WORK;
       break;
     }
-    orc_ewt(S, z[0], o, ewt); /* from y^{n-1}, held through retries */
+    orc_ewt(n, S, z[0], o, ewt); /* from y^{n-1}, held through retries */
     int nef_step = 0, ncf_step = 0, nsf_step = 0;
     double dsm = 0.0, tn = t, gamma = h;
     int accepted = 0;
@@ -747,7 +768,7 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
       int landing = 0;
       if (t + h >= tout * (1.0 - 4.0 * ORC_UROUND)) {
         double hnew = tout - t;
-        orc_rescale(S, q, hnew / h, z);
+        orc_rescale(n, q, hnew / h, z);
         h = hnew;
         landing = 1;
       }
@@ -756,7 +777,7 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
         break;
       }
       tn = landing ? tout : t + h;
-      orc_predict(S, q, z);
+      orc_predict(n, q, z);
       orc_xi(h, hist, q, xi);
       orc_bdf_coeffs(q, xi, l, &Cerr);
       gamma = h / l[1];
@@ -768,23 +789,29 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
           orc_jac_dq(s, z[0], ewt, h, J, &st->nfe);
         else
           sys_jac(s, z[0], J);
-        for (int i = 0; i < S; ++i)
-          for (int j = 0; j < S; ++j) M[i * S + j] = (i == j ? 1.0 : 0.0) - gamma * J[i * S + j];
+        /* block b of M = I - gamma J is cell b's S x S Newton matrix */
+        for (int b = 0; b < s->nb; ++b)
+          for (int i = 0; i < S; ++i)
+            for (int j = 0; j < S; ++j)
+              M[(b * S + i) * S + j] = (i == j ? 1.0 : 0.0) - gamma * J[(b * S + i) * S + j];
         st->nsetups++;
         nst_setup = st->nst;
         gamma_bar = gamma;
         Rrate = 1.0;
         need_setup = 0;
         fresh = 1;
-        if (orc_lu_factor(S, M, perm) != 0) {
+        int singular = 0;
+        for (int b = 0; b < s->nb; ++b)
+          if (orc_lu_factor(S, M + b * S * S, perm + b * S) != 0) singular = 1;
+        if (singular) {
           /* singular Newton matrix: recoverable once per step by cutting h */
-          orc_unpredict(S, q, z);
+          orc_unpredict(n, q, z);
           need_setup = 1;
           if (++nsf_step >= 2) {
             status = ORC_SETUP_FAILURE;
             break;
           }
-          orc_rescale(S, q, 0.25, z);
+          orc_rescale(n, q, 0.25, z);
           h *= 0.25;
           eta_max = 1.0;
           continue;
@@ -794,22 +821,22 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
       /* Newton iteration, stopping test of Eq. (4) */
       int conv = 0;
       double dprev = 0.0;
-      for (int i = 0; i < S; ++i) e[i] = 0.0;
+      for (int i = 0; i < n; ++i) e[i] = 0.0;
       for (int mit = 0; mit < 3; ++mit) {
-        for (int i = 0; i < S; ++i) ycur[i] = z[0][i] + e[i];
+        for (int i = 0; i < n; ++i) ycur[i] = z[0][i] + e[i];
         sys_f(s, ycur, f);
         st->nfe++;
         st->nni++;
-        for (int i = 0; i < S; ++i) G[i] = e[i] - gamma * f[i] + z[1][i] / l[1];
-        for (int i = 0; i < S; ++i) delta[i] = -G[i];
+        for (int i = 0; i < n; ++i) G[i] = e[i] - gamma * f[i] + z[1][i] / l[1];
+        for (int i = 0; i < n; ++i) delta[i] = -G[i];
         if (krylov) {
           /* inexact Newton: J at the current iterate, Eq. (6) with
            * c_l = 0.05 on the Newton tolerance c_eps eps = 0.1 / Cerr, in
            * WRMS units (the scaled 2-norm is sqrt(S) times the WRMS norm) */
-          double rhs_b[ORC_MAXS], rho;
-          for (int i = 0; i < S; ++i) rhs_b[i] = delta[i];
+          double rhs_b[ORC_MAXN], rho;
+          for (int i = 0; i < n; ++i) rhs_b[i] = delta[i];
           int32_t nli = 0;
-          int lret = orc_gmres(s, ycur, f, ewt, gamma, o->gmres_maxl, 0.05 * (0.1 / Cerr) * sqrt(S),
+          int lret = orc_gmres(s, ycur, f, ewt, gamma, o->gmres_maxl, 0.05 * (0.1 / Cerr) * sqrt(n),
                                rhs_b, delta, &nli, &rho);
           st->nli += nli;
           st->nfe += nli;
@@ -818,14 +845,15 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
           if (lret != 0) st->ncfl++;
           if (lret == 2 || (lret == 1 && mit > 0)) break;
         } else {
-          orc_lu_solve(S, M, perm, delta);
+          for (int b = 0; b < s->nb; ++b)
+            orc_lu_solve(S, M + b * S * S, perm + b * S, delta + b * S);
         }
         if (!krylov && gamma != gamma_bar) {
           double c = 2.0 / (1.0 + gamma / gamma_bar);
-          for (int i = 0; i < S; ++i) delta[i] *= c;
+          for (int i = 0; i < n; ++i) delta[i] *= c;
         }
-        for (int i = 0; i < S; ++i) e[i] += delta[i];
-        double d = orc_wrms(S, delta, ewt);
+        for (int i = 0; i < n; ++i) e[i] += delta[i];
+        double d = orc_wrms(n, delta, ewt);
         if (!isfinite(d)) break;
         if (mit >= 1) {
           double ratio = d / dprev;
@@ -841,13 +869,13 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
 
       if (!conv) {
         st->ncfn++;
-        orc_unpredict(S, q, z);
+        orc_unpredict(n, q, z);
         if (++ncf_step >= 10) {
           status = ORC_CONV_FAILURE;
           break;
         }
         if (fresh || krylov) {
-          orc_rescale(S, q, 0.25, z);
+          orc_rescale(n, q, 0.25, z);
           h *= 0.25;
           eta_max = 1.0;
         }
@@ -856,10 +884,10 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
       }
 
       /* local error test, ||LTE|| <= 1 (Sec. 2) */
-      dsm = Cerr * orc_wrms(S, e, ewt);
+      dsm = Cerr * orc_wrms(n, e, ewt);
       if (!(dsm <= 1.0)) {
         st->netf++;
-        orc_unpredict(S, q, z);
+        orc_unpredict(n, q, z);
         if (++nef_step >= 7) {
           status = ORC_ERR_FAILURE;
           break;
@@ -872,8 +900,8 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
           sys_f(s, z[0], f);
           st->nfe++;
           for (int j = 1; j <= ORC_QMAX + 1; ++j)
-            for (int i = 0; i < S; ++i) z[j][i] = 0.0;
-          for (int i = 0; i < S; ++i) z[1][i] = hnew * f[i];
+            for (int i = 0; i < n; ++i) z[j][i] = 0.0;
+          for (int i = 0; i < n; ++i) z[1][i] = hnew * f[i];
           h = hnew;
           qwait = 2;
           have_eprev = 0;
@@ -882,7 +910,7 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
           double eta = orc_eta(6.0, dsm, q + 1);
           if (eta < 0.1) eta = 0.1;
           if (nef_step >= 2 && eta > 0.2) eta = 0.2;
-          orc_rescale(S, q, eta, z);
+          orc_rescale(n, q, eta, z);
           h *= eta;
         }
         continue;
@@ -894,7 +922,7 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
     /* accept: correct the Nordsieck array */
     t = tn;
     for (int j = 0; j <= q; ++j)
-      for (int i = 0; i < S; ++i) z[j][i] += l[j] * e[i];
+      for (int i = 0; i < n; ++i) z[j][i] += l[j] * e[i];
     st->nst++;
     for (int k = ORC_QMAX; k >= 1; --k) hist[k] = hist[k - 1];
     hist[0] = h;
@@ -903,7 +931,7 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
         status = ORC_RECORD_FULL;
         break;
       }
-      for (int i = 0; i < S; ++i) rec->y[(size_t)rec->n * S + i] = z[0][i];
+      for (int i = 0; i < n; ++i) rec->y[(size_t)rec->n * S + i] = z[0][i];
       rec->h[rec->n] = h;
       rec->q[rec->n] = q;
       rec->rebuild[rec->n] = rebuilt;
@@ -913,7 +941,7 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
     double hstep = h;
     qwait--;
     if (qwait == 1 && q < qmax) {
-      for (int i = 0; i < S; ++i) eprev[i] = e[i];
+      for (int i = 0; i < n; ++i) eprev[i] = e[i];
       hprev = hstep;
       have_eprev = 1;
     }
@@ -928,7 +956,7 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
         if (qwait == 0) {
           qwait = 2;
           if (q > 1) {
-            double lte = orc_factorial(q - 1) / orc_harmonic(q - 1) * orc_wrms(S, z[q], ewt);
+            double lte = orc_factorial(q - 1) / orc_harmonic(q - 1) * orc_wrms(n, z[q], ewt);
             double eta_qm1 = orc_eta(6.0, lte, q);
             if (eta_qm1 > eta) {
               eta = eta_qm1;
@@ -936,9 +964,9 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
             }
           }
           if (q < qmax && have_eprev) {
-            double r = pow(hstep / hprev, q + 1), d[ORC_MAXS];
-            for (int i = 0; i < S; ++i) d[i] = e[i] - r * eprev[i];
-            double lte = orc_wrms(S, d, ewt) / ((q + 2) * orc_harmonic(q + 1));
+            double r = pow(hstep / hprev, q + 1), d[ORC_MAXN];
+            for (int i = 0; i < n; ++i) d[i] = e[i] - r * eprev[i];
+            double lte = orc_wrms(n, d, ewt) / ((q + 2) * orc_harmonic(q + 1));
             double eta_qp1 = orc_eta(10.0, lte, q + 2);
             if (eta_qp1 > eta) {
               eta = eta_qp1;
@@ -948,14 +976,14 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
         }
         if (eta >= 1.5) {
           if (eta > eta_max) eta = eta_max;
-          if (qnew == q + 1) orc_order_up(S, q, l, xi, e, z);
-          if (qnew == q - 1) orc_order_down(S, q, xi, z);
+          if (qnew == q + 1) orc_order_up(n, q, l, xi, e, z);
+          if (qnew == q - 1) orc_order_down(n, q, xi, z);
           if (qnew != q) {
             q = qnew;
             qwait = q + 1;
             have_eprev = 0;
           }
-          orc_rescale(S, q, eta, z);
+          orc_rescale(n, q, eta, z);
           h *= eta;
         }
       }
@@ -963,10 +991,12 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
     eta_max = 10.0;
   }
 
-  for (int i = 0; i < S; ++i) y[i] = z[0][i];
+  free(J);
+  free(M);
+  for (int i = 0; i < n; ++i) y[i] = z[0][i];
   if (zout)
     for (int j = 0; j <= ORC_QMAX; ++j)
-      for (int i = 0; i < S; ++i) zout[j * S + i] = j <= q ? z[j][i] : 0.0;
+      for (int i = 0; i < n; ++i) zout[j * S + i] = j <= q ? z[j][i] : 0.0;
   st->status = status;
   st->q_last = q;
   st->h_last = h;
@@ -995,7 +1025,7 @@ int32_t orc_integrate_cell(const orc_mech *m, const orc_opts *o, double T, const
   } else {
     orc_rates(m, T, kscale, kf, kr);
   }
-  orc_sys s = {m, kf, kr, F, m->n_species + thermal, kscale};
+  orc_sys s = {m, kf, kr, F, m->n_species + thermal, kscale, 1};
   if (!isfinite(T)) {
     memset(st, 0, sizeof(*st));
     st->t_reached = t0;
@@ -1024,6 +1054,99 @@ void orc_integrate_batch(int64_t N, const orc_mech *mechs, const int32_t *cell_m
   }
 }
 
+/* Cells integrated in lock step (the paper's batches, Sec. 2: all cells of
+ * a batch share one integrator, so the step size is the one the stiffest
+ * cell allows): the nb cells cells[0..nb-1] of mechanism m form one system
+ * of nb S entries -- one step size and order, one WRMS norm over all nb S
+ * entries (N = nb S in Eq. (3)), one Newton iteration whose matrix is block
+ * diagonal with one S x S block per cell (each block is factored on its own:
+ * partial pivoting on the whole matrix picks the same pivots, the entries
+ * outside a block being zero).  The batch succeeds or fails as a whole and
+ * every cell of it receives the batch's statistics.  Direct solver with the
+ * analytic Jacobian only.  T, kscale, F and y are the arrays of
+ * orc_integrate_batch.  Returns the batch status, or -100 for arguments
+ * outside these limits. */
+int32_t orc_integrate_lockstep(const orc_mech *m, const orc_opts *o, int32_t nb,
+                               const int64_t *cells, const double *T, const double *kscale,
+                               int32_t ldk, const double *F, int32_t ldy, double t0, double tout,
+                               double *y, orc_stats *stats) {
+  const int thermal = m->cv != NULL;
+  const int S = m->n_species + thermal, R = m->n_reactions;
+  if (nb < 1 || nb > ORC_MAXB || S > ORC_MAXS || R > 4096 || o->jac_dq || o->gmres_maxl > 0)
+    return -100;
+  double *yb = malloc(sizeof(double) * (size_t)nb * S);
+  double *kf = malloc(sizeof(double) * (size_t)nb * R);
+  double *kr = malloc(sizeof(double) * (size_t)nb * R);
+  double *Fb = F ? malloc(sizeof(double) * (size_t)nb * S) : NULL;
+  double *ks = (thermal && kscale) ? malloc(sizeof(double) * (size_t)nb * R) : NULL;
+  int finite = 1;
+  for (int b = 0; b < nb; ++b) {
+    const int64_t c = cells[b];
+    for (int i = 0; i < S; ++i) yb[b * S + i] = y[c * ldy + i];
+    if (Fb)
+      for (int i = 0; i < S; ++i) Fb[b * S + i] = F[c * ldy + i];
+    if (thermal) {
+      if (ks)
+        for (int r = 0; r < R; ++r) ks[b * R + r] = kscale[c * ldk + r];
+    } else {
+      const double Tc = T ? T[c] : 1.0;
+      if (!isfinite(Tc)) finite = 0;
+      orc_rates(m, Tc, kscale ? kscale + c * ldk : NULL, kf + b * R, kr + b * R);
+    }
+  }
+  orc_sys s = {m, kf, kr, Fb, S, ks, nb};
+  orc_stats st;
+  if (finite) {
+    orc_integrate_core(&s, o, t0, tout, yb, &st, NULL, NULL);
+  } else {
+    memset(&st, 0, sizeof(st));
+    st.t_reached = t0;
+    st.status = ORC_NONFINITE;
+  }
+  for (int b = 0; b < nb; ++b) {
+    const int64_t c = cells[b];
+    for (int i = 0; i < S; ++i) y[c * ldy + i] = yb[b * S + i];
+    stats[c] = st;
+  }
+  free(yb);
+  free(kf);
+  free(kr);
+  free(Fb);
+  free(ks);
+  return st.status;
+}
+
+/* All cells in lock-step batches of `batch` cells: the cells of each
+ * mechanism, in increasing index order, are cut into consecutive batches
+ * (the last one may be shorter); OpenMP over the batches of a mechanism.
+ * Arguments as orc_integrate_batch, plus the number of mechanisms. */
+void orc_integrate_lockstep_batch(int64_t N, int32_t batch, int32_t n_mech,
+                                  const orc_mech *mechs, const int32_t *cell_mech,
+                                  const orc_opts *o, const double *T, const double *kscale,
+                                  int32_t ldk, const double *F, int32_t ldy, double t0,
+                                  double tout, double *y, orc_stats *stats, int32_t nthreads) {
+  int64_t *list = malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+  for (int32_t mm = 0; mm < n_mech; ++mm) {
+    int64_t cnt = 0;
+    for (int64_t c = 0; c < N; ++c)
+      if ((cell_mech ? cell_mech[c] : 0) == mm) list[cnt++] = c;
+    const int64_t nbatches = (cnt + batch - 1) / batch;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t k = 0; k < nbatches; ++k) {
+      const int64_t first = k * batch;
+      const int32_t nb = (int32_t)(cnt - first < batch ? cnt - first : batch);
+      orc_integrate_lockstep(&mechs[mm], o, nb, list + first, T, kscale, ldk, F, ldy, t0, tout,
+                             y, stats);
+    }
+  }
+  free(list);
+}
+
 int32_t orc_max_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();
@@ -1042,8 +1165,8 @@ int32_t orc_max_threads(void) {
 int32_t orc_fixed_steps(const orc_mech *m, const double *kf, const double *kr, const double *F,
                         int q, double h, int nsteps, double *zio) {
   int S = m->n_species;
-  orc_sys s = {m, kf, kr, F, S};
-  double z[ORC_QMAX + 2][ORC_MAXS];
+  orc_sys s = {m, kf, kr, F, S, NULL, 1};
+  double z[ORC_QMAX + 2][ORC_MAXN];
   double xi[ORC_QMAX + 2], l[ORC_QMAX + 2], Cerr, e[ORC_MAXS], yv[ORC_MAXS], f[ORC_MAXS];
   double J[ORC_MAXS * ORC_MAXS];
   int32_t perm[ORC_MAXS];
@@ -1141,8 +1264,8 @@ static int orc_solve_exact(const orc_sys *s, double gamma, const double *a, doub
 int32_t orc_replay_cell(const orc_mech *m, const double *kf, const double *kr, const double *F,
                         const double *y0, const orc_record *rec, double *yout, double *yrec) {
   int S = m->n_species;
-  orc_sys s = {m, kf, kr, F, S};
-  double z[ORC_QMAX + 2][ORC_MAXS], f[ORC_MAXS], a[ORC_MAXS], y[ORC_MAXS], e[ORC_MAXS];
+  orc_sys s = {m, kf, kr, F, S, NULL, 1};
+  double z[ORC_QMAX + 2][ORC_MAXN], f[ORC_MAXS], a[ORC_MAXS], y[ORC_MAXS], e[ORC_MAXS];
   double xi[ORC_QMAX + 2], l[ORC_QMAX + 2], Cerr;
   double xip[ORC_QMAX + 2], lp[ORC_QMAX + 2];
   memset(z, 0, sizeof(z));
@@ -1245,8 +1368,8 @@ int32_t orc_tangent_cell(const orc_mech *m, const double *kf, const double *kr, 
                          const double *y0, const orc_record *rec, const double *yrec,
                          const double *dy0, const double *dp, double *dyout) {
   int S = m->n_species;
-  orc_sys s = {m, kf, kr, F, S};
-  double dz[ORC_QMAX + 2][ORC_MAXS], J[ORC_MAXS * ORC_MAXS], t1[ORC_MAXS], t2[ORC_MAXS];
+  orc_sys s = {m, kf, kr, F, S, NULL, 1};
+  double dz[ORC_QMAX + 2][ORC_MAXN], J[ORC_MAXS * ORC_MAXS], t1[ORC_MAXS], t2[ORC_MAXS];
   double da[ORC_MAXS], de[ORC_MAXS];
   double xi[ORC_QMAX + 2], l[ORC_QMAX + 2], Cerr, xip[ORC_QMAX + 2], lp[ORC_QMAX + 2];
   int32_t perm[ORC_MAXS];
@@ -1310,8 +1433,8 @@ int32_t orc_adjoint_cell(const orc_mech *m, const double *kf, const double *kr, 
                          const double *y0, const orc_record *rec, const double *yrec,
                          const double *ybar, double *y0bar, double *pbar) {
   int S = m->n_species;
-  orc_sys s = {m, kf, kr, F, S};
-  double zb[ORC_QMAX + 2][ORC_MAXS], J[ORC_MAXS * ORC_MAXS], mu[ORC_MAXS], t1[ORC_MAXS];
+  orc_sys s = {m, kf, kr, F, S, NULL, 1};
+  double zb[ORC_QMAX + 2][ORC_MAXN], J[ORC_MAXS * ORC_MAXS], mu[ORC_MAXS], t1[ORC_MAXS];
   double ebar_extra[ORC_MAXS], eb[ORC_MAXS];
   double xi[ORC_QMAX + 2], l[ORC_QMAX + 2], Cerr;
   int32_t perm[ORC_MAXS];

@@ -100,6 +100,9 @@ def lib():
         L.orc_integrate_batch.argtypes = [C.c_int64, P, P, P, P, P, C.c_int32, P, C.c_int32,
                                           C.c_double, C.c_double, P, P, C.c_int32]
         L.orc_max_threads.restype = C.c_int32
+        L.orc_integrate_lockstep_batch.argtypes = [C.c_int64, C.c_int32, C.c_int32, P, P, P, P,
+                                                   P, C.c_int32, P, C.c_int32, C.c_double,
+                                                   C.c_double, P, P, C.c_int32]
         L.orc_fixed_steps.argtypes = [P, P, P, P, C.c_int, C.c_double, C.c_int, P]
         L.orc_fixed_steps.restype = C.c_int32
         L.orc_replay_cell.argtypes = [P, P, P, P, P, P, P, P]
@@ -256,11 +259,14 @@ def bdf_coeffs(q, xi):
 
 
 def integrate(mechs, y0, t0, t_out, rtol, atol, T=None, kscale=None, F=None, cell_mech=None,
-              max_order=5, max_steps=5000, nthreads=0, jac_dq=False, gmres_maxl=0):
+              max_order=5, max_steps=5000, nthreads=0, jac_dq=False, gmres_maxl=0, lockstep=0):
     """Integrate a batch of cells; returns (y, stats structured array).
     jac_dq: Jacobian by difference quotients instead of the analytic one.
     gmres_maxl > 0: inexact Newton with matrix-free GMRES of that Krylov
-    dimension (approaches 1A/1B) instead of the direct solve."""
+    dimension (approaches 1A/1B) instead of the direct solve.
+    lockstep = B > 0: the cells of each mechanism, in index order, are
+    integrated in lock-step batches of B (one step size and one WRMS norm
+    per batch; direct solver, analytic Jacobian)."""
     if isinstance(mechs, dict):
         mechs = [mechs]
     oms = [OracleMech(m) for m in mechs]
@@ -274,6 +280,14 @@ def integrate(mechs, y0, t0, t_out, rtol, atol, T=None, kscale=None, F=None, cel
     cm = None if cell_mech is None else np.ascontiguousarray(cell_mech, dtype=np.int32)
     o, atol_arr = _opts(rtol, atol, max_order, max_steps, jac_dq, gmres_maxl)
     stats = np.zeros(N, dtype=STATS_DTYPE)
+    if lockstep:
+        if not 1 <= lockstep <= 16 or jac_dq or gmres_maxl:
+            raise ValueError("lock-step batches: 1..16 cells, direct solver, analytic Jacobian")
+        lib().orc_integrate_lockstep_batch(N, int(lockstep), len(oms), C.cast(arr, C.c_void_p),
+                                           _p(cm), C.byref(o), _p(T), _p(ks), ldk, _p(F), ldy,
+                                           float(t0), float(t_out), _p(y), _p(stats),
+                                           int(nthreads))
+        return y, stats
     lib().orc_integrate_batch(N, C.cast(arr, C.c_void_p), _p(cm), C.byref(o), _p(T), _p(ks),
                               ldk, _p(F), ldy, float(t0), float(t_out), _p(y), _p(stats),
                               int(nthreads))
