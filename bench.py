@@ -458,6 +458,52 @@ def run_gmres(tuning_cache=None, n_check=128, t_out=1e-8, steps=3, warmup=1):
     return out
 
 
+def run_lockstep(tuning_cache=None, n_check=128, batches=(2, 4, 8), steps=3, warmup=1):
+    """Per-cell step control against the paper's lock-step batches (Sec. 2:
+    the cells of a batch share one step size and one WRMS norm) on the
+    21-species workload (262,144 cells, one outer step, FP32 Newton matrix,
+    work queue): time per outer step and accepted steps per cell, and the
+    first n_check cells against the oracle run with the same batches."""
+    from paper_2405_01713_amd import bdfx
+
+    w = W.make_workload("s21_r84_262k")
+    out = dict(workload="s21_r84_262k", n_cells=w["n_cells"])
+    ys = {}
+    for B in (0,) + tuple(batches):
+        name = "per_cell" if B == 0 else f"batch{B}"
+        integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"], scheduler=1,
+                                lu_precision=32, lockstep=B)
+        tuning = integ.autotune(0.0, w["t_out"], cache=tuning_cache) if B == 0 else None
+        y0 = integ.y.clone()
+
+        def step():
+            integ.y.copy_(y0)
+            integ.integrate(0.0, w["t_out"])
+
+        ms = _timed_events(step, integ.stream, steps, warmup)
+        st = integ.cell_stats()
+        ys[B] = integ.state()[:n_check]
+        integ.close()
+        log(f"lockstep leg {name}: {ms:.1f} ms")
+        out[name] = dict(kernel_ms=ms, cells_per_s=w["n_cells"] / (ms * 1e-3),
+                         mean_nst=float(st["nst"].mean()), mean_nfe=float(st["nfe"].mean()),
+                         mean_nsetups=float(st["nsetups"].mean()),
+                         failed_cells=int(np.sum(st["status"] != 0)), tuning=tuning)
+    for B in batches:
+        out[f"batch{B}_over_per_cell"] = out[f"batch{B}"]["kernel_ms"] / out["per_cell"]["kernel_ms"]
+    try:
+        from oracle import oracle as O
+        sub = lambda a: a[:n_check]
+        for B in batches:
+            yo, _ = O.integrate(w["mechs"], sub(w["y0"]), 0.0, w["t_out"], w["rtol"], w["atol"],
+                                T=sub(w["T"]), lockstep=B)
+            out[f"batch{B}"]["vs_oracle"] = _errors(ys[B], yo, w["rtol"], w["atol"])
+        out["check_cells"] = n_check
+    except Exception as e:  # the oracle is optional on the timing path
+        out["check_error"] = repr(e)
+    return out
+
+
 def run_typical(tuning_cache=None, reps=50, eta=1e-10):
     """Typical-value absolute tolerances (Sec. 4.1.3): the device min/max pass
     over the states (HBM-bound; bytes = cells x species x 8 read) timed with
@@ -611,7 +657,8 @@ def main():
                          "(typical-value tolerances: reduction bandwidth and integration), "
                          "'thermal' (262,144 non-isothermal 21-species cells), 'dq' "
                          "(difference-quotient vs analytic Jacobian), 'gmres' (matrix-free "
-                         "GMRES vs the direct solve over a 1e-8 s outer step)")
+                         "GMRES vs the direct solve over a 1e-8 s outer step), 'lockstep' "
+                         "(per-cell step control vs lock-step batches of 2, 4 and 8 cells)")
     ap.add_argument("--tuning-cache", default=None,
                     help="JSON file of autotuned launch shapes (reused when present)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
@@ -701,6 +748,8 @@ def main():
         extra["dq"] = run_dq(tuning_cache=args.tuning_cache)
     if "gmres" in args.extra.split(","):
         extra["gmres"] = run_gmres(tuning_cache=args.tuning_cache)
+    if "lockstep" in args.extra.split(","):
+        extra["lockstep"] = run_lockstep(tuning_cache=args.tuning_cache)
     ok = {k: v for k, v in forms.items() if v.get("parity_ok", True) and v["failed_cells"] == 0}
     best = max(ok or forms, key=lambda k: forms[k]["cells_per_s"])
     b = forms[best]

@@ -45,6 +45,7 @@ extern "C" {
 #define BDFX_SLOTS 3
 #define BDFX_MAX_MECH 8
 #define BDFX_GMRES_MAXL 10 /* largest Krylov dimension of bdfx_options.gmres_maxl */
+#define BDFX_MAX_LOCKSTEP 16 /* largest lock-step batch of bdfx_options.lockstep */
 
 /* call status */
 #define BDFX_OK 0
@@ -134,6 +135,18 @@ typedef struct {
                               solve that misses its tolerance after the first Newton
                               iteration (or does not reduce the residual at all) is a
                               convergence failure. */
+  int32_t lockstep;        /* 0: every cell has its own step size and order (default).
+                              1..BDFX_MAX_LOCKSTEP: the paper's lock-step batches (Sec. 2):
+                              each mechanism's cells, in bin order, are cut into consecutive
+                              batches of this many cells; the cells of a batch share one
+                              step size and order, and every WRMS norm of Eqs. (3)-(4) runs
+                              over the batch vector (N = cells x state entries).  The batch
+                              succeeds or fails as a whole; each of its cells reports the
+                              batch's status and counters.  Direct solver with the analytic
+                              Jacobian, isothermal mechanisms, no step recording; one wave
+                              per cell, so the batch's LDS (cells x the per-wave area) must
+                              fit 64 KiB, else bdfx_bind() fails with BDFX_EUNSUPPORTED.
+                              The launch shape is fixed (bdfx_autotune() keeps it). */
 } bdfx_options;
 
 #define BDFX_JAC_ANALYTIC 0

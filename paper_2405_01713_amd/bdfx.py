@@ -22,6 +22,7 @@ BDFX_SCHED_STATIC = 0
 BDFX_SCHED_QUEUE = 1
 BDFX_JAC_ANALYTIC, BDFX_JAC_DQ = 0, 1
 BDFX_GMRES_MAXL = 10
+BDFX_MAX_LOCKSTEP = 16
 MAX_SPECIES = 64
 
 CELL_STATUS = {0: "success", -1: "too_much_work", -3: "err_failure", -4: "conv_failure",
@@ -48,7 +49,7 @@ class Options(C.Structure):
                 ("record_steps", C.c_int32), ("waves_per_block", C.c_int32),
                 ("blocks_per_cu", C.c_int32), ("queue_chunk", C.c_int32),
                 ("waves_per_simd", C.c_int32), ("cells_per_wave", C.c_int32),
-                ("jacobian", C.c_int32), ("gmres_maxl", C.c_int32)]
+                ("jacobian", C.c_int32), ("gmres_maxl", C.c_int32), ("lockstep", C.c_int32)]
 
 
 class Summary(C.Structure):
@@ -180,12 +181,13 @@ def bdfx_mech_destroy(mech):
 def make_options(rtol, atol, max_order=5, max_steps=5000, lu_precision=64,
                  scheduler=BDFX_SCHED_STATIC, record_steps=0, waves_per_block=0,
                  blocks_per_cu=0, queue_chunk=0, waves_per_simd=0, cells_per_wave=0,
-                 jacobian=0, gmres_maxl=0):
+                 jacobian=0, gmres_maxl=0, lockstep=0):
     atol_arr = np.ascontiguousarray(np.atleast_1d(np.asarray(atol, dtype=np.float64)))
     o = Options(float(rtol), atol_arr.ctypes.data_as(C.c_void_p), int(atol_arr.size),
                 int(max_order), int(max_steps), int(lu_precision), int(scheduler),
                 int(record_steps), int(waves_per_block), int(blocks_per_cu), int(queue_chunk),
-                int(waves_per_simd), int(cells_per_wave), int(jacobian), int(gmres_maxl))
+                int(waves_per_simd), int(cells_per_wave), int(jacobian), int(gmres_maxl),
+                int(lockstep))
     o._keep = atol_arr
     return o
 
@@ -350,7 +352,8 @@ class Integrator:
                          f"{'|thermal' if self.mechs[m].get('cv') is not None else ''}"
                          f"|lu{self.opts.lu_precision}|sched{self.opts.scheduler}"
                          f"{'|dq' if self.opts.jacobian else ''}"
-                         f"{f'|gmres{self.opts.gmres_maxl}' if self.opts.gmres_maxl else ''}")
+                         f"{f'|gmres{self.opts.gmres_maxl}' if self.opts.gmres_maxl else ''}"
+                         f"{f'|lock{self.opts.lockstep}' if self.opts.lockstep else ''}")
         db = {}
         if cache and os.path.exists(cache):
             with open(cache) as fh:

@@ -863,6 +863,14 @@ __device__ __forceinline__ void newton_matrix_thermal(LT (&a)[S], const MechDev 
   wave_lds_sync();
 }
 
+// squared WRMS norm of Eq. (3); inv_n = 1 / (species of the cell).  The
+// integrator compares and raises squared norms, so no square root is taken.
+template <int S, int G>
+__device__ __forceinline__ double wrms2(const Grp<G> &W, double v, double w, double inv_n) {
+  const double t = v * w;  // w = 0 on lanes without a species
+  return W.uni(W.template sum<(S + 15) / 16>(t * t) * inv_n);
+}
+
 // Row li of M = I - gamma J with J by forward difference quotients, one
 // right-hand side per state entry (Table 1, approaches 3A/3B; increments of
 // the dense difference-quotient scheme documented for CVODE): f0 = f(y),
@@ -1024,13 +1032,54 @@ __device__ __forceinline__ double inv_solve(const Lds &L, const Grp<G> &W, doubl
 // per-cell integration
 // ---------------------------------------------------------------------------
 
-// squared WRMS norm of Eq. (3); inv_n = 1 / (species of the cell).  The
-// integrator compares and raises squared norms, so no square root is taken.
-template <int S, int G>
-__device__ __forceinline__ double wrms2(const Grp<G> &W, double v, double w, double inv_n) {
-  const double t = v * w;  // w = 0 on lanes without a species
-  return W.uni(W.template sum<(S + 15) / 16>(t * t) * inv_n);
-}
+
+// Lock-step batches (the paper's batches, Sec. 2): the waves of a block
+// integrate the cells of one batch with one step size and order and one WRMS
+// norm over the batch vector.  Every decision of the step control then rests
+// on batch reductions: each wave puts its wave-uniform partial value into its
+// LDS slot, one block barrier, and every wave combines all slots in slot
+// order, so every wave computes the same value and takes the same branch
+// (the barriers need exactly that).  Slots alternate between two halves, so
+// one barrier per reduction suffices: a half is written again only after
+// every wave has passed the barrier of the reduction in between.  A wave
+// without a cell (the last batch can be short) repeats the first cell's work
+// and contributes 0.  LOCK = false: every reduction is the identity.
+constexpr int kMaxBatch = 16;
+
+template <bool LOCK>
+struct BatchRed {
+  double *slots = nullptr;  // [2][kMaxBatch] in the block's LDS
+  int wid = 0, nw = 1;      // this wave's slot, waves of the block
+  int half = 0;
+  bool active = true;       // the wave integrates a cell of the batch
+  __device__ double sum(double v) {
+    if constexpr (!LOCK) {
+      return v;
+    } else {
+      double *h = slots + half * kMaxBatch;
+      half ^= 1;
+      if (threadIdx.x % kWave == 0) h[wid] = active ? v : 0.0;
+      __syncthreads();
+      double t = 0.0;
+      for (int k = 0; k < nw; ++k) t += h[k];
+      return uni(t);
+    }
+  }
+  __device__ double max(double v) {  // of non-negative values
+    if constexpr (!LOCK) {
+      return v;
+    } else {
+      double *h = slots + half * kMaxBatch;
+      half ^= 1;
+      if (threadIdx.x % kWave == 0) h[wid] = active ? v : 0.0;
+      __syncthreads();
+      double t = 0.0;
+      for (int k = 0; k < nw; ++k) t = fmax(t, h[k]);
+      return uni(t);
+    }
+  }
+  __device__ bool any(bool p) { return LOCK ? max(p ? 1.0 : 0.0) != 0.0 : p; }
+};
 
 // Linear solve of the inexact Newton iteration (Table 1, approaches 1A/1B):
 // GMRES on the system scaled by the error weights (Sec. 2, Eq. (5),
@@ -1131,9 +1180,11 @@ __device__ int gmres(const MechDev &m, const Lds &L, const Grp<G> &W, double y, 
   return rho < beta ? 1 : 2;
 }
 
-template <int S, typename LT, int TAB, int G, bool ABC, bool TH, int LIN>
+template <int S, typename LT, int TAB, int G, bool ABC, bool TH, int LIN, bool LOCK = false>
 __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, const Grp<G> &W,
-                                               double *lds, double *kk_slot) {
+                                               double *lds, double *kk_slot,
+                                               BatchRed<LOCK> br = BatchRed<LOCK>{},
+                                               int batch_cells = 1) {
   constexpr bool KRY = LIN == kLinGmres;
   const MechDev &m = P.mech;
   const int R = m.R;
@@ -1144,6 +1195,17 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
   const int n = P.n_sp;
   const double inv_n = 1.0 / n;
   const bool own = W.lane < n;
+  // squared WRMS norm of Eq. (3) over the cell, or over the lock-step batch
+  // vector (batch_cells n entries)
+  const double inv_bn = 1.0 / (static_cast<double>(batch_cells) * n);
+  auto norm2 = [&](double v, double w) {
+    if constexpr (LOCK) {
+      const double t = v * w;  // w = 0 on lanes without a species
+      return W.uni(br.sum(W.uni(W.template sum<(S + 15) / 16>(t * t))) * inv_bn);
+    } else {
+      return wrms2<S>(W, v, w, inv_n);
+    }
+  };
   const double rtol = P.rtol, t0 = P.t0, tout = P.tout;
   const int qmax = P.max_order < 1 ? 1 : (P.max_order > kQmax ? kQmax : P.max_order);
 
@@ -1183,7 +1245,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
   for (int j = 0; j <= kQmax; ++j) z[j] = 0.0;
   bool write_y = true;
 
-  if (W.any(!isfinite(T) || (own && !isfinite(yin)))) {
+  if (br.any(W.any(!isfinite(T) || (own && !isfinite(yin))))) {
     status = kNonfinite;
     write_y = false;
   }
@@ -1192,7 +1254,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
     z[0] = yin;
     f = rhs<ABC, TH>(m, L, W, yin, Fi, ns);
     nfe = 1;
-    if (W.any(own && !isfinite(f))) {
+    if (br.any(W.any(own && !isfinite(f)))) {
       status = kNonfinite;
       write_y = false;
     }
@@ -1203,7 +1265,8 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
     const double tdist = fabs(tout - t0);
     const double hlb = 100.0 * kUround * fmax(fabs(t0), fabs(tout));
     double hub = 0.1 * tdist;
-    const double hub_inv = W.uni(W.template max<(S + 15) / 16>(own ? fabs(f) / (0.1 * fabs(yin) + atol_i) : 0.0));
+    const double hub_inv = br.max(
+        W.uni(W.template max<(S + 15) / 16>(own ? fabs(f) / (0.1 * fabs(yin) + atol_i) : 0.0)));
     if (hub * hub_inv > 1.0) hub = 1.0 / hub_inv;
     if (hub < hlb) {
       h = hub;
@@ -1214,7 +1277,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
         const double ft = rhs<ABC, TH>(m, L, W, yin + hg * f, Fi, ns);
         nfe++;
         const double ydd = (ft - f) / hg;
-        const double yddnrm = sqrt(wrms2<S>(W, ydd, ewt, inv_n));
+        const double yddnrm = sqrt(norm2(ydd, ewt));
         if (!(yddnrm > 0.0)) {
           at_ub = true;
           break;
@@ -1323,7 +1386,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
           R2 = 1.0;
           need_setup = false;
           fresh = true;
-          if (info != 0) {
+          if (br.any(info != 0)) {
             // singular Newton matrix: recoverable once per step by cutting h
             nd_unpredict(z);
             need_setup = true;
@@ -1372,7 +1435,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
           if (cfac != 1.0) delta *= cfac;
         }
         e += delta;
-        const double d2 = wrms2<S>(W, delta, ewt, inv_n);
+        const double d2 = norm2(delta, ewt);
         if (!isfinite(d2)) break;
         if (mit >= 1) {
           const double ratio2 = d2 * rcp(dprev2);
@@ -1402,7 +1465,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       }
 
       // local error test (Sec. 2)
-      dsm2 = W.uni(Cerr * Cerr * wrms2<S>(W, e, ewt, inv_n));
+      dsm2 = W.uni(Cerr * Cerr * norm2(e, ewt));
       if (dsm2 <= 1.0) break;
       netf++;
       nd_unpredict(z);
@@ -1479,7 +1542,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
           if (q > 1) {
             const double lte =
                 factorial(q - 1) / harmonic(q - 1);
-            const double lte2 = lte * lte * wrms2<S>(W, nd_get(z, q), ewt, inv_n);
+            const double lte2 = lte * lte * norm2(nd_get(z, q), ewt);
             const double eta_qm1 = W.uni(eta_from2(6.0, lte2, q));
             if (eta_qm1 > eta) {
               eta = eta_qm1;
@@ -1489,7 +1552,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
           if (q < qmax && have_eprev) {
             const double r = ipow(hstep / C[Ctl::kHprev], q + 1);
             const double c = rcp((q + 2) * harmonic(q + 1));
-            const double lte2 = c * c * wrms2<S>(W, e - r * eprev, ewt, inv_n);
+            const double lte2 = c * c * norm2(e - r * eprev, ewt);
             const double eta_qp1 = W.uni(eta_from2(10.0, lte2, q + 2));
             if (eta_qp1 > eta) {
               eta = eta_qp1;
@@ -1540,8 +1603,8 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
     C[Ctl::kEtaMax] = 10.0;
   }
 
-  if (write_y && own) P.y[cell * P.ldy + W.lane] = z[0];
-  if (W.lane == 0) {
+  if (write_y && own && br.active) P.y[cell * P.ldy + W.lane] = z[0];
+  if (W.lane == 0 && br.active) {
     P.status[cell] = status;
     if (P.stats) {
       CellStats st;

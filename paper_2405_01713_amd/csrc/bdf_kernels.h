@@ -22,13 +22,46 @@ namespace bdfx {
 // as the last state entry, rates re-evaluated from it).  LIN: linear solver
 // of the Newton iteration (kLin*: Newton matrix from the analytic Jacobian or
 // from difference quotients, or matrix-free GMRES; LT is unused by GMRES).
-template <int S, typename LT, int MINW, int TAB, int G, bool ABC, bool TH, int LIN = kLinAnalytic>
-__global__ void __launch_bounds__(256, MINW) k_integrate(Params P) {
+// LOCK: lock-step batches (the paper's batches, Sec. 2): block k integrates
+// batch k of P.batch consecutive list entries, one wave per cell, with one
+// step size and one WRMS norm over the batch (BatchRed); the work queue then
+// hands out batches.  Blocks of up to kMaxBatch waves.
+template <int S, typename LT, int MINW, int TAB, int G, bool ABC, bool TH,
+          int LIN = kLinAnalytic, bool LOCK = false>
+__global__ void __launch_bounds__(LOCK ? kWave * kMaxBatch : 256, MINW) k_integrate(Params P) {
   extern __shared__ double smem[];
   const int wib = threadIdx.x / kWave;
   const Grp<G> W(threadIdx.x & (kWave - 1));
   const int wpb = blockDim.x / kWave;
   double *lds = smem + static_cast<int64_t>(wib * G + W.grp) * P.lds_doubles;
+  if constexpr (LOCK) {
+    static_assert(G == 1 && TAB == kTabLds, "lock-step batches: one cell per wave, tables in LDS");
+    // the batch slots follow the waves' areas; slot 2 kMaxBatch holds the popped batch index
+    double *slots = smem + static_cast<int64_t>(wpb) * P.lds_doubles;
+    const int64_t n_batches = (P.n_list + wpb - 1) / wpb;
+    int64_t b = P.use_queue ? -1 : blockIdx.x;
+    for (;;) {
+      __syncthreads();
+      if (P.use_queue) {
+        if (threadIdx.x == 0) slots[2 * kMaxBatch] = static_cast<double>(atomicAdd(P.queue, 1u));
+        __syncthreads();
+        b = static_cast<int64_t>(slots[2 * kMaxBatch]);
+      }
+      if (b >= n_batches) break;
+      const int64_t first = b * wpb;
+      const int nb = static_cast<int>(P.n_list - first < wpb ? P.n_list - first : wpb);
+      BatchRed<true> br;
+      br.slots = slots;
+      br.wid = wib;
+      br.nw = wpb;
+      br.active = wib < nb;
+      const int64_t idx = first + (br.active ? wib : 0);
+      const int64_t cell = P.list ? P.list[idx] : idx;
+      integrate_cell<S, LT, TAB, G, ABC, TH, LIN, true>(P, cell, W, lds, nullptr, br, nb);
+      if (!P.use_queue) break;
+    }
+    return;
+  }
   double *kk_slot = nullptr;
   if constexpr (TAB == kTabGlobal)
     kk_slot = P.kk_slots + ((static_cast<int64_t>(blockIdx.x) * wpb + wib) * G + W.grp) * (2 * P.mech.R);
@@ -68,6 +101,17 @@ struct LaunchCfg {
 };
 
 // the three register budgets of one kernel configuration
+// lock-step kernels: one register budget (the block of up to 16 waves caps
+// the registers anyway), one cell per wave, tables in LDS
+template <int S>
+const void *lock_kernel(bool fp32, bool abc) {
+  if (abc)
+    return fp32 ? (const void *)&k_integrate<S, float, 1, kTabLds, 1, true, false, kLinAnalytic, true>
+                : (const void *)&k_integrate<S, double, 1, kTabLds, 1, true, false, kLinAnalytic, true>;
+  return fp32 ? (const void *)&k_integrate<S, float, 1, kTabLds, 1, false, false, kLinAnalytic, true>
+              : (const void *)&k_integrate<S, double, 1, kTabLds, 1, false, false, kLinAnalytic, true>;
+}
+
 template <int S, typename LT, int TAB, int G, bool ABC, bool TH = false, int LIN = kLinAnalytic>
 const void *by_budget(int w) {
   using F = const void *;
@@ -127,8 +171,12 @@ const void *integrate_kernel_abc(bool fp32, int w, int tab, int cells_per_wave) 
 // one cell per wave with the tables in LDS)
 template <int S>
 const void *integrate_kernel(bool fp32, int minw, int tab, int cells_per_wave, bool abc,
-                             bool thermal, int lin) {
+                             bool thermal, int lin, bool lock = false) {
   const int w = minw >= 4 ? 2 : minw >= 3 ? 1 : 0;
+  if (lock) {
+    if (tab != kTabLds || cells_per_wave != 1 || thermal || lin != kLinAnalytic) return nullptr;
+    return lock_kernel<S>(fp32, abc);
+  }
   if (lin != kLinAnalytic) {
     if (tab != kTabLds || cells_per_wave != 1) return nullptr;
     if (lin == kLinDq)
@@ -153,8 +201,9 @@ const void *integrate_kernel(bool fp32, int minw, int tab, int cells_per_wave, b
 
 template <int S>
 hipError_t launch_integrate(const Params &P, bool fp32, int minw, int tab, int cells_per_wave,
-                            bool abc, bool thermal, int lin, const LaunchCfg &c, hipStream_t s) {
-  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc, thermal, lin);
+                            bool abc, bool thermal, int lin, bool lock, const LaunchCfg &c,
+                            hipStream_t s) {
+  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc, thermal, lin, lock);
   if (!f) return hipErrorInvalidDeviceFunction;
   Params arg = P;
   void *args[] = {&arg};
@@ -169,9 +218,9 @@ hipError_t launch_adjoint(const Params &P, const LaunchCfg &c, hipStream_t s) {
 
 template <int S>
 hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave, bool abc,
-                               bool thermal, int lin, int block, size_t lds_bytes,
+                               bool thermal, int lin, bool lock, int block, size_t lds_bytes,
                                int *blocks_per_cu) {
-  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc, thermal, lin);
+  const void *f = integrate_kernel<S>(fp32, minw, tab, cells_per_wave, abc, thermal, lin, lock);
   if (!f) {
     *blocks_per_cu = 0;
     return hipSuccess;
@@ -183,19 +232,19 @@ hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave,
 
 // One translation unit per species size (compiled in parallel).  The
 // kernel flags are passed packed: bit 0 A + B <=> C, bit 1 non-isothermal,
-// bit 2 difference-quotient Jacobian, bit 3 GMRES.
+// bit 2 difference-quotient Jacobian, bit 3 GMRES, bit 4 lock-step batches.
 #define BDFX_LIN_OF_FLAGS(f) \
   ((f) & 8 ? bdfx::kLinGmres : (f) & 4 ? bdfx::kLinDq : bdfx::kLinAnalytic)
 #define BDFX_DEFINE_SIZE(S)                                                                      \
   hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, int tab, int cpw,      \
                               int flags, const bdfx::LaunchCfg &c, hipStream_t s) {              \
     return bdfx::launch_integrate<S>(P, fp32, minw, tab, cpw, flags & 1, flags & 2,              \
-                                     BDFX_LIN_OF_FLAGS(flags), c, s);                            \
+                                     BDFX_LIN_OF_FLAGS(flags), flags & 16, c, s);                \
   }                                                                                              \
   hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, int flags, int block,    \
                                  size_t lds, int *out) {                                         \
     return bdfx::occupancy_integrate<S>(fp32, minw, tab, cpw, flags & 1, flags & 2,              \
-                                        BDFX_LIN_OF_FLAGS(flags), block, lds, out);              \
+                                        BDFX_LIN_OF_FLAGS(flags), flags & 16, block, lds, out);  \
   }                                                                                              \
   hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s) { \
     return bdfx::launch_adjoint<S>(P, c, s);                                                     \

@@ -359,12 +359,20 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
                                   "GMRES forms none (use BDFX_JAC_ANALYTIC)");
   if (o->gmres_maxl > 0 && o->record_steps > 0)
     return fail(ctx, BDFX_EUNSUPPORTED, "step recording (adjoint) needs the direct solver");
+  if (o->lockstep < 0 || o->lockstep > BDFX_MAX_LOCKSTEP)
+    return fail(ctx, BDFX_EINVAL, "lockstep must be 0..%d", BDFX_MAX_LOCKSTEP);
+  if (o->lockstep > 0 &&
+      (o->jacobian != BDFX_JAC_ANALYTIC || o->gmres_maxl > 0 || o->record_steps > 0))
+    return fail(ctx, BDFX_EUNSUPPORTED,
+                "lock-step batches: direct solver, analytic Jacobian, no step recording");
   int S_max = 0, R_max = 0;
   for (int m = 0; m < n_mech; ++m) {
     if (!mechs[m] || mechs[m]->ctx != ctx) return fail(ctx, BDFX_EINVAL, "bad mechanism %d", m);
     S_max = std::max(S_max, mechs[m]->n);
     if (mechs[m]->thermal && o->record_steps > 0)
       return fail(ctx, BDFX_EUNSUPPORTED, "step recording (adjoint) needs isothermal mechanisms");
+    if (mechs[m]->thermal && o->lockstep > 0)
+      return fail(ctx, BDFX_EUNSUPPORTED, "lock-step batches need isothermal mechanisms");
     R_max = std::max(R_max, mechs[m]->R);
   }
   if (o->atol_len != 1 && o->atol_len < S_max)
@@ -431,13 +439,14 @@ static int configure_bins(bdfx_ctx ctx);
 // kernel selection flags of a mechanism under the context's options
 static int kernel_flags(bdfx_ctx ctx, bdfx_mech m) {
   return (m->abc ? 1 : 0) | (m->thermal ? 2 : 0) | (ctx->opt.jacobian == BDFX_JAC_DQ ? 4 : 0) |
-         (ctx->opt.gmres_maxl > 0 ? 8 : 0);
+         (ctx->opt.gmres_maxl > 0 ? 8 : 0) | (ctx->opt.lockstep > 0 ? 16 : 0);
 }
 
 // whether a mechanism of this size can run two cells per wave under the
 // context's options (isothermal, analytic Jacobian, direct solver)
 static bool two_cells_per_wave_ok(bdfx_ctx ctx, bdfx_mech m, int S) {
-  return S <= 32 && !m->thermal && ctx->opt.jacobian != BDFX_JAC_DQ && ctx->opt.gmres_maxl == 0;
+  return S <= 32 && !m->thermal && ctx->opt.jacobian != BDFX_JAC_DQ && ctx->opt.gmres_maxl == 0 &&
+         ctx->opt.lockstep == 0;
 }
 
 int bdfx_bind(bdfx_ctx ctx, void *d_ws, size_t ws_bytes, double *d_y, int32_t ldy,
@@ -513,7 +522,11 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
   if (cpw != 1 && !(cpw == 2 && two_cells_per_wave_ok(ctx, m, b.se->S)))
     return fail(ctx, BDFX_EUNSUPPORTED, "%d cells per wave with %d state entries%s", cpw, b.se->S,
                 m->thermal ? " (non-isothermal)" : "");
-  const int waves = std::max(b.waves_per_block, 1);
+  // lock-step: one block per batch, one wave per cell of it, tables in LDS,
+  // and the batch's reduction slots after the waves' areas
+  const int lock = ctx->opt.lockstep;
+  const int waves = lock > 0 ? lock : std::max(b.waves_per_block, 1);
+  const size_t lock_bytes = lock > 0 ? (2 * bdfx::kMaxBatch + 2) * 8 : 0;
   b.cfg.block = bdfx::kWave * waves;
   const int64_t per_block = static_cast<int64_t>(waves) * cpw;
   const int64_t need = (b.count + per_block - 1) / per_block;
@@ -529,8 +542,9 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
         align_up(bdfx::lds_doubles(b.se->S, m->R, fp32 ? 4 : 8, k, m->thermal,
                                    ctx->opt.gmres_maxl),
                  2));
-    lds[k] = static_cast<size_t>(waves) * cpw * d * 8;
-    if (lds[k] > 65536 || (k != bdfx::kTabLds && cpw != 1) || (k == bdfx::kTabGlobal && !queue))
+    lds[k] = static_cast<size_t>(waves) * cpw * d * 8 + lock_bytes;
+    if (lds[k] > 65536 || (k != bdfx::kTabLds && cpw != 1) || (k == bdfx::kTabGlobal && !queue) ||
+        (k != bdfx::kTabLds && lock > 0))
       continue;
     HIPCHK(ctx, b.se->occupancy(fp32, b.waves_per_simd, k, cpw, kernel_flags(ctx, m), b.cfg.block,
                                 lds[k], &occ[k]));
@@ -545,7 +559,7 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
   if (occ[bdfx::kTabGlobal] > occ[k]) k = bdfx::kTabGlobal;
   b.tab = k;
   b.cfg.lds_bytes = lds[k];
-  b.lds_doubles = static_cast<int32_t>(lds[k] / 8 / (waves * cpw));
+  b.lds_doubles = static_cast<int32_t>((lds[k] - lock_bytes) / 8 / (waves * cpw));
   if (b.cfg.lds_bytes > 65536)
     return fail(ctx, BDFX_EUNSUPPORTED, "LDS per block %zu exceeds 64 KiB", b.cfg.lds_bytes);
   if (queue) {
