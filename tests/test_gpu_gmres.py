@@ -116,3 +116,45 @@ def test_gmres_option_checks():
     assert np.all(integ.cell_stats()["status"] == 0)
     assert all(t["cells_per_wave"] == 1 for t in integ.tuning())
     integ.close()
+
+
+def test_gmres_forcing(oracle, parity):
+    import torch
+    from paper_2405_01713_amd import bdfx
+    w = dict(W.make_workload("s21_r84_262k", 128), t_out=1e-8)
+    rng = np.random.default_rng(21)
+    F = rng.uniform(-1.0, 1.0, w["y0"].shape) * 1e2
+    w = dict(w, F=F)
+    integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"], forcing=F,
+                            scheduler=1, gmres_maxl=10)
+    integ.integrate(0.0, w["t_out"])
+    torch.cuda.synchronize()
+    y, st = integ.state(), integ.cell_stats()
+    integ.close()
+    yo, sto = oracle.integrate(w["mechs"], w["y0"], 0.0, w["t_out"], w["rtol"], w["atol"],
+                               T=w["T"], F=F, gmres_maxl=10)
+    assert np.all(st["status"] == 0) and np.all(sto["status"] == 0)
+    parity(y, yo, w, "gmres forcing")
+
+
+def test_gmres_graph_replay():
+    """GMRES in the captured outer loop: replays equal the eager run bit for bit."""
+    import torch
+    from paper_2405_01713_amd import bdfx
+    w = W.make_workload("s21_r84_262k", 120)
+    integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"], scheduler=1,
+                            gmres_maxl=10)
+    y0 = integ.y.clone()
+    integ.outer_loop(2, 1e-8, 9, 0.01)
+    torch.cuda.synchronize()
+    y_eager, st_eager = integ.state(), integ.cell_stats()
+    assert np.all(st_eager["status"] == 0)
+    g = integ.capture_outer_loop(2, 1e-8, 9, 0.01)
+    for rep in range(3):
+        integ.y.copy_(y0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(integ.state(), y_eager), f"replay {rep}"
+        assert np.array_equal(integ.cell_stats(), st_eager), f"replay {rep}"
+    integ.close()

@@ -91,3 +91,48 @@ def test_lockstep_option_checks():
     with pytest.raises(bdfx.BdfxError):
         bdfx.Integrator(w53["mechs"], w53["y0"], w53["rtol"], w53["atol"], T=w53["T"],
                         lockstep=4, lu_precision=64)
+
+
+def test_lockstep_graph_replay():
+    """The outer loop (perturb, integrate) in lock-step batches: HIP-graph
+    replays equal the eager run bit for bit."""
+    import torch
+    from paper_2405_01713_amd import bdfx
+    w = W.make_workload("mixed_s9_s53_1m", 150)
+    integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"],
+                            cell_mech=w["cell_mech"], scheduler=1, lu_precision=32, lockstep=3)
+    y0 = integ.y.clone()
+    integ.outer_loop(2, w["t_out"], 5, w["perturb"])
+    torch.cuda.synchronize()
+    y_eager, st_eager = integ.state(), integ.cell_stats()
+    assert np.all(st_eager["status"] == 0)
+    g = integ.capture_outer_loop(2, w["t_out"], 5, w["perturb"])
+    for rep in range(3):
+        integ.y.copy_(y0)
+        integ.status.fill_(7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(integ.state(), y_eager), f"replay {rep}"
+        assert np.array_equal(integ.cell_stats(), st_eager), f"replay {rep}"
+    integ.close()
+
+
+def test_lockstep_forcing_and_per_species_atol(oracle, parity):
+    w = W.make_workload("s21_r84_262k", 96)
+    rng = np.random.default_rng(12)
+    F = rng.uniform(-1.0, 1.0, w["y0"].shape) * 1e2
+    atol = np.geomspace(1e-12, 1e-9, 21)
+    w = dict(w, F=F, atol=atol)
+    import torch
+    from paper_2405_01713_amd import bdfx
+    integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], atol, T=w["T"], forcing=F,
+                            scheduler=0, lockstep=4)
+    integ.integrate(0.0, w["t_out"])
+    torch.cuda.synchronize()
+    y, st = integ.state(), integ.cell_stats()
+    integ.close()
+    yo, sto = oracle.integrate(w["mechs"], w["y0"], 0.0, w["t_out"], w["rtol"], atol, T=w["T"],
+                               F=F, lockstep=4)
+    assert np.all(st["status"] == 0) and np.all(sto["status"] == 0)
+    parity(y, yo, w, "lock-step forcing")
