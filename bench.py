@@ -712,6 +712,9 @@ def main():
                            mean_nst=float(st["nst"].mean()), mean_nfe=float(st["nfe"].mean()),
                            mean_nsetups=float(st["nsetups"].mean()), alg_flops=F,
                            tuning=r["tuning"],
+                           # no positivity constraint is imposed: report how far below 0 it went
+                           min_y=float(r["y"].min()),
+                           n_below_minus_atol=int(np.sum(r["y"] < -np.asarray(w["atol"]))),
                            _y=r["y"])
 
     cpu = None
