@@ -269,6 +269,19 @@ def _timed_events(fn, stream, steps, warmup):
     return float(np.median([a.elapsed_time(b) for a, b in ev]))
 
 
+def _invariant_drift(w, y):
+    """max over cells of |sum_i w_i y_i - sum_i w_i y0_i| (species weights of
+    each cell's mechanism)."""
+    cm = w["cell_mech"] if w.get("cell_mech") is not None else np.zeros(len(y), dtype=int)
+    drift = 0.0
+    for k, m in enumerate(w["mechs"]):
+        sel = cm == k
+        S = m["n_species"]
+        d = np.abs(y[sel, :S] @ m["w"] - w["y0"][sel, :S] @ m["w"])
+        drift = max(drift, float(d.max()) if d.size else 0.0)
+    return drift
+
+
 def _errors(y, yo, rtol, atol):
     """max |dy| / (|y_o| + atol) and max |dy| / (rtol |y_o| + atol) (error-weight units)."""
     dy = np.abs(y - yo)
@@ -715,6 +728,8 @@ def main():
                            # no positivity constraint is imposed: report how far below 0 it went
                            min_y=float(r["y"].min()),
                            n_below_minus_atol=int(np.sum(r["y"] < -np.asarray(w["atol"]))),
+                           # the linear invariant sum_i w_i y_i (exact with the FP64 solve)
+                           invariant_drift=_invariant_drift(w, r["y"]),
                            _y=r["y"])
 
     cpu = None
