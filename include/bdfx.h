@@ -146,7 +146,9 @@ typedef struct {
                               Jacobian, isothermal mechanisms, no step recording; one wave
                               per cell, so the batch's LDS (cells x the per-wave area) must
                               fit 64 KiB, else bdfx_bind() fails with BDFX_EUNSUPPORTED.
-                              The launch shape is fixed (bdfx_autotune() keeps it). */
+                              The launch shape is fixed: one block of this many waves per
+                              batch; bdfx_autotune() times nothing and reports it, and
+                              bdfx_set_tuning() does not change it. */
 } bdfx_options;
 
 #define BDFX_JAC_ANALYTIC 0

@@ -525,6 +525,11 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
   // lock-step: one block per batch, one wave per cell of it, tables in LDS,
   // and the batch's reduction slots after the waves' areas
   const int lock = ctx->opt.lockstep;
+  if (lock > 0) {  // the one shape of the lock-step kernels, as reported by bdfx_get_tuning
+    b.waves_per_block = lock;
+    b.waves_per_simd = 0;
+    b.queue_chunk = 1;
+  }
   const int waves = lock > 0 ? lock : std::max(b.waves_per_block, 1);
   const size_t lock_bytes = lock > 0 ? (2 * bdfx::kMaxBatch + 2) * 8 : 0;
   b.cfg.block = bdfx::kWave * waves;
@@ -696,6 +701,10 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
   if (!(t_out > t0) || !std::isfinite(t0) || !std::isfinite(t_out))
     return fail(ctx, BDFX_EINVAL, "need finite t_out > t0");
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  if (ctx->opt.lockstep > 0) {  // lock-step kernels have one launch shape: nothing to time
+    for (size_t bi = 0; bi < ctx->bins.size() && out; ++bi) out[bi] = tuning_of(ctx->bins[bi]);
+    return BDFX_OK;
+  }
   const bool fp32 = ctx->opt.lu_precision == 32;
   const bool queue = ctx->opt.scheduler == BDFX_SCHED_QUEUE;
   const int64_t ns = sample_cells > 0 ? std::min(sample_cells, ctx->tune_cells) : ctx->tune_cells;

@@ -136,3 +136,14 @@ def test_lockstep_forcing_and_per_species_atol(oracle, parity):
                                F=F, lockstep=4)
     assert np.all(st["status"] == 0) and np.all(sto["status"] == 0)
     parity(y, yo, w, "lock-step forcing")
+
+
+def test_lockstep_reports_its_launch_shape():
+    from paper_2405_01713_amd import bdfx
+    w = W.make_workload("s21_r84_262k", 40)
+    integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"], scheduler=1,
+                            lockstep=4, waves_per_block=2, queue_chunk=4)
+    for t in (integ.tuning(), integ.autotune(0.0, w["t_out"])):
+        assert t[0]["waves_per_block"] == 4 and t[0]["cells_per_wave"] == 1
+        assert t[0]["queue_chunk"] == 1 and t[0]["tables"] == 1 and t[0]["sample_cells"] == 0
+    integ.close()
