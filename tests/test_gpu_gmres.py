@@ -158,3 +158,15 @@ def test_gmres_graph_replay():
         assert np.array_equal(integ.state(), y_eager), f"replay {rep}"
         assert np.array_equal(integ.cell_stats(), st_eager), f"replay {rep}"
     integ.close()
+
+
+def test_gmres_largest_size_all_lanes(oracle):
+    """64 species, 10 Krylov vectors: every lane holds a species, and the
+    Krylov area is at its largest."""
+    m = W.synthetic_mechanism(64, 150, 5)
+    c = W.cell_states(m, 64, seed=8)
+    w = dict(mechs=[m], y0=c["y0"], T=c["T"], rtol=1e-6, atol=1e-10, t_out=1e-8)
+    y, st, _ = _gpu(w, 10, scheduler=1)
+    yo, sto = _oracle(oracle, w, 10)
+    assert np.all(st["status"] == 0) and np.all(sto["status"] == 0)
+    assert_parity_global(y, yo, w, oracle, "gmres S=64")

@@ -147,3 +147,16 @@ def test_lockstep_reports_its_launch_shape():
         assert t[0]["waves_per_block"] == 4 and t[0]["cells_per_wave"] == 1
         assert t[0]["queue_chunk"] == 1 and t[0]["tables"] == 1 and t[0]["sample_cells"] == 0
     integ.close()
+
+
+def test_lockstep_largest_batch_small_system(oracle, parity):
+    """Robertson (3 species) in batches of 16 cells, the largest batch: 1,024
+    threads per block; 100 cells leave a short last batch of 4."""
+    w = W.make_workload("robertson_4k", 100)
+    y, st = _gpu(w, lockstep=16, scheduler=1)
+    yo, sto = _oracle(oracle, w, 16)
+    assert np.all(st["status"] == 0) and np.all(sto["status"] == 0)
+    parity(y, yo, w, "lock-step B16")
+    nst = st["nst"]
+    for k in range(0, 100, 16):
+        assert np.all(nst[k:k + 16] == nst[k])
