@@ -1064,16 +1064,24 @@ void orc_integrate_batch(int64_t N, const orc_mech *mechs, const int32_t *cell_m
  * outside a block being zero).  The batch succeeds or fails as a whole and
  * every cell of it receives the batch's statistics.  Direct solver with the
  * analytic Jacobian only.  T, kscale, F and y are the arrays of
- * orc_integrate_batch.  Returns the batch status, or -100 for arguments
- * outside these limits. */
+ * orc_integrate_batch.  Returns the batch status.  Arguments outside these
+ * limits (or a mechanism too large for the oracle, as in
+ * orc_integrate_cell) give every cell of the batch status ORC_NONFINITE
+ * with y unchanged. */
 int32_t orc_integrate_lockstep(const orc_mech *m, const orc_opts *o, int32_t nb,
                                const int64_t *cells, const double *T, const double *kscale,
                                int32_t ldk, const double *F, int32_t ldy, double t0, double tout,
                                double *y, orc_stats *stats) {
   const int thermal = m->cv != NULL;
   const int S = m->n_species + thermal, R = m->n_reactions;
-  if (nb < 1 || nb > ORC_MAXB || S > ORC_MAXS || R > 4096 || o->jac_dq || o->gmres_maxl > 0)
-    return -100;
+  if (nb < 1 || nb > ORC_MAXB || S > ORC_MAXS || R > 4096 || o->jac_dq || o->gmres_maxl > 0) {
+    for (int b = 0; b < nb; ++b) {
+      memset(&stats[cells[b]], 0, sizeof(orc_stats));
+      stats[cells[b]].t_reached = t0;
+      stats[cells[b]].status = ORC_NONFINITE;
+    }
+    return ORC_NONFINITE;
+  }
   double *yb = malloc(sizeof(double) * (size_t)nb * S);
   double *kf = malloc(sizeof(double) * (size_t)nb * R);
   double *kr = malloc(sizeof(double) * (size_t)nb * R);
