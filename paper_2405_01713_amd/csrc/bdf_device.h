@@ -1106,24 +1106,27 @@ __device__ int gmres(const MechDev &m, const Lds &L, const Grp<G> &W, double y, 
   const int ld = maxl + 1;  // Hessenberg column stride
   const bool own = W.lane < n;
   const int li = own ? W.lane : 0;
+  const double rw = own ? 1.0 / ewt : 0.0;  // S2^{-1} (one division per solve)
   const double r0 = own ? ewt * b : 0.0;  // b~ = S1 b, the residual of x = 0
   const double beta = W.uni(sqrt(W.template sum<NR>(r0 * r0)));
   x = 0.0;
   if (beta <= delta) return 0;
   wave_lds_sync();
-  if (own) kb[K.V + li] = r0 / beta;
+  if (own) kb[K.V + li] = r0 * W.uni(rcp(beta));
   double gl = beta;  // last entry of the rotated right-hand side
   double rho = beta;
   int k = 0;
   for (int l = 0; l < maxl; ++l) {
     wave_lds_sync();
-    // w = A~ V_l = S1 (v - gamma J v) with v = S2^{-1} V_l
+    // w = A~ V_l = S1 (v - gamma J v) with v = S2^{-1} V_l; sigma = 1 / ||v||
+    // and J v = (f(y + sigma v) - f(y)) ||v||
     const double vl = own ? kb[K.V + l * S + li] : 0.0;
-    const double v = own ? vl / ewt : 0.0;
-    const double sigma = W.uni(1.0 / sqrt(wrms2<S>(W, v, ewt, inv_n)));
+    const double v = vl * rw;
+    const double vn = W.uni(sqrt(wrms2<S>(W, v, ewt, inv_n)));
+    const double sigma = W.uni(rcp(vn));
     const double fp = rhs<ABC, TH>(m, L, W, y + sigma * v, Fi, ns);
     nli++;
-    double w = own ? ewt * (v - gamma * ((fp - fy) / sigma)) : 0.0;
+    double w = own ? ewt * (v - gamma * ((fp - fy) * vn)) : 0.0;
     // modified Gram-Schmidt: column l of the Hessenberg matrix
     for (int j = 0; j <= l; ++j) {
       const double vj = own ? kb[K.V + j * S + li] : 0.0;
@@ -1134,14 +1137,13 @@ __device__ int gmres(const MechDev &m, const Lds &L, const Grp<G> &W, double y, 
     const double hn = W.uni(sqrt(W.template sum<NR>(w * w)));
     wave_lds_sync();
     // the earlier rotations, then the one that zeroes the subdiagonal entry
+    // (each store goes to an entry no later read of the loop touches)
     double a = kb[K.H + l * ld];
     for (int j = 0; j < l; ++j) {
       const double c = kb[K.cs + j], sn = kb[K.sn + j], a1 = kb[K.H + l * ld + j + 1];
       const double top = c * a + sn * a1;
       a = -sn * a + c * a1;
-      wave_lds_sync();
       if (W.lane == 0) kb[K.H + l * ld + j] = top;
-      wave_lds_sync();
     }
     const double r = W.uni(hypot(a, hn));
     if (!(r > 0.0)) break;  // singular Hessenberg column: keep k columns
@@ -1159,7 +1161,7 @@ __device__ int gmres(const MechDev &m, const Lds &L, const Grp<G> &W, double y, 
     if (rho <= delta) break;
     if (l + 1 < maxl) {
       if (!(hn > 0.0)) break;
-      if (own) kb[K.V + (l + 1) * S + li] = w / hn;
+      if (own) kb[K.V + (l + 1) * S + li] = w * W.uni(rcp(hn));
     }
   }
   // back substitution for the coefficients, then x = S2^{-1} sum_j c_j V_j
@@ -1174,7 +1176,7 @@ __device__ int gmres(const MechDev &m, const Lds &L, const Grp<G> &W, double y, 
   }
   double t = 0.0;
   for (int j = 0; j < k; ++j) t += kb[K.c + j] * (own ? kb[K.V + j * S + li] : 0.0);
-  x = own ? t / ewt : 0.0;
+  x = t * rw;
   wave_lds_sync();
   if (rho <= delta) return 0;
   return rho < beta ? 1 : 2;
