@@ -1116,14 +1116,16 @@ __device__ int gmres(const MechDev &m, const Lds &L, const Grp<G> &W, double y, 
   double gl = beta;  // last entry of the rotated right-hand side
   double rho = beta;
   int k = 0;
+  // every basis vector has unit 2-norm in the scaled space, so v = S2^{-1} V_l
+  // has ||v||_wrms = 1 / sqrt(n): sigma = sqrt(n) without a reduction
+  const double vn = W.uni(sqrt(inv_n));
+  const double sigma = W.uni(sqrt(static_cast<double>(n)));
   for (int l = 0; l < maxl; ++l) {
     wave_lds_sync();
     // w = A~ V_l = S1 (v - gamma J v) with v = S2^{-1} V_l; sigma = 1 / ||v||
     // and J v = (f(y + sigma v) - f(y)) ||v||
     const double vl = own ? kb[K.V + l * S + li] : 0.0;
     const double v = vl * rw;
-    const double vn = W.uni(sqrt(wrms2<S>(W, v, ewt, inv_n)));
-    const double sigma = W.uni(rcp(vn));
     const double fp = rhs<ABC, TH>(m, L, W, y + sigma * v, Fi, ns);
     nli++;
     double w = own ? ewt * (v - gamma * ((fp - fy) * vn)) : 0.0;
