@@ -1147,7 +1147,7 @@ __device__ int gmres(const MechDev &m, const Lds &L, const Grp<G> &W, double y, 
       a = -sn * a + c * a1;
       if (W.lane == 0) kb[K.H + l * ld + j] = top;
     }
-    const double r = W.uni(hypot(a, hn));
+    const double r = W.uni(sqrt(fma(a, a, hn * hn)));  // a and hn are O(beta): no overflow
     if (!(r > 0.0)) break;  // singular Hessenberg column: keep k columns
     const double c = W.uni(a / r), sn = W.uni(hn / r);
     wave_lds_sync();
