@@ -30,11 +30,14 @@ def test_dq_parity(oracle, parity, lu):
                                T=w["T"], jac_dq=True)
     assert np.all(st["status"] == 0) and np.all(sto["status"] == 0)
     parity(y, yo, w, f"dq lu{lu}")
-    # n + 1 right-hand sides per setup, as in the oracle
+    # n + 1 right-hand sides per setup, as in the oracle.  Mean work counts of
+    # adaptive runs move with round-off: the oracle against itself with inputs
+    # perturbed by 1e-15 moves them by up to 2.5 % here.  6 % still fails a
+    # count of n instead of n + 1 per setup (10 % of the remainder).
     extra = st["nfe"] - 22 * st["nsetups"]
     extra_o = sto["nfe"] - 22 * sto["nsetups"]
-    assert abs(extra.mean() / extra_o.mean() - 1.0) < 0.03
-    assert abs(st["nfe"].mean() / sto["nfe"].mean() - 1.0) < 0.03
+    assert abs(extra.mean() / extra_o.mean() - 1.0) < 0.06
+    assert abs(st["nfe"].mean() / sto["nfe"].mean() - 1.0) < 0.06
 
 
 def test_dq_non_isothermal(oracle):
