@@ -1022,16 +1022,26 @@ __device__ __forceinline__ double inv_solve(const Lds &L, const Grp<G> &W, doubl
   if (W.lane < S) bb[W.lane] = static_cast<LT>(b);
   wave_lds_sync();
   const int lr = W.lane < S ? W.lane : 0;
-  // three partial sums (column c into sum c mod 3, added in a fixed order)
-  // shorten the dependent FMA chain: -2.5 % time at 21 species, -3.7 % at 53
-  LT acc0 = 0, acc1 = 0, acc2 = 0;
+  if constexpr (sizeof(LT) == 4) {
+    // FP32 inverse: three partial sums (column c into sum c mod 3, added in a
+    // fixed order) shorten the dependent FMA chain, and the unrolled loop
+    // issues the LDS reads early: -2.6 % time at 21 species, -3.7 % at 53.
+    // (With the FP64 inverse the same form raises register use and occupancy
+    // drops; the single chain is faster there.)
+    LT acc0 = 0, acc1 = 0, acc2 = 0;
 #pragma unroll
-  for (int c = 0; c < S; c += 3) {
-    acc0 = fma(inv[c * S + lr], bb[c], acc0);
-    if (c + 1 < S) acc1 = fma(inv[(c + 1) * S + lr], bb[c + 1], acc1);
-    if (c + 2 < S) acc2 = fma(inv[(c + 2) * S + lr], bb[c + 2], acc2);
+    for (int c = 0; c < S; c += 3) {
+      acc0 = fma(inv[c * S + lr], bb[c], acc0);
+      if (c + 1 < S) acc1 = fma(inv[(c + 1) * S + lr], bb[c + 1], acc1);
+      if (c + 2 < S) acc2 = fma(inv[(c + 2) * S + lr], bb[c + 2], acc2);
+    }
+    return W.lane < S ? static_cast<double>((acc0 + acc1) + acc2) : 0.0;
+  } else {
+    LT acc = 0;
+#pragma unroll
+    for (int c = 0; c < S; ++c) acc = fma(inv[c * S + lr], bb[c], acc);
+    return W.lane < S ? static_cast<double>(acc) : 0.0;
   }
-  return W.lane < S ? static_cast<double>((acc0 + acc1) + acc2) : 0.0;
 }
 
 // ---------------------------------------------------------------------------
