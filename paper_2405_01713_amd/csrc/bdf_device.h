@@ -1014,7 +1014,8 @@ __device__ __forceinline__ int gj_invert(LT (&a)[S], const Grp<G> &W, const Lds 
 }
 
 // x = M^{-1} b with the inverse in LDS; lane i passes b_i and gets x_i.
-template <int S, typename LT, int G>
+// SPLIT: three partial sums (FP32 inverse of isothermal kernels, see below).
+template <int S, typename LT, bool SPLIT, int G>
 __device__ __forceinline__ double inv_solve(const Lds &L, const Grp<G> &W, double b) {
   const LT *inv = reinterpret_cast<const LT *>(L.fac);
   LT *bb = reinterpret_cast<LT *>(L.yb);
@@ -1022,12 +1023,12 @@ __device__ __forceinline__ double inv_solve(const Lds &L, const Grp<G> &W, doubl
   if (W.lane < S) bb[W.lane] = static_cast<LT>(b);
   wave_lds_sync();
   const int lr = W.lane < S ? W.lane : 0;
-  if constexpr (sizeof(LT) == 4) {
-    // FP32 inverse: three partial sums (column c into sum c mod 3, added in a
-    // fixed order) shorten the dependent FMA chain, and the unrolled loop
-    // issues the LDS reads early: -2.6 % time at 21 species, -3.7 % at 53.
-    // (With the FP64 inverse the same form raises register use and occupancy
-    // drops; the single chain is faster there.)
+  if constexpr (SPLIT) {
+    // three partial sums (column c into sum c mod 3, added in a fixed order)
+    // shorten the dependent FMA chain, and the unrolled loop issues the LDS
+    // reads early: -2.6 % time at 21 species, -3.7 % at 53 with the FP32
+    // inverse.  With the FP64 inverse, or in the non-isothermal kernels, the
+    // same form raises register pressure and runs slower.
     LT acc0 = 0, acc1 = 0, acc2 = 0;
 #pragma unroll
     for (int c = 0; c < S; c += 3) {
@@ -1451,7 +1452,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
           if (lret != 0) ncfl++;
           if (lret == 2 || (lret == 1 && mit > 0)) break;
         } else {
-          delta = inv_solve<S, LT>(L, W, -Gi);
+          delta = inv_solve<S, LT, sizeof(LT) == 4 && !TH>(L, W, -Gi);
           if (cfac != 1.0) delta *= cfac;
         }
         e += delta;
@@ -1784,7 +1785,7 @@ __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int 
       newton_matrix<S, double>(a, m, L, W1, yn, gamma, true);
       gj_invert<S, double>(a, W1, L);
     }
-    const double mu = own ? inv_solve<S, double>(L, W1, eb) : 0.0;
+    const double mu = own ? inv_solve<S, double, false>(L, W1, eb) : 0.0;
     adj_scatter(m, L, vb, pb, li, yn, mu, gamma, false);
     // a = zp_0 - zp_1 / l_1
     zb[0] += mu;
