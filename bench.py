@@ -37,12 +37,14 @@ def kernel_source_hash() -> str:
     reported only while this matches."""
     import hashlib
     from paper_2405_01713_amd import build as B
-    h = hashlib.sha256(" ".join(B.CFLAGS).encode())
+    # flags without the checkout's location, so that copies of the tree agree
+    h = hashlib.sha256(" ".join(f.replace(B.ROOT, "<root>") for f in B.CFLAGS).encode())
     csrc = os.path.join(ROOT, "paper_2405_01713_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode() + fh.read())
+    files = [os.path.join(csrc, f) for f in sorted(os.listdir(csrc)) if f.endswith((".hip", ".h"))]
+    files.append(os.path.join(ROOT, "include", "bdfx.h"))
+    for path in files:
+        with open(path, "rb") as fh:
+            h.update(os.path.basename(path).encode() + fh.read())
     return h.hexdigest()[:16]
 
 
