@@ -45,3 +45,41 @@ def test_errors_without_device_are_loud():
         pass
     with pytest.raises(bdfx.BdfxError):
         bdfx.bdfx_create(0, 0)
+
+
+def _struct_fields(name):
+    """Field names of `typedef struct { ... } name;` in include/bdfx.h, in order
+    (arrays by their name)."""
+    src = open(os.path.join(ROOT, "include", "bdfx.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    end = re.search(r"\}\s*" + name + r"\s*;", src)
+    assert end, name
+    start = src.rfind("typedef struct {", 0, end.start())
+    body = src[start + len("typedef struct {"):end.start()]
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        # "int64_t nst, nfe" / "const double *atol" / "int64_t status_count[11]"
+        names = decl.split(",")
+        first = re.findall(r"\**\s*([A-Za-z_]\w*)\s*(?:\[\d+\])?\s*$", names[0])
+        fields.append(first[0])
+        for n in names[1:]:
+            fields.append(re.findall(r"([A-Za-z_]\w*)", n)[0])
+    return fields
+
+
+@pytest.mark.parametrize("cname,pyname", [("bdfx_options", "Options"), ("bdfx_mech_desc", "MechDesc"),
+                                          ("bdfx_summary", "Summary"), ("bdfx_tuning", "Tuning")])
+def test_binding_structs_follow_the_header(cname, pyname):
+    """The ctypes structures of the binding list the header's fields, by name,
+    in the header's order."""
+    from paper_2405_01713_amd import bdfx
+    assert [n for n, _ in getattr(bdfx, pyname)._fields_] == _struct_fields(cname)
+
+
+def test_cell_stats_dtype_follows_the_header():
+    from paper_2405_01713_amd import bdfx
+    assert list(bdfx.STATS_DTYPE.names) == _struct_fields("bdfx_cell_stats")
+    assert bdfx.STATS_DTYPE.itemsize == 56
