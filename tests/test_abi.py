@@ -83,3 +83,22 @@ def test_cell_stats_dtype_follows_the_header():
     from paper_2405_01713_amd import bdfx
     assert list(bdfx.STATS_DTYPE.names) == _struct_fields("bdfx_cell_stats")
     assert bdfx.STATS_DTYPE.itemsize == 56
+
+
+@pytest.mark.parametrize("cname,pyname", [("orc_opts", "Opts"), ("orc_stats", "Stats"),
+                                          ("orc_mech", "Mech"), ("orc_record", "Record")])
+def test_oracle_binding_structs_follow_its_source(cname, pyname):
+    """Same check for the oracle's structures (test infrastructure)."""
+    from oracle import oracle as O
+    src = open(os.path.join(ROOT, "oracle", "bdf_oracle.c")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    end = re.search(r"\}\s*" + cname + r"\s*;", src)
+    start = src.rfind("typedef struct {", 0, end.start())
+    fields = []
+    for decl in src[start + len("typedef struct {"):end.start()].split(";"):
+        decl = decl.strip()
+        if decl:
+            parts = decl.split(",")
+            fields.append(re.findall(r"([A-Za-z_]\w*)\s*(?:\[\d+\])?\s*$", parts[0])[0])
+            fields += [re.findall(r"([A-Za-z_]\w*)", p)[0] for p in parts[1:]]
+    assert [n for n, _ in getattr(O, pyname)._fields_] == fields
