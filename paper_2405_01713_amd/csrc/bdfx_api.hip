@@ -83,7 +83,7 @@ constexpr int64_t kTuneCells = 16384;
 // persistent grids
 constexpr int64_t kMaxWavesPerCu = 32;
 // blocks of the typical-value extremes pass per mechanism (partials in the workspace)
-constexpr int kExtMaxBlocks = 1024;
+constexpr int kExtMaxBlocks = 256;
 
 struct bdfx_mech_s {
   bdfx_ctx ctx = nullptr;

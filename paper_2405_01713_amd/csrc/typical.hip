@@ -4,11 +4,12 @@
 // Two kernels per call.  k_extremes streams the state rows of one mechanism
 // once (the HBM-bound part): a wave covers floor(64 / S) cells per pass, lane
 // l holding species l mod S of cell l / S, so the rows of consecutive cells
-// are read as one contiguous run; each block leaves its per-species extremes
-// in a partial array.  k_typical combines the partials of every mechanism
-// and writes the tolerances.  Minimum and maximum are exact, so the result
-// does not depend on the order in which cells are visited.  A NaN entry
-// makes both extremes NaN (as a plain minimum over the values would).
+// are read as one contiguous run; each block (16 waves, at most 256 blocks per
+// mechanism) leaves its per-species extremes in a partial array.  k_typical
+// combines the partials of every mechanism and writes the tolerances.  Minimum
+// and maximum are exact, so the result does not depend on the order in which
+// cells are visited.  A NaN entry makes both extremes NaN (as a plain minimum
+// over the values would).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -18,7 +19,7 @@
 
 namespace bdfx {
 
-constexpr int kExtBlock = 256;  // threads per k_extremes block
+constexpr int kExtBlock = 1024;  // threads per k_extremes block
 constexpr int kExtUnroll = 4;   // passes per loop iteration (loads in flight)
 
 __device__ __forceinline__ double lo_of(double a, double v) { return (v < a || v != v) ? v : a; }
@@ -80,46 +81,48 @@ struct TypicalArgs {
   int64_t part_off[BDFX_MAX_MECH];   // offset (doubles) of its partials
 };
 
-// One block per mechanism: kTypGroups groups of 64 threads split the partial
-// blocks (thread (g, i) takes blocks g, g + kTypGroups, ... for species i),
-// the groups' extremes are combined in LDS, then
+// One block per mechanism of kTypThreads threads: thread t takes species
+// t mod S and every (kTypThreads / S)-th partial block from t / S on, so all
+// threads work whatever S is; the chunks' extremes are combined in LDS, then
 // typ = 0.5 (min + max), atol = (typ > 0 ? typ : 1) eta.  Entries beyond the
 // mechanism's species (and all of a mechanism without cells) get typ = 0,
-// atol = eta.
-constexpr int kTypGroups = 16;
+// atol = eta.  Minimum and maximum are exact: the partition changes no bit.
+constexpr int kTypThreads = 1024;
 
-__global__ void __launch_bounds__(kTypGroups * kWave) k_typical(TypicalArgs a, const double *part,
-                                                               double eta, double *atol, double *typ) {
+__global__ void __launch_bounds__(kTypThreads) k_typical(TypicalArgs a, const double *part,
+                                                         double eta, double *atol, double *typ) {
 #pragma clang fp contract(off)
-  __shared__ double lo_s[kTypGroups][kWave], hi_s[kTypGroups][kWave];
+  __shared__ double lo_s[kTypThreads], hi_s[kTypThreads];
   const int m = blockIdx.x;
-  const int g = threadIdx.x / kWave, i = threadIdx.x % kWave;
+  const int S = a.S[m];
+  const int t = threadIdx.x;
+  const int nchunk = kTypThreads / S;  // S <= 64: at least 16 chunks
+  const int i = t % S, g = t / S;
   const double *pm = part + a.part_off[m];
   double l = __builtin_huge_val(), h = -__builtin_huge_val();
-  if (i < a.S[m]) {
+  if (g < nchunk) {
 #pragma unroll 4
-    for (int b = g; b < a.nblk[m]; b += kTypGroups) {
+    for (int b = g; b < a.nblk[m]; b += nchunk) {
       l = lo_of(l, pm[(static_cast<int64_t>(b) * 2) * kWave + i]);
       h = hi_of(h, pm[(static_cast<int64_t>(b) * 2 + 1) * kWave + i]);
     }
   }
-  lo_s[g][i] = l;
-  hi_s[g][i] = h;
+  lo_s[t] = l;
+  hi_s[t] = h;
   __syncthreads();
-  if (g == 0) {
-    for (int k = 1; k < kTypGroups; ++k) {
-      l = lo_of(l, lo_s[k][i]);
-      h = hi_of(h, hi_s[k][i]);
-    }
-    for (int j = i; j < a.ldt; j += kWave) {
-      double t = 0.0, at = eta;
-      if (j < a.S[m] && a.nblk[m] > 0) {  // j == i: ldt <= 64
-        t = 0.5 * (l + h);
-        at = (t > 0.0 ? t : 1.0) * eta;
+  if (t < a.ldt) {  // ldt <= 64: thread t writes entry t
+    double tv = 0.0, at = eta;
+    if (t < S && a.nblk[m] > 0) {
+      double lt = lo_s[t], ht = hi_s[t];
+      for (int k = 1; k < nchunk; ++k) {
+        lt = lo_of(lt, lo_s[k * S + t]);
+        ht = hi_of(ht, hi_s[k * S + t]);
       }
-      atol[static_cast<int64_t>(m) * a.ldt + j] = at;
-      if (typ) typ[static_cast<int64_t>(m) * a.ldt + j] = t;
+      tv = 0.5 * (lt + ht);
+      at = (tv > 0.0 ? tv : 1.0) * eta;
     }
+    atol[static_cast<int64_t>(m) * a.ldt + t] = at;
+    if (typ) typ[static_cast<int64_t>(m) * a.ldt + t] = tv;
   }
 }
 
@@ -154,7 +157,7 @@ hipError_t bdfx_launch_typical(int n_mech, int ldt, const int32_t *S, const int3
     a.nblk[m] = nblk[m];
     a.part_off[m] = part_off[m];
   }
-  hipLaunchKernelGGL(bdfx::k_typical, dim3(n_mech), dim3(bdfx::kTypGroups * bdfx::kWave), 0, s, a,
+  hipLaunchKernelGGL(bdfx::k_typical, dim3(n_mech), dim3(bdfx::kTypThreads), 0, s, a,
                      part, eta, atol, typ);
   return hipGetLastError();
 }
