@@ -20,7 +20,7 @@
 namespace bdfx {
 
 constexpr int kExtBlock = 1024;  // threads per k_extremes block
-constexpr int kExtUnroll = 4;   // passes per loop iteration (loads in flight)
+constexpr int kExtUnroll = 8;   // passes per loop iteration (loads in flight)
 
 __device__ __forceinline__ double lo_of(double a, double v) { return (v < a || v != v) ? v : a; }
 __device__ __forceinline__ double hi_of(double a, double v) { return (v > a || v != v) ? v : a; }
