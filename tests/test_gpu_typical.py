@@ -46,6 +46,29 @@ def test_typical_values_bit_exact_single(oracle, n):
     assert np.array_equal(typ, to, equal_nan=True)
 
 
+@pytest.mark.parametrize("S", [1, 64])
+def test_typical_values_species_limits(oracle, S):
+    """One species (a pass covers 64 cells; the combine splits the partials
+    1,024 ways) and 64 species (one cell per pass; 16 ways), over a cell
+    count that fills the block cap and leaves a ragged last pass."""
+    if S == 1:
+        m = dict(name="sink_s1", n_species=1, n_reactions=1,
+                 reac=np.array([[0, -1, -1]], dtype=np.int32),
+                 prod=np.full((1, 3), -1, dtype=np.int32), lnA=np.zeros(1), EaR=np.zeros(1),
+                 lnK=None, w=np.ones(1))
+    else:
+        m = W.unimolecular_mechanism(64, 64, 3)
+    n = 300007
+    rng = np.random.default_rng(S)
+    y = rng.uniform(-0.1, 1.0, (n, S))
+    y[rng.integers(0, n, 5), rng.integers(0, S, 5)] = rng.uniform(1.0, 2.0, 5)
+    integ = _integrator(dict(mechs=[m], y0=y, rtol=1e-6, atol=1e-10), scheduler=1)
+    typ = _typical_gpu(integ, 1e-10)
+    integ.close()
+    to, _ = oracle.typical_atol(y, 1e-10, [S])
+    assert np.array_equal(typ, to)
+
+
 def test_typical_values_bit_exact_mixed(oracle):
     w = W.make_workload("mixed_s9_s53_1m", 3001)
     integ = _integrator(w, scheduler=0)
