@@ -61,14 +61,28 @@ __global__ void __launch_bounds__(kExtBlock) k_extremes(const double *y, int ldy
   lo_s[threadIdx.x] = lo;
   hi_s[threadIdx.x] = hi;
   __syncthreads();
-  if (threadIdx.x < S) {
-    // lanes sp, sp + S, ... of every wave hold species sp
+  // Two-level combine.  First thread t < (waves per block) S takes wave
+  // t / S, species t mod S, over that wave's lanes holding the species
+  // (sp, sp + S, ...); then thread t < S takes species t over the waves.
+  constexpr int kExtWaves = kExtBlock / kWave;
+  __shared__ double lo_w[kExtWaves * kWave], hi_w[kExtWaves * kWave];
+  if (threadIdx.x < kExtWaves * S) {
+    const int w = threadIdx.x / S, s = threadIdx.x - w * S;
     double l = __builtin_huge_val(), h = -__builtin_huge_val();
-    for (int w = 0; w < kExtBlock / kWave; ++w)
-      for (int k = 0; k < per; ++k) {
-        l = lo_of(l, lo_s[w * kWave + k * S + threadIdx.x]);
-        h = hi_of(h, hi_s[w * kWave + k * S + threadIdx.x]);
-      }
+    for (int k = 0; k < per; ++k) {
+      l = lo_of(l, lo_s[w * kWave + k * S + s]);
+      h = hi_of(h, hi_s[w * kWave + k * S + s]);
+    }
+    lo_w[threadIdx.x] = l;
+    hi_w[threadIdx.x] = h;
+  }
+  __syncthreads();
+  if (threadIdx.x < S) {
+    double l = __builtin_huge_val(), h = -__builtin_huge_val();
+    for (int w = 0; w < kExtWaves; ++w) {
+      l = lo_of(l, lo_w[w * S + threadIdx.x]);
+      h = hi_of(h, hi_w[w * S + threadIdx.x]);
+    }
     part[(static_cast<int64_t>(blockIdx.x) * 2) * kWave + threadIdx.x] = l;
     part[(static_cast<int64_t>(blockIdx.x) * 2 + 1) * kWave + threadIdx.x] = h;
   }
