@@ -97,10 +97,10 @@ struct TypicalArgs {
 
 // One block per mechanism of kTypThreads threads: thread t takes species
 // t mod S and every (kTypThreads / S)-th partial block from t / S on, so all
-// threads work whatever S is; the chunks' extremes are combined in LDS, then
-// typ = 0.5 (min + max), atol = (typ > 0 ? typ : 1) eta.  Entries beyond the
-// mechanism's species (and all of a mechanism without cells) get typ = 0,
-// atol = eta.  Minimum and maximum are exact: the partition changes no bit.
+// threads work whatever S is; the chunks' extremes are combined in LDS in two
+// levels, then typ = 0.5 (min + max), atol = (typ > 0 ? typ : 1) eta.  Entries
+// beyond the mechanism's species (and all of a mechanism without cells) get
+// typ = 0, atol = eta.  Minimum and maximum are exact: the partition changes no bit.
 constexpr int kTypThreads = 1024;
 
 __global__ void __launch_bounds__(kTypThreads) k_typical(TypicalArgs a, const double *part,
@@ -124,13 +124,30 @@ __global__ void __launch_bounds__(kTypThreads) k_typical(TypicalArgs a, const do
   lo_s[t] = l;
   hi_s[t] = h;
   __syncthreads();
+  // two-level combine: thread t < nq S takes species t mod S over chunks
+  // 8q .. 8q + 7 (q = t / S), then thread t < S over the nq groups
+  constexpr int kTypGroup = 8;
+  const int nq = (nchunk + kTypGroup - 1) / kTypGroup;  // nq S <= 1024 / 8 + 64
+  __shared__ double lo_q[kTypThreads / kTypGroup + kWave], hi_q[kTypThreads / kTypGroup + kWave];
+  if (t < nq * S) {
+    const int q = t / S, s = t - q * S;
+    const int k1 = (q + 1) * kTypGroup < nchunk ? (q + 1) * kTypGroup : nchunk;
+    double lq = __builtin_huge_val(), hq = -__builtin_huge_val();
+    for (int k = q * kTypGroup; k < k1; ++k) {
+      lq = lo_of(lq, lo_s[k * S + s]);
+      hq = hi_of(hq, hi_s[k * S + s]);
+    }
+    lo_q[t] = lq;
+    hi_q[t] = hq;
+  }
+  __syncthreads();
   if (t < a.ldt) {  // ldt <= 64: thread t writes entry t
     double tv = 0.0, at = eta;
     if (t < S && a.nblk[m] > 0) {
-      double lt = lo_s[t], ht = hi_s[t];
-      for (int k = 1; k < nchunk; ++k) {
-        lt = lo_of(lt, lo_s[k * S + t]);
-        ht = hi_of(ht, hi_s[k * S + t]);
+      double lt = lo_q[t], ht = hi_q[t];
+      for (int q = 1; q < nq; ++q) {
+        lt = lo_of(lt, lo_q[q * S + t]);
+        ht = hi_of(ht, hi_q[q * S + t]);
       }
       tv = 0.5 * (lt + ht);
       at = (tv > 0.0 ? tv : 1.0) * eta;
