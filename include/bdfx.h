@@ -149,12 +149,17 @@ typedef struct {
                               The launch shape is fixed: one block of this many waves per
                               batch; bdfx_autotune() times nothing and reports it, and
                               bdfx_set_tuning() does not change it. */
+  int32_t max_err_test_fails; /* error-test failures within one step that fail the cell with
+                                 BDFX_CELL_ERR_FAILURE (0 = 7); the cell keeps its last
+                                 accepted state and time (the accept/reject logic of Sec. 2) */
+  int32_t max_conv_fails;     /* Newton convergence failures within one step that fail the cell
+                                 with BDFX_CELL_CONV_FAILURE (0 = 10) */
 } bdfx_options;
 
 #define BDFX_JAC_ANALYTIC 0
 #define BDFX_JAC_DQ 1
 
-/* Per-cell statistics written by bdfx_integrate() (48 bytes, [N]). */
+/* Per-cell statistics written by bdfx_integrate() (56 bytes, [N]). */
 typedef struct {
   int32_t status;  /* BDFX_CELL_* */
   int32_t nst;     /* accepted steps */
@@ -196,10 +201,25 @@ const char *bdfx_last_error(bdfx_ctx ctx);
  * term lists from the stoichiometry).  Synchronous. */
 int bdfx_mech_create(bdfx_ctx ctx, const bdfx_mech_desc *desc, bdfx_mech *out);
 int bdfx_mech_destroy(bdfx_mech mech);
+/* Replace the mechanism's ln pre-exponential factors lnA_r (the parameters
+ * of the Arrhenius terms of Sec. 3.1 that bdfx_adjoint() differentiates) by
+ * d_lnA, a device array [R] of FP64 owned by the caller: one device-to-device
+ * copy enqueued on the context's stream (no allocation, no synchronisation),
+ * so that a bound context can integrate again with new parameters.  Later
+ * bdfx_integrate() calls on the stream use the new values.  Errors:
+ * BDFX_EINVAL for NULL arguments, BDFX_EHIP if the copy cannot be
+ * enqueued. */
+int bdfx_mech_set_lnA(bdfx_mech mech, const double *d_lnA);
 
 /* Fix the batch shape and options; *workspace_bytes receives the device
  * workspace size bdfx_bind() needs (queue counters, cell bins, adjoint
- * records).  mechs[m] is the mechanism of cells with cell_mech == m. */
+ * records).  mechs[m] is the mechanism of cells with cell_mech == m.
+ * Planning and binding separate all allocation from the integration, so that
+ * the device memory comes from the caller's pool once and later calls
+ * allocate nothing (the memory-pool lesson of Sec. 4.3.1).  Host-only.
+ * Errors: BDFX_EINVAL for n_cells < 1, n_mech outside 1..BDFX_MAX_MECH,
+ * NULL mechanisms or option values outside their documented ranges;
+ * BDFX_EUNSUPPORTED for option combinations the kernels do not provide. */
 int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *mechs,
               const bdfx_options *opts, size_t *workspace_bytes);
 
@@ -216,13 +236,25 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
  *   d_status    [N] out             per-cell BDFX_CELL_* status
  *   d_stats     [N] out or NULL     per-cell statistics
  * Reads d_cell_mech once (synchronously) to build the per-mechanism cell
- * bins in the workspace. */
+ * bins in the workspace.  The state stays where the application keeps it, in
+ * its cell-major ("CY", Sec. 4.1.2) array; no copy is made (Sec. 4.3.1 on
+ * device-resident data).  Errors: BDFX_EORDER before bdfx_plan();
+ * BDFX_EWORKSPACE if workspace_bytes is below the planned size; BDFX_EINVAL
+ * for NULL d_y / d_status / d_workspace, ldy below the largest state length,
+ * or a cell_mech entry outside 0..n_mech-1. */
 int bdfx_bind(bdfx_ctx ctx, void *d_workspace, size_t workspace_bytes, double *d_y, int32_t ldy,
               const int32_t *d_cell_mech, const double *d_T, const double *d_kscale,
               int32_t ldk, const double *d_forcing, int32_t *d_status,
               bdfx_cell_stats *d_stats);
 
-/* Integrate every bound cell from t0 to t_out (t_out > t0); enqueue only. */
+/* Integrate every bound cell from t0 to t_out (t_out > t0): one outer
+ * (splitting) step of Sec. 3.1, Eq. (7), for every cell's ODE system
+ * y' = R(y) + F by the BDF method of Sec. 2, Eq. (1), each cell with its own
+ * step size and order.  d_y holds y(t_out) afterwards (or the last accepted
+ * state of a failed cell, whose d_status entry is negative).  Enqueue only
+ * (no allocation, no synchronisation; capturable in a HIP graph).  Errors:
+ * BDFX_EINVAL unless t_out > t0 (both finite); BDFX_EORDER before
+ * bdfx_bind(); BDFX_EHIP if a launch fails. */
 int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out);
 
 /* Outer-step perturbation between splitting steps: for every cell and
@@ -252,7 +284,10 @@ int bdfx_typical_atol(bdfx_ctx ctx, double eta, double *d_typical);
 int bdfx_mech_set_weights(bdfx_mech mech, const double *weights);
 
 /* Sum the per-cell statistics of the last integrate; synchronises the
- * context's stream.  Requires d_stats bound. */
+ * context's stream.  Requires d_stats bound.  The right-hand-side counts are
+ * the per-cell work estimates an application can feed back into its load
+ * balancing (Sec. 4.1.1).  Errors: BDFX_EORDER before bdfx_bind() or without
+ * d_stats; BDFX_EHIP if the copy fails. */
 int bdfx_stats_summary(bdfx_ctx ctx, bdfx_summary *out);
 
 /* Discrete adjoint of the last bdfx_integrate() (which must have been run
@@ -265,6 +300,30 @@ int bdfx_stats_summary(bdfx_ctx ctx, bdfx_summary *out);
  * orders held fixed and each corrector solved exactly (Jacobians re-evaluated
  * at the recorded states).  Enqueue only. */
 int bdfx_adjoint(bdfx_ctx ctx, const double *d_ybar, double *d_y0bar, double *d_lnA_bar);
+
+/* Where bdfx_integrate() with record_steps > 0 leaves the step record in the
+ * bound workspace (byte offsets from d_workspace), for callers that inspect or
+ * checkpoint it.  For cell c (its index in d_y):
+ *   steps [N][cap][stride] FP64: accepted step n (0-based) of cell c, whose
+ *         mechanism has S state entries, holds the accepted state y_n in
+ *         entries 0..S-1, the step size h_n in entry S and
+ *         q_n + 256 * rebuilt_n in entry S+1, where q_n is the order the step
+ *         was taken with and rebuilt_n = 1 if the Nordsieck array was rebuilt
+ *         at order 1 (repeated error-test failures, Sec. 2) before it;
+ *   count [N] int32: accepted steps recorded;
+ *   hpad  [N] FP64: the initial step size, with which the step-size history
+ *         before the first step is padded;
+ *   y0    [N][stride] FP64: the state at t0.
+ * The record describes the frozen discrete map that bdfx_adjoint()
+ * differentiates (the step sequence of the run with each corrector solved
+ * exactly).  Host-only.  Errors: BDFX_EORDER before bdfx_bind() or without
+ * recording. */
+typedef struct {
+  int32_t cap;    /* recorded steps per cell (bdfx_options.record_steps) */
+  int32_t stride; /* doubles per recorded step (largest state length + 2) */
+  size_t off_steps, off_count, off_hpad, off_y0;
+} bdfx_record_layout;
+int bdfx_get_record_layout(bdfx_ctx ctx, bdfx_record_layout *out);
 
 /* Launch shape of the integrator for the cells of one mechanism. */
 typedef struct {

@@ -85,6 +85,8 @@ typedef struct {
   int32_t jac_dq;     /* 1: Jacobian by difference quotients (approaches 3A/3B), 0: analytic */
   int32_t gmres_maxl; /* 1..ORC_GMRES_MAXL: inexact Newton with GMRES of this Krylov dimension
                          (approaches 1A/1B); 0: modified Newton with a direct solve */
+  int32_t max_netf;   /* error-test failures in one step that fail the cell (0 = 7) */
+  int32_t max_ncf;    /* Newton convergence failures in one step that fail the cell (0 = 10) */
 } orc_opts;
 
 typedef struct {
@@ -426,6 +428,29 @@ static double orc_factorial(int k) {
   return s;
 }
 
+/* Local-error estimates of the neighbouring orders, used to choose the order
+ * (Sec. 2: CVODE may change the method order after an accepted step; the
+ * estimates are a reading, the paper gives none).  With constant steps the
+ * local truncation error of the order-k BDF is h^{k+1} y^{(k+1)} / ((k+1) H_k),
+ * H_k the harmonic number (the error constants 1/2, 2/9, 3/22, 12/125,
+ * 10/137).
+ *   order q-1: h^q y^{(q)} = q! z_q, so the estimate is (q-1)!/H_{q-1} ||z_q||;
+ *   order q+1: each correction e is ~ h^{q+1} y^{(q+1)} times a constant, so
+ *              the change e_n - (h_n/h_{n-1})^{q+1} e_{n-1} between successive
+ *              steps is ~ h^{q+2} y^{(q+2)}; the estimate is its norm over
+ *              (q+2) H_{q+1}.
+ * Norms are the WRMS norm of Eq. (3) with weights ewt over n entries. */
+double orc_lte_lower(int n, int q, const double *zq, const double *ewt) {
+  return orc_factorial(q - 1) / orc_harmonic(q - 1) * orc_wrms(n, zq, ewt);
+}
+
+double orc_lte_higher(int n, int q, const double *e, const double *eprev, double h, double hprev,
+                      const double *ewt) {
+  double r = pow(h / hprev, q + 1), d[ORC_MAXN];
+  for (int i = 0; i < n; ++i) d[i] = e[i] - r * eprev[i];
+  return orc_wrms(n, d, ewt) / ((q + 2) * orc_harmonic(q + 1));
+}
+
 static int orc_all_finite(int n, const double *v) {
   for (int i = 0; i < n; ++i)
     if (!isfinite(v[i])) return 0;
@@ -687,8 +712,9 @@ static double orc_eta(double bias, double err, int p) {
  * when |gamma/gamma_setup - 1| > 0.3 and after a convergence failure with a
  * stale matrix; when gamma differs from the factored one, delta is scaled by
  * 2/(1 + gamma/gamma_setup).  Convergence failure with a fresh matrix cuts
- * h by 4; 10 in one step fail the cell (-4).  Error-test failure: 7 in one
- * step fail the cell (-3); from the third, restart at order 1 from y with
+ * h by 4; 10 in one step (o->max_ncf) fail the cell (-4).  Error-test
+ * failure: 7 in one step (o->max_netf) fail the cell (-3), which keeps its
+ * last accepted state and time; from the third, restart at order 1 from y with
  * eta = 0.1; otherwise eta = max(0.1, eta_q) and eta <= 0.2 from the second.
  * After every accepted step the next step size is chosen (Sec. 2) from
  * eta_q (bias 6); the order is reconsidered only when qwait reaches 0
@@ -713,6 +739,8 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
   const int S = s->S, n = s->S * s->nb; /* entries per cell, entries of the system */
   const int qmax = o->max_order < 1 ? 1 : (o->max_order > ORC_QMAX ? ORC_QMAX : o->max_order);
   const int krylov = o->gmres_maxl > 0;
+  const int max_netf = o->max_netf > 0 ? o->max_netf : 7;
+  const int max_ncf = o->max_ncf > 0 ? o->max_ncf : 10;
   double z[ORC_QMAX + 2][ORC_MAXN];
   double ewt[ORC_MAXN], e[ORC_MAXN], eprev[ORC_MAXN], ycur[ORC_MAXN], f[ORC_MAXN], G[ORC_MAXN];
   double delta[ORC_MAXN];
@@ -870,7 +898,7 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
       if (!conv) {
         st->ncfn++;
         orc_unpredict(n, q, z);
-        if (++ncf_step >= 10) {
+        if (++ncf_step >= max_ncf) {
           status = ORC_CONV_FAILURE;
           break;
         }
@@ -888,7 +916,7 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
       if (!(dsm <= 1.0)) {
         st->netf++;
         orc_unpredict(n, q, z);
-        if (++nef_step >= 7) {
+        if (++nef_step >= max_netf) {
           status = ORC_ERR_FAILURE;
           break;
         }
@@ -918,6 +946,13 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
       accepted = 1;
     }
     if (status != ORC_SUCCESS) break;
+    if (rec && rec->n >= rec->cap) {
+      /* the record is full: the cell stops at its last recorded step, so the
+       * returned state is the end point of the recorded (differentiable) map */
+      orc_unpredict(n, q, z);
+      status = ORC_RECORD_FULL;
+      break;
+    }
 
     /* accept: correct the Nordsieck array */
     t = tn;
@@ -927,10 +962,6 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
     for (int k = ORC_QMAX; k >= 1; --k) hist[k] = hist[k - 1];
     hist[0] = h;
     if (rec) {
-      if (rec->n >= rec->cap) {
-        status = ORC_RECORD_FULL;
-        break;
-      }
       for (int i = 0; i < n; ++i) rec->y[(size_t)rec->n * S + i] = z[0][i];
       rec->h[rec->n] = h;
       rec->q[rec->n] = q;
@@ -956,17 +987,14 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
         if (qwait == 0) {
           qwait = 2;
           if (q > 1) {
-            double lte = orc_factorial(q - 1) / orc_harmonic(q - 1) * orc_wrms(n, z[q], ewt);
-            double eta_qm1 = orc_eta(6.0, lte, q);
+            double eta_qm1 = orc_eta(6.0, orc_lte_lower(n, q, z[q], ewt), q);
             if (eta_qm1 > eta) {
               eta = eta_qm1;
               qnew = q - 1;
             }
           }
           if (q < qmax && have_eprev) {
-            double r = pow(hstep / hprev, q + 1), d[ORC_MAXN];
-            for (int i = 0; i < n; ++i) d[i] = e[i] - r * eprev[i];
-            double lte = orc_wrms(n, d, ewt) / ((q + 2) * orc_harmonic(q + 1));
+            double lte = orc_lte_higher(n, q, e, eprev, hstep, hprev, ewt);
             double eta_qp1 = orc_eta(10.0, lte, q + 2);
             if (eta_qp1 > eta) {
               eta = eta_qp1;
@@ -1033,6 +1061,35 @@ int32_t orc_integrate_cell(const orc_mech *m, const orc_opts *o, double T, const
     return st->status;
   }
   return orc_integrate_core(&s, o, t0, tout, y, st, rec, zout);
+}
+
+/* Initial step size of one cell, as orc_integrate_cell would choose it
+ * (test hook for orc_initial_step): rates from T and kscale, f0 = f(y0),
+ * weights of Eq. (3) at y0.  *nfe receives the right-hand sides used
+ * (1 for f0 plus the refinements).  Returns 0 for input the integrator
+ * would reject as non-finite. */
+double orc_initial_step_cell(const orc_mech *m, const orc_opts *o, double T, const double *kscale,
+                             const double *F, double t0, double tout, const double *y0,
+                             int32_t *nfe) {
+  double kf[4096], kr[4096], f0[ORC_MAXS], ewt[ORC_MAXS];
+  const int thermal = m->cv != NULL;
+  const int n = m->n_species + thermal;
+  *nfe = 0;
+  if (m->n_reactions > 4096 || n > ORC_MAXS) return 0.0;
+  if (thermal)
+    T = y0[m->n_species];
+  else
+    orc_rates(m, T, kscale, kf, kr);
+  if (!isfinite(T) || !orc_all_finite(n, y0)) return 0.0;
+  orc_sys s = {m, kf, kr, F, n, kscale, 1};
+  sys_f(&s, y0, f0);
+  *nfe = 1;
+  if (!orc_all_finite(n, f0)) return 0.0;
+  orc_ewt(n, n, y0, o, ewt);
+  int32_t extra = 0;
+  double h0 = orc_initial_step(&s, o, t0, tout, y0, f0, ewt, &extra);
+  *nfe += extra;
+  return h0;
 }
 
 /* Batch of N cells (each one independent), OpenMP over cells.  y is [N][ldy]
@@ -1163,6 +1220,15 @@ int32_t orc_max_threads(void) {
 #endif
 }
 
+/* OpenMP threads of later batch integrations (n > 0; otherwise unchanged). */
+void orc_set_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Fixed order / fixed step mode (order-of-accuracy checks)                  */
 /* ------------------------------------------------------------------------ */
@@ -1265,6 +1331,56 @@ static int orc_solve_exact(const orc_sys *s, double gamma, const double *a, doub
     if (dn <= 4.0 * ORC_UROUND * (yn > 0 ? yn : 1.0)) return 0;
   }
   return 0; /* converged to round-off level (stagnation) */
+}
+
+/* Steps of the variable-coefficient BDF at a fixed order q with prescribed
+ * sizes h[0..nsteps-1] (test hook for the local-error estimate and the order
+ * estimates).  z ([q+1][S], row-major) is the Nordsieck array at the start,
+ * in units of h[0]; hist0[k] is the size of the (k+1)-th step before the
+ * first one (k = 0..ORC_QMAX), which sets the xi of the first steps.  Each
+ * step: rescale the array to the step's size, predict, coefficients from the
+ * step history, corrector solved to round-off (fresh Jacobian every
+ * iteration), correct.  Per step n it writes the accepted y_n (yout
+ * [nsteps][S]), the correction e_n = y_n - predicted value (eout
+ * [nsteps][S]) and the error constant Cerr_n (cerr [nsteps]); on exit z is
+ * the array after the last step, in units of its size.  Returns 0, -6 for a
+ * singular Newton matrix, -9 for arguments outside the oracle's limits. */
+int32_t orc_steps(const orc_mech *m, const double *kf, const double *kr, const double *F, int q,
+                  int nsteps, const double *h, const double *hist0, double *zio, double *yout,
+                  double *eout, double *cerr) {
+  const int S = m->n_species;
+  if (q < 1 || q > ORC_QMAX || S > ORC_MAXS || m->cv != NULL) return ORC_NONFINITE;
+  orc_sys s = {m, kf, kr, F, S, NULL, 1};
+  double z[ORC_QMAX + 2][ORC_MAXN];
+  double hist[ORC_QMAX + 1], xi[ORC_QMAX + 2], l[ORC_QMAX + 2], Cerr, a[ORC_MAXS], y[ORC_MAXS];
+  memset(z, 0, sizeof(z));
+  for (int j = 0; j <= q; ++j)
+    for (int i = 0; i < S; ++i) z[j][i] = zio[j * S + i];
+  for (int k = 0; k <= ORC_QMAX; ++k) hist[k] = hist0[k];
+  for (int n = 0; n < nsteps; ++n) {
+    if (n > 0) orc_rescale(S, q, h[n] / h[n - 1], z);
+    orc_predict(S, q, z);
+    orc_xi(h[n], hist, q, xi);
+    orc_bdf_coeffs(q, xi, l, &Cerr);
+    double gamma = h[n] / l[1];
+    for (int i = 0; i < S; ++i) {
+      a[i] = z[0][i] - z[1][i] / l[1];
+      y[i] = z[0][i];
+    }
+    if (orc_solve_exact(&s, gamma, a, y)) return ORC_SETUP_FAILURE;
+    for (int i = 0; i < S; ++i) {
+      double e = y[i] - z[0][i];
+      eout[(size_t)n * S + i] = e;
+      for (int j = 0; j <= q; ++j) z[j][i] += l[j] * e;
+      yout[(size_t)n * S + i] = z[0][i];
+    }
+    cerr[n] = Cerr;
+    for (int k = ORC_QMAX; k >= 1; --k) hist[k] = hist[k - 1];
+    hist[0] = h[n];
+  }
+  for (int j = 0; j <= q; ++j)
+    for (int i = 0; i < S; ++i) zio[j * S + i] = z[j][i];
+  return 0;
 }
 
 /* Replay the frozen step sequence of rec from y0; writes the final state to

@@ -7,6 +7,7 @@ seeded generators); outputs are numpy arrays.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -44,7 +45,7 @@ class Mech(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_void_p), ("atol_len", C.c_int32),
                 ("max_order", C.c_int32), ("max_steps", C.c_int32), ("jac_dq", C.c_int32),
-                ("gmres_maxl", C.c_int32)]
+                ("gmres_maxl", C.c_int32), ("max_netf", C.c_int32), ("max_ncf", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -77,7 +78,27 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
+        _lib = load(LIB)
+    return _lib
+
+
+@contextlib.contextmanager
+def use_library(path):
+    """Run the bindings against another build of the oracle (for example a
+    copy with a deliberately planted mistake, to show that a pin detects it)."""
+    global _lib
+    saved = _lib
+    _lib = load(path)
+    try:
+        yield _lib
+    finally:
+        _lib = saved
+
+
+def load(path):
+    """Open an oracle library and declare its functions."""
+    if True:
+        L = C.CDLL(path)
         P = C.c_void_p
         L.orc_rates.argtypes = [P, C.c_double, P, P, P]
         L.orc_rhs.argtypes = [P, P, P, P, P, P]
@@ -117,8 +138,16 @@ def lib():
         L.orc_perturb_uniform.restype = C.c_double
         L.orc_perturb_batch.argtypes = [C.c_int64, P, C.c_int32, P, P, C.c_uint64, C.c_int64,
                                         C.c_double]
-        _lib = L
-    return _lib
+        L.orc_lte_lower.argtypes = [C.c_int, C.c_int, P, P]
+        L.orc_lte_lower.restype = C.c_double
+        L.orc_lte_higher.argtypes = [C.c_int, C.c_int, P, P, C.c_double, C.c_double, P]
+        L.orc_lte_higher.restype = C.c_double
+        L.orc_initial_step_cell.argtypes = [P, P, C.c_double, P, P, C.c_double, C.c_double, P, P]
+        L.orc_initial_step_cell.restype = C.c_double
+        L.orc_steps.argtypes = [P, P, P, P, C.c_int, C.c_int, P, P, P, P, P, P]
+        L.orc_steps.restype = C.c_int32
+        L.orc_set_threads.argtypes = [C.c_int32]
+    return L
 
 
 def _p(a):
@@ -151,10 +180,11 @@ class OracleMech:
         return C.byref(self.c)
 
 
-def _opts(rtol, atol, max_order=5, max_steps=5000, jac_dq=False, gmres_maxl=0):
+def _opts(rtol, atol, max_order=5, max_steps=5000, jac_dq=False, gmres_maxl=0, max_netf=0,
+          max_ncf=0):
     atol_arr = np.atleast_1d(np.asarray(atol, dtype=np.float64)).copy()
     o = Opts(float(rtol), _p(atol_arr), int(atol_arr.size), int(max_order), int(max_steps),
-             int(bool(jac_dq)), int(gmres_maxl))
+             int(bool(jac_dq)), int(gmres_maxl), int(max_netf), int(max_ncf))
     return o, atol_arr
 
 
@@ -259,14 +289,17 @@ def bdf_coeffs(q, xi):
 
 
 def integrate(mechs, y0, t0, t_out, rtol, atol, T=None, kscale=None, F=None, cell_mech=None,
-              max_order=5, max_steps=5000, nthreads=0, jac_dq=False, gmres_maxl=0, lockstep=0):
+              max_order=5, max_steps=5000, nthreads=0, jac_dq=False, gmres_maxl=0, lockstep=0,
+              max_netf=0, max_ncf=0):
     """Integrate a batch of cells; returns (y, stats structured array).
     jac_dq: Jacobian by difference quotients instead of the analytic one.
     gmres_maxl > 0: inexact Newton with matrix-free GMRES of that Krylov
     dimension (approaches 1A/1B) instead of the direct solve.
     lockstep = B > 0: the cells of each mechanism, in index order, are
     integrated in lock-step batches of B (one step size and one WRMS norm
-    per batch; direct solver, analytic Jacobian)."""
+    per batch; direct solver, analytic Jacobian).
+    max_netf / max_ncf: error-test / Newton convergence failures in one step
+    that fail a cell (0: the defaults 7 and 10)."""
     if isinstance(mechs, dict):
         mechs = [mechs]
     oms = [OracleMech(m) for m in mechs]
@@ -278,7 +311,7 @@ def integrate(mechs, y0, t0, t_out, rtol, atol, T=None, kscale=None, F=None, cel
     ldk = 0 if ks is None else ks.shape[1]
     F = _f64(F)
     cm = None if cell_mech is None else np.ascontiguousarray(cell_mech, dtype=np.int32)
-    o, atol_arr = _opts(rtol, atol, max_order, max_steps, jac_dq, gmres_maxl)
+    o, atol_arr = _opts(rtol, atol, max_order, max_steps, jac_dq, gmres_maxl, max_netf, max_ncf)
     stats = np.zeros(N, dtype=STATS_DTYPE)
     if lockstep:
         if not 1 <= lockstep <= 16 or jac_dq or gmres_maxl:
@@ -395,6 +428,61 @@ def fixed_steps(mech, kf, kr, z, q, h, nsteps, F=None):
     if rc:
         raise RuntimeError(f"fixed_steps failed: {rc}")
     return zz
+
+
+def lte_lower(q, zq, ewt):
+    """Order-selection estimate of the local error of the order q-1 method from
+    the top Nordsieck column z_q of the order-q array (WRMS norm, weights ewt)."""
+    zq, ewt = _f64(zq), _f64(ewt)
+    return float(lib().orc_lte_lower(zq.size, int(q), _p(zq), _p(ewt)))
+
+
+def lte_higher(q, e, eprev, h, hprev, ewt):
+    """Order-selection estimate of the local error of the order q+1 method from
+    the corrections e (step of size h) and eprev (previous step, size hprev)."""
+    e, eprev, ewt = _f64(e), _f64(eprev), _f64(ewt)
+    return float(lib().orc_lte_higher(e.size, int(q), _p(e), _p(eprev), float(h), float(hprev),
+                                      _p(ewt)))
+
+
+def initial_step(mech, y0, t0, t_out, rtol, atol, T=1.0, kscale=None, F=None):
+    """The integrator's initial step size for one cell; returns (h0, right-hand
+    sides used)."""
+    m = OracleMech(mech)
+    o, atol_arr = _opts(rtol, atol)
+    y0 = _f64(y0)
+    nfe = C.c_int32(0)
+    h0 = lib().orc_initial_step_cell(m.ptr, C.byref(o), float(T), _p(_f64(kscale)), _p(_f64(F)),
+                                     float(t0), float(t_out), _p(y0), C.byref(nfe))
+    return float(h0), int(nfe.value)
+
+
+def steps(mech, kf, kr, z, q, h, hist0, F=None):
+    """Fixed-order variable-coefficient BDF steps of prescribed sizes h[n] from
+    the Nordsieck array z ([q+1][S], units of h[0]) with prior step sizes
+    hist0 (hist0[k] = size of the (k+1)-th earlier step).  Correctors are
+    solved to round-off.  Returns (y_n [n][S], e_n [n][S], Cerr_n [n], final z)."""
+    m = OracleMech(mech)
+    S = m.S
+    kf, kr, F = _f64(kf), _f64(kr), _f64(F)
+    h = _f64(np.atleast_1d(h))
+    hist = np.zeros(QMAX + 1)
+    hv = np.atleast_1d(np.asarray(hist0, dtype=np.float64))
+    hist[: min(hv.size, QMAX + 1)] = hv[: QMAX + 1]
+    zz = np.zeros((q + 1, S))
+    zz[:] = np.asarray(z, dtype=np.float64)[: q + 1]
+    n = h.size
+    yo, eo, co = np.zeros((n, S)), np.zeros((n, S)), np.zeros(n)
+    rc = lib().orc_steps(m.ptr, _p(kf), _p(kr), _p(F), int(q), n, _p(h), _p(hist), _p(zz), _p(yo),
+                         _p(eo), _p(co))
+    if rc:
+        raise RuntimeError(f"steps failed: {rc}")
+    return yo, eo, co, zz
+
+
+def set_threads(n):
+    """OpenMP threads of the batch integrations (0: leave unchanged)."""
+    lib().orc_set_threads(int(n))
 
 
 def splitmix64(x):

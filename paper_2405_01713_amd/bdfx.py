@@ -29,10 +29,11 @@ CELL_STATUS = {0: "success", -1: "too_much_work", -3: "err_failure", -4: "conv_f
                -6: "setup_failure", -9: "nonfinite", -10: "record_full"}
 
 EXPORTED = ["bdfx_create", "bdfx_set_stream", "bdfx_destroy", "bdfx_last_error",
-            "bdfx_mech_create", "bdfx_mech_destroy", "bdfx_mech_set_weights", "bdfx_plan",
+            "bdfx_mech_create", "bdfx_mech_destroy", "bdfx_mech_set_weights", "bdfx_mech_set_lnA",
+            "bdfx_plan",
             "bdfx_bind", "bdfx_integrate", "bdfx_perturb", "bdfx_stats_summary",
             "bdfx_adjoint", "bdfx_autotune", "bdfx_set_tuning", "bdfx_get_tuning", "bdfx_typical_atol",
-            "bdfx_version"]
+            "bdfx_get_record_layout", "bdfx_version"]
 
 
 class MechDesc(C.Structure):
@@ -49,7 +50,8 @@ class Options(C.Structure):
                 ("record_steps", C.c_int32), ("waves_per_block", C.c_int32),
                 ("blocks_per_cu", C.c_int32), ("queue_chunk", C.c_int32),
                 ("waves_per_simd", C.c_int32), ("cells_per_wave", C.c_int32),
-                ("jacobian", C.c_int32), ("gmres_maxl", C.c_int32), ("lockstep", C.c_int32)]
+                ("jacobian", C.c_int32), ("gmres_maxl", C.c_int32), ("lockstep", C.c_int32),
+                ("max_err_test_fails", C.c_int32), ("max_conv_fails", C.c_int32)]
 
 
 class Summary(C.Structure):
@@ -58,6 +60,11 @@ class Summary(C.Structure):
                 ("nsetups", C.c_int64), ("netf", C.c_int64), ("ncfn", C.c_int64),
                 ("max_nst", C.c_int64), ("status_count", C.c_int64 * 11),
                 ("nli", C.c_int64), ("ncfl", C.c_int64)]
+
+
+class RecordLayout(C.Structure):
+    _fields_ = [("cap", C.c_int32), ("stride", C.c_int32), ("off_steps", C.c_size_t),
+                ("off_count", C.c_size_t), ("off_hpad", C.c_size_t), ("off_y0", C.c_size_t)]
 
 
 class Tuning(C.Structure):
@@ -93,6 +100,7 @@ def lib():
             "bdfx_mech_create": ([P, C.POINTER(MechDesc), C.POINTER(P)], C.c_int),
             "bdfx_mech_destroy": ([P], C.c_int),
             "bdfx_mech_set_weights": ([P, P], C.c_int),
+            "bdfx_mech_set_lnA": ([P, P], C.c_int),
             "bdfx_plan": ([P, I64, I32, P, C.POINTER(Options), C.POINTER(C.c_size_t)], C.c_int),
             "bdfx_bind": ([P, P, C.c_size_t, P, I32, P, P, P, I32, P, P, P], C.c_int),
             "bdfx_integrate": ([P, C.c_double, C.c_double], C.c_int),
@@ -103,6 +111,7 @@ def lib():
             "bdfx_set_tuning": ([P, C.POINTER(Tuning), I32], C.c_int),
             "bdfx_get_tuning": ([P, C.POINTER(Tuning), I32], C.c_int),
             "bdfx_typical_atol": ([P, C.c_double, P], C.c_int),
+            "bdfx_get_record_layout": ([P, C.POINTER(RecordLayout)], C.c_int),
             "bdfx_version": ([], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -178,16 +187,21 @@ def bdfx_mech_destroy(mech):
     _check(lib().bdfx_mech_destroy(mech))
 
 
+def bdfx_mech_set_lnA(mech, lnA_ptr, ctx=None):
+    """Device-to-device copy of R doubles at lnA_ptr into the mechanism's lnA."""
+    _check(lib().bdfx_mech_set_lnA(mech, C.c_void_p(int(lnA_ptr))), ctx)
+
+
 def make_options(rtol, atol, max_order=5, max_steps=5000, lu_precision=64,
                  scheduler=BDFX_SCHED_STATIC, record_steps=0, waves_per_block=0,
                  blocks_per_cu=0, queue_chunk=0, waves_per_simd=0, cells_per_wave=0,
-                 jacobian=0, gmres_maxl=0, lockstep=0):
+                 jacobian=0, gmres_maxl=0, lockstep=0, max_err_test_fails=0, max_conv_fails=0):
     atol_arr = np.ascontiguousarray(np.atleast_1d(np.asarray(atol, dtype=np.float64)))
     o = Options(float(rtol), atol_arr.ctypes.data_as(C.c_void_p), int(atol_arr.size),
                 int(max_order), int(max_steps), int(lu_precision), int(scheduler),
                 int(record_steps), int(waves_per_block), int(blocks_per_cu), int(queue_chunk),
                 int(waves_per_simd), int(cells_per_wave), int(jacobian), int(gmres_maxl),
-                int(lockstep))
+                int(lockstep), int(max_err_test_fails), int(max_conv_fails))
     o._keep = atol_arr
     return o
 
@@ -231,6 +245,12 @@ def bdfx_stats_summary(ctx) -> dict:
 def bdfx_adjoint(ctx, ybar_ptr, y0bar_ptr, lnA_bar_ptr):
     v = lambda x: C.c_void_p(int(x) if x else 0)
     _check(lib().bdfx_adjoint(ctx, v(ybar_ptr), v(y0bar_ptr), v(lnA_bar_ptr)), ctx)
+
+
+def bdfx_get_record_layout(ctx) -> dict:
+    r = RecordLayout()
+    _check(lib().bdfx_get_record_layout(ctx, C.byref(r)), ctx)
+    return {k: getattr(r, k) for k, _ in RecordLayout._fields_}
 
 
 _TUNING_KEYS = ("mech", "waves_per_simd", "waves_per_block", "queue_chunk", "cells_per_wave",
@@ -319,6 +339,16 @@ class Integrator:
             assert typical.is_contiguous() and typical.numel() >= len(self.mechs) * self.S_max
         bdfx_typical_atol(self.ctx, eta, None if typical is None else typical.data_ptr())
 
+    def set_lnA(self, lnA, mech=0):
+        """New ln pre-exponential factors for mechanism ``mech`` from a float64
+        device tensor [R] (a device copy enqueued on the context's stream)."""
+        torch = self.torch
+        R = int(self.mechs[mech]["n_reactions"])
+        a = lnA.detach().to(device=self.dev, dtype=torch.float64).contiguous()
+        assert a.numel() == R
+        bdfx_mech_set_lnA(self.mech_handles[mech], a.data_ptr(), self.ctx)
+        self._keep_lnA = a
+
     def set_state(self, y0):
         self.y.copy_(self.torch.as_tensor(np.ascontiguousarray(y0), dtype=self.torch.float64))
 
@@ -337,6 +367,35 @@ class Integrator:
         bdfx_adjoint(self.ctx, yb.data_ptr(), y0bar.data_ptr(), lnA_bar.data_ptr())
         self._keep = yb
         return y0bar, lnA_bar
+
+    def step_record(self, cells):
+        """The recorded accepted steps of the given cells after an integrate
+        with record_steps > 0 (bdfx_get_record_layout): a list of dicts with
+        n, h_pad, y [n][S], h [n], q [n], rebuild [n] and y0 [S], S the
+        cell's state length (host copies; synchronises)."""
+        torch = self.torch
+        lay = bdfx_get_record_layout(self.ctx)
+        cap, stride = lay["cap"], lay["stride"]
+        torch.cuda.synchronize(self.dev)
+        f64 = lambda off, count: self.ws[off:off + 8 * count].view(torch.float64)
+        count = self.ws[lay["off_count"]:lay["off_count"] + 4 * self.N].view(torch.int32).cpu().numpy()
+        hpad = f64(lay["off_hpad"], self.N).cpu().numpy()
+        cm = (np.zeros(self.N, dtype=np.int64) if self.cell_mech is None
+              else self.cell_mech.cpu().numpy())
+        out = []
+        for c in np.atleast_1d(cells):
+            c = int(c)
+            m = self.mechs[int(cm[c])]
+            S = int(m["n_species"]) + (m.get("cv") is not None)
+            n = int(count[c])
+            steps = f64(lay["off_steps"] + 8 * c * cap * stride, cap * stride).view(cap, stride)
+            steps = steps[:n].cpu().numpy()
+            code = steps[:, S + 1].astype(np.int64)
+            y0 = f64(lay["off_y0"] + 8 * c * stride, stride).cpu().numpy()[:S]
+            out.append(dict(n=n, h_pad=float(hpad[c]), y=steps[:, :S].copy(), h=steps[:, S].copy(),
+                            q=(code & 255).astype(np.int32), rebuild=(code >> 8).astype(np.int32),
+                            y0=y0))
+        return out
 
     def autotune(self, t0, t_out, sample_cells=0, cache=None):
         """Pick the launch shape per mechanism with bdfx_autotune().  With
@@ -433,24 +492,66 @@ class Integrator:
 
 def make_bdf_function():
     """torch.autograd.Function over the library: forward integrates with step
-    recording, backward runs the discrete adjoint (bdfx_adjoint)."""
+    recording, backward runs the discrete adjoint (bdfx_adjoint).
+
+    One bound Integrator per batch shape, mechanism structure, tolerances and
+    device is created on first use and reused: each forward copies y0, T and
+    lnA into it on the device and enqueues the integration, with no new
+    context, workspace or host synchronisation.  A cell that fails (negative
+    status) returns NaN in place of y(t_out), and its gradients are NaN (the
+    lnA gradient, a sum over cells, is NaN if any cell failed).  One
+    forward/backward pair may be in flight per cached Integrator: a backward
+    whose forward was overwritten by a later forward raises."""
     import torch
+
+    cache = {}
+
+    def key_of(y0, mech, T, rtol, atol, record_steps):
+        parts = [tuple(y0.shape), str(y0.device), int(mech["n_species"]),
+                 int(mech["n_reactions"]), T is None, float(rtol),
+                 np.asarray(atol, dtype=np.float64).tobytes(), int(record_steps)]
+        for k in ("reac", "prod", "EaR", "lnK"):
+            v = mech.get(k)
+            parts.append(None if v is None else np.ascontiguousarray(v).tobytes())
+        return tuple(parts)
 
     class BDFFunction(torch.autograd.Function):
         @staticmethod
         def forward(ctx, y0, lnA, mech, T, t_out, rtol, atol, record_steps=4096):
-            m = dict(mech)
-            m["lnA"] = lnA.detach().cpu().numpy().astype(np.float64)
-            integ = Integrator([m], y0, rtol, atol, T=T, device=y0.device.index or 0,
-                               record_steps=record_steps)
+            k = key_of(y0, mech, T, rtol, atol, record_steps)
+            integ = cache.get(k)
+            if integ is None:
+                m = dict(mech)
+                m["lnA"] = np.asarray(mech["lnA"], dtype=np.float64)
+                integ = Integrator([m], y0, rtol, atol, T=T, device=y0.device.index or 0,
+                                   record_steps=record_steps)
+                integ.generation = 0
+                cache[k] = integ
+            integ.y.copy_(y0.detach())
+            if T is not None:
+                integ.T.copy_(torch.as_tensor(T, dtype=torch.float64, device=integ.dev))
+            integ.set_lnA(lnA)
             integ.integrate(0.0, float(t_out))
-            ctx.integ = integ
-            return integ.y.clone()
+            integ.generation += 1
+            ctx.integ, ctx.generation = integ, integ.generation
+            failed = integ.status != 0
+            ctx.failed = failed.clone()
+            return torch.where(failed[:, None], torch.full_like(integ.y, float("nan")), integ.y)
 
         @staticmethod
         def backward(ctx, ybar):
-            y0bar, lnA_bar = ctx.integ.adjoint(ybar)
-            R = int(ctx.integ.mechs[0]["n_reactions"])
-            return y0bar, lnA_bar[0, :R].clone(), None, None, None, None, None, None
+            integ = ctx.integ
+            if integ.generation != ctx.generation:
+                raise RuntimeError("BDFFunction: a later forward on the same batch replaced the "
+                                   "step record this backward needs")
+            y0bar, lnA_bar = integ.adjoint(ybar)
+            R = int(integ.mechs[0]["n_reactions"])
+            nan = float("nan")
+            failed = ctx.failed
+            y0bar = torch.where(failed[:, None], torch.full_like(y0bar, nan), y0bar)
+            g = lnA_bar[0, :R].clone()
+            g = torch.where(failed.any(), torch.full_like(g, nan), g)
+            return y0bar, g, None, None, None, None, None, None
 
+    BDFFunction.cache = cache
     return BDFFunction

@@ -91,6 +91,7 @@ struct Params {
   CellStats *stats;
   double t0, tout, rtol;
   int32_t atol_len, max_order, max_steps;
+  int32_t max_netf, max_ncf;  // failures within one step that fail the cell
   int32_t n_sp;           // species of the mechanism (<= template S)
   int32_t gmres_maxl;     // Krylov vectors per GMRES solve (GMRES kernels only)
   int32_t lds_doubles;    // LDS per wave
@@ -1472,7 +1473,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       if (!conv) {
         ncfn++;
         nd_unpredict(z);
-        if (++ncf_step >= 10) {
+        if (++ncf_step >= P.max_ncf) {
           status = kConvFailure;
           break;
         }
@@ -1490,7 +1491,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       if (dsm2 <= 1.0) break;
       netf++;
       nd_unpredict(z);
-      if (++nef_step >= 7) {
+      if (++nef_step >= P.max_netf) {
         status = kErrFailure;
         break;
       }
@@ -1518,6 +1519,13 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       }
     }
     if (status != kSuccess) break;
+    if (P.rec && nst >= P.rec_cap) {
+      // the record is full: stop at the last recorded step, so that the
+      // returned state is the end point of the recorded map
+      nd_unpredict(z);
+      status = kRecordFull;
+      break;
+    }
 
     // accept: correct the Nordsieck array
     t = W.uni(C[Ctl::kTn]);
@@ -1530,10 +1538,6 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
     for (int k = kQmax; k >= 1; --k) C[Ctl::kHist + k] = C[Ctl::kHist + k - 1];
     C[Ctl::kHist] = h;
     if (P.rec) {
-      if (nst > P.rec_cap) {
-        status = kRecordFull;
-        break;
-      }
       double *rp = P.rec + (static_cast<int64_t>(cell) * P.rec_cap + (nst - 1)) * P.rec_stride;
       if (own) rp[W.lane] = z[0];
       if (W.lane == 0) {

@@ -318,6 +318,16 @@ int bdfx_mech_set_weights(bdfx_mech m, const double *weights) {
   return BDFX_OK;
 }
 
+int bdfx_mech_set_lnA(bdfx_mech m, const double *d_lnA) {
+  if (!m || !d_lnA) return BDFX_EINVAL;
+  bdfx_ctx c = m->ctx;
+  if (!c) return BDFX_EINVAL;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipMemcpyAsync(const_cast<double *>(m->dev.lnA), d_lnA, static_cast<size_t>(m->R) * 8,
+                           hipMemcpyDeviceToDevice, c->stream));
+  return BDFX_OK;
+}
+
 int bdfx_mech_destroy(bdfx_mech m) {
   if (!m) return BDFX_EINVAL;
   if (m->ctx) hipSetDevice(m->ctx->device);
@@ -387,6 +397,8 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
   ctx->opt = *o;
   if (ctx->opt.max_order == 0) ctx->opt.max_order = 5;
   if (ctx->opt.max_steps <= 0) ctx->opt.max_steps = 5000;
+  if (ctx->opt.max_err_test_fails <= 0) ctx->opt.max_err_test_fails = 7;
+  if (ctx->opt.max_conv_fails <= 0) ctx->opt.max_conv_fails = 10;
   if (ctx->opt.lu_precision == 0) ctx->opt.lu_precision = 64;
   if (ctx->opt.queue_chunk <= 0) ctx->opt.queue_chunk = 1;
   ctx->atol.assign(o->atol, o->atol + o->atol_len);
@@ -624,6 +636,8 @@ static bdfx::Params make_params(bdfx_ctx ctx, const Bin &b, double t0, double to
   }
   P.max_order = ctx->opt.max_order;
   P.max_steps = ctx->opt.max_steps;
+  P.max_netf = ctx->opt.max_err_test_fails;
+  P.max_ncf = ctx->opt.max_conv_fails;
   P.n_sp = m->n;
   P.gmres_maxl = ctx->opt.gmres_maxl;
   P.queue = reinterpret_cast<uint32_t *>(ctx->ws + ctx->off_queue) + b.mech;
@@ -885,6 +899,19 @@ int bdfx_stats_summary(bdfx_ctx ctx, bdfx_summary *out) {
     out->ncfl += s.ncfl;
     out->max_nst = std::max<int64_t>(out->max_nst, s.nst);
   }
+  return BDFX_OK;
+}
+
+int bdfx_get_record_layout(bdfx_ctx ctx, bdfx_record_layout *out) {
+  if (!ctx || !out) return fail(ctx, BDFX_EINVAL, "NULL argument");
+  if (!ctx->bound || ctx->opt.record_steps <= 0)
+    return fail(ctx, BDFX_EORDER, "no step record: bind with record_steps > 0 first");
+  out->cap = ctx->opt.record_steps;
+  out->stride = ctx->rec_stride;
+  out->off_steps = ctx->off_rec;
+  out->off_count = ctx->off_recn;
+  out->off_hpad = ctx->off_rechpad;
+  out->off_y0 = ctx->off_recy0;
   return BDFX_OK;
 }
 
