@@ -1,15 +1,21 @@
 """Benchmark: cells integrated per second per outer step (one MI355X).
 
-One step = every cell of the workload integrated over one outer (splitting)
-step [0, dt] from the same resident initial state (restored by a device copy
-at the start of the step).  Default workload: the 21-species / 84-reaction
-synthetic mass-action mechanism on 64^3 = 262,144 cells, dt = 1e-5 s,
-rtol = 1e-6, atol = 1e-10, FP64.
+Headline workload: 1,048,576 cells, half with the 9-species / 30-reaction and
+half with the 53-species / 325-reaction synthetic mass-action mechanism
+(T ~ U[800, 2800] K), ten outer splitting steps of 1e-5 s, each a 1 %
+perturbation of the states followed by the integration of every cell, all ten
+captured in one HIP graph; rtol = 1e-6, atol = 1e-10, FP64 throughout, the
+persistent work-queue ("batched") form with autotuned launch shapes.  One bench
+step is one outer step; K steps are timed as graph replays from the resident
+initial state (K/10 replays of the ten-step graph, plus one graph of K mod 10
+steps), with HIP events on the replay stream.
 
-Forms timed: plain (one lane group per cell, static grid), batched
-(persistent work-queue waves) and batched with the Newton-matrix LU in FP32.
-The headline `value` is the fastest form that matches the oracle sample.
-Prints one JSON line.
+Also measured (labelled keys, each with its own small step count): the same
+workload with the FP32 Newton matrix and in the plain (static grid) form; the
+21-species workload on 262,144 cells in the three forms; the 53-species
+mechanism on 262,144 cells (FP64 vs FP32 Newton matrix) and on 1,048,576 cells;
+the discrete adjoint on 65,536 cells; and the CPU oracle on a random sample of
+the headline workload.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -59,10 +65,11 @@ def _pmc_rows(d):
 
 
 def traffic_from(fetch_dir, write_dir, copy_mib, workload, form, out=TRAFFIC_FILE):
-    """HBM traffic of the integrator launch from two rocprofv3 --pmc runs of
-    ``bench.py --copy-probe copy_mib --forms form --steps 1 --warmup 0``
-    (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  Each counter is scaled
-    by its reading for the probe copy, which reads and writes copy_mib MiB."""
+    """HBM traffic of the integrator launches of one outer step from two
+    rocprofv3 --pmc runs of ``bench.py --pmc-step --copy-probe copy_mib``
+    (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch): the k_integrate
+    dispatches after the probe copy are summed.  Each counter is scaled by its
+    reading for the probe copy, which reads and writes copy_mib MiB."""
     res = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = [r for r in _pmc_rows(d) if r["Counter_Name"] == counter]
@@ -70,12 +77,14 @@ def traffic_from(fetch_dir, write_dir, copy_mib, workload, form, out=TRAFFIC_FIL
         for r in rows:
             k = int(r["Dispatch_Id"])
             by.setdefault(k, [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
-        integ = [v for k, v in sorted(by.items()) if "k_integrate" in v[0]]
-        copies = [v for k, v in sorted(by.items()) if "bdfx" not in v[0]]
-        copy_kib = max(v[1] for v in copies)
+        copies = [(k, v) for k, v in sorted(by.items()) if "bdfx" not in v[0]]
+        k_copy, (_, copy_kib) = max(copies, key=lambda kv: kv[1][1])
+        # the integrator launches after the probe: those of the measured step
+        integ = [v for k, v in sorted(by.items()) if "k_integrate" in v[0] and k > k_copy]
+        kib = sum(v[1] for v in integ)
         factor = copy_mib * 1024.0 / copy_kib
-        res[counter] = dict(integrate_kib=integ[-1][1], copy_kib=copy_kib, scale=factor,
-                            bytes=integ[-1][1] * factor * 1024.0)
+        res[counter] = dict(integrate_kib=kib, launches=len(integ), copy_kib=copy_kib,
+                            scale=factor, bytes=kib * factor * 1024.0)
     doc = dict(workload=workload, form=form, source_hash=kernel_source_hash(), copy_mib=copy_mib,
                fetch=res["FETCH_SIZE"], write=res["WRITE_SIZE"],
                traffic_bytes=res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"])
@@ -95,55 +104,167 @@ def stored_traffic(workload, form):
     return d["traffic_bytes"] if d.get("source_hash") == kernel_source_hash() else None
 
 
-def flops_model(mech: dict, forcing: bool = False) -> dict:
-    """Algorithmic FP64 flops of each integrator event for one mechanism
-    (FMA = 2, divide / sqrt / exp = 1), derived from its stoichiometry."""
-    S, R = mech["n_species"], mech["n_reactions"]
-    reac, prod = np.asarray(mech["reac"]), np.asarray(mech["prod"])
-    nr = (reac >= 0).sum(1)
-    npd = (prod >= 0).sum(1)
-    rev = mech.get("lnK") is not None
-    # rates: k_f times reactant slots, k_r times product slots, subtract
-    rate = int(np.sum(nr + (npd if rev else 0) + 1))
-    gather = 2 * int(np.sum(nr + npd))  # one FMA per slot occurrence
-    rhs = rate + gather + (S if forcing else 0)
-    # Jacobian terms: per slot and distributed row, product of the other slots + FMA
-    terms = 0
-    for r in range(R):
-        rows = nr[r] + npd[r]
-        for side_n in ((nr[r],) + ((npd[r],) if rev else ())):
-            terms += side_n * rows * (2 + max(side_n - 1, 0))
-    jac = terms + 2 * S * S  # + M = I - gamma J
-    lu = sum(m * (1 + 2 * m) for m in range(S))  # divides + FMA updates
-    solve = 2 * S * (S - 1) + S
-    newton_vec = 10 * S
-    q = 4  # typical order
-    step_vec = (q * (q + 1) // 2 + 2 * (q + 1) + 6) * S
-    rates0 = 6 * R
-    return dict(rhs=rhs, setup=jac + lu, nni=solve + newton_vec, nst=step_vec, cell=rates0,
-                lu=lu, solve=solve)
 
 
-def algorithmic_flops(stats: np.ndarray, fm: dict, fp32_lu: bool = False) -> tuple:
-    """(FP64 flops, FP32 flops) of a launch; with the FP32 Newton-matrix
-    inverse the factorisation and the solves are FP32."""
-    total = float(stats["nfe"].sum() * fm["rhs"] + stats["nsetups"].sum() * fm["setup"]
-                  + stats["nni"].sum() * fm["nni"] + stats["nst"].sum() * fm["nst"]
-                  + stats.size * fm["cell"])
-    f32 = float(stats["nsetups"].sum() * fm["lu"] + stats["nni"].sum() * fm["solve"]) if fp32_lu else 0.0
+# ---------------------------------------------------------------------------
+# algorithmic flops
+# ---------------------------------------------------------------------------
+
+def flops_per_cell(S: int, R: int, st: np.ndarray, fp32_lu: bool = False) -> tuple:
+    """Algorithmic flops of one integration of each cell in ``st`` (per-cell
+    statistics of a mechanism with S species and R reactions), counted from
+    the cell's own event counters (FMA = 2, divide / sqrt / exp = 1):
+
+        F = nfe 7R + nsetups (11R + S^2 + 2S^3/3) + nni (2S^2 + 8S)
+            + nst (q^2/2 + 2q + 12) S + R (4 + 1)
+
+    (right-hand sides; Jacobian, Newton matrix and LU factorisation per setup;
+    solve and vector work per Newton iteration; predictor, correction, norms
+    and rescaling per step at order q; rate constants with one exp each).  q is
+    the cell's last order.  Returns (FP64 flops, FP32 flops) per cell; with the
+    FP32 Newton matrix the factorisation and the solves are FP32."""
+    nfe, nst, nni, nsu = (st[k].astype(np.float64) for k in ("nfe", "nst", "nni", "nsetups"))
+    q = st["q_last"].astype(np.float64)
+    lu, solve = 2.0 * S ** 3 / 3.0, 2.0 * S * S
+    total = (nfe * 7 * R + nsu * (11 * R + S * S + lu) + nni * (solve + 8 * S)
+             + nst * (q * q / 2 + 2 * q + 12) * S + R * 5)
+    f32 = nsu * lu + nni * solve if fp32_lu else np.zeros_like(total)
     return total - f32, f32
 
 
-def run_form(w, form, steps, warmup, opts_extra=None, tuning_cache=None):
+def launch_flops(w, st, fp32_lu=False) -> tuple:
+    """(FP64, FP32) algorithmic flops summed over the cells of a launch."""
+    cm = w["cell_mech"] if w.get("cell_mech") is not None else np.zeros(len(st), dtype=int)
+    F64 = F32 = 0.0
+    for k, m in enumerate(w["mechs"]):
+        sel = cm == k
+        if sel.any():
+            a, b = flops_per_cell(int(m["n_species"]), int(m["n_reactions"]), st[sel], fp32_lu)
+            F64 += float(a.sum())
+            F32 += float(b.sum())
+    return F64, F32
+
+
+def roofline_frac(F64, F32, seconds):
+    """Fraction of the vector peaks: F64 / t / 78.6 TF + F32 / t / 157.3 TF."""
+    return (F64 / seconds / (FP64_VECTOR_PEAK_TFLOPS * 1e12)
+            + F32 / seconds / (FP32_VECTOR_PEAK_TFLOPS * 1e12))
+
+
+FORM_OPTS = dict(plain=dict(scheduler=0, lu_precision=64),
+                 batched=dict(scheduler=1, lu_precision=64),
+                 batched_fp32lu=dict(scheduler=1, lu_precision=32))
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# headline: the outer splitting loop in a HIP graph
+# ---------------------------------------------------------------------------
+
+def run_outer_loop(w, form, steps, warmup, tuning_cache=None, seed=3, account=True):
+    """Time exactly ``steps`` outer steps of the workload (graphs of 10 outer
+    steps replayed from the resident initial state, plus one graph of
+    steps mod 10), after ``warmup`` untimed outer steps run the same way.
+    With ``account``, one more eager pass of the ten outer steps from the same
+    state reads every step's per-cell statistics (algorithmic flops) and times
+    each integrator launch with HIP events on the launch stream; its final
+    state must equal the graph's bit for bit."""
     import torch
     from paper_2405_01713_amd import bdfx
 
-    # plain: static grid, default launch shape; batched: persistent work
-    # queue with the launch shape picked by the autotuner (untimed)
-    opts = dict(plain=dict(scheduler=0, lu_precision=64),
-                batched=dict(scheduler=1, lu_precision=64),
-                batched_fp32lu=dict(scheduler=1, lu_precision=32))[form]
-    opts.update(opts_extra or {})
+    n_outer, dt, amp = w["outer_steps"], w["t_out"], w["perturb"]
+    integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"],
+                            kscale=w["kscale"], cell_mech=w["cell_mech"], **FORM_OPTS[form])
+    tuning = integ.autotune(0.0, dt, cache=tuning_cache) if FORM_OPTS[form]["scheduler"] else None
+    y0 = integ.y.clone()
+    graphs = {}
+
+    def graph(n):
+        if n not in graphs:
+            graphs[n] = integ.capture_outer_loop(n, dt, seed, amp)
+        return graphs[n]
+
+    def plan(total):
+        return [n_outer] * (total // n_outer) + ([total % n_outer] if total % n_outer else [])
+
+    stream = torch.cuda.current_stream()
+    for n in plan(warmup):
+        integ.y.copy_(y0)
+        graph(n).replay()
+    torch.cuda.synchronize()
+    times = []
+    wall0 = time.perf_counter()
+    for n in plan(steps):
+        integ.y.copy_(y0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        graph(n).replay()
+        b.record(stream)
+        times.append((n, a, b))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = [(n, a.elapsed_time(b)) for n, a, b in times]
+    total_ms = sum(t for _, t in ms)
+    # state after one full graph of n_outer steps from y0 (for the oracle check)
+    integ.y.copy_(y0)
+    graph(n_outer).replay()
+    torch.cuda.synchronize()
+    y_graph = integ.state()
+    st_last = integ.cell_stats()
+    out = dict(form=form, outer_steps_timed=steps, replays=[n for n, _ in ms],
+               replay_ms=[t for _, t in ms], ms_per_outer_step=total_ms / steps,
+               wall_ms_per_outer_step=1e3 * wall / steps,
+               cells_per_s=w["n_cells"] * steps / (total_ms * 1e-3), tuning=tuning,
+               failed_cells_last_step=int(np.sum(st_last["status"] != 0)))
+    if account:
+        integ.y.copy_(y0)
+        F64 = F32 = 0.0
+        launch_ms, failed = [], 0
+        per_mech_nst = {}
+        with torch.cuda.stream(integ.stream):
+            for k in range(n_outer):
+                integ.perturb(seed, k, amp)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(integ.stream)
+                integ.integrate(k * dt, (k + 1) * dt)
+                b.record(integ.stream)
+                torch.cuda.synchronize()
+                launch_ms.append(a.elapsed_time(b))
+                st = integ.cell_stats()
+                failed += int(np.sum(st["status"] != 0))
+                f64, f32 = launch_flops(w, st, form == "batched_fp32lu")
+                F64 += f64
+                F32 += f32
+                for m in range(len(w["mechs"])):
+                    key = f"S{w['mechs'][m]['n_species']}"
+                    nst = st["nst"][w["cell_mech"] == m] if w["cell_mech"] is not None else st["nst"]
+                    per_mech_nst.setdefault(key, []).append(float(nst.mean()))
+        y_eager = integ.state()
+        out.update(alg_flops_fp64_per_outer_step=F64 / n_outer,
+                   alg_flops_fp32_per_outer_step=F32 / n_outer,
+                   eager_integrate_ms=launch_ms, eager_integrate_ms_mean=float(np.mean(launch_ms)),
+                   failed_cell_steps=failed, mean_nst_per_outer_step=per_mech_nst,
+                   graph_equals_eager_bitwise=bool(np.array_equal(y_graph, y_eager)))
+    integ.close()
+    out["_y"] = y_graph
+    return out
+
+
+# ---------------------------------------------------------------------------
+# single-step forms (21-species workload)
+# ---------------------------------------------------------------------------
+
+def run_form(w, form, steps, warmup, tuning_cache=None):
+    """One outer step of every cell from the same resident state (restored by
+    a device copy before each step), timed with HIP events on the launch
+    stream; ``steps`` timed after ``warmup``."""
+    import torch
+    from paper_2405_01713_amd import bdfx
+
+    opts = FORM_OPTS[form]
     integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"],
                             kscale=w["kscale"], cell_mech=w["cell_mech"], **opts)
     tuning = (integ.autotune(0.0, w["t_out"], cache=tuning_cache) if opts["scheduler"] == 1
@@ -157,20 +278,48 @@ def run_form(w, form, steps, warmup, opts_extra=None, tuning_cache=None):
             integ.y.copy_(y0)
             integ.integrate(0.0, w["t_out"])
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
         for k in range(steps):
             integ.y.copy_(y0)
             ev[k][0].record(stream)
             integ.integrate(0.0, w["t_out"])
             ev[k][1].record(stream)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
     kern_ms = [a.elapsed_time(b) for a, b in ev]
     y = integ.state()
     st = integ.cell_stats()
     integ.close()
-    return dict(wall_ms_per_step=1e3 * wall / steps, kernel_ms=float(np.mean(kern_ms)),
-                kernel_ms_min=float(np.min(kern_ms)), y=y, stats=st, tuning=tuning)
+    F64, F32 = launch_flops(w, st, form == "batched_fp32lu")
+    t = float(np.mean(kern_ms)) * 1e-3
+    return dict(kernel_ms=float(np.mean(kern_ms)), kernel_ms_min=float(np.min(kern_ms)),
+                cells_per_s=w["n_cells"] / t, alg_flops_fp64=F64, alg_flops_fp32=F32,
+                roofline_frac=roofline_frac(F64, F32, t),
+                failed_cells=int(np.sum(st["status"] != 0)), mean_nst=float(st["nst"].mean()),
+                mean_nsetups=float(st["nsetups"].mean()), tuning=tuning,
+                min_y=float(y.min()), n_below_minus_atol=int(np.sum(y < -np.asarray(w["atol"]))),
+                invariant_drift=_invariant_drift(w, y), _y=y)
+
+
+def run_c1(steps, warmup, tuning_cache=None, n_check=256):
+    """The 21-species / 84-reaction workload on 262,144 cells in the three
+    forms; the first n_check cells against the oracle."""
+    w = W.make_workload("s21_r84_262k")
+    out = dict(workload="s21_r84_262k", n_cells=w["n_cells"])
+    ys = {}
+    for form in ("plain", "batched", "batched_fp32lu"):
+        r = run_form(w, form, steps, warmup, tuning_cache)
+        ys[form] = r.pop("_y")[:n_check]
+        out[form] = r
+        log(f"21 species {form}: {r['kernel_ms']:.1f} ms")
+    try:
+        from oracle import oracle as O
+        yo, _ = O.integrate(w["mechs"], w["y0"][:n_check], 0.0, w["t_out"], w["rtol"], w["atol"],
+                            T=w["T"][:n_check])
+        for form in ys:
+            out[form]["vs_oracle"] = _errors(ys[form], yo, w["rtol"], w["atol"])
+        out["check_cells"] = n_check
+    except Exception as e:  # the oracle is optional on the timing path
+        out["check_error"] = repr(e)
+    return out
 
 
 def run_adjoint(steps, warmup, n_cells=None, record_steps=2048, n_check=32):
@@ -250,10 +399,6 @@ def run_adjoint(steps, warmup, n_cells=None, record_steps=2048, n_check=32):
     except Exception as e:  # the oracle is optional on the timing path
         res["check_error"] = repr(e)
     return res
-
-
-def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def _timed_events(fn, stream, steps, warmup):
@@ -572,112 +717,137 @@ def run_typical(tuning_cache=None, reps=50, eta=1e-10):
     return out
 
 
-def _oracle_outer_loop(O, w, idx, n_outer, seed):
-    ms, cm = w["mechs"], w["cell_mech"][idx]
-    y = w["y0"][idx].copy()
-    for k in range(n_outer):
-        # the perturbation is keyed by the cell index: perturb the whole rows
-        # of the sampled cells at their own indices
-        full = np.zeros_like(w["y0"][: idx.max() + 1])
-        full[idx] = y
-        S_of = [ms[m]["n_species"] for m in w["cell_mech"][: idx.max() + 1]]
-        W_of = [ms[m]["w"] for m in w["cell_mech"][: idx.max() + 1]]
-        full = O.perturb(full, S_of, W_of, seed, k, w["perturb"])
-        y, _ = O.integrate(ms, full[idx], k * w["t_out"], (k + 1) * w["t_out"], w["rtol"], w["atol"],
-                           T=w["T"][idx], cell_mech=cm)
-    return y
+# ---------------------------------------------------------------------------
+# CPU oracle baseline
+# ---------------------------------------------------------------------------
 
-
-def run_batching(steps, warmup, tuning_cache=None, n_cells=None, n_check=64, seed=3):
-    """1,048,576 cells, half 9 / 30 and half 53 / 325, 10 outer splitting steps
-    (1 % perturbation, then integration over 1e-5 s) captured in one HIP graph;
-    cells/s = 10 N / t_graph for the plain (static grid, FP64) and batched
-    (work queue, autotuned; FP64 and FP32 Newton matrix) forms; the first
-    n_check cells are checked against the oracle's composed loop."""
-    from paper_2405_01713_amd import bdfx
-
-    w = W.make_workload("mixed_s9_s53_1m", n_cells)
-    n_outer = w["outer_steps"]
-    out = dict(workload="mixed_s9_s53_1m", n_cells=w["n_cells"], outer_steps=n_outer)
-    y_check = {}
-    for form, sched, lu in (("plain", 0, 64), ("batched", 1, 64), ("batched_fp32lu", 1, 32)):
-        integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"],
-                                cell_mech=w["cell_mech"], scheduler=sched, lu_precision=lu)
-        tune = integ.autotune(0.0, w["t_out"], cache=tuning_cache) if sched else None
-        y0 = integ.y.clone()
-        g = integ.capture_outer_loop(n_outer, w["t_out"], seed, w["perturb"])
-
-        def run():
-            integ.y.copy_(y0)
-            g.replay()
-
-        import torch
-        ms = _timed_events(run, torch.cuda.current_stream(), steps, warmup)
-        st = integ.cell_stats()
-        y_check[form] = integ.state()[:n_check]
-        per_mech = {}
-        for m in range(len(w["mechs"])):
-            nst = st["nst"][w["cell_mech"] == m]
-            per_mech[f"S{w['mechs'][m]['n_species']}"] = dict(
-                mean_nst=float(nst.mean()), p01_nst=float(np.percentile(nst, 1)),
-                p99_nst=float(np.percentile(nst, 99)))
-        integ.close()
-        log(f"batching {form}: {ms:.1f} ms per graph of {n_outer} outer steps")
-        out[form] = dict(graph_ms=ms, cells_per_s=n_outer * w["n_cells"] / (ms * 1e-3),
-                         tuning=tune, failed_cells=int(np.sum(st["status"] != 0)),
-                         last_outer_step_nst=per_mech)
-    out["speedup_batched_over_plain"] = out["plain"]["graph_ms"] / out["batched"]["graph_ms"]
-    out["speedup_batched_fp32lu_over_plain"] = (out["plain"]["graph_ms"] /
-                                                out["batched_fp32lu"]["graph_ms"])
+def _cpu_model():
     try:
-        from oracle import oracle as O
-        yo = _oracle_outer_loop(O, w, np.arange(n_check), n_outer, seed)
-        for form in ("plain", "batched", "batched_fp32lu"):
-            out[form]["vs_oracle"] = _errors(y_check[form], yo, w["rtol"], w["atol"])
-        out["check_cells"] = n_check
-    except Exception as e:
-        out["check_error"] = repr(e)
-    return out
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
-def cpu_baseline(w, n_sample):
+def _native_oracle():
+    """Build the oracle with -O3 -march=native (same source, no FMA
+    contraction, so its results equal the -O2 build's) into a temporary
+    directory on this host; returns the library path."""
+    import subprocess
+    import tempfile
     from oracle import oracle as O
-    idx = np.arange(min(n_sample, w["n_cells"]))
-    t0 = time.perf_counter()
-    yo, sto = O.integrate(w["mechs"], w["y0"][idx], 0.0, w["t_out"], w["rtol"], w["atol"],
-                          T=None if w["T"] is None else w["T"][idx],
-                          kscale=None if w["kscale"] is None else w["kscale"][idx],
-                          cell_mech=None if w["cell_mech"] is None else w["cell_mech"][idx])
-    dt = time.perf_counter() - t0
-    return dict(value=len(idx) / dt, seconds=dt, cores=O.max_threads(), idx=idx, y=yo, stats=sto)
+    d = tempfile.mkdtemp(prefix="bdfx_oracle_native_")
+    path = os.path.join(d, "liboracle_native.so")
+    subprocess.run(["gcc", "-O3", "-march=native", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                    "-ffp-contract=off", "-o", path, O.SRC, "-lm"], check=True)
+    return path
 
+
+def cpu_baseline(w, n_sample=4096, n_single=128, reps=3, seed=11, pert_seed=3):
+    """The oracle on the GPU machine's host cores, on a random sample of the
+    workload's cells (seeded): the whole outer loop (every outer step's
+    perturbation, untimed, then the integration of the sample, timed), built
+    with -O3 -march=native and OpenMP over all threads; median of ``reps``
+    runs, plus one run on one thread over the first n_single cells of the
+    sample.  cells/s per outer step = cells x outer steps / integration time."""
+    from oracle import oracle as O
+
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(w["n_cells"], size=min(n_sample, w["n_cells"]), replace=False))
+    n_outer = w["outer_steps"]
+    cm = w["cell_mech"][idx] if w["cell_mech"] is not None else np.zeros(idx.size, dtype=np.int32)
+    T = None if w["T"] is None else w["T"][idx]
+
+    def run(sel, threads):
+        secs = []
+        y, st = O.outer_loop(w["mechs"], w["y0"][idx[sel]], idx[sel], cm[sel], n_outer,
+                             w["t_out"], pert_seed, w["perturb"], w["rtol"], w["atol"],
+                             T=None if T is None else T[sel], integrate_seconds=secs,
+                             nthreads=threads)
+        return y, st, sum(secs)
+
+    path = _native_oracle()
+    all_sel = np.arange(idx.size)
+    with O.use_library(path):
+        threads = O.max_threads()
+        times, y = [], None
+        for _ in range(reps):
+            y, st, t = run(all_sel, threads)
+            times.append(t)
+        t1 = run(all_sel[:n_single], 1)[2]
+        O.set_threads(threads)
+    # the -O2 oracle gives the same numbers (no FMA contraction in either build)
+    y2, _ = O.outer_loop(w["mechs"], w["y0"][idx[:16]], idx[:16], cm[:16], 1, w["t_out"],
+                         pert_seed, w["perturb"], w["rtol"], w["atol"],
+                         T=None if T is None else T[:16])
+    with O.use_library(path):
+        y3, _ = O.outer_loop(w["mechs"], w["y0"][idx[:16]], idx[:16], cm[:16], 1, w["t_out"],
+                             pert_seed, w["perturb"], w["rtol"], w["atol"],
+                             T=None if T is None else T[:16])
+    med = float(np.median(times))
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return dict(value=idx.size * n_outer / med, unit="cells/s", cores=threads, kind="oracle",
+                sample=(f"{idx.size} random cells (seed {seed}) of the {w['n_cells']} of the same "
+                        f"workload, all {n_outer} outer steps (perturbation untimed), oracle "
+                        f"built -O3 -march=native, OpenMP over {threads} threads; median of "
+                        f"{reps} runs ({med:.1f} s)"),
+                seconds=times, single_thread=dict(cells=int(min(n_single, idx.size)),
+                                                  seconds=t1,
+                                                  value=min(n_single, idx.size) * n_outer / t1),
+                cpu_model=_cpu_model(), nproc=os.cpu_count(), affinity=affinity,
+                native_equals_O2_build=bool(np.array_equal(y2, y3)),
+                _idx=idx, _y=y)
+
+
+def parity_summary(y, yo, rtol, atol):
+    """Fraction of entries within 10 rtol |y_oracle| + atol, the worst entry
+    over that bar, and the worst in units of 100 error weights."""
+    err = np.abs(y - yo)
+    r10 = err / (10 * rtol * np.abs(yo) + atol)
+    r100 = err / (100 * (rtol * np.abs(yo) + atol))
+    frac = float(np.mean(r10 <= 1.0))
+    return dict(frac_within_10rtol=frac, worst_over_10rtol=float(r10.max()),
+                worst_over_100_weights=float(r100.max()),
+                parity_ok=bool(frac >= 0.99 and r100.max() <= 1.0))
+
+
+# ---------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="s21_r84_262k")
-    ap.add_argument("--cells", type=int, default=None)
-    ap.add_argument("--forms", default="plain,batched,batched_fp32lu")
-    ap.add_argument("--cpu-sample", type=int, default=262144)
+    ap.add_argument("--steps", type=int, default=10, help="timed outer steps of the headline")
+    ap.add_argument("--warmup", type=int, default=10, help="untimed outer steps before them")
+    ap.add_argument("--cells", type=int, default=None, help="fewer headline cells (testing)")
+    ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the headline workload's FP32-LU and plain forms")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 21-species legs")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-precision", action="store_true",
-                    help="skip the 53-species FP64 vs FP32-LU measurement")
+                    help="skip the 53-species legs (262,144 and 1,048,576 cells)")
     ap.add_argument("--extra", default="",
-                    help="comma list of longer measurements: 'batching' (1 M mixed cells, "
-                         "10 outer steps in a HIP graph), 's53_1m' (1 M cells of the "
-                         "53-species mechanism, FP64 and FP32 Newton matrix), 'typical' "
-                         "(typical-value tolerances: reduction bandwidth and integration), "
-                         "'thermal' (262,144 non-isothermal 21-species cells), 'dq' "
-                         "(difference-quotient vs analytic Jacobian), 'gmres' (matrix-free "
-                         "GMRES vs the direct solve over a 1e-8 s outer step), 'lockstep' "
-                         "(per-cell step control vs lock-step batches of 2, 4 and 8 cells)")
+                    help="comma list of longer measurements: 'typical' (typical-value "
+                         "tolerances: reduction bandwidth and integration), 'thermal' (262,144 "
+                         "non-isothermal 21-species cells), 'dq' (difference-quotient vs "
+                         "analytic Jacobian), 'gmres' (matrix-free GMRES vs the direct solve over "
+                         "a 1e-8 s outer step), 'lockstep' (per-cell step control vs lock-step "
+                         "batches of 2, 4 and 8 cells)")
     ap.add_argument("--tuning-cache", default=None,
                     help="JSON file of autotuned launch shapes (reused when present)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="first run a device copy of this many MiB (traffic scale reference)")
+    ap.add_argument("--pmc-step", action="store_true",
+                    help="run the headline form's first outer step once, eagerly, after the "
+                         "copy probe, and exit (for rocprofv3 --pmc counter runs)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc outputs and exit")
     args = ap.parse_args()
@@ -686,11 +856,11 @@ def main():
                                    "larger domain shards as contiguous cell ranges, one context "
                                    "per GPU, with no communication during integration)"}))
         sys.exit(2)
-
+    workload, form = "mixed_s9_s53_1m", "batched"
     if args.traffic_from:
-        form = args.forms.split(",")[0]
-        print(json.dumps(traffic_from(*args.traffic_from, args.copy_probe, args.workload, form)))
+        print(json.dumps(traffic_from(*args.traffic_from, args.copy_probe, workload, form)))
         return
+    w = W.make_workload(workload, args.cells)
     if args.copy_probe > 0:
         import torch
         n = int(args.copy_probe * 2**20) // 8
@@ -699,109 +869,99 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    w = W.make_workload(args.workload, args.cells)
-    m0 = w["mechs"][0]
-    fms = [flops_model(m) for m in w["mechs"]]
-    forms = {}
-    for form in args.forms.split(","):
-        r = run_form(w, form, args.steps, args.warmup, tuning_cache=args.tuning_cache)
-        log(f"{form}: {r['kernel_ms']:.1f} ms per step")
-        st = r["stats"]
-        f32lu = form == "batched_fp32lu"
-        if w["cell_mech"] is None:
-            F64, F32 = algorithmic_flops(st, fms[0], f32lu)
-        else:
-            parts = [algorithmic_flops(st[w["cell_mech"] == k], fms[k], f32lu) for k in range(len(fms))]
-            F64, F32 = sum(p[0] for p in parts), sum(p[1] for p in parts)
-        F = F64 + F32
-        t_s = r["kernel_ms"] * 1e-3
-        forms[form] = dict(kernel_ms=r["kernel_ms"], kernel_ms_min=r["kernel_ms_min"],
-                           wall_ms_per_step=r["wall_ms_per_step"],
-                           cells_per_s=w["n_cells"] / (r["kernel_ms"] * 1e-3),
-                           tflops=F / t_s / 1e12,
-                           # FP32 flops weighted by the FP64 : FP32 vector peak ratio
-                           fp64_equiv_tflops=(F64 + F32 * FP64_VECTOR_PEAK_TFLOPS
-                                              / FP32_VECTOR_PEAK_TFLOPS) / t_s / 1e12,
-                           fp64_flops=F64, fp32_flops=F32,
-                           failed_cells=int(np.sum(st["status"] != 0)),
-                           mean_nst=float(st["nst"].mean()), mean_nfe=float(st["nfe"].mean()),
-                           mean_nsetups=float(st["nsetups"].mean()), alg_flops=F,
-                           tuning=r["tuning"],
-                           # no positivity constraint is imposed: report how far below 0 it went
-                           min_y=float(r["y"].min()),
-                           n_below_minus_atol=int(np.sum(r["y"] < -np.asarray(w["atol"]))),
-                           # the linear invariant sum_i w_i y_i (exact with the FP64 solve)
-                           invariant_drift=_invariant_drift(w, r["y"]),
-                           _y=r["y"])
+    if args.pmc_step:
+        import torch
+        from paper_2405_01713_amd import bdfx
+        integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"],
+                                cell_mech=w["cell_mech"], **FORM_OPTS[form])
+        integ.autotune(0.0, w["t_out"], cache=args.tuning_cache)
+        y0 = integ.y.clone()
+        if args.copy_probe > 0:  # the probe must precede the measured launches
+            src = torch.ones(int(args.copy_probe * 2**20) // 8, dtype=torch.float64, device="cuda")
+            torch.empty_like(src).copy_(src)
+        integ.y.copy_(y0)
+        integ.perturb(3, 0, w["perturb"])
+        integ.integrate(0.0, w["t_out"])
+        torch.cuda.synchronize()
+        integ.close()
+        log("pmc step done")
+        return
+
+    head = run_outer_loop(w, form, args.steps, args.warmup, tuning_cache=args.tuning_cache)
+    log(f"headline {form}: {head['ms_per_outer_step']:.1f} ms per outer step")
+    y_head = head.pop("_y")
+    forms = {form: head}
+    if not args.no_forms:
+        for f in ("batched_fp32lu", "plain"):
+            r = run_outer_loop(w, f, w["outer_steps"], 0, tuning_cache=args.tuning_cache,
+                               account=False)
+            r["_y_sample"] = r.pop("_y")
+            forms[f] = r
+            log(f"headline workload {f}: {r['ms_per_outer_step']:.1f} ms per outer step")
 
     cpu = None
     if not args.no_cpu:
         c = cpu_baseline(w, args.cpu_sample)
         log(f"cpu baseline: {c['value']:.0f} cells/s on {c['cores']} threads")
-        for form, f in forms.items():
-            yg = f["_y"][c["idx"]]
-            err = np.abs(yg - c["y"])
-            r10 = err / (10 * w["rtol"] * np.abs(c["y"]) + w["atol"])
-            r100 = err / (100 * (w["rtol"] * np.abs(c["y"]) + w["atol"]))
-            f["parity_frac_within_10rtol"] = float(np.mean(r10 <= 1.0))
-            f["parity_max_err_over_10rtol"] = float(r10.max())
-            f["parity_ok"] = bool(f["parity_frac_within_10rtol"] >= 0.99 and r100.max() <= 1.0)
-        cpu = {"value": c["value"], "unit": "cells/s", "cores": c["cores"], "kind": "oracle",
-               "sample": f"first {len(c['idx'])} of {w['n_cells']} cells of the same workload, "
-                         f"one outer step, OpenMP over host cores ({c['seconds']:.1f} s)"}
-    for f in forms.values():
-        f.pop("_y")
+        idx, yo = c.pop("_idx"), c.pop("_y")
+        head["vs_oracle"] = dict(parity_summary(y_head[idx], yo, w["rtol"], w["atol"]),
+                                 cells=int(idx.size))
+        for f, r in forms.items():
+            if f != form:
+                r["vs_oracle"] = dict(parity_summary(r.pop("_y_sample")[idx], yo, w["rtol"],
+                                                     w["atol"]), cells=int(idx.size))
+        cpu = c
+    for r in forms.values():
+        r.pop("_y_sample", None)
 
-    adj = None if args.no_adjoint else run_adjoint(args.steps, args.warmup)
-    prec = (None if args.no_precision else
-            run_precision(args.steps, args.warmup, tuning_cache=args.tuning_cache))
+    t_step = head["ms_per_outer_step"] * 1e-3
+    F64, F32 = head["alg_flops_fp64_per_outer_step"], head["alg_flops_fp32_per_outer_step"]
+    frac = roofline_frac(F64, F32, t_step)
+    roof = {"bound": "alu", "achieved": frac * FP64_VECTOR_PEAK_TFLOPS,
+            "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": frac,
+            "traffic": stored_traffic(workload, form), "kernel": "bdfx::k_integrate",
+            "launches_per_outer_step": len(head.get("tuning") or w["mechs"]),
+            "flops_per_outer_step": F64 + F32,
+            "alg_bytes_per_outer_step": int(sum(
+                (16 * int(w["mechs"][k]["n_species"]) + 56) * int(np.sum(w["cell_mech"] == k))
+                for k in range(len(w["mechs"]))))}
     extra = {}
-    if "batching" in args.extra.split(","):
-        extra["batching"] = run_batching(1, 1, tuning_cache=args.tuning_cache)
-    if "s53_1m" in args.extra.split(","):
-        extra["s53_1m"] = run_precision(1, 1, tuning_cache=args.tuning_cache, n_cells=1 << 20)
-    if "typical" in args.extra.split(","):
-        extra["typical"] = run_typical(tuning_cache=args.tuning_cache)
-    if "thermal" in args.extra.split(","):
-        extra["thermal"] = run_thermal(tuning_cache=args.tuning_cache)
-    if "dq" in args.extra.split(","):
-        extra["dq"] = run_dq(tuning_cache=args.tuning_cache)
-    if "gmres" in args.extra.split(","):
-        extra["gmres"] = run_gmres(tuning_cache=args.tuning_cache)
-    if "lockstep" in args.extra.split(","):
-        extra["lockstep"] = run_lockstep(tuning_cache=args.tuning_cache)
-    ok = {k: v for k, v in forms.items() if v.get("parity_ok", True) and v["failed_cells"] == 0}
-    best = max(ok or forms, key=lambda k: forms[k]["cells_per_s"])
-    b = forms[best]
-    # achieved: algorithmic flops per second, FP32 flops (FP32 inverse form)
-    # counted at the FP64 : FP32 peak ratio, so that frac = F64 / t / P64 + F32 / t / P32
-    roof = {"bound": "alu", "achieved": b["fp64_equiv_tflops"], "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": b["fp64_equiv_tflops"] / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": stored_traffic(args.workload, best),
-            "kernel": "bdfx::k_integrate", "flops_per_launch": b["alg_flops"],
-            "alg_bytes_per_launch": w["n_cells"] * (16 * max(m["n_species"] for m in w["mechs"]) + 56)}
+    if not args.no_c1:
+        extra["s21_r84_262k"] = run_c1(3, 1, tuning_cache=args.tuning_cache)
+    if not args.no_adjoint:
+        extra["adjoint"] = run_adjoint(3, 1)
+    if not args.no_precision:
+        extra["s53_r325_262k_fp32lu"] = run_precision(3, 1, tuning_cache=args.tuning_cache)
+        extra["s53_r325_1m"] = run_precision(1, 1, tuning_cache=args.tuning_cache,
+                                             n_cells=1 << 20)
+    for name, fn in (("typical", run_typical), ("thermal", run_thermal), ("dq", run_dq),
+                     ("gmres", run_gmres), ("lockstep", run_lockstep)):
+        if name in args.extra.split(","):
+            extra[name] = fn(tuning_cache=args.tuning_cache)
+    parity = head.get("vs_oracle", {}).get("parity_ok")
     out = {
         "metric": "cells integrated/s per outer step @rtol 1e-6",
-        "value": b["cells_per_s"],
+        "value": head["cells_per_s"],
         "unit": "cells/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": b["kernel_ms"],
+        "ms_per_step": head["ms_per_outer_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if best != "batched_fp32lu" else "f64 (LU f32)",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n_cells": w["n_cells"],
+        "config": {"workload": workload, "n_cells": w["n_cells"],
                    "species": [m["n_species"] for m in w["mechs"]],
                    "reactions": [m["n_reactions"] for m in w["mechs"]],
-                   "dt": w["t_out"], "rtol": w["rtol"], "atol": w["atol"], "form": best},
+                   "outer_steps_per_graph": w["outer_steps"], "dt": w["t_out"],
+                   "perturbation": w["perturb"], "rtol": w["rtol"], "atol": w["atol"],
+                   "form": form},
+        "parity_ok": parity,
         "roofline": roof,
         "cpu_baseline": cpu,
         "forms": forms,
-        "adjoint": adj,
-        "precision": prec,
         **extra,
     }
     print(json.dumps(out))

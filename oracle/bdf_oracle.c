@@ -787,6 +787,12 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
       status = ORC_TOO_MUCH_WORK;
       break;
     }
+    if (rec && rec->n >= rec->cap) {
+      /* the record is full and time is left: stop at the last recorded step,
+       * so that the returned state is the end point of the recorded map */
+      status = ORC_RECORD_FULL;
+      break;
+    }
     orc_ewt(n, S, z[0], o, ewt); /* from y^{n-1}, held through retries */
     int nef_step = 0, ncf_step = 0, nsf_step = 0;
     double dsm = 0.0, tn = t, gamma = h;
@@ -946,13 +952,6 @@ static int32_t orc_integrate_core(const orc_sys *s, const orc_opts *o, double t0
       accepted = 1;
     }
     if (status != ORC_SUCCESS) break;
-    if (rec && rec->n >= rec->cap) {
-      /* the record is full: the cell stops at its last recorded step, so the
-       * returned state is the end point of the recorded (differentiable) map */
-      orc_unpredict(n, q, z);
-      status = ORC_RECORD_FULL;
-      break;
-    }
 
     /* accept: correct the Nordsieck array */
     t = tn;
@@ -1680,18 +1679,20 @@ double orc_perturb_uniform(uint64_t seed, int64_t step, int64_t cell, int32_t sp
 }
 
 /* y_i <- max(0, y_i (1 + amp u_i)), then rescale the cell so that
- * sum_i w_i y_i keeps its value from before the perturbation. */
-void orc_perturb_batch(int64_t N, const int32_t *n_species_of_cell, int32_t ldy, double *y,
-                       const double *const *weights_of_cell, uint64_t seed, int64_t step,
-                       double amp) {
+ * sum_i w_i y_i keeps its value from before the perturbation.  Row c of y is
+ * the cell with index cell_index[c] (NULL: c) in the perturbation's key. */
+void orc_perturb_cells(int64_t N, const int64_t *cell_index, const int32_t *n_species_of_cell,
+                       int32_t ldy, double *y, const double *const *weights_of_cell,
+                       uint64_t seed, int64_t step, double amp) {
   for (int64_t c = 0; c < N; ++c) {
     int S = n_species_of_cell[c];
     const double *w = weights_of_cell[c];
+    const int64_t cell = cell_index ? cell_index[c] : c;
     double *yc = y + c * ldy;
     double before = 0.0, after = 0.0;
     for (int i = 0; i < S; ++i) before += w[i] * yc[i];
     for (int i = 0; i < S; ++i) {
-      double v = yc[i] * (1.0 + amp * orc_perturb_uniform(seed, step, c, i));
+      double v = yc[i] * (1.0 + amp * orc_perturb_uniform(seed, step, cell, i));
       yc[i] = v > 0.0 ? v : 0.0;
       after += w[i] * yc[i];
     }
@@ -1700,4 +1701,11 @@ void orc_perturb_batch(int64_t N, const int32_t *n_species_of_cell, int32_t ldy,
       for (int i = 0; i < S; ++i) yc[i] *= s;
     }
   }
+}
+
+/* The rows of y are the cells 0..N-1. */
+void orc_perturb_batch(int64_t N, const int32_t *n_species_of_cell, int32_t ldy, double *y,
+                       const double *const *weights_of_cell, uint64_t seed, int64_t step,
+                       double amp) {
+  orc_perturb_cells(N, NULL, n_species_of_cell, ldy, y, weights_of_cell, seed, step, amp);
 }

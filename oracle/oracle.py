@@ -138,6 +138,8 @@ def load(path):
         L.orc_perturb_uniform.restype = C.c_double
         L.orc_perturb_batch.argtypes = [C.c_int64, P, C.c_int32, P, P, C.c_uint64, C.c_int64,
                                         C.c_double]
+        L.orc_perturb_cells.argtypes = [C.c_int64, P, P, C.c_int32, P, P, C.c_uint64,
+                                        C.c_int64, C.c_double]
         L.orc_lte_lower.argtypes = [C.c_int, C.c_int, P, P]
         L.orc_lte_lower.restype = C.c_double
         L.orc_lte_higher.argtypes = [C.c_int, C.c_int, P, P, C.c_double, C.c_double, P]
@@ -493,20 +495,44 @@ def perturb_uniform(seed, step, cell, species):
     return float(lib().orc_perturb_uniform(int(seed), int(step), int(cell), int(species)))
 
 
-def perturb(y, n_species_of_cell, weights_of_cell, seed, step, amp):
-    """In-place style: returns a perturbed copy of y ([N][ldy])."""
+def perturb(y, n_species_of_cell, weights_of_cell, seed, step, amp, cell_index=None):
+    """Returns a perturbed copy of y ([N][ldy]); row c is the cell with index
+    cell_index[c] (default c) in the perturbation's key."""
     y = np.array(y, dtype=np.float64, order="C", copy=True)
     N, ldy = y.shape
     ns = np.ascontiguousarray(n_species_of_cell, dtype=np.int32)
     ws = [np.ascontiguousarray(w, dtype=np.float64) for w in weights_of_cell]
-    uniq = {}
     ptrs = (C.c_void_p * N)()
     for c in range(N):
         ptrs[c] = ws[c].ctypes.data
-    lib().orc_perturb_batch(N, _p(ns), ldy, _p(y), C.cast(ptrs, C.c_void_p), int(seed),
+    ci = None if cell_index is None else np.ascontiguousarray(cell_index, dtype=np.int64)
+    lib().orc_perturb_cells(N, _p(ci), _p(ns), ldy, _p(y), C.cast(ptrs, C.c_void_p), int(seed),
                             int(step), float(amp))
-    del uniq
     return y
+
+
+def outer_loop(mechs, y0, cell_index, cell_mech, n_outer, dt, seed, amp, rtol, atol, T=None,
+               integrate_seconds=None, **kw):
+    """The operator-splitting outer loop on the cells ``cell_index`` of a
+    batch (rows of y0, mechanisms cell_mech, temperatures T): for outer step
+    k, perturb (keyed by the cells' own indices), then integrate over
+    [k dt, (k+1) dt].  Returns (y, stats of the last step).  If
+    ``integrate_seconds`` is a list, the wall time of each integration is
+    appended to it (the perturbation is not timed)."""
+    import time
+
+    y = np.array(y0, dtype=np.float64, copy=True)
+    S_of = [int(mechs[m]["n_species"]) for m in cell_mech]
+    W_of = [mechs[m]["w"] for m in cell_mech]
+    st = None
+    for k in range(n_outer):
+        y = perturb(y, S_of, W_of, seed, k, amp, cell_index=cell_index)
+        t = time.perf_counter()
+        y, st = integrate(mechs, y, k * dt, (k + 1) * dt, rtol, atol, T=T, cell_mech=cell_mech,
+                          **kw)
+        if integrate_seconds is not None:
+            integrate_seconds.append(time.perf_counter() - t)
+    return y, st
 
 
 def typical_atol(y, eta, n_species, cell_mech=None):

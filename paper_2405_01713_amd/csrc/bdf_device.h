@@ -1340,6 +1340,12 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       status = kTooMuchWork;
       break;
     }
+    if (P.rec && nst >= P.rec_cap) {
+      // the record is full and time is left: stop at the last recorded step,
+      // so that the returned state is the end point of the recorded map
+      status = kRecordFull;
+      break;
+    }
     ewt = own ? rcp(rtol * fabs(z[0]) + atol_i) : 0.0;  // from y^{n-1}, Eq. (3)
     int nef_step = 0, ncf_step = 0, nsf_step = 0;
     double dsm2 = 0.0, Cerr = 0.5;
@@ -1519,13 +1525,6 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       }
     }
     if (status != kSuccess) break;
-    if (P.rec && nst >= P.rec_cap) {
-      // the record is full: stop at the last recorded step, so that the
-      // returned state is the end point of the recorded map
-      nd_unpredict(z);
-      status = kRecordFull;
-      break;
-    }
 
     // accept: correct the Nordsieck array
     t = W.uni(C[Ctl::kTn]);

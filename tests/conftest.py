@@ -19,11 +19,14 @@ def oracle():
     return O
 
 
-def assert_parity(y, yo, w, oracle, label="", reference=None):
+def assert_parity(y, yo, w, oracle, label="", reference=None, min_frac=0.999):
     """GPU vs oracle for an adaptive integration.
 
-    (a) the spec bar |dy| <= 10 rtol |y_oracle| + atol holds for >= 99 %
-        of entries;
+    (a) the spec bar |dy| <= 10 rtol |y_oracle| + atol holds for
+        >= min_frac of entries: 99.9 % by default (the oracle against itself
+        with inputs perturbed by 1e-15 keeps 99.98-100 % on the benchmark
+        workloads); 99 % for the sparse 40-species / 70-reaction test
+        mechanism, where the oracle against itself keeps only 99.67-99.75 %;
     (b) every entry is within 100 units of the error weights of Eq. (3),
         100 (rtol |y_oracle| + atol) -- the global-accuracy envelope (the
         oracle's own global error reaches ~25 units on these workloads);
@@ -44,7 +47,7 @@ def assert_parity(y, yo, w, oracle, label="", reference=None):
     err = np.abs(y - yo)
     r10 = err / tol10
     frac_ok = float(np.mean(r10 <= 1.0))
-    assert frac_ok >= 0.99, f"{label}: only {frac_ok:.4f} of entries within 10 rtol |y| + atol"
+    assert frac_ok >= min_frac, f"{label}: only {frac_ok:.4f} of entries within 10 rtol |y| + atol"
     r100 = err / (100 * (rtol * np.abs(yo) + atol))
     assert np.all(r100 <= 1.0), f"{label}: worst |dy| / (100 (rtol |y| + atol)) = {r100.max():.3g}"
     bad_cells = np.nonzero(np.any(r10 > 1.0, axis=1))[0]
@@ -130,4 +133,4 @@ def assert_parity_global(y, yo, w, oracle, label="", min_frac=0.88):
 
 @pytest.fixture
 def parity(oracle):
-    return lambda y, yo, w, label="": assert_parity(y, yo, w, oracle, label)
+    return lambda y, yo, w, label="", **kw: assert_parity(y, yo, w, oracle, label, **kw)

