@@ -99,6 +99,16 @@ typedef struct {
 /* Scheduler for bdfx_options.scheduler */
 #define BDFX_SCHED_STATIC 0 /* one lane group per cell, grid covers every cell */
 #define BDFX_SCHED_QUEUE 1  /* persistent waves pop cells from an atomic work queue */
+#define BDFX_SCHED_FUSED 2  /* as BDFX_SCHED_QUEUE, and a batch of two mechanisms runs in
+                               one launch: each block holds waves for both, the larger
+                               mechanism's cells start first and the smaller one's run
+                               beside them and in the tail (the load balancing of uneven
+                               cells, Sec. 2 and Sec. 4.1.1).  Applies to isothermal
+                               A + B <=> C mechanisms on the direct solver with the analytic
+                               Jacobian whose padded sizes have a compiled pair (53 with 9);
+                               otherwise the bins are launched one after the other.  One
+                               cell per wave.  Results equal the BDFX_SCHED_QUEUE ones bit
+                               for bit. */
 
 typedef struct {
   double rtol;           /* relative tolerance of Eq. (3), > 0 */
@@ -339,6 +349,10 @@ typedef struct {
                               2 slot words and the cell's rate constants in global memory
                               (a per-wave workspace slot; work-queue scheduler, one cell per
                               wave, 32 species or more).  Ignored by bdfx_set_tuning(). */
+  int32_t fused;           /* out: 1 if the mechanisms' cells run in one launch
+                              (BDFX_SCHED_FUSED with an eligible pair), with the larger
+                              mechanism's register budget and table placement.  Ignored by
+                              bdfx_set_tuning(). */
 } bdfx_tuning;
 
 /* Autotuner: for every mechanism, times each candidate launch shape

@@ -74,11 +74,16 @@ _lib = None
 
 
 def lib():
+    """The oracle library: liboracle.so, built on first use, or the build named
+    by the environment variable BDFX_ORACLE_LIB (e.g. a sanitizer build)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
-            build()
-        _lib = load(LIB)
+        path = os.environ.get("BDFX_ORACLE_LIB")
+        if not path:
+            path = LIB
+            if not os.path.exists(LIB):
+                build()
+        _lib = load(path)
     return _lib
 
 

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(PKG, "libbdfx.so")
 BDFX_OK = 0
 BDFX_SCHED_STATIC = 0
 BDFX_SCHED_QUEUE = 1
+BDFX_SCHED_FUSED = 2
 BDFX_JAC_ANALYTIC, BDFX_JAC_DQ = 0, 1
 BDFX_GMRES_MAXL = 10
 BDFX_MAX_LOCKSTEP = 16
@@ -71,7 +72,7 @@ class Tuning(C.Structure):
     _fields_ = [("mech", C.c_int32), ("waves_per_simd", C.c_int32),
                 ("waves_per_block", C.c_int32), ("queue_chunk", C.c_int32),
                 ("sample_cells", C.c_int64), ("ms", C.c_float), ("cells_per_wave", C.c_int32),
-                ("tables", C.c_int32)]
+                ("tables", C.c_int32), ("fused", C.c_int32)]
 
 
 STATS_DTYPE = np.dtype([("status", np.int32), ("nst", np.int32), ("nfe", np.int32),
@@ -254,7 +255,7 @@ def bdfx_get_record_layout(ctx) -> dict:
 
 
 _TUNING_KEYS = ("mech", "waves_per_simd", "waves_per_block", "queue_chunk", "cells_per_wave",
-                "sample_cells", "ms", "tables")
+                "sample_cells", "ms", "tables", "fused")
 
 
 def bdfx_autotune(ctx, n_mech: int, t0: float, t_out: float, sample_cells: int = 0) -> list:

@@ -95,6 +95,7 @@ struct Params {
   int32_t n_sp;           // species of the mechanism (<= template S)
   int32_t gmres_maxl;     // Krylov vectors per GMRES solve (GMRES kernels only)
   int32_t lds_doubles;    // LDS per wave
+  int32_t pair_waves;     // k_integrate_pair: waves per block of the larger mechanism
   int32_t use_queue;      // 0: one cell per wave from the grid index; 1: work queue
   uint32_t *queue;
   int32_t chunk;

@@ -85,6 +85,82 @@ __global__ void __launch_bounds__(LOCK ? kWave * kMaxBatch : 256, MINW) k_integr
   }
 }
 
+// Two mechanism bins in one persistent launch (several mechanism sizes in one
+// grid).  Each block holds PA.pair_waves waves for the larger mechanism (bin A,
+// padded size SA, table placement TABA) followed by the rest of its waves for
+// the smaller one (bin B, padded size SB, tables in LDS), each wave with an
+// LDS area for its own bin.  A-waves pop cells of bin A and, once its queue is
+// exhausted, cells of bin B (an A area holds a B cell); B-waves pop cells of
+// bin B only.  The large cells start first; the small ones run beside them,
+// in the issue slots the A-waves leave while they wait, and then in the tail
+// of bin A.  Every cell runs the integrate_cell code of its own bin's launch
+// (one cell per wave, A + B <=> C mechanisms, isothermal, direct solver with
+// the analytic Jacobian), so results do not depend on the launch.
+template <int SA, int SB, typename LT, int MINW, int TABA>
+__global__ void __launch_bounds__(256, MINW) k_integrate_pair(Params PA, Params PB) {
+  extern __shared__ double smem[];
+  const int wib = threadIdx.x / kWave;
+  const Grp<1> W(threadIdx.x & (kWave - 1));
+  const int wa = PA.pair_waves;
+  const bool is_a = wib < wa;
+  double *lds = is_a ? smem + static_cast<int64_t>(wib) * PA.lds_doubles
+                     : smem + static_cast<int64_t>(wa) * PA.lds_doubles +
+                           static_cast<int64_t>(wib - wa) * PB.lds_doubles;
+  double *kk_slot = nullptr;
+  if constexpr (TABA == kTabGlobal)
+    if (is_a) kk_slot = PA.kk_slots + (static_cast<int64_t>(blockIdx.x) * wa + wib) * (2 * PA.mech.R);
+  int64_t next = 0, stop = 0;
+  if (is_a) {
+    for (;;) {
+      if (next >= stop) {
+        unsigned int base = 0;
+        if (W.lane == 0) base = atomicAdd(PA.queue, static_cast<unsigned int>(PA.chunk));
+        next = W.from_lane0(static_cast<int>(base));
+        stop = next + PA.chunk;
+      }
+      if (next >= PA.n_list) break;
+      const int64_t cell = PA.list ? PA.list[next] : next;
+      ++next;
+      integrate_cell<SA, LT, TABA, 1, true, false, kLinAnalytic>(PA, cell, W, lds, kk_slot);
+    }
+  }
+  next = stop = 0;
+  for (;;) {
+    if (next >= stop) {
+      unsigned int base = 0;
+      if (W.lane == 0) base = atomicAdd(PB.queue, static_cast<unsigned int>(PB.chunk));
+      next = W.from_lane0(static_cast<int>(base));
+      stop = next + PB.chunk;
+    }
+    if (next >= PB.n_list) break;
+    const int64_t cell = PB.list ? PB.list[next] : next;
+    ++next;
+    integrate_cell<SB, LT, kTabLds, 1, true, false, kLinAnalytic>(PB, cell, W, lds, nullptr);
+  }
+}
+
+template <int SA, int SB>
+const void *pair_kernel(bool fp32, int minw, int taba) {
+  using F = const void *;
+  const int w = minw >= 4 ? 2 : minw >= 3 ? 1 : 0;
+  static const F t64[3][3] = {
+      {F(&k_integrate_pair<SA, SB, double, 1, kTabRxGlobal>), F(&k_integrate_pair<SA, SB, double, 1, kTabLds>),
+       F(&k_integrate_pair<SA, SB, double, 1, kTabGlobal>)},
+      {F(&k_integrate_pair<SA, SB, double, 3, kTabRxGlobal>), F(&k_integrate_pair<SA, SB, double, 3, kTabLds>),
+       F(&k_integrate_pair<SA, SB, double, 3, kTabGlobal>)},
+      {F(&k_integrate_pair<SA, SB, double, 4, kTabRxGlobal>), F(&k_integrate_pair<SA, SB, double, 4, kTabLds>),
+       F(&k_integrate_pair<SA, SB, double, 4, kTabGlobal>)}};
+  static const F t32[3][3] = {
+      {F(&k_integrate_pair<SA, SB, float, 1, kTabRxGlobal>), F(&k_integrate_pair<SA, SB, float, 1, kTabLds>),
+       F(&k_integrate_pair<SA, SB, float, 1, kTabGlobal>)},
+      {F(&k_integrate_pair<SA, SB, float, 3, kTabRxGlobal>), F(&k_integrate_pair<SA, SB, float, 3, kTabLds>),
+       F(&k_integrate_pair<SA, SB, float, 3, kTabGlobal>)},
+      {F(&k_integrate_pair<SA, SB, float, 4, kTabRxGlobal>), F(&k_integrate_pair<SA, SB, float, 4, kTabLds>),
+       F(&k_integrate_pair<SA, SB, float, 4, kTabGlobal>)}};
+  if (taba < 0 || taba > 2) return nullptr;
+  return fp32 ? t32[w][taba] : t64[w][taba];
+}
+
 template <int S>
 __global__ void __launch_bounds__(256) k_adjoint(Params P) {
   extern __shared__ double smem[];
@@ -249,6 +325,39 @@ hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave,
   hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s) { \
     return bdfx::launch_adjoint<S>(P, c, s);                                                     \
   }
+
+// Both bins of a two-mechanism batch in one launch (k_integrate_pair).
+#define BDFX_DEFINE_PAIR(SA, SB)                                                                 \
+  hipError_t bdfx_launch_pair_s##SA##_s##SB(const bdfx::Params &PA, const bdfx::Params &PB,      \
+                                            bool fp32, int minw, int taba,                       \
+                                            const bdfx::LaunchCfg &c, hipStream_t s) {           \
+    const void *f = bdfx::pair_kernel<SA, SB>(fp32, minw, taba);                                 \
+    if (!f) return hipErrorInvalidDeviceFunction;                                                \
+    bdfx::Params a = PA, b = PB;                                                                 \
+    void *args[] = {&a, &b};                                                                     \
+    return hipLaunchKernel(f, dim3(c.grid), dim3(c.block), args, c.lds_bytes, s);                \
+  }                                                                                              \
+  /* blocks per CU for this block size and LDS; lds above 64 KiB is first allowed for the     */ \
+  /* kernel (the device's per-block maximum bounds it)                                         */ \
+  hipError_t bdfx_occupancy_pair_s##SA##_s##SB(bool fp32, int minw, int taba, int block,         \
+                                               size_t lds, int *out) {                           \
+    const void *f = bdfx::pair_kernel<SA, SB>(fp32, minw, taba);                                 \
+    *out = 0;                                                                                    \
+    if (!f) return hipSuccess;                                                                   \
+    if (lds > 65536) {                                                                           \
+      const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,    \
+                                               static_cast<int>(lds));                           \
+      if (e != hipSuccess) return e;                                                             \
+    }                                                                                            \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, f, block, lds);                     \
+  }
+
+#define BDFX_DECLARE_PAIR(SA, SB)                                                                \
+  hipError_t bdfx_launch_pair_s##SA##_s##SB(const bdfx::Params &PA, const bdfx::Params &PB,      \
+                                            bool fp32, int minw, int taba,                       \
+                                            const bdfx::LaunchCfg &c, hipStream_t s);            \
+  hipError_t bdfx_occupancy_pair_s##SA##_s##SB(bool fp32, int minw, int taba, int block,         \
+                                               size_t lds, int *out);
 
 #define BDFX_DECLARE_SIZE(S)                                                                     \
   hipError_t bdfx_launch_s##S(const bdfx::Params &P, bool fp32, int minw, int tab, int cpw,      \

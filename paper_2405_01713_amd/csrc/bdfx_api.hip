@@ -28,6 +28,7 @@ BDFX_DECLARE_SIZE(21)
 BDFX_DECLARE_SIZE(32)
 BDFX_DECLARE_SIZE(53)
 BDFX_DECLARE_SIZE(64)
+BDFX_DECLARE_PAIR(53, 9)
 
 hipError_t bdfx_launch_perturb(const bdfx::Params &P, uint64_t seed, int64_t step, double amp,
                                hipStream_t s);
@@ -75,6 +76,25 @@ const SizeEntry *size_for(int S) {
   return nullptr;
 }
 
+// Compiled pairs of padded sizes for the one-launch form of two-mechanism
+// batches (k_integrate_pair): larger size first.
+struct PairEntry {
+  int SA, SB;
+  hipError_t (*launch)(const bdfx::Params &, const bdfx::Params &, bool, int, int,
+                       const bdfx::LaunchCfg &, hipStream_t);
+  hipError_t (*occupancy)(bool, int, int, int, size_t, int *);
+};
+
+const PairEntry kPairs[] = {
+    {53, 9, bdfx_launch_pair_s53_s9, bdfx_occupancy_pair_s53_s9},
+};
+
+const PairEntry *pair_for(int SA, int SB) {
+  for (const auto &e : kPairs)
+    if (e.SA == SA && e.SB == SB) return &e;
+  return nullptr;
+}
+
 }  // namespace
 
 // largest per-bin sample the autotuner times (rows saved in the workspace)
@@ -118,6 +138,7 @@ struct bdfx_ctx_s {
   hipStream_t stream = nullptr;
   std::string err;
   int n_cu = 0;
+  int lds_max_block = 65536;  // LDS one block may allocate on the device
   // plan
   bool planned = false, bound = false, integrated = false;
   int64_t N = 0;
@@ -142,6 +163,12 @@ struct bdfx_ctx_s {
   int32_t *status = nullptr;
   bdfx_cell_stats *stats = nullptr;
   std::vector<Bin> bins;
+  // BDFX_SCHED_FUSED: both bins in one launch (nullptr: one launch per bin)
+  const PairEntry *pair = nullptr;
+  int pair_a = 0, pair_b = 1;    // bin indices of the larger and the smaller mechanism
+  int pair_waves = 1;            // A-waves per block (the rest of the block's waves are B-waves)
+  int32_t pair_lds_b = 0;        // LDS doubles of a bin-B wave (tables in LDS)
+  bdfx::LaunchCfg pair_cfg{};
   double last_t0 = 0.0, last_tout = 0.0;
 };
 
@@ -185,7 +212,9 @@ int bdfx_create(bdfx_ctx *out, int device, void *hip_stream) {
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   if (hipSetDevice(device) != hipSuccess ||
-      hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+      hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      hipDeviceGetAttribute(&c->lds_max_block, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+          hipSuccess) {
     delete c;
     return fail(nullptr, BDFX_EHIP, "cannot query device %d", device);
   }
@@ -350,7 +379,8 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
   if (!o->atol || o->atol_len < 1) return fail(ctx, BDFX_EINVAL, "atol required");
   if (o->lu_precision != 0 && o->lu_precision != 64 && o->lu_precision != 32)
     return fail(ctx, BDFX_EINVAL, "lu_precision must be 64 or 32");
-  if (o->scheduler != BDFX_SCHED_STATIC && o->scheduler != BDFX_SCHED_QUEUE)
+  if (o->scheduler != BDFX_SCHED_STATIC && o->scheduler != BDFX_SCHED_QUEUE &&
+      o->scheduler != BDFX_SCHED_FUSED)
     return fail(ctx, BDFX_EINVAL, "unknown scheduler %d", o->scheduler);
   if (o->waves_per_simd != 0 && o->waves_per_simd != 3 && o->waves_per_simd != 4)
     return fail(ctx, BDFX_EINVAL, "waves_per_simd must be 0, 3 or 4");
@@ -433,7 +463,7 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
   ctx->tune_cells = std::min<int64_t>(n_cells, kTuneCells);
   ctx->off_tune = reserve(static_cast<size_t>(ctx->tune_cells) * S_max * 8);
   // persistent grids may keep each wave's rate constants in global memory
-  ctx->kk_slots = o->scheduler == BDFX_SCHED_QUEUE
+  ctx->kk_slots = o->scheduler != BDFX_SCHED_STATIC
                       ? std::min<int64_t>(static_cast<int64_t>(ctx->n_cu) * kMaxWavesPerCu, n_cells + 16)
                       : 0;
   ctx->off_kk = reserve(static_cast<size_t>(ctx->kk_slots) * 2 * R_max * 8);
@@ -458,7 +488,7 @@ static int kernel_flags(bdfx_ctx ctx, bdfx_mech m) {
 // context's options (isothermal, analytic Jacobian, direct solver)
 static bool two_cells_per_wave_ok(bdfx_ctx ctx, bdfx_mech m, int S) {
   return S <= 32 && !m->thermal && ctx->opt.jacobian != BDFX_JAC_DQ && ctx->opt.gmres_maxl == 0 &&
-         ctx->opt.lockstep == 0;
+         ctx->opt.lockstep == 0 && ctx->opt.scheduler != BDFX_SCHED_FUSED;
 }
 
 int bdfx_bind(bdfx_ctx ctx, void *d_ws, size_t ws_bytes, double *d_y, int32_t ldy,
@@ -526,7 +556,7 @@ int bdfx_bind(bdfx_ctx ctx, void *d_ws, size_t ws_bytes, double *d_y, int32_t ld
 // Kernel, LDS size and grid of one bin from its launch shape.
 static int configure_bin(bdfx_ctx ctx, Bin &b) {
   const bool fp32 = ctx->opt.lu_precision == 32;
-  const bool queue = ctx->opt.scheduler == BDFX_SCHED_QUEUE;
+  const bool queue = ctx->opt.scheduler != BDFX_SCHED_STATIC;
   const bdfx_mech m = ctx->mechs[b.mech];
   b.se = size_for(m->n);
   if (!b.se) return fail(ctx, BDFX_EUNSUPPORTED, "no kernel for %d state entries", m->n);
@@ -588,6 +618,75 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
   return BDFX_OK;
 }
 
+// The one launch of a two-mechanism batch (BDFX_SCHED_FUSED): the bins of the
+// larger and the smaller mechanism become bins A and B of k_integrate_pair,
+// with bin A's register budget and table placement.  A block holds wa A-waves
+// and wb B-waves (wa + wb <= 4, LDS within the device's per-block limit); the
+// shape chosen keeps as many A-waves per CU as bin A's own launch has and,
+// among those, adds the most B-waves, which then run in the register and LDS
+// room A leaves.  The grid holds as many blocks as fit the GPU.  Used when
+// both mechanisms are isothermal A + B <=> C mechanisms on the direct solver
+// with the analytic Jacobian, their padded sizes form a compiled pair, an A
+// area holds a B cell and some shape keeps A's resident waves; otherwise
+// ctx->pair stays null and the bins are launched one after the other (one
+// cell per wave in either case).
+static int configure_pair(bdfx_ctx ctx) {
+  ctx->pair = nullptr;
+  if (ctx->opt.scheduler != BDFX_SCHED_FUSED || ctx->bins.size() != 2) return BDFX_OK;
+  if (ctx->opt.jacobian != BDFX_JAC_ANALYTIC || ctx->opt.gmres_maxl > 0 || ctx->opt.lockstep > 0)
+    return BDFX_OK;
+  int ia = 0, ib = 1;
+  if (ctx->bins[0].se->S < ctx->bins[1].se->S) std::swap(ia, ib);
+  const Bin &a = ctx->bins[ia], &b = ctx->bins[ib];
+  const bdfx_mech ma = ctx->mechs[a.mech], mb = ctx->mechs[b.mech];
+  if (a.count == 0 || b.count == 0 || !ma->abc || !mb->abc || ma->thermal || mb->thermal ||
+      a.cells_per_wave != 1 || b.cells_per_wave != 1)
+    return BDFX_OK;
+  const PairEntry *pe = pair_for(a.se->S, b.se->S);
+  if (!pe) return BDFX_OK;
+  const bool fp32 = ctx->opt.lu_precision == 32;
+  const int32_t lds_b = static_cast<int32_t>(
+      align_up(bdfx::lds_doubles(b.se->S, mb->R, fp32 ? 4 : 8, bdfx::kTabLds), 2));
+  if (a.lds_doubles < lds_b) return BDFX_OK;
+  // A-waves per CU in bin A's own launch
+  int occ_a = 0;
+  HIPCHK(ctx, a.se->occupancy(fp32, a.waves_per_simd, a.tab, 1, kernel_flags(ctx, ma),
+                              a.cfg.block, a.cfg.lds_bytes, &occ_a));
+  const int a_per_cu = occ_a * std::max(a.waves_per_block, 1);
+  int best_a = 0, best_b = 0, best_wa = 0, best_wb = 0, best_occ = 0;
+  for (int wa = 1; wa <= 3; ++wa)
+    for (int wb = 1; wa + wb <= 4; ++wb) {
+      const size_t lds = (static_cast<size_t>(wa) * a.lds_doubles + wb * lds_b) * 8;
+      if (lds > static_cast<size_t>(ctx->lds_max_block)) continue;
+      int occ = 0;
+      HIPCHK(ctx, pe->occupancy(fp32, a.waves_per_simd, a.tab, bdfx::kWave * (wa + wb), lds, &occ));
+      const int na = occ * wa, nb = occ * wb;
+      if (na > best_a || (na == best_a && nb > best_b)) {
+        best_a = na;
+        best_b = nb;
+        best_wa = wa;
+        best_wb = wb;
+        best_occ = occ;
+      }
+    }
+  if (best_occ < 1 || best_a < a_per_cu) return BDFX_OK;
+  const size_t lds = (static_cast<size_t>(best_wa) * a.lds_doubles + best_wb * lds_b) * 8;
+  int64_t grid = static_cast<int64_t>(ctx->opt.blocks_per_cu > 0 ? ctx->opt.blocks_per_cu : best_occ) *
+                 ctx->n_cu;
+  if (a.tab == bdfx::kTabGlobal) grid = std::min<int64_t>(grid, ctx->kk_slots / best_wa);
+  grid = std::min<int64_t>(grid, (a.count + b.count + best_wa + best_wb - 1) / (best_wa + best_wb));
+  if (grid < 1) return BDFX_OK;
+  ctx->pair = pe;
+  ctx->pair_a = ia;
+  ctx->pair_b = ib;
+  ctx->pair_waves = best_wa;
+  ctx->pair_lds_b = lds_b;
+  ctx->pair_cfg.grid = static_cast<int>(grid);
+  ctx->pair_cfg.block = bdfx::kWave * (best_wa + best_wb);
+  ctx->pair_cfg.lds_bytes = lds;
+  return BDFX_OK;
+}
+
 // Kernel, LDS size and grid of every bin (called by bdfx_bind).
 static int configure_bins(bdfx_ctx ctx) {
   for (Bin &b : ctx->bins) {
@@ -604,7 +703,7 @@ static int configure_bins(bdfx_ctx ctx) {
     }
     if (const int rc = configure_bin(ctx, b)) return rc;
   }
-  return BDFX_OK;
+  return configure_pair(ctx);
 }
 
 static bdfx::Params make_params(bdfx_ctx ctx, const Bin &b, double t0, double tout) {
@@ -662,9 +761,23 @@ int bdfx_integrate(bdfx_ctx ctx, double t0, double t_out) {
     return fail(ctx, BDFX_EINVAL, "need finite t_out > t0");
   HIPCHK(ctx, hipSetDevice(ctx->device));
   const bool fp32 = ctx->opt.lu_precision == 32;
-  const bool queue = ctx->opt.scheduler == BDFX_SCHED_QUEUE;
+  const bool queue = ctx->opt.scheduler != BDFX_SCHED_STATIC;
   if (queue) HIPCHK(ctx, bdfx_launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->ws + ctx->off_queue),
                                               64, 0u, ctx->stream));
+  if (ctx->pair) {
+    const Bin &a = ctx->bins[ctx->pair_a], &b = ctx->bins[ctx->pair_b];
+    bdfx::Params PA = make_params(ctx, a, t0, t_out), PB = make_params(ctx, b, t0, t_out);
+    PA.use_queue = PB.use_queue = 1;
+    PA.lds_doubles = a.lds_doubles;
+    PB.lds_doubles = ctx->pair_lds_b;
+    PA.pair_waves = PB.pair_waves = ctx->pair_waves;
+    HIPCHK(ctx, ctx->pair->launch(PA, PB, fp32, a.waves_per_simd, a.tab, ctx->pair_cfg,
+                                  ctx->stream));
+    ctx->last_t0 = t0;
+    ctx->last_tout = t_out;
+    ctx->integrated = true;
+    return BDFX_OK;
+  }
   for (const Bin &b : ctx->bins) {
     if (b.count == 0 || b.cfg.grid < 1) continue;
     bdfx::Params P = make_params(ctx, b, t0, t_out);
@@ -709,6 +822,12 @@ static bdfx_tuning tuning_of(const Bin &b) {
   return t;
 }
 
+static bdfx_tuning tuning_of(bdfx_ctx ctx, const Bin &b) {
+  bdfx_tuning t = tuning_of(b);
+  t.fused = ctx->pair != nullptr ? 1 : 0;
+  return t;
+}
+
 int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, bdfx_tuning *out) {
   if (!ctx) return BDFX_EINVAL;
   if (!ctx->bound) return fail(ctx, BDFX_EORDER, "bdfx_bind must precede bdfx_autotune");
@@ -716,11 +835,11 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
     return fail(ctx, BDFX_EINVAL, "need finite t_out > t0");
   HIPCHK(ctx, hipSetDevice(ctx->device));
   if (ctx->opt.lockstep > 0) {  // lock-step kernels have one launch shape: nothing to time
-    for (size_t bi = 0; bi < ctx->bins.size() && out; ++bi) out[bi] = tuning_of(ctx->bins[bi]);
+    for (size_t bi = 0; bi < ctx->bins.size() && out; ++bi) out[bi] = tuning_of(ctx, ctx->bins[bi]);
     return BDFX_OK;
   }
   const bool fp32 = ctx->opt.lu_precision == 32;
-  const bool queue = ctx->opt.scheduler == BDFX_SCHED_QUEUE;
+  const bool queue = ctx->opt.scheduler != BDFX_SCHED_STATIC;
   const int64_t ns = sample_cells > 0 ? std::min(sample_cells, ctx->tune_cells) : ctx->tune_cells;
   double *save = reinterpret_cast<double *>(ctx->ws + ctx->off_tune);
   uint32_t *qctr = reinterpret_cast<uint32_t *>(ctx->ws + ctx->off_queue);
@@ -794,10 +913,12 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
     b.tune_sample = trial.count;
     b.tune_ms = best / 2.0f;
     rc = configure_bin(ctx, b);
-    if (out) out[bi] = tuning_of(b);
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  if (rc == BDFX_OK) rc = configure_pair(ctx);
+  for (size_t bi = 0; bi < ctx->bins.size() && out && rc == BDFX_OK; ++bi)
+    out[bi] = tuning_of(ctx, ctx->bins[bi]);
   if (rc == BDFX_OK) {
     const hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return fail(ctx, BDFX_EHIP, "%s", hipGetErrorString(e));
@@ -826,7 +947,7 @@ int bdfx_set_tuning(bdfx_ctx ctx, const bdfx_tuning *t, int32_t n) {
         if (const int rc = configure_bin(ctx, b)) return rc;
       }
   }
-  return BDFX_OK;
+  return configure_pair(ctx);
 }
 
 int bdfx_typical_atol(bdfx_ctx ctx, double eta, double *d_typical) {
@@ -867,7 +988,7 @@ int bdfx_get_tuning(bdfx_ctx ctx, bdfx_tuning *out, int32_t n) {
   if (!ctx || (n > 0 && !out) || n < 0) return BDFX_EINVAL;
   if (!ctx->bound) return fail(ctx, BDFX_EORDER, "bdfx_bind must precede bdfx_get_tuning");
   for (int32_t k = 0; k < n && k < static_cast<int32_t>(ctx->bins.size()); ++k)
-    out[k] = tuning_of(ctx->bins[k]);
+    out[k] = tuning_of(ctx, ctx->bins[k]);
   return BDFX_OK;
 }
 

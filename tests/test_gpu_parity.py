@@ -118,6 +118,32 @@ def test_mixed_mechanisms_and_queue(oracle, parity):
         assert np.all(ys[c, S[c]:] == w["y0"][c, S[c]:])
 
 
+@pytest.mark.parametrize("lu", [64, 32])
+def test_fused_launch_matches_per_bin_launches(oracle, parity, lu):
+    """Both mechanism sizes in one launch (BDFX_SCHED_FUSED) give the results
+    of one launch per mechanism bit for bit; with the FP64 Newton matrix the
+    53-species cells keep their resident waves and the 9-species cells run
+    beside them, so the pair launch is taken."""
+    import torch
+    from paper_2405_01713_amd import bdfx
+    w = W.make_workload("mixed_s9_s53_1m", 3000)
+    out = {}
+    for sched in (1, 2):
+        integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"],
+                                cell_mech=w["cell_mech"], scheduler=sched, lu_precision=lu)
+        integ.integrate(0.0, w["t_out"])
+        torch.cuda.synchronize()
+        out[sched] = (integ.state(), integ.cell_stats(), integ.tuning())
+        integ.close()
+    (y1, st1, t1), (y2, st2, t2) = out[1], out[2]
+    assert np.array_equal(y1, y2) and np.array_equal(st1, st2)
+    assert all(t["fused"] == 0 for t in t1)
+    if lu == 64:
+        assert all(t["fused"] == 1 for t in t2), t2
+    yo, _ = _oracle(oracle, w)
+    parity(y2, yo, w, f"fused lu{lu}")
+
+
 @pytest.mark.parametrize("S,R,seed", [(2, 3, 0), (5, 9, 1), (12, 20, 2), (40, 70, 3)])
 def test_padded_sizes(oracle, parity, S, R, seed):
     m = W.synthetic_mechanism(S, R, seed) if S > 2 else W.unimolecular_mechanism(S, R, seed)
