@@ -290,6 +290,29 @@ int bdfx_perturb(bdfx_ctx ctx, uint64_t seed, int64_t outer_step, double amplitu
  * without cells).  Enqueue only (two kernels, no allocation, capturable).
  * Errors: BDFX_EINVAL for eta < 0 or not finite; BDFX_EORDER before bind. */
 int bdfx_typical_atol(bdfx_ctx ctx, double eta, double *d_typical);
+/* bdfx_typical_atol() for callers that cannot allocate device memory or bind
+ * a workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the typical-value tolerances of n_cells cells of
+ * one mechanism, with no context.
+ *   d_y       [n_cells][ldy] FP64 in   states (entries 0..n_species-1 read)
+ *   d_atol    [n_species] FP64 out     eta * ytyp_i, or eta where ytyp_i is
+ *                                      not positive (as bdfx_typical_atol())
+ *   d_typical [n_species] FP64 out     ytyp_i = 0.5 (min + max), or NULL
+ * Work is enqueued on hip_stream (hipStream_t, NULL = default stream) of HIP
+ * device `device`; the caller's current device is restored before return.
+ * Scratch: the per-block extremes live in a fixed 256 KiB device array of the
+ * library (room for 64 species), one copy per device, held until the process
+ * ends; the first call on a device looks up its address, no call allocates.
+ * Calls that overlap on one device (any streams) share that array and race:
+ * serialise them.  For the same states, the results equal bit for bit those
+ * of bdfx_typical_atol() on a context whose cells all belong to one mechanism.
+ * Errors (text from bdfx_last_error(NULL)): BDFX_EINVAL for NULL d_y or d_atol,
+ * n_cells < 1, n_species outside 1..BDFX_MAX_SPECIES (the scratch's limit),
+ * ldy < n_species, eta not finite or not > 0, or a bad device; BDFX_EHIP if
+ * the device cannot be selected or a launch fails. */
+int bdfx_typical_atol_static(int device, void *hip_stream, const double *d_y, int64_t n_cells,
+                             int32_t ldy, int32_t n_species, double eta, double *d_atol,
+                             double *d_typical);
 /* Species weights w [S] (host) used by bdfx_perturb(); default all ones. */
 int bdfx_mech_set_weights(bdfx_mech mech, const double *weights);
 

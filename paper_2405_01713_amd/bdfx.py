@@ -34,7 +34,7 @@ EXPORTED = ["bdfx_create", "bdfx_set_stream", "bdfx_destroy", "bdfx_last_error",
             "bdfx_plan",
             "bdfx_bind", "bdfx_integrate", "bdfx_perturb", "bdfx_stats_summary",
             "bdfx_adjoint", "bdfx_autotune", "bdfx_set_tuning", "bdfx_get_tuning", "bdfx_typical_atol",
-            "bdfx_get_record_layout", "bdfx_version"]
+            "bdfx_get_record_layout", "bdfx_version", "bdfx_typical_atol_static"]
 
 
 class MechDesc(C.Structure):
@@ -112,6 +112,7 @@ def lib():
             "bdfx_set_tuning": ([P, C.POINTER(Tuning), I32], C.c_int),
             "bdfx_get_tuning": ([P, C.POINTER(Tuning), I32], C.c_int),
             "bdfx_typical_atol": ([P, C.c_double, P], C.c_int),
+            "bdfx_typical_atol_static": ([C.c_int, P, P, I64, I32, I32, C.c_double, P, P], C.c_int),
             "bdfx_get_record_layout": ([P, C.POINTER(RecordLayout)], C.c_int),
             "bdfx_version": ([], C.c_char_p),
         }
@@ -233,6 +234,15 @@ def bdfx_perturb(ctx, seed: int, outer_step: int, amplitude: float):
 
 def bdfx_typical_atol(ctx, eta: float, d_typical=None):
     _check(lib().bdfx_typical_atol(ctx, float(eta), d_typical), ctx)
+
+
+def bdfx_typical_atol_static(device: int, stream: int, y_ptr: int, n_cells: int, ldy: int,
+                             n_species: int, eta: float, atol_ptr: int, typical_ptr=None):
+    """Allocation-free typical-value tolerances (no context); device pointers
+    as integers."""
+    _check(lib().bdfx_typical_atol_static(int(device), stream or None, y_ptr, int(n_cells),
+                                          int(ldy), int(n_species), float(eta), atol_ptr,
+                                          typical_ptr))
 
 
 def bdfx_stats_summary(ctx) -> dict:

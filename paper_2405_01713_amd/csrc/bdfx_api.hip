@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -981,6 +982,64 @@ int bdfx_typical_atol(bdfx_ctx ctx, double eta, double *d_typical) {
                                   reinterpret_cast<double *>(ctx->ws + ctx->off_tatol), d_typical,
                                   ctx->stream));
   ctx->typical = true;
+  return BDFX_OK;
+}
+
+// Scratch of bdfx_typical_atol_static: the k_extremes block partials of one
+// call (kExtMaxBlocks blocks x {minimum, maximum} x 64 species, 256 KiB),
+// resident on every device the library runs on until the process ends.  Host
+// code never passes this name to a kernel: the kernels take the device address
+// that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[kExtMaxBlocks * 2 * bdfx::kWave];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch`, per device
+
+// Device address of this device's copy of `scratch` (the device must be
+// current); looked up once per device.
+hipError_t scratch_on(int device, double **out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double *>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+}  // namespace
+
+int bdfx_typical_atol_static(int device, void *hip_stream, const double *d_y, int64_t n_cells,
+                             int32_t ldy, int32_t n_species, double eta, double *d_atol,
+                             double *d_typical) {
+  if (!d_y || !d_atol) return fail(nullptr, BDFX_EINVAL, "d_y and d_atol must not be NULL");
+  if (n_cells < 1) return fail(nullptr, BDFX_EINVAL, "n_cells must be >= 1");
+  if (n_species < 1 || n_species > BDFX_MAX_SPECIES)
+    return fail(nullptr, BDFX_EINVAL, "n_species %d outside 1..%d (the scratch holds %d species)",
+                n_species, BDFX_MAX_SPECIES, BDFX_MAX_SPECIES);
+  if (ldy < n_species) return fail(nullptr, BDFX_EINVAL, "ldy %d < n_species %d", ldy, n_species);
+  if (!std::isfinite(eta) || !(eta > 0.0)) return fail(nullptr, BDFX_EINVAL, "eta must be finite, > 0");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(nullptr, BDFX_EHIP, "no HIP device available");
+  if (device < 0 || device >= ndev || device >= kMaxDevices)
+    return fail(nullptr, BDFX_EINVAL, "bad device %d", device);
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess)
+    return fail(nullptr, BDFX_EHIP, "cannot select device %d", device);
+  const hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  double *part = nullptr;
+  hipError_t e = scratch_on(device, &part);
+  const int32_t S[1] = {n_species};
+  const int32_t nblk[1] = {bdfx_extremes_blocks(n_cells, n_species, kExtMaxBlocks)};
+  const int64_t off[1] = {0};
+  if (e == hipSuccess) e = bdfx_launch_extremes(d_y, ldy, nullptr, n_cells, n_species, nblk[0], part, s);
+  if (e == hipSuccess) e = bdfx_launch_typical(1, n_species, S, nblk, off, part, eta, d_atol, d_typical, s);
+  hipSetDevice(prev);
+  if (e != hipSuccess) return fail(nullptr, BDFX_EHIP, "typical values: %s", hipGetErrorString(e));
   return BDFX_OK;
 }
 
