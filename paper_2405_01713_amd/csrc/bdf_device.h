@@ -931,81 +931,185 @@ __device__ __forceinline__ uint64_t abs_key(float v) {
   return static_cast<uint64_t>(__builtin_bit_cast(uint32_t, v) & 0x7FFFFFFFu) + 1ull;
 }
 
-// x * y + z as the three-address VOP3 FMA with y in a scalar register, so
-// that the rotated working row needs no register copies (the two-address form
-// ties its result to z).  y is usually written by v_readlane just before:
-// two wait states keep the VALU write of the SGPR ahead of the read.
-__device__ __forceinline__ float fma3s(float x, float y, float z) {
-  float r;
-  asm("s_nop 1\n\tv_fma_f32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "s"(y), "v"(z));
-  return r;
+// Four updates a_j <- ng * b_j + a_j whose broadcast operands b_j sit in
+// scalar registers just written by v_readlane: one pair of wait states at the
+// top covers all four FMAs (the first one may read the last register
+// written).  In place (fmac4s) or into fresh registers (fma4s, early-clobber
+// outputs, for the rotating step of a Gauss-Jordan block).
+__device__ __forceinline__ void fmac4s(double &a0, double &a1, double &a2, double &a3, double ng,
+                                       double b0, double b1, double b2, double b3) {
+  asm("s_nop 1\n\tv_fmac_f64 %0, %4, %8\n\tv_fmac_f64 %1, %5, %8\n\t"
+      "v_fmac_f64 %2, %6, %8\n\tv_fmac_f64 %3, %7, %8"
+      : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3)
+      : "s"(b0), "s"(b1), "s"(b2), "s"(b3), "v"(ng));
 }
-__device__ __forceinline__ double fma3s(double x, double y, double z) {
-  double r;
-  asm("s_nop 1\n\tv_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(x), "s"(y), "v"(z));
-  return r;
+__device__ __forceinline__ void fmac4s(float &a0, float &a1, float &a2, float &a3, float ng, float b0,
+                                       float b1, float b2, float b3) {
+  asm("s_nop 1\n\tv_fmac_f32 %0, %4, %8\n\tv_fmac_f32 %1, %5, %8\n\t"
+      "v_fmac_f32 %2, %6, %8\n\tv_fmac_f32 %3, %7, %8"
+      : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3)
+      : "s"(b0), "s"(b1), "s"(b2), "s"(b3), "v"(ng));
+}
+__device__ __forceinline__ void fma4s(double &d0, double &d1, double &d2, double &d3, double ng,
+                                      double b0, double b1, double b2, double b3, double c0,
+                                      double c1, double c2, double c3) {
+  asm("s_nop 1\n\tv_fma_f64 %0, %4, %5, %6\n\tv_fma_f64 %1, %4, %7, %8\n\t"
+      "v_fma_f64 %2, %4, %9, %10\n\tv_fma_f64 %3, %4, %11, %12"
+      : "=&v"(d0), "=&v"(d1), "=&v"(d2), "=&v"(d3)
+      : "v"(ng), "s"(b0), "v"(c0), "s"(b1), "v"(c1), "s"(b2), "v"(c2), "s"(b3), "v"(c3));
+}
+__device__ __forceinline__ void fma4s(float &d0, float &d1, float &d2, float &d3, float ng, float b0,
+                                      float b1, float b2, float b3, float c0, float c1, float c2,
+                                      float c3) {
+  asm("s_nop 1\n\tv_fma_f32 %0, %4, %5, %6\n\tv_fma_f32 %1, %4, %7, %8\n\t"
+      "v_fma_f32 %2, %4, %9, %10\n\tv_fma_f32 %3, %4, %11, %12"
+      : "=&v"(d0), "=&v"(d1), "=&v"(d2), "=&v"(d3)
+      : "v"(ng), "s"(b0), "v"(c0), "s"(b1), "v"(c1), "s"(b2), "v"(c2), "s"(b3), "v"(c3));
+}
+
+// Slot updated i-th by an in-place Gauss-Jordan step on slot E: slot E + 1
+// first (the next step's column, so that its pivot search can start while
+// the rest of the row is updated), then the others in ascending order.
+template <int S, int E>
+constexpr int gj_slot(int i) {
+  if (E + 1 < S) {
+    if (i == 0) return E + 1;
+    --i;
+  }
+  for (int j = 0;; ++j) {
+    if (j == E || j == E + 1) continue;
+    if (i-- == 0) return j;
+  }
+}
+
+// In-place update a_j += ng * a_pj of the S - 1 slots other than E, from the
+// I-th in gj_slot order; four per asm block where one wave holds one cell.
+template <int S, int E, int I, typename LT, int G>
+__device__ __forceinline__ void gj_update(LT (&a)[S], const Grp<G> &W, int p, LT ng) {
+  constexpr int N = S - 1;
+  if constexpr (G == 1 && I + 4 <= N) {
+    constexpr int j0 = gj_slot<S, E>(I), j1 = gj_slot<S, E>(I + 1), j2 = gj_slot<S, E>(I + 2),
+                  j3 = gj_slot<S, E>(I + 3);
+    const LT b0 = W.bcast(a[j0], p), b1 = W.bcast(a[j1], p), b2 = W.bcast(a[j2], p),
+             b3 = W.bcast(a[j3], p);
+    fmac4s(a[j0], a[j1], a[j2], a[j3], ng, b0, b1, b2, b3);
+    gj_update<S, E, I + 4>(a, W, p, ng);
+  } else if constexpr (I < N) {
+    constexpr int j = gj_slot<S, E>(I);
+    a[j] = fma(ng, W.bcast(a[j], p), a[j]);
+    gj_update<S, E, I + 1>(a, W, p, ng);
+  }
+}
+
+// a_{j - SH} = ng * a_pj + a_j for slots j = J .. S-1 (the rotating last step
+// of a block), four per asm block where one wave holds one cell.
+template <int S, int SH, int J, typename LT, int G>
+__device__ __forceinline__ void gj_rotate(LT (&a)[S], const Grp<G> &W, int p, LT ng) {
+  if constexpr (G == 1 && J + 4 <= S) {
+    const LT b0 = W.bcast(a[J], p), b1 = W.bcast(a[J + 1], p), b2 = W.bcast(a[J + 2], p),
+             b3 = W.bcast(a[J + 3], p);
+    const LT c0 = a[J], c1 = a[J + 1], c2 = a[J + 2], c3 = a[J + 3];
+    fma4s(a[J - SH], a[J + 1 - SH], a[J + 2 - SH], a[J + 3 - SH], ng, b0, b1, b2, b3, c0, c1, c2, c3);
+    gj_rotate<S, SH, J + 4>(a, W, p, ng);
+  } else if constexpr (J < S) {
+    a[J - SH] = fma(ng, W.bcast(a[J], p), a[J]);
+    gj_rotate<S, SH, J + 1>(a, W, p, ng);
+  }
+}
+
+// One Gauss-Jordan step on the cell's S x S Newton matrix (row i in lane i's
+// registers): eliminates the column held in slot E.  Its pivot is the largest
+// |a_iE| among rows not yet used, lowest row on ties (the pivot sequence of an
+// LU factorisation with partial pivoting); every other row is updated as
+// row_i -= (a_iE / p) row_p and slot E becomes that column of the
+// accumulated inverse.  Pivot rows stay unscaled (all later updates are linear
+// in them): the owner of a pivot keeps 1/p and divides its row at the end, so
+// each entry costs one FMA per step and large pivots cause no cancellation.
+// SH = 0 updates the slots in place; SH > 0 (the last step of a block, E =
+// SH - 1) also rotates the row by SH slots: slot j goes to j - SH and slots
+// 0..SH-1 to S-SH..S-1, so that the next block again eliminates slots 0, 1, ...
+template <int S, int E, int SH, typename LT, int G>
+__device__ __forceinline__ void gj_step(LT (&a)[S], const Grp<G> &W, int k, int &piv, LT &dinv,
+                                        int &info) {
+  int p;
+  bool zero_pivot;
+  if constexpr (sizeof(LT) == 4) {
+    const uint32_t key = piv < 0 ? static_cast<uint32_t>(abs_key(a[E])) : 0u;
+    const uint32_t kmax = W.template max_u32<(S + 15) / 16>(key);
+    p = W.first(key == kmax);
+    zero_pivot = kmax <= 1u;
+  } else {
+    // exact 64-bit maximum in two 32-bit passes: high words, then the low
+    // words of the lanes that tie on the high word
+    const uint64_t key = piv < 0 ? abs_key(a[E]) : 0ull;
+    const uint32_t hi = static_cast<uint32_t>(key >> 32), lo = static_cast<uint32_t>(key);
+    const uint32_t hmax = W.template max_u32<(S + 15) / 16>(hi);
+    const uint32_t lmax = W.template max_u32<(S + 15) / 16>(hi == hmax ? lo : 0u);
+    p = W.first(hi == hmax && lo == lmax);
+    zero_pivot = hmax == 0u && lmax <= 1u;
+  }
+  if (zero_pivot && info == 0) info = k + 1;
+  const bool is_p = W.lane == p;
+  const LT pk = W.bcast(a[E], p);
+  const LT rp = rcp(pk);
+  const LT ng = is_p ? static_cast<LT>(0) : -(a[E] * rp);
+  if (is_p) {
+    piv = k;
+    dinv = rp;
+  }
+  const LT col = is_p ? static_cast<LT>(1) : ng;  // new column of the inverse
+  if constexpr (SH == 0) {
+    gj_update<S, E, 0>(a, W, p, ng);
+    a[E] = col;
+  } else {
+    static_assert(E == SH - 1, "a block rotates on its last step");
+    gj_update<S, E, 0>(a, W, p, ng);
+    a[E] = col;
+    LT t[SH];
+#pragma unroll
+    for (int u = 0; u < SH; ++u) t[u] = a[u];
+#pragma unroll
+    for (int j = SH; j < S; ++j) a[j - SH] = a[j];
+#pragma unroll
+    for (int u = 0; u < SH; ++u) a[S - SH + u] = t[u];
+  }
+}
+
+// steps E = 0 .. B-1 of a block of B steps starting at step k0
+template <int S, int B, int E, typename LT, int G>
+__device__ __forceinline__ void gj_block(LT (&a)[S], const Grp<G> &W, int k0, int &piv, LT &dinv,
+                                         int &info) {
+  if constexpr (E < B) {
+    gj_step<S, E, (E == B - 1 ? B : 0)>(a, W, k0 + E, piv, dinv, info);
+    gj_block<S, B, E + 1>(a, W, k0, piv, dinv, info);
+  }
 }
 
 // Inverts the cell's S x S Newton matrix M (row i in lane i's registers) by
-// Gauss-Jordan elimination with partial pivoting: the pivot of column k is
-// the largest |a_ik| among rows not yet used, lowest row on ties (the same
-// pivot sequence as an LU factorisation with partial pivoting).  Step k
-// eliminates column k from all other rows, row_i -= (a_ik / p_k) row_p, and
-// turns it into column p_k of the accumulated inverse.  The working row is
-// rotated by one slot per step (the column being eliminated is always slot 0,
-// the updated slot j is written to slot j-1 and the new inverse column to the
-// last slot), so every register index is static and the step loop need not
-// be unrolled; after S steps slot k holds the inverse column of step k.
-// Pivot rows are left unscaled during the elimination (all later updates are
-// linear in them) and each lane divides its row by its own pivot at the end:
-// one FMA per entry and step, and no cancellation on large pivots.  M^{-1} is
-// written to LDS in natural order, column-major (entry (r, c) at c*S + r), so
-// that a solve is one lane-parallel matrix-vector product.  Returns 0, or k+1
-// for the first column k without a nonzero pivot (the elimination then runs
-// on garbage).
+// Gauss-Jordan elimination with partial pivoting (gj_step), in blocks of four
+// steps whose slot indices are static, so the block loop need not be unrolled
+// (at S = 53 the unrolled form would not fit the instruction cache) and only
+// one step in four writes its row to rotated slots.  After S steps slot k
+// holds the inverse column of step k, i.e. column p_k.  M^{-1} is written to
+// LDS in natural order, column-major (entry (r, c) at c*S + r), so that a
+// solve is one lane-parallel matrix-vector product.  Returns 0, or k+1 for the
+// first column k without a nonzero pivot (the elimination then runs on
+// garbage).
 template <int S, typename LT, int G>
 __device__ __forceinline__ int gj_invert(LT (&a)[S], const Grp<G> &W, const Lds &L) {
+  constexpr int B = 4;
   int piv = W.lane < S ? -1 : 1 << 20;
   int info = 0;
-  int *perm = L.perm;
   LT dinv = static_cast<LT>(1);  // 1 / own pivot
-  for (int k = 0; k < S; ++k) {
-    int p;
-    bool zero_pivot;
-    if constexpr (sizeof(LT) == 4) {
-      const uint32_t key = piv < 0 ? static_cast<uint32_t>(abs_key(a[0])) : 0u;
-      const uint32_t kmax = W.template max_u32<(S + 15) / 16>(key);
-      p = W.first(key == kmax);
-      zero_pivot = kmax <= 1u;
-    } else {
-      // exact 64-bit maximum in two 32-bit passes: high words, then the low
-      // words of the lanes that tie on the high word
-      const uint64_t key = piv < 0 ? abs_key(a[0]) : 0ull;
-      const uint32_t hi = static_cast<uint32_t>(key >> 32), lo = static_cast<uint32_t>(key);
-      const uint32_t hmax = W.template max_u32<(S + 15) / 16>(hi);
-      const uint32_t lmax = W.template max_u32<(S + 15) / 16>(hi == hmax ? lo : 0u);
-      p = W.first(hi == hmax && lo == lmax);
-      zero_pivot = hmax == 0u && lmax <= 1u;
-    }
-    if (zero_pivot && info == 0) info = k + 1;
-    const bool is_p = W.lane == p;
-    const LT pk = W.bcast(a[0], p);
-    const LT rp = rcp(pk);
-    const LT g = is_p ? static_cast<LT>(0) : a[0] * rp;
-    if (is_p) {
-      piv = k;
-      dinv = rp;
-    }
-#pragma unroll
-    for (int j = 1; j < S; ++j) {
-      if constexpr (G == 1) a[j - 1] = fma3s(-g, W.bcast(a[j], p), a[j]);
-      else a[j - 1] = fma(-g, W.bcast(a[j], p), a[j]);
-    }
-    a[S - 1] = is_p ? static_cast<LT>(1) : -g;
-    if (W.lane == 0) perm[k] = p;
-  }
-  // lane i holds row piv(i) of M^{-1} (times its pivot); slot k is column perm[k]
+  for (int k0 = 0; k0 + B <= S; k0 += B) gj_block<S, B, 0>(a, W, k0, piv, dinv, info);
+  constexpr int T = S % B;
+  if constexpr (T > 0) gj_block<S, T, 0>(a, W, S - T, piv, dinv, info);
+  // lane i holds row piv(i) of M^{-1} (times its pivot); slot k is column
+  // perm[k], the row that was the pivot of step k
+  int *perm = L.perm;
   LT *inv = reinterpret_cast<LT *>(L.fac);
+  wave_lds_sync();
+  if (W.lane < S) perm[piv] = W.lane;
   wave_lds_sync();
   if (W.lane < S) {
 #pragma unroll
