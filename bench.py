@@ -5,13 +5,15 @@ half with the 53-species / 325-reaction synthetic mass-action mechanism
 (T ~ U[800, 2800] K), ten outer splitting steps of 1e-5 s, each a 1 %
 perturbation of the states followed by the integration of every cell, all ten
 captured in one HIP graph; rtol = 1e-6, atol = 1e-10, FP64 throughout, the
-persistent work-queue ("batched") form with autotuned launch shapes.  One bench
+persistent work-queue form with autotuned launch shapes and both mechanism
+sizes in one launch per outer step ("batched_fused").  One bench
 step is one outer step; K steps are timed as graph replays from the resident
 initial state (K/10 replays of the ten-step graph, plus one graph of K mod 10
 steps), with HIP events on the replay stream.
 
 Also measured (labelled keys, each with its own small step count): the same
-workload with the FP32 Newton matrix and in the plain (static grid) form; the
+workload with one launch per mechanism ("batched"), with the FP32 Newton matrix
+and in the plain (static grid) form; the
 21-species workload on 262,144 cells in the three forms; the 53-species
 mechanism on 262,144 cells (FP64 vs FP32 Newton matrix) and on 1,048,576 cells;
 the discrete adjoint on 65,536 cells; and the CPU oracle on a random sample of
@@ -153,6 +155,7 @@ def roofline_frac(F64, F32, seconds):
 
 FORM_OPTS = dict(plain=dict(scheduler=0, lu_precision=64),
                  batched=dict(scheduler=1, lu_precision=64),
+                 batched_fused=dict(scheduler=2, lu_precision=64),
                  batched_fp32lu=dict(scheduler=1, lu_precision=32))
 
 
@@ -856,7 +859,7 @@ def main():
                                    "larger domain shards as contiguous cell ranges, one context "
                                    "per GPU, with no communication during integration)"}))
         sys.exit(2)
-    workload, form = "mixed_s9_s53_1m", "batched"
+    workload, form = "mixed_s9_s53_1m", "batched_fused"
     if args.traffic_from:
         print(json.dumps(traffic_from(*args.traffic_from, args.copy_probe, workload, form)))
         return
@@ -892,7 +895,7 @@ def main():
     y_head = head.pop("_y")
     forms = {form: head}
     if not args.no_forms:
-        for f in ("batched_fp32lu", "plain"):
+        for f in ("batched", "batched_fp32lu", "plain"):
             r = run_outer_loop(w, f, w["outer_steps"], 0, tuning_cache=args.tuning_cache,
                                account=False)
             r["_y_sample"] = r.pop("_y")
@@ -920,7 +923,9 @@ def main():
     roof = {"bound": "alu", "achieved": frac * FP64_VECTOR_PEAK_TFLOPS,
             "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": frac,
             "traffic": stored_traffic(workload, form), "kernel": "bdfx::k_integrate",
-            "launches_per_outer_step": len(head.get("tuning") or w["mechs"]),
+            "launches_per_outer_step": (1 if head.get("tuning") and all(
+                t.get("fused") for t in head["tuning"]) else len(head.get("tuning") or w["mechs"])),
+            "launch_ms": head.get("eager_integrate_ms_mean"),
             "flops_per_outer_step": F64 + F32,
             "alg_bytes_per_outer_step": int(sum(
                 (16 * int(w["mechs"][k]["n_species"]) + 56) * int(np.sum(w["cell_mech"] == k))

@@ -931,11 +931,10 @@ __device__ __forceinline__ uint64_t abs_key(float v) {
   return static_cast<uint64_t>(__builtin_bit_cast(uint32_t, v) & 0x7FFFFFFFu) + 1ull;
 }
 
-// Four updates a_j <- ng * b_j + a_j whose broadcast operands b_j sit in
-// scalar registers just written by v_readlane: one pair of wait states at the
-// top covers all four FMAs (the first one may read the last register
-// written).  In place (fmac4s) or into fresh registers (fma4s, early-clobber
-// outputs, for the rotating step of a Gauss-Jordan block).
+// Four in-place updates a_j <- ng * b_j + a_j whose broadcast operands b_j
+// sit in scalar registers just written by v_readlane: one pair of wait states
+// at the top covers all four FMAs (the first one may read the last register
+// written).
 __device__ __forceinline__ void fmac4s(double &a0, double &a1, double &a2, double &a3, double ng,
                                        double b0, double b1, double b2, double b3) {
   asm("s_nop 1\n\tv_fmac_f64 %0, %4, %8\n\tv_fmac_f64 %1, %5, %8\n\t"
@@ -950,23 +949,6 @@ __device__ __forceinline__ void fmac4s(float &a0, float &a1, float &a2, float &a
       : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3)
       : "s"(b0), "s"(b1), "s"(b2), "s"(b3), "v"(ng));
 }
-__device__ __forceinline__ void fma4s(double &d0, double &d1, double &d2, double &d3, double ng,
-                                      double b0, double b1, double b2, double b3, double c0,
-                                      double c1, double c2, double c3) {
-  asm("s_nop 1\n\tv_fma_f64 %0, %4, %5, %6\n\tv_fma_f64 %1, %4, %7, %8\n\t"
-      "v_fma_f64 %2, %4, %9, %10\n\tv_fma_f64 %3, %4, %11, %12"
-      : "=&v"(d0), "=&v"(d1), "=&v"(d2), "=&v"(d3)
-      : "v"(ng), "s"(b0), "v"(c0), "s"(b1), "v"(c1), "s"(b2), "v"(c2), "s"(b3), "v"(c3));
-}
-__device__ __forceinline__ void fma4s(float &d0, float &d1, float &d2, float &d3, float ng, float b0,
-                                      float b1, float b2, float b3, float c0, float c1, float c2,
-                                      float c3) {
-  asm("s_nop 1\n\tv_fma_f32 %0, %4, %5, %6\n\tv_fma_f32 %1, %4, %7, %8\n\t"
-      "v_fma_f32 %2, %4, %9, %10\n\tv_fma_f32 %3, %4, %11, %12"
-      : "=&v"(d0), "=&v"(d1), "=&v"(d2), "=&v"(d3)
-      : "v"(ng), "s"(b0), "v"(c0), "s"(b1), "v"(c1), "s"(b2), "v"(c2), "s"(b3), "v"(c3));
-}
-
 // Slot updated i-th by an in-place Gauss-Jordan step on slot E: slot E + 1
 // first (the next step's column, so that its pivot search can start while
 // the rest of the row is updated), then the others in ascending order.
@@ -998,22 +980,6 @@ __device__ __forceinline__ void gj_update(LT (&a)[S], const Grp<G> &W, int p, LT
     constexpr int j = gj_slot<S, E>(I);
     a[j] = fma(ng, W.bcast(a[j], p), a[j]);
     gj_update<S, E, I + 1>(a, W, p, ng);
-  }
-}
-
-// a_{j - SH} = ng * a_pj + a_j for slots j = J .. S-1 (the rotating last step
-// of a block), four per asm block where one wave holds one cell.
-template <int S, int SH, int J, typename LT, int G>
-__device__ __forceinline__ void gj_rotate(LT (&a)[S], const Grp<G> &W, int p, LT ng) {
-  if constexpr (G == 1 && J + 4 <= S) {
-    const LT b0 = W.bcast(a[J], p), b1 = W.bcast(a[J + 1], p), b2 = W.bcast(a[J + 2], p),
-             b3 = W.bcast(a[J + 3], p);
-    const LT c0 = a[J], c1 = a[J + 1], c2 = a[J + 2], c3 = a[J + 3];
-    fma4s(a[J - SH], a[J + 1 - SH], a[J + 2 - SH], a[J + 3 - SH], ng, b0, b1, b2, b3, c0, c1, c2, c3);
-    gj_rotate<S, SH, J + 4>(a, W, p, ng);
-  } else if constexpr (J < S) {
-    a[J - SH] = fma(ng, W.bcast(a[J], p), a[J]);
-    gj_rotate<S, SH, J + 1>(a, W, p, ng);
   }
 }
 
