@@ -329,7 +329,8 @@ def run_adjoint(steps, warmup, n_cells=None, record_steps=2048, n_check=32):
     """Adjoint/forward cost on the 65,536-cell 21-species workload: plain
     forward (no recording), forward with step recording, discrete-adjoint
     backward of the loss sum_cells sum_i c_i y_i; a sample of cells is checked
-    against the oracle's adjoint along its own step record."""
+    against the oracle's adjoint along the GPU's own step record (the same
+    frozen map, so the two differ by round-off)."""
     import torch
     from paper_2405_01713_amd import bdfx
 
@@ -381,6 +382,7 @@ def run_adjoint(steps, warmup, n_cells=None, record_steps=2048, n_check=32):
     log(f"adjoint: forward {t_fwd:.1f} ms, backward {t_bwd:.1f} ms")
     st = rec.cell_stats()
     y0bar = out["g"][0][:n_check].cpu().numpy()
+    recs = rec.step_record(np.arange(n_check))
     rec.close()
     res = dict(workload="s21_r84_65k_adjoint", n_cells=N, fwd_ms=t_fwd, fwd_record_ms=t_rec,
                bwd_ms=t_bwd, ratio_bwd_over_fwd=t_bwd / t_fwd,
@@ -391,14 +393,14 @@ def run_adjoint(steps, warmup, n_cells=None, record_steps=2048, n_check=32):
         go = np.zeros((n_check, m["n_species"]))
         for k in range(n_check):
             kf, kr = O.rates(m, w["T"][k])
-            _, _, r = O.integrate_record(m, w["y0"][k], 0.0, w["t_out"], w["rtol"], w["atol"],
-                                         T=w["T"][k])
-            go[k] = O.adjoint(m, kf, kr, w["y0"][k], r, r["y"], c)[0]
-        rel = np.abs(y0bar[:, :m["n_species"]] - go).max(axis=1) / np.abs(go).max()
+            r = recs[k]
+            go[k] = O.adjoint(m, kf, kr, r["y0"], r, r["y"], c)[0]
+        rel = np.abs(y0bar[:, :m["n_species"]] - go).max(axis=1) / np.abs(go).max(axis=1)
         res["check_cells"] = n_check
         res["check_worst_rel"] = float(rel.max())
         res["check_median_rel"] = float(np.median(rel))
-        res["check_ok"] = bool(rel.max() <= 1e-4 and np.median(rel) <= 1e-6)
+        # the GPU test's bar for dL/dy0 along the GPU record (3e-10 per cell)
+        res["check_ok"] = bool(rel.max() <= 3e-10)
     except Exception as e:  # the oracle is optional on the timing path
         res["check_error"] = repr(e)
     return res
