@@ -164,6 +164,18 @@ typedef struct {
                                  accepted state and time (the accept/reject logic of Sec. 2) */
   int32_t max_conv_fails;     /* Newton convergence failures within one step that fail the cell
                                  with BDFX_CELL_CONV_FAILURE (0 = 10) */
+  int32_t checkpoint_every;   /* with record_steps > 0: 0 stores every accepted step for
+                                 bdfx_adjoint() (record_steps x (S_max + 2) doubles per cell).
+                                 K > 0 stores instead the integrator's whole state at every
+                                 K-th accepted step (ceil(record_steps / K) checkpoints of
+                                 20 + 8 S doubles per cell, S the largest mechanism size
+                                 padded to a compiled size), and bdfx_adjoint() reruns
+                                 each K-step segment from its checkpoint with the same step
+                                 code before sweeping it backwards: the gradient equals the
+                                 full record's bit for bit, for about one more forward run of
+                                 work.  Needs lu_precision 64 and the analytic Jacobian;
+                                 cells run one per wave; bdfx_get_record_layout() does not
+                                 apply (BDFX_EUNSUPPORTED). */
 } bdfx_options;
 
 #define BDFX_JAC_ANALYTIC 0
@@ -331,7 +343,11 @@ int bdfx_stats_summary(bdfx_ctx ctx, bdfx_summary *out);
  *                       mechanism (may be NULL)
  * The gradient is that of the discrete map with the recorded step sizes and
  * orders held fixed and each corrector solved exactly (Jacobians re-evaluated
- * at the recorded states).  Enqueue only. */
+ * at the recorded states).  With checkpoint_every = K > 0 the sweep first
+ * reruns each K-step segment from its checkpoint into a workspace area (one
+ * segment per resident wave of the sweep), which gives the same steps bit for
+ * bit; the bound inputs (T, rate scales, forcing) must be unchanged since the
+ * integrate.  Enqueue only. */
 int bdfx_adjoint(bdfx_ctx ctx, const double *d_ybar, double *d_y0bar, double *d_lnA_bar);
 
 /* Where bdfx_integrate() with record_steps > 0 leaves the step record in the
@@ -350,7 +366,7 @@ int bdfx_adjoint(bdfx_ctx ctx, const double *d_ybar, double *d_y0bar, double *d_
  * The record describes the frozen discrete map that bdfx_adjoint()
  * differentiates (the step sequence of the run with each corrector solved
  * exactly).  Host-only.  Errors: BDFX_EORDER before bdfx_bind() or without
- * recording. */
+ * recording; BDFX_EUNSUPPORTED with checkpoint_every > 0 (no per-step record). */
 typedef struct {
   int32_t cap;    /* recorded steps per cell (bdfx_options.record_steps) */
   int32_t stride; /* doubles per recorded step (largest state length + 2) */

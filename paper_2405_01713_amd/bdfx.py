@@ -18,6 +18,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libbdfx.so")
 
 BDFX_OK = 0
+BDFX_EINVAL, BDFX_EWORKSPACE, BDFX_EHIP, BDFX_EORDER, BDFX_EUNSUPPORTED = -1, -2, -3, -4, -5
+BDFX_CELL_RECORD_FULL = -10
 BDFX_SCHED_STATIC = 0
 BDFX_SCHED_QUEUE = 1
 BDFX_SCHED_FUSED = 2
@@ -52,7 +54,8 @@ class Options(C.Structure):
                 ("blocks_per_cu", C.c_int32), ("queue_chunk", C.c_int32),
                 ("waves_per_simd", C.c_int32), ("cells_per_wave", C.c_int32),
                 ("jacobian", C.c_int32), ("gmres_maxl", C.c_int32), ("lockstep", C.c_int32),
-                ("max_err_test_fails", C.c_int32), ("max_conv_fails", C.c_int32)]
+                ("max_err_test_fails", C.c_int32), ("max_conv_fails", C.c_int32),
+                ("checkpoint_every", C.c_int32)]
 
 
 class Summary(C.Structure):
@@ -197,13 +200,15 @@ def bdfx_mech_set_lnA(mech, lnA_ptr, ctx=None):
 def make_options(rtol, atol, max_order=5, max_steps=5000, lu_precision=64,
                  scheduler=BDFX_SCHED_STATIC, record_steps=0, waves_per_block=0,
                  blocks_per_cu=0, queue_chunk=0, waves_per_simd=0, cells_per_wave=0,
-                 jacobian=0, gmres_maxl=0, lockstep=0, max_err_test_fails=0, max_conv_fails=0):
+                 jacobian=0, gmres_maxl=0, lockstep=0, max_err_test_fails=0, max_conv_fails=0,
+                 checkpoint_every=0):
     atol_arr = np.ascontiguousarray(np.atleast_1d(np.asarray(atol, dtype=np.float64)))
     o = Options(float(rtol), atol_arr.ctypes.data_as(C.c_void_p), int(atol_arr.size),
                 int(max_order), int(max_steps), int(lu_precision), int(scheduler),
                 int(record_steps), int(waves_per_block), int(blocks_per_cu), int(queue_chunk),
                 int(waves_per_simd), int(cells_per_wave), int(jacobian), int(gmres_maxl),
-                int(lockstep), int(max_err_test_fails), int(max_conv_fails))
+                int(lockstep), int(max_err_test_fails), int(max_conv_fails),
+                int(checkpoint_every))
     o._keep = atol_arr
     return o
 

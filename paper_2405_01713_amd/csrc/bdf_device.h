@@ -107,6 +107,14 @@ struct Params {
   int32_t *rec_n;         // [N]
   double *rec_hpad;       // [N]
   double *rec_y0;         // [N][rec_stride]
+  // checkpointed records (ckpt != nullptr: no per-step states; at every
+  // ckpt_every-th accepted step the integrator's whole state is saved, and the
+  // adjoint recomputes the steps in between from it with this same code)
+  double *ckpt;           // [N][ckpt_cap][Ckpt::stride(ckpt_vs)]
+  double *ckpt_setup;     // [N][ckpt_vs]: predicted state of the cell's last Newton-matrix setup
+  int32_t ckpt_every, ckpt_cap, ckpt_vs;
+  int32_t seg_rows;       // adjoint: rows of a recomputed segment (ckpt_every + kQmax + 1)
+  double *seg;            // adjoint: [waves][seg_rows][rec_stride], one per wave of the grid
   const double *atol;     // [atol_len] (device)
   // adjoint (bdfx_adjoint only)
   const double *ybar;     // [N][ldy] dL/dy(t_out)
@@ -495,6 +503,40 @@ struct Ctl {
   static constexpr int kGammaBar = 22;
   static constexpr int kTn = 23;
   static constexpr int kSize = 24;
+};
+
+// One checkpoint (doubles): the integrator's state at the top of its step
+// loop after nst accepted steps, everything the steps after it read.  Scalars
+// (lane 0): t, h, q, nst, the order-change countdown, the step of the last
+// Newton-matrix setup, the squared convergence rate, the setup/e_prev flags,
+// the step sizes h_nst .. h_{nst-kQmax}, the step-growth limit, the step size
+// of e_prev, the gamma of the last setup and the order step nst was taken
+// with.  Lane vectors, vs apart (the kernel's padded size, so that their
+// offsets are constants): the Nordsieck array z_0 .. z_kQmax, e_prev and the
+// predicted state the last setup formed its Newton matrix at (the inverse is
+// rebuilt from it, bit for bit).  Checkpoints of a cell lie stride(vs_max)
+// apart, vs_max the largest padded size of the batch.
+struct Ckpt {
+  static constexpr int kT = 0, kH = 1, kQ = 2, kNst = 3, kQwait = 4, kNstSetup = 5, kR2 = 6,
+                       kNeedSetup = 7, kHaveEprev = 8, kHist = 9 /* [kQmax + 1] */,
+                       kEtaMax = kHist + kQmax + 1, kHprev = kEtaMax + 1, kGammaBar = kHprev + 1,
+                       kQtaken = kGammaBar + 1, kScalars = 20;
+  static_assert(kQtaken < kScalars, "checkpoint scalars overlap the vectors");
+  // lane vectors: z_j is vector j, then e_prev and the setup state
+  static constexpr int kVecEprev = kQmax + 1, kVecSetup = kQmax + 2;
+  __host__ __device__ static constexpr int vec(int j, int vs) { return kScalars + j * vs; }
+  __host__ __device__ static constexpr int stride(int vs) { return vec(kVecSetup + 1, vs); }
+};
+
+// A resumed integration (the adjoint's recomputation of one segment): start
+// from checkpoint `ck` instead of the cell's input state, stop once `stop`
+// steps are accepted, record accepted step s into row s - first of `rows`
+// (n_rows rows of P.rec_stride; steps outside are not recorded) and write none
+// of the cell's outputs.
+struct Resume {
+  const double *ck;
+  double *rows;
+  int first, stop, n_rows;
 };
 
 struct Lds {
@@ -1273,11 +1315,16 @@ __device__ int gmres(const MechDev &m, const Lds &L, const Grp<G> &W, double y, 
   return rho < beta ? 1 : 2;
 }
 
-template <int S, typename LT, int TAB, int G, bool ABC, bool TH, int LIN, bool LOCK = false>
+// RES: a resumed integration (Resume); its Newton matrix is the analytic one
+// in FP64, one cell per wave.
+template <int S, typename LT, int TAB, int G, bool ABC, bool TH, int LIN, bool LOCK = false,
+          bool RES = false>
 __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, const Grp<G> &W,
                                                double *lds, double *kk_slot,
                                                BatchRed<LOCK> br = BatchRed<LOCK>{},
-                                               int batch_cells = 1) {
+                                               int batch_cells = 1, const Resume *rs = nullptr) {
+  static_assert(!RES || (G == 1 && !LOCK && !TH && LIN == kLinAnalytic && sizeof(LT) == 8),
+                "resumed integrations: FP64 direct solver, analytic Jacobian, one cell per wave");
   constexpr bool KRY = LIN == kLinGmres;
   const MechDev &m = P.mech;
   const int R = m.R;
@@ -1324,98 +1371,161 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
     if constexpr (TAB == kTabLds) const_cast<int2 *>(L.rx)[r] = reinterpret_cast<const int2 *>(m.rx)[r];
   }
 
-  const double yin = own ? P.y[cell * P.ldy + W.lane] : 0.0;
   const double Fi = (own && P.F) ? P.F[cell * P.ldy + W.lane] : 0.0;
   const double atol_i = own ? (P.atol_len == 1 ? P.atol[0] : P.atol[W.lane]) : 1.0;
-  if (P.rec && own) P.rec_y0[cell * P.rec_stride + W.lane] = yin;
+  const bool keep = (P.rec || P.ckpt) && !RES;  // this run records its steps for the adjoint
 
   int status = kSuccess;
   int nst = 0, nfe = 0, nni = 0, nsetups = 0, netf = 0, ncfn = 0, nli = 0, ncfl = 0;
-  int q = 1;
+  int q = 1, qstep = 1;  // qstep: the order the last accepted step was taken with
   double t = t0, h = 0.0;
   double z[kQmax + 1];
 #pragma unroll
   for (int j = 0; j <= kQmax; ++j) z[j] = 0.0;
-  bool write_y = true;
-
-  if (br.any(W.any(!isfinite(T) || (own && !isfinite(yin))))) {
-    status = kNonfinite;
-    write_y = false;
-  }
-  double f = 0.0, ewt = 0.0;
-  if (status == kSuccess) {
-    z[0] = yin;
-    f = rhs<ABC, TH>(m, L, W, yin, Fi, ns);
-    nfe = 1;
-    if (br.any(W.any(own && !isfinite(f)))) {
-      status = kNonfinite;
-      write_y = false;
-    }
-  }
-  if (status == kSuccess) {
-    // initial step (same reading as the oracle)
-    ewt = own ? 1.0 / (rtol * fabs(yin) + atol_i) : 0.0;
-    const double tdist = fabs(tout - t0);
-    const double hlb = 100.0 * kUround * fmax(fabs(t0), fabs(tout));
-    double hub = 0.1 * tdist;
-    const double hub_inv = br.max(
-        W.uni(W.template max<(S + 15) / 16>(own ? fabs(f) / (0.1 * fabs(yin) + atol_i) : 0.0)));
-    if (hub * hub_inv > 1.0) hub = 1.0 / hub_inv;
-    if (hub < hlb) {
-      h = hub;
-    } else {
-      double hg = sqrt(hlb * hub), hnew = hg;
-      bool at_ub = false;
-      for (int it = 0; it < 4; ++it) {
-        const double ft = rhs<ABC, TH>(m, L, W, yin + hg * f, Fi, ns);
-        nfe++;
-        const double ydd = (ft - f) / hg;
-        const double yddnrm = sqrt(norm2(ydd, ewt));
-        if (!(yddnrm > 0.0)) {
-          at_ub = true;
-          break;
-        }
-        hnew = W.uni(sqrt(2.0 / yddnrm));
-        const double ratio = hnew / hg;
-        hg = hnew;
-        if (ratio >= 0.5 && ratio <= 2.0) break;
-      }
-      if (at_ub) {
-        h = hub;
-      } else {
-        h = 0.5 * hnew;
-        if (h < hlb) h = hlb;
-        if (h > hub) h = hub;
-      }
-    }
-    h = W.uni(h);
-    z[1] = h * f;
-  }
-
-  wave_lds_sync();
-#pragma unroll
-  for (int k = 0; k <= kQmax; ++k) C[Ctl::kHist + k] = h;
-  C[Ctl::kEtaMax] = 1.0e4;
-  C[Ctl::kHprev] = h;
-  C[Ctl::kGammaBar] = 0.0;
-  if (P.rec && W.lane == 0) P.rec_hpad[cell] = h;
-
+  bool write_y = !RES;
   int qwait = 2, nst_setup = 0;
   double R2 = 1.0;  // squared Newton convergence rate
   bool need_setup = true, have_eprev = false, rebuilt = false;
   double e = 0.0, eprev = 0.0;
+  double f = 0.0, ewt = 0.0;
+
+  if constexpr (RES) {
+    // the state after ck[kNst] accepted steps, as the step loop left it
+    const double *ck = rs->ck;
+#pragma unroll
+    for (int j = 0; j <= kQmax; ++j) z[j] = own ? ck[Ckpt::vec(j, S) + W.lane] : 0.0;
+    eprev = own ? ck[Ckpt::vec(Ckpt::kVecEprev, S) + W.lane] : 0.0;
+    t = uni(ck[Ckpt::kT]);
+    h = uni(ck[Ckpt::kH]);
+    q = static_cast<int>(uni(ck[Ckpt::kQ]));
+    nst = static_cast<int>(uni(ck[Ckpt::kNst]));
+    qwait = static_cast<int>(uni(ck[Ckpt::kQwait]));
+    nst_setup = static_cast<int>(uni(ck[Ckpt::kNstSetup]));
+    R2 = uni(ck[Ckpt::kR2]);
+    need_setup = uni(ck[Ckpt::kNeedSetup]) != 0.0;
+    have_eprev = uni(ck[Ckpt::kHaveEprev]) != 0.0;
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k <= kQmax; ++k) C[Ctl::kHist + k] = ck[Ckpt::kHist + k];
+    C[Ctl::kEtaMax] = ck[Ckpt::kEtaMax];
+    C[Ctl::kHprev] = ck[Ckpt::kHprev];
+    C[Ctl::kGammaBar] = ck[Ckpt::kGammaBar];
+    if (!need_setup) {
+      // the inverse the run held: the same matrix at the same state and gamma
+      const double zs = own ? ck[Ckpt::vec(Ckpt::kVecSetup, S) + W.lane] : 0.0;
+      LT a[S];
+      newton_matrix<S, LT, ABC>(a, m, L, W, zs, uni(ck[Ckpt::kGammaBar]), false);
+      gj_invert<S, LT>(a, W, L);
+    }
+  } else {
+    const double yin = own ? P.y[cell * P.ldy + W.lane] : 0.0;
+    if (keep && own) P.rec_y0[cell * P.rec_stride + W.lane] = yin;
+    if (br.any(W.any(!isfinite(T) || (own && !isfinite(yin))))) {
+      status = kNonfinite;
+      write_y = false;
+    }
+    if (status == kSuccess) {
+      z[0] = yin;
+      f = rhs<ABC, TH>(m, L, W, yin, Fi, ns);
+      nfe = 1;
+      if (br.any(W.any(own && !isfinite(f)))) {
+        status = kNonfinite;
+        write_y = false;
+      }
+    }
+    if (status == kSuccess) {
+      // initial step (same reading as the oracle)
+      ewt = own ? 1.0 / (rtol * fabs(yin) + atol_i) : 0.0;
+      const double tdist = fabs(tout - t0);
+      const double hlb = 100.0 * kUround * fmax(fabs(t0), fabs(tout));
+      double hub = 0.1 * tdist;
+      const double hub_inv = br.max(
+          W.uni(W.template max<(S + 15) / 16>(own ? fabs(f) / (0.1 * fabs(yin) + atol_i) : 0.0)));
+      if (hub * hub_inv > 1.0) hub = 1.0 / hub_inv;
+      if (hub < hlb) {
+        h = hub;
+      } else {
+        double hg = sqrt(hlb * hub), hnew = hg;
+        bool at_ub = false;
+        for (int it = 0; it < 4; ++it) {
+          const double ft = rhs<ABC, TH>(m, L, W, yin + hg * f, Fi, ns);
+          nfe++;
+          const double ydd = (ft - f) / hg;
+          const double yddnrm = sqrt(norm2(ydd, ewt));
+          if (!(yddnrm > 0.0)) {
+            at_ub = true;
+            break;
+          }
+          hnew = W.uni(sqrt(2.0 / yddnrm));
+          const double ratio = hnew / hg;
+          hg = hnew;
+          if (ratio >= 0.5 && ratio <= 2.0) break;
+        }
+        if (at_ub) {
+          h = hub;
+        } else {
+          h = 0.5 * hnew;
+          if (h < hlb) h = hlb;
+          if (h > hub) h = hub;
+        }
+      }
+      h = W.uni(h);
+      z[1] = h * f;
+    }
+
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k <= kQmax; ++k) C[Ctl::kHist + k] = h;
+    C[Ctl::kEtaMax] = 1.0e4;
+    C[Ctl::kHprev] = h;
+    C[Ctl::kGammaBar] = 0.0;
+    if (keep && W.lane == 0) P.rec_hpad[cell] = h;
+  }
 
   // step loop (same structure as the oracle: steps, attempts, Newton iterations)
   while (status == kSuccess && t < tout) {
+    if constexpr (RES) {
+      if (nst >= rs->stop) break;
+    }
     if (nst >= P.max_steps) {
       status = kTooMuchWork;
       break;
     }
-    if (P.rec && nst >= P.rec_cap) {
+    if (keep && nst >= P.rec_cap) {
       // the record is full and time is left: stop at the last recorded step,
       // so that the returned state is the end point of the recorded map
       status = kRecordFull;
       break;
+    }
+    if (!RES && P.ckpt && nst % P.ckpt_every == 0) {
+      // checkpoint nst / ckpt_every (nst < rec_cap <= ckpt_cap ckpt_every)
+      // (vectors S apart: constant offsets from one address per lane)
+      double *ck = P.ckpt + (cell * P.ckpt_cap + nst / P.ckpt_every) * Ckpt::stride(P.ckpt_vs);
+      if (own) {
+#pragma unroll
+        for (int j = 0; j <= kQmax; ++j) ck[Ckpt::vec(j, S) + W.lane] = z[j];
+        ck[Ckpt::vec(Ckpt::kVecEprev, S) + W.lane] = eprev;
+      }
+      wave_lds_sync();
+      if (W.lane == 0) {
+        ck[Ckpt::kT] = t;
+        ck[Ckpt::kH] = h;
+        ck[Ckpt::kQ] = q;
+        ck[Ckpt::kNst] = nst;
+        ck[Ckpt::kQwait] = qwait;
+        ck[Ckpt::kNstSetup] = nst_setup;
+        ck[Ckpt::kR2] = R2;
+        ck[Ckpt::kNeedSetup] = need_setup ? 1.0 : 0.0;
+        ck[Ckpt::kHaveEprev] = have_eprev ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k <= kQmax; ++k) ck[Ckpt::kHist + k] = C[Ctl::kHist + k];
+        ck[Ckpt::kEtaMax] = C[Ctl::kEtaMax];
+        ck[Ckpt::kHprev] = C[Ctl::kHprev];
+        ck[Ckpt::kGammaBar] = C[Ctl::kGammaBar];
+        ck[Ckpt::kQtaken] = qstep;
+      }
+      if (!need_setup && own)
+        ck[Ckpt::vec(Ckpt::kVecSetup, S) + W.lane] = P.ckpt_setup[cell * P.ckpt_vs + W.lane];
     }
     ewt = own ? rcp(rtol * fabs(z[0]) + atol_i) : 0.0;  // from y^{n-1}, Eq. (3)
     int nef_step = 0, ncf_step = 0, nsf_step = 0;
@@ -1478,6 +1588,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
             }
             info = gj_invert<S, LT>(a, W, L);
           }
+          if (!RES && P.ckpt && own) P.ckpt_setup[cell * P.ckpt_vs + W.lane] = z[0];
           nsetups++;
           nst_setup = nst;
           gamma_bar = gamma;
@@ -1607,8 +1718,11 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
 #pragma unroll
     for (int k = kQmax; k >= 1; --k) C[Ctl::kHist + k] = C[Ctl::kHist + k - 1];
     C[Ctl::kHist] = h;
-    if (P.rec) {
-      double *rp = P.rec + (static_cast<int64_t>(cell) * P.rec_cap + (nst - 1)) * P.rec_stride;
+    qstep = q;
+    if (RES ? static_cast<unsigned>(nst - rs->first) < static_cast<unsigned>(rs->n_rows)
+            : P.rec != nullptr) {
+      double *rp = RES ? rs->rows + static_cast<int64_t>(nst - rs->first) * P.rec_stride
+                       : P.rec + (static_cast<int64_t>(cell) * P.rec_cap + (nst - 1)) * P.rec_stride;
       if (own) rp[W.lane] = z[0];
       if (W.lane == 0) {
         rp[n] = h;
@@ -1698,6 +1812,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
     C[Ctl::kEtaMax] = 10.0;
   }
 
+  if constexpr (RES) return;
   if (write_y && own && br.active) P.y[cell * P.ldy + W.lane] = z[0];
   if (W.lane == 0 && br.active) {
     P.status[cell] = status;
@@ -1717,7 +1832,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       st.t_reached = t;
       P.stats[cell] = st;
     }
-    if (P.rec) P.rec_n[cell] = nst < P.rec_cap ? nst : P.rec_cap;
+    if (keep) P.rec_n[cell] = nst < P.rec_cap ? nst : P.rec_cap;
   }
 }
 
@@ -1785,25 +1900,40 @@ __device__ __forceinline__ double adj_scatter(const MechDev &m, const Lds &L, do
   return L.fb[li];
 }
 
+// Recorded steps of one cell: step s (1-based) is the row p + (s - first) *
+// stride (the whole record, first = 1; or a recomputed segment).
+struct RecView {
+  const double *p;
+  int first, stride;
+  __device__ const double *row(int s) const { return p + static_cast<int64_t>(s - first) * stride; }
+};
+
 // xi_i and l_j of recorded step `step` (1-based); hist from the records.
-__device__ __forceinline__ void rec_coeffs(const double *rec, int stride, int n, double hpad,
-                                           int step, int q, double (&xi)[kQmax + 2],
-                                           double (&l)[kQmax + 2], double &Cerr) {
-  const double hn = rec[(step - 1) * stride + n];
+__device__ __forceinline__ void rec_coeffs(const RecView &rv, int n, double hpad, int step, int q,
+                                           double (&xi)[kQmax + 2], double (&l)[kQmax + 2],
+                                           double &Cerr) {
+  const double hn = rv.row(step)[n];
   double sum = hn;
   xi[0] = 0.0;
   xi[1] = 1.0;
 #pragma unroll
   for (int i = 2; i <= kQmax + 1; ++i) {
     const int idx = step - i + 1;  // 1-based step of h_{n-i+1}
-    sum += idx >= 1 ? rec[(idx - 1) * stride + n] : hpad;
+    sum += idx >= 1 ? rv.row(idx)[n] : hpad;
     xi[i] = i <= q + 1 ? sum / hn : 0.0;
   }
   bdf_coeffs(q, xi, l, Cerr);
 }
 
-template <int S>
-__device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int li, double *lds) {
+// With checkpoints (P.ckpt) the steps are not stored: when the sweep reaches
+// a segment it reruns the integrator from the segment's checkpoint (the same
+// integrate_cell code, so the same steps to the bit) into `seg`, the wave's
+// segment rows, whose first kQmax + 1 rows take the step sizes before the
+// checkpoint, its state and its order from the checkpoint.  ABC: the forward
+// run's rate-expression specialisation.
+template <int S, bool ABC>
+__device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int li, double *lds,
+                                             double *seg) {
   const MechDev &m = P.mech;
   const int R = m.R;
   const Lds L = carve<kTabLds>(lds, R, m.rx, nullptr);
@@ -1830,9 +1960,11 @@ __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int 
     const_cast<int2 *>(L.rx)[r] = reinterpret_cast<const int2 *>(m.rx)[r];
     pb[r] = 0.0;
   }
-  const double *rec = P.rec + static_cast<int64_t>(cell) * P.rec_cap * stride;
+  const bool ckpt = P.ckpt != nullptr;
+  RecView rv{ckpt ? seg : P.rec + static_cast<int64_t>(cell) * P.rec_cap * stride, 1, stride};
   const int N = uni(P.rec_n[cell]);
   const double hpad = uni(P.rec_hpad[cell]);
+  int lo = ckpt ? N + 1 : 1;  // first step the rows hold
   double zb[kQmax + 1];
 #pragma unroll
   for (int j = 0; j <= kQmax; ++j) zb[j] = 0.0;
@@ -1840,13 +1972,31 @@ __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int 
   double ebx = 0.0, y0bar = zb[0];
 
   for (int step = N; step >= 1; --step) {
-    const int qr = uni(static_cast<int>(rec[(step - 1) * stride + n + 1]));
+    if (step < lo) {
+      // recompute the segment of steps n0 + 1 .. n0 + K from checkpoint n0 / K
+      const int K = P.ckpt_every, c = (step - 1) / K, n0 = c * K;
+      const double *ck = P.ckpt + (cell * P.ckpt_cap + c) * Ckpt::stride(P.ckpt_vs);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the last segment's reads are done
+      if (li == 0) {
+#pragma unroll
+        for (int j = 0; j <= kQmax; ++j) seg[j * stride + n] = ck[Ckpt::kHist + kQmax - j];
+        seg[kQmax * stride + n + 1] = ck[Ckpt::kQtaken];
+      }
+      if (own) seg[kQmax * stride + li] = ck[Ckpt::vec(0, S) + li];
+      const Resume rs{ck, seg, n0 - kQmax, n0 + K < N ? n0 + K : N, P.seg_rows};
+      integrate_cell<S, double, kTabLds, 1, ABC, false, kLinAnalytic, false, true>(
+          P, cell, W1, lds, nullptr, BatchRed<false>{}, 1, &rs);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // its rows are written
+      rv.first = n0 - kQmax;
+      lo = n0 + 1;
+    }
+    const int qr = uni(static_cast<int>(rv.row(step)[n + 1]));
     const int q = qr & 255;
-    const double hn = uni(rec[(step - 1) * stride + n]);
+    const double hn = uni(rv.row(step)[n]);
     double xi[kQmax + 2], l[kQmax + 2], Cerr;
-    rec_coeffs(rec, stride, n, hpad, step, q, xi, l, Cerr);
+    rec_coeffs(rv, n, hpad, step, q, xi, l, Cerr);
     const double gamma = uni(hn / l[1]);
-    const double yn = own ? rec[(step - 1) * stride + li] : 0.0;
+    const double yn = own ? rv.row(step)[li] : 0.0;
     // z_n = zp + l e, e = y_n - zp_0
     double eb = ebx;
 #pragma unroll
@@ -1878,16 +2028,16 @@ __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int 
       y0bar = zb[0] + hn * jtv;
       break;
     }
-    const int qp = uni(static_cast<int>(rec[(step - 2) * stride + n + 1])) & 255;
+    const int qp = uni(static_cast<int>(rv.row(step - 1)[n + 1])) & 255;
     if (qr >> 8) {
       // z was rebuilt as [y_{n-1}, h_n f(y_{n-1})] before this step
-      const double yp = own ? rec[(step - 2) * stride + li] : 0.0;
+      const double yp = own ? rv.row(step - 1)[li] : 0.0;
       const double jtv = adj_scatter(m, L, vb, pb, li, yp, zb[1], hn, true);
       zb[0] += hn * jtv;
 #pragma unroll
       for (int j = 1; j <= kQmax; ++j) zb[j] = 0.0;
     } else {
-      const double eta = uni(hn / rec[(step - 2) * stride + n]);
+      const double eta = uni(hn / rv.row(step - 1)[n]);
       double fct = 1.0;
 #pragma unroll
       for (int j = 1; j <= kQmax; ++j) {
@@ -1896,7 +2046,7 @@ __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int 
       }
       if (q == qp + 1 || q == qp - 1) {
         double xip[kQmax + 2], lp[kQmax + 2], Cp;
-        rec_coeffs(rec, stride, n, hpad, step - 1, qp, xip, lp, Cp);
+        rec_coeffs(rv, n, hpad, step - 1, qp, xip, lp, Cp);
         if (q == qp + 1) {
           const double c = 1.0 / pick(xip, qp + 1);
 #pragma unroll

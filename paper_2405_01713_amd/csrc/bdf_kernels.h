@@ -161,14 +161,26 @@ const void *pair_kernel(bool fp32, int minw, int taba) {
   return fp32 ? t32[w][taba] : t64[w][taba];
 }
 
-template <int S>
+// Adjoint sweep, one wave per cell.  From a full record every wave takes the
+// cell of its grid index; from checkpoints wave w owns segment rows w of
+// P.seg (the host sizes the grid to the rows it holds) and strides over the
+// cells.  ABC as in k_integrate (the recomputed steps run that code).
+template <int S, bool ABC>
 __global__ void __launch_bounds__(256) k_adjoint(Params P) {
   extern __shared__ double smem[];
   const int wib = threadIdx.x / kWave;
   const int li = threadIdx.x & (kWave - 1);
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + wib;
-  if (idx >= P.n_list) return;
-  adjoint_cell<S>(P, P.list ? P.list[idx] : idx, li, smem + static_cast<int64_t>(wib) * P.lds_doubles);
+  const int wpb = blockDim.x / kWave;
+  const int64_t w = static_cast<int64_t>(blockIdx.x) * wpb + wib;
+  double *lds = smem + static_cast<int64_t>(wib) * P.lds_doubles;
+  if (!P.ckpt) {
+    if (w >= P.n_list) return;
+    adjoint_cell<S, ABC>(P, P.list ? P.list[w] : w, li, lds, nullptr);
+    return;
+  }
+  double *seg = P.seg + w * P.seg_rows * P.rec_stride;
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * wpb;
+  for (int64_t i = w; i < P.n_list; i += nw) adjoint_cell<S, ABC>(P, P.list ? P.list[i] : i, li, lds, seg);
 }
 
 struct LaunchCfg {
@@ -287,9 +299,18 @@ hipError_t launch_integrate(const Params &P, bool fp32, int minw, int tab, int c
 }
 
 template <int S>
-hipError_t launch_adjoint(const Params &P, const LaunchCfg &c, hipStream_t s) {
-  hipLaunchKernelGGL((k_adjoint<S>), dim3(c.grid), dim3(c.block), c.lds_bytes, s, P);
+hipError_t launch_adjoint(const Params &P, bool abc, const LaunchCfg &c, hipStream_t s) {
+  if (abc)
+    hipLaunchKernelGGL((k_adjoint<S, true>), dim3(c.grid), dim3(c.block), c.lds_bytes, s, P);
+  else
+    hipLaunchKernelGGL((k_adjoint<S, false>), dim3(c.grid), dim3(c.block), c.lds_bytes, s, P);
   return hipGetLastError();
+}
+
+template <int S>
+hipError_t occupancy_adjoint(bool abc, int block, size_t lds_bytes, int *blocks_per_cu) {
+  const void *f = abc ? (const void *)&k_adjoint<S, true> : (const void *)&k_adjoint<S, false>;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds_bytes);
 }
 
 template <int S>
@@ -322,8 +343,12 @@ hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave,
     return bdfx::occupancy_integrate<S>(fp32, minw, tab, cpw, flags & 1, flags & 2,              \
                                         BDFX_LIN_OF_FLAGS(flags), flags & 16, block, lds, out);  \
   }                                                                                              \
-  hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s) { \
-    return bdfx::launch_adjoint<S>(P, c, s);                                                     \
+  hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, bool abc, const bdfx::LaunchCfg &c,       \
+                                hipStream_t s) {                                                 \
+    return bdfx::launch_adjoint<S>(P, abc, c, s);                                                \
+  }                                                                                              \
+  hipError_t bdfx_adjoint_occupancy_s##S(bool abc, int block, size_t lds, int *out) {            \
+    return bdfx::occupancy_adjoint<S>(abc, block, lds, out);                                     \
   }
 
 // Both bins of a two-mechanism batch in one launch (k_integrate_pair).
@@ -364,4 +389,6 @@ hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave,
                               int flags, const bdfx::LaunchCfg &c, hipStream_t s);               \
   hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, int flags, int block,    \
                                  size_t lds, int *out);                                          \
-  hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, const bdfx::LaunchCfg &c, hipStream_t s);
+  hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, bool abc, const bdfx::LaunchCfg &c,       \
+                                hipStream_t s);                                                  \
+  hipError_t bdfx_adjoint_occupancy_s##S(bool abc, int block, size_t lds, int *out);

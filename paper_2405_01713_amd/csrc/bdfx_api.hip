@@ -57,10 +57,12 @@ struct SizeEntry {
   hipError_t (*launch)(const bdfx::Params &, bool, int, int, int, int, const bdfx::LaunchCfg &,
                        hipStream_t);
   hipError_t (*occupancy)(bool, int, int, int, int, int, size_t, int *);
-  hipError_t (*adjoint)(const bdfx::Params &, const bdfx::LaunchCfg &, hipStream_t);
+  hipError_t (*adjoint)(const bdfx::Params &, bool, const bdfx::LaunchCfg &, hipStream_t);
+  hipError_t (*adjoint_occupancy)(bool, int, size_t, int *);
 };
 
-#define BDFX_SIZE_ENTRY(S) {S, bdfx_launch_s##S, bdfx_occupancy_s##S, bdfx_adjoint_s##S}
+#define BDFX_SIZE_ENTRY(S) \
+  {S, bdfx_launch_s##S, bdfx_occupancy_s##S, bdfx_adjoint_s##S, bdfx_adjoint_occupancy_s##S}
 const SizeEntry kSizes[] = {
     BDFX_SIZE_ENTRY(3),  BDFX_SIZE_ENTRY(4),  BDFX_SIZE_ENTRY(8),
     BDFX_SIZE_ENTRY(9),  BDFX_SIZE_ENTRY(16), BDFX_SIZE_ENTRY(21),
@@ -150,7 +152,11 @@ struct bdfx_ctx_s {
   int S_max = 0, R_max = 0;
   size_t ws_need = 0;
   size_t off_queue = 0, off_bins = 0, off_rec = 0, off_recn = 0, off_rechpad = 0, off_recy0 = 0,
-         off_pbar = 0, off_tune = 0, off_kk = 0, off_ext = 0, off_tatol = 0;
+         off_pbar = 0, off_tune = 0, off_kk = 0, off_ext = 0, off_tatol = 0, off_ckpt = 0,
+         off_ckpt_setup = 0, off_seg = 0;
+  int32_t ckpt_cap = 0;    // checkpoints per cell (checkpoint_every > 0)
+  int32_t ckpt_vs = 0;     // largest padded size: checkpoint vectors hold at most this many
+  int64_t seg_slots = 0;   // waves of the checkpointed adjoint sweep (segment row sets)
   bool typical = false;  // per-mechanism typical-value atol in effect (bdfx_typical_atol)
   int64_t tune_cells = 0;  // rows the autotuner can save in the workspace
   int64_t kk_slots = 0;    // rate-constant slots (waves) for tables in global memory
@@ -400,6 +406,12 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
                                   "GMRES forms none (use BDFX_JAC_ANALYTIC)");
   if (o->gmres_maxl > 0 && o->record_steps > 0)
     return fail(ctx, BDFX_EUNSUPPORTED, "step recording (adjoint) needs the direct solver");
+  if (o->checkpoint_every < 0) return fail(ctx, BDFX_EINVAL, "checkpoint_every < 0");
+  if (o->checkpoint_every > 0 && o->record_steps <= 0)
+    return fail(ctx, BDFX_EINVAL, "checkpoint_every needs record_steps > 0");
+  if (o->checkpoint_every > 0 && (o->lu_precision == 32 || o->jacobian != BDFX_JAC_ANALYTIC))
+    return fail(ctx, BDFX_EUNSUPPORTED,
+                "checkpointed records: FP64 Newton matrix from the analytic Jacobian");
   if (o->lockstep < 0 || o->lockstep > BDFX_MAX_LOCKSTEP)
     return fail(ctx, BDFX_EINVAL, "lockstep must be 0..%d", BDFX_MAX_LOCKSTEP);
   if (o->lockstep > 0 &&
@@ -456,7 +468,33 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
   ctx->off_bins = reserve(static_cast<size_t>(n_mech > 1 ? n_cells : 0) * 4);
   ctx->rec_stride = S_max + 2;
   const int64_t cap = o->record_steps;
-  ctx->off_rec = reserve(static_cast<size_t>(n_cells) * cap * ctx->rec_stride * 8);
+  const int K = o->checkpoint_every;
+  ctx->off_rec = reserve(K > 0 ? 0 : static_cast<size_t>(n_cells) * cap * ctx->rec_stride * 8);
+  ctx->ckpt_cap = K > 0 ? static_cast<int32_t>((cap + K - 1) / K) : 0;
+  ctx->ckpt_vs = 0;
+  for (int m = 0; m < n_mech; ++m)
+    if (const SizeEntry *se = size_for(mechs[m]->n)) ctx->ckpt_vs = std::max(ctx->ckpt_vs, se->S);
+  ctx->off_ckpt = reserve(static_cast<size_t>(n_cells) * ctx->ckpt_cap *
+                          bdfx::Ckpt::stride(ctx->ckpt_vs) * 8);
+  ctx->off_ckpt_setup = reserve(K > 0 ? static_cast<size_t>(n_cells) * ctx->ckpt_vs * 8 : 0);
+  // the checkpointed sweep: as many waves as can be resident (at least one
+  // per CU), each with the rows of one segment
+  ctx->seg_slots = 0;
+  if (K > 0 && n_cells > 0) {
+    int64_t slots = ctx->n_cu;
+    for (int m = 0; m < n_mech; ++m) {
+      const SizeEntry *se = size_for(mechs[m]->n);
+      if (!se) continue;
+      const size_t lds = align_up(bdfx::lds_doubles_adjoint(se->S, mechs[m]->R), 2) * 8;
+      int per_cu = 0;
+      if (lds <= 65536 &&
+          se->adjoint_occupancy(mechs[m]->abc, bdfx::kWave, lds, &per_cu) == hipSuccess)
+        slots = std::max<int64_t>(slots, static_cast<int64_t>(per_cu) * ctx->n_cu);
+    }
+    ctx->seg_slots = std::min<int64_t>(slots, n_cells);
+  }
+  ctx->off_seg = reserve(static_cast<size_t>(ctx->seg_slots) * (K + bdfx::kQmax + 1) *
+                         ctx->rec_stride * 8);
   ctx->off_recn = reserve(cap ? static_cast<size_t>(n_cells) * 4 : 0);
   ctx->off_rechpad = reserve(cap ? static_cast<size_t>(n_cells) * 8 : 0);
   ctx->off_recy0 = reserve(cap ? static_cast<size_t>(n_cells) * ctx->rec_stride * 8 : 0);
@@ -489,7 +527,8 @@ static int kernel_flags(bdfx_ctx ctx, bdfx_mech m) {
 // context's options (isothermal, analytic Jacobian, direct solver)
 static bool two_cells_per_wave_ok(bdfx_ctx ctx, bdfx_mech m, int S) {
   return S <= 32 && !m->thermal && ctx->opt.jacobian != BDFX_JAC_DQ && ctx->opt.gmres_maxl == 0 &&
-         ctx->opt.lockstep == 0 && ctx->opt.scheduler != BDFX_SCHED_FUSED;
+         ctx->opt.lockstep == 0 && ctx->opt.scheduler != BDFX_SCHED_FUSED &&
+         ctx->opt.checkpoint_every == 0;
 }
 
 int bdfx_bind(bdfx_ctx ctx, void *d_ws, size_t ws_bytes, double *d_y, int32_t ldy,
@@ -745,7 +784,15 @@ static bdfx::Params make_params(bdfx_ctx ctx, const Bin &b, double t0, double to
   P.kk_slots = ctx->kk_slots ? reinterpret_cast<double *>(ctx->ws + ctx->off_kk) : nullptr;
   P.kk_nslots = ctx->kk_slots;
   if (ctx->opt.record_steps > 0) {
-    P.rec = reinterpret_cast<double *>(ctx->ws + ctx->off_rec);
+    if (ctx->opt.checkpoint_every > 0) {
+      P.ckpt = reinterpret_cast<double *>(ctx->ws + ctx->off_ckpt);
+      P.ckpt_setup = reinterpret_cast<double *>(ctx->ws + ctx->off_ckpt_setup);
+      P.ckpt_every = ctx->opt.checkpoint_every;
+      P.ckpt_cap = ctx->ckpt_cap;
+      P.ckpt_vs = ctx->ckpt_vs;
+    } else {
+      P.rec = reinterpret_cast<double *>(ctx->ws + ctx->off_rec);
+    }
     P.rec_cap = ctx->opt.record_steps;
     P.rec_stride = ctx->rec_stride;
     P.rec_n = reinterpret_cast<int32_t *>(ctx->ws + ctx->off_recn);
@@ -842,6 +889,7 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
   const bool fp32 = ctx->opt.lu_precision == 32;
   const bool queue = ctx->opt.scheduler != BDFX_SCHED_STATIC;
   const int64_t ns = sample_cells > 0 ? std::min(sample_cells, ctx->tune_cells) : ctx->tune_cells;
+  ctx->integrated = false;  // the timed runs overwrite the sample cells' step records
   double *save = reinterpret_cast<double *>(ctx->ws + ctx->off_tune);
   uint32_t *qctr = reinterpret_cast<uint32_t *>(ctx->ws + ctx->off_queue);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1086,6 +1134,8 @@ int bdfx_get_record_layout(bdfx_ctx ctx, bdfx_record_layout *out) {
   if (!ctx || !out) return fail(ctx, BDFX_EINVAL, "NULL argument");
   if (!ctx->bound || ctx->opt.record_steps <= 0)
     return fail(ctx, BDFX_EORDER, "no step record: bind with record_steps > 0 first");
+  if (ctx->opt.checkpoint_every > 0)
+    return fail(ctx, BDFX_EUNSUPPORTED, "checkpointed records hold no per-step rows");
   out->cap = ctx->opt.record_steps;
   out->stride = ctx->rec_stride;
   out->off_steps = ctx->off_rec;
@@ -1122,7 +1172,13 @@ int bdfx_adjoint(bdfx_ctx ctx, const double *d_ybar, double *d_y0bar, double *d_
     if (cfg.lds_bytes > 65536)
       return fail(ctx, BDFX_EUNSUPPORTED, "adjoint LDS per block %zu exceeds 64 KiB", cfg.lds_bytes);
     cfg.grid = static_cast<int>((b.count + waves - 1) / waves);
-    HIPCHK(ctx, se->adjoint(P, cfg, ctx->stream));
+    if (P.ckpt) {
+      // one segment row set per wave of the grid
+      P.seg = reinterpret_cast<double *>(ctx->ws + ctx->off_seg);
+      P.seg_rows = ctx->opt.checkpoint_every + bdfx::kQmax + 1;
+      cfg.grid = static_cast<int>(std::min<int64_t>(b.count, ctx->seg_slots / waves));
+    }
+    HIPCHK(ctx, se->adjoint(P, m->abc, cfg, ctx->stream));
     if (d_lnA_bar)
       HIPCHK(ctx, bdfx_launch_sum_cells(pbar, ctx->R_max, P.list, b.count, m->R,
                                         d_lnA_bar + static_cast<int64_t>(b.mech) * ctx->R_max,
