@@ -325,12 +325,15 @@ def run_c1(steps, warmup, tuning_cache=None, n_check=256):
     return out
 
 
-def run_adjoint(steps, warmup, n_cells=None, record_steps=2048, n_check=32):
+def run_adjoint(steps, warmup, n_cells=None, record_steps=2048, n_check=32, ckpt_every=32):
     """Adjoint/forward cost on the 65,536-cell 21-species workload: plain
     forward (no recording), forward with step recording, discrete-adjoint
     backward of the loss sum_cells sum_i c_i y_i; a sample of cells is checked
     against the oracle's adjoint along the GPU's own step record (the same
-    frozen map, so the two differ by round-off)."""
+    frozen map, so the two differ by round-off).  Then the same with
+    checkpointed records (a checkpoint every ckpt_every steps, segments rerun
+    in the backward sweep): its workspace, times, and whether its gradient
+    equals the full record's bit for bit."""
     import torch
     from paper_2405_01713_amd import bdfx
 
@@ -381,13 +384,40 @@ def run_adjoint(steps, warmup, n_cells=None, record_steps=2048, n_check=32):
     t_bwd = timed(bwd, rec.stream)
     log(f"adjoint: forward {t_fwd:.1f} ms, backward {t_bwd:.1f} ms")
     st = rec.cell_stats()
-    y0bar = out["g"][0][:n_check].cpu().numpy()
+    g_full = [t.clone() for t in out["g"]]
+    y0bar = g_full[0][:n_check].cpu().numpy()
     recs = rec.step_record(np.arange(n_check))
+    ws_full = rec.ws_bytes
     rec.close()
     res = dict(workload="s21_r84_65k_adjoint", n_cells=N, fwd_ms=t_fwd, fwd_record_ms=t_rec,
                bwd_ms=t_bwd, ratio_bwd_over_fwd=t_bwd / t_fwd,
                ratio_fwd_record_plus_bwd_over_fwd=(t_rec + t_bwd) / t_fwd,
-               failed_cells=int(np.sum(st["status"] != 0)), max_nst=int(st["nst"].max()))
+               failed_cells=int(np.sum(st["status"] != 0)), max_nst=int(st["nst"].max()),
+               workspace_full_record_mb=ws_full / 1e6)
+
+    ck = bdfx.Integrator([m], w["y0"], w["rtol"], w["atol"], T=w["T"], record_steps=record_steps,
+                         checkpoint_every=ckpt_every, **common)
+
+    def fwd_ck():
+        ck.y.copy_(y0)
+        ck.integrate(0.0, w["t_out"])
+
+    t_fck = timed(fwd_ck, ck.stream)
+
+    def bwd_ck():
+        out["gc"] = ck.adjoint(ybar)
+
+    t_bck = timed(bwd_ck, ck.stream)
+    torch.cuda.synchronize()
+    res["checkpointed"] = dict(
+        every=ckpt_every, workspace_mb=ck.ws_bytes / 1e6, fwd_ms=t_fck, bwd_ms=t_bck,
+        ratio_bwd_over_fwd=t_bck / t_fwd, ratio_fwd_plus_bwd_over_fwd=(t_fck + t_bck) / t_fwd,
+        workspace_ratio_full_over_checkpointed=ws_full / ck.ws_bytes,
+        gradient_bitwise_equal=bool(torch.equal(out["gc"][0], g_full[0]) and
+                                    torch.equal(out["gc"][1], g_full[1])))
+    ck.close()
+    log(f"checkpointed adjoint (every {ckpt_every}): forward {t_fck:.1f} ms, backward "
+        f"{t_bck:.1f} ms, workspace {ws_full / 1e6:.0f} -> {res['checkpointed']['workspace_mb']:.0f} MB")
     try:
         from oracle import oracle as O
         go = np.zeros((n_check, m["n_species"]))

@@ -343,11 +343,13 @@ int bdfx_stats_summary(bdfx_ctx ctx, bdfx_summary *out);
  *                       mechanism (may be NULL)
  * The gradient is that of the discrete map with the recorded step sizes and
  * orders held fixed and each corrector solved exactly (Jacobians re-evaluated
- * at the recorded states).  With checkpoint_every = K > 0 the sweep first
- * reruns each K-step segment from its checkpoint into a workspace area (one
- * segment per resident wave of the sweep), which gives the same steps bit for
- * bit; the bound inputs (T, rate scales, forcing) must be unchanged since the
- * integrate.  Enqueue only. */
+ * at the recorded states).  With checkpoint_every = K > 0 the sweep runs in
+ * passes over the segments from the last: each pass reruns one K-step segment
+ * of every cell from its checkpoint into the workspace ((K + 6) x (S_max + 2)
+ * doubles per cell), which gives the same steps bit for bit, and then sweeps
+ * it; ceil(record_steps / K) passes of two launches each.  The bound inputs
+ * (T, rate scales, forcing) must be unchanged since the integrate.  Enqueue
+ * only. */
 int bdfx_adjoint(bdfx_ctx ctx, const double *d_ybar, double *d_y0bar, double *d_lnA_bar);
 
 /* Where bdfx_integrate() with record_steps > 0 leaves the step record in the

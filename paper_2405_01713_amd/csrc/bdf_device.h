@@ -113,8 +113,9 @@ struct Params {
   double *ckpt;           // [N][ckpt_cap][Ckpt::stride(ckpt_vs)]
   double *ckpt_setup;     // [N][ckpt_vs]: predicted state of the cell's last Newton-matrix setup
   int32_t ckpt_every, ckpt_cap, ckpt_vs;
-  int32_t seg_rows;       // adjoint: rows of a recomputed segment (ckpt_every + kQmax + 1)
-  double *seg;            // adjoint: [waves][seg_rows][rec_stride], one per wave of the grid
+  int32_t seg_rows;       // adjoint: rows of a rerun segment (ckpt_every + kQmax + 1)
+  double *seg;            // adjoint: [N][seg_rows][rec_stride], each cell's current segment
+  double *adj;            // adjoint: [N][kQmax + 2][ckpt_vs], sweep state between segments
   const double *atol;     // [atol_len] (device)
   // adjoint (bdfx_adjoint only)
   const double *ybar;     // [N][ldy] dL/dy(t_out)
@@ -1925,15 +1926,17 @@ __device__ __forceinline__ void rec_coeffs(const RecView &rv, int n, double hpad
   bdf_coeffs(q, xi, l, Cerr);
 }
 
-// With checkpoints (P.ckpt) the steps are not stored: when the sweep reaches
-// a segment it reruns the integrator from the segment's checkpoint (the same
-// integrate_cell code, so the same steps to the bit) into `seg`, the wave's
-// segment rows, whose first kQmax + 1 rows take the step sizes before the
-// checkpoint, its state and its order from the checkpoint.  ABC: the forward
-// run's rate-expression specialisation.
-template <int S, bool ABC>
-__device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int li, double *lds,
-                                             double *seg) {
+// Sweeps steps hi down to lo (1 <= lo, hi <= the cell's step count) of one
+// cell through the rows rv.  init: the sweep starts at the cell's last step
+// from dL/dy(t_out); else from the state an earlier call parked (P.adj: the
+// lane vectors zbar_0 .. zbar_kQmax and the order-raise term; P.pbar: the
+// dL/dlnA sums).  lo == 1 finishes the cell (dL/dy0 and dL/dlnA written),
+// else the state is parked for the call that sweeps the steps before lo.  The
+// sums run in step order either way, so a sweep in pieces equals one sweep
+// over all steps bit for bit.
+template <int S>
+__device__ __forceinline__ void adjoint_steps(const Params &P, int64_t cell, int li, double *lds,
+                                              const RecView &rv, int hi, int lo, bool init) {
   const MechDev &m = P.mech;
   const int R = m.R;
   const Lds L = carve<kTabLds>(lds, R, m.rx, nullptr);
@@ -1947,6 +1950,7 @@ __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int 
   const int n = P.n_sp;
   const bool own = li < n;
   const int stride = P.rec_stride;
+  double *park = P.adj ? P.adj + cell * (kQmax + 2) * P.ckpt_vs : nullptr;
 
   const double T = P.T ? P.T[cell] : 1.0;
   wave_lds_sync();
@@ -1958,38 +1962,23 @@ __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int 
     L.kk[2 * r] = kf;
     L.kk[2 * r + 1] = m.reversible ? -(kf * exp(-m.lnK[r])) : -0.0;
     const_cast<int2 *>(L.rx)[r] = reinterpret_cast<const int2 *>(m.rx)[r];
-    pb[r] = 0.0;
+    pb[r] = init ? 0.0 : P.pbar[cell * P.ldp + r];
   }
-  const bool ckpt = P.ckpt != nullptr;
-  RecView rv{ckpt ? seg : P.rec + static_cast<int64_t>(cell) * P.rec_cap * stride, 1, stride};
-  const int N = uni(P.rec_n[cell]);
   const double hpad = uni(P.rec_hpad[cell]);
-  int lo = ckpt ? N + 1 : 1;  // first step the rows hold
   double zb[kQmax + 1];
+  double ebx = 0.0;
+  if (init) {
 #pragma unroll
-  for (int j = 0; j <= kQmax; ++j) zb[j] = 0.0;
-  zb[0] = own ? P.ybar[cell * P.ldy + li] : 0.0;
-  double ebx = 0.0, y0bar = zb[0];
+    for (int j = 0; j <= kQmax; ++j) zb[j] = 0.0;
+    zb[0] = own ? P.ybar[cell * P.ldy + li] : 0.0;
+  } else {
+#pragma unroll
+    for (int j = 0; j <= kQmax; ++j) zb[j] = own ? park[j * P.ckpt_vs + li] : 0.0;
+    ebx = own ? park[(kQmax + 1) * P.ckpt_vs + li] : 0.0;
+  }
+  double y0bar = zb[0];
 
-  for (int step = N; step >= 1; --step) {
-    if (step < lo) {
-      // recompute the segment of steps n0 + 1 .. n0 + K from checkpoint n0 / K
-      const int K = P.ckpt_every, c = (step - 1) / K, n0 = c * K;
-      const double *ck = P.ckpt + (cell * P.ckpt_cap + c) * Ckpt::stride(P.ckpt_vs);
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the last segment's reads are done
-      if (li == 0) {
-#pragma unroll
-        for (int j = 0; j <= kQmax; ++j) seg[j * stride + n] = ck[Ckpt::kHist + kQmax - j];
-        seg[kQmax * stride + n + 1] = ck[Ckpt::kQtaken];
-      }
-      if (own) seg[kQmax * stride + li] = ck[Ckpt::vec(0, S) + li];
-      const Resume rs{ck, seg, n0 - kQmax, n0 + K < N ? n0 + K : N, P.seg_rows};
-      integrate_cell<S, double, kTabLds, 1, ABC, false, kLinAnalytic, false, true>(
-          P, cell, W1, lds, nullptr, BatchRed<false>{}, 1, &rs);
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // its rows are written
-      rv.first = n0 - kQmax;
-      lo = n0 + 1;
-    }
+  for (int step = hi; step >= lo; --step) {
     const int qr = uni(static_cast<int>(rv.row(step)[n + 1]));
     const int q = qr & 255;
     const double hn = uni(rv.row(step)[n]);
@@ -2077,9 +2066,65 @@ __device__ __forceinline__ void adjoint_cell(const Params &P, int64_t cell, int 
       }
     }
   }
-  if (own) P.y0bar[cell * P.ldy + li] = y0bar;
+  if (lo == 1) {
+    if (own) P.y0bar[cell * P.ldy + li] = y0bar;
+  } else if (own) {
+#pragma unroll
+    for (int j = 0; j <= kQmax; ++j) park[j * P.ckpt_vs + li] = zb[j];
+    park[(kQmax + 1) * P.ckpt_vs + li] = ebx;
+  }
   wave_lds_sync();
   for (int r = li; r < R; r += kWave) P.pbar[cell * P.ldp + r] = pb[r];
+}
+
+// Checkpointed records: the segments of a cell (steps cK + 1 .. (c + 1)K,
+// K = P.ckpt_every, the last one cut at the cell's step count) are swept from
+// the last in passes; pass j takes segment nseg - 1 - j of every cell that
+// has more than j segments.  A cell without steps has one empty segment.
+__device__ __forceinline__ int adj_segments(const Params &P, int64_t cell) {
+  const int N = uni(P.rec_n[cell]);
+  return N > 0 ? (N + P.ckpt_every - 1) / P.ckpt_every : 1;
+}
+
+// The rows of one cell's segment (P.seg_rows rows of P.rec_stride from
+// P.seg): rows 0 .. kQmax hold steps n0 - kQmax .. n0 (their step sizes; step
+// n0 also its state and order, from the checkpoint), the rest steps n0 + 1 ..
+__device__ __forceinline__ RecView adj_rows(const Params &P, int64_t cell, int n0) {
+  return RecView{P.seg + cell * P.seg_rows * P.rec_stride, n0 - kQmax, P.rec_stride};
+}
+
+// Pass j, first half: rerun the cell's segment from its checkpoint with the
+// forward step code (the same steps, bit for bit) into its rows.
+template <int S, bool ABC>
+__device__ __forceinline__ void rerun_segment(const Params &P, int64_t cell, const Grp<1> &W,
+                                              double *lds, int j) {
+  const int nseg = adj_segments(P, cell);
+  const int N = uni(P.rec_n[cell]);
+  if (j >= nseg || N == 0) return;
+  const int K = P.ckpt_every, c = nseg - 1 - j, n0 = c * K;
+  const double *ck = P.ckpt + (cell * P.ckpt_cap + c) * Ckpt::stride(P.ckpt_vs);
+  double *rows = P.seg + cell * P.seg_rows * P.rec_stride;
+  const int n = P.n_sp, stride = P.rec_stride;
+  if (W.lane == 0) {
+#pragma unroll
+    for (int k = 0; k <= kQmax; ++k) rows[k * stride + n] = ck[Ckpt::kHist + kQmax - k];
+    rows[kQmax * stride + n + 1] = ck[Ckpt::kQtaken];
+  }
+  if (W.lane < n) rows[kQmax * stride + W.lane] = ck[Ckpt::vec(0, S) + W.lane];
+  const Resume rs{ck, rows, n0 - kQmax, n0 + K < N ? n0 + K : N, P.seg_rows};
+  integrate_cell<S, double, kTabLds, 1, ABC, false, kLinAnalytic, false, true>(
+      P, cell, W, lds, nullptr, BatchRed<false>{}, 1, &rs);
+}
+
+// Pass j, second half: sweep the rerun segment.
+template <int S>
+__device__ __forceinline__ void sweep_segment(const Params &P, int64_t cell, int li, double *lds,
+                                              int j) {
+  const int nseg = adj_segments(P, cell);
+  if (j >= nseg) return;
+  const int N = uni(P.rec_n[cell]);
+  const int K = P.ckpt_every, c = nseg - 1 - j, n0 = c * K;
+  adjoint_steps<S>(P, cell, li, lds, adj_rows(P, cell, n0), n0 + K < N ? n0 + K : N, n0 + 1, j == 0);
 }
 
 __host__ __device__ constexpr int lds_doubles_adjoint(int S, int R) {

@@ -161,26 +161,52 @@ const void *pair_kernel(bool fp32, int minw, int taba) {
   return fp32 ? t32[w][taba] : t64[w][taba];
 }
 
-// Adjoint sweep, one wave per cell.  From a full record every wave takes the
-// cell of its grid index; from checkpoints wave w owns segment rows w of
-// P.seg (the host sizes the grid to the rows it holds) and strides over the
-// cells.  ABC as in k_integrate (the recomputed steps run that code).
-template <int S, bool ABC>
+// Adjoint sweep over a full record: one wave per cell.
+template <int S>
 __global__ void __launch_bounds__(256) k_adjoint(Params P) {
   extern __shared__ double smem[];
   const int wib = threadIdx.x / kWave;
   const int li = threadIdx.x & (kWave - 1);
-  const int wpb = blockDim.x / kWave;
-  const int64_t w = static_cast<int64_t>(blockIdx.x) * wpb + wib;
-  double *lds = smem + static_cast<int64_t>(wib) * P.lds_doubles;
-  if (!P.ckpt) {
-    if (w >= P.n_list) return;
-    adjoint_cell<S, ABC>(P, P.list ? P.list[w] : w, li, lds, nullptr);
-    return;
-  }
-  double *seg = P.seg + w * P.seg_rows * P.rec_stride;
-  const int64_t nw = static_cast<int64_t>(gridDim.x) * wpb;
-  for (int64_t i = w; i < P.n_list; i += nw) adjoint_cell<S, ABC>(P, P.list ? P.list[i] : i, li, lds, seg);
+  const int64_t w = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + wib;
+  if (w >= P.n_list) return;
+  const int64_t cell = P.list ? P.list[w] : w;
+  const RecView rv{P.rec + cell * P.rec_cap * P.rec_stride, 1, P.rec_stride};
+  adjoint_steps<S>(P, cell, li, smem + static_cast<int64_t>(wib) * P.lds_doubles, rv,
+                   uni(P.rec_n[cell]), 1, true);
+}
+
+// Pass j of the sweep over checkpointed records, as two launches: k_adj_rerun
+// reruns the pass's segment of every cell (the forward step code, at a
+// forward run's register budget), k_adj_sweep sweeps it (at the sweep's).  One
+// wave per cell of the list; a cell without a segment in this pass returns at
+// once.  (A persistent loop over cells costs these kernels 20-35 % more
+// registers.)  ABC as in k_integrate.
+template <int S, bool ABC>
+__global__ void __launch_bounds__(256) k_adj_rerun(Params P, int j) {
+  extern __shared__ double smem[];
+  const int wib = threadIdx.x / kWave;
+  const Grp<1> W(threadIdx.x & (kWave - 1));
+  const int64_t w = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + wib;
+  if (w >= P.n_list) return;
+  rerun_segment<S, ABC>(P, P.list ? P.list[w] : w, W, smem + static_cast<int64_t>(wib) * P.lds_doubles, j);
+}
+
+template <int S>
+__global__ void __launch_bounds__(256) k_adj_sweep(Params P, int j) {
+  extern __shared__ double smem[];
+  const int wib = threadIdx.x / kWave;
+  const int li = threadIdx.x & (kWave - 1);
+  const int64_t w = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + wib;
+  if (w >= P.n_list) return;
+  sweep_segment<S>(P, P.list ? P.list[w] : w, li, smem + static_cast<int64_t>(wib) * P.lds_doubles, j);
+}
+
+// kind 0: full-record sweep; 1: segment rerun; 2: segment sweep
+template <int S>
+const void *adjoint_kernel(int kind, bool abc) {
+  if (kind == 0) return (const void *)&k_adjoint<S>;
+  if (kind == 2) return (const void *)&k_adj_sweep<S>;
+  return abc ? (const void *)&k_adj_rerun<S, true> : (const void *)&k_adj_rerun<S, false>;
 }
 
 struct LaunchCfg {
@@ -299,19 +325,15 @@ hipError_t launch_integrate(const Params &P, bool fp32, int minw, int tab, int c
 }
 
 template <int S>
-hipError_t launch_adjoint(const Params &P, bool abc, const LaunchCfg &c, hipStream_t s) {
-  if (abc)
-    hipLaunchKernelGGL((k_adjoint<S, true>), dim3(c.grid), dim3(c.block), c.lds_bytes, s, P);
-  else
-    hipLaunchKernelGGL((k_adjoint<S, false>), dim3(c.grid), dim3(c.block), c.lds_bytes, s, P);
-  return hipGetLastError();
+hipError_t launch_adjoint(const Params &P, int kind, int pass, bool abc, const LaunchCfg &c,
+                          hipStream_t s) {
+  Params arg = P;
+  int j = pass;
+  void *args[] = {&arg, &j};
+  return hipLaunchKernel(adjoint_kernel<S>(kind, abc), dim3(c.grid), dim3(c.block), args,
+                         c.lds_bytes, s);
 }
 
-template <int S>
-hipError_t occupancy_adjoint(bool abc, int block, size_t lds_bytes, int *blocks_per_cu) {
-  const void *f = abc ? (const void *)&k_adjoint<S, true> : (const void *)&k_adjoint<S, false>;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds_bytes);
-}
 
 template <int S>
 hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave, bool abc,
@@ -343,12 +365,9 @@ hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave,
     return bdfx::occupancy_integrate<S>(fp32, minw, tab, cpw, flags & 1, flags & 2,              \
                                         BDFX_LIN_OF_FLAGS(flags), flags & 16, block, lds, out);  \
   }                                                                                              \
-  hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, bool abc, const bdfx::LaunchCfg &c,       \
-                                hipStream_t s) {                                                 \
-    return bdfx::launch_adjoint<S>(P, abc, c, s);                                                \
-  }                                                                                              \
-  hipError_t bdfx_adjoint_occupancy_s##S(bool abc, int block, size_t lds, int *out) {            \
-    return bdfx::occupancy_adjoint<S>(abc, block, lds, out);                                     \
+  hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, int kind, int pass, bool abc,            \
+                                const bdfx::LaunchCfg &c, hipStream_t s) {                       \
+    return bdfx::launch_adjoint<S>(P, kind, pass, abc, c, s);                                    \
   }
 
 // Both bins of a two-mechanism batch in one launch (k_integrate_pair).
@@ -389,6 +408,5 @@ hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave,
                               int flags, const bdfx::LaunchCfg &c, hipStream_t s);               \
   hipError_t bdfx_occupancy_s##S(bool fp32, int minw, int tab, int cpw, int flags, int block,    \
                                  size_t lds, int *out);                                          \
-  hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, bool abc, const bdfx::LaunchCfg &c,       \
-                                hipStream_t s);                                                  \
-  hipError_t bdfx_adjoint_occupancy_s##S(bool abc, int block, size_t lds, int *out);
+  hipError_t bdfx_adjoint_s##S(const bdfx::Params &P, int kind, int pass, bool abc,            \
+                                const bdfx::LaunchCfg &c, hipStream_t s);

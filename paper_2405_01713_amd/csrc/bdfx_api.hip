@@ -57,12 +57,14 @@ struct SizeEntry {
   hipError_t (*launch)(const bdfx::Params &, bool, int, int, int, int, const bdfx::LaunchCfg &,
                        hipStream_t);
   hipError_t (*occupancy)(bool, int, int, int, int, int, size_t, int *);
-  hipError_t (*adjoint)(const bdfx::Params &, bool, const bdfx::LaunchCfg &, hipStream_t);
-  hipError_t (*adjoint_occupancy)(bool, int, size_t, int *);
+  // adjoint kernels (kind 0: full-record sweep; 1, 2: rerun and sweep of a
+  // checkpointed pass)
+  hipError_t (*adjoint)(const bdfx::Params &, int, int, bool, const bdfx::LaunchCfg &, hipStream_t);
+
 };
 
 #define BDFX_SIZE_ENTRY(S) \
-  {S, bdfx_launch_s##S, bdfx_occupancy_s##S, bdfx_adjoint_s##S, bdfx_adjoint_occupancy_s##S}
+  {S, bdfx_launch_s##S, bdfx_occupancy_s##S, bdfx_adjoint_s##S}
 const SizeEntry kSizes[] = {
     BDFX_SIZE_ENTRY(3),  BDFX_SIZE_ENTRY(4),  BDFX_SIZE_ENTRY(8),
     BDFX_SIZE_ENTRY(9),  BDFX_SIZE_ENTRY(16), BDFX_SIZE_ENTRY(21),
@@ -153,10 +155,9 @@ struct bdfx_ctx_s {
   size_t ws_need = 0;
   size_t off_queue = 0, off_bins = 0, off_rec = 0, off_recn = 0, off_rechpad = 0, off_recy0 = 0,
          off_pbar = 0, off_tune = 0, off_kk = 0, off_ext = 0, off_tatol = 0, off_ckpt = 0,
-         off_ckpt_setup = 0, off_seg = 0;
+         off_ckpt_setup = 0, off_seg = 0, off_adj = 0;
   int32_t ckpt_cap = 0;    // checkpoints per cell (checkpoint_every > 0)
   int32_t ckpt_vs = 0;     // largest padded size: checkpoint vectors hold at most this many
-  int64_t seg_slots = 0;   // waves of the checkpointed adjoint sweep (segment row sets)
   bool typical = false;  // per-mechanism typical-value atol in effect (bdfx_typical_atol)
   int64_t tune_cells = 0;  // rows the autotuner can save in the workspace
   int64_t kk_slots = 0;    // rate-constant slots (waves) for tables in global memory
@@ -477,24 +478,11 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
   ctx->off_ckpt = reserve(static_cast<size_t>(n_cells) * ctx->ckpt_cap *
                           bdfx::Ckpt::stride(ctx->ckpt_vs) * 8);
   ctx->off_ckpt_setup = reserve(K > 0 ? static_cast<size_t>(n_cells) * ctx->ckpt_vs * 8 : 0);
-  // the checkpointed sweep: as many waves as can be resident (at least one
-  // per CU), each with the rows of one segment
-  ctx->seg_slots = 0;
-  if (K > 0 && n_cells > 0) {
-    int64_t slots = ctx->n_cu;
-    for (int m = 0; m < n_mech; ++m) {
-      const SizeEntry *se = size_for(mechs[m]->n);
-      if (!se) continue;
-      const size_t lds = align_up(bdfx::lds_doubles_adjoint(se->S, mechs[m]->R), 2) * 8;
-      int per_cu = 0;
-      if (lds <= 65536 &&
-          se->adjoint_occupancy(mechs[m]->abc, bdfx::kWave, lds, &per_cu) == hipSuccess)
-        slots = std::max<int64_t>(slots, static_cast<int64_t>(per_cu) * ctx->n_cu);
-    }
-    ctx->seg_slots = std::min<int64_t>(slots, n_cells);
-  }
-  ctx->off_seg = reserve(static_cast<size_t>(ctx->seg_slots) * (K + bdfx::kQmax + 1) *
-                         ctx->rec_stride * 8);
+  // the checkpointed sweep: each cell's current segment rows and its parked
+  // sweep state
+  const size_t seg_rows = K > 0 ? static_cast<size_t>(K) + bdfx::kQmax + 1 : 0;
+  ctx->off_seg = reserve(static_cast<size_t>(n_cells) * seg_rows * ctx->rec_stride * 8);
+  ctx->off_adj = reserve(K > 0 ? static_cast<size_t>(n_cells) * (bdfx::kQmax + 2) * ctx->ckpt_vs * 8 : 0);
   ctx->off_recn = reserve(cap ? static_cast<size_t>(n_cells) * 4 : 0);
   ctx->off_rechpad = reserve(cap ? static_cast<size_t>(n_cells) * 8 : 0);
   ctx->off_recy0 = reserve(cap ? static_cast<size_t>(n_cells) * ctx->rec_stride * 8 : 0);
@@ -1155,6 +1143,7 @@ int bdfx_adjoint(bdfx_ctx ctx, const double *d_ybar, double *d_y0bar, double *d_
   if (!d_ybar || !d_y0bar) return fail(ctx, BDFX_EINVAL, "ybar and y0bar required");
   HIPCHK(ctx, hipSetDevice(ctx->device));
   double *pbar = reinterpret_cast<double *>(ctx->ws + ctx->off_pbar);
+  const int K = ctx->opt.checkpoint_every;
   for (const Bin &b : ctx->bins) {
     if (b.count == 0) continue;
     const bdfx_mech m = ctx->mechs[b.mech];
@@ -1164,21 +1153,30 @@ int bdfx_adjoint(bdfx_ctx ctx, const double *d_ybar, double *d_y0bar, double *d_
     P.y0bar = d_y0bar;
     P.pbar = pbar;
     P.ldp = ctx->R_max;
-    const int waves = 1;
-    P.lds_doubles = static_cast<int32_t>(align_up(bdfx::lds_doubles_adjoint(se->S, m->R), 2));
+    const int32_t lds_sweep = static_cast<int32_t>(align_up(bdfx::lds_doubles_adjoint(se->S, m->R), 2));
     bdfx::LaunchCfg cfg;
-    cfg.block = bdfx::kWave * waves;
-    cfg.lds_bytes = static_cast<size_t>(waves) * P.lds_doubles * 8;
+    cfg.block = bdfx::kWave;  // one wave per block, one block per cell
+    cfg.grid = static_cast<int>(b.count);
+    cfg.lds_bytes = static_cast<size_t>(lds_sweep) * 8;
     if (cfg.lds_bytes > 65536)
       return fail(ctx, BDFX_EUNSUPPORTED, "adjoint LDS per block %zu exceeds 64 KiB", cfg.lds_bytes);
-    cfg.grid = static_cast<int>((b.count + waves - 1) / waves);
-    if (P.ckpt) {
-      // one segment row set per wave of the grid
+    P.lds_doubles = lds_sweep;
+    if (K == 0) {
+      HIPCHK(ctx, se->adjoint(P, 0, 0, m->abc, cfg, ctx->stream));
+    } else {
+      // passes over the segments from the last: rerun, then sweep
       P.seg = reinterpret_cast<double *>(ctx->ws + ctx->off_seg);
-      P.seg_rows = ctx->opt.checkpoint_every + bdfx::kQmax + 1;
-      cfg.grid = static_cast<int>(std::min<int64_t>(b.count, ctx->seg_slots / waves));
+      P.seg_rows = K + bdfx::kQmax + 1;
+      P.adj = reinterpret_cast<double *>(ctx->ws + ctx->off_adj);
+      bdfx::Params PR = P;
+      PR.lds_doubles = static_cast<int32_t>(align_up(bdfx::lds_doubles(se->S, m->R, 8), 2));
+      bdfx::LaunchCfg cr = cfg;
+      cr.lds_bytes = static_cast<size_t>(PR.lds_doubles) * 8;
+      for (int j = 0; j < ctx->ckpt_cap; ++j) {
+        HIPCHK(ctx, se->adjoint(PR, 1, j, m->abc, cr, ctx->stream));
+        HIPCHK(ctx, se->adjoint(P, 2, j, m->abc, cfg, ctx->stream));
+      }
     }
-    HIPCHK(ctx, se->adjoint(P, m->abc, cfg, ctx->stream));
     if (d_lnA_bar)
       HIPCHK(ctx, bdfx_launch_sum_cells(pbar, ctx->R_max, P.list, b.count, m->R,
                                         d_lnA_bar + static_cast<int64_t>(b.mech) * ctx->R_max,

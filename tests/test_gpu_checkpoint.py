@@ -7,7 +7,8 @@ backwards.  The rerun takes the same steps to the bit, so the gradient must
 equal the full record's exactly: compared bit for bit here for several K (one
 step per segment, K dividing nothing, one segment for the whole run), on one
 mechanism and on a two-mechanism batch (per-bin launches and the one-launch
-form), with more cells than the sweep has waves, and when the record fills up.
+form), on 4,096 cells whose segment counts differ (each pass covers those
+cells that still have a segment), and when the record fills up.
 The forward results do not depend on the recording mode either.
 """
 import numpy as np
@@ -85,12 +86,16 @@ def test_checkpointed_gradient_two_mechanisms(scheduler):
     _same(full, ck, f"scheduler {scheduler}")
 
 
-def test_checkpointed_sweep_with_more_cells_than_waves():
-    """4096 cells: the sweep's waves (one set of segment rows each) take
-    several cells one after the other."""
+def test_checkpointed_sweep_on_4096_cells():
+    """4,096 cells in segments of 24 steps; their step counts differ by many
+    segments, so the later passes rerun and sweep only the cells with the most
+    steps."""
     w = W.make_workload("s21_r84_65k_adjoint", 4096)
     yb = _ybar(w)
     full = _grad(w, yb, record_steps=2048, scheduler=1)
+    nst = full["st"]["nst"]
+    print(f"steps per cell {nst.min()}..{nst.max()}")
+    assert np.all(full["st"]["status"] == 0) and nst.max() - nst.min() >= 10 * 24
     ck = _grad(w, yb, record_steps=2048, scheduler=1, checkpoint_every=24)
     _same(full, ck, "4096 cells")
     assert ck["ws"] * 2 < full["ws"]  # 188 doubles per 24 steps instead of 23 per step
