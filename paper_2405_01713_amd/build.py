@@ -19,8 +19,14 @@ BUILD = os.path.join(ROOT, "_build", "bdfx")
 LIB = os.path.join(PKG, "libbdfx.so")
 ARCH = os.environ.get("BDFX_OFFLOAD_ARCH", "gfx950")
 
+# -disable-machine-licm: machine-level loop-invariant hoisting lifts values
+# out of the kernels' outer loops (over cells) and keeps them live through the
+# whole integration; without it the integrator kernels need 15-25 % fewer
+# registers and spill less at the 3- and 4-wave budgets (measured: same
+# results bit for bit, 0-3 % faster).
 CFLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-disable-machine-licm",
           "-I", os.path.join(ROOT, "include"), "-Wno-unused-result"]
 
 
