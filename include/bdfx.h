@@ -107,8 +107,10 @@ typedef struct {
                                A + B <=> C mechanisms on the direct solver with the analytic
                                Jacobian whose padded sizes have a compiled pair (53 with 9);
                                otherwise the bins are launched one after the other.  One
-                               cell per wave.  Results equal the BDFX_SCHED_QUEUE ones bit
-                               for bit. */
+                               cell per wave.  bdfx_autotune() also times the one launch
+                               against the per-mechanism launches on its samples and keeps
+                               the faster (bdfx_tuning.fused).  Results equal the
+                               BDFX_SCHED_QUEUE ones bit for bit. */
 
 typedef struct {
   double rtol;           /* relative tolerance of Eq. (3), > 0 */

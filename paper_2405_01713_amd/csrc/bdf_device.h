@@ -159,6 +159,15 @@ __device__ __forceinline__ float lane_bcast(float v, int lane) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
 
+// value of lane `src` (per-lane index, taken mod 64) by ds_bpermute
+__device__ __forceinline__ double lane_pull(double v, int src) {
+  const int2 p = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_ds_bpermute(src << 2, p.x);
+  r.y = __builtin_amdgcn_ds_bpermute(src << 2, p.y);
+  return __builtin_bit_cast(double, r);
+}
+
 // One 32-bit DPP move.  With every row enabled the permutations used here
 // read a valid source lane everywhere, so no old value is needed (and none
 // is materialised); rows a row mask disables read 0.
@@ -575,17 +584,39 @@ struct KryLayout {
         c(g + maxl + 1), size(c + maxl) {}
 };
 
+// Slots of the inverse Newton matrix a wave keeps in registers instead of
+// LDS (inv_tail columns of S entries).  At 53 species with the FP64 matrix
+// (analytic Jacobian, one isothermal cell per wave, not lock-step) the last 9
+// pivot slots: with the tables in global memory the wave then needs 20,192
+// bytes of LDS, so 8 waves fit a CU's 160 KiB instead of 6, for 18 more VGPRs.
+__host__ __device__ constexpr int inv_tail(int S, int lt_bytes, bool thermal, int lin, bool lock,
+                                           int cells_per_wave) {
+  return S == 53 && lt_bytes == 8 && !thermal && lin == kLinAnalytic && !lock && cells_per_wave == 1
+             ? 9
+             : 0;
+}
+
 // doubles of LDS per wave for S state entries, R reactions, factor type
 // size, table placement and non-isothermal cells; gmres_maxl > 0: GMRES
 // kernels, whose Krylov area replaces the Newton matrix and the
-// non-isothermal Jacobian rows
+// non-isothermal Jacobian rows; tail: inverse slots held in registers
+// (inv_tail)
 __host__ __device__ constexpr int lds_doubles(int S, int R, int lt_bytes, int tab = kTabLds,
-                                              bool thermal = false, int gmres_maxl = 0) {
+                                              bool thermal = false, int gmres_maxl = 0,
+                                              int tail = 0) {
   return 2 * kWave + 8 + Ctl::kSize + kWave / 2 + (tab == kTabLds ? R : 0) +
          (tab == kTabGlobal ? 0 : 2 * R) +
          (gmres_maxl > 0 ? KryLayout(S, gmres_maxl).size
-                         : (S * S * lt_bytes + 7) / 8 + (thermal ? 2 * (kWave + 8) : 0));
+                         : ((S - tail) * S * lt_bytes + 7) / 8 + (thermal ? 2 * (kWave + 8) : 0));
 }
+
+// Inverse slots held in registers (lane r: M^{-1}(r, perm[S - T + t])).
+template <int T, typename LT>
+struct InvTail {
+  LT v[T];
+};
+template <typename LT>
+struct InvTail<0, LT> {};
 
 template <int TAB, bool TH = false, bool KRY = false>
 __device__ __forceinline__ Lds carve(double *base, int R, const int32_t *mech_rx, double *kk_slot,
@@ -735,70 +766,87 @@ __device__ __forceinline__ double rhs(const MechDev &m, const Lds &L, const Grp<
 // -gamma nu_ir d q_r / d y_c to M(i, c) for every occupied slot i of the
 // reaction (reactant slots count -1, product slots +1) with LDS atomics.
 // Each lane then reads its row (its column for M^T).  Terms are rounded to LT
-// before they are summed.
-template <int S, typename LT, bool ABC = false, int G>
+// before they are summed.  T > 0 (an inverse with T slots in registers,
+// whose LDS area holds S - T columns): two passes over the reactions, columns
+// 0 .. S-T-1 and then the last T, each entry with the same terms in the same
+// order as in one pass.
+template <int S, typename LT, bool ABC = false, int T = 0, int G>
 __device__ __forceinline__ void newton_matrix(LT (&a)[S], const MechDev &m, const Lds &L, const Grp<G> &W,
                                               double yi, double gamma, bool transposed) {
+  static_assert(T == 0 || G == 1, "an inverse tail needs one cell per wave");
   LT *M = reinterpret_cast<LT *>(L.fac);
+  const int lr = W.lane < S ? W.lane : 0;
   wave_lds_sync();
   L.yb[W.lane] = yi;
-  for (int e = W.lane; e < S * S; e += W.kLanes)
-    M[e] = e % (S + 1) == 0 ? static_cast<LT>(1) : static_cast<LT>(0);
-  wave_lds_sync();
-  for (int r = W.lane; r < m.R; r += W.kLanes) {
-    const int2 w = L.rx[r];
-    if constexpr (ABC) {
-      // columns A, B (forward side) and C (reverse side), each scattered
-      // into rows A, C, B: the generic path's terms in its order
-      const int a0 = slot_species(w.x, 0), a1 = slot_species(w.x, 1), b0 = slot_species(w.y, 0);
-      const double kf = L.kk[2 * r];
-      const int col[3] = {a0, a1, b0};
-      const double d[3] = {kf * L.yb[a1], kf * L.yb[a0], L.kk[2 * r + 1]};
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (c == 2 && !m.reversible) break;
-        const LT g = static_cast<LT>(gamma * d[c]);
-        LT *Mc = M + col[c] * S;
-        atomicAdd(Mc + a0, g);
-        atomicAdd(Mc + b0, -g);
-        atomicAdd(Mc + a1, g);
+  for (int pass = 0; pass < (T > 0 ? 2 : 1); ++pass) {
+    // columns c0 .. c0 + nc - 1, column c at (c - c0) * S
+    const int c0 = pass == 0 ? 0 : S - T, nc = T == 0 ? S : (pass == 0 ? S - T : T);
+    if (pass > 0) wave_lds_sync();
+    for (int e = W.lane; e < nc * S; e += W.kLanes)
+      M[e] = e % S == c0 + e / S ? static_cast<LT>(1) : static_cast<LT>(0);
+    wave_lds_sync();
+    for (int r = W.lane; r < m.R; r += W.kLanes) {
+      const int2 w = L.rx[r];
+      if constexpr (ABC) {
+        // columns A, B (forward side) and C (reverse side), each scattered
+        // into rows A, C, B: the generic path's terms in its order
+        const int a0 = slot_species(w.x, 0), a1 = slot_species(w.x, 1), b0 = slot_species(w.y, 0);
+        const double kf = L.kk[2 * r];
+        const int col[3] = {a0, a1, b0};
+        const double d[3] = {kf * L.yb[a1], kf * L.yb[a0], L.kk[2 * r + 1]};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (c == 2 && !m.reversible) break;
+          if constexpr (T > 0) {
+            if (col[c] < c0 || col[c] >= c0 + nc) continue;
+          }
+          const LT g = static_cast<LT>(gamma * d[c]);
+          LT *Mc = M + (col[c] - c0) * S;
+          atomicAdd(Mc + a0, g);
+          atomicAdd(Mc + b0, -g);
+          atomicAdd(Mc + a1, g);
+        }
+        continue;
       }
-      continue;
-    }
-    int sp[2][3];
+      int sp[2][3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      sp[0][k] = slot_species(w.x, k);
-      sp[1][k] = slot_species(w.y, k);
-    }
+      for (int k = 0; k < 3; ++k) {
+        sp[0][k] = slot_species(w.x, k);
+        sp[1][k] = slot_species(w.y, k);
+      }
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      if (side == 1 && !m.reversible) break;
-      const double kside = L.kk[2 * r + side];
+      for (int side = 0; side < 2; ++side) {
+        if (side == 1 && !m.reversible) break;
+        const double kside = L.kk[2 * r + side];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int col = sp[side][c];
-        if (col == kEmptySlot) continue;
-        double d = kside;
+        for (int c = 0; c < 3; ++c) {
+          const int col = sp[side][c];
+          if (col == kEmptySlot) continue;
+          if constexpr (T > 0) {
+            if (col < c0 || col >= c0 + nc) continue;
+          }
+          double d = kside;
 #pragma unroll
-        for (int o = 0; o < 3; ++o)
-          if (o != c) d *= L.yb[sp[side][o]];  // empty slots multiply by 1
-        const LT g = static_cast<LT>(gamma * d);
-        LT *Mc = M + col * S;
+          for (int o = 0; o < 3; ++o)
+            if (o != c) d *= L.yb[sp[side][o]];  // empty slots multiply by 1
+          const LT g = static_cast<LT>(gamma * d);
+          LT *Mc = M + (col - c0) * S;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          if (sp[0][i] != kEmptySlot) atomicAdd(Mc + sp[0][i], g);
-          if (sp[1][i] != kEmptySlot) atomicAdd(Mc + sp[1][i], -g);
+          for (int i = 0; i < 3; ++i) {
+            if (sp[0][i] != kEmptySlot) atomicAdd(Mc + sp[0][i], g);
+            if (sp[1][i] != kEmptySlot) atomicAdd(Mc + sp[1][i], -g);
+          }
         }
       }
     }
-  }
-  wave_lds_sync();
-  const int lr = W.lane < S ? W.lane : 0;
+    wave_lds_sync();
 #pragma unroll
-  for (int j = 0; j < S; ++j) {
-    const LT v = transposed ? M[lr * S + j] : M[j * S + lr];
-    a[j] = W.lane < S ? v : static_cast<LT>(0);
+    for (int j = 0; j < S; ++j) {
+      if (j < c0 || j >= c0 + nc) continue;
+      const LT v = (T == 0 && transposed) ? M[lr * S + j] : M[(j - c0) * S + lr];
+      a[j] = W.lane < S ? v : static_cast<LT>(0);
+    }
   }
   wave_lds_sync();
 }
@@ -1101,18 +1149,23 @@ __device__ __forceinline__ void gj_block(LT (&a)[S], const Grp<G> &W, int k0, in
 // one step in four writes its row to rotated slots.  After S steps slot k
 // holds the inverse column of step k, i.e. column p_k.  M^{-1} is written to
 // LDS in natural order, column-major (entry (r, c) at c*S + r), so that a
-// solve is one lane-parallel matrix-vector product.  Returns 0, or k+1 for the
-// first column k without a nonzero pivot (the elimination then runs on
-// garbage).
-template <int S, typename LT, int G>
-__device__ __forceinline__ int gj_invert(LT (&a)[S], const Grp<G> &W, const Lds &L) {
+// solve is one lane-parallel matrix-vector product.  T > 0: M^{-1} is kept in
+// slot order instead ((r, k) at k*S + r holds M^{-1}(r, p_k)), slots 0 .. S-T-1
+// in LDS and the last T in registers of lane r (moved there from the lane
+// that computed row r by ds_bpermute), so the LDS area is (S - T) S entries.
+// Returns 0, or k+1 for the first column k without a nonzero pivot (the
+// elimination then runs on garbage).
+template <int S, typename LT, int T = 0, int G>
+__device__ __forceinline__ int gj_invert(LT (&a)[S], const Grp<G> &W, const Lds &L,
+                                         InvTail<T, LT> *tail = nullptr) {
+  static_assert(T == 0 || (G == 1 && sizeof(LT) == 8), "an inverse tail: FP64, one cell per wave");
   constexpr int B = 4;
   int piv = W.lane < S ? -1 : 1 << 20;
   int info = 0;
   LT dinv = static_cast<LT>(1);  // 1 / own pivot
   for (int k0 = 0; k0 + B <= S; k0 += B) gj_block<S, B, 0>(a, W, k0, piv, dinv, info);
-  constexpr int T = S % B;
-  if constexpr (T > 0) gj_block<S, T, 0>(a, W, S - T, piv, dinv, info);
+  constexpr int BT = S % B;
+  if constexpr (BT > 0) gj_block<S, BT, 0>(a, W, S - BT, piv, dinv, info);
   // lane i holds row piv(i) of M^{-1} (times its pivot); slot k is column
   // perm[k], the row that was the pivot of step k
   int *perm = L.perm;
@@ -1120,9 +1173,20 @@ __device__ __forceinline__ int gj_invert(LT (&a)[S], const Grp<G> &W, const Lds 
   wave_lds_sync();
   if (W.lane < S) perm[piv] = W.lane;
   wave_lds_sync();
-  if (W.lane < S) {
+  if constexpr (T == 0) {
+    if (W.lane < S) {
 #pragma unroll
-    for (int k = 0; k < S; ++k) inv[perm[k] * S + piv] = a[k] * dinv;
+      for (int k = 0; k < S; ++k) inv[perm[k] * S + piv] = a[k] * dinv;
+    }
+  } else {
+    if (W.lane < S) {
+#pragma unroll
+      for (int k = 0; k < S - T; ++k) inv[k * S + piv] = a[k] * dinv;
+    }
+    // lane r takes row r from the lane whose pivot step put it there
+    const int src = W.lane < S ? perm[W.lane] : W.lane;
+#pragma unroll
+    for (int t = 0; t < T; ++t) tail->v[t] = lane_pull(a[S - T + t] * dinv, src);
   }
   wave_lds_sync();
   return info;
@@ -1130,10 +1194,27 @@ __device__ __forceinline__ int gj_invert(LT (&a)[S], const Grp<G> &W, const Lds 
 
 // x = M^{-1} b with the inverse in LDS; lane i passes b_i and gets x_i.
 // SPLIT: three partial sums (FP32 inverse of isothermal kernels, see below).
-template <int S, typename LT, bool SPLIT, int G>
-__device__ __forceinline__ double inv_solve(const Lds &L, const Grp<G> &W, double b) {
+// T > 0 (gj_invert's slot order with a register tail): the sum runs over the
+// slots k, b_{p_k} gathered to lane k first.
+template <int S, typename LT, bool SPLIT, int T = 0, int G>
+__device__ __forceinline__ double inv_solve(const Lds &L, const Grp<G> &W, double b,
+                                            const InvTail<T, LT> *tail = nullptr) {
   const LT *inv = reinterpret_cast<const LT *>(L.fac);
   LT *bb = reinterpret_cast<LT *>(L.yb);
+  if constexpr (T > 0) {
+    static_assert(!SPLIT && sizeof(LT) == 8, "an inverse tail: FP64, one chain");
+    wave_lds_sync();
+    const double bk = lane_pull(b, W.lane < S ? L.perm[W.lane] : W.lane);
+    if (W.lane < S) bb[W.lane] = bk;
+    wave_lds_sync();
+    const int lr = W.lane < S ? W.lane : 0;
+    LT acc = 0;
+#pragma unroll
+    for (int k = 0; k < S - T; ++k) acc = fma(inv[k * S + lr], bb[k], acc);
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc = fma(tail->v[t], bb[S - T + t], acc);
+    return W.lane < S ? static_cast<double>(acc) : 0.0;
+  }
   wave_lds_sync();
   if (W.lane < S) bb[W.lane] = static_cast<LT>(b);
   wave_lds_sync();
@@ -1375,6 +1456,9 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
   const double Fi = (own && P.F) ? P.F[cell * P.ldy + W.lane] : 0.0;
   const double atol_i = own ? (P.atol_len == 1 ? P.atol[0] : P.atol[W.lane]) : 1.0;
   const bool keep = (P.rec || P.ckpt) && !RES;  // this run records its steps for the adjoint
+  // inverse slots in registers (kept from one setup to the next)
+  constexpr int TL = inv_tail(S, static_cast<int>(sizeof(LT)), TH, LIN, LOCK, G);
+  InvTail<TL, LT> itail;
 
   int status = kSuccess;
   int nst = 0, nfe = 0, nni = 0, nsetups = 0, netf = 0, ncfn = 0, nli = 0, ncfl = 0;
@@ -1415,8 +1499,8 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       // the inverse the run held: the same matrix at the same state and gamma
       const double zs = own ? ck[Ckpt::vec(Ckpt::kVecSetup, S) + W.lane] : 0.0;
       LT a[S];
-      newton_matrix<S, LT, ABC>(a, m, L, W, zs, uni(ck[Ckpt::kGammaBar]), false);
-      gj_invert<S, LT>(a, W, L);
+      newton_matrix<S, LT, ABC, TL>(a, m, L, W, zs, uni(ck[Ckpt::kGammaBar]), false);
+      gj_invert<S, LT, TL>(a, W, L, &itail);
     }
   } else {
     const double yin = own ? P.y[cell * P.ldy + W.lane] : 0.0;
@@ -1585,9 +1669,9 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
             } else if constexpr (TH) {
               newton_matrix_thermal<S, LT>(a, m, L, W, z[0], Fi, gamma, ns);
             } else {
-              newton_matrix<S, LT, ABC>(a, m, L, W, z[0], gamma, false);
+              newton_matrix<S, LT, ABC, TL>(a, m, L, W, z[0], gamma, false);
             }
-            info = gj_invert<S, LT>(a, W, L);
+            info = gj_invert<S, LT, TL>(a, W, L, &itail);
           }
           if (!RES && P.ckpt && own) P.ckpt_setup[cell * P.ckpt_vs + W.lane] = z[0];
           nsetups++;
@@ -1642,7 +1726,7 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
           if (lret != 0) ncfl++;
           if (lret == 2 || (lret == 1 && mit > 0)) break;
         } else {
-          delta = inv_solve<S, LT, sizeof(LT) == 4 && !TH>(L, W, -Gi);
+          delta = inv_solve<S, LT, sizeof(LT) == 4 && !TH, TL>(L, W, -Gi, &itail);
           if (cfac != 1.0) delta *= cfac;
         }
         e += delta;

@@ -176,6 +176,7 @@ struct bdfx_ctx_s {
   int pair_a = 0, pair_b = 1;    // bin indices of the larger and the smaller mechanism
   int pair_waves = 1;            // A-waves per block (the rest of the block's waves are B-waves)
   int32_t pair_lds_b = 0;        // LDS doubles of a bin-B wave (tables in LDS)
+  bool pair_off = false;         // bdfx_autotune timed the one launch slower than two
   bdfx::LaunchCfg pair_cfg{};
   double last_t0 = 0.0, last_tout = 0.0;
 };
@@ -488,7 +489,8 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
   ctx->off_recy0 = reserve(cap ? static_cast<size_t>(n_cells) * ctx->rec_stride * 8 : 0);
   ctx->off_pbar = reserve(cap ? static_cast<size_t>(n_cells) * R_max * 8 : 0);
   ctx->tune_cells = std::min<int64_t>(n_cells, kTuneCells);
-  ctx->off_tune = reserve(static_cast<size_t>(ctx->tune_cells) * S_max * 8);
+  // (two bins' samples at once: the autotuner times the one-launch form too)
+  ctx->off_tune = reserve(static_cast<size_t>(2) * ctx->tune_cells * S_max * 8);
   // persistent grids may keep each wave's rate constants in global memory
   ctx->kk_slots = o->scheduler != BDFX_SCHED_STATIC
                       ? std::min<int64_t>(static_cast<int64_t>(ctx->n_cu) * kMaxWavesPerCu, n_cells + 16)
@@ -504,6 +506,13 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
 }
 
 static int configure_bins(bdfx_ctx ctx);
+
+// linear solver of the context's integrator kernels (bdfx::kLin*)
+static int lin_of(bdfx_ctx ctx) {
+  return ctx->opt.gmres_maxl > 0 ? bdfx::kLinGmres
+         : ctx->opt.jacobian == BDFX_JAC_DQ ? bdfx::kLinDq
+                                            : bdfx::kLinAnalytic;
+}
 
 // kernel selection flags of a mechanism under the context's options
 static int kernel_flags(bdfx_ctx ctx, bdfx_mech m) {
@@ -544,6 +553,7 @@ int bdfx_bind(bdfx_ctx ctx, void *d_ws, size_t ws_bytes, double *d_y, int32_t ld
   ctx->status = d_status;
   ctx->stats = d_stats;
   ctx->bins.clear();
+  ctx->pair_off = false;
   const int nm = static_cast<int>(ctx->mechs.size());
   if (nm == 1) {
     ctx->bins.push_back({0, 0, ctx->N});
@@ -612,10 +622,11 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
   int occ[3] = {0, 0, 0};
   size_t lds[3];
   int64_t grid[3] = {0, 0, 0};
+  const int tail = bdfx::inv_tail(b.se->S, fp32 ? 4 : 8, m->thermal, lin_of(ctx), lock > 0, cpw);
   for (int k : {bdfx::kTabLds, bdfx::kTabRxGlobal, bdfx::kTabGlobal}) {
     const int32_t d = static_cast<int32_t>(
         align_up(bdfx::lds_doubles(b.se->S, m->R, fp32 ? 4 : 8, k, m->thermal,
-                                   ctx->opt.gmres_maxl),
+                                   ctx->opt.gmres_maxl, tail),
                  2));
     lds[k] = static_cast<size_t>(waves) * cpw * d * 8 + lock_bytes;
     if (lds[k] > 65536 || (k != bdfx::kTabLds && cpw != 1) || (k == bdfx::kTabGlobal && !queue) ||
@@ -649,10 +660,11 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
 // The one launch of a two-mechanism batch (BDFX_SCHED_FUSED): the bins of the
 // larger and the smaller mechanism become bins A and B of k_integrate_pair,
 // with bin A's register budget and table placement.  A block holds wa A-waves
-// and wb B-waves (wa + wb <= 4, LDS within the device's per-block limit); the
-// shape chosen keeps as many A-waves per CU as bin A's own launch has and,
-// among those, adds the most B-waves, which then run in the register and LDS
-// room A leaves.  The grid holds as many blocks as fit the GPU.  Used when
+// and wb B-waves (wa + wb <= 4, wb >= 0, LDS within the device's per-block
+// limit); the shape chosen keeps as many A-waves per CU as bin A's own launch
+// has and, among those, adds the most B-waves, which then run in the register
+// and LDS room A leaves (with none left, the A-waves take the B cells after
+// their own, in one launch).  The grid holds as many blocks as fit the GPU.  Used when
 // both mechanisms are isothermal A + B <=> C mechanisms on the direct solver
 // with the analytic Jacobian, their padded sizes form a compiled pair, an A
 // area holds a B cell and some shape keeps A's resident waves; otherwise
@@ -660,7 +672,8 @@ static int configure_bin(bdfx_ctx ctx, Bin &b) {
 // cell per wave in either case).
 static int configure_pair(bdfx_ctx ctx) {
   ctx->pair = nullptr;
-  if (ctx->opt.scheduler != BDFX_SCHED_FUSED || ctx->bins.size() != 2) return BDFX_OK;
+  if (ctx->opt.scheduler != BDFX_SCHED_FUSED || ctx->bins.size() != 2 || ctx->pair_off)
+    return BDFX_OK;
   if (ctx->opt.jacobian != BDFX_JAC_ANALYTIC || ctx->opt.gmres_maxl > 0 || ctx->opt.lockstep > 0)
     return BDFX_OK;
   int ia = 0, ib = 1;
@@ -673,8 +686,10 @@ static int configure_pair(bdfx_ctx ctx) {
   const PairEntry *pe = pair_for(a.se->S, b.se->S);
   if (!pe) return BDFX_OK;
   const bool fp32 = ctx->opt.lu_precision == 32;
-  const int32_t lds_b = static_cast<int32_t>(
-      align_up(bdfx::lds_doubles(b.se->S, mb->R, fp32 ? 4 : 8, bdfx::kTabLds), 2));
+  const int32_t lds_b = static_cast<int32_t>(align_up(
+      bdfx::lds_doubles(b.se->S, mb->R, fp32 ? 4 : 8, bdfx::kTabLds, false, 0,
+                        bdfx::inv_tail(b.se->S, fp32 ? 4 : 8, false, bdfx::kLinAnalytic, false, 1)),
+      2));
   if (a.lds_doubles < lds_b) return BDFX_OK;
   // A-waves per CU in bin A's own launch
   int occ_a = 0;
@@ -682,8 +697,10 @@ static int configure_pair(bdfx_ctx ctx) {
                               a.cfg.block, a.cfg.lds_bytes, &occ_a));
   const int a_per_cu = occ_a * std::max(a.waves_per_block, 1);
   int best_a = 0, best_b = 0, best_wa = 0, best_wb = 0, best_occ = 0;
-  for (int wa = 1; wa <= 3; ++wa)
-    for (int wb = 1; wa + wb <= 4; ++wb) {
+  // (wb = 0: blocks of larger-mechanism waves only, which take the smaller
+  // mechanism's cells once their own are done)
+  for (int wa = 1; wa <= 4; ++wa)
+    for (int wb = 0; wa + wb <= 4; ++wb) {
       const size_t lds = (static_cast<size_t>(wa) * a.lds_doubles + wb * lds_b) * 8;
       if (lds > static_cast<size_t>(ctx->lds_max_block)) continue;
       int occ = 0;
@@ -864,6 +881,67 @@ static bdfx_tuning tuning_of(bdfx_ctx ctx, const Bin &b) {
   return t;
 }
 
+}  // extern "C"
+
+// Times, on the first ns cells of both bins (rows saved and restored around
+// each run, first run a warm-up), the two bins' own launches one after the
+// other and the one-launch form (ctx->pair set); both in ms.
+static hipError_t time_pair(bdfx_ctx ctx, double t0, double t_out, int64_t ns, hipEvent_t e0,
+                            hipEvent_t e1, float *t_seq, float *t_pair) {
+  const bool fp32 = ctx->opt.lu_precision == 32;
+  const Bin *bin[2] = {&ctx->bins[ctx->pair_a], &ctx->bins[ctx->pair_b]};
+  Bin tb[2];
+  bdfx::Params P[2];
+  double *save[2];
+  for (int k = 0; k < 2; ++k) {
+    tb[k] = *bin[k];
+    tb[k].count = std::min(ns, bin[k]->count);
+    P[k] = make_params(ctx, tb[k], t0, t_out);
+    P[k].use_queue = 1;
+    P[k].lds_doubles = bin[k]->lds_doubles;
+    P[k].chunk = bin[k]->queue_chunk;
+    save[k] = reinterpret_cast<double *>(ctx->ws + ctx->off_tune) +
+              static_cast<int64_t>(k) * ctx->tune_cells * ctx->S_max;
+  }
+  uint32_t *qctr = reinterpret_cast<uint32_t *>(ctx->ws + ctx->off_queue);
+  hipError_t e = hipSuccess;
+  for (int form = 0; form < 2 && e == hipSuccess; ++form) {
+    float total = 0.0f;
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+      for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        e = bdfx_launch_copy_rows(ctx->y, ctx->ldy, P[k].list, tb[k].count,
+                                  ctx->mechs[tb[k].mech]->n, save[k], false, ctx->stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+      if (e == hipSuccess) e = bdfx_launch_fill_u32(qctr, 64, 0u, ctx->stream);
+      if (form == 0) {
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+          const bdfx_mech m = ctx->mechs[tb[k].mech];
+          e = tb[k].se->launch(P[k], fp32, tb[k].waves_per_simd, tb[k].tab, 1, kernel_flags(ctx, m),
+                               tb[k].cfg, ctx->stream);
+        }
+      } else if (e == hipSuccess) {
+        bdfx::Params PA = P[0], PB = P[1];
+        PB.lds_doubles = ctx->pair_lds_b;
+        PA.pair_waves = PB.pair_waves = ctx->pair_waves;
+        e = ctx->pair->launch(PA, PB, fp32, tb[0].waves_per_simd, tb[0].tab, ctx->pair_cfg,
+                              ctx->stream);
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+      for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        e = bdfx_launch_copy_rows(ctx->y, ctx->ldy, P[k].list, tb[k].count,
+                                  ctx->mechs[tb[k].mech]->n, save[k], true, ctx->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) total += ms;
+    }
+    (form == 0 ? *t_seq : *t_pair) = total / 2.0f;
+  }
+  return e;
+}
+
+extern "C" {
+
 int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, bdfx_tuning *out) {
   if (!ctx) return BDFX_EINVAL;
   if (!ctx->bound) return fail(ctx, BDFX_EORDER, "bdfx_bind must precede bdfx_autotune");
@@ -951,9 +1029,21 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
     b.tune_ms = best / 2.0f;
     rc = configure_bin(ctx, b);
   }
+  ctx->pair_off = false;
+  if (rc == BDFX_OK) rc = configure_pair(ctx);
+  if (rc == BDFX_OK && ctx->pair) {
+    // the one launch against the two bins' own launches, on both samples
+    float t_seq = 0.0f, t_pair = 0.0f;
+    const hipError_t e = time_pair(ctx, t0, t_out, ns, e0, e1, &t_seq, &t_pair);
+    if (e != hipSuccess) {
+      rc = fail(ctx, BDFX_EHIP, "autotune pair trial: %s", hipGetErrorString(e));
+    } else if (t_pair > t_seq) {
+      ctx->pair_off = true;
+      ctx->pair = nullptr;
+    }
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  if (rc == BDFX_OK) rc = configure_pair(ctx);
   for (size_t bi = 0; bi < ctx->bins.size() && out && rc == BDFX_OK; ++bi)
     out[bi] = tuning_of(ctx, ctx->bins[bi]);
   if (rc == BDFX_OK) {
@@ -1169,7 +1259,10 @@ int bdfx_adjoint(bdfx_ctx ctx, const double *d_ybar, double *d_y0bar, double *d_
       P.seg_rows = K + bdfx::kQmax + 1;
       P.adj = reinterpret_cast<double *>(ctx->ws + ctx->off_adj);
       bdfx::Params PR = P;
-      PR.lds_doubles = static_cast<int32_t>(align_up(bdfx::lds_doubles(se->S, m->R, 8), 2));
+      PR.lds_doubles = static_cast<int32_t>(align_up(
+          bdfx::lds_doubles(se->S, m->R, 8, bdfx::kTabLds, false, 0,
+                            bdfx::inv_tail(se->S, 8, false, bdfx::kLinAnalytic, false, 1)),
+          2));
       bdfx::LaunchCfg cr = cfg;
       cr.lds_bytes = static_cast<size_t>(PR.lds_doubles) * 8;
       for (int j = 0; j < ctx->ckpt_cap; ++j) {
