@@ -126,8 +126,10 @@ typedef struct {
   int32_t blocks_per_cu;   /* persistent grid: resident blocks per CU (0 = auto) */
   int32_t queue_chunk;     /* cells per work-queue pop (0 = 1) */
   int32_t waves_per_simd;  /* register budget of the integrator kernel: 0 = compiler's
-                              choice, 3 or 4 = code built for that many resident waves
-                              per SIMD (at most 168 / 128 VGPRs, spilling if needed) */
+                              choice, 3, 4 or 5 = code built for that many resident waves
+                              per SIMD (at most 168 / 128 / 96 VGPRs, spilling if needed;
+                              the one-launch pair of BDFX_SCHED_FUSED has no 5-wave code
+                              and then runs as two launches) */
   int32_t cells_per_wave;  /* 0 or 1; 2 = each half-wave integrates its own cell
                               (mechanisms of at most 32 species) */
   int32_t jacobian;        /* BDFX_JAC_ANALYTIC (0) or BDFX_JAC_DQ (1): Newton matrix from
@@ -381,7 +383,7 @@ int bdfx_get_record_layout(bdfx_ctx ctx, bdfx_record_layout *out);
 /* Launch shape of the integrator for the cells of one mechanism. */
 typedef struct {
   int32_t mech;            /* mechanism index (as in d_cell_mech) */
-  int32_t waves_per_simd;  /* 0, 3 or 4, as bdfx_options.waves_per_simd */
+  int32_t waves_per_simd;  /* 0, 3, 4 or 5, as bdfx_options.waves_per_simd */
   int32_t waves_per_block; /* 1..16 */
   int32_t queue_chunk;     /* cells per work-queue pop, >= 1 */
   int64_t sample_cells;    /* bdfx_autotune(): cells timed */
@@ -400,7 +402,7 @@ typedef struct {
 
 /* Autotuner: for every mechanism, times each candidate launch shape
  * (cells_per_wave in {1, 2} (2 only up to 32 species) x waves_per_simd in
- * {0, 3, 4} x waves_per_block in {1, 2, 4} x queue_chunk in {1, 4} for the
+ * {0, 3, 4, 5} x waves_per_block in {1, 2, 4} x queue_chunk in {1, 4} for the
  * queue scheduler) integrating the first min(sample_cells,
  * 16384) cells of that mechanism over [t0, t_out] with HIP events, and keeps
  * the fastest; sample_cells <= 0 means 16384.  The sampled states are saved

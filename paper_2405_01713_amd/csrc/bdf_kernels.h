@@ -12,8 +12,8 @@
 namespace bdfx {
 
 // MINW: minimum resident waves per SIMD the register allocation must allow
-// (1 = compiler's choice; 3 = at most 168 VGPRs, 4 = at most 128, spilling
-// if needed).  TAB: placement of the reaction tables (kTab*).  G: cells per
+// (1 = compiler's choice; 3 = at most 168 VGPRs, 4 = at most 128, 5 = at
+// most 96, spilling if needed).  TAB: placement of the reaction tables (kTab*).  G: cells per
 // wave (2: each half-wave integrates its own cell, S <= 32); each group has
 // its own LDS area of P.lds_doubles and pops its own cells.  With the tables
 // in global memory, wave w of the grid owns rate-constant slot w (the host
@@ -142,6 +142,7 @@ __global__ void __launch_bounds__(256, MINW) k_integrate_pair(Params PA, Params 
 template <int SA, int SB>
 const void *pair_kernel(bool fp32, int minw, int taba) {
   using F = const void *;
+  if (minw >= 5) return nullptr;  // built for the budgets 0, 3 and 4
   const int w = minw >= 4 ? 2 : minw >= 3 ? 1 : 0;
   static const F t64[3][3] = {
       {F(&k_integrate_pair<SA, SB, double, 1, kTabRxGlobal>), F(&k_integrate_pair<SA, SB, double, 1, kTabLds>),
@@ -229,9 +230,10 @@ const void *lock_kernel(bool fp32, bool abc) {
 template <int S, typename LT, int TAB, int G, bool ABC, bool TH = false, int LIN = kLinAnalytic>
 const void *by_budget(int w) {
   using F = const void *;
-  static const F t[3] = {F(&k_integrate<S, LT, 1, TAB, G, ABC, TH, LIN>),
+  static const F t[4] = {F(&k_integrate<S, LT, 1, TAB, G, ABC, TH, LIN>),
                          F(&k_integrate<S, LT, 3, TAB, G, ABC, TH, LIN>),
-                         F(&k_integrate<S, LT, 4, TAB, G, ABC, TH, LIN>)};
+                         F(&k_integrate<S, LT, 4, TAB, G, ABC, TH, LIN>),
+                         F(&k_integrate<S, LT, 5, TAB, G, ABC, TH, LIN>)};
   return t[w];
 }
 
@@ -286,7 +288,7 @@ const void *integrate_kernel_abc(bool fp32, int w, int tab, int cells_per_wave) 
 template <int S>
 const void *integrate_kernel(bool fp32, int minw, int tab, int cells_per_wave, bool abc,
                              bool thermal, int lin, bool lock = false) {
-  const int w = minw >= 4 ? 2 : minw >= 3 ? 1 : 0;
+  const int w = minw >= 5 ? 3 : minw >= 4 ? 2 : minw >= 3 ? 1 : 0;
   if (lock) {
     if (tab != kTabLds || cells_per_wave != 1 || thermal || lin != kLinAnalytic) return nullptr;
     return lock_kernel<S>(fp32, abc);

@@ -391,8 +391,8 @@ int bdfx_plan(bdfx_ctx ctx, int64_t n_cells, int32_t n_mech, const bdfx_mech *me
   if (o->scheduler != BDFX_SCHED_STATIC && o->scheduler != BDFX_SCHED_QUEUE &&
       o->scheduler != BDFX_SCHED_FUSED)
     return fail(ctx, BDFX_EINVAL, "unknown scheduler %d", o->scheduler);
-  if (o->waves_per_simd != 0 && o->waves_per_simd != 3 && o->waves_per_simd != 4)
-    return fail(ctx, BDFX_EINVAL, "waves_per_simd must be 0, 3 or 4");
+  if (o->waves_per_simd != 0 && (o->waves_per_simd < 3 || o->waves_per_simd > 5))
+    return fail(ctx, BDFX_EINVAL, "waves_per_simd must be 0, 3, 4 or 5");
   if (o->waves_per_block < 0 || o->waves_per_block > 16 || o->blocks_per_cu < 0 ||
       o->queue_chunk < 0 || o->cells_per_wave < 0 || o->cells_per_wave > 2)
     return fail(ctx, BDFX_EINVAL, "invalid launch shape");
@@ -965,7 +965,7 @@ int bdfx_autotune(bdfx_ctx ctx, double t0, double t_out, int64_t sample_cells, b
     return fail(ctx, BDFX_EHIP, "hipEventCreate failed");
   }
   int rc = BDFX_OK;
-  const int wps_c[] = {0, 3, 4}, wpb_c[] = {1, 2, 4}, chunk_c[] = {1, 4}, cpw_c[] = {1, 2};
+  const int wps_c[] = {0, 3, 4, 5}, wpb_c[] = {1, 2, 4}, chunk_c[] = {1, 4}, cpw_c[] = {1, 2};
   for (size_t bi = 0; bi < ctx->bins.size() && rc == BDFX_OK; ++bi) {
     Bin &b = ctx->bins[bi];
     if (b.count == 0) continue;
@@ -1057,8 +1057,8 @@ int bdfx_set_tuning(bdfx_ctx ctx, const bdfx_tuning *t, int32_t n) {
   if (!ctx || (n > 0 && !t)) return BDFX_EINVAL;
   if (!ctx->bound) return fail(ctx, BDFX_EORDER, "bdfx_bind must precede bdfx_set_tuning");
   for (int32_t k = 0; k < n; ++k) {
-    if (t[k].waves_per_simd != 0 && t[k].waves_per_simd != 3 && t[k].waves_per_simd != 4)
-      return fail(ctx, BDFX_EINVAL, "waves_per_simd must be 0, 3 or 4");
+    if (t[k].waves_per_simd != 0 && (t[k].waves_per_simd < 3 || t[k].waves_per_simd > 5))
+      return fail(ctx, BDFX_EINVAL, "waves_per_simd must be 0, 3, 4 or 5");
     if (t[k].waves_per_block < 1 || t[k].waves_per_block > 16 || t[k].queue_chunk < 1 ||
         (t[k].cells_per_wave != 1 && t[k].cells_per_wave != 2))
       return fail(ctx, BDFX_EINVAL, "invalid launch shape");
