@@ -77,6 +77,19 @@ def test_s53_fp32_lu_parity(oracle, parity):
     parity(y, yo, w)
 
 
+@pytest.mark.parametrize("wl", ["s21_r84_262k", "s53_r325_262k_fp32lu"])
+def test_register_budgets_bit_identical(oracle, parity, wl):
+    """The register budgets (compiler's choice, 3, 4 and 5 waves per SIMD)
+    build the same arithmetic with different register allocations (and
+    spills): results agree bit for bit, and with the oracle."""
+    w = W.make_workload(wl, 250)
+    out = [_gpu(w, scheduler=1, waves_per_simd=wps) for wps in (0, 3, 4, 5)]
+    for y, st in out[1:]:
+        assert np.array_equal(y, out[0][0]) and np.array_equal(st, out[0][1])
+    yo, _ = _oracle(oracle, w)
+    parity(out[0][0], yo, w, f"{wl} budgets")
+
+
 @pytest.mark.parametrize("lu,wps", [(64, 0), (32, 3)])
 def test_tables_in_global_memory(oracle, parity, lu, wps):
     """53 species under the work queue: LDS limits the resident waves, so the
