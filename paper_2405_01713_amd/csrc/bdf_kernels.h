@@ -13,9 +13,10 @@ namespace bdfx {
 
 // MINW: minimum resident waves per SIMD the register allocation must allow
 // (1 = compiler's choice; 3 = at most 168 VGPRs, 4 = at most 128, 5 = at
-// most 96, spilling if needed).  TAB: placement of the reaction tables (kTab*).  G: cells per
-// wave (2: each half-wave integrates its own cell, S <= 32); each group has
-// its own LDS area of P.lds_doubles and pops its own cells.  With the tables
+// most 96, spilling if needed).  TAB: placement of the reaction tables
+// (kTab*).  G: cells per wave (2: each half-wave integrates its own cell,
+// S <= 32); each group has its own LDS area of P.lds_doubles and pops its
+// own cells.  With the tables
 // in global memory, wave w of the grid owns rate-constant slot w (the host
 // guarantees that the grid's waves fit the slot array).  ABC: every reaction
 // is A + B <=> C (see rhs_reaction).  TH: non-isothermal cells (temperature
@@ -177,8 +178,8 @@ __global__ void __launch_bounds__(256) k_adjoint(Params P) {
 }
 
 // Pass j of the sweep over checkpointed records, as two launches: k_adj_rerun
-// reruns the pass's segment of every cell (the forward step code, at a
-// forward run's register budget), k_adj_sweep sweeps it (at the sweep's).  One
+// reruns the pass's segment of every cell (the forward step code, with the
+// registers of that code alone), k_adj_sweep sweeps it (with the sweep's).  One
 // wave per cell of the list; a cell without a segment in this pass returns at
 // once.  (A persistent loop over cells costs these kernels 20-35 % more
 // registers.)  ABC as in k_integrate.
@@ -335,7 +336,6 @@ hipError_t launch_adjoint(const Params &P, int kind, int pass, bool abc, const L
   return hipLaunchKernel(adjoint_kernel<S>(kind, abc), dim3(c.grid), dim3(c.block), args,
                          c.lds_bytes, s);
 }
-
 
 template <int S>
 hipError_t occupancy_integrate(bool fp32, int minw, int tab, int cells_per_wave, bool abc,
