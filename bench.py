@@ -324,7 +324,7 @@ def run_c1(steps, warmup, tuning_cache=None, n_check=256):
     return out
 
 
-def run_adjoint(steps, warmup, n_cells=None, record_steps=2048, n_check=32, ckpt_every=64):
+def run_adjoint(steps, warmup, n_cells=None, record_steps=2048, n_check=32, ckpt_every=128):
     """Adjoint/forward cost on the 65,536-cell 21-species workload: plain
     forward (no recording), forward with step recording, discrete-adjoint
     backward of the loss sum_cells sum_i c_i y_i; a sample of cells is checked
