@@ -478,7 +478,8 @@ def run_precision(steps, warmup, tuning_cache=None, n_cells=None, n_check=256):
     from paper_2405_01713_amd import bdfx
 
     w = W.make_workload("s53_r325_262k_fp32lu", n_cells)
-    out = dict(workload="s53_r325_262k_fp32lu", n_cells=w["n_cells"])
+    label = "s53_r325_1m" if w["n_cells"] == 1 << 20 else "s53_r325_262k_fp32lu"
+    out = dict(workload=label, n_cells=w["n_cells"])
     ys = {}
     for lu in (64, 32):
         integ = bdfx.Integrator(w["mechs"], w["y0"], w["rtol"], w["atol"], T=w["T"], scheduler=1,
@@ -495,9 +496,13 @@ def run_precision(steps, warmup, tuning_cache=None, n_cells=None, n_check=256):
         ys[lu] = integ.state()[:n_check]
         integ.close()
         log(f"precision lu{lu}: {ms:.1f} ms")
+        F64, F32 = launch_flops(w, st, lu == 32)
         out[f"lu{lu}"] = dict(kernel_ms=ms, cells_per_s=w["n_cells"] / (ms * 1e-3), tuning=tune,
                               failed_cells=int(np.sum(st["status"] != 0)),
-                              mean_nst=float(st["nst"].mean()))
+                              mean_nst=float(st["nst"].mean()),
+                              mean_nsetups=float(st["nsetups"].mean()),
+                              alg_flops_fp64=F64, alg_flops_fp32=F32,
+                              roofline_frac=roofline_frac(F64, F32, ms * 1e-3))
     out["speedup_fp32lu_over_fp64"] = out["lu64"]["kernel_ms"] / out["lu32"]["kernel_ms"]
     try:
         from oracle import oracle as O

@@ -1097,23 +1097,32 @@ __device__ __forceinline__ void gj_step(LT (&a)[S], const Grp<G> &W, int k, int 
     zero_pivot = kmax <= 1u;
   } else {
     // exact 64-bit maximum in two 32-bit passes: high words, then the low
-    // words of the lanes that tie on the high word
+    // words of the lanes that tie on the high word.  With one cell per wave
+    // a high word held by one lane only decides alone (the low-word pass
+    // would return that lane, and its key is not zero); ties, the all-zero
+    // column among them, take the second pass.
     const uint64_t key = piv < 0 ? abs_key(a[E]) : 0ull;
     const uint32_t hi = static_cast<uint32_t>(key >> 32), lo = static_cast<uint32_t>(key);
     const uint32_t hmax = W.template max_u32<(S + 15) / 16>(hi);
-    const uint32_t lmax = W.template max_u32<(S + 15) / 16>(hi == hmax ? lo : 0u);
-    p = W.first(hi == hmax && lo == lmax);
-    zero_pivot = hmax == 0u && lmax <= 1u;
+    uint64_t tie = 0;
+    if constexpr (G == 1) tie = __ballot(hi == hmax);
+    if (G == 1 && __builtin_popcountll(tie) == 1) {
+      p = __builtin_ctzll(tie);
+      zero_pivot = false;
+    } else {
+      const uint32_t lmax = W.template max_u32<(S + 15) / 16>(hi == hmax ? lo : 0u);
+      p = W.first(hi == hmax && lo == lmax);
+      zero_pivot = hmax == 0u && lmax <= 1u;
+    }
   }
   if (zero_pivot && info == 0) info = k + 1;
   const bool is_p = W.lane == p;
   const LT pk = W.bcast(a[E], p);
   const LT rp = rcp(pk);
   const LT ng = is_p ? static_cast<LT>(0) : -(a[E] * rp);
-  if (is_p) {
-    piv = k;
-    dinv = rp;
-  }
+  // selects, not a branch: a block of steps stays one basic block
+  piv = is_p ? k : piv;
+  dinv = is_p ? rp : dinv;
   const LT col = is_p ? static_cast<LT>(1) : ng;  // new column of the inverse
   if constexpr (SH == 0) {
     gj_update<S, E, 0>(a, W, p, ng);
