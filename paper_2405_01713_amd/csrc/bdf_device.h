@@ -1098,15 +1098,18 @@ __device__ __forceinline__ void gj_step(LT (&a)[S], const Grp<G> &W, int k, int 
   } else {
     // exact 64-bit maximum in two 32-bit passes: high words, then the low
     // words of the lanes that tie on the high word.  With one cell per wave
-    // a high word held by one lane only decides alone (the low-word pass
-    // would return that lane, and its key is not zero); ties, the all-zero
-    // column among them, take the second pass.
+    // and S > 16, a high word held by one lane only decides alone (the
+    // low-word pass would return that lane, and its key is not zero); ties,
+    // the all-zero column among them, take the second pass.  (The smallest
+    // kernels, whose elimination is a minor cost, stay without the extra
+    // branch: it costs them spilled registers.)
+    constexpr bool kShortcut = G == 1 && S > 16;
     const uint64_t key = piv < 0 ? abs_key(a[E]) : 0ull;
     const uint32_t hi = static_cast<uint32_t>(key >> 32), lo = static_cast<uint32_t>(key);
     const uint32_t hmax = W.template max_u32<(S + 15) / 16>(hi);
     uint64_t tie = 0;
-    if constexpr (G == 1) tie = __ballot(hi == hmax);
-    if (G == 1 && __builtin_popcountll(tie) == 1) {
+    if constexpr (kShortcut) tie = __ballot(hi == hmax);
+    if (kShortcut && __builtin_popcountll(tie) == 1) {
       p = __builtin_ctzll(tie);
       zero_pivot = false;
     } else {
@@ -1120,9 +1123,14 @@ __device__ __forceinline__ void gj_step(LT (&a)[S], const Grp<G> &W, int k, int 
   const LT pk = W.bcast(a[E], p);
   const LT rp = rcp(pk);
   const LT ng = is_p ? static_cast<LT>(0) : -(a[E] * rp);
-  // selects, not a branch: a block of steps stays one basic block
-  piv = is_p ? k : piv;
-  dinv = is_p ? rp : dinv;
+  if constexpr (S > 16) {
+    // selects, not a branch: a block of steps stays one basic block
+    piv = is_p ? k : piv;
+    dinv = is_p ? rp : dinv;
+  } else if (is_p) {
+    piv = k;
+    dinv = rp;
+  }
   const LT col = is_p ? static_cast<LT>(1) : ng;  // new column of the inverse
   if constexpr (SH == 0) {
     gj_update<S, E, 0>(a, W, p, ng);
