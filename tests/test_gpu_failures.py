@@ -134,6 +134,35 @@ def test_singular_newton_matrix(oracle, lu):
     assert np.all(sto["status"] == -6) and np.all(sto["nsetups"] == 2) and np.all(yo == 0.0)
 
 
+
+@pytest.mark.parametrize("lu", [64, 32])
+def test_singular_newton_matrix_in_a_large_kernel(oracle, lu):
+    """The same two autocatalytic reactions among 19 species (17 of them
+    inert: unit rows of the Newton matrix), so the cells run the 21-species
+    kernels, whose FP64 pivot search takes its second (low-word) pass only
+    when the largest high word is tied: an all-zero column ties every lane
+    and must still be found singular.  Every cell fails with -6 before any
+    step, as in the oracle, with its state untouched."""
+    sing = _autocatalytic()
+    S = 19
+    m = dict(sing, n_species=S, w=np.ones(S))
+    n = 64
+    rng = np.random.default_rng(5)
+    y0 = np.zeros((n, S))
+    y0[:, 2:] = rng.uniform(0.1, 1.0, size=(n, S - 2))
+    ks = np.ones((n, 2))
+    ks[:, 0], ks[:, 1] = 2.0 ** 20, 2.0 ** 22
+    T = np.ones(n)
+    t_out = 10.0 * 2.0 ** -20
+    w = dict(mechs=[m], y0=y0, T=T, kscale=ks, rtol=1e-6, atol=1e-10, t_out=t_out)
+    y, st = _gpu(w, lu_precision=lu)
+    assert np.all(st["status"] == -6) and np.all(st["nst"] == 0)
+    assert np.all(st["nsetups"] == 2) and np.all(st["t_reached"] == 0.0)
+    assert np.array_equal(y[:, :S], y0)
+    yo, sto = oracle.integrate([m], y0[:8], 0.0, t_out, 1e-6, 1e-10, T=T[:8], kscale=ks[:8])
+    assert np.all(sto["status"] == -6) and np.all(sto["nsetups"] == 2)
+    assert np.array_equal(yo, y0[:8])
+
 def test_record_capacity(oracle):
     """A cell that needs more accepted steps than the record holds fails with
     -10 at its last recorded step: the returned state is the record's last
