@@ -1161,9 +1161,10 @@ __device__ __forceinline__ void gj_block(LT (&a)[S], const Grp<G> &W, int k0, in
 
 // Inverts the cell's S x S Newton matrix M (row i in lane i's registers) by
 // Gauss-Jordan elimination with partial pivoting (gj_step), in blocks of four
-// steps whose slot indices are static, so the block loop need not be unrolled
-// (at S = 53 the unrolled form would not fit the instruction cache) and only
-// one step in four writes its row to rotated slots.  After S steps slot k
+// (eight above 32 species) steps whose slot indices are static, so the block
+// loop need not be unrolled (at S = 53 the unrolled form would not fit the
+// instruction cache) and only the last step of a block writes its row to
+// rotated slots.  After S steps slot k
 // holds the inverse column of step k, i.e. column p_k.  M^{-1} is written to
 // LDS in natural order, column-major (entry (r, c) at c*S + r), so that a
 // solve is one lane-parallel matrix-vector product.  T > 0: M^{-1} is kept in
@@ -1176,7 +1177,11 @@ template <int S, typename LT, int T = 0, int G>
 __device__ __forceinline__ int gj_invert(LT (&a)[S], const Grp<G> &W, const Lds &L,
                                          InvTail<T, LT> *tail = nullptr) {
   static_assert(T == 0 || (G == 1 && sizeof(LT) == 8), "an inverse tail: FP64, one cell per wave");
-  constexpr int B = 4;
+  // steps per block (one register rotation per block): eight above 32
+  // species, where the rotation's S moves are a larger share; sixteen
+  // steps made the 53-species FP64 kernels' loop too large for the
+  // instruction cache (27 % slower), eight at 21 species gained nothing
+  constexpr int B = S > 32 ? 8 : 4;
   int piv = W.lane < S ? -1 : 1 << 20;
   int info = 0;
   LT dinv = static_cast<LT>(1);  // 1 / own pivot
