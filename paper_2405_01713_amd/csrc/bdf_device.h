@@ -1851,30 +1851,44 @@ __device__ __forceinline__ void integrate_cell(const Params &P, int64_t cell, co
       } else {
         // without an order decision this step, h changes only if eta >= 1.5
         double eta = 0.0;
-        if (qwait == 0 || 36.0 * dsm2 <= hold_bound(q + 1)) eta = W.uni(eta_from2(6.0, dsm2, q + 1));
         int qnew = q;
         if (qwait == 0) {
           qwait = 2;
-          if (q > 1) {
-            const double lte =
-                factorial(q - 1) / harmonic(q - 1);
-            const double lte2 = lte * lte * norm2(nd_get(z, q), ewt);
-            const double eta_qm1 = W.uni(eta_from2(6.0, lte2, q));
+          const bool lower = q > 1, higher = q < qmax && have_eprev;
+          double lte2m = 0.0, lte2p = 0.0;
+          if (lower) {
+            const double lte = factorial(q - 1) / harmonic(q - 1);
+            lte2m = lte * lte * norm2(nd_get(z, q), ewt);
+          }
+          if (higher) {
+            const double r = ipow(hstep / C[Ctl::kHprev], q + 1);
+            const double c = rcp((q + 2) * harmonic(q + 1));
+            lte2p = c * c * norm2(e - r * eprev, ewt);
+          }
+          // the three candidates' roots in one evaluation: the group's lane 0
+          // takes order q, lane 1 order q - 1, lane 2 order q + 1 (each lane
+          // computes the same function of its own inputs, so the values are
+          // those of three separate evaluations)
+          const int gl = W.lane;
+          const double et = eta_from2(gl == 2 ? 10.0 : 6.0, gl == 0 ? dsm2 : gl == 1 ? lte2m : lte2p,
+                                      gl == 0 ? q + 1 : gl == 1 ? q : q + 2);
+          eta = W.uni(W.bcast(et, 0));
+          if (lower) {
+            const double eta_qm1 = W.uni(W.bcast(et, 1));
             if (eta_qm1 > eta) {
               eta = eta_qm1;
               qnew = q - 1;
             }
           }
-          if (q < qmax && have_eprev) {
-            const double r = ipow(hstep / C[Ctl::kHprev], q + 1);
-            const double c = rcp((q + 2) * harmonic(q + 1));
-            const double lte2 = c * c * norm2(e - r * eprev, ewt);
-            const double eta_qp1 = W.uni(eta_from2(10.0, lte2, q + 2));
+          if (higher) {
+            const double eta_qp1 = W.uni(W.bcast(et, 2));
             if (eta_qp1 > eta) {
               eta = eta_qp1;
               qnew = q + 1;
             }
           }
+        } else if (36.0 * dsm2 <= hold_bound(q + 1)) {
+          eta = W.uni(eta_from2(6.0, dsm2, q + 1));
         }
         if (eta >= 1.5) {
           if (eta > eta_max) eta = eta_max;
